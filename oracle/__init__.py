@@ -1,0 +1,37 @@
+"""Plain FP64 CPU oracle for the Chebyshev-filtered plane-wave eigensolver path.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and the
+bench's ``cpu_baseline`` leg may import this package; the product path (the HIP
+library and its Python binding) never calls it and shares no code with it.
+
+Each function follows a passage of the paper (arXiv 2604.11139): the problem
+statement H psi = lambda S psi with S = I (section "Problem setup"), the
+matrix-free Hamiltonian with FFT local part and projector nonlocal part
+(sections "Main computational kernels" and "Low-level operations"), the
+Chebyshev spectral filter with Rayleigh-quotient bounds (Algorithm
+"Parallel Chebyshev filtering of degree k" in the appendix on parallel
+subspace iteration algorithms), S-orthogonalisation by Cholesky (Algorithm
+"S-ortho") and the Rayleigh-Ritz procedure (Algorithms "Rayleigh-Ritz
+procedure" / "Matrix-free Rayleigh-Ritz procedure").  Where the paper is silent
+the module docstrings state the reading taken.
+
+Everything is written in float64 / complex128 with NumPy and SciPy; library
+primitives (FFT, dense eigensolver, Cholesky) are used as single steps, never
+blocked, fused or reordered.
+"""
+from .sphere import GSphere, gsphere, reciprocal_vectors  # noqa: F401
+from .hamiltonian import Hamiltonian  # noqa: F401
+from .chebyshev import (  # noqa: F401
+    cheb_filter,
+    cheb_sigmas,
+    filter_bounds,
+    lanczos,
+    lanczos_upper_bound,
+    rayleigh_quotients,
+)
+from .subspace import (  # noqa: F401
+    cholesky_upper,
+    gram,
+    rayleigh_ritz,
+    residual_norms,
+)
