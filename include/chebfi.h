@@ -1,0 +1,174 @@
+/*
+ * chebfi.h - C ABI of the MI355X Chebyshev-filter eigensolver hot path.
+ *
+ * The library finds the lowest M eigenpairs of a plane-wave Kohn-Sham
+ * Hamiltonian H psi = lambda psi (S = I) on an N x M block of wave functions
+ * kept in GPU memory, as stated in arXiv 2604.11139, section "Problem setup".
+ * H = 0.5|k+G|^2 (diagonal) + V_loc (applied on the FFT grid) + sum_R P_R D_R P_R^H
+ * (section "Low-level operations").  The block is filtered by a Chebyshev
+ * polynomial of H (Algorithm "Parallel Chebyshev filtering of degree k"),
+ * orthonormalised through the Cholesky factor of its Gram matrix (Algorithm
+ * "S-ortho") and rotated by Rayleigh-Ritz (Algorithm "RR").  Only eigenvalues
+ * and scalars come back to the host (section "Host-device memory transfers").
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Blocks: device pointers to interleaved complex numbers (re, im), column-major
+ *   npw x nband with leading dimension ld >= npw (one band per column; the
+ *   band stride of section "Batch processing").  dtype ABI_C128 means double
+ *   pairs (16 bytes per coefficient), ABI_C64 float pairs (8 bytes).  The row
+ *   order is the library's sphere order (abi_get_gsphere): ascending FFT-box
+ *   index i1 + n1*(i2 + n2*i3) with i_d = m_d mod n_d.
+ * Ownership: the caller allocates and owns every block and output buffer; the
+ *   library owns the handle and its tables and work buffers, frees them in
+ *   abi_destroy, and keeps no caller pointer after the call's stream work.
+ * Streams: `stream` is a hipStream_t (NULL = default stream).  Calls enqueue
+ *   work and return; calls that return host values synchronise that stream.
+ *   One handle must not be used from two host threads or streams at once.
+ * Errors: every call returns ABI_OK (0) or a negative code; abi_last_error()
+ *   gives the message of the calling thread's last failure.  On error nothing
+ *   is guaranteed about output buffers.
+ */
+#ifndef CHEBFI_H
+#define CHEBFI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t abi_status;
+
+enum {
+  ABI_OK = 0,
+  ABI_ERR_ARG = -1,     /* null pointer, nband <= 0, ld < npw, degree < 1, b <= a, a0 > a ... */
+  ABI_ERR_GRID = -2,    /* sphere does not fit the box, radix not in {2,3,5}, box too large */
+  ABI_ERR_NOT_HPD = -3, /* Cholesky breakdown (pivot index in abi_last_error) */
+  ABI_ERR_DEVICE = -4,  /* HIP runtime error */
+  ABI_ERR_NOMEM = -5,   /* device allocation failed */
+  ABI_ERR_STATE = -6    /* dtype or precision not allowed for this handle */
+};
+
+enum { ABI_C128 = 0, ABI_C64 = 1 };
+enum { ABI_PREC_FP64 = 0, ABI_PREC_MIXED = 1 };
+
+typedef struct abi_system_s *abi_system;
+
+/* One Hamiltonian.  Host pointers are read during abi_set_system only. */
+typedef struct {
+  int32_t abi_version;   /* must be 1 */
+  double lattice[9];     /* rows a1, a2, a3 in bohr */
+  double kpt_red[3];     /* k-point in reduced coordinates of the reciprocal basis */
+  double ecut;           /* Ha; basis = {G : 0.5|k+G|^2 < ecut} (strict) */
+  int32_t ngrid[3];      /* FFT box n1, n2, n3; each {2,3,5}-smooth and <= 64 */
+  const double *vloc;    /* n1*n2*n3 reals, V_loc(r_i) with i1 fastest */
+  int32_t natom;         /* >= 0; four projectors (s, px, py, pz) per atom */
+  const double *tau_cart;/* natom*3 cartesian positions, bohr */
+  double rc;             /* projector Gaussian width, bohr (> 0) */
+  const double *dij;     /* natom*4*4 complex (re,im interleaved), row-major D_R[i][j], Hermitian */
+  int32_t precision;     /* ABI_PREC_FP64 or ABI_PREC_MIXED */
+} abi_system_desc;
+
+/* ---- host-only helpers (no GPU needed) ------------------------------------ */
+
+/* Number of plane waves of the basis of `desc` (section "Low-level operations":
+ * the cut-off fixes the grid and the data are moved into the FFT layout).
+ * Fails with ABI_ERR_GRID if the sphere leaves the box window
+ * [-n/2, n/2-1] (even n) / [-(n-1)/2, (n-1)/2] (odd n). */
+abi_status abi_gsphere_count(const abi_system_desc *desc, int64_t *npw);
+
+/* Fills host arrays of length npw (as returned by abi_gsphere_count):
+ * miller (npw*3, m1 m2 m3 per plane wave), box_index (npw) and kinetic (npw,
+ * 0.5|k+G|^2).  Any of the three may be NULL. */
+abi_status abi_gsphere_build(const abi_system_desc *desc, int64_t npw, int32_t *miller,
+                             int32_t *box_index, double *kinetic);
+
+/* ---- handle ---------------------------------------------------------------- */
+
+/* Builds the basis, the kinetic and projector tables and the FFT plans of one
+ * Hamiltonian on the current HIP device and uploads V_loc and D.  The
+ * projector matrix P (npw x 4*natom) has columns
+ * p_s = g e^{-iG.R}/sqrt(Omega), p_c = rc q_c g e^{-iG.R}/sqrt(Omega),
+ * q = k+G, g = exp(-|q|^2 rc^2/2) (section "Low-level operations").
+ * Synchronises `stream`.  On success *out owns device memory until abi_destroy. */
+abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system *out);
+
+abi_status abi_system_info(abi_system sys, int64_t *npw, int32_t *nproj, int32_t ngrid[3]);
+
+/* Copies the basis maps to host arrays (npw*3 and npw int32). */
+abi_status abi_get_gsphere(abi_system sys, int32_t *miller, int32_t *box_index);
+
+/* Copies the FP64 projector matrix to a caller device buffer of npw*nproj
+ * complex doubles, column-major with leading dimension npw.  Synchronises. */
+abi_status abi_get_projectors(abi_system sys, void *P_out, void *stream);
+
+abi_status abi_destroy(abi_system sys);
+
+/* ---- hot path ------------------------------------------------------------- */
+
+/* HX = H X for nband columns (matrix-free H application of section "Main
+ * computational kernels": kinetic diagonal, V_loc through batched 3D FFTs,
+ * nonlocal through P^H X, D and P(...)).  X and HX must not overlap. */
+abi_status abi_apply_H(abi_system sys, const void *X, void *HX, int64_t nband, int64_t ld,
+                       int32_t dtype, void *stream);
+
+/* Bounds of the Chebyshev filter (Algorithm "Parallel Chebyshev filtering of
+ * degree k", Rayleigh-quotient step): out[0] = a = max_i RQ_i,
+ * out[2] = a0 = min_i RQ_i with RQ_i = Re(x_i^H H x_i)/(x_i^H x_i), and
+ * out[1] = b = theta_max(T) + beta_last from `nlanczos` (1..64) Lanczos steps
+ * with full reorthogonalisation started from the device vector v0 (npw
+ * complex, same dtype as X); the run stops early with b = theta_max when
+ * beta_j <= 1e-12 max(1, |alpha_j|).  `out` is a host array of 3 doubles.
+ * Synchronises `stream`. */
+abi_status abi_spectral_bounds(abi_system sys, const void *X, int64_t nband, int64_t ld,
+                               int32_t dtype, const void *v0, int32_t nlanczos, double *out,
+                               void *stream);
+
+/* Y = T_m((H - c)/e) X / T_m((a0 - c)/e), e = (b-a)/2, c = (b+a)/2, by the
+ * scaled three-term recurrence (the "axpy" recurrence of section "Parallel
+ * implementation design"): Y_1 = (s_1/e)(H - c)X,
+ * Y_{k+1} = (2 s_{k+1}/e)(H - c)Y_k - s_k s_{k+1} Y_{k-1}, s_1 = e/(a0 - c),
+ * s_{k+1} = 1/(2/s_1 - s_k).  degree = m >= 1 H applications; requires b > a
+ * and a0 <= a.  X and Y (both npw x nband, leading dimension ld) must not
+ * overlap; X is not modified. */
+abi_status abi_cheb_filter(abi_system sys, const void *X, void *Y, int64_t nband, int64_t ld,
+                           int32_t dtype, int32_t degree, double a, double b, double a0,
+                           void *stream);
+
+/* Rayleigh-Ritz on the filtered block (Algorithms "S-ortho" and "RR" with
+ * S = I): G = Y^H Y = U^H U (Cholesky, FP64), H_s = Y^H (H Y),
+ * U^-H H_s U^-1 = Z Lambda Z^H, Psi = Y U^-1 Z, H Psi = (H Y) U^-1 Z, and the
+ * residual norms ||H psi_n - lambda_n psi_n|| (Algorithm "Parallel Chebyshev
+ * filtering of degree k", last two steps).
+ * Y (c128, npw x nband, ld): in: filtered block; out: Ritz vectors Psi.
+ * HPsi: optional c128 output (npw x nband, ld) or NULL.
+ * eval: host, nband doubles, ascending.  resnorm: host, nband doubles, or NULL.
+ * flags: host int32 or NULL (bit 0 reserved for the mixed-precision fallback).
+ * Fails with ABI_ERR_NOT_HPD if the Gram matrix is not positive definite.
+ * Synchronises `stream`. */
+abi_status abi_rayleigh_ritz(abi_system sys, void *Y, void *HPsi, int64_t nband, int64_t ld,
+                             double *eval, double *resnorm, int32_t *flags, void *stream);
+
+/* ---- dense FP64 building blocks of the Rayleigh-Ritz step ---------------------
+ * Column-major complex double matrices in device memory, leading dimension lda. */
+
+/* In place: A (m x m Hermitian, upper triangle read) -> U upper with real
+ * positive diagonal, A = U^H U; the strict lower triangle is zeroed
+ * (Algorithm "S-ortho", potrf). */
+abi_status abi_zpotrf_upper(int64_t m, void *A, int64_t lda, void *stream);
+
+/* Eigen-decomposition of a Hermitian m x m matrix (upper and lower triangles
+ * read as the average (A + A^H)/2): w (device, m doubles, ascending) and Z
+ * (device, m x m, ldz) with A = Z diag(w) Z^H.  A is overwritten.  The hegvd
+ * step of Algorithm "RR" after the Cholesky reduction. */
+abi_status abi_zheev(int64_t m, void *A, int64_t lda, double *w, void *Z, int64_t ldz,
+                     void *stream);
+
+const char *abi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHEBFI_H */

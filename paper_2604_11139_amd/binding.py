@@ -1,0 +1,284 @@
+"""ctypes binding of ``libchebfi.so`` (argument marshalling only).
+
+Every computation runs in the HIP library; this module only converts Python
+and torch objects to the pointers and sizes of the C ABI (include/chebfi.h).
+PyTorch provides device memory and the current HIP stream.
+
+Blocks of wave functions are torch complex128 tensors of shape (nband, npw)
+with unit stride along the plane waves: row b is band b, which is exactly the
+column-major npw x nband layout of the ABI with ld = tensor.stride(0).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchebfi.so")
+
+ABI_OK = 0
+ABI_ERR_ARG = -1
+ABI_ERR_GRID = -2
+ABI_ERR_NOT_HPD = -3
+ABI_ERR_DEVICE = -4
+ABI_ERR_NOMEM = -5
+ABI_ERR_STATE = -6
+ABI_C128 = 0
+ABI_C64 = 1
+ABI_PREC_FP64 = 0
+ABI_PREC_MIXED = 1
+
+EXPORTS = [
+    "abi_gsphere_count", "abi_gsphere_build", "abi_set_system", "abi_system_info",
+    "abi_get_gsphere", "abi_get_projectors", "abi_destroy", "abi_apply_H",
+    "abi_spectral_bounds", "abi_cheb_filter", "abi_rayleigh_ritz", "abi_zpotrf_upper",
+    "abi_zheev", "abi_last_error",
+]
+
+
+class ChebfiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"chebfi error {code}: {msg}")
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", c_int32),
+        ("lattice", c_double * 9),
+        ("kpt_red", c_double * 3),
+        ("ecut", c_double),
+        ("ngrid", c_int32 * 3),
+        ("vloc", POINTER(c_double)),
+        ("natom", c_int32),
+        ("tau_cart", POINTER(c_double)),
+        ("rc", c_double),
+        ("dij", POINTER(c_double)),
+        ("precision", c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Loads the library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2604_11139_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = c_void_p
+    sig = {
+        "abi_gsphere_count": [POINTER(Desc), POINTER(c_int64)],
+        "abi_gsphere_build": [POINTER(Desc), c_int64, vp, vp, vp],
+        "abi_set_system": [POINTER(Desc), vp, POINTER(vp)],
+        "abi_system_info": [vp, POINTER(c_int64), POINTER(c_int32), POINTER(c_int32)],
+        "abi_get_gsphere": [vp, vp, vp],
+        "abi_get_projectors": [vp, vp, vp],
+        "abi_destroy": [vp],
+        "abi_apply_H": [vp, vp, vp, c_int64, c_int64, c_int32, vp],
+        "abi_spectral_bounds": [vp, vp, c_int64, c_int64, c_int32, vp, c_int32, vp, vp],
+        "abi_cheb_filter": [vp, vp, vp, c_int64, c_int64, c_int32, c_int32, c_double, c_double,
+                            c_double, vp],
+        "abi_rayleigh_ritz": [vp, vp, vp, c_int64, c_int64, vp, vp, vp, vp],
+        "abi_zpotrf_upper": [c_int64, vp, c_int64, vp],
+        "abi_zheev": [c_int64, vp, c_int64, vp, vp, c_int64, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = c_int32
+    L.abi_last_error.argtypes = []
+    L.abi_last_error.restype = c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != ABI_OK:
+        raise ChebfiError(rc, lib().abi_last_error().decode(errors="replace"))
+
+
+def _stream():
+    import torch
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _block(t, npw: int):
+    """(pointer, nband, ld) of a (nband, npw) complex128 CUDA tensor."""
+    import torch
+    if t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError("blocks must be complex128 CUDA tensors")
+    if t.dim() == 1:
+        t = t.view(1, -1)
+    if t.shape[1] != npw or (t.shape[1] > 1 and t.stride(1) != 1):
+        raise ValueError("block must be (nband, npw) with unit stride along plane waves")
+    ld = int(t.stride(0)) if t.shape[0] > 1 else npw  # a one-row stride is arbitrary
+    if ld < npw:
+        raise ValueError("block rows overlap (stride(0) < npw)")
+    return c_void_p(t.data_ptr()), int(t.shape[0]), ld
+
+
+class _DescHolder:
+    """Keeps the numpy arrays referenced by a Desc alive."""
+
+    def __init__(self, lattice, kpt_red, ecut, ngrid, vloc, tau, dij, rc, precision):
+        self.vloc = np.ascontiguousarray(np.asarray(vloc, dtype=np.float64).reshape(-1))
+        self.tau = np.ascontiguousarray(np.asarray(tau, dtype=np.float64).reshape(-1, 3))
+        d = np.ascontiguousarray(np.asarray(dij, dtype=np.complex128).reshape(-1, 4, 4))
+        self.dij = np.ascontiguousarray(d.view(np.float64).reshape(-1))
+        self.desc = Desc()
+        self.desc.abi_version = 1
+        lat = np.asarray(lattice, dtype=np.float64).reshape(-1)
+        for i in range(9):
+            self.desc.lattice[i] = float(lat[i])
+        for i in range(3):
+            self.desc.kpt_red[i] = float(kpt_red[i])
+            self.desc.ngrid[i] = int(ngrid[i])
+        self.desc.ecut = float(ecut)
+        self.desc.vloc = self.vloc.ctypes.data_as(POINTER(c_double))
+        self.desc.natom = int(self.tau.shape[0])
+        self.desc.tau_cart = self.tau.ctypes.data_as(POINTER(c_double))
+        self.desc.rc = float(rc)
+        self.desc.dij = self.dij.ctypes.data_as(POINTER(c_double))
+        self.desc.precision = int(precision)
+
+    @classmethod
+    def from_system(cls, s, precision=ABI_PREC_FP64):
+        return cls(s.lattice, s.kpt_red, s.ecut, s.ngrid, s.vloc, s.tau, s.dij, s.rc, precision)
+
+
+def gsphere_host(s):
+    """Host-only basis build: (miller (npw,3) int32, box_index (npw,) int32, kinetic)."""
+    h = _DescHolder.from_system(s)
+    n = c_int64(0)
+    _check(lib().abi_gsphere_count(ctypes.byref(h.desc), ctypes.byref(n)))
+    npw = n.value
+    miller = np.zeros((npw, 3), dtype=np.int32)
+    box = np.zeros(npw, dtype=np.int32)
+    kin = np.zeros(npw, dtype=np.float64)
+    _check(lib().abi_gsphere_build(ctypes.byref(h.desc), npw, miller.ctypes.data_as(c_void_p),
+                                   box.ctypes.data_as(c_void_p), kin.ctypes.data_as(c_void_p)))
+    return miller, box, kin
+
+
+class System:
+    """One Hamiltonian resident on the current GPU."""
+
+    def __init__(self, s, precision=ABI_PREC_FP64):
+        h = _DescHolder.from_system(s, precision)
+        handle = c_void_p()
+        _check(lib().abi_set_system(ctypes.byref(h.desc), _stream(), ctypes.byref(handle)))
+        self._h = handle
+        npw = c_int64(0)
+        nproj = c_int32(0)
+        grid = (c_int32 * 3)()
+        _check(lib().abi_system_info(self._h, ctypes.byref(npw), ctypes.byref(nproj), grid))
+        self.npw = npw.value
+        self.nproj = nproj.value
+        self.ngrid = tuple(grid)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().abi_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- tables ------------------------------------------------------------
+    def gsphere(self):
+        miller = np.zeros((self.npw, 3), dtype=np.int32)
+        box = np.zeros(self.npw, dtype=np.int32)
+        _check(lib().abi_get_gsphere(self._h, miller.ctypes.data_as(c_void_p),
+                                     box.ctypes.data_as(c_void_p)))
+        return miller, box
+
+    def projectors(self):
+        import torch
+        P = torch.empty((self.nproj, self.npw), dtype=torch.complex128, device="cuda")
+        _check(lib().abi_get_projectors(self._h, c_void_p(P.data_ptr()), _stream()))
+        return P  # row j = projector column j
+
+    # -- hot path ------------------------------------------------------------
+    def apply_H(self, X, out=None):
+        import torch
+        px, nb, ld = _block(X, self.npw)
+        if out is None:
+            out = torch.empty_strided(X.shape, X.stride(), dtype=X.dtype, device=X.device)
+        po, nbo, ldo = _block(out, self.npw)
+        if nbo != nb or ldo != ld:
+            raise ValueError("out must match X's shape and stride")
+        _check(lib().abi_apply_H(self._h, px, po, nb, ld, ABI_C128, _stream()))
+        return out
+
+    def cheb_filter(self, X, degree, a, b, a0, out=None):
+        import torch
+        px, nb, ld = _block(X, self.npw)
+        if out is None:
+            out = torch.empty_strided(X.shape, X.stride(), dtype=X.dtype, device=X.device)
+        po, nbo, ldo = _block(out, self.npw)
+        if nbo != nb or ldo != ld:
+            raise ValueError("out must match X's shape and stride")
+        _check(lib().abi_cheb_filter(self._h, px, po, nb, ld, ABI_C128, int(degree), float(a),
+                                     float(b), float(a0), _stream()))
+        return out
+
+    def spectral_bounds(self, X, v0, nlanczos=10):
+        px, nb, ld = _block(X, self.npw)
+        pv, _, _ = _block(v0, self.npw)
+        out = (c_double * 3)()
+        _check(lib().abi_spectral_bounds(self._h, px, nb, ld, ABI_C128, pv, int(nlanczos), out,
+                                         _stream()))
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def rayleigh_ritz(self, Y, hpsi=None):
+        """In place: Y <- Ritz vectors.  Returns (eval, resnorm, flags)."""
+        py, nb, ld = _block(Y, self.npw)
+        ph = c_void_p(0)
+        if hpsi is not None:
+            ph, nbh, ldh = _block(hpsi, self.npw)
+            if nbh != nb or ldh != ld:
+                raise ValueError("hpsi must match Y's shape and stride")
+        ev = np.zeros(nb, dtype=np.float64)
+        rn = np.zeros(nb, dtype=np.float64)
+        fl = c_int32(0)
+        _check(lib().abi_rayleigh_ritz(self._h, py, ph, nb, ld, ev.ctypes.data_as(c_void_p),
+                                       rn.ctypes.data_as(c_void_p), ctypes.byref(fl), _stream()))
+        return ev, rn, fl.value
+
+
+# -- dense building blocks (matrices as torch (m, m) tensors, math layout) ------
+def zpotrf_upper(A):
+    """Upper Cholesky factor U (A = U^H U) of a Hermitian positive definite matrix."""
+    m = A.shape[0]
+    cm = A.t().contiguous()  # column-major storage
+    _check(lib().abi_zpotrf_upper(m, c_void_p(cm.data_ptr()), m, _stream()))
+    return cm.t()
+
+
+def zheev(A):
+    """(w ascending, Z) with A = Z diag(w) Z^H for a Hermitian matrix."""
+    import torch
+    m = A.shape[0]
+    cm = A.t().contiguous()
+    w = torch.empty(m, dtype=torch.float64, device=A.device)
+    Z = torch.empty((m, m), dtype=torch.complex128, device=A.device)
+    _check(lib().abi_zheev(m, c_void_p(cm.data_ptr()), m, c_void_p(w.data_ptr()),
+                           c_void_p(Z.data_ptr()), m, _stream()))
+    return w, Z.t()

@@ -1,0 +1,495 @@
+// extern "C" entry points of the library (declared in include/chebfi.h).
+//
+// Each call validates its arguments, converts failures to status codes with a
+// thread-local message, and enqueues kernels on the caller's stream.  The
+// order of operations follows arXiv 2604.11139: the matrix-free H application
+// (section "Main computational kernels"), the Chebyshev filter loop of
+// Algorithm "Parallel Chebyshev filtering of degree k" and the S-ortho / RR
+// algorithms of section "Parallel implementation design" with S = I.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "kernels.h"
+
+namespace chebfi {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+void *DevBuf::get(size_t need) {
+  if (need == 0) need = 256;
+  if (bytes >= need) return ptr;
+  release();
+  hipError_t e = hipMalloc(&ptr, need);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    bytes = 0;
+    (void)hipGetLastError();
+    throw Error{ABI_ERR_NOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed"};
+  }
+  bytes = need;
+  return ptr;
+}
+
+void DevBuf::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+}  // namespace chebfi
+
+using namespace chebfi;
+
+namespace {
+
+template <typename F> abi_status guarded(F &&f) {
+  try {
+    f();
+    return ABI_OK;
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    set_error("host allocation failed");
+    return ABI_ERR_NOMEM;
+  } catch (...) {
+    set_error("unexpected exception");
+    return ABI_ERR_DEVICE;
+  }
+}
+
+inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+void check_desc(const abi_system_desc *d) {
+  CHEBFI_REQUIRE(d != nullptr, ABI_ERR_ARG, "desc is NULL");
+  CHEBFI_REQUIRE(d->abi_version == 1, ABI_ERR_ARG, "abi_version must be 1");
+  CHEBFI_REQUIRE(d->ecut > 0.0 && std::isfinite(d->ecut), ABI_ERR_ARG, "ecut must be > 0");
+  for (int c = 0; c < 3; ++c) {
+    const int n = d->ngrid[c];
+    CHEBFI_REQUIRE(n >= 2 && n <= kMaxN, ABI_ERR_GRID, "FFT box edge must be in [2, 64]");
+    Plan1D p;
+    CHEBFI_REQUIRE(make_plan(n, &p), ABI_ERR_GRID, "FFT box edge must be {2,3,5}-smooth");
+  }
+  CHEBFI_REQUIRE(d->natom >= 0, ABI_ERR_ARG, "natom < 0");
+  if (d->natom > 0) {
+    CHEBFI_REQUIRE(d->tau_cart && d->dij, ABI_ERR_ARG, "tau_cart/dij are NULL");
+    CHEBFI_REQUIRE(d->rc > 0.0, ABI_ERR_ARG, "rc must be > 0");
+  }
+  CHEBFI_REQUIRE(d->precision == ABI_PREC_FP64 || d->precision == ABI_PREC_MIXED, ABI_ERR_ARG,
+                 "unknown precision");
+  double B[9];
+  reciprocal(d->lattice, B);
+  for (double b : B) CHEBFI_REQUIRE(std::isfinite(b), ABI_ERR_ARG, "singular lattice");
+}
+
+template <typename T> T *upload(const T *host, size_t count) {
+  T *dev = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&dev, sizeof(T) * count) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{ABI_ERR_NOMEM, "hipMalloc failed during set_system"};
+  }
+  if (host) CHEBFI_HIP(hipMemcpy(dev, host, sizeof(T) * count, hipMemcpyHostToDevice));
+  return dev;
+}
+
+void free_tables(abi_system_s *s) {
+  void *ptrs[] = {s->d_kin, s->d_box, s->d_plane, s->d_P, s->d_D, s->d_V, s->d_tw};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  s->d_kin = nullptr;
+  s->d_box = nullptr;
+  s->d_plane = nullptr;
+  s->d_P = nullptr;
+  s->d_D = nullptr;
+  s->d_V = nullptr;
+  s->d_tw = nullptr;
+}
+
+void check_block(const abi_system_s *s, const void *p, int64_t nband, int64_t ld, int32_t dtype) {
+  CHEBFI_REQUIRE(s != nullptr, ABI_ERR_ARG, "system handle is NULL");
+  CHEBFI_REQUIRE(p != nullptr, ABI_ERR_ARG, "block pointer is NULL");
+  CHEBFI_REQUIRE(nband > 0, ABI_ERR_ARG, "nband must be > 0");
+  CHEBFI_REQUIRE(ld >= s->npw, ABI_ERR_ARG, "ld must be >= npw");
+  CHEBFI_REQUIRE(dtype == ABI_C128, ABI_ERR_STATE, "only complex128 blocks are supported");
+}
+
+// Out = alpha * (H - cshift) X - beta * Xprev   (Xprev may be null)
+void apply_core(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
+                void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
+                hipStream_t st) {
+  const int64_t npw = s->npw;
+  const int nproj = s->nproj;
+  int splits = 1;
+  double2 *cpart = nullptr, *cprime = nullptr;
+  if (nproj > 0) {
+    splits = zgemm_splits(nproj, nband, npw);
+    cpart = (double2 *)s->cpart.get(sizeof(double2) * (size_t)splits * nproj * nband);
+    cprime = (double2 *)s->cprime.get(sizeof(double2) * (size_t)nproj * nband);
+    // C = P^H X (split along the plane waves), C' = alpha D C
+    zgemm(OP_C, OP_N, nproj, nband, npw, s->d_P, npw, X, ldx, nullptr, 0, double2{1, 0},
+          double2{0, 0}, st, cpart, splits);
+    launch_dapply(s->natom, nband, cpart, splits, s->d_D, alpha, cprime, st);
+  }
+  const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
+  const int fb = (int)std::min<int64_t>(s->fft_batch, nband);
+  void *box = s->box.get(sizeof(double2) * (size_t)nbox * fb);
+  for (int64_t b0 = 0; b0 < nband; b0 += fb) {
+    const int nb = (int)std::min<int64_t>(fb, nband - b0);
+    launch_local_potential<double>(s, X, ldx, Xprev, ldp, Out, ldo, (int)b0, nb, box, s->d_V,
+                                   alpha, cshift, beta, st);
+  }
+  if (nproj > 0) {
+    // Out += P C'
+    zgemm(OP_N, OP_N, npw, nband, nproj, s->d_P, npw, cprime, nproj, Out, ldo, double2{1, 0},
+          double2{1, 0}, st);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *abi_last_error(void) { return g_last_error.c_str(); }
+
+abi_status abi_gsphere_count(const abi_system_desc *desc, int64_t *npw) {
+  return guarded([&] {
+    check_desc(desc);
+    CHEBFI_REQUIRE(npw != nullptr, ABI_ERR_ARG, "npw is NULL");
+    Sphere sp;
+    std::string err;
+    abi_status st = build_sphere(desc, &sp, &err);
+    if (st != ABI_OK) throw Error{st, err};
+    *npw = (int64_t)sp.kinetic.size();
+  });
+}
+
+abi_status abi_gsphere_build(const abi_system_desc *desc, int64_t npw, int32_t *miller,
+                             int32_t *box_index, double *kinetic) {
+  return guarded([&] {
+    check_desc(desc);
+    Sphere sp;
+    std::string err;
+    abi_status st = build_sphere(desc, &sp, &err);
+    if (st != ABI_OK) throw Error{st, err};
+    CHEBFI_REQUIRE(npw == (int64_t)sp.kinetic.size(), ABI_ERR_ARG, "npw does not match the basis");
+    if (miller) std::memcpy(miller, sp.miller.data(), sizeof(int32_t) * 3 * npw);
+    if (box_index) std::memcpy(box_index, sp.box_index.data(), sizeof(int32_t) * npw);
+    if (kinetic) std::memcpy(kinetic, sp.kinetic.data(), sizeof(double) * npw);
+  });
+}
+
+abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system *out) {
+  abi_system_s *s = nullptr;
+  abi_status rc = guarded([&] {
+    check_desc(desc);
+    CHEBFI_REQUIRE(out != nullptr, ABI_ERR_ARG, "out is NULL");
+    CHEBFI_REQUIRE(desc->vloc != nullptr, ABI_ERR_ARG, "vloc is NULL");
+    s = new abi_system_s();
+    CHEBFI_HIP(hipGetDevice(&s->device));
+    s->n1 = desc->ngrid[0];
+    s->n2 = desc->ngrid[1];
+    s->n3 = desc->ngrid[2];
+    s->natom = desc->natom;
+    s->nproj = 4 * desc->natom;
+    s->precision = desc->precision;
+    std::string err;
+    abi_status st = build_sphere(desc, &s->sphere, &err);
+    if (st != ABI_OK) throw Error{st, err};
+    s->npw = (int64_t)s->sphere.kinetic.size();
+    CHEBFI_REQUIRE(s->npw > 0, ABI_ERR_ARG, "empty basis");
+    for (int c = 0; c < 3; ++c) make_plan(desc->ngrid[c], &s->plan.d[c]);
+    const int64_t nxy = (int64_t)s->n1 * s->n2;
+    const int64_t nbox = nxy * s->n3;
+    std::vector<int32_t> plane(s->n3 + 1, 0);
+    {
+      int64_t idx = 0;
+      for (int i3 = 0; i3 <= s->n3; ++i3) {
+        while (idx < s->npw && s->sphere.box_index[idx] < (int64_t)i3 * nxy) ++idx;
+        plane[i3] = (int32_t)idx;
+      }
+      plane[s->n3] = (int32_t)s->npw;
+    }
+    std::vector<double> tw(3 * kMaxN * 2, 0.0);
+    for (int c = 0; c < 3; ++c) {
+      const int n = desc->ngrid[c];
+      for (int j = 0; j < n; ++j) {
+        const double ang = 2.0 * M_PI * (double)j / (double)n;
+        tw[2 * (c * kMaxN + j)] = std::cos(ang);
+        tw[2 * (c * kMaxN + j) + 1] = -std::sin(ang);
+      }
+    }
+    std::vector<double> P;
+    build_projectors(desc, s->sphere, &P);
+    s->d_kin = upload(s->sphere.kinetic.data(), s->npw);
+    s->d_box = upload(s->sphere.box_index.data(), s->npw);
+    s->d_plane = upload(plane.data(), plane.size());
+    s->d_P = upload(P.data(), P.size());
+    s->d_D = upload(desc->dij, (size_t)desc->natom * 32);
+    s->d_V = upload(desc->vloc, (size_t)nbox);
+    s->d_tw = upload(tw.data(), tw.size());
+    // bands per FFT batch: keep the box buffer near 128 MiB (env override)
+    int64_t fb = (int64_t)((128ll << 20) / (sizeof(double2) * nbox));
+    if (const char *e = std::getenv("CHEBFI_FFT_BATCH")) fb = std::atoll(e);
+    s->fft_batch = (int)std::max<int64_t>(1, std::min<int64_t>(fb, 4096));
+    CHEBFI_HIP(hipStreamSynchronize(S(stream)));
+    *out = s;
+  });
+  if (rc != ABI_OK && s) {
+    free_tables(s);
+    delete s;
+  }
+  return rc;
+}
+
+abi_status abi_system_info(abi_system s, int64_t *npw, int32_t *nproj, int32_t ngrid[3]) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(s != nullptr, ABI_ERR_ARG, "system handle is NULL");
+    if (npw) *npw = s->npw;
+    if (nproj) *nproj = s->nproj;
+    if (ngrid) {
+      ngrid[0] = s->n1;
+      ngrid[1] = s->n2;
+      ngrid[2] = s->n3;
+    }
+  });
+}
+
+abi_status abi_get_gsphere(abi_system s, int32_t *miller, int32_t *box_index) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(s != nullptr, ABI_ERR_ARG, "system handle is NULL");
+    if (miller) std::memcpy(miller, s->sphere.miller.data(), sizeof(int32_t) * 3 * s->npw);
+    if (box_index) std::memcpy(box_index, s->sphere.box_index.data(), sizeof(int32_t) * s->npw);
+  });
+}
+
+abi_status abi_get_projectors(abi_system s, void *P_out, void *stream) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(s != nullptr && P_out != nullptr, ABI_ERR_ARG, "NULL argument");
+    const size_t bytes = sizeof(double2) * (size_t)s->npw * (size_t)std::max(s->nproj, 0);
+    if (bytes)
+      CHEBFI_HIP(hipMemcpyAsync(P_out, s->d_P, bytes, hipMemcpyDeviceToDevice, S(stream)));
+    CHEBFI_HIP(hipStreamSynchronize(S(stream)));
+  });
+}
+
+abi_status abi_destroy(abi_system s) {
+  return guarded([&] {
+    if (!s) return;
+    (void)hipDeviceSynchronize();
+    free_tables(s);
+    delete s;
+  });
+}
+
+abi_status abi_apply_H(abi_system s, const void *X, void *HX, int64_t nband, int64_t ld,
+                       int32_t dtype, void *stream) {
+  return guarded([&] {
+    check_block(s, X, nband, ld, dtype);
+    CHEBFI_REQUIRE(HX != nullptr, ABI_ERR_ARG, "HX is NULL");
+    CHEBFI_REQUIRE(HX != X, ABI_ERR_ARG, "X and HX must not overlap");
+    apply_core(s, X, ld, nullptr, 0, HX, ld, nband, 1.0, 0.0, 0.0, S(stream));
+  });
+}
+
+abi_status abi_cheb_filter(abi_system s, const void *X, void *Y, int64_t nband, int64_t ld,
+                           int32_t dtype, int32_t degree, double a, double b, double a0,
+                           void *stream) {
+  return guarded([&] {
+    check_block(s, X, nband, ld, dtype);
+    CHEBFI_REQUIRE(Y != nullptr && Y != X, ABI_ERR_ARG, "Y must be a separate block");
+    CHEBFI_REQUIRE(degree >= 1, ABI_ERR_ARG, "degree must be >= 1");
+    CHEBFI_REQUIRE(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0), ABI_ERR_ARG,
+                   "bounds must be finite");
+    CHEBFI_REQUIRE(b > a, ABI_ERR_ARG, "need b > a");
+    CHEBFI_REQUIRE(a0 <= a, ABI_ERR_ARG, "need a0 <= a");
+    hipStream_t st = S(stream);
+    const int64_t npw = s->npw;
+    const double e = (b - a) / 2.0, c = (b + a) / 2.0;
+    const double s1 = e / (a0 - c);
+    // Y_j lives in bufs[(degree - j) % 3] so that Y_degree lands in Y.
+    void *bufs[3] = {Y, nullptr, nullptr};
+    int64_t lds[3] = {ld, npw, npw};
+    if (degree >= 2) bufs[1] = s->blk1.get(sizeof(double2) * (size_t)npw * nband);
+    if (degree >= 3) bufs[2] = s->blk2.get(sizeof(double2) * (size_t)npw * nband);
+    auto slot = [&](int j) { return (degree - j) % 3; };
+    // Y_1 = (s1/e)(H - c) X
+    apply_core(s, X, ld, nullptr, 0, bufs[slot(1)], lds[slot(1)], nband, s1 / e, c, 0.0, st);
+    double sk = s1;
+    for (int j = 1; j < degree; ++j) {
+      const double sk1 = 1.0 / (2.0 / s1 - sk);
+      const void *yk = bufs[slot(j)];
+      const int64_t ldk = lds[slot(j)];
+      const void *yp = (j == 1) ? X : bufs[slot(j - 1)];
+      const int64_t ldp = (j == 1) ? ld : lds[slot(j - 1)];
+      apply_core(s, yk, ldk, yp, ldp, bufs[slot(j + 1)], lds[slot(j + 1)], nband, 2.0 * sk1 / e,
+                 c, sk * sk1, st);
+      sk = sk1;
+    }
+  });
+}
+
+abi_status abi_spectral_bounds(abi_system s, const void *X, int64_t nband, int64_t ld,
+                               int32_t dtype, const void *v0, int32_t nlanczos, double *out,
+                               void *stream) {
+  return guarded([&] {
+    check_block(s, X, nband, ld, dtype);
+    CHEBFI_REQUIRE(v0 != nullptr && out != nullptr, ABI_ERR_ARG, "NULL argument");
+    CHEBFI_REQUIRE(nlanczos >= 1 && nlanczos <= 64, ABI_ERR_ARG, "nlanczos must be in [1, 64]");
+    hipStream_t st = S(stream);
+    const int64_t npw = s->npw;
+    void *HX = s->blk3.get(sizeof(double2) * (size_t)npw * nband);
+    // scalars: [0..2] out, [8..8+64) alpha, [80..80+64) beta, rq after 160
+    double *scal = (double *)s->scal.get(sizeof(double) * (size_t)(160 + nband));
+    double *alpha = scal + 8, *beta = scal + 80, *rq = scal + 160;
+    apply_core(s, X, ld, nullptr, 0, HX, npw, nband, 1.0, 0.0, 0.0, st);
+    launch_rayleigh_quotients(npw, nband, X, ld, HX, npw, rq, st);
+    launch_minmax(nband, rq, scal, st);
+    // Lanczos basis V (npw x (nl+1)), residual w, projections h
+    const int nl = nlanczos;
+    double2 *V = (double2 *)s->blk2.get(sizeof(double2) * (size_t)npw * (nl + 2));
+    double2 *w = V + (size_t)npw * (nl + 1);
+    double2 *h = (double2 *)s->small4.get(sizeof(double2) * 128);
+    launch_norm(npw, v0, scal + 3, st);
+    launch_scale_inv(npw, scal + 3, v0, V, st);
+    int k = nl;
+    int add_last = 1;
+    for (int j = 0; j < nl; ++j) {
+      apply_core(s, V + (size_t)j * npw, npw, nullptr, 0, w, npw, 1, 1.0, 0.0, 0.0, st);
+      if (j > 0) launch_axpy_dev(npw, beta + (j - 1), -1.0, V + (size_t)(j - 1) * npw, w, st);
+      launch_dot_re(npw, V + (size_t)j * npw, w, alpha + j, st);
+      launch_axpy_dev(npw, alpha + j, -1.0, V + (size_t)j * npw, w, st);
+      launch_multi_dot(npw, j + 1, V, npw, w, h, st);
+      launch_multi_axpy(npw, j + 1, V, npw, h, w, st);
+      launch_norm(npw, w, beta + j, st);
+      double ab[2];
+      CHEBFI_HIP(hipMemcpyAsync(&ab[0], alpha + j, sizeof(double), hipMemcpyDeviceToHost, st));
+      CHEBFI_HIP(hipMemcpyAsync(&ab[1], beta + j, sizeof(double), hipMemcpyDeviceToHost, st));
+      CHEBFI_HIP(hipStreamSynchronize(st));
+      if (ab[1] <= 1e-12 * std::max(1.0, std::fabs(ab[0]))) {
+        k = j + 1;
+        add_last = 0;
+        break;
+      }
+      launch_scale_inv(npw, beta + j, w, V + (size_t)(j + 1) * npw, st);
+    }
+    launch_tridiag_bound(k, alpha, beta, add_last, scal, st);
+    double host[3];
+    CHEBFI_HIP(hipMemcpyAsync(host, scal, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
+    CHEBFI_HIP(hipStreamSynchronize(st));
+    out[0] = host[0];
+    out[1] = host[1];
+    out[2] = host[2];
+  });
+}
+
+abi_status abi_rayleigh_ritz(abi_system s, void *Y, void *HPsi, int64_t nband, int64_t ld,
+                             double *eval, double *resnorm, int32_t *flags, void *stream) {
+  return guarded([&] {
+    check_block(s, Y, nband, ld, ABI_C128);
+    CHEBFI_REQUIRE(eval != nullptr, ABI_ERR_ARG, "eval is NULL");
+    CHEBFI_REQUIRE(HPsi != Y, ABI_ERR_ARG, "HPsi must not alias Y");
+    hipStream_t st = S(stream);
+    const int64_t npw = s->npw, M = nband;
+    const size_t mm = sizeof(double2) * (size_t)M * M;
+    double2 *G = (double2 *)s->small1.get(mm);
+    double2 *Hs = (double2 *)s->small2.get(mm);
+    double2 *T = (double2 *)s->small3.get(mm);
+    double2 *Z = (double2 *)s->small4.get(mm);
+    double *scal = (double *)s->scal.get(sizeof(double) * (size_t)(160 + 3 * M + 64));
+    double *w_dev = scal + 160;
+    double *r_dev = w_dev + M;
+    int *info = (int *)(r_dev + M);
+    // Gram G = Y^H Y -> U (Cholesky, upper)
+    int splits = zgemm_splits(M, M, npw);
+    void *part = s->cpart.get(sizeof(double2) * (size_t)splits * M * M);
+    zgemm(OP_C, OP_N, M, M, npw, Y, ld, Y, ld, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
+          splits);
+    zsum_parts(M, M, part, splits, G, M, double2{1, 0}, double2{0, 0}, st);
+    launch_hermitize(M, G, M, st);
+    zpotrf_upper(M, G, M, info, nullptr, st);
+    int hinfo = 0;
+    CHEBFI_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, st));
+    CHEBFI_HIP(hipStreamSynchronize(st));
+    if (hinfo != 0)
+      throw Error{ABI_ERR_NOT_HPD,
+                  "Gram matrix not positive definite at pivot " + std::to_string(hinfo)};
+    // H Y and H_s = Y^H (H Y)
+    double2 *HY = (double2 *)s->blk1.get(sizeof(double2) * (size_t)npw * M);
+    apply_core(s, Y, ld, nullptr, 0, HY, npw, M, 1.0, 0.0, 0.0, st);
+    part = s->cpart.get(sizeof(double2) * (size_t)splits * M * M);  // apply_core may regrow it
+    zgemm(OP_C, OP_N, M, M, npw, Y, ld, HY, npw, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
+          splits);
+    zsum_parts(M, M, part, splits, Hs, M, double2{1, 0}, double2{0, 0}, st);
+    launch_hermitize(M, Hs, M, st);
+    // U^-1 and the reduced matrix U^-H H_s U^-1
+    void *trw = s->eig2.get(ztrtri_work_bytes(M));
+    ztrtri_upper(M, G, M, trw, st);
+    zgemm(OP_N, OP_N, M, M, M, Hs, M, G, M, T, M, double2{1, 0}, double2{0, 0}, st);
+    zgemm(OP_C, OP_N, M, M, M, G, M, T, M, Hs, M, double2{1, 0}, double2{0, 0}, st);
+    // eigen-decomposition (Hs overwritten), W = U^-1 Z
+    void *ew = s->eig1.get(zheev_work_bytes(M));
+    zheev(M, Hs, M, w_dev, Z, M, ew, st);
+    zgemm(OP_N, OP_N, M, M, M, G, M, Z, M, T, M, double2{1, 0}, double2{0, 0}, st);
+    // Psi = Y W, H Psi = (H Y) W
+    double2 *Psi = (double2 *)s->blk2.get(sizeof(double2) * (size_t)npw * M);
+    zgemm(OP_N, OP_N, npw, M, M, Y, ld, T, M, Psi, npw, double2{1, 0}, double2{0, 0}, st);
+    double2 *HP;
+    int64_t ldh;
+    if (HPsi) {
+      HP = (double2 *)HPsi;
+      ldh = ld;
+    } else {
+      HP = (double2 *)s->blk3.get(sizeof(double2) * (size_t)npw * M);
+      ldh = npw;
+    }
+    zgemm(OP_N, OP_N, npw, M, M, HY, npw, T, M, HP, ldh, double2{1, 0}, double2{0, 0}, st);
+    launch_copy_block(npw, M, Psi, npw, Y, ld, st);
+    launch_residual_norms(npw, M, Y, ld, HP, ldh, w_dev, r_dev, st);
+    CHEBFI_HIP(hipMemcpyAsync(eval, w_dev, sizeof(double) * M, hipMemcpyDeviceToHost, st));
+    if (resnorm)
+      CHEBFI_HIP(hipMemcpyAsync(resnorm, r_dev, sizeof(double) * M, hipMemcpyDeviceToHost, st));
+    CHEBFI_HIP(hipStreamSynchronize(st));
+    if (flags) *flags = 0;
+  });
+}
+
+abi_status abi_zpotrf_upper(int64_t m, void *A, int64_t lda, void *stream) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(m >= 1 && A != nullptr && lda >= m, ABI_ERR_ARG, "bad matrix arguments");
+    hipStream_t st = S(stream);
+    int *info = nullptr;
+    CHEBFI_HIP(hipMalloc(&info, sizeof(int)));
+    zpotrf_upper(m, A, lda, info, nullptr, st);
+    int h = 0;
+    CHEBFI_HIP(hipMemcpyAsync(&h, info, sizeof(int), hipMemcpyDeviceToHost, st));
+    CHEBFI_HIP(hipStreamSynchronize(st));
+    (void)hipFree(info);
+    if (h != 0) throw Error{ABI_ERR_NOT_HPD, "not positive definite at pivot " + std::to_string(h)};
+  });
+}
+
+abi_status abi_zheev(int64_t m, void *A, int64_t lda, double *w, void *Z, int64_t ldz,
+                     void *stream) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(m >= 1 && A && w && Z && lda >= m && ldz >= m, ABI_ERR_ARG,
+                   "bad matrix arguments");
+    hipStream_t st = S(stream);
+    void *work = nullptr;
+    CHEBFI_HIP(hipMalloc(&work, zheev_work_bytes(m)));
+    try {
+      zheev(m, A, lda, w, Z, ldz, work, st);
+      CHEBFI_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      (void)hipFree(work);
+      throw;
+    }
+    (void)hipFree(work);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,647 @@
+// Dense FP64 linear algebra of the Rayleigh-Ritz step on one GPU.
+//
+// The paper solves the M x M problems redundantly on each process with
+// vendor potrf / trsm / hegvd calls (arXiv 2604.11139, Algorithms "S-ortho"
+// and "RR", section "Parallel implementation design"), and names hegvd the
+// main AMD bottleneck (section "Single-step benchmarks: GPU kernel
+// rooflines").  Here every step is a hand-written kernel:
+//
+// * Cholesky A = U^H U: right-looking blocked, 32-column diagonal blocks
+//   factored in LDS by one workgroup, the panel solved column-parallel and the
+//   trailing matrix updated by the MFMA GEMM;
+// * U^-1: blocked, diagonal blocks inverted in LDS, off-diagonal panels by GEMM;
+// * Hermitian eigensolver: Householder reduction to real symmetric tridiagonal
+//   form (reflectors H = I - tau u u^H with a real sub-diagonal, applied from
+//   both sides as a rank-2 update), eigenvalues by Sturm-count bisection (one
+//   thread per eigenvalue), eigenvectors of the tridiagonal by inverse
+//   iteration with partial-pivoting LU and modified Gram-Schmidt inside
+//   clusters of (nearly) equal eigenvalues, then the reflectors applied back.
+//   These are the classical Householder / bisection / inverse-iteration
+//   methods (Wilkinson; Golub & Van Loan, "Matrix Computations", chapter 8).
+#include <cfloat>
+
+#include "cplx.h"
+#include "kernels.h"
+
+namespace chebfi {
+
+namespace {
+
+constexpr int NB = 32;           // Cholesky / trtri block size
+constexpr int kEigMaxM = 2560;   // LDS-resident inverse iteration limit
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ double block_sum(double v, double *scratch) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) scratch[wave] = v;
+  __syncthreads();
+  double t = 0;
+  for (int w = 0; w < nw; ++w) t += scratch[w];
+  return t;
+}
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// ---------------------------------------------------------------- Cholesky --
+// Factor the nb x nb diagonal block at (j0, j0) in LDS (upper, A = U^H U).
+__global__ __launch_bounds__(256) void potrf_diag_kernel(int nb, double2 *__restrict__ A, int64_t lda, int64_t j0,
+                                  int *__restrict__ info) {
+  __shared__ double2 a[NB][NB + 1];  // a[i][j] = A(j0+i, j0+j)
+  const int t = threadIdx.x;
+  for (int idx = t; idx < nb * nb; idx += blockDim.x) {
+    const int i = idx % nb, j = idx / nb;
+    a[i][j] = A[(j0 + i) + (j0 + j) * lda];
+  }
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    const double dkk = a[k][k].x;
+    const bool bad = !(dkk > 0.0);
+    const double dk = bad ? 1.0 : sqrt(dkk);
+    __syncthreads();
+    if (t == 0) {
+      if (bad && *info == 0) *info = (int)(j0 + k + 1);
+      a[k][k] = double2{dk, 0.0};
+    }
+    for (int j = k + 1 + t; j < nb; j += blockDim.x) a[k][j] = cscale(a[k][j], 1.0 / dk);
+    __syncthreads();
+    for (int idx = t; idx < nb * nb; idx += blockDim.x) {
+      const int i = idx % nb, j = idx / nb;
+      if (i > k && j >= i) {
+        const double2 u = a[k][i], v = a[k][j];
+        const double2 cu{u.x, -u.y};
+        a[i][j] = csub(a[i][j], cmul(cu, v));
+      }
+    }
+    __syncthreads();
+  }
+  for (int idx = t; idx < nb * nb; idx += blockDim.x) {
+    const int i = idx % nb, j = idx / nb;
+    if (i <= j) A[(j0 + i) + (j0 + j) * lda] = a[i][j];
+  }
+}
+
+// U12 = U11^-H A12 for the panel rows j0..j0+nb-1, columns j1..m-1.
+__global__ __launch_bounds__(64) void potrf_panel_kernel(int nb, int64_t m, double2 *__restrict__ A, int64_t lda,
+                                   int64_t j0) {
+  __shared__ double2 u[NB][NB + 1];
+  const int t = threadIdx.x;
+  for (int idx = t; idx < nb * nb; idx += blockDim.x) {
+    const int i = idx % nb, j = idx / nb;
+    u[i][j] = A[(j0 + i) + (j0 + j) * lda];
+  }
+  __syncthreads();
+  const int64_t col = j0 + nb + (int64_t)blockIdx.x * blockDim.x + t;
+  if (col >= m) return;
+  double2 x[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) x[i] = (i < nb) ? A[(j0 + i) + col * lda] : double2{0, 0};
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    if (i < nb) {
+      double2 s = x[i];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        if (k < i) {
+          const double2 cu{u[k][i].x, -u[k][i].y};
+          s = csub(s, cmul(cu, x[k]));
+        }
+      }
+      x[i] = cscale(s, 1.0 / u[i][i].x);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+    if (i < nb) A[(j0 + i) + col * lda] = x[i];
+}
+
+__global__ void set_int_kernel(int *p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// ---------------------------------------------------------------- trtri ----
+// Invert the nb x nb upper triangular diagonal block in place (LDS).
+__global__ __launch_bounds__(256) void trtri_diag_kernel(int nb, double2 *__restrict__ A, int64_t lda, int64_t j0) {
+  __shared__ double2 a[NB][NB + 1];
+  __shared__ double2 r[NB][NB + 1];
+  const int t = threadIdx.x;
+  for (int idx = t; idx < nb * nb; idx += blockDim.x) {
+    const int i = idx % nb, j = idx / nb;
+    a[i][j] = (i <= j) ? A[(j0 + i) + (j0 + j) * lda] : double2{0, 0};
+  }
+  __syncthreads();
+  // column j of the inverse: back substitution of U x = e_j (one thread per column)
+  if (t < nb) {
+    const int j = t;
+    for (int i = nb - 1; i >= 0; --i) {
+      double2 s = (i == j) ? double2{1.0, 0.0} : double2{0, 0};
+      if (i <= j) {
+        for (int k = i + 1; k <= j; ++k) s = csub(s, cmul(a[i][k], r[k][j]));
+        // divide by complex diagonal
+        const double2 d = a[i][i];
+        const double den = d.x * d.x + d.y * d.y;
+        s = double2{(s.x * d.x + s.y * d.y) / den, (s.y * d.x - s.x * d.y) / den};
+      }
+      r[i][j] = s;
+    }
+  }
+  __syncthreads();
+  for (int idx = t; idx < nb * nb; idx += blockDim.x) {
+    const int i = idx % nb, j = idx / nb;
+    A[(j0 + i) + (j0 + j) * lda] = (i <= j) ? r[i][j] : double2{0, 0};
+  }
+}
+
+// ------------------------------------------------------ tridiagonalisation --
+// Householder vector of column j below the diagonal (LAPACK-style larfg):
+// H^H (alpha, x) = (beta, 0), H = I - tau u u^H, u = (1, x/(alpha-beta)).
+__global__ __launch_bounds__(256) void house_kernel(int64_t m, double2 *__restrict__ A, int64_t lda, int64_t j,
+                             double *__restrict__ d, double *__restrict__ e,
+                             double2 *__restrict__ tau, double2 *__restrict__ u) {
+  __shared__ double scratch[16];
+  double2 *col = A + j * lda;
+  const double2 alpha = col[j + 1];
+  double s = 0;
+  for (int64_t i = j + 2 + threadIdx.x; i < m; i += blockDim.x) {
+    const double2 v = col[i];
+    s += v.x * v.x + v.y * v.y;
+  }
+  const double xnorm2 = block_sum(s, scratch);
+  double beta, tr, ti;
+  double2 scal{0, 0};
+  if (xnorm2 == 0.0 && alpha.y == 0.0) {
+    beta = alpha.x;
+    tr = 0.0;
+    ti = 0.0;
+  } else {
+    const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xnorm2);
+    beta = (alpha.x >= 0.0) ? -nrm : nrm;
+    tr = (beta - alpha.x) / beta;
+    ti = -alpha.y / beta;
+    const double2 den{alpha.x - beta, alpha.y};
+    const double dd = den.x * den.x + den.y * den.y;
+    scal = double2{den.x / dd, -den.y / dd};
+  }
+  for (int64_t i = j + 2 + threadIdx.x; i < m; i += blockDim.x) {
+    const double2 v = cmul(col[i], scal);
+    col[i] = v;
+    u[i] = v;
+  }
+  if (threadIdx.x == 0) {
+    u[j + 1] = double2{1.0, 0.0};
+    d[j] = col[j].x;
+    e[j] = beta;
+    tau[j] = double2{tr, ti};
+  }
+}
+
+// part[ks][i] = sum_{k in chunk ks} A22[i][k] u[k]   (A22 = A[j+1:, j+1:])
+__global__ __launch_bounds__(256) void hemv_part_kernel(int64_t m, const double2 *__restrict__ A, int64_t lda, int64_t j,
+                                 const double2 *__restrict__ u, int64_t kchunk,
+                                 double2 *__restrict__ part) {
+  const int64_t L = m - j - 1;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ks = blockIdx.y;
+  const int64_t k0 = ks * kchunk, k1 = (k0 + kchunk < L) ? k0 + kchunk : L;
+  if (i >= L) return;
+  const double2 *a = A + (j + 1) + (j + 1) * lda;
+  double2 s{0, 0};
+  for (int64_t k = k0; k < k1; ++k) s = cadd(s, cmul(a[i + k * lda], u[j + 1 + k]));
+  part[ks * L + i] = s;
+}
+
+// p = tau sum_ks part; w = p - 0.5 tau (p^H u) u   (one workgroup)
+__global__ __launch_bounds__(256) void hemv_finish_kernel(int64_t m, int64_t j, const double2 *__restrict__ part, int ksn,
+                                   const double2 *__restrict__ tau, const double2 *__restrict__ u,
+                                   double2 *__restrict__ w) {
+  __shared__ double scratch[16];
+  const int64_t L = m - j - 1;
+  const double2 t = tau[j];
+  double sr = 0, si = 0;
+  for (int64_t i = threadIdx.x; i < L; i += blockDim.x) {
+    double2 p{0, 0};
+    for (int ks = 0; ks < ksn; ++ks) p = cadd(p, part[(int64_t)ks * L + i]);
+    p = cmul(t, p);
+    w[j + 1 + i] = p;
+    const double2 uv = u[j + 1 + i];
+    sr += p.x * uv.x + p.y * uv.y;  // conj(p) u
+    si += p.x * uv.y - p.y * uv.x;
+  }
+  sr = block_sum(sr, scratch);
+  si = block_sum(si, scratch);
+  const double2 a2 = cscale(cmul(t, double2{sr, si}), -0.5);
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < L; i += blockDim.x)
+    w[j + 1 + i] = cadd(w[j + 1 + i], cmul(a2, u[j + 1 + i]));
+}
+
+// A22 -= u w^H + w u^H
+__global__ __launch_bounds__(256) void her2_kernel(int64_t m, double2 *__restrict__ A, int64_t lda, int64_t j,
+                            const double2 *__restrict__ u, const double2 *__restrict__ w) {
+  const int64_t L = m - j - 1;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = blockIdx.y;
+  if (i >= L || k >= L) return;
+  const double2 ui = u[j + 1 + i], wi = w[j + 1 + i];
+  const double2 uk = u[j + 1 + k], wk = w[j + 1 + k];
+  const double2 cwk{wk.x, -wk.y}, cuk{uk.x, -uk.y};
+  double2 *p = A + (j + 1 + i) + (j + 1 + k) * lda;
+  *p = csub(*p, cadd(cmul(ui, cwk), cmul(wi, cuk)));
+}
+
+__global__ void last_diag_kernel(int64_t m, const double2 *__restrict__ A, int64_t lda,
+                                 double *__restrict__ d) {
+  if (threadIdx.x == 0) d[m - 1] = A[(m - 1) + (m - 1) * lda].x;
+}
+
+// ---------------------------------------------------------------- bisection --
+__device__ int sturm_less(int64_t m, const double *d, const double *e2, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0) ++cnt;
+  for (int64_t i = 1; i < m; ++i) {
+    q = (d[i] - x) - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+__global__ __launch_bounds__(256) void tri_prep_kernel(int64_t m, const double *__restrict__ d,
+                                const double *__restrict__ e, double *__restrict__ e2,
+                                double *__restrict__ stats) {
+  // stats[0] = Gershgorin lower, stats[1] = upper, stats[2] = |T| scale, stats[3] = pivmin
+  __shared__ double slo[256], shi[256], smax[256];
+  double lo = 1e300, hi = -1e300, mx = 0, emax2 = 0;
+  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < m - 1 ? fabs(e[i]) : 0.0);
+    lo = fmin(lo, d[i] - r);
+    hi = fmax(hi, d[i] + r);
+    mx = fmax(mx, fmax(fabs(d[i] - r), fabs(d[i] + r)));
+    if (i < m - 1) {
+      e2[i] = e[i] * e[i];
+      emax2 = fmax(emax2, e2[i]);
+    }
+  }
+  slo[threadIdx.x] = lo;
+  shi[threadIdx.x] = hi;
+  smax[threadIdx.x] = fmax(mx, emax2);
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + s]);
+      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + s]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double scale = fmax(fmax(fabs(slo[0]), fabs(shi[0])), 1e-300);
+    stats[0] = slo[0] - 2.0 * DBL_EPSILON * scale * (double)m - 1e-300;
+    stats[1] = shi[0] + 2.0 * DBL_EPSILON * scale * (double)m + 1e-300;
+    stats[2] = scale;
+    stats[3] = fmax(DBL_MIN, DBL_MIN * smax[0]);
+  }
+}
+
+__global__ __launch_bounds__(64) void bisect_kernel(int64_t m, const double *__restrict__ d, const double *__restrict__ e2,
+                              const double *__restrict__ stats, double *__restrict__ w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double lo = stats[0], hi = stats[1];
+  const double pivmin = stats[3];
+  const double tol = 2.0 * DBL_EPSILON * stats[2];
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (hi - lo <= tol) break;
+    if (sturm_less(m, d, e2, mid, pivmin) >= i + 1)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  w[i] = 0.5 * (lo + hi);
+}
+
+// ------------------------------------------------------- inverse iteration --
+__device__ __forceinline__ double hash_uniform(uint64_t a, uint64_t b) {
+  // splitmix64 of (a, b) -> (-1, 1)
+  uint64_t z = a * 0x9E3779B97F4A7C15ull + b + 0x632BE59BD9B4E019ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return ((double)(z >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
+}
+
+// One workgroup per cluster of eigenvalues closer than `gaptol`; the group
+// leader (first index of the cluster) computes all members in order.
+// S (m x m, real, column-major, lds) receives the tridiagonal eigenvectors.
+__global__ __launch_bounds__(256) void invit_kernel(int64_t m, const double *__restrict__ d, const double *__restrict__ e,
+                             const double *__restrict__ w, const double *__restrict__ stats,
+                             double *__restrict__ S, int64_t lds) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t c0 = blockIdx.x;
+  const double scale = stats[2];
+  const double gaptol = 1e-6 * scale;
+  if (c0 > 0 && w[c0] - w[c0 - 1] <= gaptol) return;  // not a cluster leader
+  int64_t c1 = c0 + 1;
+  while (c1 < m && w[c1] - w[c1 - 1] <= gaptol) ++c1;
+
+  double *sd = reinterpret_cast<double *>(smem_raw);
+  double *se = sd + m;
+  double *ud = se + m;   // U diagonal
+  double *u1 = ud + m;   // first superdiagonal
+  double *u2 = u1 + m;   // second superdiagonal
+  double *lm = u2 + m;   // multipliers
+  double *x = lm + m;
+  unsigned char *swp = reinterpret_cast<unsigned char *>(x + m);
+  __shared__ double scratch[16];
+  __shared__ double sh_coef;
+
+  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+    sd[i] = d[i];
+    se[i] = (i < m - 1) ? e[i] : 0.0;
+  }
+  __syncthreads();
+  const double tiny = DBL_EPSILON * scale;
+  const double pert = 10.0 * DBL_EPSILON * scale;
+  double shift_prev = 0.0;
+  for (int64_t q = c0; q < c1; ++q) {
+    double shift = w[q];
+    if (q > c0 && shift - shift_prev < pert) shift = shift_prev + pert;
+    shift_prev = shift;
+    // LU with partial pivoting of T - shift I (thread 0, sequential)
+    if (threadIdx.x == 0) {
+      double a = sd[0] - shift;
+      double cc = (m > 1) ? se[0] : 0.0;  // current superdiagonal of row i
+      for (int64_t i = 0; i < m - 1; ++i) {
+        const double b = se[i];               // subdiagonal (row i+1, col i)
+        const double an = sd[i + 1] - shift;  // diagonal of row i+1
+        const double cn = (i + 1 < m - 1) ? se[i + 1] : 0.0;
+        if (fabs(a) >= fabs(b)) {
+          const double l = (a != 0.0) ? b / a : 0.0;
+          ud[i] = a;
+          u1[i] = cc;
+          u2[i] = 0.0;
+          lm[i] = l;
+          swp[i] = 0;
+          a = an - l * cc;
+          cc = cn;
+        } else {
+          const double l = a / b;
+          ud[i] = b;
+          u1[i] = an;
+          u2[i] = cn;
+          lm[i] = l;
+          swp[i] = 1;
+          a = cc - l * an;
+          cc = -l * cn;
+        }
+        if (fabs(ud[i]) < tiny) ud[i] = (ud[i] < 0.0) ? -tiny : tiny;
+      }
+      ud[m - 1] = (fabs(a) < tiny) ? ((a < 0.0) ? -tiny : tiny) : a;
+    }
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) x[i] = hash_uniform(q, i);
+    __syncthreads();
+    for (int it = 0; it < 3; ++it) {
+      if (threadIdx.x == 0) {
+        for (int64_t i = 0; i < m - 1; ++i) {
+          if (swp[i]) {
+            const double t = x[i];
+            x[i] = x[i + 1];
+            x[i + 1] = t;
+          }
+          x[i + 1] -= lm[i] * x[i];
+        }
+        x[m - 1] = x[m - 1] / ud[m - 1];
+        if (m > 1) x[m - 2] = (x[m - 2] - u1[m - 2] * x[m - 1]) / ud[m - 2];
+        for (int64_t i = m - 3; i >= 0; --i)
+          x[i] = (x[i] - u1[i] * x[i + 1] - u2[i] * x[i + 2]) / ud[i];
+      }
+      __syncthreads();
+      // scale to avoid overflow, then MGS against earlier members of the cluster
+      double mx = 0;
+      for (int64_t i = threadIdx.x; i < m; i += blockDim.x) mx = fmax(mx, fabs(x[i]));
+      {
+        // block max via sums of a one-hot is awkward; reuse scratch with max
+        __syncthreads();
+        for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+        if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = mx;
+        __syncthreads();
+        mx = 0;
+        for (int wv = 0; wv < (int)((blockDim.x + 63) >> 6); ++wv) mx = fmax(mx, scratch[wv]);
+        __syncthreads();
+      }
+      const double inv = (mx > 0) ? 1.0 / mx : 1.0;
+      for (int64_t i = threadIdx.x; i < m; i += blockDim.x) x[i] *= inv;
+      __syncthreads();
+      for (int64_t r = c0; r < q; ++r) {
+        const double *sr = S + r * lds;
+        double s = 0;
+        for (int64_t i = threadIdx.x; i < m; i += blockDim.x) s += sr[i] * x[i];
+        s = block_sum(s, scratch);
+        for (int64_t i = threadIdx.x; i < m; i += blockDim.x) x[i] -= s * sr[i];
+        __syncthreads();
+      }
+      double nn = 0;
+      for (int64_t i = threadIdx.x; i < m; i += blockDim.x) nn += x[i] * x[i];
+      nn = block_sum(nn, scratch);
+      const double invn = (nn > 0) ? 1.0 / sqrt(nn) : 1.0;
+      for (int64_t i = threadIdx.x; i < m; i += blockDim.x) x[i] *= invn;
+      __syncthreads();
+    }
+    // sign: largest-magnitude component (first on ties) made positive
+    if (threadIdx.x == 0) {
+      int64_t jm = 0;
+      double best = -1;
+      for (int64_t i = 0; i < m; ++i)
+        if (fabs(x[i]) > best) {
+          best = fabs(x[i]);
+          jm = i;
+        }
+      sh_coef = (x[jm] < 0) ? -1.0 : 1.0;
+    }
+    __syncthreads();
+    const double sg = sh_coef;
+    double *sq = S + q * lds;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) sq[i] = sg * x[i];
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+// Z = S as complex
+__global__ __launch_bounds__(256) void real_to_complex_kernel(int64_t m, const double *__restrict__ S, int64_t lds,
+                                       double2 *__restrict__ Z, int64_t ldz) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * m) return;
+  const int64_t i = idx % m, j = idx / m;
+  Z[i + j * ldz] = double2{S[i + j * lds], 0.0};
+}
+
+// wrow[c] = sum_{i>j} conj(u_i) Z[i, c]
+__global__ __launch_bounds__(256) void bt_dot_kernel(int64_t m, int64_t j, const double2 *__restrict__ u,
+                              const double2 *__restrict__ Z, int64_t ldz,
+                              double2 *__restrict__ wrow) {
+  __shared__ double scratch[16];
+  const int64_t c = blockIdx.x;
+  double sr = 0, si = 0;
+  for (int64_t i = j + 1 + threadIdx.x; i < m; i += blockDim.x) {
+    const double2 uv = u[i], z = Z[i + c * ldz];
+    sr += uv.x * z.x + uv.y * z.y;
+    si += uv.x * z.y - uv.y * z.x;
+  }
+  sr = block_sum(sr, scratch);
+  si = block_sum(si, scratch);
+  if (threadIdx.x == 0) wrow[c] = double2{sr, si};
+}
+
+// Z[i, c] -= tau u_i wrow[c]  for i > j
+__global__ __launch_bounds__(256) void bt_update_kernel(int64_t m, int64_t j, const double2 *__restrict__ tau,
+                                 const double2 *__restrict__ u, const double2 *__restrict__ wrow,
+                                 double2 *__restrict__ Z, int64_t ldz) {
+  const int64_t L = m - j - 1;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (i >= L) return;
+  const double2 t = cmul(tau[j], u[j + 1 + i]);
+  double2 *p = Z + (j + 1 + i) + c * ldz;
+  *p = csub(*p, cmul(t, wrow[c]));
+}
+
+// Householder vector u_j (with u_{j+1} = 1) restored from column j of A.
+__global__ __launch_bounds__(256) void load_u_kernel(int64_t m, const double2 *__restrict__ A, int64_t lda, int64_t j,
+                              double2 *__restrict__ u) {
+  const int64_t i = j + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  u[i] = (i == j + 1) ? double2{1.0, 0.0} : A[i + j * lda];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- drivers ----
+size_t zpotrf_work_bytes(int64_t) { return 0; }
+
+void zpotrf_upper(int64_t m, void *Av, int64_t lda, int *info, void *, hipStream_t st) {
+  double2 *A = (double2 *)Av;
+  hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, st, info, 0);
+  for (int64_t j0 = 0; j0 < m; j0 += NB) {
+    const int nb = (int)std::min<int64_t>(NB, m - j0);
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, nb, A, lda, j0, info);
+    CHEBFI_HIP(hipGetLastError());
+    const int64_t rest = m - j0 - nb;
+    if (rest > 0) {
+      hipLaunchKernelGGL(potrf_panel_kernel, dim3(nblk(rest, 64)), dim3(64), 0, st, nb, m, A, lda,
+                         j0);
+      CHEBFI_HIP(hipGetLastError());
+      double2 *U12 = A + j0 + (j0 + nb) * lda;
+      double2 *A22 = A + (j0 + nb) + (j0 + nb) * lda;
+      zgemm(OP_C, OP_N, rest, rest, nb, U12, lda, U12, lda, A22, lda, double2{-1.0, 0.0},
+            double2{1.0, 0.0}, st);
+    }
+  }
+  launch_zero_lower(m, A, lda, st);
+}
+
+size_t ztrtri_work_bytes(int64_t m) { return sizeof(double2) * (size_t)m * NB; }
+
+void ztrtri_upper(int64_t m, void *Av, int64_t lda, void *work, hipStream_t st) {
+  double2 *A = (double2 *)Av;
+  double2 *T = (double2 *)work;  // m x NB
+  for (int64_t j0 = 0; j0 < m; j0 += NB) {
+    const int nb = (int)std::min<int64_t>(NB, m - j0);
+    hipLaunchKernelGGL(trtri_diag_kernel, dim3(1), dim3(256), 0, st, nb, A, lda, j0);
+    CHEBFI_HIP(hipGetLastError());
+    if (j0 > 0) {
+      // A[0:j0, j0:j0+nb] = -Uinv[0:j0,0:j0] * A[0:j0, j0:j0+nb] * Uinv_jj
+      zgemm(OP_N, OP_N, j0, nb, j0, A, lda, A + j0 * lda, lda, T, j0, double2{1.0, 0.0},
+            double2{0.0, 0.0}, st);
+      zgemm(OP_N, OP_N, j0, nb, nb, T, j0, A + j0 + j0 * lda, lda, A + j0 * lda, lda,
+            double2{-1.0, 0.0}, double2{0.0, 0.0}, st);
+    }
+  }
+}
+
+size_t zheev_work_bytes(int64_t m) {
+  // d, e, e2, w-tmp, stats, tau, u, wv, wrow, hemv parts, S (real m x m)
+  const size_t ks = 64;
+  return sizeof(double) * (size_t)(4 * m + 8) + sizeof(double2) * (size_t)(4 * m) +
+         sizeof(double2) * ks * (size_t)m + sizeof(double) * (size_t)m * m +
+         16 * 256;  // each of the 11 sub-buffers is rounded up to 256 bytes
+}
+
+void zheev(int64_t m, void *Av, int64_t lda, double *wout, void *Zv, int64_t ldz, void *work,
+           hipStream_t st) {
+  CHEBFI_REQUIRE(m >= 1 && m <= kEigMaxM, ABI_ERR_ARG, "eigensolver size out of range");
+  double2 *A = (double2 *)Av;
+  double2 *Z = (double2 *)Zv;
+  char *wp = (char *)work;
+  auto take = [&](size_t bytes) {
+    void *p = wp;
+    wp += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  double *d = (double *)take(sizeof(double) * m);
+  double *e = (double *)take(sizeof(double) * m);
+  double *e2 = (double *)take(sizeof(double) * m);
+  double *stats = (double *)take(sizeof(double) * 8);
+  double2 *tau = (double2 *)take(sizeof(double2) * m);
+  double2 *u = (double2 *)take(sizeof(double2) * m);
+  double2 *wv = (double2 *)take(sizeof(double2) * m);
+  double2 *wrow = (double2 *)take(sizeof(double2) * m);
+  const int ks_max = 64;
+  double2 *part = (double2 *)take(sizeof(double2) * (size_t)ks_max * m);
+  double *S = (double *)take(sizeof(double) * (size_t)m * m);
+
+  launch_hermitize(m, A, lda, st);
+  // reduction to tridiagonal form
+  for (int64_t j = 0; j + 1 < m; ++j) {
+    const int64_t L = m - j - 1;
+    hipLaunchKernelGGL(house_kernel, dim3(1), dim3(256), 0, st, m, A, lda, j, d, e, tau, u);
+    const int64_t rb = (L + 255) / 256;
+    int ks = (int)std::min<int64_t>(ks_max, std::max<int64_t>(1, 512 / rb));
+    int64_t kchunk = (L + ks - 1) / ks;
+    if (kchunk < 16) {
+      kchunk = 16;
+      ks = (int)((L + kchunk - 1) / kchunk);
+    }
+    hipLaunchKernelGGL(hemv_part_kernel, dim3((unsigned)rb, (unsigned)ks), dim3(256), 0, st, m, A,
+                       lda, j, u, kchunk, part);
+    hipLaunchKernelGGL(hemv_finish_kernel, dim3(1), dim3(256), 0, st, m, j, part, ks, tau, u, wv);
+    hipLaunchKernelGGL(her2_kernel, dim3((unsigned)rb, (unsigned)L), dim3(256), 0, st, m, A, lda, j,
+                       u, wv);
+  }
+  CHEBFI_HIP(hipGetLastError());
+  hipLaunchKernelGGL(last_diag_kernel, dim3(1), dim3(64), 0, st, m, A, lda, d);
+  // eigenvalues of the tridiagonal
+  hipLaunchKernelGGL(tri_prep_kernel, dim3(1), dim3(256), 0, st, m, d, e, e2, stats);
+  hipLaunchKernelGGL(bisect_kernel, dim3(nblk(m, 64)), dim3(64), 0, st, m, d, e2, stats, wout);
+  CHEBFI_HIP(hipGetLastError());
+  // eigenvectors of the tridiagonal
+  const size_t lds_bytes = sizeof(double) * 7 * (size_t)m + (size_t)m + 64;
+  CHEBFI_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(invit_kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+  hipLaunchKernelGGL(invit_kernel, dim3((unsigned)m), dim3(256), lds_bytes, st, m, d, e, wout,
+                     stats, S, m);
+  CHEBFI_HIP(hipGetLastError());
+  hipLaunchKernelGGL(real_to_complex_kernel, dim3(nblk(m * m, 256)), dim3(256), 0, st, m, S, m, Z,
+                     ldz);
+  // back-transformation Z = H_0 H_1 ... H_{m-2} S
+  for (int64_t j = m - 2; j >= 0; --j) {
+    const int64_t L = m - j - 1;
+    hipLaunchKernelGGL(load_u_kernel, dim3(nblk(L, 256)), dim3(256), 0, st, m, A, lda, j, u);
+    hipLaunchKernelGGL(bt_dot_kernel, dim3((unsigned)m), dim3(256), 0, st, m, j, u, Z, ldz, wrow);
+    hipLaunchKernelGGL(bt_update_kernel, dim3(nblk(L, 256), (unsigned)m), dim3(256), 0, st, m, j,
+                       tau, u, wrow, Z, ldz);
+  }
+  CHEBFI_HIP(hipGetLastError());
+}
+
+}  // namespace chebfi

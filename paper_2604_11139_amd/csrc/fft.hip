@@ -1,0 +1,340 @@
+// Local-potential part of H on a batch of bands: scatter sphere -> box,
+// inverse 3D FFT, multiply by V_loc(r), forward 3D FFT, gather sphere.
+//
+// The paper applies V_loc to all bands with one batched FFT call instead of a
+// per-band loop (arXiv 2604.11139, section "Batch processing", Algorithms
+// "Per-band kernel execution" / "Batched bands kernel execution").  Here the
+// batched 3D transform is split in three HBM passes, each holding one 2D slab
+// of one band in LDS:
+//   pass A  (band, i3 plane): scatter the plane's sphere rows into a zeroed
+//           n1 x n2 plane, inverse FFT along x then y, store the plane;
+//   pass B  (band, i2 slab):  load n1 x n3, inverse FFT along z, multiply by
+//           V(r), forward FFT along z, store;
+//   pass C  (band, i3 plane): load, forward FFT along y then x, gather the
+//           sphere rows, scale 1/(n1 n2 n3) and combine with the kinetic term
+//           and the Chebyshev recurrence:
+//           out = alpha (local + (kin - cshift) yk) - beta yprev.
+// Each 1D transform is a Stockham autosort FFT with radix-2/3/4/5 stages
+// executed in place in LDS (every thread holds its butterflies' outputs in
+// registers across a barrier).  Twiddles are FP64 tables built on the host.
+#include "cplx.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace chebfi {
+
+namespace {
+
+constexpr int kMaxB = 4;  // butterflies per thread per stage
+
+// Radix-R DFT in registers; sgn = -1 forward (e^{-}), +1 inverse (e^{+}).
+template <typename T, int R> struct Dft;
+
+template <typename T> struct Dft<T, 2> {
+  static __device__ __forceinline__ void run(C2<T> *x, int) {
+    C2<T> a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  }
+};
+
+template <typename T> struct Dft<T, 4> {
+  static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
+    C2<T> s02 = cadd(x[0], x[2]), d02 = csub(x[0], x[2]);
+    C2<T> s13 = cadd(x[1], x[3]), d13 = cmul_i(csub(x[1], x[3]), sgn);
+    x[0] = cadd(s02, s13);
+    x[2] = csub(s02, s13);
+    x[1] = cadd(d02, d13);
+    x[3] = csub(d02, d13);
+  }
+};
+
+template <typename T> struct Dft<T, 3> {
+  static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
+    const T h = (T)0.86602540378443864676;  // sin(2 pi / 3)
+    C2<T> t1 = cadd(x[1], x[2]);
+    C2<T> t2 = cmul_i(cscale(csub(x[1], x[2]), h), sgn);
+    C2<T> m = csub(x[0], cscale(t1, (T)0.5));
+    x[0] = cadd(x[0], t1);
+    x[1] = cadd(m, t2);
+    x[2] = csub(m, t2);
+  }
+};
+
+template <typename T> struct Dft<T, 5> {
+  static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
+    const T c1 = (T)0.30901699437494742410;   // cos(2 pi / 5)
+    const T c2 = (T)-0.80901699437494742410;  // cos(4 pi / 5)
+    const T s1 = (T)0.95105651629515357212;   // sin(2 pi / 5)
+    const T s2 = (T)0.58778525229247312917;   // sin(4 pi / 5)
+    C2<T> t1 = cadd(x[1], x[4]), t2 = cadd(x[2], x[3]);
+    C2<T> t3 = csub(x[1], x[4]), t4 = csub(x[2], x[3]);
+    C2<T> a1 = cadd(x[0], cadd(cscale(t1, c1), cscale(t2, c2)));
+    C2<T> a2 = cadd(x[0], cadd(cscale(t1, c2), cscale(t2, c1)));
+    C2<T> b1 = cmul_i(cadd(cscale(t3, s1), cscale(t4, s2)), sgn);
+    C2<T> b2 = cmul_i(csub(cscale(t3, s2), cscale(t4, s1)), sgn);
+    x[0] = cadd(x[0], cadd(t1, t2));
+    x[1] = cadd(a1, b1);
+    x[4] = csub(a1, b1);
+    x[2] = cadd(a2, b2);
+    x[3] = csub(a2, b2);
+  }
+};
+
+// One Stockham stage of radix R over `npen` pencils of length n held in LDS.
+// Element e of pencil q sits at buf[q*pstride + e*estride].  p is the product
+// of the radices already applied.
+template <typename T, int R>
+__device__ void stage(C2<T> *buf, int n, int estride, int npen, int pstride, int p,
+                      const C2<T> *tw, int sgn) {
+  const int nbf = n / R;
+  const int total = npen * nbf;
+  const int m = n / (p * R);
+  const bool pen_fast = (pstride == 1);
+  C2<T> y[kMaxB][R];
+  int dst[kMaxB];
+#pragma unroll
+  for (int c = 0; c < kMaxB; ++c) {
+    const int i = threadIdx.x + c * blockDim.x;
+    dst[c] = -1;
+    if (i < total) {
+      int pen, bf;
+      if (pen_fast) {
+        pen = i % npen;
+        bf = i / npen;
+      } else {
+        bf = i % nbf;
+        pen = i / nbf;
+      }
+      const int base = pen * pstride;
+      C2<T> x[R];
+#pragma unroll
+      for (int t = 0; t < R; ++t) x[t] = buf[base + (bf + t * nbf) * estride];
+      const int k = bf % p;
+#pragma unroll
+      for (int t = 1; t < R; ++t) {
+        C2<T> w = tw[t * k * m];
+        if (sgn > 0) w.y = -w.y;
+        x[t] = cmul(x[t], w);
+      }
+      Dft<T, R>::run(x, sgn);
+#pragma unroll
+      for (int t = 0; t < R; ++t) y[c][t] = x[t];
+      dst[c] = base + ((bf - k) * R + k) * estride;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < kMaxB; ++c) {
+    if (dst[c] >= 0) {
+#pragma unroll
+      for (int t = 0; t < R; ++t) buf[dst[c] + t * p * estride] = y[c][t];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void lds_fft(C2<T> *buf, const Plan1D &pl, int estride, int npen, int pstride,
+                        const C2<T> *tw, int sgn) {
+  int p = 1;
+  for (int s = 0; s < pl.nstage; ++s) {
+    const int r = pl.radix[s];
+    if (r == 4)
+      stage<T, 4>(buf, pl.n, estride, npen, pstride, p, tw, sgn);
+    else if (r == 2)
+      stage<T, 2>(buf, pl.n, estride, npen, pstride, p, tw, sgn);
+    else if (r == 3)
+      stage<T, 3>(buf, pl.n, estride, npen, pstride, p, tw, sgn);
+    else
+      stage<T, 5>(buf, pl.n, estride, npen, pstride, p, tw, sgn);
+    p *= r;
+  }
+}
+
+template <typename T>
+__device__ void load_twiddles(C2<T> *dst, const double2 *src, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = to_c2<T>(src[i]);
+}
+
+// ---- pass A: sphere plane -> inverse xy FFT -> box plane -------------------
+template <typename T>
+__global__ __launch_bounds__(512) void pass_a_kernel(const C2<T> *__restrict__ X, int64_t ldx, int band0,
+                              const int32_t *__restrict__ box_index,
+                              const int32_t *__restrict__ plane, BoxPlan plan,
+                              const double2 *__restrict__ twg, C2<T> *__restrict__ box) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
+  const int n1 = plan.d[0].n, n2 = plan.d[1].n, n3 = plan.d[2].n;
+  const int nxy = n1 * n2;
+  C2<T> *tw1 = buf + nxy;
+  C2<T> *tw2 = tw1 + n1;
+  const int i3 = blockIdx.x;
+  const int bl = blockIdx.y;
+  load_twiddles<T>(tw1, twg, n1);
+  load_twiddles<T>(tw2, twg + kMaxN, n2);
+  for (int i = threadIdx.x; i < nxy; i += blockDim.x) buf[i] = C2<T>{0, 0};
+  __syncthreads();
+  const int s0 = plane[i3], s1 = plane[i3 + 1];
+  const C2<T> *xb = X + (int64_t)(band0 + bl) * ldx;
+  const int off = i3 * nxy;
+  for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x) buf[box_index[idx] - off] = xb[idx];
+  __syncthreads();
+  lds_fft<T>(buf, plan.d[0], 1, n2, n1, tw1, +1);
+  lds_fft<T>(buf, plan.d[1], n1, n1, 1, tw2, +1);
+  C2<T> *dst = box + (int64_t)bl * nxy * n3 + off;
+  for (int i = threadIdx.x; i < nxy; i += blockDim.x) dst[i] = buf[i];
+}
+
+// ---- pass B: z pencils of one i2 slab, inverse FFT, * V, forward FFT -------
+template <typename T, typename VT>
+__global__ __launch_bounds__(512) void pass_b_kernel(C2<T> *__restrict__ box, const VT *__restrict__ V, BoxPlan plan,
+                              const double2 *__restrict__ twg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
+  const int n1 = plan.d[0].n, n2 = plan.d[1].n, n3 = plan.d[2].n;
+  const int nxz = n1 * n3;
+  C2<T> *tw3 = buf + nxz;
+  const int i2 = blockIdx.x;
+  const int bl = blockIdx.y;
+  load_twiddles<T>(tw3, twg + 2 * kMaxN, n3);
+  C2<T> *src = box + (int64_t)bl * n1 * n2 * n3;
+  for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
+    const int i1 = i % n1, i3 = i / n1;
+    buf[i] = src[i1 + n1 * (i2 + n2 * i3)];
+  }
+  __syncthreads();
+  lds_fft<T>(buf, plan.d[2], n1, n1, 1, tw3, +1);
+  for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
+    const int i1 = i % n1, i3 = i / n1;
+    buf[i] = cscale(buf[i], (T)V[i1 + n1 * (i2 + n2 * i3)]);
+  }
+  __syncthreads();
+  lds_fft<T>(buf, plan.d[2], n1, n1, 1, tw3, -1);
+  for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
+    const int i1 = i % n1, i3 = i / n1;
+    src[i1 + n1 * (i2 + n2 * i3)] = buf[i];
+  }
+}
+
+// ---- pass C: box plane -> forward xy FFT -> gather + recurrence combine ----
+template <typename T>
+__global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ box, BoxPlan plan,
+                              const double2 *__restrict__ twg,
+                              const int32_t *__restrict__ box_index,
+                              const int32_t *__restrict__ plane, const double *__restrict__ kin,
+                              int band0, const C2<T> *__restrict__ Yk, int64_t ldk,
+                              const C2<T> *__restrict__ Yprev, int64_t ldp,
+                              C2<T> *__restrict__ Out, int64_t ldo, T alpha, T cshift, T beta,
+                              T scale) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
+  const int n1 = plan.d[0].n, n2 = plan.d[1].n;
+  const int nxy = n1 * n2;
+  C2<T> *tw1 = buf + nxy;
+  C2<T> *tw2 = tw1 + n1;
+  const int i3 = blockIdx.x;
+  const int bl = blockIdx.y;
+  load_twiddles<T>(tw1, twg, n1);
+  load_twiddles<T>(tw2, twg + kMaxN, n2);
+  const int off = i3 * nxy;
+  const C2<T> *src = box + (int64_t)bl * nxy * plan.d[2].n + off;
+  for (int i = threadIdx.x; i < nxy; i += blockDim.x) buf[i] = src[i];
+  __syncthreads();
+  lds_fft<T>(buf, plan.d[1], n1, n1, 1, tw2, -1);
+  lds_fft<T>(buf, plan.d[0], 1, n2, n1, tw1, -1);
+  const int s0 = plane[i3], s1 = plane[i3 + 1];
+  const int64_t b = band0 + bl;
+  const C2<T> *yk = Yk + b * ldk;
+  C2<T> *out = Out + b * ldo;
+  if (Yprev != nullptr) {
+    const C2<T> *yp = Yprev + b * ldp;
+    for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x) {
+      C2<T> loc = cscale(buf[box_index[idx] - off], scale);
+      C2<T> x = yk[idx];
+      const T kd = (T)kin[idx] - cshift;
+      C2<T> h = cadd(loc, cscale(x, kd));
+      C2<T> p = yp[idx];
+      out[idx] = C2<T>{alpha * h.x - beta * p.x, alpha * h.y - beta * p.y};
+    }
+  } else {
+    for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x) {
+      C2<T> loc = cscale(buf[box_index[idx] - off], scale);
+      C2<T> x = yk[idx];
+      const T kd = (T)kin[idx] - cshift;
+      C2<T> h = cadd(loc, cscale(x, kd));
+      out[idx] = cscale(h, alpha);
+    }
+  }
+}
+
+int stage_threads(const Plan1D &pl, int npen) {
+  // smallest multiple of 64 threads with total butterflies <= kMaxB * threads
+  int need = 64;
+  for (int s = 0; s < pl.nstage; ++s) {
+    const int total = npen * (pl.n / pl.radix[s]);
+    const int t = (total + kMaxB - 1) / kMaxB;
+    if (t > need) need = t;
+  }
+  need = (need + 63) / 64 * 64;
+  if (need < 256) need = 256;
+  return need;
+}
+
+template <typename F> void set_lds(F kernel, size_t bytes) {
+  CHEBFI_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+}  // namespace
+
+template <typename T>
+void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Yprev,
+                            int64_t ldp, void *Out, int64_t ldo, int band0, int nb, void *box,
+                            const void *V, double alpha, double cshift, double beta,
+                            hipStream_t st) {
+  using V2 = C2<T>;
+  const BoxPlan &plan = s->plan;
+  const int n1 = plan.d[0].n, n2 = plan.d[1].n, n3 = plan.d[2].n;
+  const double2 *tw = reinterpret_cast<const double2 *>(s->d_tw);
+  const int tA = std::max(stage_threads(plan.d[0], n2), stage_threads(plan.d[1], n1));
+  const int tB = stage_threads(plan.d[2], n1);
+  CHEBFI_REQUIRE(tA <= 512 && tB <= 512, ABI_ERR_GRID, "FFT plane too large for one workgroup");
+  const size_t ldsA = sizeof(V2) * (size_t)(n1 * n2 + n1 + n2);
+  const size_t ldsB = sizeof(V2) * (size_t)(n1 * n3 + n3);
+  set_lds(pass_a_kernel<T>, ldsA);
+  set_lds(pass_c_kernel<T>, ldsA);
+  if (std::is_same<T, double>::value)
+    set_lds(pass_b_kernel<T, double>, ldsB);
+  else
+    set_lds(pass_b_kernel<T, float>, ldsB);
+  V2 *bx = reinterpret_cast<V2 *>(box);
+  hipLaunchKernelGGL(pass_a_kernel<T>, dim3(n3, nb), dim3(tA), ldsA, st,
+                     reinterpret_cast<const V2 *>(Yk), ldk, band0, s->d_box, s->d_plane, plan, tw,
+                     bx);
+  CHEBFI_HIP(hipGetLastError());
+  if (std::is_same<T, double>::value)
+    hipLaunchKernelGGL((pass_b_kernel<T, double>), dim3(n2, nb), dim3(tB), ldsB, st, bx,
+                       reinterpret_cast<const double *>(V), plan, tw);
+  else
+    hipLaunchKernelGGL((pass_b_kernel<T, float>), dim3(n2, nb), dim3(tB), ldsB, st, bx,
+                       reinterpret_cast<const float *>(V), plan, tw);
+  CHEBFI_HIP(hipGetLastError());
+  const T scale = (T)(1.0 / ((double)n1 * (double)n2 * (double)n3));
+  hipLaunchKernelGGL(pass_c_kernel<T>, dim3(n3, nb), dim3(tA), ldsA, st, bx, plan, tw, s->d_box,
+                     s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Yk), ldk,
+                     reinterpret_cast<const V2 *>(Yprev), ldp, reinterpret_cast<V2 *>(Out), ldo,
+                     (T)alpha, (T)cshift, (T)beta, scale);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+template void launch_local_potential<double>(const abi_system_s *, const void *, int64_t,
+                                             const void *, int64_t, void *, int64_t, int, int,
+                                             void *, const void *, double, double, double,
+                                             hipStream_t);
+template void launch_local_potential<float>(const abi_system_s *, const void *, int64_t,
+                                            const void *, int64_t, void *, int64_t, int, int,
+                                            void *, const void *, double, double, double,
+                                            hipStream_t);
+
+}  // namespace chebfi

@@ -1,0 +1,227 @@
+// Complex FP64 GEMM on the gfx950 matrix cores (v_mfma_f64_16x16x4_f64).
+//
+// Serves the dense contractions of the path: the nonlocal projections P^H X and
+// P (D C) (section "Low-level operations" of arXiv 2604.11139: level-3 BLAS for
+// the nonlocal operator), the Gram and subspace matrices Y^H Y, Y^H (H Y) and
+// the rotations Y Z (Algorithms "S-ortho" and "RR").  A complex product is four
+// real MFMA chains on separate real/imaginary LDS planes:
+//   Re C += Re A Re B - Im A Im B,  Im C += Re A Im B + Im A Re B.
+// Workgroup tile 64 x 64 complex, four waves of 32 x 32, K step 16; operands are
+// staged global -> registers -> LDS with the next K step's loads in flight
+// while the current one is multiplied.  Tall-skinny products (K = npw) are
+// split along K; each chunk writes its own partial product and a separate pass
+// adds the chunks in a fixed order, so results do not depend on scheduling.
+#include "cplx.h"
+#include "kernels.h"
+
+namespace chebfi {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;
+
+template <int OPA, int OPB, bool SPLIT>
+__global__ __launch_bounds__(256) void zgemm_kernel(int64_t m, int64_t n, int64_t k,
+                                                    const double2 *__restrict__ A, int64_t lda,
+                                                    const double2 *__restrict__ B, int64_t ldb,
+                                                    double2 *__restrict__ C, int64_t ldc,
+                                                    double2 alpha, double2 beta, int64_t kchunk,
+                                                    double2 *__restrict__ part) {
+  __shared__ double As[2][BK][BM + PAD];
+  __shared__ double Bs[2][BK][BN + PAD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int64_t row0 = (int64_t)blockIdx.x * BM, col0 = (int64_t)blockIdx.y * BN;
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = (kbeg + kchunk < k) ? kbeg + kchunk : k;
+
+  v4d acc_re[2][2], acc_im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc_re[i][j] = v4d{0, 0, 0, 0};
+      acc_im[i][j] = v4d{0, 0, 0, 0};
+    }
+
+  double2 ra[4], rb[4];
+  // Index maps: the thread-fastest index follows each operand's contiguous axis.
+  auto a_idx = [&](int c, int *kk, int *i) {
+    if (OPA == OP_N) {
+      *kk = tid >> 4;
+      *i = (tid & 15) + 16 * c;
+    } else {
+      *kk = tid & 15;
+      *i = (tid >> 4) + 16 * c;
+    }
+  };
+  auto b_idx = [&](int c, int *kk, int *j) {
+    if (OPB == OP_N) {
+      *kk = tid & 15;
+      *j = (tid >> 4) + 16 * c;
+    } else {
+      *kk = tid >> 4;
+      *j = (tid & 15) + 16 * c;
+    }
+  };
+  auto load_tiles = [&](int64_t k0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      int kk, i;
+      a_idx(c, &kk, &i);
+      const int64_t gr = row0 + i, gk = k0 + kk;
+      ra[c] = double2{0, 0};
+      if (gr < m && gk < kend) ra[c] = (OPA == OP_N) ? A[gr + gk * lda] : A[gk + gr * lda];
+      int j;
+      b_idx(c, &kk, &j);
+      const int64_t gc = col0 + j, gk2 = k0 + kk;
+      rb[c] = double2{0, 0};
+      if (gc < n && gk2 < kend) rb[c] = (OPB == OP_N) ? B[gk2 + gc * ldb] : B[gc + gk2 * ldb];
+    }
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      int kk, i;
+      a_idx(c, &kk, &i);
+      As[0][kk][i] = ra[c].x;
+      As[1][kk][i] = (OPA == OP_C) ? -ra[c].y : ra[c].y;
+      int j;
+      b_idx(c, &kk, &j);
+      Bs[0][kk][j] = rb[c].x;
+      Bs[1][kk][j] = (OPB == OP_C) ? -rb[c].y : rb[c].y;
+    }
+  };
+
+  if (kbeg < kend) load_tiles(kbeg);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    store_tiles();
+    __syncthreads();
+    if (k0 + BK < kend) load_tiles(k0 + BK);
+#pragma unroll
+    for (int kq = 0; kq < BK / 4; ++kq) {
+      const int kk = kq * 4 + (lane >> 4);
+      double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int ii = wm * 32 + s * 16 + (lane & 15);
+        ar[s] = As[0][kk][ii];
+        ai[s] = As[1][kk][ii];
+        const int jj = wn * 32 + s * 16 + (lane & 15);
+        br[s] = Bs[0][kk][jj];
+        bi[s] = Bs[1][kk][jj];
+      }
+#pragma unroll
+      for (int si = 0; si < 2; ++si)
+#pragma unroll
+        for (int sj = 0; sj < 2; ++sj) {
+          acc_re[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[si], br[sj], acc_re[si][sj], 0, 0, 0);
+          acc_im[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[si], bi[sj], acc_im[si][sj], 0, 0, 0);
+        }
+#pragma unroll
+      for (int si = 0; si < 2; ++si)
+#pragma unroll
+        for (int sj = 0; sj < 2; ++sj) {
+          acc_re[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[si], bi[sj], acc_re[si][sj], 0, 0, 0);
+          acc_im[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[si], br[sj], acc_im[si][sj], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+
+  // D layout of the 16x16 f64 MFMA: lane l, element r -> row l/16 + 4r, column l%16.
+  const bool use_beta = (beta.x != 0.0 || beta.y != 0.0);
+#pragma unroll
+  for (int si = 0; si < 2; ++si)
+#pragma unroll
+    for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + wm * 32 + si * 16 + (lane >> 4) + 4 * r;
+        const int64_t col = col0 + wn * 32 + sj * 16 + (lane & 15);
+        if (row < m && col < n) {
+          const double2 v{acc_re[si][sj][r], acc_im[si][sj][r]};
+          if (SPLIT) {
+            part[(int64_t)blockIdx.z * m * n + row + col * m] = v;
+          } else {
+            double2 o = cmul(alpha, v);
+            if (use_beta) o = cadd(o, cmul(beta, C[row + col * ldc]));
+            C[row + col * ldc] = o;
+          }
+        }
+      }
+}
+
+__global__ void zsum_parts_kernel(int64_t m, int64_t n, const double2 *__restrict__ part,
+                                  int splits, double2 *__restrict__ C, int64_t ldc, double2 alpha,
+                                  double2 beta) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * n) return;
+  const int64_t row = idx % m, col = idx / m;
+  double2 s{0, 0};
+  for (int z = 0; z < splits; ++z) s = cadd(s, part[(int64_t)z * m * n + idx]);
+  double2 o = cmul(alpha, s);
+  if (beta.x != 0.0 || beta.y != 0.0) o = cadd(o, cmul(beta, C[row + col * ldc]));
+  C[row + col * ldc] = o;
+}
+
+template <int OPA, int OPB>
+void launch_t(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
+              int64_t ldb, void *C, int64_t ldc, double2 alpha, double2 beta, hipStream_t st,
+              void *part, int splits) {
+  const int64_t chunk = part ? ((k + splits - 1) / splits + BK - 1) / BK * BK : k;
+  // every chunk index gets launched; a chunk past the end of K writes zeros
+  const int zs = part ? splits : 1;
+  dim3 grid((unsigned)((m + BM - 1) / BM), (unsigned)((n + BN - 1) / BN), (unsigned)zs);
+  if (part) {
+    hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, true>), grid, dim3(256), 0, st, m, n, k,
+                       (const double2 *)A, lda, (const double2 *)B, ldb, (double2 *)C, ldc,
+                       alpha, beta, chunk, (double2 *)part);
+    CHEBFI_HIP(hipGetLastError());
+  } else {
+    hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, false>), grid, dim3(256), 0, st, m, n, k,
+                       (const double2 *)A, lda, (const double2 *)B, ldb, (double2 *)C, ldc,
+                       alpha, beta, chunk, (double2 *)nullptr);
+    CHEBFI_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace
+
+int zgemm_splits(int64_t m, int64_t n, int64_t k) {
+  const int64_t tiles = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
+  int64_t s = (1024 + tiles - 1) / tiles;
+  const int64_t kmax = (k + 511) / 512;  // keep at least ~512 K per chunk
+  if (s > kmax) s = kmax;
+  if (s > 64) s = 64;
+  if (s < 1) s = 1;
+  return (int)s;
+}
+
+void zgemm(Op opa, Op opb, int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+           const void *B, int64_t ldb, void *C, int64_t ldc, double2 alpha, double2 beta,
+           hipStream_t st, void *part, int splits) {
+  if (m <= 0 || n <= 0) return;
+  if (opa == OP_N && opb == OP_N)
+    launch_t<OP_N, OP_N>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
+  else if (opa == OP_C && opb == OP_N)
+    launch_t<OP_C, OP_N>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
+  else if (opa == OP_N && opb == OP_C)
+    launch_t<OP_N, OP_C>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
+  else
+    launch_t<OP_C, OP_C>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
+}
+
+void zsum_parts(int64_t m, int64_t n, const void *part, int splits, void *C, int64_t ldc,
+                double2 alpha, double2 beta, hipStream_t st) {
+  const int64_t total = m * n;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(zsum_parts_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     m, n, (const double2 *)part, splits, (double2 *)C, ldc, alpha, beta);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+}  // namespace chebfi

@@ -1,0 +1,101 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/chebfi.h"
+
+namespace chebfi {
+
+// ---- errors ---------------------------------------------------------------
+void set_error(const std::string &msg);
+
+struct Error {
+  abi_status code;
+  std::string msg;
+};
+
+#define CHEBFI_HIP(call)                                                        \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess)                                                       \
+      throw ::chebfi::Error{ABI_ERR_DEVICE, std::string(#call) + ": " +        \
+                                                hipGetErrorString(e_)};         \
+  } while (0)
+
+#define CHEBFI_REQUIRE(cond, code, msg)                                         \
+  do {                                                                          \
+    if (!(cond)) throw ::chebfi::Error{(code), (msg)};                          \
+  } while (0)
+
+// ---- device buffers -------------------------------------------------------
+// A grow-only device allocation owned by the handle.
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  void *get(size_t need);  // (re)allocates when too small; contents not kept
+  void release();
+  ~DevBuf() { release(); }
+};
+
+// ---- FFT plan -------------------------------------------------------------
+constexpr int kMaxN = 64;       // largest box edge handled by the LDS passes
+constexpr int kMaxStages = 6;   // radix stages per 1D transform
+
+struct Plan1D {
+  int n = 0;
+  int nstage = 0;
+  int radix[kMaxStages] = {0};
+};
+
+bool make_plan(int n, Plan1D *p);  // false if n is not {2,3,5}-smooth
+
+// All 1D plans of a box, passed by value to the FFT kernels.
+struct BoxPlan {
+  Plan1D d[3];
+};
+
+// ---- host setup (system.cpp) ----------------------------------------------
+struct Sphere {
+  std::vector<int32_t> miller;     // npw*3
+  std::vector<int32_t> box_index;  // npw
+  std::vector<double> kinetic;     // npw
+  std::vector<double> qcart;       // npw*3, k+G
+  std::vector<double> gcart;       // npw*3, G
+};
+
+abi_status build_sphere(const abi_system_desc *d, Sphere *out, std::string *err);
+void reciprocal(const double lattice[9], double B[9]);
+void build_projectors(const abi_system_desc *d, const Sphere &s, std::vector<double> *P);
+
+}  // namespace chebfi
+
+// ---- the handle -----------------------------------------------------------
+struct abi_system_s {
+  int device = 0;
+  int n1 = 0, n2 = 0, n3 = 0;
+  int64_t npw = 0;
+  int natom = 0, nproj = 0;
+  int precision = ABI_PREC_FP64;
+  chebfi::Sphere sphere;
+  chebfi::BoxPlan plan;
+
+  // device tables
+  double *d_kin = nullptr;         // npw
+  int32_t *d_box = nullptr;        // npw, box index of each sphere point
+  int32_t *d_plane = nullptr;      // n3+1 sphere ranges per i3 plane
+  double *d_P = nullptr;           // npw x nproj complex (interleaved), ld = npw
+  double *d_D = nullptr;           // natom*16 complex, row-major per atom
+  double *d_V = nullptr;           // n1*n2*n3
+  double *d_tw = nullptr;          // 3 * kMaxN complex twiddles exp(-2 pi i j/n_d)
+
+  // work buffers
+  chebfi::DevBuf box, cpart, cprime, blk1, blk2, blk3, small1, small2, small3, small4, scal;
+  chebfi::DevBuf eig1, eig2, eig3;
+
+  int fft_batch = 0;  // bands per FFT batch (box buffer holds this many boxes)
+};

@@ -1,0 +1,90 @@
+// Host-side launchers of the HIP kernels (one declaration per kernel family).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <type_traits>
+
+#include "internal.h"
+
+namespace chebfi {
+
+enum Op { OP_N = 0, OP_C = 1 };  // op(X) = X or X^H
+
+// ---- fft.hip ----------------------------------------------------------------
+// Out[:, b] = alpha * (V_loc Yk[:, b] + (kin - cshift) Yk[:, b]) - beta * Yprev[:, b]
+// for b in [band0, band0 + nb); Yprev may be null (then beta is ignored).
+// `box` holds nb boxes; V is double (T = double) or float (T = float).
+template <typename T>
+void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Yprev,
+                            int64_t ldp, void *Out, int64_t ldo, int band0, int nb, void *box,
+                            const void *V, double alpha, double cshift, double beta,
+                            hipStream_t st);
+
+// ---- gemm.hip ---------------------------------------------------------------
+// C = alpha op(A) op(B) + beta C, complex double, column-major.  When `part`
+// is non-null the K range is split in `splits` chunks and chunk z writes its
+// raw product to part + z*m*n (ld = m); C, alpha and beta are then unused.
+void zgemm(Op opa, Op opb, int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+           const void *B, int64_t ldb, void *C, int64_t ldc, double2 alpha, double2 beta,
+           hipStream_t st, void *part = nullptr, int splits = 1);
+
+// Number of K splits that fills the chip for an m x n output.
+int zgemm_splits(int64_t m, int64_t n, int64_t k);
+
+// C = alpha * sum_z part[z] + beta C  (m x n, part ld = m)
+void zsum_parts(int64_t m, int64_t n, const void *part, int splits, void *C, int64_t ldc,
+                double2 alpha, double2 beta, hipStream_t st);
+
+// ---- stream.hip -------------------------------------------------------------
+// Cprime[4R+i, b] = alpha * sum_j D_R[i][j] * sum_z part[z][4R+j, b]
+void launch_dapply(int natom, int64_t nband, const void *part, int splits, const void *D,
+                   double alpha, void *Cprime, hipStream_t st);
+
+// rq[b] = Re(x_b^H hx_b) / (x_b^H x_b)
+void launch_rayleigh_quotients(int64_t npw, int64_t nband, const void *X, int64_t ldx,
+                               const void *HX, int64_t ldh, double *rq, hipStream_t st);
+// out[0] = max rq, out[2] = min rq
+void launch_minmax(int64_t n, const double *rq, double *out, hipStream_t st);
+
+// Lanczos helpers (vectors of npw complex doubles, scalars in device memory).
+void launch_dot_re(int64_t npw, const void *x, const void *y, double *out, hipStream_t st);
+void launch_axpy_dev(int64_t npw, const double *coef, double sign, const void *x, void *y,
+                     hipStream_t st);  // y += sign * (*coef) * x
+void launch_multi_dot(int64_t npw, int nvec, const void *V, int64_t ldv, const void *w,
+                      void *h, hipStream_t st);  // h[j] = v_j^H w
+void launch_multi_axpy(int64_t npw, int nvec, const void *V, int64_t ldv, const void *h,
+                       void *w, hipStream_t st);  // w -= V h
+void launch_norm(int64_t npw, const void *x, double *out, hipStream_t st);
+void launch_scale_inv(int64_t npw, const double *s, const void *x, void *y, hipStream_t st);
+// out[1] = theta_max(T(alpha, beta[0..k-2])) + (add_last ? beta[k-1] : 0)
+void launch_tridiag_bound(int k, const double *alpha, const double *beta, int add_last,
+                          double *out, hipStream_t st);
+
+// resnorm[b] = || HPsi[:, b] - eval[b] Psi[:, b] ||
+void launch_residual_norms(int64_t npw, int64_t nband, const void *Psi, int64_t ldp,
+                           const void *HPsi, int64_t ldh, const double *eval, double *res,
+                           hipStream_t st);
+
+// dense helpers (m x m complex double)
+void launch_hermitize(int64_t m, void *A, int64_t lda, hipStream_t st);  // A = (A + A^H)/2
+void launch_copy_block(int64_t rows, int64_t cols, const void *src, int64_t lds, void *dst,
+                       int64_t ldd, hipStream_t st);
+void launch_zero_lower(int64_t m, void *A, int64_t lda, hipStream_t st);
+
+// ---- dense.hip ----------------------------------------------------------------
+// Cholesky A = U^H U in place (upper); returns the failing pivot (1-based) via
+// *info_dev (0 = success).
+void zpotrf_upper(int64_t m, void *A, int64_t lda, int *info_dev, void *work, hipStream_t st);
+size_t zpotrf_work_bytes(int64_t m);
+// Inverse of an upper triangular matrix in place.
+void ztrtri_upper(int64_t m, void *A, int64_t lda, void *work, hipStream_t st);
+size_t ztrtri_work_bytes(int64_t m);
+// Hermitian eigensolver: A (m x m, overwritten) -> w ascending, Z.
+void zheev(int64_t m, void *A, int64_t lda, double *w, void *Z, int64_t ldz, void *work,
+           hipStream_t st);
+size_t zheev_work_bytes(int64_t m);
+
+}  // namespace chebfi

@@ -1,0 +1,357 @@
+// Bandwidth-bound helper kernels of the path: the per-atom D application of
+// the nonlocal operator, Rayleigh quotients and their extremes, the Lanczos
+// vector operations, residual norms and small dense-matrix utilities.
+//
+// Paper (arXiv 2604.11139): D_ij^R couples the projections of one atom
+// (section "Low-level operations"); the filter's bounds come from the minimum
+// and maximum Rayleigh quotient (section "Parallel implementation design",
+// Algorithm "Parallel Chebyshev filtering of degree k"); the cycle ends with
+// W = (H - Lambda S) Psi and its column norms.  All reductions run in a fixed
+// order inside one workgroup per result, so repeated runs agree bitwise.
+#include "cplx.h"
+#include "kernels.h"
+
+namespace chebfi {
+
+namespace {
+
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the workgroup; every thread receives the total.
+__device__ double block_sum(double v, double *scratch) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) scratch[wave] = v;
+  __syncthreads();
+  double t = 0;
+  for (int w = 0; w < nw; ++w) t += scratch[w];
+  return t;
+}
+
+__global__ void dapply_kernel(int natom, int64_t nband, const double2 *__restrict__ part,
+                              int splits, const double2 *__restrict__ D, double alpha,
+                              double2 *__restrict__ Cp) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)natom * nband) return;
+  const int64_t R = idx % natom, b = idx / natom;
+  const int64_t nproj = 4 * (int64_t)natom;
+  const int64_t mn = nproj * nband;
+  double2 c[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double2 s{0, 0};
+    for (int z = 0; z < splits; ++z) s = cadd(s, part[(int64_t)z * mn + (4 * R + j) + b * nproj]);
+    c[j] = s;
+  }
+  const double2 *d = D + 16 * R;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double2 s{0, 0};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s = cadd(s, cmul(d[4 * i + j], c[j]));
+    Cp[(4 * R + i) + b * nproj] = cscale(s, alpha);
+  }
+}
+
+__global__ void rq_kernel(int64_t npw, const double2 *__restrict__ X, int64_t ldx,
+                          const double2 *__restrict__ HX, int64_t ldh, double *__restrict__ rq) {
+  __shared__ double scratch[16];
+  const int64_t b = blockIdx.x;
+  const double2 *x = X + b * ldx;
+  const double2 *h = HX + b * ldh;
+  double num = 0, den = 0;
+  for (int64_t i = threadIdx.x; i < npw; i += blockDim.x) {
+    const double2 xv = x[i], hv = h[i];
+    num += xv.x * hv.x + xv.y * hv.y;
+    den += xv.x * xv.x + xv.y * xv.y;
+  }
+  num = block_sum(num, scratch);
+  den = block_sum(den, scratch);
+  if (threadIdx.x == 0) rq[b] = num / den;
+}
+
+__global__ void minmax_kernel(int64_t n, const double *__restrict__ v, double *__restrict__ out) {
+  __shared__ double smax[kRedThreads], smin[kRedThreads];
+  double mx = -1.0 / 0.0, mn = 1.0 / 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    mx = fmax(mx, v[i]);
+    mn = fmin(mn, v[i]);
+  }
+  smax[threadIdx.x] = mx;
+  smin[threadIdx.x] = mn;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = smax[0];
+    out[2] = smin[0];
+  }
+}
+
+__global__ void dot_re_kernel(int64_t npw, const double2 *__restrict__ x,
+                              const double2 *__restrict__ y, double *__restrict__ out) {
+  __shared__ double scratch[16];
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < npw; i += blockDim.x) {
+    const double2 a = x[i], b = y[i];
+    s += a.x * b.x + a.y * b.y;
+  }
+  s = block_sum(s, scratch);
+  if (threadIdx.x == 0) *out = s;
+}
+
+__global__ void norm_kernel(int64_t npw, const double2 *__restrict__ x, double *__restrict__ out) {
+  __shared__ double scratch[16];
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < npw; i += blockDim.x) {
+    const double2 a = x[i];
+    s += a.x * a.x + a.y * a.y;
+  }
+  s = block_sum(s, scratch);
+  if (threadIdx.x == 0) *out = sqrt(s);
+}
+
+__global__ void axpy_dev_kernel(int64_t npw, const double *__restrict__ coef, double sign,
+                                const double2 *__restrict__ x, double2 *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npw) return;
+  const double a = sign * (*coef);
+  const double2 xv = x[i];
+  double2 yv = y[i];
+  yv.x += a * xv.x;
+  yv.y += a * xv.y;
+  y[i] = yv;
+}
+
+__global__ void scale_inv_kernel(int64_t npw, const double *__restrict__ s,
+                                 const double2 *__restrict__ x, double2 *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npw) return;
+  const double inv = 1.0 / (*s);
+  y[i] = cscale(x[i], inv);
+}
+
+__global__ void multi_dot_kernel(int64_t npw, const double2 *__restrict__ V, int64_t ldv,
+                                 const double2 *__restrict__ w, double2 *__restrict__ h) {
+  __shared__ double scratch[16];
+  const int j = blockIdx.x;
+  const double2 *v = V + (int64_t)j * ldv;
+  double re = 0, im = 0;
+  for (int64_t i = threadIdx.x; i < npw; i += blockDim.x) {
+    const double2 a = v[i], b = w[i];
+    re += a.x * b.x + a.y * b.y;  // conj(a) * b
+    im += a.x * b.y - a.y * b.x;
+  }
+  re = block_sum(re, scratch);
+  im = block_sum(im, scratch);
+  if (threadIdx.x == 0) h[j] = double2{re, im};
+}
+
+__global__ void multi_axpy_kernel(int64_t npw, int nvec, const double2 *__restrict__ V,
+                                  int64_t ldv, const double2 *__restrict__ h,
+                                  double2 *__restrict__ w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npw) return;
+  double2 s = w[i];
+  for (int j = 0; j < nvec; ++j) s = csub(s, cmul(V[(int64_t)j * ldv + i], h[j]));
+  w[i] = s;
+}
+
+// Number of eigenvalues of the symmetric tridiagonal (d, e) below x (Sturm count).
+__device__ int sturm_count(int k, const double *d, const double *e, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  for (int i = 0; i < k; ++i) {
+    const double e2 = (i > 0) ? e[i - 1] * e[i - 1] : 0.0;
+    q = (d[i] - x) - ((i > 0) ? e2 / q : 0.0);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+__global__ void tridiag_bound_kernel(int k, const double *__restrict__ alpha,
+                                     const double *__restrict__ beta, int add_last,
+                                     double *__restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? fabs(beta[i - 1]) : 0.0) + (i < k - 1 ? fabs(beta[i]) : 0.0);
+    lo = fmin(lo, alpha[i] - r);
+    hi = fmax(hi, alpha[i] + r);
+  }
+  const double span = fmax(fabs(lo), fabs(hi));
+  lo -= 1e-12 * span + 1e-300;
+  hi += 1e-12 * span + 1e-300;
+  for (int it = 0; it < 400; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_count(k, alpha, beta, mid) >= k)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  double theta = 0.5 * (lo + hi);
+  if (k == 1) theta = alpha[0];
+  out[1] = theta + (add_last ? beta[k - 1] : 0.0);
+}
+
+__global__ void residual_kernel(int64_t npw, const double2 *__restrict__ Psi, int64_t ldp,
+                                const double2 *__restrict__ HPsi, int64_t ldh,
+                                const double *__restrict__ eval, double *__restrict__ res) {
+  __shared__ double scratch[16];
+  const int64_t b = blockIdx.x;
+  const double lam = eval[b];
+  const double2 *p = Psi + b * ldp;
+  const double2 *h = HPsi + b * ldh;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < npw; i += blockDim.x) {
+    const double2 pv = p[i], hv = h[i];
+    const double rx = hv.x - lam * pv.x, ry = hv.y - lam * pv.y;
+    s += rx * rx + ry * ry;
+  }
+  s = block_sum(s, scratch);
+  if (threadIdx.x == 0) res[b] = sqrt(s);
+}
+
+__global__ void hermitize_kernel(int64_t m, double2 *__restrict__ A, int64_t lda) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * m) return;
+  const int64_t i = idx % m, j = idx / m;
+  if (i > j) return;
+  if (i == j) {
+    A[i + j * lda].y = 0.0;
+    return;
+  }
+  const double2 a = A[i + j * lda], b = A[j + i * lda];
+  const double2 v{0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
+  A[i + j * lda] = v;
+  A[j + i * lda] = double2{v.x, -v.y};
+}
+
+__global__ void copy_block_kernel(int64_t rows, int64_t cols, const double2 *__restrict__ src,
+                                  int64_t lds, double2 *__restrict__ dst, int64_t ldd) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t i = idx % rows, j = idx / rows;
+  dst[i + j * ldd] = src[i + j * lds];
+}
+
+__global__ void zero_lower_kernel(int64_t m, double2 *__restrict__ A, int64_t lda) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * m) return;
+  const int64_t i = idx % m, j = idx / m;
+  if (i > j) A[i + j * lda] = double2{0, 0};
+}
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+void launch_dapply(int natom, int64_t nband, const void *part, int splits, const void *D,
+                   double alpha, void *Cprime, hipStream_t st) {
+  const int64_t total = (int64_t)natom * nband;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(dapply_kernel, dim3(nblk(total, 256)), dim3(256), 0, st, natom, nband,
+                     (const double2 *)part, splits, (const double2 *)D, alpha, (double2 *)Cprime);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_rayleigh_quotients(int64_t npw, int64_t nband, const void *X, int64_t ldx,
+                               const void *HX, int64_t ldh, double *rq, hipStream_t st) {
+  hipLaunchKernelGGL(rq_kernel, dim3((unsigned)nband), dim3(kRedThreads), 0, st, npw,
+                     (const double2 *)X, ldx, (const double2 *)HX, ldh, rq);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_minmax(int64_t n, const double *rq, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(minmax_kernel, dim3(1), dim3(kRedThreads), 0, st, n, rq, out);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_dot_re(int64_t npw, const void *x, const void *y, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(dot_re_kernel, dim3(1), dim3(1024), 0, st, npw, (const double2 *)x,
+                     (const double2 *)y, out);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_axpy_dev(int64_t npw, const double *coef, double sign, const void *x, void *y,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(axpy_dev_kernel, dim3(nblk(npw, 256)), dim3(256), 0, st, npw, coef, sign,
+                     (const double2 *)x, (double2 *)y);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_multi_dot(int64_t npw, int nvec, const void *V, int64_t ldv, const void *w, void *h,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(multi_dot_kernel, dim3((unsigned)nvec), dim3(1024), 0, st, npw,
+                     (const double2 *)V, ldv, (const double2 *)w, (double2 *)h);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_multi_axpy(int64_t npw, int nvec, const void *V, int64_t ldv, const void *h, void *w,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(multi_axpy_kernel, dim3(nblk(npw, 256)), dim3(256), 0, st, npw, nvec,
+                     (const double2 *)V, ldv, (const double2 *)h, (double2 *)w);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_norm(int64_t npw, const void *x, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(norm_kernel, dim3(1), dim3(1024), 0, st, npw, (const double2 *)x, out);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_scale_inv(int64_t npw, const double *s, const void *x, void *y, hipStream_t st) {
+  hipLaunchKernelGGL(scale_inv_kernel, dim3(nblk(npw, 256)), dim3(256), 0, st, npw, s,
+                     (const double2 *)x, (double2 *)y);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_tridiag_bound(int k, const double *alpha, const double *beta, int add_last,
+                          double *out, hipStream_t st) {
+  hipLaunchKernelGGL(tridiag_bound_kernel, dim3(1), dim3(64), 0, st, k, alpha, beta, add_last,
+                     out);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_residual_norms(int64_t npw, int64_t nband, const void *Psi, int64_t ldp,
+                           const void *HPsi, int64_t ldh, const double *eval, double *res,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(residual_kernel, dim3((unsigned)nband), dim3(kRedThreads), 0, st, npw,
+                     (const double2 *)Psi, ldp, (const double2 *)HPsi, ldh, eval, res);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_hermitize(int64_t m, void *A, int64_t lda, hipStream_t st) {
+  hipLaunchKernelGGL(hermitize_kernel, dim3(nblk(m * m, 256)), dim3(256), 0, st, m,
+                     (double2 *)A, lda);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_copy_block(int64_t rows, int64_t cols, const void *src, int64_t lds, void *dst,
+                       int64_t ldd, hipStream_t st) {
+  if (rows * cols <= 0) return;
+  hipLaunchKernelGGL(copy_block_kernel, dim3(nblk(rows * cols, 256)), dim3(256), 0, st, rows,
+                     cols, (const double2 *)src, lds, (double2 *)dst, ldd);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_zero_lower(int64_t m, void *A, int64_t lda, hipStream_t st) {
+  hipLaunchKernelGGL(zero_lower_kernel, dim3(nblk(m * m, 256)), dim3(256), 0, st, m,
+                     (double2 *)A, lda);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+}  // namespace chebfi

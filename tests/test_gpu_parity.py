@@ -1,0 +1,235 @@
+"""Parity of the HIP path against the FP64 oracle (needs an MI355X).
+
+Tolerances (FP64 path): H X per column ||diff|| / ||ref|| <= 1e-10; filter
+output per column <= 1e-9 (relative, a degree-m polynomial compounds
+rounding); bounds <= 1e-10 relative; Ritz values <= 1e-8 Ha absolute.
+Basis maps are compared bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from paper_2604_11139_amd import binding as B
+
+from gpu_util import SMALL, col_rel_err, hamiltonian, system, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    B.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def _sys(name, **kw):
+    return B.System(system(name, **kw))
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_tables(name):
+    H = hamiltonian(name)
+    with _sys(name) as g:
+        miller, box = g.gsphere()
+        assert np.array_equal(miller, H.sphere.miller)
+        assert np.array_equal(box.astype(np.int64), H.sphere.box_index)
+        P = to_host(g.projectors())
+        assert P.shape == H.P.shape
+        assert np.abs(P - H.P).max() <= 1e-14 * np.abs(H.P).max()
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_apply_H(name):
+    H = hamiltonian(name)
+    s = system(name)
+    X = W.random_block(H.npw, s.nband, s.tag)
+    with _sys(name) as g:
+        got = to_host(g.apply_H(to_dev(X)))
+    assert col_rel_err(got, H(X)) <= 1e-10
+
+
+@pytest.mark.parametrize("parts", ["local", "nonlocal", "free"])
+def test_apply_H_parts(parts):
+    scales = {"local": (1.0, 0.0), "nonlocal": (0.0, 100.0), "free": (0.0, 0.0)}[parts]
+    H = hamiltonian("n27", *scales)
+    s = system("n27", *scales)
+    X = W.random_block(H.npw, s.nband, 7)
+    with B.System(s) as g:
+        got = to_host(g.apply_H(to_dev(X)))
+    if parts == "free":
+        assert np.array_equal(got, H.sphere.kinetic[:, None] * X)
+    else:
+        ref = H(X)
+        part = H.local_apply(X) if parts == "local" else H.nonlocal_apply(X)
+        assert col_rel_err(got, ref) <= 1e-10
+        # the isolated part itself is resolved well above rounding
+        assert np.linalg.norm(got - H.kinetic_apply(X) - part) <= 1e-10 * np.linalg.norm(part)
+
+
+def test_apply_H_config2_ragged():
+    s = W.make_system(2)
+    H = O.Hamiltonian.from_system(s)
+    X = W.random_block(H.npw, 77, 2)  # 77 bands: one full 64-column tile and a ragged tail
+    with B.System(s) as g:
+        got = to_host(g.apply_H(to_dev(X)))
+    assert col_rel_err(got, H(X)) <= 1e-10
+
+
+@pytest.mark.parametrize("name,degree", [("tiny_k", 1), ("tiny_k", 2), ("odd15", 3), ("n27", 4),
+                                         ("c1", 8)])
+def test_cheb_filter(name, degree):
+    H = hamiltonian(name)
+    s = system(name)
+    X = W.random_block(H.npw, s.nband, s.tag)
+    v0 = W.random_vector(H.npw, s.tag)
+    a, b, a0 = O.filter_bounds(H, X, v0)
+    ref = O.cheb_filter(H, X, degree, a, b, a0)
+    with _sys(name) as g:
+        got = to_host(g.cheb_filter(to_dev(X), degree, a, b, a0))
+    assert col_rel_err(got, ref) <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["tiny_k", "n25", "c1"])
+def test_spectral_bounds(name):
+    H = hamiltonian(name)
+    s = system(name)
+    X = W.random_block(H.npw, s.nband, s.tag)
+    v0 = W.random_vector(H.npw, s.tag)
+    ref = O.filter_bounds(H, X, v0)
+    with _sys(name) as g:
+        got = g.spectral_bounds(to_dev(X), to_dev(v0))
+    for x, y in zip(got, ref):
+        assert abs(x - y) <= 1e-10 * max(1.0, abs(y))
+
+
+def test_spectral_bounds_invariant_start():
+    """Lanczos from an eigenvector stops after one step: b = its eigenvalue."""
+    s = system("c1", 0.0, 0.0)
+    H = hamiltonian("c1", 0.0, 0.0)
+    X = W.random_block(H.npw, 4, 1)
+    v0 = np.zeros(H.npw, dtype=np.complex128)
+    v0[11] = 2.0
+    ref = O.filter_bounds(H, X, v0)
+    with B.System(s) as g:
+        got = g.spectral_bounds(to_dev(X), to_dev(v0))
+    assert abs(got[1] - H.sphere.kinetic[11]) <= 1e-12 and abs(ref[1] - got[1]) <= 1e-12
+
+
+def _principal_sines(A, B_):
+    qa, _ = np.linalg.qr(A)
+    qb, _ = np.linalg.qr(B_)
+    s = np.linalg.svd(qa.conj().T @ qb, compute_uv=False)
+    return np.sqrt(np.maximum(0.0, 1.0 - np.min(s) ** 2))
+
+
+@pytest.mark.parametrize("name", ["odd15", "n27", "c1"])
+def test_rayleigh_ritz(name):
+    H = hamiltonian(name)
+    s = system(name)
+    X = W.random_block(H.npw, s.nband, s.tag)
+    v0 = W.random_vector(H.npw, s.tag)
+    a, b, a0 = O.filter_bounds(H, X, v0)
+    Y = O.cheb_filter(H, X, 6, a, b, a0)
+    rr = O.rayleigh_ritz(H, Y)
+    res_ref = O.residual_norms(rr["Psi"], rr["HPsi"], rr["eval"])
+    import torch
+    with _sys(name) as g:
+        Yd = to_dev(Y)
+        hp = torch.empty_like(Yd)
+        ev, res, flags = g.rayleigh_ritz(Yd, hp)
+        Psi = to_host(Yd)
+        HPsi = to_host(hp)
+    assert flags == 0
+    assert np.abs(ev - rr["eval"]).max() <= 1e-8
+    assert np.abs(Psi.conj().T @ Psi - np.eye(s.nband)).max() <= 1e-9
+    assert np.abs(res - res_ref).max() <= 1e-8
+    assert col_rel_err(HPsi, H(Psi)) <= 1e-9
+    # same lowest invariant subspace where the spectrum has a gap
+    lam = rr["eval"]
+    gaps = np.diff(lam[: s.nband // 2 + 1])
+    p = int(np.argmax(gaps)) + 1
+    assert _principal_sines(Psi[:, :p], rr["Psi"][:, :p]) <= 1e-7
+
+
+def test_rayleigh_ritz_rank_deficient():
+    s = system("tiny_k")
+    H = hamiltonian("tiny_k")
+    X = W.random_block(H.npw, 6, 3)
+    X[:, 5] = X[:, 1]  # duplicate column: Gram matrix singular
+    with B.System(s) as g:
+        with pytest.raises(B.ChebfiError) as e:
+            g.rayleigh_ritz(to_dev(X))
+    assert e.value.code == B.ABI_ERR_NOT_HPD
+
+
+@pytest.mark.parametrize("m", [1, 2, 7, 33, 64, 130, 300])
+def test_zheev(m):
+    import torch
+    rng = np.random.default_rng(m)
+    A = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    A = A + A.conj().T
+    w, Z = B.zheev(torch.from_numpy(A).cuda())
+    w = w.cpu().numpy()
+    Z = Z.cpu().numpy()
+    ref = np.linalg.eigvalsh(A)
+    scale = np.abs(ref).max()
+    assert np.abs(w - ref).max() <= 1e-12 * scale * max(1, np.sqrt(m))
+    assert np.abs(A @ Z - Z * w[None, :]).max() <= 1e-11 * scale
+    assert np.abs(Z.conj().T @ Z - np.eye(m)).max() <= 1e-11
+
+
+def test_zheev_degenerate():
+    import torch
+    rng = np.random.default_rng(9)
+    m = 40
+    Q, _ = np.linalg.qr(rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)))
+    lam = np.repeat(np.arange(8, dtype=np.float64), 5)  # 8 five-fold clusters
+    A = (Q * lam[None, :]) @ Q.conj().T
+    w, Z = B.zheev(torch.from_numpy(A).cuda())
+    w = w.cpu().numpy()
+    Z = Z.cpu().numpy()
+    assert np.abs(w - lam).max() <= 1e-12 * 8
+    assert np.abs(A @ Z - Z * w[None, :]).max() <= 1e-11 * 8
+    assert np.abs(Z.conj().T @ Z - np.eye(m)).max() <= 1e-11
+
+
+@pytest.mark.parametrize("m", [1, 31, 33, 100, 257])
+def test_zpotrf(m):
+    import scipy.linalg
+    import torch
+    rng = np.random.default_rng(100 + m)
+    X = rng.standard_normal((m + 5, m)) + 1j * rng.standard_normal((m + 5, m))
+    G = X.conj().T @ X
+    U = B.zpotrf_upper(torch.from_numpy(G).cuda()).cpu().numpy()
+    ref = scipy.linalg.cholesky(G, lower=False)
+    assert np.abs(U - ref).max() <= 1e-12 * np.abs(ref).max() * max(1.0, np.sqrt(m))
+
+
+def test_zpotrf_not_hpd():
+    import torch
+    G = np.eye(40, dtype=np.complex128)
+    G[17, 17] = -1.0
+    with pytest.raises(B.ChebfiError) as e:
+        B.zpotrf_upper(torch.from_numpy(G).cuda())
+    assert e.value.code == B.ABI_ERR_NOT_HPD
+    assert "18" in str(e.value)
+
+
+def test_argument_errors():
+    import torch
+    s = system("tiny_k")
+    with B.System(s) as g:
+        X = torch.zeros((4, g.npw), dtype=torch.complex128, device="cuda")
+        with pytest.raises(B.ChebfiError) as e:
+            g.cheb_filter(X, 0, 1.0, 2.0, 0.0)
+        assert e.value.code == B.ABI_ERR_ARG
+        with pytest.raises(B.ChebfiError) as e:
+            g.cheb_filter(X, 3, 2.0, 1.0, 0.0)
+        assert e.value.code == B.ABI_ERR_ARG
+        with pytest.raises(B.ChebfiError) as e:
+            g.cheb_filter(X, 3, 1.0, 2.0, 1.5)
+        assert e.value.code == B.ABI_ERR_ARG
