@@ -165,6 +165,25 @@ abi_status abi_zpotrf_upper(int64_t m, void *A, int64_t lda, void *stream);
 abi_status abi_zheev(int64_t m, void *A, int64_t lda, double *w, void *Z, int64_t ldz,
                      void *stream);
 
+/* ---- timing ------------------------------------------------------------------
+ * Per-kernel-class timing with HIP events recorded on the stream of each call
+ * (the method of the paper's section "Single-step benchmarks: GPU kernel
+ * rooflines": time and algorithmic work aggregated per code section).
+ * Classes: 0 projection GEMM P^H X, 1 expansion GEMM P C', 2-4 FFT passes
+ * A/B/C, 5 split-K sum + D (classes 0-5 count the launches inside
+ * abi_cheb_filter only), 6 Gram and subspace GEMMs, 7 Cholesky + inverse +
+ * reduction, 8 eigensolver, 9 rotations (classes 6-9: abi_rayleigh_ritz).  `work` is the algorithmic flop count
+ * (GEMM, dense classes) or HBM byte count (FFT passes) of the timed launches. */
+
+/* Turns timing on or off and clears the accumulated figures. */
+abi_status abi_profile_enable(abi_system sys, int32_t on);
+
+/* Waits for the recorded events and returns, for classes 0..nclass-1, the
+ * summed milliseconds, summed work and number of timed launches (host arrays of
+ * nclass entries; classes past the last one read as zero). */
+abi_status abi_profile_read(abi_system sys, int32_t nclass, double *total_ms, double *work,
+                            int64_t *count);
+
 const char *abi_last_error(void);
 
 #ifdef __cplusplus

@@ -35,8 +35,11 @@ EXPORTS = [
     "abi_gsphere_count", "abi_gsphere_build", "abi_set_system", "abi_system_info",
     "abi_get_gsphere", "abi_get_projectors", "abi_destroy", "abi_apply_H",
     "abi_spectral_bounds", "abi_cheb_filter", "abi_rayleigh_ritz", "abi_zpotrf_upper",
-    "abi_zheev", "abi_last_error",
+    "abi_zheev", "abi_profile_enable", "abi_profile_read", "abi_last_error",
 ]
+
+PROFILE_CLASSES = ["proj_gemm", "expand_gemm", "fft_a", "fft_b", "fft_c", "dapply", "gram",
+                   "chol", "eig", "rot"]
 
 
 class ChebfiError(RuntimeError):
@@ -89,6 +92,8 @@ def lib():
         "abi_rayleigh_ritz": [vp, vp, vp, c_int64, c_int64, vp, vp, vp, vp],
         "abi_zpotrf_upper": [c_int64, vp, c_int64, vp],
         "abi_zheev": [c_int64, vp, c_int64, vp, vp, c_int64, vp],
+        "abi_profile_enable": [vp, c_int32],
+        "abi_profile_read": [vp, c_int32, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -246,6 +251,19 @@ class System:
         _check(lib().abi_spectral_bounds(self._h, px, nb, ld, ABI_C128, pv, int(nlanczos), out,
                                          _stream()))
         return float(out[0]), float(out[1]), float(out[2])
+
+    def profile(self, on=True):
+        _check(lib().abi_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """{class: (total_ms, work, count)} for the launches timed so far."""
+        n = len(PROFILE_CLASSES)
+        ms = np.zeros(n)
+        wk = np.zeros(n)
+        ct = np.zeros(n, dtype=np.int64)
+        _check(lib().abi_profile_read(self._h, n, ms.ctypes.data_as(c_void_p),
+                                      wk.ctypes.data_as(c_void_p), ct.ctypes.data_as(c_void_p)))
+        return {c: (float(ms[i]), float(wk[i]), int(ct[i])) for i, c in enumerate(PROFILE_CLASSES)}
 
     def rayleigh_ritz(self, Y, hpsi=None):
         """In place: Y <- Ritz vectors.  Returns (eval, resnorm, flags)."""

@@ -40,6 +40,53 @@ void DevBuf::release() {
   bytes = 0;
 }
 
+hipEvent_t Profiler::take() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  CHEBFI_HIP(hipEventCreate(&e));
+  return e;
+}
+
+int Profiler::begin(int cls, double w, hipStream_t st) {
+  if (!on) return -1;
+  if (cls <= PROF_DAPPLY && !in_filter) return -1;  // H-application classes: filter only
+  Rec r{cls, take(), take(), w};
+  CHEBFI_HIP(hipEventRecord(r.a, st));
+  pending.push_back(r);
+  return (int)pending.size() - 1;
+}
+
+void Profiler::end(int token, hipStream_t st) {
+  if (!on || token < 0) return;
+  CHEBFI_HIP(hipEventRecord(pending[token].b, st));
+}
+
+void Profiler::collect() {
+  for (Rec &r : pending) {
+    CHEBFI_HIP(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    CHEBFI_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    total_ms[r.cls] += ms;
+    work[r.cls] += r.work;
+    count[r.cls] += 1;
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  pending.clear();
+}
+
+Profiler::~Profiler() {
+  for (Rec &r : pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
 }  // namespace chebfi
 
 using namespace chebfi;
@@ -126,14 +173,22 @@ void apply_core(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, 
   const int nproj = s->nproj;
   int splits = 1;
   double2 *cpart = nullptr, *cprime = nullptr;
+  const bool single = (nband == 1);
   if (nproj > 0) {
-    splits = zgemm_splits(nproj, nband, npw);
+    splits = single ? 1 : zgemm_splits(nproj, nband, npw);
     cpart = (double2 *)s->cpart.get(sizeof(double2) * (size_t)splits * nproj * nband);
     cprime = (double2 *)s->cprime.get(sizeof(double2) * (size_t)nproj * nband);
     // C = P^H X (split along the plane waves), C' = alpha D C
-    zgemm(OP_C, OP_N, nproj, nband, npw, s->d_P, npw, X, ldx, nullptr, 0, double2{1, 0},
-          double2{0, 0}, st, cpart, splits);
+    const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
+    int tok = s->prof.begin(PROF_PROJ, flops, st);
+    if (single)
+      proj_gemv(npw, nproj, s->d_P, X, cpart, st);
+    else
+      proj_gemm(nproj, nband, npw, s->d_P, X, ldx, cpart, splits, st);
+    s->prof.end(tok, st);
+    tok = s->prof.begin(PROF_DAPPLY, 16.0 * (double)nproj * nband * (splits + 1), st);
     launch_dapply(s->natom, nband, cpart, splits, s->d_D, alpha, cprime, st);
+    s->prof.end(tok, st);
   }
   const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
   const int fb = (int)std::min<int64_t>(s->fft_batch, nband);
@@ -141,12 +196,17 @@ void apply_core(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, 
   for (int64_t b0 = 0; b0 < nband; b0 += fb) {
     const int nb = (int)std::min<int64_t>(fb, nband - b0);
     launch_local_potential<double>(s, X, ldx, Xprev, ldp, Out, ldo, (int)b0, nb, box, s->d_V,
-                                   alpha, cshift, beta, st);
+                                   alpha, cshift, beta, st, s->prof.on ? &s->prof : nullptr);
   }
   if (nproj > 0) {
     // Out += P C'
-    zgemm(OP_N, OP_N, npw, nband, nproj, s->d_P, npw, cprime, nproj, Out, ldo, double2{1, 0},
-          double2{1, 0}, st);
+    const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
+    int tok = s->prof.begin(PROF_EXPAND, flops, st);
+    if (single)
+      expand_gemv(npw, nproj, s->d_P, cprime, Out, st);
+    else
+      expand_gemm(npw, nband, nproj, s->d_P, cprime, Out, ldo, st);
+    s->prof.end(tok, st);
   }
 }
 
@@ -317,6 +377,11 @@ abi_status abi_cheb_filter(abi_system s, const void *X, void *Y, int64_t nband, 
     if (degree >= 2) bufs[1] = s->blk1.get(sizeof(double2) * (size_t)npw * nband);
     if (degree >= 3) bufs[2] = s->blk2.get(sizeof(double2) * (size_t)npw * nband);
     auto slot = [&](int j) { return (degree - j) % 3; };
+    struct Scope {
+      Profiler &p;
+      explicit Scope(Profiler &q) : p(q) { p.in_filter = true; }
+      ~Scope() { p.in_filter = false; }
+    } scope(s->prof);
     // Y_1 = (s1/e)(H - c) X
     apply_core(s, X, ld, nullptr, 0, bufs[slot(1)], lds[slot(1)], nband, s1 / e, c, 0.0, st);
     double sk = s1;
@@ -407,11 +472,16 @@ abi_status abi_rayleigh_ritz(abi_system s, void *Y, void *HPsi, int64_t nband, i
     // Gram G = Y^H Y -> U (Cholesky, upper)
     int splits = zgemm_splits(M, M, npw);
     void *part = s->cpart.get(sizeof(double2) * (size_t)splits * M * M);
+    const double gflops = 8.0 * (double)M * M * npw;
+    int tok = s->prof.begin(PROF_GRAM, gflops, st);
     zgemm(OP_C, OP_N, M, M, npw, Y, ld, Y, ld, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
           splits);
     zsum_parts(M, M, part, splits, G, M, double2{1, 0}, double2{0, 0}, st);
+    s->prof.end(tok, st);
     launch_hermitize(M, G, M, st);
+    tok = s->prof.begin(PROF_CHOL, 4.0 / 3.0 * (double)M * M * M, st);
     zpotrf_upper(M, G, M, info, nullptr, st);
+    s->prof.end(tok, st);
     int hinfo = 0;
     CHEBFI_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, st));
     CHEBFI_HIP(hipStreamSynchronize(st));
@@ -422,18 +492,25 @@ abi_status abi_rayleigh_ritz(abi_system s, void *Y, void *HPsi, int64_t nband, i
     double2 *HY = (double2 *)s->blk1.get(sizeof(double2) * (size_t)npw * M);
     apply_core(s, Y, ld, nullptr, 0, HY, npw, M, 1.0, 0.0, 0.0, st);
     part = s->cpart.get(sizeof(double2) * (size_t)splits * M * M);  // apply_core may regrow it
+    tok = s->prof.begin(PROF_GRAM, gflops, st);
     zgemm(OP_C, OP_N, M, M, npw, Y, ld, HY, npw, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
           splits);
     zsum_parts(M, M, part, splits, Hs, M, double2{1, 0}, double2{0, 0}, st);
+    s->prof.end(tok, st);
     launch_hermitize(M, Hs, M, st);
     // U^-1 and the reduced matrix U^-H H_s U^-1
+    tok = s->prof.begin(PROF_CHOL, 16.0 * (double)M * M * M, st);
     void *trw = s->eig2.get(ztrtri_work_bytes(M));
     ztrtri_upper(M, G, M, trw, st);
     zgemm(OP_N, OP_N, M, M, M, Hs, M, G, M, T, M, double2{1, 0}, double2{0, 0}, st);
     zgemm(OP_C, OP_N, M, M, M, G, M, T, M, Hs, M, double2{1, 0}, double2{0, 0}, st);
+    s->prof.end(tok, st);
     // eigen-decomposition (Hs overwritten), W = U^-1 Z
     void *ew = s->eig1.get(zheev_work_bytes(M));
+    tok = s->prof.begin(PROF_EIG, 16.0 / 3.0 * (double)M * M * M, st);
     zheev(M, Hs, M, w_dev, Z, M, ew, st);
+    s->prof.end(tok, st);
+    tok = s->prof.begin(PROF_ROT, 8.0 * (double)M * M * M + 16.0 * (double)npw * M * M, st);
     zgemm(OP_N, OP_N, M, M, M, G, M, Z, M, T, M, double2{1, 0}, double2{0, 0}, st);
     // Psi = Y W, H Psi = (H Y) W
     double2 *Psi = (double2 *)s->blk2.get(sizeof(double2) * (size_t)npw * M);
@@ -448,6 +525,7 @@ abi_status abi_rayleigh_ritz(abi_system s, void *Y, void *HPsi, int64_t nband, i
       ldh = npw;
     }
     zgemm(OP_N, OP_N, npw, M, M, HY, npw, T, M, HP, ldh, double2{1, 0}, double2{0, 0}, st);
+    s->prof.end(tok, st);
     launch_copy_block(npw, M, Psi, npw, Y, ld, st);
     launch_residual_norms(npw, M, Y, ld, HP, ldh, w_dev, r_dev, st);
     CHEBFI_HIP(hipMemcpyAsync(eval, w_dev, sizeof(double) * M, hipMemcpyDeviceToHost, st));
@@ -455,6 +533,33 @@ abi_status abi_rayleigh_ritz(abi_system s, void *Y, void *HPsi, int64_t nband, i
       CHEBFI_HIP(hipMemcpyAsync(resnorm, r_dev, sizeof(double) * M, hipMemcpyDeviceToHost, st));
     CHEBFI_HIP(hipStreamSynchronize(st));
     if (flags) *flags = 0;
+  });
+}
+
+abi_status abi_profile_enable(abi_system s, int32_t on) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(s != nullptr, ABI_ERR_ARG, "system handle is NULL");
+    s->prof.collect();
+    for (int c = 0; c < PROF_NCLASS; ++c) {
+      s->prof.total_ms[c] = 0;
+      s->prof.work[c] = 0;
+      s->prof.count[c] = 0;
+    }
+    s->prof.on = (on != 0);
+  });
+}
+
+abi_status abi_profile_read(abi_system s, int32_t nclass, double *total_ms, double *work,
+                            int64_t *count) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(s != nullptr && total_ms && work && count, ABI_ERR_ARG, "NULL argument");
+    s->prof.collect();
+    for (int c = 0; c < nclass; ++c) {
+      const bool ok = c < PROF_NCLASS;
+      total_ms[c] = ok ? s->prof.total_ms[c] : 0.0;
+      work[c] = ok ? s->prof.work[c] : 0.0;
+      count[c] = ok ? s->prof.count[c] : 0;
+    }
   });
 }
 

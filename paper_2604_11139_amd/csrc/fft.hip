@@ -292,7 +292,7 @@ template <typename T>
 void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Yprev,
                             int64_t ldp, void *Out, int64_t ldo, int band0, int nb, void *box,
                             const void *V, double alpha, double cshift, double beta,
-                            hipStream_t st) {
+                            hipStream_t st, Profiler *prof) {
   using V2 = C2<T>;
   const BoxPlan &plan = s->plan;
   const int n1 = plan.d[0].n, n2 = plan.d[1].n, n3 = plan.d[2].n;
@@ -309,10 +309,18 @@ void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, 
   else
     set_lds(pass_b_kernel<T, float>, ldsB);
   V2 *bx = reinterpret_cast<V2 *>(box);
+  // algorithmic HBM bytes of each pass (sphere rows, box planes, V once)
+  const double es = (double)sizeof(V2), nbx = (double)n1 * n2 * n3, np = (double)s->npw;
+  const double bytesA = nb * (np + nbx) * es;
+  const double bytesB = nb * 2.0 * nbx * es + nbx * (double)sizeof(T);
+  const double bytesC = nb * (nbx + np * (Yprev ? 3.0 : 2.0)) * es;
+  int tok = prof ? prof->begin(PROF_FFT_A, bytesA, st) : -1;
   hipLaunchKernelGGL(pass_a_kernel<T>, dim3(n3, nb), dim3(tA), ldsA, st,
                      reinterpret_cast<const V2 *>(Yk), ldk, band0, s->d_box, s->d_plane, plan, tw,
                      bx);
   CHEBFI_HIP(hipGetLastError());
+  if (prof) prof->end(tok, st);
+  tok = prof ? prof->begin(PROF_FFT_B, bytesB, st) : -1;
   if (std::is_same<T, double>::value)
     hipLaunchKernelGGL((pass_b_kernel<T, double>), dim3(n2, nb), dim3(tB), ldsB, st, bx,
                        reinterpret_cast<const double *>(V), plan, tw);
@@ -320,21 +328,24 @@ void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, 
     hipLaunchKernelGGL((pass_b_kernel<T, float>), dim3(n2, nb), dim3(tB), ldsB, st, bx,
                        reinterpret_cast<const float *>(V), plan, tw);
   CHEBFI_HIP(hipGetLastError());
+  if (prof) prof->end(tok, st);
+  tok = prof ? prof->begin(PROF_FFT_C, bytesC, st) : -1;
   const T scale = (T)(1.0 / ((double)n1 * (double)n2 * (double)n3));
   hipLaunchKernelGGL(pass_c_kernel<T>, dim3(n3, nb), dim3(tA), ldsA, st, bx, plan, tw, s->d_box,
                      s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Yk), ldk,
                      reinterpret_cast<const V2 *>(Yprev), ldp, reinterpret_cast<V2 *>(Out), ldo,
                      (T)alpha, (T)cshift, (T)beta, scale);
   CHEBFI_HIP(hipGetLastError());
+  if (prof) prof->end(tok, st);
 }
 
 template void launch_local_potential<double>(const abi_system_s *, const void *, int64_t,
                                              const void *, int64_t, void *, int64_t, int, int,
                                              void *, const void *, double, double, double,
-                                             hipStream_t);
+                                             hipStream_t, Profiler *);
 template void launch_local_potential<float>(const abi_system_s *, const void *, int64_t,
                                             const void *, int64_t, void *, int64_t, int, int,
                                             void *, const void *, double, double, double,
-                                            hipStream_t);
+                                            hipStream_t, Profiler *);
 
 }  // namespace chebfi

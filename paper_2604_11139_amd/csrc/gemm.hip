@@ -22,7 +22,9 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;
 
-template <int OPA, int OPB, bool SPLIT>
+// TAG only separates instantiations (1 = projector products of the H
+// application) so that kernel traces report them apart from the dense ones.
+template <int OPA, int OPB, bool SPLIT, int TAG>
 __global__ __launch_bounds__(256) void zgemm_kernel(int64_t m, int64_t n, int64_t k,
                                                     const double2 *__restrict__ A, int64_t lda,
                                                     const double2 *__restrict__ B, int64_t ldb,
@@ -168,7 +170,7 @@ __global__ void zsum_parts_kernel(int64_t m, int64_t n, const double2 *__restric
   C[row + col * ldc] = o;
 }
 
-template <int OPA, int OPB>
+template <int OPA, int OPB, int TAG>
 void launch_t(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
               int64_t ldb, void *C, int64_t ldc, double2 alpha, double2 beta, hipStream_t st,
               void *part, int splits) {
@@ -177,12 +179,12 @@ void launch_t(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda, const
   const int zs = part ? splits : 1;
   dim3 grid((unsigned)((m + BM - 1) / BM), (unsigned)((n + BN - 1) / BN), (unsigned)zs);
   if (part) {
-    hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, true>), grid, dim3(256), 0, st, m, n, k,
+    hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, true, TAG>), grid, dim3(256), 0, st, m, n, k,
                        (const double2 *)A, lda, (const double2 *)B, ldb, (double2 *)C, ldc,
                        alpha, beta, chunk, (double2 *)part);
     CHEBFI_HIP(hipGetLastError());
   } else {
-    hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, false>), grid, dim3(256), 0, st, m, n, k,
+    hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, false, TAG>), grid, dim3(256), 0, st, m, n, k,
                        (const double2 *)A, lda, (const double2 *)B, ldb, (double2 *)C, ldc,
                        alpha, beta, chunk, (double2 *)nullptr);
     CHEBFI_HIP(hipGetLastError());
@@ -206,13 +208,82 @@ void zgemm(Op opa, Op opb, int64_t m, int64_t n, int64_t k, const void *A, int64
            hipStream_t st, void *part, int splits) {
   if (m <= 0 || n <= 0) return;
   if (opa == OP_N && opb == OP_N)
-    launch_t<OP_N, OP_N>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
+    launch_t<OP_N, OP_N, 0>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
   else if (opa == OP_C && opb == OP_N)
-    launch_t<OP_C, OP_N>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
+    launch_t<OP_C, OP_N, 0>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
   else if (opa == OP_N && opb == OP_C)
-    launch_t<OP_N, OP_C>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
+    launch_t<OP_N, OP_C, 0>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
   else
-    launch_t<OP_C, OP_C>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
+    launch_t<OP_C, OP_C, 0>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
+}
+
+void proj_gemm(int64_t nproj, int64_t nband, int64_t npw, const void *P, const void *X,
+               int64_t ldx, void *part, int splits, hipStream_t st) {
+  launch_t<OP_C, OP_N, 1>(nproj, nband, npw, P, npw, X, ldx, nullptr, 0, double2{1, 0},
+                          double2{0, 0}, st, part, splits);
+}
+
+void expand_gemm(int64_t npw, int64_t nband, int64_t nproj, const void *P, const void *Cp,
+                 void *Out, int64_t ldo, hipStream_t st) {
+  launch_t<OP_N, OP_N, 1>(npw, nband, nproj, P, npw, Cp, nproj, Out, ldo, double2{1, 0},
+                          double2{1, 0}, st, nullptr, 1);
+}
+
+namespace {
+
+// c[j] = sum_i conj(P[i, j]) x[i]: one workgroup per projector (single band).
+__global__ __launch_bounds__(256) void proj_gemv_kernel(int64_t npw, const double2 *__restrict__ P,
+                                                        const double2 *__restrict__ x,
+                                                        double2 *__restrict__ c) {
+  __shared__ double sr[4], si[4];
+  const int64_t j = blockIdx.x;
+  const double2 *p = P + j * npw;
+  double re = 0, im = 0;
+  for (int64_t i = threadIdx.x; i < npw; i += blockDim.x) {
+    const double2 a = p[i], b = x[i];
+    re += a.x * b.x + a.y * b.y;
+    im += a.x * b.y - a.y * b.x;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sr[threadIdx.x >> 6] = re;
+    si[threadIdx.x >> 6] = im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) c[j] = double2{sr[0] + sr[1] + sr[2] + sr[3], si[0] + si[1] + si[2] + si[3]};
+}
+
+// out[i] += sum_j P[i, j] c[j]: one thread per plane wave (single band).
+__global__ __launch_bounds__(256) void expand_gemv_kernel(int64_t npw, int nproj,
+                                                          const double2 *__restrict__ P,
+                                                          const double2 *__restrict__ c,
+                                                          double2 *__restrict__ out) {
+  extern __shared__ double2 cs[];
+  for (int j = threadIdx.x; j < nproj; j += blockDim.x) cs[j] = c[j];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npw) return;
+  double2 s = out[i];
+  for (int j = 0; j < nproj; ++j) s = cadd(s, cmul(P[i + (int64_t)j * npw], cs[j]));
+  out[i] = s;
+}
+
+}  // namespace
+
+void proj_gemv(int64_t npw, int nproj, const void *P, const void *x, void *c, hipStream_t st) {
+  hipLaunchKernelGGL(proj_gemv_kernel, dim3((unsigned)nproj), dim3(256), 0, st, npw,
+                     (const double2 *)P, (const double2 *)x, (double2 *)c);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void expand_gemv(int64_t npw, int nproj, const void *P, const void *c, void *out, hipStream_t st) {
+  hipLaunchKernelGGL(expand_gemv_kernel, dim3((unsigned)((npw + 255) / 256)), dim3(256),
+                     sizeof(double2) * (size_t)nproj, st, npw, nproj, (const double2 *)P,
+                     (const double2 *)c, (double2 *)out);
+  CHEBFI_HIP(hipGetLastError());
 }
 
 void zsum_parts(int64_t m, int64_t n, const void *part, int splits, void *C, int64_t ldc,

@@ -69,6 +69,42 @@ struct Sphere {
 };
 
 abi_status build_sphere(const abi_system_desc *d, Sphere *out, std::string *err);
+
+// ---- per-kernel-class timing (HIP events on the launch stream) ---------------
+enum ProfClass {
+  PROF_PROJ = 0,     // C = P^H X (projection GEMM, split along plane waves)
+  PROF_EXPAND = 1,   // Out += P C' (expansion GEMM)
+  PROF_FFT_A = 2,    // sphere -> inverse xy FFT
+  PROF_FFT_B = 3,    // z FFT, * V, z FFT
+  PROF_FFT_C = 4,    // forward xy FFT -> sphere + recurrence combine
+  PROF_DAPPLY = 5,   // split-K sum + D application
+  PROF_GRAM = 6,     // Y^H Y and Y^H (H Y)
+  PROF_CHOL = 7,     // Cholesky + triangular inverse + reduction to U^-H H_s U^-1
+  PROF_EIG = 8,      // Hermitian eigensolver
+  PROF_ROT = 9,      // Psi = Y W, H Psi = (H Y) W
+  PROF_NCLASS = 10
+};
+
+struct Profiler {
+  bool on = false;
+  bool in_filter = false;  // H-application classes are timed inside the filter only
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+    double work;  // algorithmic flops or bytes of the bracketed launch
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double total_ms[PROF_NCLASS] = {0};
+  double work[PROF_NCLASS] = {0};
+  int64_t count[PROF_NCLASS] = {0};
+  hipEvent_t take();
+  // Brackets one launch: begin() before, end() after (no-ops when off).
+  int begin(int cls, double work, hipStream_t st);
+  void end(int token, hipStream_t st);
+  void collect();  // waits for pending events and accumulates them
+  ~Profiler();
+};
 void reciprocal(const double lattice[9], double B[9]);
 void build_projectors(const abi_system_desc *d, const Sphere &s, std::vector<double> *P);
 
@@ -98,4 +134,5 @@ struct abi_system_s {
   chebfi::DevBuf eig1, eig2, eig3;
 
   int fft_batch = 0;  // bands per FFT batch (box buffer holds this many boxes)
+  chebfi::Profiler prof;
 };

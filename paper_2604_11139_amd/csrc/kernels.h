@@ -21,7 +21,7 @@ template <typename T>
 void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Yprev,
                             int64_t ldp, void *Out, int64_t ldo, int band0, int nb, void *box,
                             const void *V, double alpha, double cshift, double beta,
-                            hipStream_t st);
+                            hipStream_t st, Profiler *prof = nullptr);
 
 // ---- gemm.hip ---------------------------------------------------------------
 // C = alpha op(A) op(B) + beta C, complex double, column-major.  When `part`
@@ -30,6 +30,16 @@ void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, 
 void zgemm(Op opa, Op opb, int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
            const void *B, int64_t ldb, void *C, int64_t ldc, double2 alpha, double2 beta,
            hipStream_t st, void *part = nullptr, int splits = 1);
+
+// Projector products of the H application (same kernels, own instantiations):
+// part[z] = P^H X over K chunk z, and Out += P C'.
+void proj_gemm(int64_t nproj, int64_t nband, int64_t npw, const void *P, const void *X,
+               int64_t ldx, void *part, int splits, hipStream_t st);
+void expand_gemm(int64_t npw, int64_t nband, int64_t nproj, const void *P, const void *Cp,
+                 void *Out, int64_t ldo, hipStream_t st);
+// Single-band forms: c = P^H x, out += P c.
+void proj_gemv(int64_t npw, int nproj, const void *P, const void *x, void *c, hipStream_t st);
+void expand_gemv(int64_t npw, int nproj, const void *P, const void *c, void *out, hipStream_t st);
 
 // Number of K splits that fills the chip for an m x n output.
 int zgemm_splits(int64_t m, int64_t n, int64_t k);
