@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 
@@ -36,6 +38,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3])
+    ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"],
+                    help="both: time the mixed form (value) and the FP64 form beside it")
     ap.add_argument("--cpu-bands", type=int, default=160,
                     help="bands in the oracle's timed sample (0 skips the CPU baseline)")
     return ap.parse_args()
@@ -71,6 +75,94 @@ def cpu_baseline(s, degree, bounds, nbands):
     }
 
 
+def roofline_of(prof, peak_mfma, mfma_label):
+    """Dominant H-application kernel class (by time) and its live achieved rate."""
+    gemm_cls = ("proj_gemm", "expand_gemm")
+    h_cls = ("proj_gemm", "expand_gemm", "fft_a", "fft_b", "fft_c", "dapply")
+    dom = max(h_cls, key=lambda c: prof[c][0])
+    ms_tot, work, cnt = prof[dom]
+    avg_s = ms_tot / 1e3 / max(cnt, 1)
+    per_launch = work / max(cnt, 1)
+    if dom in gemm_cls:
+        achieved = per_launch / avg_s / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak_mfma,
+                "unit": "TFLOP/s", "frac": round(achieved / peak_mfma, 4),
+                "peak_kind": mfma_label}
+    else:
+        achieved = per_launch / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4)}
+    roof.update({"kernel": dom, "launches": cnt, "avg_launch_ms": round(avg_s * 1e3, 4),
+                 "work_per_launch": per_launch, "traffic": None})
+    return roof
+
+
+def class_table(prof):
+    rate_tflops = ("proj_gemm", "expand_gemm", "gram", "rot")
+    out = {}
+    for c, (ms, work, cnt) in prof.items():
+        if ms <= 0:
+            out[c] = {"ms": 0.0, "launches": cnt, "rate": None}
+            continue
+        rate = work / (ms / 1e3)
+        out[c] = {"ms": round(ms, 3), "launches": cnt,
+                  "rate": round(rate / 1e12, 3) if c in rate_tflops else round(rate / 1e9, 1),
+                  "rate_unit": "TFLOP/s" if c in rate_tflops else "GB/s or GFLOP/s"}
+    return out
+
+
+def run_cycles(g, X0, v0, degree, steps, warmup):
+    """warmup + steps full cycles (bounds, filter, Rayleigh-Ritz) from X0."""
+    import numpy as np
+    import torch
+
+    X = X0.clone()
+    Y = torch.empty_like(X)
+    f_start = torch.cuda.Event(enable_timing=True)
+    f_stop = torch.cuda.Event(enable_timing=True)
+    first_bounds = None
+
+    def step(X, Y):
+        bounds = g.spectral_bounds(X, v0)
+        a, b, a0 = bounds
+        f_start.record()
+        g.cheb_filter(X, degree, a, b, a0, out=Y)
+        f_stop.record()
+        ev, res, _ = g.rayleigh_ritz(Y)
+        f_stop.synchronize()
+        return bounds, f_start.elapsed_time(f_stop), ev, res
+
+    for _ in range(warmup):
+        bounds, _, ev, res = step(X, Y)
+        X, Y = Y, X
+        first_bounds = first_bounds or bounds
+    g.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    filt_ms = []
+    for _ in range(steps):
+        bounds, ms, ev, res = step(X, Y)
+        X, Y = Y, X
+        filt_ms.append(ms)
+        first_bounds = first_bounds or bounds
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = g.profile_read()
+    g.profile(False)
+    nband = X.shape[0]
+    filt_s = sum(filt_ms) / 1e3
+    return {
+        "value": steps * degree * nband / filt_s,
+        "filter_ms_per_step": filt_s * 1e3 / steps,
+        "ms_per_step": wall * 1e3 / steps,
+        "cycle_band_apps_per_s": steps * degree * nband / wall,
+        "prof": prof,
+        "eval": np.asarray(ev),
+        "res": np.asarray(res),
+        "bounds": first_bounds,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -88,7 +180,7 @@ def main():
     s = W.make_system(args.config)
     degree = s.degree
     t_setup = time.perf_counter()
-    g = B.System(s)
+    g = B.System(s, precision=B.ABI_PREC_MIXED)
     t_setup = time.perf_counter() - t_setup
     npw, nband = g.npw, s.nband
 
@@ -96,104 +188,67 @@ def main():
     # torch's complex normal has variance 1/2 per part, scaled to N(0,1) parts
     gen = torch.Generator(device="cuda")
     gen.manual_seed(2604_11139 + args.config)
-    X = torch.randn((nband, npw), dtype=torch.complex128, device="cuda", generator=gen)
-    X.mul_(2.0 ** 0.5)
+    X64 = torch.randn((nband, npw), dtype=torch.complex128, device="cuda", generator=gen)
+    X64.mul_(2.0 ** 0.5)
     v0 = torch.randn((npw,), dtype=torch.complex128, device="cuda", generator=gen)
-    Y = torch.empty_like(X)
-    ev_first = None
-    first_bounds = None
+    # both forms start from the same block (the complex64 rounding of it)
+    X32 = X64.to(torch.complex64)
+    X64 = X32.to(torch.complex128)
 
-    f_start = torch.cuda.Event(enable_timing=True)
-    f_stop = torch.cuda.Event(enable_timing=True)
-
-    def step(X, Y):
-        bounds = g.spectral_bounds(X, v0)
-        a, b, a0 = bounds
-        f_start.record()
-        g.cheb_filter(X, degree, a, b, a0, out=Y)
-        f_stop.record()
-        ev, res, _ = g.rayleigh_ritz(Y)
-        f_stop.synchronize()
-        return bounds, f_start.elapsed_time(f_stop), ev, res
-
-    for _ in range(args.warmup):
-        bounds, _, ev, res = step(X, Y)
-        X, Y = Y, X
-        if first_bounds is None:
-            first_bounds, ev_first = bounds, ev
-
-    g.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    filt_ms = []
-    res_max = []
-    for _ in range(args.steps):
-        bounds, ms, ev, res = step(X, Y)
-        X, Y = Y, X
-        filt_ms.append(ms)
-        res_max.append(float(np.max(res)))
-        if first_bounds is None:
-            first_bounds, ev_first = bounds, ev
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof = g.profile_read()
-    g.profile(False)
-
-    filt_s = sum(filt_ms) / 1e3
-    value = args.steps * degree * nband / filt_s
-
-    # dominant kernel class by total time and its live average launch time
-    gemm_cls = ("proj_gemm", "expand_gemm")
-    dom = max(prof, key=lambda c: prof[c][0])
-    ms_tot, work, cnt = prof[dom]
-    avg_s = ms_tot / 1e3 / max(cnt, 1)
-    per_launch = work / max(cnt, 1)
-    if dom in gemm_cls or dom in ("gram", "rot", "chol", "eig"):
-        achieved = per_launch / avg_s / 1e12
-        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4)}
-    else:
-        achieved = per_launch / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4)}
-    roof.update({"kernel": dom, "launches": cnt, "avg_launch_ms": round(avg_s * 1e3, 4),
-                 "work_per_launch": per_launch, "traffic": None})
-    classes = {c: {"ms": round(v[0], 3), "launches": v[2],
-                   "rate": (round(v[1] / (v[0] / 1e3) / 1e12, 3) if c in gemm_cls + ("gram", "rot")
-                            else round(v[1] / (v[0] / 1e3) / 1e9, 1)) if v[0] > 0 else None}
-               for c, v in prof.items()}
+    runs = {}
+    if args.precision in ("both", "fp64"):
+        runs["fp64"] = run_cycles(g, X64, v0, degree, args.steps, args.warmup)
+    if args.precision in ("both", "mixed"):
+        runs["mixed"] = run_cycles(g, X32, v0, degree, args.steps, args.warmup)
+    head = runs["mixed"] if "mixed" in runs else runs["fp64"]
+    mixed = "mixed" in runs
 
     out = {
         "metric": "H.psi band-applications/s in Chebyshev filter",
-        "value": round(value, 2),
+        "value": round(head["value"], 2),
         "unit": "band-apps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall * 1e3 / args.steps, 2),
+        "ms_per_step": round(head["ms_per_step"], 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if mixed else "f64",
         "data": "synthetic",
         "config": {
             "workload": f"config{args.config}: cubic a={s.a:g} bohr, Ecut={s.ecut:g} Ha, "
                         f"{npw} plane waves, {s.ngrid[0]}^3 FFT grid, {s.natom} atoms / "
                         f"{4 * s.natom} projectors, {nband} bands, Chebyshev degree {degree}, "
-                        "plain FP64 form",
+                        + ("FP32-mixed filter (complex64 FFT + recurrence, FP32 MFMA projector "
+                           "products) with FP64 bounds / Cholesky / eigensolver / Rayleigh-Ritz"
+                           if mixed else "plain FP64 form"),
             "npw": npw, "nband": nband, "degree": degree, "ngrid": list(s.ngrid),
-            "nproj": 4 * s.natom, "precision": "fp64",
+            "nproj": 4 * s.natom, "precision": "mixed" if mixed else "fp64",
         },
-        "filter_ms_per_step": round(filt_s * 1e3 / args.steps, 2),
-        "cycle_band_apps_per_s": round(args.steps * degree * nband / wall, 2),
+        "filter_ms_per_step": round(head["filter_ms_per_step"], 2),
+        "cycle_band_apps_per_s": round(head["cycle_band_apps_per_s"], 2),
         "setup_s": round(t_setup, 2),
-        "max_residual_last_step": res_max[-1],
-        "lowest_eval_last_step": float(ev[0]),
-        "roofline": roof,
-        "kernel_classes": classes,
+        "max_residual_last_step": float(head["res"].max()),
+        "roofline": roofline_of(head["prof"], PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS,
+                                "fp32 MFMA" if mixed else "fp64 MFMA"),
+        "kernel_classes": class_table(head["prof"]),
     }
+    if "fp64" in runs and mixed:
+        f = runs["fp64"]
+        out["fp64"] = {
+            "value": round(f["value"], 2),
+            "filter_ms_per_step": round(f["filter_ms_per_step"], 2),
+            "ms_per_step": round(f["ms_per_step"], 2),
+            "roofline": roofline_of(f["prof"], PEAK_FP64_TFLOPS, "fp64 MFMA"),
+            "kernel_classes": class_table(f["prof"]),
+        }
+        out["mixed_over_fp64"] = round(head["value"] / f["value"], 3)
+        d = np.abs(runs["mixed"]["eval"] - f["eval"])
+        out["eval_max_abs_diff_mixed_vs_fp64_ha"] = float(d.max())
+        out["eval_max_abs_diff_lower_half_ha"] = float(d[: nband // 2].max())
     if args.cpu_bands > 0:
-        out["cpu_baseline"] = cpu_baseline(s, degree, first_bounds, args.cpu_bands)
+        out["cpu_baseline"] = cpu_baseline(s, degree, head["bounds"], args.cpu_bands)
     print(json.dumps(out), flush=True)
 
 

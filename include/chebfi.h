@@ -109,7 +109,10 @@ abi_status abi_destroy(abi_system sys);
 
 /* HX = H X for nband columns (matrix-free H application of section "Main
  * computational kernels": kinetic diagonal, V_loc through batched 3D FFTs,
- * nonlocal through P^H X, D and P(...)).  X and HX must not overlap. */
+ * nonlocal through P^H X, D and P(...)).  X and HX must not overlap.
+ * dtype ABI_C128: FP64 throughout.  dtype ABI_C64 (handles built with
+ * ABI_PREC_MIXED only): complex64 blocks, FP32 FFT passes and recurrence,
+ * FP32-accumulated MFMA projector products; D is applied in FP64. */
 abi_status abi_apply_H(abi_system sys, const void *X, void *HX, int64_t nband, int64_t ld,
                        int32_t dtype, void *stream);
 
@@ -118,7 +121,7 @@ abi_status abi_apply_H(abi_system sys, const void *X, void *HX, int64_t nband, i
  * out[2] = a0 = min_i RQ_i with RQ_i = Re(x_i^H H x_i)/(x_i^H x_i), and
  * out[1] = b = theta_max(T) + beta_last from `nlanczos` (1..64) Lanczos steps
  * with full reorthogonalisation started from the device vector v0 (npw
- * complex, same dtype as X); the run stops early with b = theta_max when
+ * complex doubles, always FP64); the run stops early with b = theta_max when
  * beta_j <= 1e-12 max(1, |alpha_j|).  `out` is a host array of 3 doubles.
  * Synchronises `stream`. */
 abi_status abi_spectral_bounds(abi_system sys, const void *X, int64_t nband, int64_t ld,
@@ -131,7 +134,7 @@ abi_status abi_spectral_bounds(abi_system sys, const void *X, int64_t nband, int
  * Y_{k+1} = (2 s_{k+1}/e)(H - c)Y_k - s_k s_{k+1} Y_{k-1}, s_1 = e/(a0 - c),
  * s_{k+1} = 1/(2/s_1 - s_k).  degree = m >= 1 H applications; requires b > a
  * and a0 <= a.  X and Y (both npw x nband, leading dimension ld) must not
- * overlap; X is not modified. */
+ * overlap; X is not modified.  dtype as for abi_apply_H. */
 abi_status abi_cheb_filter(abi_system sys, const void *X, void *Y, int64_t nband, int64_t ld,
                            int32_t dtype, int32_t degree, double a, double b, double a0,
                            void *stream);
@@ -140,15 +143,18 @@ abi_status abi_cheb_filter(abi_system sys, const void *X, void *Y, int64_t nband
  * S = I): G = Y^H Y = U^H U (Cholesky, FP64), H_s = Y^H (H Y),
  * U^-H H_s U^-1 = Z Lambda Z^H, Psi = Y U^-1 Z, H Psi = (H Y) U^-1 Z, and the
  * residual norms ||H psi_n - lambda_n psi_n|| (Algorithm "Parallel Chebyshev
- * filtering of degree k", last two steps).
- * Y (c128, npw x nband, ld): in: filtered block; out: Ritz vectors Psi.
- * HPsi: optional c128 output (npw x nband, ld) or NULL.
+ * filtering of degree k", last two steps).  Always computed in FP64: a
+ * complex64 block (dtype ABI_C64, mixed handles) is promoted, processed and
+ * rounded back, so the eigenvalues are those of the FP64 pencil of the block.
+ * Y (npw x nband, ld): in: filtered block; out: Ritz vectors Psi.
+ * HPsi: optional output of the same dtype and ld, or NULL.
  * eval: host, nband doubles, ascending.  resnorm: host, nband doubles, or NULL.
- * flags: host int32 or NULL (bit 0 reserved for the mixed-precision fallback).
+ * flags: host int32 or NULL (bit 0 reserved for a mixed-precision fallback).
  * Fails with ABI_ERR_NOT_HPD if the Gram matrix is not positive definite.
  * Synchronises `stream`. */
 abi_status abi_rayleigh_ritz(abi_system sys, void *Y, void *HPsi, int64_t nband, int64_t ld,
-                             double *eval, double *resnorm, int32_t *flags, void *stream);
+                             int32_t dtype, double *eval, double *resnorm, int32_t *flags,
+                             void *stream);
 
 /* ---- dense FP64 building blocks of the Rayleigh-Ritz step ---------------------
  * Column-major complex double matrices in device memory, leading dimension lda. */

@@ -89,7 +89,7 @@ def lib():
         "abi_spectral_bounds": [vp, vp, c_int64, c_int64, c_int32, vp, c_int32, vp, vp],
         "abi_cheb_filter": [vp, vp, vp, c_int64, c_int64, c_int32, c_int32, c_double, c_double,
                             c_double, vp],
-        "abi_rayleigh_ritz": [vp, vp, vp, c_int64, c_int64, vp, vp, vp, vp],
+        "abi_rayleigh_ritz": [vp, vp, vp, c_int64, c_int64, c_int32, vp, vp, vp, vp],
         "abi_zpotrf_upper": [c_int64, vp, c_int64, vp],
         "abi_zheev": [c_int64, vp, c_int64, vp, vp, c_int64, vp],
         "abi_profile_enable": [vp, c_int32],
@@ -116,10 +116,16 @@ def _stream():
 
 
 def _block(t, npw: int):
-    """(pointer, nband, ld) of a (nband, npw) complex128 CUDA tensor."""
+    """(pointer, nband, ld, dtype code) of a (nband, npw) complex CUDA tensor."""
     import torch
-    if t.dtype != torch.complex128 or not t.is_cuda:
-        raise TypeError("blocks must be complex128 CUDA tensors")
+    if t.dtype == torch.complex128:
+        code = ABI_C128
+    elif t.dtype == torch.complex64:
+        code = ABI_C64
+    else:
+        raise TypeError("blocks must be complex128 or complex64 tensors")
+    if not t.is_cuda:
+        raise TypeError("blocks must live on the GPU")
     if t.dim() == 1:
         t = t.view(1, -1)
     if t.shape[1] != npw or (t.shape[1] > 1 and t.stride(1) != 1):
@@ -127,7 +133,7 @@ def _block(t, npw: int):
     ld = int(t.stride(0)) if t.shape[0] > 1 else npw  # a one-row stride is arbitrary
     if ld < npw:
         raise ValueError("block rows overlap (stride(0) < npw)")
-    return c_void_p(t.data_ptr()), int(t.shape[0]), ld
+    return c_void_p(t.data_ptr()), int(t.shape[0]), ld, code
 
 
 class _DescHolder:
@@ -221,34 +227,38 @@ class System:
         return P  # row j = projector column j
 
     # -- hot path ------------------------------------------------------------
-    def apply_H(self, X, out=None):
+    def _out_like(self, X, out):
         import torch
-        px, nb, ld = _block(X, self.npw)
         if out is None:
             out = torch.empty_strided(X.shape, X.stride(), dtype=X.dtype, device=X.device)
-        po, nbo, ldo = _block(out, self.npw)
-        if nbo != nb or ldo != ld:
-            raise ValueError("out must match X's shape and stride")
-        _check(lib().abi_apply_H(self._h, px, po, nb, ld, ABI_C128, _stream()))
+        if out.dtype != X.dtype or out.shape != X.shape or (X.dim() == 2 and X.shape[0] > 1
+                                                             and out.stride() != X.stride()):
+            raise ValueError("out must match X's dtype, shape and stride")
+        return out
+
+    def apply_H(self, X, out=None):
+        px, nb, ld, code = _block(X, self.npw)
+        out = self._out_like(X, out)
+        po, _, _, _ = _block(out, self.npw)
+        _check(lib().abi_apply_H(self._h, px, po, nb, ld, code, _stream()))
         return out
 
     def cheb_filter(self, X, degree, a, b, a0, out=None):
-        import torch
-        px, nb, ld = _block(X, self.npw)
-        if out is None:
-            out = torch.empty_strided(X.shape, X.stride(), dtype=X.dtype, device=X.device)
-        po, nbo, ldo = _block(out, self.npw)
-        if nbo != nb or ldo != ld:
-            raise ValueError("out must match X's shape and stride")
-        _check(lib().abi_cheb_filter(self._h, px, po, nb, ld, ABI_C128, int(degree), float(a),
+        px, nb, ld, code = _block(X, self.npw)
+        out = self._out_like(X, out)
+        po, _, _, _ = _block(out, self.npw)
+        _check(lib().abi_cheb_filter(self._h, px, po, nb, ld, code, int(degree), float(a),
                                      float(b), float(a0), _stream()))
         return out
 
     def spectral_bounds(self, X, v0, nlanczos=10):
-        px, nb, ld = _block(X, self.npw)
-        pv, _, _ = _block(v0, self.npw)
+        """(a, b, a0); v0 must be complex128 (the Lanczos run is FP64)."""
+        px, nb, ld, code = _block(X, self.npw)
+        pv, _, _, vcode = _block(v0, self.npw)
+        if vcode != ABI_C128:
+            raise TypeError("v0 must be complex128")
         out = (c_double * 3)()
-        _check(lib().abi_spectral_bounds(self._h, px, nb, ld, ABI_C128, pv, int(nlanczos), out,
+        _check(lib().abi_spectral_bounds(self._h, px, nb, ld, code, pv, int(nlanczos), out,
                                          _stream()))
         return float(out[0]), float(out[1]), float(out[2])
 
@@ -267,16 +277,15 @@ class System:
 
     def rayleigh_ritz(self, Y, hpsi=None):
         """In place: Y <- Ritz vectors.  Returns (eval, resnorm, flags)."""
-        py, nb, ld = _block(Y, self.npw)
+        py, nb, ld, code = _block(Y, self.npw)
         ph = c_void_p(0)
         if hpsi is not None:
-            ph, nbh, ldh = _block(hpsi, self.npw)
-            if nbh != nb or ldh != ld:
-                raise ValueError("hpsi must match Y's shape and stride")
+            self._out_like(Y, hpsi)
+            ph, _, _, _ = _block(hpsi, self.npw)
         ev = np.zeros(nb, dtype=np.float64)
         rn = np.zeros(nb, dtype=np.float64)
         fl = c_int32(0)
-        _check(lib().abi_rayleigh_ritz(self._h, py, ph, nb, ld, ev.ctypes.data_as(c_void_p),
+        _check(lib().abi_rayleigh_ritz(self._h, py, ph, nb, ld, code, ev.ctypes.data_as(c_void_p),
                                        rn.ctypes.data_as(c_void_p), ctypes.byref(fl), _stream()))
         return ev, rn, fl.value
 

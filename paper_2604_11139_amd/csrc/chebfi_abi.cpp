@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 
+#include "cplx.h"
 #include "kernels.h"
 
 namespace chebfi {
@@ -145,7 +146,7 @@ template <typename T> T *upload(const T *host, size_t count) {
 }
 
 void free_tables(abi_system_s *s) {
-  void *ptrs[] = {s->d_kin, s->d_box, s->d_plane, s->d_P, s->d_D, s->d_V, s->d_tw};
+  void *ptrs[] = {s->d_kin, s->d_box, s->d_plane, s->d_P, s->d_D, s->d_V, s->d_tw, s->d_Pf, s->d_Vf};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   s->d_kin = nullptr;
@@ -155,6 +156,8 @@ void free_tables(abi_system_s *s) {
   s->d_D = nullptr;
   s->d_V = nullptr;
   s->d_tw = nullptr;
+  s->d_Pf = nullptr;
+  s->d_Vf = nullptr;
 }
 
 void check_block(const abi_system_s *s, const void *p, int64_t nband, int64_t ld, int32_t dtype) {
@@ -162,52 +165,150 @@ void check_block(const abi_system_s *s, const void *p, int64_t nband, int64_t ld
   CHEBFI_REQUIRE(p != nullptr, ABI_ERR_ARG, "block pointer is NULL");
   CHEBFI_REQUIRE(nband > 0, ABI_ERR_ARG, "nband must be > 0");
   CHEBFI_REQUIRE(ld >= s->npw, ABI_ERR_ARG, "ld must be >= npw");
-  CHEBFI_REQUIRE(dtype == ABI_C128, ABI_ERR_STATE, "only complex128 blocks are supported");
+  CHEBFI_REQUIRE(dtype == ABI_C128 || dtype == ABI_C64, ABI_ERR_ARG, "unknown dtype");
+  CHEBFI_REQUIRE(dtype == ABI_C128 || s->precision == ABI_PREC_MIXED, ABI_ERR_STATE,
+                 "complex64 blocks need a handle built with ABI_PREC_MIXED");
 }
 
-// Out = alpha * (H - cshift) X - beta * Xprev   (Xprev may be null)
-void apply_core(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
-                void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
-                hipStream_t st) {
+inline size_t elem_bytes(int32_t dtype) { return dtype == ABI_C64 ? sizeof(float2) : sizeof(double2); }
+
+// Out = alpha * (H - cshift) X - beta * Xprev   (Xprev may be null).
+// T = double: FP64 tables, FP64 MFMA; T = float: complex64 blocks, FP32 FFT
+// passes and FP32 MFMA projector products (mixed form).
+template <typename T>
+void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
+                  void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
+                  hipStream_t st) {
+  typedef C2<T> V2;
+  const bool fp32 = std::is_same<T, float>::value;
+  const void *P = fp32 ? (const void *)s->d_Pf : (const void *)s->d_P;
+  const void *V = fp32 ? (const void *)s->d_Vf : (const void *)s->d_V;
   const int64_t npw = s->npw;
   const int nproj = s->nproj;
   int splits = 1;
-  double2 *cpart = nullptr, *cprime = nullptr;
-  const bool single = (nband == 1);
+  V2 *cpart = nullptr, *cprime = nullptr;
+  const bool single = (nband == 1) && !fp32;
   if (nproj > 0) {
     splits = single ? 1 : zgemm_splits(nproj, nband, npw);
-    cpart = (double2 *)s->cpart.get(sizeof(double2) * (size_t)splits * nproj * nband);
-    cprime = (double2 *)s->cprime.get(sizeof(double2) * (size_t)nproj * nband);
+    cpart = (V2 *)s->cpart.get(sizeof(V2) * (size_t)splits * nproj * nband);
+    cprime = (V2 *)s->cprime.get(sizeof(V2) * (size_t)nproj * nband);
     // C = P^H X (split along the plane waves), C' = alpha D C
     const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
     int tok = s->prof.begin(PROF_PROJ, flops, st);
     if (single)
-      proj_gemv(npw, nproj, s->d_P, X, cpart, st);
+      proj_gemv(npw, nproj, P, X, cpart, st);
     else
-      proj_gemm(nproj, nband, npw, s->d_P, X, ldx, cpart, splits, st);
+      proj_gemm(nproj, nband, npw, P, X, ldx, cpart, splits, st, fp32);
     s->prof.end(tok, st);
-    tok = s->prof.begin(PROF_DAPPLY, 16.0 * (double)nproj * nband * (splits + 1), st);
-    launch_dapply(s->natom, nband, cpart, splits, s->d_D, alpha, cprime, st);
+    tok = s->prof.begin(PROF_DAPPLY, (double)sizeof(V2) * nproj * nband * (splits + 1), st);
+    launch_dapply(s->natom, nband, cpart, splits, s->d_D, alpha, cprime, st, fp32);
     s->prof.end(tok, st);
   }
   const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
-  const int fb = (int)std::min<int64_t>(s->fft_batch, nband);
-  void *box = s->box.get(sizeof(double2) * (size_t)nbox * fb);
+  const int fb = (int)std::min<int64_t>(s->fft_batch * (fp32 ? 2 : 1), nband);
+  void *box = s->box.get(sizeof(V2) * (size_t)nbox * fb);
   for (int64_t b0 = 0; b0 < nband; b0 += fb) {
     const int nb = (int)std::min<int64_t>(fb, nband - b0);
-    launch_local_potential<double>(s, X, ldx, Xprev, ldp, Out, ldo, (int)b0, nb, box, s->d_V,
-                                   alpha, cshift, beta, st, s->prof.on ? &s->prof : nullptr);
+    launch_local_potential<T>(s, X, ldx, Xprev, ldp, Out, ldo, (int)b0, nb, box, V, alpha, cshift,
+                              beta, st, s->prof.on ? &s->prof : nullptr);
   }
   if (nproj > 0) {
     // Out += P C'
     const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
     int tok = s->prof.begin(PROF_EXPAND, flops, st);
     if (single)
-      expand_gemv(npw, nproj, s->d_P, cprime, Out, st);
+      expand_gemv(npw, nproj, P, cprime, Out, st);
     else
-      expand_gemm(npw, nband, nproj, s->d_P, cprime, Out, ldo, st);
+      expand_gemm(npw, nband, nproj, P, cprime, Out, ldo, st, fp32);
     s->prof.end(tok, st);
   }
+}
+
+void apply_core(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
+                void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
+                hipStream_t st, int32_t dtype = ABI_C128) {
+  if (dtype == ABI_C64)
+    apply_core_t<float>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, st);
+  else
+    apply_core_t<double>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, st);
+}
+
+// FP64 Rayleigh-Ritz on a complex128 block Y (in: filtered block, out: Psi).
+void rr_core(abi_system_s *s, double2 *Y, int64_t ld, double2 *HPsi, int64_t ldh_in, int64_t M,
+             double *eval, double *resnorm, hipStream_t st) {
+  const int64_t npw = s->npw;
+  const size_t mm = sizeof(double2) * (size_t)M * M;
+  double2 *G = (double2 *)s->small1.get(mm);
+  double2 *Hs = (double2 *)s->small2.get(mm);
+  double2 *T = (double2 *)s->small3.get(mm);
+  double2 *Z = (double2 *)s->small4.get(mm);
+  double *scal = (double *)s->scal.get(sizeof(double) * (size_t)(160 + 3 * M + 64));
+  double *w_dev = scal + 160;
+  double *r_dev = w_dev + M;
+  int *info = (int *)(r_dev + M);
+  // Gram G = Y^H Y -> U (Cholesky, upper)
+  int splits = zgemm_splits(M, M, npw);
+  void *part = s->cpart.get(sizeof(double2) * (size_t)splits * M * M);
+  const double gflops = 8.0 * (double)M * M * npw;
+  int tok = s->prof.begin(PROF_GRAM, gflops, st);
+  zgemm(OP_C, OP_N, M, M, npw, Y, ld, Y, ld, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
+        splits);
+  zsum_parts(M, M, part, splits, G, M, double2{1, 0}, double2{0, 0}, st);
+  s->prof.end(tok, st);
+  launch_hermitize(M, G, M, st);
+  tok = s->prof.begin(PROF_CHOL, 4.0 / 3.0 * (double)M * M * M, st);
+  zpotrf_upper(M, G, M, info, nullptr, st);
+  s->prof.end(tok, st);
+  int hinfo = 0;
+  CHEBFI_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, st));
+  CHEBFI_HIP(hipStreamSynchronize(st));
+  if (hinfo != 0)
+    throw Error{ABI_ERR_NOT_HPD,
+                "Gram matrix not positive definite at pivot " + std::to_string(hinfo)};
+  // H Y and H_s = Y^H (H Y)
+  double2 *HY = (double2 *)s->blk1.get(sizeof(double2) * (size_t)npw * M);
+  apply_core(s, Y, ld, nullptr, 0, HY, npw, M, 1.0, 0.0, 0.0, st);
+  part = s->cpart.get(sizeof(double2) * (size_t)splits * M * M);  // apply_core may regrow it
+  tok = s->prof.begin(PROF_GRAM, gflops, st);
+  zgemm(OP_C, OP_N, M, M, npw, Y, ld, HY, npw, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
+        splits);
+  zsum_parts(M, M, part, splits, Hs, M, double2{1, 0}, double2{0, 0}, st);
+  s->prof.end(tok, st);
+  launch_hermitize(M, Hs, M, st);
+  // U^-1 and the reduced matrix U^-H H_s U^-1
+  tok = s->prof.begin(PROF_CHOL, 16.0 * (double)M * M * M, st);
+  void *trw = s->eig2.get(ztrtri_work_bytes(M));
+  ztrtri_upper(M, G, M, trw, st);
+  zgemm(OP_N, OP_N, M, M, M, Hs, M, G, M, T, M, double2{1, 0}, double2{0, 0}, st);
+  zgemm(OP_C, OP_N, M, M, M, G, M, T, M, Hs, M, double2{1, 0}, double2{0, 0}, st);
+  s->prof.end(tok, st);
+  // eigen-decomposition (Hs overwritten), W = U^-1 Z
+  void *ew = s->eig1.get(zheev_work_bytes(M));
+  tok = s->prof.begin(PROF_EIG, 16.0 / 3.0 * (double)M * M * M, st);
+  zheev(M, Hs, M, w_dev, Z, M, ew, st);
+  s->prof.end(tok, st);
+  tok = s->prof.begin(PROF_ROT, 8.0 * (double)M * M * M + 16.0 * (double)npw * M * M, st);
+  zgemm(OP_N, OP_N, M, M, M, G, M, Z, M, T, M, double2{1, 0}, double2{0, 0}, st);
+  // Psi = Y W, H Psi = (H Y) W
+  double2 *Psi = (double2 *)s->blk2.get(sizeof(double2) * (size_t)npw * M);
+  zgemm(OP_N, OP_N, npw, M, M, Y, ld, T, M, Psi, npw, double2{1, 0}, double2{0, 0}, st);
+  double2 *HP;
+  int64_t ldh;
+  if (HPsi) {
+    HP = HPsi;
+    ldh = ldh_in;
+  } else {
+    HP = (double2 *)s->blk3.get(sizeof(double2) * (size_t)npw * M);
+    ldh = npw;
+  }
+  zgemm(OP_N, OP_N, npw, M, M, HY, npw, T, M, HP, ldh, double2{1, 0}, double2{0, 0}, st);
+  s->prof.end(tok, st);
+  launch_copy_block(npw, M, Psi, npw, Y, ld, st);
+  launch_residual_norms(npw, M, Y, ld, HP, ldh, w_dev, r_dev, st);
+  CHEBFI_HIP(hipMemcpyAsync(eval, w_dev, sizeof(double) * M, hipMemcpyDeviceToHost, st));
+  if (resnorm)
+    CHEBFI_HIP(hipMemcpyAsync(resnorm, r_dev, sizeof(double) * M, hipMemcpyDeviceToHost, st));
+  CHEBFI_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace
@@ -292,6 +393,13 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
     s->d_D = upload(desc->dij, (size_t)desc->natom * 32);
     s->d_V = upload(desc->vloc, (size_t)nbox);
     s->d_tw = upload(tw.data(), tw.size());
+    if (s->precision == ABI_PREC_MIXED) {
+      std::vector<float> Pf(P.size()), Vf((size_t)nbox);
+      for (size_t i = 0; i < P.size(); ++i) Pf[i] = (float)P[i];
+      for (int64_t i = 0; i < nbox; ++i) Vf[i] = (float)desc->vloc[i];
+      s->d_Pf = upload(Pf.data(), Pf.size());
+      s->d_Vf = upload(Vf.data(), Vf.size());
+    }
     // bands per FFT batch: keep the box buffer near 128 MiB (env override)
     int64_t fb = (int64_t)((128ll << 20) / (sizeof(double2) * nbox));
     if (const char *e = std::getenv("CHEBFI_FFT_BATCH")) fb = std::atoll(e);
@@ -352,7 +460,7 @@ abi_status abi_apply_H(abi_system s, const void *X, void *HX, int64_t nband, int
     check_block(s, X, nband, ld, dtype);
     CHEBFI_REQUIRE(HX != nullptr, ABI_ERR_ARG, "HX is NULL");
     CHEBFI_REQUIRE(HX != X, ABI_ERR_ARG, "X and HX must not overlap");
-    apply_core(s, X, ld, nullptr, 0, HX, ld, nband, 1.0, 0.0, 0.0, S(stream));
+    apply_core(s, X, ld, nullptr, 0, HX, ld, nband, 1.0, 0.0, 0.0, S(stream), dtype);
   });
 }
 
@@ -374,8 +482,9 @@ abi_status abi_cheb_filter(abi_system s, const void *X, void *Y, int64_t nband, 
     // Y_j lives in bufs[(degree - j) % 3] so that Y_degree lands in Y.
     void *bufs[3] = {Y, nullptr, nullptr};
     int64_t lds[3] = {ld, npw, npw};
-    if (degree >= 2) bufs[1] = s->blk1.get(sizeof(double2) * (size_t)npw * nband);
-    if (degree >= 3) bufs[2] = s->blk2.get(sizeof(double2) * (size_t)npw * nband);
+    const size_t eb = elem_bytes(dtype);
+    if (degree >= 2) bufs[1] = s->blk1.get(eb * (size_t)npw * nband);
+    if (degree >= 3) bufs[2] = s->blk2.get(eb * (size_t)npw * nband);
     auto slot = [&](int j) { return (degree - j) % 3; };
     struct Scope {
       Profiler &p;
@@ -383,7 +492,8 @@ abi_status abi_cheb_filter(abi_system s, const void *X, void *Y, int64_t nband, 
       ~Scope() { p.in_filter = false; }
     } scope(s->prof);
     // Y_1 = (s1/e)(H - c) X
-    apply_core(s, X, ld, nullptr, 0, bufs[slot(1)], lds[slot(1)], nband, s1 / e, c, 0.0, st);
+    apply_core(s, X, ld, nullptr, 0, bufs[slot(1)], lds[slot(1)], nband, s1 / e, c, 0.0, st,
+               dtype);
     double sk = s1;
     for (int j = 1; j < degree; ++j) {
       const double sk1 = 1.0 / (2.0 / s1 - sk);
@@ -392,7 +502,7 @@ abi_status abi_cheb_filter(abi_system s, const void *X, void *Y, int64_t nband, 
       const void *yp = (j == 1) ? X : bufs[slot(j - 1)];
       const int64_t ldp = (j == 1) ? ld : lds[slot(j - 1)];
       apply_core(s, yk, ldk, yp, ldp, bufs[slot(j + 1)], lds[slot(j + 1)], nband, 2.0 * sk1 / e,
-                 c, sk * sk1, st);
+                 c, sk * sk1, st, dtype);
       sk = sk1;
     }
   });
@@ -407,12 +517,12 @@ abi_status abi_spectral_bounds(abi_system s, const void *X, int64_t nband, int64
     CHEBFI_REQUIRE(nlanczos >= 1 && nlanczos <= 64, ABI_ERR_ARG, "nlanczos must be in [1, 64]");
     hipStream_t st = S(stream);
     const int64_t npw = s->npw;
-    void *HX = s->blk3.get(sizeof(double2) * (size_t)npw * nband);
+    void *HX = s->blk3.get(elem_bytes(dtype) * (size_t)npw * nband);
     // scalars: [0..2] out, [8..8+64) alpha, [80..80+64) beta, rq after 160
     double *scal = (double *)s->scal.get(sizeof(double) * (size_t)(160 + nband));
     double *alpha = scal + 8, *beta = scal + 80, *rq = scal + 160;
-    apply_core(s, X, ld, nullptr, 0, HX, npw, nband, 1.0, 0.0, 0.0, st);
-    launch_rayleigh_quotients(npw, nband, X, ld, HX, npw, rq, st);
+    apply_core(s, X, ld, nullptr, 0, HX, npw, nband, 1.0, 0.0, 0.0, st, dtype);
+    launch_rayleigh_quotients(npw, nband, X, ld, HX, npw, rq, st, dtype == ABI_C64);
     launch_minmax(nband, rq, scal, st);
     // Lanczos basis V (npw x (nl+1)), residual w, projections h
     const int nl = nlanczos;
@@ -453,85 +563,26 @@ abi_status abi_spectral_bounds(abi_system s, const void *X, int64_t nband, int64
 }
 
 abi_status abi_rayleigh_ritz(abi_system s, void *Y, void *HPsi, int64_t nband, int64_t ld,
-                             double *eval, double *resnorm, int32_t *flags, void *stream) {
+                             int32_t dtype, double *eval, double *resnorm, int32_t *flags,
+                             void *stream) {
   return guarded([&] {
-    check_block(s, Y, nband, ld, ABI_C128);
+    check_block(s, Y, nband, ld, dtype);
     CHEBFI_REQUIRE(eval != nullptr, ABI_ERR_ARG, "eval is NULL");
     CHEBFI_REQUIRE(HPsi != Y, ABI_ERR_ARG, "HPsi must not alias Y");
     hipStream_t st = S(stream);
     const int64_t npw = s->npw, M = nband;
-    const size_t mm = sizeof(double2) * (size_t)M * M;
-    double2 *G = (double2 *)s->small1.get(mm);
-    double2 *Hs = (double2 *)s->small2.get(mm);
-    double2 *T = (double2 *)s->small3.get(mm);
-    double2 *Z = (double2 *)s->small4.get(mm);
-    double *scal = (double *)s->scal.get(sizeof(double) * (size_t)(160 + 3 * M + 64));
-    double *w_dev = scal + 160;
-    double *r_dev = w_dev + M;
-    int *info = (int *)(r_dev + M);
-    // Gram G = Y^H Y -> U (Cholesky, upper)
-    int splits = zgemm_splits(M, M, npw);
-    void *part = s->cpart.get(sizeof(double2) * (size_t)splits * M * M);
-    const double gflops = 8.0 * (double)M * M * npw;
-    int tok = s->prof.begin(PROF_GRAM, gflops, st);
-    zgemm(OP_C, OP_N, M, M, npw, Y, ld, Y, ld, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
-          splits);
-    zsum_parts(M, M, part, splits, G, M, double2{1, 0}, double2{0, 0}, st);
-    s->prof.end(tok, st);
-    launch_hermitize(M, G, M, st);
-    tok = s->prof.begin(PROF_CHOL, 4.0 / 3.0 * (double)M * M * M, st);
-    zpotrf_upper(M, G, M, info, nullptr, st);
-    s->prof.end(tok, st);
-    int hinfo = 0;
-    CHEBFI_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, st));
-    CHEBFI_HIP(hipStreamSynchronize(st));
-    if (hinfo != 0)
-      throw Error{ABI_ERR_NOT_HPD,
-                  "Gram matrix not positive definite at pivot " + std::to_string(hinfo)};
-    // H Y and H_s = Y^H (H Y)
-    double2 *HY = (double2 *)s->blk1.get(sizeof(double2) * (size_t)npw * M);
-    apply_core(s, Y, ld, nullptr, 0, HY, npw, M, 1.0, 0.0, 0.0, st);
-    part = s->cpart.get(sizeof(double2) * (size_t)splits * M * M);  // apply_core may regrow it
-    tok = s->prof.begin(PROF_GRAM, gflops, st);
-    zgemm(OP_C, OP_N, M, M, npw, Y, ld, HY, npw, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
-          splits);
-    zsum_parts(M, M, part, splits, Hs, M, double2{1, 0}, double2{0, 0}, st);
-    s->prof.end(tok, st);
-    launch_hermitize(M, Hs, M, st);
-    // U^-1 and the reduced matrix U^-H H_s U^-1
-    tok = s->prof.begin(PROF_CHOL, 16.0 * (double)M * M * M, st);
-    void *trw = s->eig2.get(ztrtri_work_bytes(M));
-    ztrtri_upper(M, G, M, trw, st);
-    zgemm(OP_N, OP_N, M, M, M, Hs, M, G, M, T, M, double2{1, 0}, double2{0, 0}, st);
-    zgemm(OP_C, OP_N, M, M, M, G, M, T, M, Hs, M, double2{1, 0}, double2{0, 0}, st);
-    s->prof.end(tok, st);
-    // eigen-decomposition (Hs overwritten), W = U^-1 Z
-    void *ew = s->eig1.get(zheev_work_bytes(M));
-    tok = s->prof.begin(PROF_EIG, 16.0 / 3.0 * (double)M * M * M, st);
-    zheev(M, Hs, M, w_dev, Z, M, ew, st);
-    s->prof.end(tok, st);
-    tok = s->prof.begin(PROF_ROT, 8.0 * (double)M * M * M + 16.0 * (double)npw * M * M, st);
-    zgemm(OP_N, OP_N, M, M, M, G, M, Z, M, T, M, double2{1, 0}, double2{0, 0}, st);
-    // Psi = Y W, H Psi = (H Y) W
-    double2 *Psi = (double2 *)s->blk2.get(sizeof(double2) * (size_t)npw * M);
-    zgemm(OP_N, OP_N, npw, M, M, Y, ld, T, M, Psi, npw, double2{1, 0}, double2{0, 0}, st);
-    double2 *HP;
-    int64_t ldh;
-    if (HPsi) {
-      HP = (double2 *)HPsi;
-      ldh = ld;
+    if (dtype == ABI_C128) {
+      rr_core(s, (double2 *)Y, ld, (double2 *)HPsi, ld, M, eval, resnorm, st);
     } else {
-      HP = (double2 *)s->blk3.get(sizeof(double2) * (size_t)npw * M);
-      ldh = npw;
+      // promote the complex64 block, run the FP64 Rayleigh-Ritz, round back
+      double2 *Y2 = (double2 *)s->blk4.get(sizeof(double2) * (size_t)npw * M);
+      double2 *H2 = (double2 *)s->blk3.get(sizeof(double2) * (size_t)npw * M);
+      launch_c64_to_c128(npw, M, Y, ld, Y2, npw, st);
+      rr_core(s, Y2, npw, H2, npw, M, eval, resnorm, st);
+      launch_c128_to_c64(npw, M, Y2, npw, Y, ld, st);
+      if (HPsi) launch_c128_to_c64(npw, M, H2, npw, HPsi, ld, st);
+      CHEBFI_HIP(hipStreamSynchronize(st));
     }
-    zgemm(OP_N, OP_N, npw, M, M, HY, npw, T, M, HP, ldh, double2{1, 0}, double2{0, 0}, st);
-    s->prof.end(tok, st);
-    launch_copy_block(npw, M, Psi, npw, Y, ld, st);
-    launch_residual_norms(npw, M, Y, ld, HP, ldh, w_dev, r_dev, st);
-    CHEBFI_HIP(hipMemcpyAsync(eval, w_dev, sizeof(double) * M, hipMemcpyDeviceToHost, st));
-    if (resnorm)
-      CHEBFI_HIP(hipMemcpyAsync(resnorm, r_dev, sizeof(double) * M, hipMemcpyDeviceToHost, st));
-    CHEBFI_HIP(hipStreamSynchronize(st));
     if (flags) *flags = 0;
   });
 }

@@ -19,20 +19,41 @@ namespace chebfi {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;
 
+// One 16x16x4 MFMA per element type and the row of accumulator element r of a
+// lane (column is lane % 16 for both).
+template <typename T> struct Mma;
+template <> struct Mma<double> {
+  typedef v4d acc;
+  static __device__ __forceinline__ acc run(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct Mma<float> {
+  typedef v4f acc;
+  static __device__ __forceinline__ acc run(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
 // TAG only separates instantiations (1 = projector products of the H
 // application) so that kernel traces report them apart from the dense ones.
-template <int OPA, int OPB, bool SPLIT, int TAG>
+template <typename T, int OPA, int OPB, bool SPLIT, int TAG>
 __global__ __launch_bounds__(256) void zgemm_kernel(int64_t m, int64_t n, int64_t k,
-                                                    const double2 *__restrict__ A, int64_t lda,
-                                                    const double2 *__restrict__ B, int64_t ldb,
-                                                    double2 *__restrict__ C, int64_t ldc,
+                                                    const C2<T> *__restrict__ A, int64_t lda,
+                                                    const C2<T> *__restrict__ B, int64_t ldb,
+                                                    C2<T> *__restrict__ C, int64_t ldc,
                                                     double2 alpha, double2 beta, int64_t kchunk,
-                                                    double2 *__restrict__ part) {
-  __shared__ double As[2][BK][BM + PAD];
-  __shared__ double Bs[2][BK][BN + PAD];
+                                                    C2<T> *__restrict__ part) {
+  typedef C2<T> V2;
+  typedef typename Mma<T>::acc Acc;
+  __shared__ T As[2][BK][BM + PAD];
+  __shared__ T Bs[2][BK][BN + PAD];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -40,16 +61,16 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int64_t m, int64_t n, int64_
   const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
   const int64_t kend = (kbeg + kchunk < k) ? kbeg + kchunk : k;
 
-  v4d acc_re[2][2], acc_im[2][2];
+  Acc acc_re[2][2], acc_im[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      acc_re[i][j] = v4d{0, 0, 0, 0};
-      acc_im[i][j] = v4d{0, 0, 0, 0};
+      acc_re[i][j] = Acc{0, 0, 0, 0};
+      acc_im[i][j] = Acc{0, 0, 0, 0};
     }
 
-  double2 ra[4], rb[4];
+  V2 ra[4], rb[4];
   // Index maps: the thread-fastest index follows each operand's contiguous axis.
   auto a_idx = [&](int c, int *kk, int *i) {
     if (OPA == OP_N) {
@@ -75,12 +96,12 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int64_t m, int64_t n, int64_
       int kk, i;
       a_idx(c, &kk, &i);
       const int64_t gr = row0 + i, gk = k0 + kk;
-      ra[c] = double2{0, 0};
+      ra[c] = V2{0, 0};
       if (gr < m && gk < kend) ra[c] = (OPA == OP_N) ? A[gr + gk * lda] : A[gk + gr * lda];
       int j;
       b_idx(c, &kk, &j);
       const int64_t gc = col0 + j, gk2 = k0 + kk;
-      rb[c] = double2{0, 0};
+      rb[c] = V2{0, 0};
       if (gc < n && gk2 < kend) rb[c] = (OPB == OP_N) ? B[gk2 + gc * ldb] : B[gc + gk2 * ldb];
     }
   };
@@ -106,7 +127,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int64_t m, int64_t n, int64_
 #pragma unroll
     for (int kq = 0; kq < BK / 4; ++kq) {
       const int kk = kq * 4 + (lane >> 4);
-      double ar[2], ai[2], br[2], bi[2];
+      T ar[2], ai[2], br[2], bi[2];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const int ii = wm * 32 + s * 16 + (lane & 15);
@@ -120,21 +141,20 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int64_t m, int64_t n, int64_
       for (int si = 0; si < 2; ++si)
 #pragma unroll
         for (int sj = 0; sj < 2; ++sj) {
-          acc_re[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[si], br[sj], acc_re[si][sj], 0, 0, 0);
-          acc_im[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[si], bi[sj], acc_im[si][sj], 0, 0, 0);
+          acc_re[si][sj] = Mma<T>::run(ar[si], br[sj], acc_re[si][sj]);
+          acc_im[si][sj] = Mma<T>::run(ar[si], bi[sj], acc_im[si][sj]);
         }
 #pragma unroll
       for (int si = 0; si < 2; ++si)
 #pragma unroll
         for (int sj = 0; sj < 2; ++sj) {
-          acc_re[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[si], bi[sj], acc_re[si][sj], 0, 0, 0);
-          acc_im[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[si], br[sj], acc_im[si][sj], 0, 0, 0);
+          acc_re[si][sj] = Mma<T>::run(-ai[si], bi[sj], acc_re[si][sj]);
+          acc_im[si][sj] = Mma<T>::run(ai[si], br[sj], acc_im[si][sj]);
         }
     }
     __syncthreads();
   }
 
-  // D layout of the 16x16 f64 MFMA: lane l, element r -> row l/16 + 4r, column l%16.
   const bool use_beta = (beta.x != 0.0 || beta.y != 0.0);
 #pragma unroll
   for (int si = 0; si < 2; ++si)
@@ -142,15 +162,16 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int64_t m, int64_t n, int64_
     for (int sj = 0; sj < 2; ++sj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = row0 + wm * 32 + si * 16 + (lane >> 4) + 4 * r;
+        const int64_t row = row0 + wm * 32 + si * 16 + Mma<T>::row(lane, r);
         const int64_t col = col0 + wn * 32 + sj * 16 + (lane & 15);
         if (row < m && col < n) {
-          const double2 v{acc_re[si][sj][r], acc_im[si][sj][r]};
+          const V2 v{acc_re[si][sj][r], acc_im[si][sj][r]};
           if (SPLIT) {
             part[(int64_t)blockIdx.z * m * n + row + col * m] = v;
           } else {
-            double2 o = cmul(alpha, v);
-            if (use_beta) o = cadd(o, cmul(beta, C[row + col * ldc]));
+            const V2 al{(T)alpha.x, (T)alpha.y};
+            V2 o = cmul(al, v);
+            if (use_beta) o = cadd(o, cmul(V2{(T)beta.x, (T)beta.y}, C[row + col * ldc]));
             C[row + col * ldc] = o;
           }
         }
@@ -170,25 +191,25 @@ __global__ void zsum_parts_kernel(int64_t m, int64_t n, const double2 *__restric
   C[row + col * ldc] = o;
 }
 
-template <int OPA, int OPB, int TAG>
+template <typename T, int OPA, int OPB, int TAG>
 void launch_t(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
               int64_t ldb, void *C, int64_t ldc, double2 alpha, double2 beta, hipStream_t st,
               void *part, int splits) {
+  typedef C2<T> V2;
   const int64_t chunk = part ? ((k + splits - 1) / splits + BK - 1) / BK * BK : k;
   // every chunk index gets launched; a chunk past the end of K writes zeros
   const int zs = part ? splits : 1;
   dim3 grid((unsigned)((m + BM - 1) / BM), (unsigned)((n + BN - 1) / BN), (unsigned)zs);
   if (part) {
-    hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, true, TAG>), grid, dim3(256), 0, st, m, n, k,
-                       (const double2 *)A, lda, (const double2 *)B, ldb, (double2 *)C, ldc,
-                       alpha, beta, chunk, (double2 *)part);
-    CHEBFI_HIP(hipGetLastError());
+    hipLaunchKernelGGL((zgemm_kernel<T, OPA, OPB, true, TAG>), grid, dim3(256), 0, st, m, n, k,
+                       (const V2 *)A, lda, (const V2 *)B, ldb, (V2 *)C, ldc, alpha, beta, chunk,
+                       (V2 *)part);
   } else {
-    hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, false, TAG>), grid, dim3(256), 0, st, m, n, k,
-                       (const double2 *)A, lda, (const double2 *)B, ldb, (double2 *)C, ldc,
-                       alpha, beta, chunk, (double2 *)nullptr);
-    CHEBFI_HIP(hipGetLastError());
+    hipLaunchKernelGGL((zgemm_kernel<T, OPA, OPB, false, TAG>), grid, dim3(256), 0, st, m, n, k,
+                       (const V2 *)A, lda, (const V2 *)B, ldb, (V2 *)C, ldc, alpha, beta, chunk,
+                       (V2 *)nullptr);
   }
+  CHEBFI_HIP(hipGetLastError());
 }
 
 }  // namespace
@@ -208,25 +229,33 @@ void zgemm(Op opa, Op opb, int64_t m, int64_t n, int64_t k, const void *A, int64
            hipStream_t st, void *part, int splits) {
   if (m <= 0 || n <= 0) return;
   if (opa == OP_N && opb == OP_N)
-    launch_t<OP_N, OP_N, 0>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
+    launch_t<double, OP_N, OP_N, 0>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
   else if (opa == OP_C && opb == OP_N)
-    launch_t<OP_C, OP_N, 0>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
+    launch_t<double, OP_C, OP_N, 0>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
   else if (opa == OP_N && opb == OP_C)
-    launch_t<OP_N, OP_C, 0>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
+    launch_t<double, OP_N, OP_C, 0>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
   else
-    launch_t<OP_C, OP_C, 0>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
+    launch_t<double, OP_C, OP_C, 0>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, st, part, splits);
 }
 
 void proj_gemm(int64_t nproj, int64_t nband, int64_t npw, const void *P, const void *X,
-               int64_t ldx, void *part, int splits, hipStream_t st) {
-  launch_t<OP_C, OP_N, 1>(nproj, nband, npw, P, npw, X, ldx, nullptr, 0, double2{1, 0},
-                          double2{0, 0}, st, part, splits);
+               int64_t ldx, void *part, int splits, hipStream_t st, bool fp32) {
+  if (fp32)
+    launch_t<float, OP_C, OP_N, 1>(nproj, nband, npw, P, npw, X, ldx, nullptr, 0, double2{1, 0},
+                                   double2{0, 0}, st, part, splits);
+  else
+    launch_t<double, OP_C, OP_N, 1>(nproj, nband, npw, P, npw, X, ldx, nullptr, 0, double2{1, 0},
+                                    double2{0, 0}, st, part, splits);
 }
 
 void expand_gemm(int64_t npw, int64_t nband, int64_t nproj, const void *P, const void *Cp,
-                 void *Out, int64_t ldo, hipStream_t st) {
-  launch_t<OP_N, OP_N, 1>(npw, nband, nproj, P, npw, Cp, nproj, Out, ldo, double2{1, 0},
-                          double2{1, 0}, st, nullptr, 1);
+                 void *Out, int64_t ldo, hipStream_t st, bool fp32) {
+  if (fp32)
+    launch_t<float, OP_N, OP_N, 1>(npw, nband, nproj, P, npw, Cp, nproj, Out, ldo, double2{1, 0},
+                                   double2{1, 0}, st, nullptr, 1);
+  else
+    launch_t<double, OP_N, OP_N, 1>(npw, nband, nproj, P, npw, Cp, nproj, Out, ldo, double2{1, 0},
+                                    double2{1, 0}, st, nullptr, 1);
 }
 
 namespace {

@@ -128,10 +128,13 @@ struct abi_system_s {
   double *d_D = nullptr;           // natom*16 complex, row-major per atom
   double *d_V = nullptr;           // n1*n2*n3
   double *d_tw = nullptr;          // 3 * kMaxN complex twiddles exp(-2 pi i j/n_d)
+  // mixed-precision copies (ABI_PREC_MIXED handles only)
+  float *d_Pf = nullptr;           // npw x nproj complex float
+  float *d_Vf = nullptr;           // n1*n2*n3 float
 
   // work buffers
   chebfi::DevBuf box, cpart, cprime, blk1, blk2, blk3, small1, small2, small3, small4, scal;
-  chebfi::DevBuf eig1, eig2, eig3;
+  chebfi::DevBuf eig1, eig2, eig3, blk4;
 
   int fft_batch = 0;  // bands per FFT batch (box buffer holds this many boxes)
   chebfi::Profiler prof;

@@ -33,10 +33,11 @@ void zgemm(Op opa, Op opb, int64_t m, int64_t n, int64_t k, const void *A, int64
 
 // Projector products of the H application (same kernels, own instantiations):
 // part[z] = P^H X over K chunk z, and Out += P C'.
+// fp32 = true: complex float operands and FP32 MFMA (mixed form).
 void proj_gemm(int64_t nproj, int64_t nband, int64_t npw, const void *P, const void *X,
-               int64_t ldx, void *part, int splits, hipStream_t st);
+               int64_t ldx, void *part, int splits, hipStream_t st, bool fp32 = false);
 void expand_gemm(int64_t npw, int64_t nband, int64_t nproj, const void *P, const void *Cp,
-                 void *Out, int64_t ldo, hipStream_t st);
+                 void *Out, int64_t ldo, hipStream_t st, bool fp32 = false);
 // Single-band forms: c = P^H x, out += P c.
 void proj_gemv(int64_t npw, int nproj, const void *P, const void *x, void *c, hipStream_t st);
 void expand_gemv(int64_t npw, int nproj, const void *P, const void *c, void *out, hipStream_t st);
@@ -50,12 +51,19 @@ void zsum_parts(int64_t m, int64_t n, const void *part, int splits, void *C, int
 
 // ---- stream.hip -------------------------------------------------------------
 // Cprime[4R+i, b] = alpha * sum_j D_R[i][j] * sum_z part[z][4R+j, b]
+// (fp32: complex float partials and output, FP64 arithmetic inside)
 void launch_dapply(int natom, int64_t nband, const void *part, int splits, const void *D,
-                   double alpha, void *Cprime, hipStream_t st);
+                   double alpha, void *Cprime, hipStream_t st, bool fp32 = false);
 
 // rq[b] = Re(x_b^H hx_b) / (x_b^H x_b)
 void launch_rayleigh_quotients(int64_t npw, int64_t nband, const void *X, int64_t ldx,
-                               const void *HX, int64_t ldh, double *rq, hipStream_t st);
+                               const void *HX, int64_t ldh, double *rq, hipStream_t st,
+                               bool fp32 = false);
+// complex block precision conversions (round to nearest when narrowing)
+void launch_c64_to_c128(int64_t rows, int64_t cols, const void *src, int64_t lds, void *dst,
+                        int64_t ldd, hipStream_t st);
+void launch_c128_to_c64(int64_t rows, int64_t cols, const void *src, int64_t lds, void *dst,
+                        int64_t ldd, hipStream_t st);
 // out[0] = max rq, out[2] = min rq
 void launch_minmax(int64_t n, const double *rq, double *out, hipStream_t st);
 

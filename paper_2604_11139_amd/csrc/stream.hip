@@ -35,9 +35,10 @@ __device__ double block_sum(double v, double *scratch) {
   return t;
 }
 
-__global__ void dapply_kernel(int natom, int64_t nband, const double2 *__restrict__ part,
+template <typename T>
+__global__ void dapply_kernel(int natom, int64_t nband, const C2<T> *__restrict__ part,
                               int splits, const double2 *__restrict__ D, double alpha,
-                              double2 *__restrict__ Cp) {
+                              C2<T> *__restrict__ Cp) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)natom * nband) return;
   const int64_t R = idx % natom, b = idx / natom;
@@ -47,7 +48,11 @@ __global__ void dapply_kernel(int natom, int64_t nband, const double2 *__restric
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     double2 s{0, 0};
-    for (int z = 0; z < splits; ++z) s = cadd(s, part[(int64_t)z * mn + (4 * R + j) + b * nproj]);
+    for (int z = 0; z < splits; ++z) {
+      const C2<T> v = part[(int64_t)z * mn + (4 * R + j) + b * nproj];
+      s.x += (double)v.x;
+      s.y += (double)v.y;
+    }
     c[j] = s;
   }
   const double2 *d = D + 16 * R;
@@ -56,25 +61,36 @@ __global__ void dapply_kernel(int natom, int64_t nband, const double2 *__restric
     double2 s{0, 0};
 #pragma unroll
     for (int j = 0; j < 4; ++j) s = cadd(s, cmul(d[4 * i + j], c[j]));
-    Cp[(4 * R + i) + b * nproj] = cscale(s, alpha);
+    Cp[(4 * R + i) + b * nproj] = C2<T>{(T)(alpha * s.x), (T)(alpha * s.y)};
   }
 }
 
-__global__ void rq_kernel(int64_t npw, const double2 *__restrict__ X, int64_t ldx,
-                          const double2 *__restrict__ HX, int64_t ldh, double *__restrict__ rq) {
+template <typename T>
+__global__ void rq_kernel(int64_t npw, const C2<T> *__restrict__ X, int64_t ldx,
+                          const C2<T> *__restrict__ HX, int64_t ldh, double *__restrict__ rq) {
   __shared__ double scratch[16];
   const int64_t b = blockIdx.x;
-  const double2 *x = X + b * ldx;
-  const double2 *h = HX + b * ldh;
+  const C2<T> *x = X + b * ldx;
+  const C2<T> *h = HX + b * ldh;
   double num = 0, den = 0;
   for (int64_t i = threadIdx.x; i < npw; i += blockDim.x) {
-    const double2 xv = x[i], hv = h[i];
-    num += xv.x * hv.x + xv.y * hv.y;
-    den += xv.x * xv.x + xv.y * xv.y;
+    const C2<T> xv = x[i], hv = h[i];
+    num += (double)xv.x * hv.x + (double)xv.y * hv.y;
+    den += (double)xv.x * xv.x + (double)xv.y * xv.y;
   }
   num = block_sum(num, scratch);
   den = block_sum(den, scratch);
   if (threadIdx.x == 0) rq[b] = num / den;
+}
+
+template <typename S, typename D>
+__global__ void convert_block_kernel(int64_t rows, int64_t cols, const C2<S> *__restrict__ src,
+                                     int64_t lds, C2<D> *__restrict__ dst, int64_t ldd) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t i = idx % rows, j = idx / rows;
+  const C2<S> v = src[i + j * lds];
+  dst[i + j * ldd] = C2<D>{(D)v.x, (D)v.y};
 }
 
 __global__ void minmax_kernel(int64_t n, const double *__restrict__ v, double *__restrict__ out) {
@@ -261,18 +277,45 @@ inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 }  // namespace
 
 void launch_dapply(int natom, int64_t nband, const void *part, int splits, const void *D,
-                   double alpha, void *Cprime, hipStream_t st) {
+                   double alpha, void *Cprime, hipStream_t st, bool fp32) {
   const int64_t total = (int64_t)natom * nband;
   if (total <= 0) return;
-  hipLaunchKernelGGL(dapply_kernel, dim3(nblk(total, 256)), dim3(256), 0, st, natom, nband,
-                     (const double2 *)part, splits, (const double2 *)D, alpha, (double2 *)Cprime);
+  if (fp32)
+    hipLaunchKernelGGL(dapply_kernel<float>, dim3(nblk(total, 256)), dim3(256), 0, st, natom,
+                       nband, (const float2 *)part, splits, (const double2 *)D, alpha,
+                       (float2 *)Cprime);
+  else
+    hipLaunchKernelGGL(dapply_kernel<double>, dim3(nblk(total, 256)), dim3(256), 0, st, natom,
+                       nband, (const double2 *)part, splits, (const double2 *)D, alpha,
+                       (double2 *)Cprime);
   CHEBFI_HIP(hipGetLastError());
 }
 
 void launch_rayleigh_quotients(int64_t npw, int64_t nband, const void *X, int64_t ldx,
-                               const void *HX, int64_t ldh, double *rq, hipStream_t st) {
-  hipLaunchKernelGGL(rq_kernel, dim3((unsigned)nband), dim3(kRedThreads), 0, st, npw,
-                     (const double2 *)X, ldx, (const double2 *)HX, ldh, rq);
+                               const void *HX, int64_t ldh, double *rq, hipStream_t st,
+                               bool fp32) {
+  if (fp32)
+    hipLaunchKernelGGL(rq_kernel<float>, dim3((unsigned)nband), dim3(kRedThreads), 0, st, npw,
+                       (const float2 *)X, ldx, (const float2 *)HX, ldh, rq);
+  else
+    hipLaunchKernelGGL(rq_kernel<double>, dim3((unsigned)nband), dim3(kRedThreads), 0, st, npw,
+                       (const double2 *)X, ldx, (const double2 *)HX, ldh, rq);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_c64_to_c128(int64_t rows, int64_t cols, const void *src, int64_t lds, void *dst,
+                        int64_t ldd, hipStream_t st) {
+  if (rows * cols <= 0) return;
+  hipLaunchKernelGGL((convert_block_kernel<float, double>), dim3(nblk(rows * cols, 256)),
+                     dim3(256), 0, st, rows, cols, (const float2 *)src, lds, (double2 *)dst, ldd);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_c128_to_c64(int64_t rows, int64_t cols, const void *src, int64_t lds, void *dst,
+                        int64_t ldd, hipStream_t st) {
+  if (rows * cols <= 0) return;
+  hipLaunchKernelGGL((convert_block_kernel<double, float>), dim3(nblk(rows * cols, 256)),
+                     dim3(256), 0, st, rows, cols, (const double2 *)src, lds, (float2 *)dst, ldd);
   CHEBFI_HIP(hipGetLastError());
 }
 

@@ -1,0 +1,131 @@
+"""FP32-mixed form against the FP64 oracle (needs an MI355X).
+
+The mixed form runs the FFT passes, the recurrence and the projector products in
+single precision on complex64 blocks and keeps the bounds' Lanczos run, the
+Cholesky factorisation, the eigensolver and the Rayleigh-Ritz step in FP64.
+There is no closed form for its rounding error, so it is compared with the FP64
+oracle within error budgets derived from FP32 rounding (unit roundoff 6e-8):
+
+* one H application: per column ||diff||/||ref|| <= 2e-6 (FFT of 3 passes of
+  log2 n radix stages plus FP32-accumulated projector sums);
+* degree-m filter: <= 5e-6 * m per column;
+* Rayleigh-Ritz of a complex64 block: the FP64 pencil of that block, so FP64
+  tolerance (1e-8 Ha) against the oracle run on the same rounded block;
+* a full cycle (bounds, filter, Rayleigh-Ritz): Ritz values within 1e-6 Ha of
+  the FP64 oracle's cycle.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from paper_2604_11139_amd import binding as B
+
+from gpu_util import col_rel_err, hamiltonian, system, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ["odd15", "n27", "c1"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    B.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def _mixed(name):
+    return B.System(system(name), precision=B.ABI_PREC_MIXED)
+
+
+def _c64(X):
+    return to_dev(X).to(dtype=__import__("torch").complex64)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_mixed_apply_H(name):
+    H = hamiltonian(name)
+    s = system(name)
+    X = W.random_block(H.npw, s.nband, s.tag).astype(np.complex64).astype(np.complex128)
+    with _mixed(name) as g:
+        got = to_host(g.apply_H(_c64(X)))
+    assert got.dtype == np.complex64
+    assert col_rel_err(got.astype(np.complex128), H(X)) <= 2e-6
+
+
+@pytest.mark.parametrize("name,degree", [("odd15", 3), ("n27", 6), ("c1", 8)])
+def test_mixed_filter(name, degree):
+    H = hamiltonian(name)
+    s = system(name)
+    X = W.random_block(H.npw, s.nband, s.tag).astype(np.complex64).astype(np.complex128)
+    v0 = W.random_vector(H.npw, s.tag)
+    a, b, a0 = O.filter_bounds(H, X, v0)
+    ref = O.cheb_filter(H, X, degree, a, b, a0)
+    with _mixed(name) as g:
+        got = to_host(g.cheb_filter(_c64(X), degree, a, b, a0)).astype(np.complex128)
+    assert col_rel_err(got, ref) <= 5e-6 * degree
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_mixed_bounds(name):
+    H = hamiltonian(name)
+    s = system(name)
+    X = W.random_block(H.npw, s.nband, s.tag).astype(np.complex64).astype(np.complex128)
+    v0 = W.random_vector(H.npw, s.tag)
+    a, b, a0 = O.filter_bounds(H, X, v0)
+    with _mixed(name) as g:
+        ga, gb, ga0 = g.spectral_bounds(_c64(X), to_dev(v0))
+    assert abs(ga - a) <= 2e-6 * max(1.0, abs(a))
+    assert abs(ga0 - a0) <= 2e-6 * max(1.0, abs(a0))
+    assert abs(gb - b) <= 1e-10 * abs(b)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_mixed_rayleigh_ritz_is_fp64(name):
+    H = hamiltonian(name)
+    s = system(name)
+    X = W.random_block(H.npw, s.nband, s.tag)
+    v0 = W.random_vector(H.npw, s.tag)
+    a, b, a0 = O.filter_bounds(H, X, v0)
+    Y = O.cheb_filter(H, X, 6, a, b, a0).astype(np.complex64).astype(np.complex128)
+    rr = O.rayleigh_ritz(H, Y)
+    with _mixed(name) as g:
+        Yd = _c64(Y)
+        ev, res, flags = g.rayleigh_ritz(Yd)
+    assert np.abs(ev - rr["eval"]).max() <= 1e-8
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_mixed_cycle_eigenvalues(name):
+    """Two cycles: Ritz values within 1e-6 Ha of the FP64 oracle's cycles."""
+    H = hamiltonian(name)
+    s = system(name)
+    X = W.random_block(H.npw, s.nband, s.tag)
+    v0 = W.random_vector(H.npw, s.tag)
+    Xr = X.copy()
+    for _ in range(2):
+        a, b, a0 = O.filter_bounds(H, Xr, v0)
+        rr = O.rayleigh_ritz(H, O.cheb_filter(H, Xr, s.degree, a, b, a0))
+        Xr = rr["Psi"]
+    with _mixed(name) as g:
+        Xd = _c64(X)
+        v0d = to_dev(v0)
+        for _ in range(2):
+            ga, gb, ga0 = g.spectral_bounds(Xd, v0d)
+            Yd = g.cheb_filter(Xd, s.degree, ga, gb, ga0)
+            ev, res, _ = g.rayleigh_ritz(Yd)
+            Xd = Yd
+    assert np.abs(ev - rr["eval"]).max() <= 1e-6
+
+
+def test_c64_needs_mixed_handle():
+    import torch
+    s = system("tiny_k")
+    with B.System(s) as g:
+        X = torch.zeros((2, g.npw), dtype=torch.complex64, device="cuda")
+        with pytest.raises(B.ChebfiError) as e:
+            g.apply_H(X)
+        assert e.value.code == B.ABI_ERR_STATE
