@@ -2,7 +2,9 @@
 """Throughput of the Chebyshev-filter hot path on one MI355X.
 
 Metric: H.psi band-applications per second inside the Chebyshev filter
-(degree x nband per filter call / filter time).  One step is one full cycle of
+(degree x nband per filter call / filter time), for the FP32-mixed form
+(`value`) with the plain FP64 form timed beside it on the same GPU from the
+same start block, and the largest Ritz-value difference between the two.  One step is one full cycle of
 the path on one block: spectral bounds (Rayleigh quotients + 10-step Lanczos),
 the degree-m filter, and Rayleigh-Ritz (Gram, Cholesky, subspace H,
 eigensolver, rotations, residual norms); the Ritz vectors of a step are the
@@ -75,12 +77,18 @@ def cpu_baseline(s, degree, bounds, nbands):
     }
 
 
-def roofline_of(prof, peak_mfma, mfma_label):
-    """Dominant H-application kernel class (by time) and its live achieved rate."""
+def roofline_of(prof, peak_mfma, mfma_label, gemm_work_factor=1.0):
+    """Dominant H-application kernel class (by time) and its live achieved rate.
+
+    GEMM work is the complex product's 8 N_pw N_proj flops per band times
+    `gemm_work_factor` (3 for the split-BF16 form, which executes three bf16
+    products per real product)."""
     gemm_cls = ("proj_gemm", "expand_gemm")
     h_cls = ("proj_gemm", "expand_gemm", "fft_a", "fft_b", "fft_c", "dapply")
     dom = max(h_cls, key=lambda c: prof[c][0])
     ms_tot, work, cnt = prof[dom]
+    if dom in gemm_cls:
+        work *= gemm_work_factor
     avg_s = ms_tot / 1e3 / max(cnt, 1)
     per_launch = work / max(cnt, 1)
     if dom in gemm_cls:
@@ -220,8 +228,9 @@ def main():
             "workload": f"config{args.config}: cubic a={s.a:g} bohr, Ecut={s.ecut:g} Ha, "
                         f"{npw} plane waves, {s.ngrid[0]}^3 FFT grid, {s.natom} atoms / "
                         f"{4 * s.natom} projectors, {nband} bands, Chebyshev degree {degree}, "
-                        + ("FP32-mixed filter (complex64 FFT + recurrence, FP32 MFMA projector "
-                           "products) with FP64 bounds / Cholesky / eigensolver / Rayleigh-Ritz"
+                        + ("FP32-mixed filter (complex64 FFT + recurrence, split-BF16 MFMA "
+                           "projector products accumulated in FP32) with FP64 Lanczos bounds / "
+                           "Cholesky / eigensolver / Rayleigh-Ritz"
                            if mixed else "plain FP64 form"),
             "npw": npw, "nband": nband, "degree": degree, "ngrid": list(s.ngrid),
             "nproj": 4 * s.natom, "precision": "mixed" if mixed else "fp64",
@@ -230,8 +239,8 @@ def main():
         "cycle_band_apps_per_s": round(head["cycle_band_apps_per_s"], 2),
         "setup_s": round(t_setup, 2),
         "max_residual_last_step": float(head["res"].max()),
-        "roofline": roofline_of(head["prof"], PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS,
-                                "fp32 MFMA" if mixed else "fp64 MFMA"),
+        "roofline": (roofline_of(head["prof"], PEAK_BF16_TFLOPS, "bf16 MFMA (split-BF16 x3)", 3.0)
+                     if mixed else roofline_of(head["prof"], PEAK_FP64_TFLOPS, "fp64 MFMA")),
         "kernel_classes": class_table(head["prof"]),
     }
     if "fp64" in runs and mixed:

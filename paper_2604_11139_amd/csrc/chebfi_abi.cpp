@@ -146,7 +146,8 @@ template <typename T> T *upload(const T *host, size_t count) {
 }
 
 void free_tables(abi_system_s *s) {
-  void *ptrs[] = {s->d_kin, s->d_box, s->d_plane, s->d_P, s->d_D, s->d_V, s->d_tw, s->d_Pf, s->d_Vf};
+  void *ptrs[] = {s->d_kin, s->d_box, s->d_plane, s->d_P, s->d_D, s->d_V,
+                  s->d_tw,  s->d_Pf,  s->d_Vf,    s->d_PA, s->d_PB};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   s->d_kin = nullptr;
@@ -158,6 +159,22 @@ void free_tables(abi_system_s *s) {
   s->d_tw = nullptr;
   s->d_Pf = nullptr;
   s->d_Vf = nullptr;
+  s->d_PA = nullptr;
+  s->d_PB = nullptr;
+}
+
+// bf16 round-to-nearest-even of a float and its value (host side)
+uint16_t bf16_rn_host(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf16_val_host(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
 }
 
 void check_block(const abi_system_s *s, const void *p, int64_t nband, int64_t ld, int32_t dtype) {
@@ -197,6 +214,9 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
     int tok = s->prof.begin(PROF_PROJ, flops, st);
     if (single)
       proj_gemv(npw, nproj, P, X, cpart, st);
+    else if (fp32 && s->mixed_gemm == 0)
+      proj_gemm_bf16x3(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, X, ldx,
+                       cpart, splits, st);
     else
       proj_gemm(nproj, nband, npw, P, X, ldx, cpart, splits, st, fp32);
     s->prof.end(tok, st);
@@ -218,6 +238,9 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
     int tok = s->prof.begin(PROF_EXPAND, flops, st);
     if (single)
       expand_gemv(npw, nproj, P, cprime, Out, st);
+    else if (fp32 && s->mixed_gemm == 0)
+      expand_gemm_bf16x3(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB, cprime, Out, ldo,
+                         st);
     else
       expand_gemm(npw, nband, nproj, P, cprime, Out, ldo, st, fp32);
     s->prof.end(tok, st);
@@ -399,6 +422,28 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
       for (int64_t i = 0; i < nbox; ++i) Vf[i] = (float)desc->vloc[i];
       s->d_Pf = upload(Pf.data(), Pf.size());
       s->d_Vf = upload(Vf.data(), Vf.size());
+      // split-BF16 planes in the two k-contiguous layouts the projector GEMMs read
+      const int64_t npw = s->npw, np = s->nproj;
+      s->ldPA = (npw + 63) / 64 * 64;
+      s->ldPB = (np + 7) / 8 * 8;
+      const size_t szA = (size_t)np * s->ldPA, szB = (size_t)npw * s->ldPB;
+      std::vector<uint16_t> PA(4 * szA, 0), PB(4 * szB, 0);
+      for (int64_t j = 0; j < np; ++j)
+        for (int64_t g = 0; g < npw; ++g) {
+          const size_t src = 2 * ((size_t)j * npw + g);
+          for (int part = 0; part < 2; ++part) {
+            const float x = Pf[src + part];
+            const uint16_t hi = bf16_rn_host(x);
+            const uint16_t lo = bf16_rn_host(x - bf16_val_host(hi));
+            PA[(size_t)part * szA + j * s->ldPA + g] = hi;
+            PA[(size_t)(2 + part) * szA + j * s->ldPA + g] = lo;
+            PB[(size_t)part * szB + g * s->ldPB + j] = hi;
+            PB[(size_t)(2 + part) * szB + g * s->ldPB + j] = lo;
+          }
+        }
+      s->d_PA = upload(PA.data(), PA.size());
+      s->d_PB = upload(PB.data(), PB.size());
+      if (const char *e = std::getenv("CHEBFI_MIXED_GEMM")) s->mixed_gemm = (std::atoi(e) == 1);
     }
     // bands per FFT batch: keep the box buffer near 128 MiB (env override)
     int64_t fb = (int64_t)((128ll << 20) / (sizeof(double2) * nbox));

@@ -302,6 +302,189 @@ __global__ __launch_bounds__(256) void expand_gemv_kernel(int64_t npw, int nproj
 
 }  // namespace
 
+namespace {
+
+// ---- split-BF16 complex GEMM (mixed form) ------------------------------------
+// Each real operand x is carried as hi = bf16(x), lo = bf16(x - hi) and every
+// real product as hi*hi + hi*lo + lo*hi, accumulated in FP32 (the bf16x3
+// method of Henry, Tang and Heinecke, ARITH 2019; relative error ~2^-16).
+// A is given as four bf16 planes (Re hi, Im hi, Re lo, Im lo), row-major with
+// the contraction index contiguous; B is complex float, column-major, split
+// while it is staged into LDS.  CONJ selects op(A) = A^H (the projection
+// P^H Y, with A holding the rows of P^T) instead of A.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned short u16;
+
+constexpr int XBM = 64, XBN = 64, XBK = 32, XPAD = 8;
+
+__device__ __forceinline__ u16 bf16_rn(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (u16)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(u16 h) { return __uint_as_float(((unsigned)h) << 16); }
+
+__device__ __forceinline__ v4f mfma_bf16(const v8bf &a, const v8bf &b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+template <bool CONJ, bool SPLIT>
+__global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(
+    int64_t m, int64_t n, int64_t k, const u16 *__restrict__ Apl, int64_t lda, int64_t pstride,
+    const float2 *__restrict__ B, int64_t ldb, float2 *__restrict__ C, int64_t ldc,
+    int64_t kchunk, float2 *__restrict__ part) {
+  __shared__ __align__(16) u16 As[4][XBM][XBK + XPAD];
+  __shared__ __align__(16) u16 Bs[4][XBN][XBK + XPAD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int64_t row0 = (int64_t)blockIdx.x * XBM, col0 = (int64_t)blockIdx.y * XBN;
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = (kbeg + kchunk < k) ? kbeg + kchunk : k;
+
+  v4f acc[2][2][4];  // [si][sj][rr, ii, ri, ir]
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[i][j][q] = v4f{0, 0, 0, 0};
+
+  uint4 ra[4];
+  float2 rb[8];
+  auto load_tiles = [&](int64_t k0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int idx = tid + 256 * c;
+      const int kc = idx & 3, i = (idx >> 2) & 63, p = idx >> 8;
+      const int64_t gr = row0 + i, ks = k0 + 8 * kc;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (gr < m && ks < kend) {
+        const u16 *src = Apl + (int64_t)p * pstride + gr * lda + ks;
+        if (ks + 8 <= kend) {
+          v = *reinterpret_cast<const uint4 *>(src);
+        } else {
+          u16 t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+          for (int e = 0; e < 8 && ks + e < kend; ++e) t[e] = src[e];
+          v = make_uint4(t[0] | ((unsigned)t[1] << 16), t[2] | ((unsigned)t[3] << 16),
+                         t[4] | ((unsigned)t[5] << 16), t[6] | ((unsigned)t[7] << 16));
+        }
+      }
+      ra[c] = v;
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int idx = tid + 256 * c;
+      const int kk = idx & 31, j = idx >> 5;
+      const int64_t gc = col0 + j, gk = k0 + kk;
+      rb[c] = (gc < n && gk < kend) ? B[gk + gc * ldb] : float2{0.f, 0.f};
+    }
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int idx = tid + 256 * c;
+      const int kc = idx & 3, i = (idx >> 2) & 63, p = idx >> 8;
+      *reinterpret_cast<uint4 *>(&As[p][i][8 * kc]) = ra[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int idx = tid + 256 * c;
+      const int kk = idx & 31, j = idx >> 5;
+      const u16 hr = bf16_rn(rb[c].x), hi = bf16_rn(rb[c].y);
+      Bs[0][j][kk] = hr;
+      Bs[1][j][kk] = hi;
+      Bs[2][j][kk] = bf16_rn(rb[c].x - bf16_val(hr));
+      Bs[3][j][kk] = bf16_rn(rb[c].y - bf16_val(hi));
+    }
+  };
+
+  if (kbeg < kend) load_tiles(kbeg);
+  const int kb = 8 * (lane >> 4);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += XBK) {
+    store_tiles();
+    __syncthreads();
+    if (k0 + XBK < kend) load_tiles(k0 + XBK);
+    v8bf a[2][4], b[2][4];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int ii = wm * 32 + s2 * 16 + (lane & 15);
+      const int jj = wn * 32 + s2 * 16 + (lane & 15);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        a[s2][p] = *reinterpret_cast<const v8bf *>(&As[p][ii][kb]);
+        b[s2][p] = *reinterpret_cast<const v8bf *>(&Bs[p][jj][kb]);
+      }
+    }
+#pragma unroll
+    for (int si = 0; si < 2; ++si)
+#pragma unroll
+      for (int sj = 0; sj < 2; ++sj) {
+        // planes: 0 Re hi, 1 Im hi, 2 Re lo, 3 Im lo
+        v4f *q = acc[si][sj];
+        q[0] = mfma_bf16(a[si][0], b[sj][0], q[0]);
+        q[1] = mfma_bf16(a[si][1], b[sj][1], q[1]);
+        q[2] = mfma_bf16(a[si][0], b[sj][1], q[2]);
+        q[3] = mfma_bf16(a[si][1], b[sj][0], q[3]);
+        q[0] = mfma_bf16(a[si][0], b[sj][2], q[0]);
+        q[1] = mfma_bf16(a[si][1], b[sj][3], q[1]);
+        q[2] = mfma_bf16(a[si][0], b[sj][3], q[2]);
+        q[3] = mfma_bf16(a[si][1], b[sj][2], q[3]);
+        q[0] = mfma_bf16(a[si][2], b[sj][0], q[0]);
+        q[1] = mfma_bf16(a[si][3], b[sj][1], q[1]);
+        q[2] = mfma_bf16(a[si][2], b[sj][1], q[2]);
+        q[3] = mfma_bf16(a[si][3], b[sj][0], q[3]);
+      }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int si = 0; si < 2; ++si)
+#pragma unroll
+    for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + wm * 32 + si * 16 + 4 * (lane >> 4) + r;
+        const int64_t col = col0 + wn * 32 + sj * 16 + (lane & 15);
+        if (row < m && col < n) {
+          const float rr = acc[si][sj][0][r], ii = acc[si][sj][1][r];
+          const float ri = acc[si][sj][2][r], ir = acc[si][sj][3][r];
+          const float2 v = CONJ ? float2{rr + ii, ri - ir} : float2{rr - ii, ri + ir};
+          if (SPLIT) {
+            part[(int64_t)blockIdx.z * m * n + row + col * m] = v;
+          } else {
+            float2 o = C[row + col * ldc];
+            o.x += v.x;
+            o.y += v.y;
+            C[row + col * ldc] = o;
+          }
+        }
+      }
+}
+
+}  // namespace
+
+void proj_gemm_bf16x3(int64_t nproj, int64_t nband, int64_t npw, const void *Apl, int64_t lda,
+                      int64_t pstride, const void *Y, int64_t ldy, void *part, int splits,
+                      hipStream_t st) {
+  const int64_t chunk = ((npw + splits - 1) / splits + XBK - 1) / XBK * XBK;
+  dim3 grid((unsigned)((nproj + XBM - 1) / XBM), (unsigned)((nband + XBN - 1) / XBN),
+            (unsigned)splits);
+  hipLaunchKernelGGL((zgemm_bf16x3_kernel<true, true>), grid, dim3(256), 0, st, nproj, nband, npw,
+                     (const u16 *)Apl, lda, pstride, (const float2 *)Y, ldy, (float2 *)nullptr,
+                     (int64_t)0, chunk, (float2 *)part);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void expand_gemm_bf16x3(int64_t npw, int64_t nband, int64_t nproj, const void *Apl, int64_t lda,
+                        int64_t pstride, const void *Cp, void *Out, int64_t ldo, hipStream_t st) {
+  dim3 grid((unsigned)((npw + XBM - 1) / XBM), (unsigned)((nband + XBN - 1) / XBN), 1);
+  hipLaunchKernelGGL((zgemm_bf16x3_kernel<false, false>), grid, dim3(256), 0, st, npw, nband,
+                     nproj, (const u16 *)Apl, lda, pstride, (const float2 *)Cp, nproj,
+                     (float2 *)Out, ldo, nproj, (float2 *)nullptr);
+  CHEBFI_HIP(hipGetLastError());
+}
+
 void proj_gemv(int64_t npw, int nproj, const void *P, const void *x, void *c, hipStream_t st) {
   hipLaunchKernelGGL(proj_gemv_kernel, dim3((unsigned)nproj), dim3(256), 0, st, npw,
                      (const double2 *)P, (const double2 *)x, (double2 *)c);

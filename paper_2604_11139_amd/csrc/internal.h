@@ -131,6 +131,11 @@ struct abi_system_s {
   // mixed-precision copies (ABI_PREC_MIXED handles only)
   float *d_Pf = nullptr;           // npw x nproj complex float
   float *d_Vf = nullptr;           // n1*n2*n3 float
+  // split-BF16 planes of P (Re hi, Im hi, Re lo, Im lo), k-contiguous rows:
+  uint16_t *d_PA = nullptr;        // rows = projectors, k = plane waves (stride ldPA)
+  uint16_t *d_PB = nullptr;        // rows = plane waves, k = projectors (stride ldPB)
+  int64_t ldPA = 0, ldPB = 0;
+  int mixed_gemm = 0;              // 0: split-BF16 MFMA, 1: FP32 MFMA projector products
 
   // work buffers
   chebfi::DevBuf box, cpart, cprime, blk1, blk2, blk3, small1, small2, small3, small4, scal;

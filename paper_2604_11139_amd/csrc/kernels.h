@@ -38,6 +38,15 @@ void proj_gemm(int64_t nproj, int64_t nband, int64_t npw, const void *P, const v
                int64_t ldx, void *part, int splits, hipStream_t st, bool fp32 = false);
 void expand_gemm(int64_t npw, int64_t nband, int64_t nproj, const void *P, const void *Cp,
                  void *Out, int64_t ldo, hipStream_t st, bool fp32 = false);
+// Split-BF16 forms (mixed precision): A holds four bf16 planes (Re hi, Im hi,
+// Re lo, Im lo) of P^T (projection, rows = projectors, k = plane waves) or of P
+// (expansion, rows = plane waves, k = projectors), row stride lda (a multiple
+// of 8), plane stride pstride; blocks are complex float.
+void proj_gemm_bf16x3(int64_t nproj, int64_t nband, int64_t npw, const void *Apl, int64_t lda,
+                      int64_t pstride, const void *Y, int64_t ldy, void *part, int splits,
+                      hipStream_t st);
+void expand_gemm_bf16x3(int64_t npw, int64_t nband, int64_t nproj, const void *Apl, int64_t lda,
+                        int64_t pstride, const void *Cp, void *Out, int64_t ldo, hipStream_t st);
 // Single-band forms: c = P^H x, out += P c.
 void proj_gemv(int64_t npw, int nproj, const void *P, const void *x, void *c, hipStream_t st);
 void expand_gemv(int64_t npw, int nproj, const void *P, const void *c, void *out, hipStream_t st);
