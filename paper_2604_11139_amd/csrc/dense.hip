@@ -216,43 +216,54 @@ __global__ __launch_bounds__(256) void hemv_part_kernel(int64_t m, const double2
   part[ks * L + i] = s;
 }
 
-// p = tau sum_ks part; w = p - 0.5 tau (p^H u) u   (one workgroup)
-__global__ __launch_bounds__(256) void hemv_finish_kernel(int64_t m, int64_t j, const double2 *__restrict__ part, int ksn,
-                                   const double2 *__restrict__ tau, const double2 *__restrict__ u,
-                                   double2 *__restrict__ w) {
+// p = tau sum_ks part (many workgroups)
+__global__ __launch_bounds__(256) void hemv_reduce_kernel(int64_t m, int64_t j,
+                                                          const double2 *__restrict__ part, int ksn,
+                                                          const double2 *__restrict__ tau,
+                                                          double2 *__restrict__ p) {
+  const int64_t L = m - j - 1;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L) return;
+  double2 v{0, 0};
+  for (int ks = 0; ks < ksn; ++ks) v = cadd(v, part[(int64_t)ks * L + i]);
+  p[j + 1 + i] = cmul(tau[j], v);
+}
+
+// a2 = -0.5 tau (p^H u)   (one workgroup); w = p + a2 u is formed inside her2
+__global__ __launch_bounds__(256) void hemv_dot_kernel(int64_t m, int64_t j,
+                                                       const double2 *__restrict__ p,
+                                                       const double2 *__restrict__ tau,
+                                                       const double2 *__restrict__ u,
+                                                       double2 *__restrict__ a2) {
   __shared__ double scratch[16];
   const int64_t L = m - j - 1;
-  const double2 t = tau[j];
   double sr = 0, si = 0;
   for (int64_t i = threadIdx.x; i < L; i += blockDim.x) {
-    double2 p{0, 0};
-    for (int ks = 0; ks < ksn; ++ks) p = cadd(p, part[(int64_t)ks * L + i]);
-    p = cmul(t, p);
-    w[j + 1 + i] = p;
-    const double2 uv = u[j + 1 + i];
-    sr += p.x * uv.x + p.y * uv.y;  // conj(p) u
-    si += p.x * uv.y - p.y * uv.x;
+    const double2 pv = p[j + 1 + i], uv = u[j + 1 + i];
+    sr += pv.x * uv.x + pv.y * uv.y;  // conj(p) u
+    si += pv.x * uv.y - pv.y * uv.x;
   }
   sr = block_sum(sr, scratch);
   si = block_sum(si, scratch);
-  const double2 a2 = cscale(cmul(t, double2{sr, si}), -0.5);
-  __syncthreads();
-  for (int64_t i = threadIdx.x; i < L; i += blockDim.x)
-    w[j + 1 + i] = cadd(w[j + 1 + i], cmul(a2, u[j + 1 + i]));
+  if (threadIdx.x == 0) *a2 = cscale(cmul(tau[j], double2{sr, si}), -0.5);
 }
 
-// A22 -= u w^H + w u^H
-__global__ __launch_bounds__(256) void her2_kernel(int64_t m, double2 *__restrict__ A, int64_t lda, int64_t j,
-                            const double2 *__restrict__ u, const double2 *__restrict__ w) {
+// A22 -= u w^H + w u^H with w = p + a2 u
+__global__ __launch_bounds__(256) void her2_kernel(int64_t m, double2 *__restrict__ A, int64_t lda,
+                                                   int64_t j, const double2 *__restrict__ u,
+                                                   const double2 *__restrict__ p,
+                                                   const double2 *__restrict__ a2p) {
   const int64_t L = m - j - 1;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t k = blockIdx.y;
   if (i >= L || k >= L) return;
-  const double2 ui = u[j + 1 + i], wi = w[j + 1 + i];
-  const double2 uk = u[j + 1 + k], wk = w[j + 1 + k];
+  const double2 a2 = *a2p;
+  const double2 ui = u[j + 1 + i], uk = u[j + 1 + k];
+  const double2 wi = cadd(p[j + 1 + i], cmul(a2, ui));
+  const double2 wk = cadd(p[j + 1 + k], cmul(a2, uk));
   const double2 cwk{wk.x, -wk.y}, cuk{uk.x, -uk.y};
-  double2 *p = A + (j + 1 + i) + (j + 1 + k) * lda;
-  *p = csub(*p, cadd(cmul(ui, cwk), cmul(wi, cuk)));
+  double2 *q = A + (j + 1 + i) + (j + 1 + k) * lda;
+  *q = csub(*q, cadd(cmul(ui, cwk), cmul(wi, cuk)));
 }
 
 __global__ void last_diag_kernel(int64_t m, const double2 *__restrict__ A, int64_t lda,
@@ -614,9 +625,11 @@ void zheev(int64_t m, void *Av, int64_t lda, double *wout, void *Zv, int64_t ldz
     }
     hipLaunchKernelGGL(hemv_part_kernel, dim3((unsigned)rb, (unsigned)ks), dim3(256), 0, st, m, A,
                        lda, j, u, kchunk, part);
-    hipLaunchKernelGGL(hemv_finish_kernel, dim3(1), dim3(256), 0, st, m, j, part, ks, tau, u, wv);
+    hipLaunchKernelGGL(hemv_reduce_kernel, dim3((unsigned)rb), dim3(256), 0, st, m, j, part, ks,
+                       tau, wv);
+    hipLaunchKernelGGL(hemv_dot_kernel, dim3(1), dim3(256), 0, st, m, j, wv, tau, u, wrow);
     hipLaunchKernelGGL(her2_kernel, dim3((unsigned)rb, (unsigned)L), dim3(256), 0, st, m, A, lda, j,
-                       u, wv);
+                       u, wv, wrow);
   }
   CHEBFI_HIP(hipGetLastError());
   hipLaunchKernelGGL(last_diag_kernel, dim3(1), dim3(64), 0, st, m, A, lda, d);

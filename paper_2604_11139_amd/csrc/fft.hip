@@ -17,6 +17,8 @@
 // Each 1D transform is a Stockham autosort FFT with radix-2/3/4/5 stages
 // executed in place in LDS (every thread holds its butterflies' outputs in
 // registers across a barrier).  Twiddles are FP64 tables built on the host.
+#include <cstdlib>
+
 #include "cplx.h"
 #include "internal.h"
 #include "kernels.h"
@@ -78,6 +80,45 @@ template <typename T> struct Dft<T, 5> {
     x[4] = csub(a1, b1);
     x[2] = cadd(a2, b2);
     x[3] = csub(a2, b2);
+  }
+};
+
+template <typename T> struct Dft<T, 6> {
+  // even/odd split: two radix-3 DFTs combined with w6^k = e^{sgn i pi k/3}
+  static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
+    C2<T> e[3] = {x[0], x[2], x[4]}, o[3] = {x[1], x[3], x[5]};
+    Dft<T, 3>::run(e, sgn);
+    Dft<T, 3>::run(o, sgn);
+    const T h = (T)0.86602540378443864676;
+    const C2<T> w1{(T)0.5, (T)sgn * h}, w2{(T)-0.5, (T)sgn * h};
+    const C2<T> t1 = cmul(o[1], w1), t2 = cmul(o[2], w2);
+    x[0] = cadd(e[0], o[0]);
+    x[3] = csub(e[0], o[0]);
+    x[1] = cadd(e[1], t1);
+    x[4] = csub(e[1], t1);
+    x[2] = cadd(e[2], t2);
+    x[5] = csub(e[2], t2);
+  }
+};
+
+template <typename T> struct Dft<T, 8> {
+  // even/odd split: two radix-4 DFTs combined with w8^k = e^{sgn i pi k/4}
+  static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
+    C2<T> e[4] = {x[0], x[2], x[4], x[6]}, o[4] = {x[1], x[3], x[5], x[7]};
+    Dft<T, 4>::run(e, sgn);
+    Dft<T, 4>::run(o, sgn);
+    const T c = (T)0.70710678118654752440;
+    const C2<T> t1{c * (o[1].x - sgn * o[1].y), c * (o[1].y + sgn * o[1].x)};
+    const C2<T> t2 = cmul_i(o[2], sgn);
+    const C2<T> t3{c * (-o[3].x - sgn * o[3].y), c * (-o[3].y + sgn * o[3].x)};
+    x[0] = cadd(e[0], o[0]);
+    x[4] = csub(e[0], o[0]);
+    x[1] = cadd(e[1], t1);
+    x[5] = csub(e[1], t1);
+    x[2] = cadd(e[2], t2);
+    x[6] = csub(e[2], t2);
+    x[3] = cadd(e[3], t3);
+    x[7] = csub(e[3], t3);
   }
 };
 
@@ -268,6 +309,255 @@ __global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ b
   }
 }
 
+// ---- compile-time specialised passes for cubic boxes ------------------------
+// Same three passes as above with the box edge N, the radix sequence, the
+// pencil strides and the thread count known at compile time, so that all
+// index arithmetic reduces to constant multiplies and shifts.
+template <int N> struct CPlan;
+#define CHEBFI_CPLAN(N_, NS_, R0_, R1_, R2_)                              \
+  template <> struct CPlan<N_> {                                          \
+    static constexpr int ns = NS_;                                        \
+    static constexpr int r[3] = {R0_, R1_, R2_};                          \
+  };
+CHEBFI_CPLAN(12, 2, 4, 3, 1)
+CHEBFI_CPLAN(15, 2, 5, 3, 1)
+CHEBFI_CPLAN(16, 2, 4, 4, 1)
+CHEBFI_CPLAN(18, 2, 6, 3, 1)
+CHEBFI_CPLAN(20, 2, 5, 4, 1)
+CHEBFI_CPLAN(24, 2, 8, 3, 1)
+CHEBFI_CPLAN(25, 2, 5, 5, 1)
+CHEBFI_CPLAN(27, 3, 3, 3, 3)
+CHEBFI_CPLAN(30, 2, 6, 5, 1)
+CHEBFI_CPLAN(32, 2, 8, 4, 1)
+CHEBFI_CPLAN(36, 2, 6, 6, 1)
+CHEBFI_CPLAN(40, 2, 8, 5, 1)
+CHEBFI_CPLAN(45, 3, 5, 3, 3)
+CHEBFI_CPLAN(48, 2, 8, 6, 1)
+CHEBFI_CPLAN(64, 2, 8, 8, 1)
+#undef CHEBFI_CPLAN
+
+constexpr int kCT = 256;  // threads of the specialised passes
+
+template <typename T, int N, int R, int P, int NPEN, int ES, int PS, int SGN>
+__device__ __forceinline__ void cstage(C2<T> *buf, const C2<T> *tw) {
+  constexpr int NBF = N / R;
+  constexpr int TOTAL = NPEN * NBF;
+  constexpr int M = N / (P * R);
+  constexpr int MAXB = (TOTAL + kCT - 1) / kCT;
+  C2<T> y[MAXB][R];
+  int dst[MAXB];
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    const int i = threadIdx.x + c * kCT;
+    dst[c] = -1;
+    if (TOTAL % kCT == 0 || i < TOTAL) {
+      int pen, bf;
+      if (PS == 1) {
+        pen = i % NPEN;
+        bf = i / NPEN;
+      } else {
+        bf = i % NBF;
+        pen = i / NBF;
+      }
+      const int base = pen * PS;
+      C2<T> x[R];
+#pragma unroll
+      for (int t = 0; t < R; ++t) x[t] = buf[base + (bf + t * NBF) * ES];
+      const int k = bf % P;
+      if (P > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) {
+          C2<T> w = tw[t * k * M];
+          if (SGN > 0) w.y = -w.y;
+          x[t] = cmul(x[t], w);
+        }
+      }
+      Dft<T, R>::run(x, SGN);
+#pragma unroll
+      for (int t = 0; t < R; ++t) y[c][t] = x[t];
+      dst[c] = base + ((bf - k) * R + k) * ES;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    if (TOTAL % kCT == 0 || dst[c] >= 0) {
+#pragma unroll
+      for (int t = 0; t < R; ++t) buf[dst[c] + t * P * ES] = y[c][t];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int N, int S, int P, int NPEN, int ES, int PS, int SGN>
+__device__ __forceinline__ void cfft(C2<T> *buf, const C2<T> *tw) {
+  if constexpr (S < CPlan<N>::ns) {
+    constexpr int R = CPlan<N>::r[S];
+    cstage<T, N, R, P, NPEN, ES, PS, SGN>(buf, tw);
+    cfft<T, N, S + 1, P * R, NPEN, ES, PS, SGN>(buf, tw);
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(kCT) void cpass_a_kernel(const C2<T> *__restrict__ X, int64_t ldx,
+                                                      int band0, const int32_t *__restrict__ box_index,
+                                                      const int32_t *__restrict__ plane,
+                                                      const double2 *__restrict__ twg,
+                                                      C2<T> *__restrict__ box) {
+  constexpr int NXY = N * N;
+  __shared__ C2<T> buf[NXY];
+  __shared__ C2<T> tw[N];
+  const int i3 = blockIdx.x;
+  const int bl = blockIdx.y;
+  for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(twg[i]);
+  for (int i = threadIdx.x; i < NXY; i += kCT) buf[i] = C2<T>{0, 0};
+  __syncthreads();
+  const int s0 = plane[i3], s1 = plane[i3 + 1];
+  const C2<T> *xb = X + (int64_t)(band0 + bl) * ldx;
+  const int off = i3 * NXY;
+  for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) buf[box_index[idx] - off] = xb[idx];
+  __syncthreads();
+  cfft<T, N, 0, 1, N, 1, N, +1>(buf, tw);  // x: N pencils of stride-1 elements
+  cfft<T, N, 0, 1, N, N, 1, +1>(buf, tw);  // y
+  C2<T> *dst = box + (int64_t)bl * NXY * N + off;
+  for (int i = threadIdx.x; i < NXY; i += kCT) dst[i] = buf[i];
+}
+
+template <typename T, typename VT, int N>
+__global__ __launch_bounds__(kCT) void cpass_b_kernel(C2<T> *__restrict__ box,
+                                                      const VT *__restrict__ V,
+                                                      const double2 *__restrict__ twg) {
+  constexpr int NXZ = N * N;
+  __shared__ C2<T> buf[NXZ];
+  __shared__ C2<T> tw[N];
+  const int i2 = blockIdx.x;
+  const int bl = blockIdx.y;
+  for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(twg[2 * kMaxN + i]);
+  C2<T> *src = box + (int64_t)bl * N * N * N;
+  for (int i = threadIdx.x; i < NXZ; i += kCT) {
+    const int i1 = i % N, i3 = i / N;
+    buf[i] = src[i1 + N * (i2 + N * i3)];
+  }
+  __syncthreads();
+  cfft<T, N, 0, 1, N, N, 1, +1>(buf, tw);
+  for (int i = threadIdx.x; i < NXZ; i += kCT) {
+    const int i1 = i % N, i3 = i / N;
+    buf[i] = cscale(buf[i], (T)V[i1 + N * (i2 + N * i3)]);
+  }
+  __syncthreads();
+  cfft<T, N, 0, 1, N, N, 1, -1>(buf, tw);
+  for (int i = threadIdx.x; i < NXZ; i += kCT) {
+    const int i1 = i % N, i3 = i / N;
+    src[i1 + N * (i2 + N * i3)] = buf[i];
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(kCT) void cpass_c_kernel(
+    const C2<T> *__restrict__ box, const double2 *__restrict__ twg,
+    const int32_t *__restrict__ box_index, const int32_t *__restrict__ plane,
+    const double *__restrict__ kin, int band0, const C2<T> *__restrict__ Yk, int64_t ldk,
+    const C2<T> *__restrict__ Yprev, int64_t ldp, C2<T> *__restrict__ Out, int64_t ldo, T alpha,
+    T cshift, T beta, T scale) {
+  constexpr int NXY = N * N;
+  __shared__ C2<T> buf[NXY];
+  __shared__ C2<T> tw[N];
+  const int i3 = blockIdx.x;
+  const int bl = blockIdx.y;
+  for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(twg[i]);
+  const int off = i3 * NXY;
+  const C2<T> *src = box + (int64_t)bl * NXY * N + off;
+  for (int i = threadIdx.x; i < NXY; i += kCT) buf[i] = src[i];
+  __syncthreads();
+  cfft<T, N, 0, 1, N, N, 1, -1>(buf, tw);
+  cfft<T, N, 0, 1, N, 1, N, -1>(buf, tw);
+  const int s0 = plane[i3], s1 = plane[i3 + 1];
+  const int64_t b = band0 + bl;
+  const C2<T> *yk = Yk + b * ldk;
+  C2<T> *out = Out + b * ldo;
+  if (Yprev != nullptr) {
+    const C2<T> *yp = Yprev + b * ldp;
+    for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
+      const C2<T> loc = cscale(buf[box_index[idx] - off], scale);
+      const C2<T> x = yk[idx];
+      const T kd = (T)kin[idx] - cshift;
+      const C2<T> h = cadd(loc, cscale(x, kd));
+      const C2<T> p = yp[idx];
+      out[idx] = C2<T>{alpha * h.x - beta * p.x, alpha * h.y - beta * p.y};
+    }
+  } else {
+    for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
+      const C2<T> loc = cscale(buf[box_index[idx] - off], scale);
+      const C2<T> x = yk[idx];
+      const T kd = (T)kin[idx] - cshift;
+      out[idx] = cscale(cadd(loc, cscale(x, kd)), alpha);
+    }
+  }
+}
+
+template <typename T, int N>
+void launch_cubic(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Yprev,
+                  int64_t ldp, void *Out, int64_t ldo, int band0, int nb, void *box, const void *V,
+                  double alpha, double cshift, double beta, hipStream_t st, Profiler *prof,
+                  double bytesA, double bytesB, double bytesC) {
+  typedef C2<T> V2;
+  typedef typename std::conditional<std::is_same<T, double>::value, double, float>::type VT;
+  const double2 *tw = reinterpret_cast<const double2 *>(s->d_tw);
+  V2 *bx = reinterpret_cast<V2 *>(box);
+  int tok = prof ? prof->begin(PROF_FFT_A, bytesA, st) : -1;
+  hipLaunchKernelGGL((cpass_a_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st,
+                     reinterpret_cast<const V2 *>(Yk), ldk, band0, s->d_box, s->d_plane, tw, bx);
+  CHEBFI_HIP(hipGetLastError());
+  if (prof) prof->end(tok, st);
+  tok = prof ? prof->begin(PROF_FFT_B, bytesB, st) : -1;
+  hipLaunchKernelGGL((cpass_b_kernel<T, VT, N>), dim3(N, nb), dim3(kCT), 0, st, bx,
+                     reinterpret_cast<const VT *>(V), tw);
+  CHEBFI_HIP(hipGetLastError());
+  if (prof) prof->end(tok, st);
+  tok = prof ? prof->begin(PROF_FFT_C, bytesC, st) : -1;
+  const T scale = (T)(1.0 / ((double)N * N * N));
+  hipLaunchKernelGGL((cpass_c_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st, bx, tw, s->d_box,
+                     s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Yk), ldk,
+                     reinterpret_cast<const V2 *>(Yprev), ldp, reinterpret_cast<V2 *>(Out), ldo,
+                     (T)alpha, (T)cshift, (T)beta, scale);
+  CHEBFI_HIP(hipGetLastError());
+  if (prof) prof->end(tok, st);
+}
+
+template <typename T>
+bool try_cubic(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Yprev, int64_t ldp,
+               void *Out, int64_t ldo, int band0, int nb, void *box, const void *V, double alpha,
+               double cshift, double beta, hipStream_t st, Profiler *prof, double bA, double bB,
+               double bC) {
+  if (s->n1 != s->n2 || s->n1 != s->n3) return false;
+  if (std::getenv("CHEBFI_GENERIC_FFT")) return false;
+#define CHEBFI_CUBIC(N_)                                                                     \
+  case N_:                                                                                   \
+    launch_cubic<T, N_>(s, Yk, ldk, Yprev, ldp, Out, ldo, band0, nb, box, V, alpha, cshift,  \
+                        beta, st, prof, bA, bB, bC);                                         \
+    return true;
+  switch (s->n1) {
+    CHEBFI_CUBIC(12)
+    CHEBFI_CUBIC(15)
+    CHEBFI_CUBIC(16)
+    CHEBFI_CUBIC(18)
+    CHEBFI_CUBIC(20)
+    CHEBFI_CUBIC(24)
+    CHEBFI_CUBIC(25)
+    CHEBFI_CUBIC(27)
+    CHEBFI_CUBIC(30)
+    CHEBFI_CUBIC(32)
+    CHEBFI_CUBIC(36)
+    CHEBFI_CUBIC(40)
+    CHEBFI_CUBIC(45)
+    CHEBFI_CUBIC(48)
+    CHEBFI_CUBIC(64)
+    default:
+      return false;
+  }
+#undef CHEBFI_CUBIC
+}
+
 int stage_threads(const Plan1D &pl, int npen) {
   // smallest multiple of 64 threads with total butterflies <= kMaxB * threads
   int need = 64;
@@ -314,6 +604,9 @@ void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, 
   const double bytesA = nb * (np + nbx) * es;
   const double bytesB = nb * 2.0 * nbx * es + nbx * (double)sizeof(T);
   const double bytesC = nb * (nbx + np * (Yprev ? 3.0 : 2.0)) * es;
+  if (try_cubic<T>(s, Yk, ldk, Yprev, ldp, Out, ldo, band0, nb, box, V, alpha, cshift, beta, st,
+                   prof, bytesA, bytesB, bytesC))
+    return;
   int tok = prof ? prof->begin(PROF_FFT_A, bytesA, st) : -1;
   hipLaunchKernelGGL(pass_a_kernel<T>, dim3(n3, nb), dim3(tA), ldsA, st,
                      reinterpret_cast<const V2 *>(Yk), ldk, band0, s->d_box, s->d_plane, plan, tw,

@@ -39,6 +39,13 @@ SMALL = {
 
 @functools.lru_cache(maxsize=None)
 def system(name, vloc_scale=1.0, d_scale=1.0):
+    if name == "noncubic":
+        # 12 x 15 x 16 box: exercises the runtime-size FFT passes
+        s = W.make_system(105, a=7.0, ecut=4.0, n=16, natom=2, nband=11,
+                          kpt_red=(0.2, 0.1, 0.3), vloc_scale=vloc_scale, d_scale=d_scale)
+        s.ngrid = (12, 15, 16)
+        s.vloc = W.systems._gaussian_wells(s.tau, s.a, s.ngrid) * vloc_scale
+        return s
     kw = dict(SMALL[name])
     tag = kw.pop("tag")
     return W.make_system(tag, vloc_scale=vloc_scale, d_scale=d_scale, **kw)

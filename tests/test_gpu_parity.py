@@ -70,6 +70,19 @@ def test_apply_H_parts(parts):
         assert np.linalg.norm(got - H.kinetic_apply(X) - part) <= 1e-10 * np.linalg.norm(part)
 
 
+@pytest.mark.parametrize("name,generic", [("noncubic", False), ("n27", True), ("c1", True)])
+def test_apply_H_generic_fft(name, generic, monkeypatch):
+    """Runtime-size FFT passes: a non-cubic box, and cubic boxes forced onto them."""
+    if generic:
+        monkeypatch.setenv("CHEBFI_GENERIC_FFT", "1")
+    H = hamiltonian(name)
+    s = system(name)
+    X = W.random_block(H.npw, s.nband, 11)
+    with B.System(s) as g:
+        got = to_host(g.apply_H(to_dev(X)))
+    assert col_rel_err(got, H(X)) <= 1e-10
+
+
 def test_apply_H_config2_ragged():
     s = W.make_system(2)
     H = O.Hamiltonian.from_system(s)
