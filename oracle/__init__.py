@@ -35,3 +35,4 @@ from .subspace import (  # noqa: F401
     rayleigh_ritz,
     residual_norms,
 )
+from .adjoint import filter_backward, filter_coefficients, filter_iterates, filter_loss  # noqa: F401,E402
