@@ -156,6 +156,33 @@ abi_status abi_rayleigh_ritz(abi_system sys, void *Y, void *HPsi, int64_t nband,
                              int32_t dtype, double *eval, double *resnorm, int32_t *flags,
                              void *stream);
 
+/* Replaces V_loc (device, n1*n2*n3 doubles, i1 fastest) and/or D (device,
+ * natom*16 complex doubles, row-major per atom); a NULL pointer keeps the old
+ * table.  Stream-ordered; for differentiation and finite differences. */
+abi_status abi_update_potential(abi_system sys, const double *vloc, const void *dij,
+                                void *stream);
+
+/* Adjoint of abi_cheb_filter for the loss L = sum_n Re<W_n, Y_n>, Y = the
+ * filter output (reverse mode of the filter recurrence; the paper's solver is
+ * not differentiated, so this is the derivative of the operation
+ * abi_cheb_filter computes).  With gamma_0 = s_1/e, gamma_k = 2 s_{k+1}/e and
+ * delta_k = s_k s_{k+1}, the reverse recurrence A_m = W,
+ * A_k += gamma_k (H - c) A_{k+1}, A_{k-1} -= delta_k A_{k+1} gives
+ *   dX = A_0,
+ *   dV(r) = sum_k gamma_k sum_n Re[conj(A~_{k+1,n}(r)) Y~_{k,n}(r)] / (n1 n2 n3),
+ *   dD_R  = sum_k gamma_k (P_R^H A_{k+1}) (P_R^H Y_k)^H,
+ * where ~ is the unnormalised inverse FFT of a sphere vector.  Gradients use
+ * the convention dL/dRe + i dL/dIm (each D entry independent); the bounds are
+ * held fixed.  Iterates are recomputed from (Y_{s-1}, Y_s) checkpoints taken
+ * every ckpt_every steps (0 = one segment, all iterates kept).
+ * X, W: c128 npw x nband (ld).  Outputs (device, overwritten): dV (n1*n2*n3
+ * doubles), dD (natom*16 complex doubles; may be NULL when natom = 0), dX
+ * (npw x nband, ld) or NULL.  dtype must be ABI_C128. */
+abi_status abi_filter_backward(abi_system sys, const void *X, const void *W, int64_t nband,
+                               int64_t ld, int32_t dtype, int32_t degree, double a, double b,
+                               double a0, int32_t ckpt_every, double *dV, void *dD, void *dX,
+                               void *stream);
+
 /* ---- dense FP64 building blocks of the Rayleigh-Ritz step ---------------------
  * Column-major complex double matrices in device memory, leading dimension lda. */
 

@@ -35,7 +35,8 @@ EXPORTS = [
     "abi_gsphere_count", "abi_gsphere_build", "abi_set_system", "abi_system_info",
     "abi_get_gsphere", "abi_get_projectors", "abi_destroy", "abi_apply_H",
     "abi_spectral_bounds", "abi_cheb_filter", "abi_rayleigh_ritz", "abi_zpotrf_upper",
-    "abi_zheev", "abi_profile_enable", "abi_profile_read", "abi_last_error",
+    "abi_zheev", "abi_profile_enable", "abi_profile_read", "abi_update_potential",
+    "abi_filter_backward", "abi_last_error",
 ]
 
 PROFILE_CLASSES = ["proj_gemm", "expand_gemm", "fft_a", "fft_b", "fft_c", "dapply", "gram",
@@ -93,6 +94,9 @@ def lib():
         "abi_zpotrf_upper": [c_int64, vp, c_int64, vp],
         "abi_zheev": [c_int64, vp, c_int64, vp, vp, c_int64, vp],
         "abi_profile_enable": [vp, c_int32],
+        "abi_update_potential": [vp, vp, vp, vp],
+        "abi_filter_backward": [vp, vp, vp, c_int64, c_int64, c_int32, c_int32, c_double,
+                                c_double, c_double, c_int32, vp, vp, vp, vp],
         "abi_profile_read": [vp, c_int32, vp, vp, vp],
     }
     for name, args in sig.items():
@@ -262,6 +266,47 @@ class System:
                                          _stream()))
         return float(out[0]), float(out[1]), float(out[2])
 
+    def update_potential(self, vloc=None, dij=None):
+        """Replace V_loc (float64, n1*n2*n3, i1 fastest) and/or D (complex128 (natom,4,4))."""
+        import torch
+        pv = c_void_p(0)
+        pd = c_void_p(0)
+        keep = []
+        if vloc is not None:
+            v = vloc.detach().to(device="cuda", dtype=torch.float64).contiguous().reshape(-1)
+            if v.numel() != self.ngrid[0] * self.ngrid[1] * self.ngrid[2]:
+                raise ValueError("vloc has the wrong size")
+            keep.append(v)
+            pv = c_void_p(v.data_ptr())
+        if dij is not None:
+            d = dij.detach().to(device="cuda", dtype=torch.complex128).contiguous()
+            if d.numel() != 4 * self.nproj:
+                raise ValueError("dij has the wrong size")
+            keep.append(d)
+            pd = c_void_p(d.data_ptr())
+        _check(lib().abi_update_potential(self._h, pv, pd, _stream()))
+        torch.cuda.current_stream().synchronize()
+
+    def filter_backward(self, X, W, degree, a, b, a0, ckpt_every=4, want_dx=True):
+        """(dV, dD, dX) of L = sum_n Re<W_n, filter(X)_n> (dX None unless want_dx)."""
+        import torch
+        px, nb, ld, code = _block(X, self.npw)
+        self._out_like(X, W)
+        pw, _, _, _ = _block(W, self.npw)
+        n3 = self.ngrid[0] * self.ngrid[1] * self.ngrid[2]
+        dV = torch.empty(n3, dtype=torch.float64, device=X.device)
+        dD = torch.empty((max(self.nproj // 4, 1), 4, 4), dtype=torch.complex128, device=X.device)
+        dX = None
+        pdx = c_void_p(0)
+        if want_dx:
+            dX = self._out_like(X, None)
+            pdx = c_void_p(dX.data_ptr())
+        _check(lib().abi_filter_backward(self._h, px, pw, nb, ld, code, int(degree), float(a),
+                                         float(b), float(a0), int(ckpt_every),
+                                         c_void_p(dV.data_ptr()), c_void_p(dD.data_ptr()), pdx,
+                                         _stream()))
+        return dV, dD[: self.nproj // 4], dX
+
     def profile(self, on=True):
         _check(lib().abi_profile_enable(self._h, 1 if on else 0))
 
@@ -309,3 +354,46 @@ def zheev(A):
     _check(lib().abi_zheev(m, c_void_p(cm.data_ptr()), m, c_void_p(w.data_ptr()),
                            c_void_p(Z.data_ptr()), m, _stream()))
     return w, Z.t()
+
+
+def _make_autograd():
+    import torch
+
+    class ChebFilterFunction(torch.autograd.Function):
+        """Y = p(H[vloc, dij]) X with the library's adjoint as its backward.
+
+        Inputs X (complex128 (nband, npw)), vloc (float64, n1*n2*n3) and dij
+        (complex128 (natom, 4, 4)) are differentiable; the bounds are constants.
+        """
+
+        @staticmethod
+        def forward(ctx, X, vloc, dij, system, degree, a, b, a0, ckpt_every):
+            system.update_potential(vloc, dij)
+            Y = system.cheb_filter(X.detach(), degree, a, b, a0)
+            ctx.save_for_backward(X.detach(), vloc.detach(), dij.detach())
+            ctx.system = system
+            ctx.params = (degree, a, b, a0, ckpt_every)
+            return Y
+
+        @staticmethod
+        def backward(ctx, gY):
+            X, vloc, dij = ctx.saved_tensors
+            degree, a, b, a0, ckpt = ctx.params
+            ctx.system.update_potential(vloc, dij)
+            dV, dD, dX = ctx.system.filter_backward(X, gY.contiguous(), degree, a, b, a0, ckpt,
+                                                    want_dx=ctx.needs_input_grad[0])
+            return (dX, dV.reshape(vloc.shape), dD.reshape(dij.shape), None, None, None, None,
+                    None, None)
+
+    return ChebFilterFunction
+
+
+_autograd_fn = None
+
+
+def cheb_filter_autograd(X, vloc, dij, system, degree, a, b, a0, ckpt_every=4):
+    """Differentiable Chebyshev filter (torch.autograd.Function over the C ABI)."""
+    global _autograd_fn
+    if _autograd_fn is None:
+        _autograd_fn = _make_autograd()
+    return _autograd_fn.apply(X, vloc, dij, system, degree, a, b, a0, ckpt_every)

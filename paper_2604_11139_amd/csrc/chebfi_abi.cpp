@@ -632,6 +632,174 @@ abi_status abi_rayleigh_ritz(abi_system s, void *Y, void *HPsi, int64_t nband, i
   });
 }
 
+abi_status abi_update_potential(abi_system s, const double *vloc, const void *dij, void *stream) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(s != nullptr, ABI_ERR_ARG, "system handle is NULL");
+    hipStream_t st = S(stream);
+    const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
+    if (vloc) {
+      CHEBFI_HIP(hipMemcpyAsync(s->d_V, vloc, sizeof(double) * nbox, hipMemcpyDeviceToDevice, st));
+      if (s->d_Vf) launch_d2f(nbox, s->d_V, s->d_Vf, st);
+    }
+    if (dij && s->natom > 0)
+      CHEBFI_HIP(hipMemcpyAsync(s->d_D, dij, sizeof(double2) * 16 * (size_t)s->natom,
+                                hipMemcpyDeviceToDevice, st));
+  });
+}
+
+abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64_t nband,
+                               int64_t ld, int32_t dtype, int32_t degree, double a, double b,
+                               double a0, int32_t ckpt_every, double *dV, void *dD, void *dX,
+                               void *stream) {
+  return guarded([&] {
+    check_block(s, X, nband, ld, dtype);
+    CHEBFI_REQUIRE(dtype == ABI_C128, ABI_ERR_STATE, "the adjoint runs on complex128 blocks");
+    CHEBFI_REQUIRE(W != nullptr, ABI_ERR_ARG, "W is NULL");
+    CHEBFI_REQUIRE(dV != nullptr, ABI_ERR_ARG, "dV is NULL");
+    CHEBFI_REQUIRE(dD != nullptr || s->natom == 0, ABI_ERR_ARG, "dD is NULL");
+    CHEBFI_REQUIRE(degree >= 1, ABI_ERR_ARG, "degree must be >= 1");
+    CHEBFI_REQUIRE(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0), ABI_ERR_ARG,
+                   "bounds must be finite");
+    CHEBFI_REQUIRE(b > a, ABI_ERR_ARG, "need b > a");
+    CHEBFI_REQUIRE(a0 <= a, ABI_ERR_ARG, "need a0 <= a");
+    CHEBFI_REQUIRE(ckpt_every >= 0, ABI_ERR_ARG, "ckpt_every must be >= 0");
+    hipStream_t st = S(stream);
+    const int64_t npw = s->npw;
+    const int nproj = s->nproj, natom = s->natom;
+    const int m = degree;
+    // recurrence coefficients
+    const double e = (b - a) / 2.0, c = (b + a) / 2.0, s1 = e / (a0 - c);
+    std::vector<double> gam(m), del(m, 0.0);
+    {
+      double sk = s1;
+      gam[0] = s1 / e;
+      for (int k = 1; k < m; ++k) {
+        const double sk1 = 1.0 / (2.0 / s1 - sk);
+        gam[k] = 2.0 * sk1 / e;
+        del[k] = sk * sk1;
+        sk = sk1;
+      }
+    }
+    const int cseg = (ckpt_every > 0) ? std::min(ckpt_every, m) : m;
+    std::vector<int> starts;  // segment starts 0, cseg, 2 cseg, ... < m
+    for (int s0 = 0; s0 < m; s0 += cseg) starts.push_back(s0);
+    const int nck = (int)starts.size() - 1;  // checkpoint pairs (Y_{s-1}, Y_s), s > 0
+    const size_t blk = sizeof(double2) * (size_t)npw * nband;
+    const int nblocks = 2 * nck + cseg + 3;
+    char *base = (char *)s->adj.get(blk * (size_t)nblocks);
+    auto block = [&](int i) { return (double2 *)(base + blk * (size_t)i); };
+    auto ck_prev = [&](int j) { return block(2 * (j - 1)); };  // Y_{s_j - 1}
+    auto ck_cur = [&](int j) { return block(2 * (j - 1) + 1); };  // Y_{s_j}
+    double2 *seg0 = block(2 * nck);
+    auto seg = [&](int i) { return seg0 + (size_t)npw * nband * i; };
+    double2 *abuf[3] = {block(2 * nck + cseg), block(2 * nck + cseg + 1),
+                        block(2 * nck + cseg + 2)};
+    const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
+    // small accumulators: dV (nbox), dD (natom*16 complex), CA, CY (nproj*nband), C'
+    const size_t small_bytes = sizeof(double) * (size_t)nbox + sizeof(double2) * 16 * (size_t)natom +
+                               3 * sizeof(double2) * (size_t)std::max(nproj, 1) * nband + 1024;
+    char *sb = (char *)s->adjsmall.get(small_bytes);
+    double *dV_acc = (double *)sb;
+    double2 *dD_acc = (double2 *)(sb + ((sizeof(double) * nbox + 255) / 256 * 256));
+    double2 *CA = dD_acc + 16 * (size_t)natom;
+    double2 *CY = CA + (size_t)std::max(nproj, 1) * nband;
+    double2 *Cp = CY + (size_t)std::max(nproj, 1) * nband;
+    launch_fill_zero(nbox, dV_acc, st);
+    launch_fill_zero(32 * (int64_t)natom, (double *)dD_acc, st);
+
+    auto step_fwd = [&](int j, const void *ym1, int64_t ld1, const void *ym2, int64_t ld2,
+                        void *dst) {  // Y_j from Y_{j-1} (and Y_{j-2})
+      if (j == 1)
+        apply_core(s, ym1, ld1, nullptr, 0, dst, npw, nband, gam[0], c, 0.0, st);
+      else
+        apply_core(s, ym1, ld1, ym2, ld2, dst, npw, nband, gam[j - 1], c, del[j - 1], st);
+    };
+    // forward sweep: keep the checkpoint pairs
+    {
+      const int jmax = nck > 0 ? starts.back() : 0;
+      const void *p1 = X;  // Y_{j-1}
+      int64_t l1 = ld;
+      const void *p2 = nullptr;  // Y_{j-2}
+      int64_t l2 = npw;
+      for (int j = 1; j <= jmax; ++j) {
+        // slots that must receive Y_j (two when checkpoints are one step apart)
+        std::vector<void *> slots;
+        for (int q = 1; q <= nck; ++q) {
+          if (j == starts[q] - 1) slots.push_back(ck_prev(q));
+          if (j == starts[q]) slots.push_back(ck_cur(q));
+        }
+        void *dst = slots.empty() ? (void *)abuf[j % 3] : slots[0];
+        step_fwd(j, p1, l1, p2, l2, dst);
+        for (size_t t = 1; t < slots.size(); ++t)
+          launch_copy_block(npw, nband, dst, npw, slots[t], npw, st);
+        p2 = p1;
+        l2 = l1;
+        p1 = dst;
+        l1 = npw;
+      }
+    }
+    // reverse sweep, one segment at a time
+    const int fb = (int)std::min<int64_t>(s->fft_batch, nband);
+    void *box1 = s->box.get(sizeof(double2) * (size_t)nbox * fb);
+    void *box2 = s->box2.get(sizeof(double2) * (size_t)nbox * fb);
+    for (int q = (int)starts.size() - 1; q >= 0; --q) {
+      const int s0 = starts[q];
+      const int s1e = std::min(s0 + cseg, m);  // iterates Y_{s0} .. Y_{s1e-1}
+      const void *ys = (q == 0) ? X : (const void *)ck_cur(q);
+      const int64_t lys = (q == 0) ? ld : npw;
+      const void *ysm1 = (q == 0) ? nullptr : (const void *)ck_prev(q);
+      auto yk = [&](int k, int64_t *ldk) -> const void * {
+        if (k == s0) {
+          *ldk = lys;
+          return ys;
+        }
+        *ldk = npw;
+        return seg(k - s0);
+      };
+      for (int j = s0 + 1; j < s1e; ++j) {
+        int64_t l1, l2 = npw;
+        const void *p1 = yk(j - 1, &l1);
+        const void *p2 = nullptr;
+        if (j - 2 >= s0)
+          p2 = yk(j - 2, &l2);
+        else if (j >= 2)
+          p2 = ysm1;
+        step_fwd(j, p1, l1, p2, l2, seg(j - s0));
+      }
+      for (int k = s1e - 1; k >= s0; --k) {
+        int64_t ldy;
+        const void *Yk = yk(k, &ldy);
+        const void *Ak1 = (k + 1 == m) ? W : (const void *)abuf[(k + 1) % 3];
+        const int64_t lda1 = (k + 1 == m) ? ld : npw;
+        double2 *Ak = abuf[k % 3];
+        const bool acc = (k + 1 < m);
+        if (nproj > 0) {
+          const int splits = zgemm_splits(nproj, nband, npw);
+          void *part = s->cpart.get(sizeof(double2) * (size_t)splits * nproj * nband);
+          proj_gemm(nproj, nband, npw, s->d_P, Ak1, lda1, part, splits, st);
+          zsum_parts(nproj, nband, part, splits, CA, nproj, double2{1, 0}, double2{0, 0}, st);
+          proj_gemm(nproj, nband, npw, s->d_P, Yk, ldy, part, splits, st);
+          zsum_parts(nproj, nband, part, splits, CY, nproj, double2{1, 0}, double2{0, 0}, st);
+          launch_dd_accum(natom, nband, CA, CY, gam[k], dD_acc, st);
+          launch_dapply(natom, nband, CA, 1, s->d_D, gam[k], Cp, st);
+        }
+        for (int64_t b0 = 0; b0 < nband; b0 += fb) {
+          const int nb = (int)std::min<int64_t>(fb, nband - b0);
+          launch_adjoint_local<double>(s, Ak1, lda1, Yk, ldy, Ak, npw, acc, (int)b0, nb, box1, box2,
+                                       s->d_V, gam[k], c, dV_acc, st);
+        }
+        if (nproj > 0) expand_gemm(npw, nband, nproj, s->d_P, Cp, Ak, npw, st);
+        if (k >= 1) launch_scale_neg(npw, nband, Ak1, lda1, del[k], abuf[(k + 2) % 3], npw, st);
+      }
+    }
+    CHEBFI_HIP(hipMemcpyAsync(dV, dV_acc, sizeof(double) * nbox, hipMemcpyDeviceToDevice, st));
+    if (natom > 0)
+      CHEBFI_HIP(hipMemcpyAsync(dD, dD_acc, sizeof(double2) * 16 * (size_t)natom,
+                                hipMemcpyDeviceToDevice, st));
+    if (dX) launch_copy_block(npw, nband, abuf[0], npw, dX, ld, st);
+  });
+}
+
 abi_status abi_profile_enable(abi_system s, int32_t on) {
   return guarded([&] {
     CHEBFI_REQUIRE(s != nullptr, ABI_ERR_ARG, "system handle is NULL");

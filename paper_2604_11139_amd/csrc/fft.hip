@@ -309,6 +309,83 @@ __global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ b
   }
 }
 
+// ---- adjoint passes (runtime sizes) -----------------------------------------
+// z-inverse FFT only: the box then holds the band in real space.
+template <typename T>
+__global__ __launch_bounds__(512) void pass_b_inv_kernel(C2<T> *__restrict__ box, BoxPlan plan,
+                                                         const double2 *__restrict__ twg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
+  const int n1 = plan.d[0].n, n2 = plan.d[1].n, n3 = plan.d[2].n;
+  const int nxz = n1 * n3;
+  C2<T> *tw3 = buf + nxz;
+  const int i2 = blockIdx.x;
+  const int bl = blockIdx.y;
+  load_twiddles<T>(tw3, twg + 2 * kMaxN, n3);
+  C2<T> *src = box + (int64_t)bl * n1 * n2 * n3;
+  for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
+    const int i1 = i % n1, i3 = i / n1;
+    buf[i] = src[i1 + n1 * (i2 + n2 * i3)];
+  }
+  __syncthreads();
+  lds_fft<T>(buf, plan.d[2], n1, n1, 1, tw3, +1);
+  for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
+    const int i1 = i % n1, i3 = i / n1;
+    src[i1 + n1 * (i2 + n2 * i3)] = buf[i];
+  }
+}
+
+// Pass B of the adjoint H application: z-inverse of the adjoint band (box),
+// the pointwise product Re[conj(adjoint) * forward] written over the forward
+// band's real-space box (`fwd`, real part), then * V and the z-forward FFT.
+template <typename T>
+__global__ __launch_bounds__(512) void pass_b_adj_kernel(C2<T> *__restrict__ box,
+                                                         C2<T> *__restrict__ fwd,
+                                                         const T *__restrict__ V, BoxPlan plan,
+                                                         const double2 *__restrict__ twg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
+  const int n1 = plan.d[0].n, n2 = plan.d[1].n, n3 = plan.d[2].n;
+  const int nxz = n1 * n3;
+  C2<T> *tw3 = buf + nxz;
+  const int i2 = blockIdx.x;
+  const int bl = blockIdx.y;
+  load_twiddles<T>(tw3, twg + 2 * kMaxN, n3);
+  C2<T> *src = box + (int64_t)bl * n1 * n2 * n3;
+  C2<T> *fw = fwd + (int64_t)bl * n1 * n2 * n3;
+  for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
+    const int i1 = i % n1, i3 = i / n1;
+    buf[i] = src[i1 + n1 * (i2 + n2 * i3)];
+  }
+  __syncthreads();
+  lds_fft<T>(buf, plan.d[2], n1, n1, 1, tw3, +1);
+  for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
+    const int i1 = i % n1, i3 = i / n1;
+    const int64_t r = i1 + n1 * (i2 + n2 * i3);
+    const C2<T> a = buf[i], y = fw[r];
+    fw[r] = C2<T>{a.x * y.x + a.y * y.y, (T)0};
+    buf[i] = cscale(a, V[r]);
+  }
+  __syncthreads();
+  lds_fft<T>(buf, plan.d[2], n1, n1, 1, tw3, -1);
+  for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
+    const int i1 = i % n1, i3 = i / n1;
+    src[i1 + n1 * (i2 + n2 * i3)] = buf[i];
+  }
+}
+
+// dV[r] += scale * sum_b prod[b][r].x, bands summed in order.
+template <typename T>
+__global__ __launch_bounds__(256) void dv_reduce_kernel(int64_t nbox, int nb,
+                                                        const C2<T> *__restrict__ prod,
+                                                        double scale, double *__restrict__ dV) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nbox) return;
+  double acc = 0.0;
+  for (int b = 0; b < nb; ++b) acc += (double)prod[(int64_t)b * nbox + r].x;
+  dV[r] += scale * acc;
+}
+
 // ---- compile-time specialised passes for cubic boxes ------------------------
 // Same three passes as above with the box edge N, the radix sequence, the
 // pencil strides and the thread count known at compile time, so that all
@@ -631,6 +708,52 @@ void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, 
   CHEBFI_HIP(hipGetLastError());
   if (prof) prof->end(tok, st);
 }
+
+template <typename T>
+void launch_adjoint_local(const abi_system_s *s, const void *Ak1, int64_t lda1, const void *Yk,
+                          int64_t ldy, void *Ak, int64_t ldak, bool accumulate, int band0, int nb,
+                          void *box1, void *box2, const void *V, double gamma, double cshift,
+                          double *dV, hipStream_t st) {
+  using V2 = C2<T>;
+  const BoxPlan &plan = s->plan;
+  const int n1 = plan.d[0].n, n2 = plan.d[1].n, n3 = plan.d[2].n;
+  const double2 *tw = reinterpret_cast<const double2 *>(s->d_tw);
+  const int tA = std::max(stage_threads(plan.d[0], n2), stage_threads(plan.d[1], n1));
+  const int tB = stage_threads(plan.d[2], n1);
+  CHEBFI_REQUIRE(tA <= 512 && tB <= 512, ABI_ERR_GRID, "FFT plane too large for one workgroup");
+  const size_t ldsA = sizeof(V2) * (size_t)(n1 * n2 + n1 + n2);
+  const size_t ldsB = sizeof(V2) * (size_t)(n1 * n3 + n3);
+  set_lds(pass_a_kernel<T>, ldsA);
+  set_lds(pass_c_kernel<T>, ldsA);
+  set_lds(pass_b_inv_kernel<T>, ldsB);
+  set_lds(pass_b_adj_kernel<T>, ldsB);
+  V2 *b1 = reinterpret_cast<V2 *>(box1);
+  V2 *b2 = reinterpret_cast<V2 *>(box2);
+  hipLaunchKernelGGL(pass_a_kernel<T>, dim3(n3, nb), dim3(tA), ldsA, st,
+                     reinterpret_cast<const V2 *>(Ak1), lda1, band0, s->d_box, s->d_plane, plan, tw,
+                     b1);
+  hipLaunchKernelGGL(pass_a_kernel<T>, dim3(n3, nb), dim3(tA), ldsA, st,
+                     reinterpret_cast<const V2 *>(Yk), ldy, band0, s->d_box, s->d_plane, plan, tw,
+                     b2);
+  hipLaunchKernelGGL(pass_b_inv_kernel<T>, dim3(n2, nb), dim3(tB), ldsB, st, b2, plan, tw);
+  hipLaunchKernelGGL(pass_b_adj_kernel<T>, dim3(n2, nb), dim3(tB), ldsB, st, b1, b2,
+                     reinterpret_cast<const T *>(V), plan, tw);
+  const int64_t nbox = (int64_t)n1 * n2 * n3;
+  hipLaunchKernelGGL(dv_reduce_kernel<T>, dim3((unsigned)((nbox + 255) / 256)), dim3(256), 0, st,
+                     nbox, nb, (const V2 *)b2, gamma / (double)nbox, dV);
+  const T scale = (T)(1.0 / (double)nbox);
+  // Ak = gamma (local + (kin - c) Ak1) + Ak   (beta = -1 adds the previous content)
+  hipLaunchKernelGGL(pass_c_kernel<T>, dim3(n3, nb), dim3(tA), ldsA, st, b1, plan, tw, s->d_box,
+                     s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Ak1), lda1,
+                     accumulate ? reinterpret_cast<const V2 *>(Ak) : (const V2 *)nullptr, ldak,
+                     reinterpret_cast<V2 *>(Ak), ldak, (T)gamma, (T)cshift, (T)-1, scale);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+template void launch_adjoint_local<double>(const abi_system_s *, const void *, int64_t, const void *,
+                                           int64_t, void *, int64_t, bool, int, int, void *,
+                                           void *, const void *, double, double, double *,
+                                           hipStream_t);
 
 template void launch_local_potential<double>(const abi_system_s *, const void *, int64_t,
                                              const void *, int64_t, void *, int64_t, int, int,

@@ -23,6 +23,16 @@ void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, 
                             const void *V, double alpha, double cshift, double beta,
                             hipStream_t st, Profiler *prof = nullptr);
 
+// Local part of one reverse step of the filter adjoint for bands
+// [band0, band0+nb): dV += gamma/n^3 sum_b Re[conj(Ak1~) Yk~] and
+// Ak = gamma (V_loc Ak1 + (kin - cshift) Ak1) (+ Ak when accumulate).
+// box1/box2 hold nb boxes each.  Runtime-size passes (any grid).
+template <typename T>
+void launch_adjoint_local(const abi_system_s *s, const void *Ak1, int64_t lda1, const void *Yk,
+                          int64_t ldy, void *Ak, int64_t ldak, bool accumulate, int band0, int nb,
+                          void *box1, void *box2, const void *V, double gamma, double cshift,
+                          double *dV, hipStream_t st);
+
 // ---- gemm.hip ---------------------------------------------------------------
 // C = alpha op(A) op(B) + beta C, complex double, column-major.  When `part`
 // is non-null the K range is split in `splits` chunks and chunk z writes its
@@ -89,6 +99,15 @@ void launch_scale_inv(int64_t npw, const double *s, const void *x, void *y, hipS
 // out[1] = theta_max(T(alpha, beta[0..k-2])) + (add_last ? beta[k-1] : 0)
 void launch_tridiag_bound(int k, const double *alpha, const double *beta, int add_last,
                           double *out, hipStream_t st);
+
+// dD[R][i][j] += gamma sum_b CA[4R+i, b] conj(CY[4R+j, b])  (raw projections)
+void launch_dd_accum(int natom, int64_t nband, const void *CA, const void *CY, double gamma,
+                     void *dD, hipStream_t st);
+// out = -delta * in  (complex double blocks)
+void launch_scale_neg(int64_t npw, int64_t nband, const void *in, int64_t ldi, double delta,
+                      void *out, int64_t ldo, hipStream_t st);
+void launch_fill_zero(int64_t count_doubles, double *p, hipStream_t st);
+void launch_d2f(int64_t n, const double *src, float *dst, hipStream_t st);
 
 // resnorm[b] = || HPsi[:, b] - eval[b] Psi[:, b] ||
 void launch_residual_norms(int64_t npw, int64_t nband, const void *Psi, int64_t ldp,

@@ -272,9 +272,95 @@ __global__ void zero_lower_kernel(int64_t m, double2 *__restrict__ A, int64_t ld
   if (i > j) A[i + j * lda] = double2{0, 0};
 }
 
+// One workgroup per atom: 16 complex sums over the bands.
+__global__ __launch_bounds__(256) void dd_accum_kernel(int natom, int64_t nband,
+                                                       const double2 *__restrict__ CA,
+                                                       const double2 *__restrict__ CY, double gamma,
+                                                       double2 *__restrict__ dD) {
+  __shared__ double scratch[16];
+  const int R = blockIdx.x;
+  const int64_t np = 4 * (int64_t)natom;
+  double re[16], im[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) re[q] = im[q] = 0.0;
+  for (int64_t b = threadIdx.x; b < nband; b += blockDim.x) {
+    double2 a[4], y[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = CA[(4 * R + i) + b * np];
+      y[i] = CY[(4 * R + i) + b * np];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        // a_i conj(y_j)
+        re[4 * i + j] += a[i].x * y[j].x + a[i].y * y[j].y;
+        im[4 * i + j] += a[i].y * y[j].x - a[i].x * y[j].y;
+      }
+  }
+  for (int q = 0; q < 16; ++q) {
+    const double sr = block_sum(re[q], scratch);
+    const double si = block_sum(im[q], scratch);
+    if (threadIdx.x == 0) {
+      double2 d = dD[16 * R + q];
+      d.x += gamma * sr;
+      d.y += gamma * si;
+      dD[16 * R + q] = d;
+    }
+  }
+}
+
+__global__ void scale_neg_kernel(int64_t npw, int64_t nband, const double2 *__restrict__ in,
+                                 int64_t ldi, double delta, double2 *__restrict__ out,
+                                 int64_t ldo) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= npw * nband) return;
+  const int64_t i = idx % npw, b = idx / npw;
+  const double2 v = in[i + b * ldi];
+  out[i + b * ldo] = double2{-delta * v.x, -delta * v.y};
+}
+
+__global__ void fill_zero_kernel(int64_t n, double *__restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+__global__ void d2f_kernel(int64_t n, const double *__restrict__ s, float *__restrict__ d) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = (float)s[i];
+}
+
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
+
+void launch_dd_accum(int natom, int64_t nband, const void *CA, const void *CY, double gamma,
+                     void *dD, hipStream_t st) {
+  if (natom <= 0) return;
+  hipLaunchKernelGGL(dd_accum_kernel, dim3((unsigned)natom), dim3(256), 0, st, natom, nband,
+                     (const double2 *)CA, (const double2 *)CY, gamma, (double2 *)dD);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_scale_neg(int64_t npw, int64_t nband, const void *in, int64_t ldi, double delta,
+                      void *out, int64_t ldo, hipStream_t st) {
+  hipLaunchKernelGGL(scale_neg_kernel, dim3(nblk(npw * nband, 256)), dim3(256), 0, st, npw, nband,
+                     (const double2 *)in, ldi, delta, (double2 *)out, ldo);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_fill_zero(int64_t n, double *p, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, n, p);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_d2f(int64_t n, const double *src, float *dst, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(d2f_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, n, src, dst);
+  CHEBFI_HIP(hipGetLastError());
+}
 
 void launch_dapply(int natom, int64_t nband, const void *part, int splits, const void *D,
                    double alpha, void *Cprime, hipStream_t st, bool fp32) {
