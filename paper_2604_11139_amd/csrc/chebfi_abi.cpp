@@ -214,7 +214,12 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
     int tok = s->prof.begin(PROF_PROJ, flops, st);
     if (single)
       proj_gemv(npw, nproj, P, X, cpart, st);
-    else if (fp32 && s->mixed_gemm == 0)
+    else if (fp32 && s->mixed_gemm == 0) {
+      void *xpl = s->planes.get(8 * (size_t)s->ldPA * nband);
+      split_planes(npw, nband, X, ldx, xpl, s->ldPA, st);
+      proj_gemm_planes(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, xpl,
+                       s->ldPA, s->ldPA * nband, cpart, splits, st);
+    } else if (fp32 && s->mixed_gemm == 2)
       proj_gemm_bf16x3(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, X, ldx,
                        cpart, splits, st);
     else
@@ -222,6 +227,9 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
     s->prof.end(tok, st);
     tok = s->prof.begin(PROF_DAPPLY, (double)sizeof(V2) * nproj * nband * (splits + 1), st);
     launch_dapply(s->natom, nband, cpart, splits, s->d_D, alpha, cprime, st, fp32);
+    if (fp32 && s->mixed_gemm == 0)
+      split_planes(nproj, nband, cprime, nproj, s->cplanes.get(8 * (size_t)s->ldPB * nband),
+                   s->ldPB, st);
     s->prof.end(tok, st);
   }
   const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
@@ -239,6 +247,9 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
     if (single)
       expand_gemv(npw, nproj, P, cprime, Out, st);
     else if (fp32 && s->mixed_gemm == 0)
+      expand_gemm_planes(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB, s->cplanes.ptr,
+                         s->ldPB, s->ldPB * nband, Out, ldo, st);
+    else if (fp32 && s->mixed_gemm == 2)
       expand_gemm_bf16x3(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB, cprime, Out, ldo,
                          st);
     else
@@ -443,7 +454,9 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
         }
       s->d_PA = upload(PA.data(), PA.size());
       s->d_PB = upload(PB.data(), PB.size());
-      if (const char *e = std::getenv("CHEBFI_MIXED_GEMM")) s->mixed_gemm = (std::atoi(e) == 1);
+      // 0: split-BF16 planes x planes (default), 1: FP32 MFMA, 2: split-BF16 with the
+      // block split while staged
+      if (const char *e = std::getenv("CHEBFI_MIXED_GEMM")) s->mixed_gemm = std::atoi(e);
     }
     // bands per FFT batch: keep the box buffer near 128 MiB (env override)
     int64_t fb = (int64_t)((128ll << 20) / (sizeof(double2) * nbox));

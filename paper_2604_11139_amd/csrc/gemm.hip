@@ -462,6 +462,208 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(
       }
 }
 
+// Planes x planes form: both operands arrive as four bf16 planes with the
+// contraction index contiguous (A rows, B columns), so every global load is a
+// 16-byte vector and staging into LDS is a plain copy.  Tile BM x BN complex,
+// NWM x NWN waves, K step 32.  Two accumulators per 16x16 complex tile: the
+// sign of an imaginary plane is flipped in registers (bf16 sign bits), so
+//   op(A) = A^H: Re += Ar Br + Ai Bi,   Im += Ar Bi + (-Ai) Br
+//   op(A) = A  : Re += Ar Br + Ai (-Bi), Im += Ar Bi + Ai Br
+// each real product being hi*hi + hi*lo + lo*hi.  Workgroups are numbered so
+// that the tiles sharing an A panel run on the same XCD (consecutive
+// workgroup ids go to different XCDs).
+__device__ __forceinline__ v8bf bf16_neg(v8bf x) {
+  typedef unsigned v4u __attribute__((ext_vector_type(4)));
+  v4u u = __builtin_bit_cast(v4u, x);
+  u ^= v4u{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  return __builtin_bit_cast(v8bf, u);
+}
+
+template <int BM, int BN, int NWM, int NWN, bool CONJ, bool SPLIT>
+__global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl_kernel(
+    int64_t m, int64_t n, int64_t k, const u16 *__restrict__ Apl, int64_t lda, int64_t psa,
+    const u16 *__restrict__ Bpl, int64_t ldb, int64_t psb, float2 *__restrict__ C, int64_t ldc,
+    int64_t kchunk, float2 *__restrict__ part) {
+  constexpr int NT = 64 * NWM * NWN;
+  constexpr int SM = BM / NWM / 16, SN = BN / NWN / 16;
+  constexpr int CA = 16 * BM / NT, CB = 16 * BN / NT;  // 16-byte chunks per thread
+  __shared__ __align__(16) u16 As[4][BM][XBK + XPAD];
+  __shared__ __align__(16) u16 Bs[4][BN][XBK + XPAD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % NWM, wn = wave / NWM;
+  // XCD-aware order: within the leading groups of 8 row panels, the column
+  // tiles of one row panel get ids congruent mod 8 (same XCD); the remaining
+  // row panels (fewer than 8) are numbered plainly.  A bijection on the grid.
+  const unsigned ntn = gridDim.y, ntm = gridDim.x;
+  const unsigned wid = blockIdx.x + ntm * blockIdx.y;
+  const unsigned full = ntm & ~7u;
+  unsigned tm, tn;
+  if (wid < full * ntn) {
+    const unsigned xcd = wid & 7u, loc = wid >> 3;
+    tm = (loc / ntn) * 8u + xcd;
+    tn = loc % ntn;
+  } else {
+    const unsigned r = wid - full * ntn, rest = ntm - full;
+    tm = full + r % rest;
+    tn = r / rest;
+  }
+  const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = (kbeg + kchunk < k) ? kbeg + kchunk : k;
+
+  v4f acc[SM][SN][2];
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j) {
+      acc[i][j][0] = v4f{0, 0, 0, 0};
+      acc[i][j][1] = v4f{0, 0, 0, 0};
+    }
+
+  uint4 ra[CA], rb[CB];
+  auto load_chunk = [&](const u16 *base, int64_t ld, int64_t ps, int64_t lim, int idx,
+                        int64_t r0, int64_t k0) -> uint4 {
+    const int kc = idx & 3, rr = (idx >> 2), i = rr >> 2;
+    const int64_t gr = r0 + i, ks = k0 + 8 * kc;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (gr < lim && ks < kend) {
+      const u16 *src = base + (int64_t)(rr & 3) * ps + gr * ld + ks;
+      if (ks + 8 <= kend) {
+        v = *reinterpret_cast<const uint4 *>(src);
+      } else {
+        u16 t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int e = 0; e < 8 && ks + e < kend; ++e) t[e] = src[e];
+        v = make_uint4(t[0] | ((unsigned)t[1] << 16), t[2] | ((unsigned)t[3] << 16),
+                       t[4] | ((unsigned)t[5] << 16), t[6] | ((unsigned)t[7] << 16));
+      }
+    }
+    return v;
+  };
+  auto load_tiles = [&](int64_t k0) {
+#pragma unroll
+    for (int c = 0; c < CA; ++c) ra[c] = load_chunk(Apl, lda, psa, m, tid + NT * c, row0, k0);
+#pragma unroll
+    for (int c = 0; c < CB; ++c) rb[c] = load_chunk(Bpl, ldb, psb, n, tid + NT * c, col0, k0);
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int c = 0; c < CA; ++c) {
+      const int idx = tid + NT * c, kc = idx & 3, rr = idx >> 2;
+      *reinterpret_cast<uint4 *>(&As[rr & 3][rr >> 2][8 * kc]) = ra[c];
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int idx = tid + NT * c, kc = idx & 3, rr = idx >> 2;
+      *reinterpret_cast<uint4 *>(&Bs[rr & 3][rr >> 2][8 * kc]) = rb[c];
+    }
+  };
+
+  if (kbeg < kend) load_tiles(kbeg);
+  const int kb = 8 * (lane >> 4);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += XBK) {
+    store_tiles();
+    __syncthreads();
+    if (k0 + XBK < kend) load_tiles(k0 + XBK);
+    // planes: 0 Re hi, 1 Im hi, 2 Re lo, 3 Im lo; slot 4/5: negated Im hi/lo
+    v8bf a[SM][6], b[SN][6];
+#pragma unroll
+    for (int i = 0; i < SM; ++i) {
+      const int ii = wm * (BM / NWM) + i * 16 + (lane & 15);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) a[i][p] = *reinterpret_cast<const v8bf *>(&As[p][ii][kb]);
+      if (CONJ) {
+        a[i][4] = bf16_neg(a[i][1]);
+        a[i][5] = bf16_neg(a[i][3]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < SN; ++j) {
+      const int jj = wn * (BN / NWN) + j * 16 + (lane & 15);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) b[j][p] = *reinterpret_cast<const v8bf *>(&Bs[p][jj][kb]);
+      if (!CONJ) {
+        b[j][4] = bf16_neg(b[j][1]);
+        b[j][5] = bf16_neg(b[j][3]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+#pragma unroll
+      for (int j = 0; j < SN; ++j) {
+        v4f re = acc[i][j][0], im = acc[i][j][1];
+        // real part
+        re = mfma_bf16(a[i][0], b[j][0], re);
+        re = mfma_bf16(a[i][0], b[j][2], re);
+        re = mfma_bf16(a[i][2], b[j][0], re);
+        if (CONJ) {
+          re = mfma_bf16(a[i][1], b[j][1], re);
+          re = mfma_bf16(a[i][1], b[j][3], re);
+          re = mfma_bf16(a[i][3], b[j][1], re);
+        } else {
+          re = mfma_bf16(a[i][1], b[j][4], re);
+          re = mfma_bf16(a[i][1], b[j][5], re);
+          re = mfma_bf16(a[i][3], b[j][4], re);
+        }
+        // imaginary part
+        im = mfma_bf16(a[i][0], b[j][1], im);
+        im = mfma_bf16(a[i][0], b[j][3], im);
+        im = mfma_bf16(a[i][2], b[j][1], im);
+        if (CONJ) {
+          im = mfma_bf16(a[i][4], b[j][0], im);
+          im = mfma_bf16(a[i][4], b[j][2], im);
+          im = mfma_bf16(a[i][5], b[j][0], im);
+        } else {
+          im = mfma_bf16(a[i][1], b[j][0], im);
+          im = mfma_bf16(a[i][1], b[j][2], im);
+          im = mfma_bf16(a[i][3], b[j][0], im);
+        }
+        acc[i][j][0] = re;
+        acc[i][j][1] = im;
+      }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + wm * (BM / NWM) + i * 16 + 4 * (lane >> 4) + r;
+        const int64_t col = col0 + wn * (BN / NWN) + j * 16 + (lane & 15);
+        if (row < m && col < n) {
+          const float2 v{acc[i][j][0][r], acc[i][j][1][r]};
+          if (SPLIT) {
+            part[(int64_t)blockIdx.z * m * n + row + col * m] = v;
+          } else {
+            float2 o = C[row + col * ldc];
+            o.x += v.x;
+            o.y += v.y;
+            C[row + col * ldc] = o;
+          }
+        }
+      }
+}
+
+// complex float block (ld) -> four bf16 planes (Re hi, Im hi, Re lo, Im lo),
+// row-major per band with stride ldp.
+__global__ __launch_bounds__(256) void split_planes_kernel(int64_t rows, int64_t cols,
+                                                           const float2 *__restrict__ X, int64_t ld,
+                                                           u16 *__restrict__ pl, int64_t ldp,
+                                                           int64_t ps) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t i = idx % rows, j = idx / rows;
+  const float2 v = X[i + j * ld];
+  const u16 hr = bf16_rn(v.x), hi = bf16_rn(v.y);
+  const int64_t o = j * ldp + i;
+  pl[o] = hr;
+  pl[ps + o] = hi;
+  pl[2 * ps + o] = bf16_rn(v.x - bf16_val(hr));
+  pl[3 * ps + o] = bf16_rn(v.y - bf16_val(hi));
+}
+
 }  // namespace
 
 void proj_gemm_bf16x3(int64_t nproj, int64_t nband, int64_t npw, const void *Apl, int64_t lda,
@@ -473,6 +675,38 @@ void proj_gemm_bf16x3(int64_t nproj, int64_t nband, int64_t npw, const void *Apl
   hipLaunchKernelGGL((zgemm_bf16x3_kernel<true, true>), grid, dim3(256), 0, st, nproj, nband, npw,
                      (const u16 *)Apl, lda, pstride, (const float2 *)Y, ldy, (float2 *)nullptr,
                      (int64_t)0, chunk, (float2 *)part);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void split_planes(int64_t rows, int64_t cols, const void *X, int64_t ld, void *planes,
+                  int64_t ldp, hipStream_t st) {
+  const int64_t total = rows * cols;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(split_planes_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     rows, cols, (const float2 *)X, ld, (u16 *)planes, ldp, ldp * cols);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void proj_gemm_planes(int64_t nproj, int64_t nband, int64_t npw, const void *Apl, int64_t lda,
+                      int64_t psa, const void *Ypl, int64_t ldy, int64_t psy, void *part,
+                      int splits, hipStream_t st) {
+  constexpr int BM = 128, BN = 128;
+  const int64_t chunk = ((npw + splits - 1) / splits + XBK - 1) / XBK * XBK;
+  dim3 grid((unsigned)((nproj + BM - 1) / BM), (unsigned)((nband + BN - 1) / BN), (unsigned)splits);
+  hipLaunchKernelGGL((zgemm_pl_kernel<BM, BN, 2, 4, true, true>), grid, dim3(512), 0, st, nproj,
+                     nband, npw, (const u16 *)Apl, lda, psa, (const u16 *)Ypl, ldy, psy,
+                     (float2 *)nullptr, (int64_t)0, chunk, (float2 *)part);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void expand_gemm_planes(int64_t npw, int64_t nband, int64_t nproj, const void *Apl, int64_t lda,
+                        int64_t psa, const void *Cpl, int64_t ldc_pl, int64_t psc, void *Out,
+                        int64_t ldo, hipStream_t st) {
+  constexpr int BM = 128, BN = 128;
+  dim3 grid((unsigned)((npw + BM - 1) / BM), (unsigned)((nband + BN - 1) / BN), 1);
+  hipLaunchKernelGGL((zgemm_pl_kernel<BM, BN, 2, 4, false, false>), grid, dim3(512), 0, st, npw,
+                     nband, nproj, (const u16 *)Apl, lda, psa, (const u16 *)Cpl, ldc_pl, psc,
+                     (float2 *)Out, ldo, nproj, (float2 *)nullptr);
   CHEBFI_HIP(hipGetLastError());
 }
 

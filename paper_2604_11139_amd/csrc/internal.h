@@ -139,7 +139,7 @@ struct abi_system_s {
 
   // work buffers
   chebfi::DevBuf box, cpart, cprime, blk1, blk2, blk3, small1, small2, small3, small4, scal;
-  chebfi::DevBuf eig1, eig2, eig3, blk4, box2, adj, adjsmall;
+  chebfi::DevBuf eig1, eig2, eig3, blk4, box2, adj, adjsmall, planes, cplanes;
 
   int fft_batch = 0;  // bands per FFT batch (box buffer holds this many boxes)
   chebfi::Profiler prof;

@@ -57,6 +57,16 @@ void proj_gemm_bf16x3(int64_t nproj, int64_t nband, int64_t npw, const void *Apl
                       hipStream_t st);
 void expand_gemm_bf16x3(int64_t npw, int64_t nband, int64_t nproj, const void *Apl, int64_t lda,
                         int64_t pstride, const void *Cp, void *Out, int64_t ldo, hipStream_t st);
+// Planes x planes forms: the block operand is also given as bf16 planes
+// (column j = band j, contraction index contiguous, stride ld, plane stride ps).
+void split_planes(int64_t rows, int64_t cols, const void *X, int64_t ld, void *planes,
+                  int64_t ldp, hipStream_t st);
+void proj_gemm_planes(int64_t nproj, int64_t nband, int64_t npw, const void *Apl, int64_t lda,
+                      int64_t psa, const void *Ypl, int64_t ldy, int64_t psy, void *part,
+                      int splits, hipStream_t st);
+void expand_gemm_planes(int64_t npw, int64_t nband, int64_t nproj, const void *Apl, int64_t lda,
+                        int64_t psa, const void *Cpl, int64_t ldc_pl, int64_t psc, void *Out,
+                        int64_t ldo, hipStream_t st);
 // Single-band forms: c = P^H x, out += P c.
 void proj_gemv(int64_t npw, int nproj, const void *P, const void *x, void *c, hipStream_t st);
 void expand_gemv(int64_t npw, int nproj, const void *P, const void *c, void *out, hipStream_t st);
