@@ -149,12 +149,14 @@ abi_status abi_cheb_filter(abi_system sys, const void *X, void *Y, int64_t nband
  * Y (npw x nband, ld): in: filtered block; out: Ritz vectors Psi.
  * HPsi: optional output of the same dtype and ld, or NULL.
  * eval: host, nband doubles, ascending.  resnorm: host, nband doubles, or NULL.
+ * coef: device nband x nband complex doubles (ld nband) receiving C = U^-1 Z,
+ *   so that Psi = Y_in C (the coefficients of the Ritz vectors), or NULL.
  * flags: host int32 or NULL (bit 0 reserved for a mixed-precision fallback).
  * Fails with ABI_ERR_NOT_HPD if the Gram matrix is not positive definite.
  * Synchronises `stream`. */
 abi_status abi_rayleigh_ritz(abi_system sys, void *Y, void *HPsi, int64_t nband, int64_t ld,
-                             int32_t dtype, double *eval, double *resnorm, int32_t *flags,
-                             void *stream);
+                             int32_t dtype, double *eval, double *resnorm, void *coef,
+                             int32_t *flags, void *stream);
 
 /* Replaces V_loc (device, n1*n2*n3 doubles, i1 fastest) and/or D (device,
  * natom*16 complex doubles, row-major per atom); a NULL pointer keeps the old
@@ -182,6 +184,18 @@ abi_status abi_filter_backward(abi_system sys, const void *X, const void *W, int
                                int64_t ld, int32_t dtype, int32_t degree, double a, double b,
                                double a0, int32_t ckpt_every, double *dV, void *dD, void *dX,
                                void *stream);
+
+/* Density of a block on the FFT grid: rho(r) = sum_n w_n |psi~_n(r)|^2 / (n1 n2 n3),
+ * psi~ the unnormalised inverse FFT of the scattered sphere vector (so a unit
+ * band integrates to 1 over the grid points).  The SCF loop builds the density
+ * from the wave functions through FFTs (Algorithm "SCF", density step); with
+ * unit weights on the lowest p Ritz vectors this is the Hellmann-Feynman
+ * derivative of their eigenvalue sum with respect to V_loc(r).
+ * Psi: npw x nband (ld), dtype as for abi_apply_H.  weights: device, nband
+ * doubles, or NULL for unit weights.  rho: device, n1*n2*n3 doubles,
+ * overwritten (FP64 accumulation in a fixed band order). */
+abi_status abi_density(abi_system sys, const void *Psi, int64_t nband, int64_t ld, int32_t dtype,
+                       const double *weights, double *rho, void *stream);
 
 /* ---- dense FP64 building blocks of the Rayleigh-Ritz step ---------------------
  * Column-major complex double matrices in device memory, leading dimension lda. */

@@ -20,7 +20,7 @@ primitives (FFT, dense eigensolver, Cholesky) are used as single steps, never
 blocked, fused or reordered.
 """
 from .sphere import GSphere, gsphere, reciprocal_vectors  # noqa: F401
-from .hamiltonian import Hamiltonian  # noqa: F401
+from .hamiltonian import Hamiltonian, density  # noqa: F401
 from .chebyshev import (  # noqa: F401
     cheb_filter,
     cheb_sigmas,

@@ -142,3 +142,26 @@ class Hamiltonian:
         H[np.diag_indices(self.npw)] += self.sphere.kinetic
         H += self.P @ self.d_blockdiag() @ self.P.conj().T
         return H
+
+
+def density(H: Hamiltonian, Psi, weights=None) -> np.ndarray:
+    """rho(r) = sum_n w_n |psi~_n(r)|^2 / n^3 on the grid (i1 fastest).
+
+    psi~ is the unnormalised inverse FFT of the scattered sphere vector, so a
+    unit-norm band contributes sum_r |psi~(r)|^2 / n^3 = 1 (Parseval).  This is
+    the density the SCF loop builds from the wave functions through FFTs
+    (paper: Algorithm "SCF", density step); with w_n = 1 for the lowest p
+    bands it is the Hellmann-Feynman derivative of their eigenvalue sum with
+    respect to V_loc(r).
+    """
+    Psi = np.asarray(Psi, dtype=np.complex128).reshape(H.npw, -1)
+    w = np.ones(Psi.shape[1]) if weights is None else np.asarray(weights, dtype=np.float64)
+    n1, n2, n3 = H.ngrid
+    ntot = n1 * n2 * n3
+    rho = np.zeros(ntot)
+    for c0 in range(0, Psi.shape[1], _CHUNK):
+        c1 = min(Psi.shape[1], c0 + _CHUNK)
+        box = H.to_box(Psi[:, c0:c1])
+        real = scipy.fft.ifftn(box, axes=(0, 1, 2), norm="forward", workers=_WORKERS)
+        rho += (np.abs(real) ** 2 * w[c0:c1]).sum(axis=3).reshape(-1) / ntot
+    return rho

@@ -36,7 +36,7 @@ EXPORTS = [
     "abi_get_gsphere", "abi_get_projectors", "abi_destroy", "abi_apply_H",
     "abi_spectral_bounds", "abi_cheb_filter", "abi_rayleigh_ritz", "abi_zpotrf_upper",
     "abi_zheev", "abi_profile_enable", "abi_profile_read", "abi_update_potential",
-    "abi_filter_backward", "abi_last_error",
+    "abi_filter_backward", "abi_density", "abi_last_error",
 ]
 
 PROFILE_CLASSES = ["proj_gemm", "expand_gemm", "fft_a", "fft_b", "fft_c", "dapply", "gram",
@@ -90,11 +90,12 @@ def lib():
         "abi_spectral_bounds": [vp, vp, c_int64, c_int64, c_int32, vp, c_int32, vp, vp],
         "abi_cheb_filter": [vp, vp, vp, c_int64, c_int64, c_int32, c_int32, c_double, c_double,
                             c_double, vp],
-        "abi_rayleigh_ritz": [vp, vp, vp, c_int64, c_int64, c_int32, vp, vp, vp, vp],
+        "abi_rayleigh_ritz": [vp, vp, vp, c_int64, c_int64, c_int32, vp, vp, vp, vp, vp],
         "abi_zpotrf_upper": [c_int64, vp, c_int64, vp],
         "abi_zheev": [c_int64, vp, c_int64, vp, vp, c_int64, vp],
         "abi_profile_enable": [vp, c_int32],
         "abi_update_potential": [vp, vp, vp, vp],
+        "abi_density": [vp, vp, c_int64, c_int64, c_int32, vp, vp, vp],
         "abi_filter_backward": [vp, vp, vp, c_int64, c_int64, c_int32, c_int32, c_double,
                                 c_double, c_double, c_int32, vp, vp, vp, vp],
         "abi_profile_read": [vp, c_int32, vp, vp, vp],
@@ -307,6 +308,23 @@ class System:
                                          _stream()))
         return dV, dD[: self.nproj // 4], dX
 
+    def density(self, Psi, weights=None):
+        """rho(r) = sum_n w_n |psi~_n(r)|^2 / n^3 (float64, n1*n2*n3, i1 fastest)."""
+        import torch
+        pp, nb, ld, code = _block(Psi, self.npw)
+        rho = torch.empty(self.ngrid[0] * self.ngrid[1] * self.ngrid[2], dtype=torch.float64,
+                          device=Psi.device)
+        pw = c_void_p(0)
+        w = None
+        if weights is not None:
+            w = torch.as_tensor(weights, dtype=torch.float64, device=Psi.device).contiguous()
+            if w.numel() != nb:
+                raise ValueError("weights must have nband entries")
+            pw = c_void_p(w.data_ptr())
+        _check(lib().abi_density(self._h, pp, nb, ld, code, pw, c_void_p(rho.data_ptr()),
+                                 _stream()))
+        return rho
+
     def profile(self, on=True):
         _check(lib().abi_profile_enable(self._h, 1 if on else 0))
 
@@ -320,8 +338,10 @@ class System:
                                       wk.ctypes.data_as(c_void_p), ct.ctypes.data_as(c_void_p)))
         return {c: (float(ms[i]), float(wk[i]), int(ct[i])) for i, c in enumerate(PROFILE_CLASSES)}
 
-    def rayleigh_ritz(self, Y, hpsi=None):
-        """In place: Y <- Ritz vectors.  Returns (eval, resnorm, flags)."""
+    def rayleigh_ritz(self, Y, hpsi=None, want_coef=False):
+        """In place: Y <- Ritz vectors.  Returns (eval, resnorm, flags) and, with
+        want_coef, the coefficient matrix C (torch (nband, nband), Psi = Y_in C)."""
+        import torch
         py, nb, ld, code = _block(Y, self.npw)
         ph = c_void_p(0)
         if hpsi is not None:
@@ -330,8 +350,16 @@ class System:
         ev = np.zeros(nb, dtype=np.float64)
         rn = np.zeros(nb, dtype=np.float64)
         fl = c_int32(0)
+        coef = None
+        pc = c_void_p(0)
+        if want_coef:
+            coef = torch.empty((nb, nb), dtype=torch.complex128, device=Y.device)
+            pc = c_void_p(coef.data_ptr())
         _check(lib().abi_rayleigh_ritz(self._h, py, ph, nb, ld, code, ev.ctypes.data_as(c_void_p),
-                                       rn.ctypes.data_as(c_void_p), ctypes.byref(fl), _stream()))
+                                       rn.ctypes.data_as(c_void_p), pc, ctypes.byref(fl),
+                                       _stream()))
+        if want_coef:
+            return ev, rn, fl.value, coef.t()  # stored column-major
         return ev, rn, fl.value
 
 

@@ -205,8 +205,11 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
   int splits = 1;
   V2 *cpart = nullptr, *cprime = nullptr;
   const bool single = (nband == 1) && !fp32;
+  const bool planes = fp32 && s->mixed_gemm == 0;
   if (nproj > 0) {
-    splits = single ? 1 : zgemm_splits(nproj, nband, npw);
+    splits = single ? 1
+             : planes ? proj_planes_splits(s->pl_proj, nproj, nband, npw)
+                      : zgemm_splits(nproj, nband, npw);
     cpart = (V2 *)s->cpart.get(sizeof(V2) * (size_t)splits * nproj * nband);
     cprime = (V2 *)s->cprime.get(sizeof(V2) * (size_t)nproj * nband);
     // C = P^H X (split along the plane waves), C' = alpha D C
@@ -218,7 +221,7 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
       void *xpl = s->planes.get(8 * (size_t)s->ldPA * nband);
       split_planes(npw, nband, X, ldx, xpl, s->ldPA, st);
       proj_gemm_planes(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, xpl,
-                       s->ldPA, s->ldPA * nband, cpart, splits, st);
+                       s->ldPA, s->ldPA * nband, cpart, splits, st, s->pl_proj);
     } else if (fp32 && s->mixed_gemm == 2)
       proj_gemm_bf16x3(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, X, ldx,
                        cpart, splits, st);
@@ -248,7 +251,7 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
       expand_gemv(npw, nproj, P, cprime, Out, st);
     else if (fp32 && s->mixed_gemm == 0)
       expand_gemm_planes(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB, s->cplanes.ptr,
-                         s->ldPB, s->ldPB * nband, Out, ldo, st);
+                         s->ldPB, s->ldPB * nband, Out, ldo, st, s->pl_expand);
     else if (fp32 && s->mixed_gemm == 2)
       expand_gemm_bf16x3(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB, cprime, Out, ldo,
                          st);
@@ -269,7 +272,7 @@ void apply_core(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, 
 
 // FP64 Rayleigh-Ritz on a complex128 block Y (in: filtered block, out: Psi).
 void rr_core(abi_system_s *s, double2 *Y, int64_t ld, double2 *HPsi, int64_t ldh_in, int64_t M,
-             double *eval, double *resnorm, hipStream_t st) {
+             double *eval, double *resnorm, void *coef, hipStream_t st) {
   const int64_t npw = s->npw;
   const size_t mm = sizeof(double2) * (size_t)M * M;
   double2 *G = (double2 *)s->small1.get(mm);
@@ -337,6 +340,7 @@ void rr_core(abi_system_s *s, double2 *Y, int64_t ld, double2 *HPsi, int64_t ldh
   }
   zgemm(OP_N, OP_N, npw, M, M, HY, npw, T, M, HP, ldh, double2{1, 0}, double2{0, 0}, st);
   s->prof.end(tok, st);
+  if (coef) launch_copy_block(M, M, T, M, coef, M, st);
   launch_copy_block(npw, M, Psi, npw, Y, ld, st);
   launch_residual_norms(npw, M, Y, ld, HP, ldh, w_dev, r_dev, st);
   CHEBFI_HIP(hipMemcpyAsync(eval, w_dev, sizeof(double) * M, hipMemcpyDeviceToHost, st));
@@ -457,6 +461,9 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
       // 0: split-BF16 planes x planes (default), 1: FP32 MFMA, 2: split-BF16 with the
       // block split while staged
       if (const char *e = std::getenv("CHEBFI_MIXED_GEMM")) s->mixed_gemm = std::atoi(e);
+      // tile variants of the split-BF16 products (tuning knobs, 0..3)
+      if (const char *e = std::getenv("CHEBFI_PL_PROJ")) s->pl_proj = std::atoi(e) & 3;
+      if (const char *e = std::getenv("CHEBFI_PL_EXPAND")) s->pl_expand = std::atoi(e) & 3;
     }
     // bands per FFT batch: keep the box buffer near 128 MiB (env override)
     int64_t fb = (int64_t)((128ll << 20) / (sizeof(double2) * nbox));
@@ -621,8 +628,8 @@ abi_status abi_spectral_bounds(abi_system s, const void *X, int64_t nband, int64
 }
 
 abi_status abi_rayleigh_ritz(abi_system s, void *Y, void *HPsi, int64_t nband, int64_t ld,
-                             int32_t dtype, double *eval, double *resnorm, int32_t *flags,
-                             void *stream) {
+                             int32_t dtype, double *eval, double *resnorm, void *coef,
+                             int32_t *flags, void *stream) {
   return guarded([&] {
     check_block(s, Y, nband, ld, dtype);
     CHEBFI_REQUIRE(eval != nullptr, ABI_ERR_ARG, "eval is NULL");
@@ -630,13 +637,13 @@ abi_status abi_rayleigh_ritz(abi_system s, void *Y, void *HPsi, int64_t nband, i
     hipStream_t st = S(stream);
     const int64_t npw = s->npw, M = nband;
     if (dtype == ABI_C128) {
-      rr_core(s, (double2 *)Y, ld, (double2 *)HPsi, ld, M, eval, resnorm, st);
+      rr_core(s, (double2 *)Y, ld, (double2 *)HPsi, ld, M, eval, resnorm, coef, st);
     } else {
       // promote the complex64 block, run the FP64 Rayleigh-Ritz, round back
       double2 *Y2 = (double2 *)s->blk4.get(sizeof(double2) * (size_t)npw * M);
       double2 *H2 = (double2 *)s->blk3.get(sizeof(double2) * (size_t)npw * M);
       launch_c64_to_c128(npw, M, Y, ld, Y2, npw, st);
-      rr_core(s, Y2, npw, H2, npw, M, eval, resnorm, st);
+      rr_core(s, Y2, npw, H2, npw, M, eval, resnorm, coef, st);
       launch_c128_to_c64(npw, M, Y2, npw, Y, ld, st);
       if (HPsi) launch_c128_to_c64(npw, M, H2, npw, HPsi, ld, st);
       CHEBFI_HIP(hipStreamSynchronize(st));
@@ -810,6 +817,27 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
       CHEBFI_HIP(hipMemcpyAsync(dD, dD_acc, sizeof(double2) * 16 * (size_t)natom,
                                 hipMemcpyDeviceToDevice, st));
     if (dX) launch_copy_block(npw, nband, abuf[0], npw, dX, ld, st);
+  });
+}
+
+abi_status abi_density(abi_system s, const void *Psi, int64_t nband, int64_t ld, int32_t dtype,
+                       const double *weights, double *rho, void *stream) {
+  return guarded([&] {
+    check_block(s, Psi, nband, ld, dtype);
+    CHEBFI_REQUIRE(rho != nullptr, ABI_ERR_ARG, "rho is NULL");
+    hipStream_t st = S(stream);
+    const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
+    launch_fill_zero(nbox, rho, st);
+    const size_t es = elem_bytes(dtype);
+    const int fb = (int)std::min<int64_t>(s->fft_batch * (dtype == ABI_C64 ? 2 : 1), nband);
+    void *box = s->box.get(es * (size_t)nbox * fb);
+    for (int64_t b0 = 0; b0 < nband; b0 += fb) {
+      const int nb = (int)std::min<int64_t>(fb, nband - b0);
+      if (dtype == ABI_C64)
+        launch_density<float>(s, Psi, ld, (int)b0, nb, box, weights, rho, st);
+      else
+        launch_density<double>(s, Psi, ld, (int)b0, nb, box, weights, rho, st);
+    }
   });
 }
 

@@ -386,6 +386,23 @@ __global__ __launch_bounds__(256) void dv_reduce_kernel(int64_t nbox, int nb,
   dV[r] += scale * acc;
 }
 
+// rho[r] += sum_b w[band0 + b] |box_b(r)|^2 * scale, bands summed in order.
+template <typename T>
+__global__ __launch_bounds__(256) void rho_accum_kernel(int64_t nbox, int nb, int band0,
+                                                        const C2<T> *__restrict__ box,
+                                                        const double *__restrict__ w,
+                                                        double scale, double *__restrict__ rho) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nbox) return;
+  double acc = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    const C2<T> v = box[(int64_t)b * nbox + r];
+    const double wb = w ? w[band0 + b] : 1.0;
+    acc += wb * ((double)v.x * v.x + (double)v.y * v.y);
+  }
+  rho[r] += scale * acc;
+}
+
 // ---- compile-time specialised passes for cubic boxes ------------------------
 // Same three passes as above with the box edge N, the radix sequence, the
 // pencil strides and the thread count known at compile time, so that all
@@ -749,6 +766,36 @@ void launch_adjoint_local(const abi_system_s *s, const void *Ak1, int64_t lda1, 
                      reinterpret_cast<V2 *>(Ak), ldak, (T)gamma, (T)cshift, (T)-1, scale);
   CHEBFI_HIP(hipGetLastError());
 }
+
+template <typename T>
+void launch_density(const abi_system_s *s, const void *Psi, int64_t ld, int band0, int nb,
+                    void *box, const double *w, double *rho, hipStream_t st) {
+  using V2 = C2<T>;
+  const BoxPlan &plan = s->plan;
+  const int n1 = plan.d[0].n, n2 = plan.d[1].n, n3 = plan.d[2].n;
+  const double2 *tw = reinterpret_cast<const double2 *>(s->d_tw);
+  const int tA = std::max(stage_threads(plan.d[0], n2), stage_threads(plan.d[1], n1));
+  const int tB = stage_threads(plan.d[2], n1);
+  CHEBFI_REQUIRE(tA <= 512 && tB <= 512, ABI_ERR_GRID, "FFT plane too large for one workgroup");
+  const size_t ldsA = sizeof(V2) * (size_t)(n1 * n2 + n1 + n2);
+  const size_t ldsB = sizeof(V2) * (size_t)(n1 * n3 + n3);
+  set_lds(pass_a_kernel<T>, ldsA);
+  set_lds(pass_b_inv_kernel<T>, ldsB);
+  V2 *bx = reinterpret_cast<V2 *>(box);
+  hipLaunchKernelGGL(pass_a_kernel<T>, dim3(n3, nb), dim3(tA), ldsA, st,
+                     reinterpret_cast<const V2 *>(Psi), ld, band0, s->d_box, s->d_plane, plan, tw,
+                     bx);
+  hipLaunchKernelGGL(pass_b_inv_kernel<T>, dim3(n2, nb), dim3(tB), ldsB, st, bx, plan, tw);
+  const int64_t nbox = (int64_t)n1 * n2 * n3;
+  hipLaunchKernelGGL(rho_accum_kernel<T>, dim3((unsigned)((nbox + 255) / 256)), dim3(256), 0, st,
+                     nbox, nb, band0, (const V2 *)bx, w, 1.0 / (double)nbox, rho);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+template void launch_density<double>(const abi_system_s *, const void *, int64_t, int, int, void *,
+                                     const double *, double *, hipStream_t);
+template void launch_density<float>(const abi_system_s *, const void *, int64_t, int, int, void *,
+                                    const double *, double *, hipStream_t);
 
 template void launch_adjoint_local<double>(const abi_system_s *, const void *, int64_t, const void *,
                                            int64_t, void *, int64_t, bool, int, int, void *,

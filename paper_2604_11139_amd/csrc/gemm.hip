@@ -141,15 +141,15 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int64_t m, int64_t n, int64_
       for (int si = 0; si < 2; ++si)
 #pragma unroll
         for (int sj = 0; sj < 2; ++sj) {
-          acc_re[si][sj] = Mma<T>::run(ar[si], br[sj], acc_re[si][sj]);
-          acc_im[si][sj] = Mma<T>::run(ar[si], bi[sj], acc_im[si][sj]);
+          acc_re[si][sj] = Mma<T>::run(br[sj], ar[si], acc_re[si][sj]);
+          acc_im[si][sj] = Mma<T>::run(bi[sj], ar[si], acc_im[si][sj]);
         }
 #pragma unroll
       for (int si = 0; si < 2; ++si)
 #pragma unroll
         for (int sj = 0; sj < 2; ++sj) {
-          acc_re[si][sj] = Mma<T>::run(-ai[si], bi[sj], acc_re[si][sj]);
-          acc_im[si][sj] = Mma<T>::run(ai[si], br[sj], acc_im[si][sj]);
+          acc_re[si][sj] = Mma<T>::run(bi[sj], -ai[si], acc_re[si][sj]);
+          acc_im[si][sj] = Mma<T>::run(br[sj], ai[si], acc_im[si][sj]);
         }
     }
     __syncthreads();
@@ -162,8 +162,9 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int64_t m, int64_t n, int64_
     for (int sj = 0; sj < 2; ++sj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = row0 + wm * 32 + si * 16 + Mma<T>::row(lane, r);
-        const int64_t col = col0 + wn * 32 + sj * 16 + (lane & 15);
+        // transposed tile (B operand first): 16 lanes hold 16 consecutive rows
+        const int64_t row = row0 + wm * 32 + si * 16 + (lane & 15);
+        const int64_t col = col0 + wn * 32 + sj * 16 + Mma<T>::row(lane, r);
         if (row < m && col < n) {
           const V2 v{acc_re[si][sj][r], acc_im[si][sj][r]};
           if (SPLIT) {
@@ -593,30 +594,30 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl_kernel(
       for (int j = 0; j < SN; ++j) {
         v4f re = acc[i][j][0], im = acc[i][j][1];
         // real part
-        re = mfma_bf16(a[i][0], b[j][0], re);
-        re = mfma_bf16(a[i][0], b[j][2], re);
-        re = mfma_bf16(a[i][2], b[j][0], re);
+        re = mfma_bf16(b[j][0], a[i][0], re);
+        re = mfma_bf16(b[j][2], a[i][0], re);
+        re = mfma_bf16(b[j][0], a[i][2], re);
         if (CONJ) {
-          re = mfma_bf16(a[i][1], b[j][1], re);
-          re = mfma_bf16(a[i][1], b[j][3], re);
-          re = mfma_bf16(a[i][3], b[j][1], re);
+          re = mfma_bf16(b[j][1], a[i][1], re);
+          re = mfma_bf16(b[j][3], a[i][1], re);
+          re = mfma_bf16(b[j][1], a[i][3], re);
         } else {
-          re = mfma_bf16(a[i][1], b[j][4], re);
-          re = mfma_bf16(a[i][1], b[j][5], re);
-          re = mfma_bf16(a[i][3], b[j][4], re);
+          re = mfma_bf16(b[j][4], a[i][1], re);
+          re = mfma_bf16(b[j][5], a[i][1], re);
+          re = mfma_bf16(b[j][4], a[i][3], re);
         }
         // imaginary part
-        im = mfma_bf16(a[i][0], b[j][1], im);
-        im = mfma_bf16(a[i][0], b[j][3], im);
-        im = mfma_bf16(a[i][2], b[j][1], im);
+        im = mfma_bf16(b[j][1], a[i][0], im);
+        im = mfma_bf16(b[j][3], a[i][0], im);
+        im = mfma_bf16(b[j][1], a[i][2], im);
         if (CONJ) {
-          im = mfma_bf16(a[i][4], b[j][0], im);
-          im = mfma_bf16(a[i][4], b[j][2], im);
-          im = mfma_bf16(a[i][5], b[j][0], im);
+          im = mfma_bf16(b[j][0], a[i][4], im);
+          im = mfma_bf16(b[j][2], a[i][4], im);
+          im = mfma_bf16(b[j][0], a[i][5], im);
         } else {
-          im = mfma_bf16(a[i][1], b[j][0], im);
-          im = mfma_bf16(a[i][1], b[j][2], im);
-          im = mfma_bf16(a[i][3], b[j][0], im);
+          im = mfma_bf16(b[j][0], a[i][1], im);
+          im = mfma_bf16(b[j][2], a[i][1], im);
+          im = mfma_bf16(b[j][0], a[i][3], im);
         }
         acc[i][j][0] = re;
         acc[i][j][1] = im;
@@ -630,8 +631,10 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl_kernel(
     for (int j = 0; j < SN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = row0 + wm * (BM / NWM) + i * 16 + 4 * (lane >> 4) + r;
-        const int64_t col = col0 + wn * (BN / NWN) + j * 16 + (lane & 15);
+        // the MFMA computed the transposed tile (B operand first): lane & 15
+        // indexes rows, so 16 lanes store 16 consecutive rows of a column
+        const int64_t row = row0 + wm * (BM / NWM) + i * 16 + (lane & 15);
+        const int64_t col = col0 + wn * (BN / NWN) + j * 16 + 4 * (lane >> 4) + r;
         if (row < m && col < n) {
           const float2 v{acc[i][j][0][r], acc[i][j][1][r]};
           if (SPLIT) {
@@ -687,27 +690,58 @@ void split_planes(int64_t rows, int64_t cols, const void *X, int64_t ld, void *p
   CHEBFI_HIP(hipGetLastError());
 }
 
+// Tile variants of the planes x planes kernel: {BM, BN, NWM, NWN}.
+//   0: 128 x 128, 2 x 4 waves (64 x 32 per wave)
+//   1: 128 x 128, 2 x 2 waves (64 x 64 per wave)
+//   2:  64 x  64, 2 x 2 waves (32 x 32 per wave)
+//   3:  64 x 128, 1 x 4 waves (64 x 32 per wave)
+template <bool CONJ, bool SPLIT>
+static void launch_pl(int variant, dim3 grid_mn_z, int64_t m, int64_t n, int64_t k,
+                      const void *Apl, int64_t lda, int64_t psa, const void *Bpl, int64_t ldb,
+                      int64_t psb, void *C, int64_t ldc, int64_t chunk, void *part,
+                      hipStream_t st) {
+  auto go = [&](auto kern, int bm, int bn, int nt) {
+    dim3 grid((unsigned)((m + bm - 1) / bm), (unsigned)((n + bn - 1) / bn), grid_mn_z.z);
+    hipLaunchKernelGGL(kern, grid, dim3(nt), 0, st, m, n, k, (const u16 *)Apl, lda, psa,
+                       (const u16 *)Bpl, ldb, psb, (float2 *)C, ldc, chunk, (float2 *)part);
+  };
+  switch (variant) {
+    case 1: go(zgemm_pl_kernel<128, 128, 2, 2, CONJ, SPLIT>, 128, 128, 256); break;
+    case 2: go(zgemm_pl_kernel<64, 64, 2, 2, CONJ, SPLIT>, 64, 64, 256); break;
+    case 3: go(zgemm_pl_kernel<64, 128, 1, 4, CONJ, SPLIT>, 64, 128, 256); break;
+    default: go(zgemm_pl_kernel<128, 128, 2, 4, CONJ, SPLIT>, 128, 128, 512); break;
+  }
+  CHEBFI_HIP(hipGetLastError());
+}
+
+static int pl_bm(int variant) { return (variant == 2 || variant == 3) ? 64 : 128; }
+static int pl_bn(int variant) { return variant == 2 ? 64 : 128; }
+
+int proj_planes_splits(int variant, int64_t nproj, int64_t nband, int64_t npw) {
+  // about four workgroups per CU, at least 1024 plane waves per chunk
+  const int64_t tiles = ((nproj + pl_bm(variant) - 1) / pl_bm(variant)) *
+                        ((nband + pl_bn(variant) - 1) / pl_bn(variant));
+  int64_t sp = (1024 + tiles - 1) / tiles;
+  const int64_t kmax = (npw + 1023) / 1024;
+  if (sp > kmax) sp = kmax;
+  if (sp > 64) sp = 64;
+  if (sp < 1) sp = 1;
+  return (int)sp;
+}
+
 void proj_gemm_planes(int64_t nproj, int64_t nband, int64_t npw, const void *Apl, int64_t lda,
                       int64_t psa, const void *Ypl, int64_t ldy, int64_t psy, void *part,
-                      int splits, hipStream_t st) {
-  constexpr int BM = 128, BN = 128;
+                      int splits, hipStream_t st, int variant) {
   const int64_t chunk = ((npw + splits - 1) / splits + XBK - 1) / XBK * XBK;
-  dim3 grid((unsigned)((nproj + BM - 1) / BM), (unsigned)((nband + BN - 1) / BN), (unsigned)splits);
-  hipLaunchKernelGGL((zgemm_pl_kernel<BM, BN, 2, 4, true, true>), grid, dim3(512), 0, st, nproj,
-                     nband, npw, (const u16 *)Apl, lda, psa, (const u16 *)Ypl, ldy, psy,
-                     (float2 *)nullptr, (int64_t)0, chunk, (float2 *)part);
-  CHEBFI_HIP(hipGetLastError());
+  launch_pl<true, true>(variant, dim3(1, 1, (unsigned)splits), nproj, nband, npw, Apl, lda, psa,
+                        Ypl, ldy, psy, nullptr, 0, chunk, part, st);
 }
 
 void expand_gemm_planes(int64_t npw, int64_t nband, int64_t nproj, const void *Apl, int64_t lda,
                         int64_t psa, const void *Cpl, int64_t ldc_pl, int64_t psc, void *Out,
-                        int64_t ldo, hipStream_t st) {
-  constexpr int BM = 128, BN = 128;
-  dim3 grid((unsigned)((npw + BM - 1) / BM), (unsigned)((nband + BN - 1) / BN), 1);
-  hipLaunchKernelGGL((zgemm_pl_kernel<BM, BN, 2, 4, false, false>), grid, dim3(512), 0, st, npw,
-                     nband, nproj, (const u16 *)Apl, lda, psa, (const u16 *)Cpl, ldc_pl, psc,
-                     (float2 *)Out, ldo, nproj, (float2 *)nullptr);
-  CHEBFI_HIP(hipGetLastError());
+                        int64_t ldo, hipStream_t st, int variant) {
+  launch_pl<false, false>(variant, dim3(1, 1, 1), npw, nband, nproj, Apl, lda, psa, Cpl, ldc_pl,
+                          psc, Out, ldo, nproj, nullptr, st);
 }
 
 void expand_gemm_bf16x3(int64_t npw, int64_t nband, int64_t nproj, const void *Apl, int64_t lda,

@@ -136,6 +136,7 @@ struct abi_system_s {
   uint16_t *d_PB = nullptr;        // rows = plane waves, k = projectors (stride ldPB)
   int64_t ldPA = 0, ldPB = 0;
   int mixed_gemm = 0;              // 0: split-BF16 MFMA, 1: FP32 MFMA projector products
+  int pl_proj = 0, pl_expand = 0;  // tile variants of the split-BF16 products
 
   // work buffers
   chebfi::DevBuf box, cpart, cprime, blk1, blk2, blk3, small1, small2, small3, small4, scal;

@@ -33,6 +33,12 @@ void launch_adjoint_local(const abi_system_s *s, const void *Ak1, int64_t lda1, 
                           void *box1, void *box2, const void *V, double gamma, double cshift,
                           double *dV, hipStream_t st);
 
+// rho += sum_b w[band0+b] |psi~_b(r)|^2 / (n1 n2 n3) for bands [band0, band0+nb)
+// (w may be null: unit weights).  box holds nb boxes.
+template <typename T>
+void launch_density(const abi_system_s *s, const void *Psi, int64_t ld, int band0, int nb,
+                    void *box, const double *w, double *rho, hipStream_t st);
+
 // ---- gemm.hip ---------------------------------------------------------------
 // C = alpha op(A) op(B) + beta C, complex double, column-major.  When `part`
 // is non-null the K range is split in `splits` chunks and chunk z writes its
@@ -61,12 +67,15 @@ void expand_gemm_bf16x3(int64_t npw, int64_t nband, int64_t nproj, const void *A
 // (column j = band j, contraction index contiguous, stride ld, plane stride ps).
 void split_planes(int64_t rows, int64_t cols, const void *X, int64_t ld, void *planes,
                   int64_t ldp, hipStream_t st);
+// `variant` selects the tile shape (0..3, see gemm.hip); proj_planes_splits
+// gives the K split count that fills the chip for that shape.
+int proj_planes_splits(int variant, int64_t nproj, int64_t nband, int64_t npw);
 void proj_gemm_planes(int64_t nproj, int64_t nband, int64_t npw, const void *Apl, int64_t lda,
                       int64_t psa, const void *Ypl, int64_t ldy, int64_t psy, void *part,
-                      int splits, hipStream_t st);
+                      int splits, hipStream_t st, int variant);
 void expand_gemm_planes(int64_t npw, int64_t nband, int64_t nproj, const void *Apl, int64_t lda,
                         int64_t psa, const void *Cpl, int64_t ldc_pl, int64_t psc, void *Out,
-                        int64_t ldo, hipStream_t st);
+                        int64_t ldo, hipStream_t st, int variant);
 // Single-band forms: c = P^H x, out += P c.
 void proj_gemv(int64_t npw, int nproj, const void *P, const void *x, void *c, hipStream_t st);
 void expand_gemv(int64_t npw, int nproj, const void *P, const void *c, void *out, hipStream_t st);
