@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3])
     ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"],
                     help="both: time the mixed form (value) and the FP64 form beside it")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (counter calibration)")
     ap.add_argument("--cpu-bands", type=int, default=160,
                     help="bands in the oracle's timed sample (0 skips the CPU baseline)")
     return ap.parse_args()
@@ -185,6 +187,15 @@ def main():
     from paper_2604_11139_amd import binding as B
 
     torch.cuda.set_device(0)
+    if args.copy_mib > 0:
+        # a plain device copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # calibrate the per-dispatch traffic of the path's kernels
+        n = args.copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     s = W.make_system(args.config)
     degree = s.degree
     t_setup = time.perf_counter()

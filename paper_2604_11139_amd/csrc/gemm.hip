@@ -649,6 +649,180 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl_kernel(
       }
 }
 
+// Double-buffered form of the planes x planes kernel: two LDS stages of
+// 32-element K slices without padding; the 16-byte chunk kc of row i is
+// stored at chunk position kc ^ ((i >> 2) & 3), which keeps the 16-lane
+// ds_read_b128 groups on distinct banks.  One barrier per K step: the next
+// slice is written into the other stage while this one is multiplied.
+template <int BM, int BN, int NWM, int NWN, bool CONJ, bool SPLIT>
+__global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl2_kernel(
+    int64_t m, int64_t n, int64_t k, const u16 *__restrict__ Apl, int64_t lda, int64_t psa,
+    const u16 *__restrict__ Bpl, int64_t ldb, int64_t psb, float2 *__restrict__ C, int64_t ldc,
+    int64_t kchunk, float2 *__restrict__ part) {
+  constexpr int NT = 64 * NWM * NWN;
+  constexpr int SM = BM / NWM / 16, SN = BN / NWN / 16;
+  constexpr int CA = 16 * BM / NT, CB = 16 * BN / NT;
+  __shared__ __align__(16) u16 As[2][4][BM][XBK];
+  __shared__ __align__(16) u16 Bs[2][4][BN][XBK];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % NWM, wn = wave / NWM;
+  const unsigned ntn = gridDim.y, ntm = gridDim.x;
+  const unsigned wid = blockIdx.x + ntm * blockIdx.y;
+  const unsigned full = ntm & ~7u;
+  unsigned tm, tn;
+  if (wid < full * ntn) {
+    const unsigned xcd = wid & 7u, loc = wid >> 3;
+    tm = (loc / ntn) * 8u + xcd;
+    tn = loc % ntn;
+  } else {
+    const unsigned r = wid - full * ntn, rest = ntm - full;
+    tm = full + r % rest;
+    tn = r / rest;
+  }
+  const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = (kbeg + kchunk < k) ? kbeg + kchunk : k;
+
+  v4f acc[SM][SN][2];
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j) {
+      acc[i][j][0] = v4f{0, 0, 0, 0};
+      acc[i][j][1] = v4f{0, 0, 0, 0};
+    }
+
+  uint4 ra[CA], rb[CB];
+  auto load_chunk = [&](const u16 *base, int64_t ld, int64_t ps, int64_t lim, int idx,
+                        int64_t r0, int64_t k0) -> uint4 {
+    const int kc = idx & 3, rr = (idx >> 2), i = rr >> 2;
+    const int64_t gr = r0 + i, ks = k0 + 8 * kc;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (gr < lim && ks < kend) {
+      const u16 *src = base + (int64_t)(rr & 3) * ps + gr * ld + ks;
+      if (ks + 8 <= kend) {
+        v = *reinterpret_cast<const uint4 *>(src);
+      } else {
+        u16 t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int e = 0; e < 8 && ks + e < kend; ++e) t[e] = src[e];
+        v = make_uint4(t[0] | ((unsigned)t[1] << 16), t[2] | ((unsigned)t[3] << 16),
+                       t[4] | ((unsigned)t[5] << 16), t[6] | ((unsigned)t[7] << 16));
+      }
+    }
+    return v;
+  };
+  auto load_tiles = [&](int64_t k0) {
+#pragma unroll
+    for (int c = 0; c < CA; ++c) ra[c] = load_chunk(Apl, lda, psa, m, tid + NT * c, row0, k0);
+#pragma unroll
+    for (int c = 0; c < CB; ++c) rb[c] = load_chunk(Bpl, ldb, psb, n, tid + NT * c, col0, k0);
+  };
+  auto store_tiles = [&](int st) {
+#pragma unroll
+    for (int c = 0; c < CA; ++c) {
+      const int idx = tid + NT * c, kc = idx & 3, rr = idx >> 2, i = rr >> 2;
+      *reinterpret_cast<uint4 *>(&As[st][rr & 3][i][8 * (kc ^ ((i >> 2) & 3))]) = ra[c];
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int idx = tid + NT * c, kc = idx & 3, rr = idx >> 2, i = rr >> 2;
+      *reinterpret_cast<uint4 *>(&Bs[st][rr & 3][i][8 * (kc ^ ((i >> 2) & 3))]) = rb[c];
+    }
+  };
+
+  int cur = 0;
+  if (kbeg < kend) {
+    load_tiles(kbeg);
+    store_tiles(0);
+  }
+  __syncthreads();
+  const int kq = lane >> 4;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += XBK) {
+    const bool more = k0 + XBK < kend;
+    if (more) load_tiles(k0 + XBK);
+    v8bf a[SM][6], b[SN][6];
+#pragma unroll
+    for (int i = 0; i < SM; ++i) {
+      const int ii = wm * (BM / NWM) + i * 16 + (lane & 15);
+      const int kb = 8 * (kq ^ ((ii >> 2) & 3));
+#pragma unroll
+      for (int p = 0; p < 4; ++p) a[i][p] = *reinterpret_cast<const v8bf *>(&As[cur][p][ii][kb]);
+      if (CONJ) {
+        a[i][4] = bf16_neg(a[i][1]);
+        a[i][5] = bf16_neg(a[i][3]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < SN; ++j) {
+      const int jj = wn * (BN / NWN) + j * 16 + (lane & 15);
+      const int kb = 8 * (kq ^ ((jj >> 2) & 3));
+#pragma unroll
+      for (int p = 0; p < 4; ++p) b[j][p] = *reinterpret_cast<const v8bf *>(&Bs[cur][p][jj][kb]);
+      if (!CONJ) {
+        b[j][4] = bf16_neg(b[j][1]);
+        b[j][5] = bf16_neg(b[j][3]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+#pragma unroll
+      for (int j = 0; j < SN; ++j) {
+        v4f re = acc[i][j][0], im = acc[i][j][1];
+        re = mfma_bf16(b[j][0], a[i][0], re);
+        re = mfma_bf16(b[j][2], a[i][0], re);
+        re = mfma_bf16(b[j][0], a[i][2], re);
+        if (CONJ) {
+          re = mfma_bf16(b[j][1], a[i][1], re);
+          re = mfma_bf16(b[j][3], a[i][1], re);
+          re = mfma_bf16(b[j][1], a[i][3], re);
+        } else {
+          re = mfma_bf16(b[j][4], a[i][1], re);
+          re = mfma_bf16(b[j][5], a[i][1], re);
+          re = mfma_bf16(b[j][4], a[i][3], re);
+        }
+        im = mfma_bf16(b[j][1], a[i][0], im);
+        im = mfma_bf16(b[j][3], a[i][0], im);
+        im = mfma_bf16(b[j][1], a[i][2], im);
+        if (CONJ) {
+          im = mfma_bf16(b[j][0], a[i][4], im);
+          im = mfma_bf16(b[j][2], a[i][4], im);
+          im = mfma_bf16(b[j][0], a[i][5], im);
+        } else {
+          im = mfma_bf16(b[j][0], a[i][1], im);
+          im = mfma_bf16(b[j][2], a[i][1], im);
+          im = mfma_bf16(b[j][0], a[i][3], im);
+        }
+        acc[i][j][0] = re;
+        acc[i][j][1] = im;
+      }
+    if (more) store_tiles(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + wm * (BM / NWM) + i * 16 + (lane & 15);
+        const int64_t col = col0 + wn * (BN / NWN) + j * 16 + 4 * (lane >> 4) + r;
+        if (row < m && col < n) {
+          const float2 v{acc[i][j][0][r], acc[i][j][1][r]};
+          if (SPLIT) {
+            part[(int64_t)blockIdx.z * m * n + row + col * m] = v;
+          } else {
+            float2 o = C[row + col * ldc];
+            o.x += v.x;
+            o.y += v.y;
+            C[row + col * ldc] = o;
+          }
+        }
+      }
+}
+
 // complex float block (ld) -> four bf16 planes (Re hi, Im hi, Re lo, Im lo),
 // row-major per band with stride ldp.
 __global__ __launch_bounds__(256) void split_planes_kernel(int64_t rows, int64_t cols,
@@ -695,6 +869,7 @@ void split_planes(int64_t rows, int64_t cols, const void *X, int64_t ld, void *p
 //   1: 128 x 128, 2 x 2 waves (64 x 64 per wave)
 //   2:  64 x  64, 2 x 2 waves (32 x 32 per wave)
 //   3:  64 x 128, 1 x 4 waves (64 x 32 per wave)
+//   4: 128 x 128, 2 x 4 waves, double-buffered LDS (default)
 template <bool CONJ, bool SPLIT>
 static void launch_pl(int variant, dim3 grid_mn_z, int64_t m, int64_t n, int64_t k,
                       const void *Apl, int64_t lda, int64_t psa, const void *Bpl, int64_t ldb,
@@ -709,6 +884,7 @@ static void launch_pl(int variant, dim3 grid_mn_z, int64_t m, int64_t n, int64_t
     case 1: go(zgemm_pl_kernel<128, 128, 2, 2, CONJ, SPLIT>, 128, 128, 256); break;
     case 2: go(zgemm_pl_kernel<64, 64, 2, 2, CONJ, SPLIT>, 64, 64, 256); break;
     case 3: go(zgemm_pl_kernel<64, 128, 1, 4, CONJ, SPLIT>, 64, 128, 256); break;
+    case 4: go(zgemm_pl2_kernel<128, 128, 2, 4, CONJ, SPLIT>, 128, 128, 512); break;
     default: go(zgemm_pl_kernel<128, 128, 2, 4, CONJ, SPLIT>, 128, 128, 512); break;
   }
   CHEBFI_HIP(hipGetLastError());
