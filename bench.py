@@ -86,7 +86,7 @@ def roofline_of(prof, peak_mfma, mfma_label, gemm_work_factor=1.0):
     `gemm_work_factor` (3 for the split-BF16 form, which executes three bf16
     products per real product)."""
     gemm_cls = ("proj_gemm", "expand_gemm")
-    h_cls = ("proj_gemm", "expand_gemm", "fft_a", "fft_b", "fft_c", "dapply")
+    h_cls = ("proj_gemm", "expand_gemm", "fft_a", "fft_b", "fft_c", "dapply", "split")
     dom = max(h_cls, key=lambda c: prof[c][0])
     ms_tot, work, cnt = prof[dom]
     if dom in gemm_cls:

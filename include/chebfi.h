@@ -177,9 +177,12 @@ abi_status abi_update_potential(abi_system sys, const double *vloc, const void *
  * the convention dL/dRe + i dL/dIm (each D entry independent); the bounds are
  * held fixed.  Iterates are recomputed from (Y_{s-1}, Y_s) checkpoints taken
  * every ckpt_every steps (0 = one segment, all iterates kept).
- * X, W: c128 npw x nband (ld).  Outputs (device, overwritten): dV (n1*n2*n3
- * doubles), dD (natom*16 complex doubles; may be NULL when natom = 0), dX
- * (npw x nband, ld) or NULL.  dtype must be ABI_C128. */
+ * X, W: npw x nband (ld), both of `dtype`: ABI_C128, or ABI_C64 on a handle
+ * built with ABI_PREC_MIXED (then the iterates and adjoint iterates are
+ * complex64, the FFT passes FP32 and the projector products split-BF16, as in
+ * abi_cheb_filter; dV and dD are still accumulated in FP64).  Outputs (device,
+ * overwritten): dV (n1*n2*n3 doubles), dD (natom*16 complex doubles; may be
+ * NULL when natom = 0), dX (npw x nband, ld, of `dtype`) or NULL. */
 abi_status abi_filter_backward(abi_system sys, const void *X, const void *W, int64_t nband,
                                int64_t ld, int32_t dtype, int32_t degree, double a, double b,
                                double a0, int32_t ckpt_every, double *dV, void *dD, void *dX,
@@ -212,6 +215,59 @@ abi_status abi_zpotrf_upper(int64_t m, void *A, int64_t lda, void *stream);
 abi_status abi_zheev(int64_t m, void *A, int64_t lda, double *w, void *Z, int64_t ldz,
                      void *stream);
 
+/* ---- batching: many systems in one set of launches ---------------------------
+ * The paper applies the operator to a whole block of bands per call instead
+ * of band by band (section "Batch processing"); a batch extends this across
+ * independent systems (cells, k-points) of uneven plane-wave counts and FFT
+ * boxes.  One filter step of every system of the batch is four launches
+ * (projection + D, the three FFT passes with the expansion and the recurrence
+ * fused into the last), each a grid-stride loop over the work items of all
+ * systems; the 4 x degree launches of a filter are captured into a HIP graph
+ * on first use and replayed.  Limits: at most 1024 systems, at most 8 atoms
+ * (32 projectors) per system, FFT edges up to 64. */
+typedef struct abi_batch_s *abi_batch;
+
+/* Builds the nsys systems of `descs` (as abi_set_system; all with the same
+ * precision) and the batch around them.  Errors: ABI_ERR_ARG (nsys out of
+ * range, more than 8 atoms in a system, mixed precisions), and those of
+ * abi_set_system. */
+abi_status abi_set_system_batch(const abi_system_desc *descs, int32_t nsys, void *stream,
+                                abi_batch *out);
+
+/* The handle of system i (owned by the batch: valid until abi_destroy_batch,
+ * never passed to abi_destroy); for abi_system_info, abi_get_gsphere, the
+ * single-system calls and their parity checks. */
+abi_status abi_batch_system(abi_batch batch, int32_t i, abi_system *out);
+
+/* Y_i = the degree-m Chebyshev filter of X_i for every system i of the batch,
+ * with its own bounds (a[i], b[i], a0[i]); the same result as abi_cheb_filter
+ * on each system.  X, Y: host arrays of nsys device pointers (blocks npw_i x
+ * nband[i], column stride ld[i], of `dtype`; Y_i separate from X_i).  nband,
+ * ld, a, b, a0: host arrays of nsys entries.  Stream-ordered; does not
+ * synchronise (it may capture a graph on the batch's own stream the first time
+ * a configuration is seen). */
+abi_status abi_cheb_filter_batch(abi_batch batch, const void *const *X, void *const *Y,
+                                 const int64_t *nband, const int64_t *ld, int32_t dtype,
+                                 int32_t degree, const double *a, const double *b,
+                                 const double *a0, void *stream);
+
+/* Times the launch variants of the batched filter on the caller's arguments
+ * (same as abi_cheb_filter_batch; Y is overwritten) and keeps the fastest:
+ * FFT pass threads per workgroup (256 / 512 where the plans allow), projection
+ * threads (128 / 256) and the radix order of the FFT plans (ascending /
+ * descending).  choice (host, 4 entries, may be NULL) receives {fft threads,
+ * projection threads, descending radix order (0/1), timed variants}.
+ * Synchronises the stream. */
+abi_status abi_batch_autotune(abi_batch batch, const void *const *X, void *const *Y,
+                              const int64_t *nband, const int64_t *ld, int32_t dtype,
+                              int32_t degree, const double *a, const double *b, const double *a0,
+                              int32_t *choice, void *stream);
+
+/* Graph capture on (1, default) or off (0: eager launches). */
+abi_status abi_batch_use_graph(abi_batch batch, int32_t on);
+
+abi_status abi_destroy_batch(abi_batch batch);
+
 /* ---- timing ------------------------------------------------------------------
  * Per-kernel-class timing with HIP events recorded on the stream of each call
  * (the method of the paper's section "Single-step benchmarks: GPU kernel
@@ -219,8 +275,10 @@ abi_status abi_zheev(int64_t m, void *A, int64_t lda, double *w, void *Z, int64_
  * Classes: 0 projection GEMM P^H X, 1 expansion GEMM P C', 2-4 FFT passes
  * A/B/C, 5 split-K sum + D (classes 0-5 count the launches inside
  * abi_cheb_filter only), 6 Gram and subspace GEMMs, 7 Cholesky + inverse +
- * reduction, 8 eigensolver, 9 rotations (classes 6-9: abi_rayleigh_ritz).  `work` is the algorithmic flop count
- * (GEMM, dense classes) or HBM byte count (FFT passes) of the timed launches. */
+ * reduction, 8 eigensolver, 9 rotations (classes 6-9: abi_rayleigh_ritz),
+ * 10 splitting of the block into bf16 hi/lo planes (mixed form; filter only).
+ * `work` is the algorithmic flop count (GEMM, dense classes) or HBM byte count
+ * (FFT passes, plane splitting) of the timed launches. */
 
 /* Turns timing on or off and clears the accumulated figures. */
 abi_status abi_profile_enable(abi_system sys, int32_t on);

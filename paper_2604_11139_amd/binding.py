@@ -36,11 +36,13 @@ EXPORTS = [
     "abi_get_gsphere", "abi_get_projectors", "abi_destroy", "abi_apply_H",
     "abi_spectral_bounds", "abi_cheb_filter", "abi_rayleigh_ritz", "abi_zpotrf_upper",
     "abi_zheev", "abi_profile_enable", "abi_profile_read", "abi_update_potential",
-    "abi_filter_backward", "abi_density", "abi_last_error",
+    "abi_filter_backward", "abi_density", "abi_last_error", "abi_set_system_batch",
+    "abi_batch_system", "abi_cheb_filter_batch", "abi_batch_autotune", "abi_batch_use_graph",
+    "abi_destroy_batch",
 ]
 
 PROFILE_CLASSES = ["proj_gemm", "expand_gemm", "fft_a", "fft_b", "fft_c", "dapply", "gram",
-                   "chol", "eig", "rot"]
+                   "chol", "eig", "rot", "split"]
 
 
 class ChebfiError(RuntimeError):
@@ -99,6 +101,12 @@ def lib():
         "abi_filter_backward": [vp, vp, vp, c_int64, c_int64, c_int32, c_int32, c_double,
                                 c_double, c_double, c_int32, vp, vp, vp, vp],
         "abi_profile_read": [vp, c_int32, vp, vp, vp],
+        "abi_set_system_batch": [vp, c_int32, vp, POINTER(vp)],
+        "abi_batch_system": [vp, c_int32, POINTER(vp)],
+        "abi_cheb_filter_batch": [vp, vp, vp, vp, vp, c_int32, c_int32, vp, vp, vp, vp],
+        "abi_batch_autotune": [vp, vp, vp, vp, vp, c_int32, c_int32, vp, vp, vp, vp, vp],
+        "abi_batch_use_graph": [vp, c_int32],
+        "abi_destroy_batch": [vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -192,6 +200,20 @@ class System:
         handle = c_void_p()
         _check(lib().abi_set_system(ctypes.byref(h.desc), _stream(), ctypes.byref(handle)))
         self._h = handle
+        self._own = True
+        self._info()
+
+    @classmethod
+    def _borrow(cls, handle, owner):
+        """A view of a handle owned by `owner` (a Batch): never destroyed here."""
+        obj = cls.__new__(cls)
+        obj._h = handle
+        obj._own = False
+        obj._owner = owner
+        obj._info()
+        return obj
+
+    def _info(self):
         npw = c_int64(0)
         nproj = c_int32(0)
         grid = (c_int32 * 3)()
@@ -201,9 +223,9 @@ class System:
         self.ngrid = tuple(grid)
 
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
+        if getattr(self, "_h", None) is not None and self._h.value and self._own:
             _check(lib().abi_destroy(self._h))
-            self._h = None
+        self._h = None
 
     def __del__(self):
         try:
@@ -384,14 +406,103 @@ def zheev(A):
     return w, Z.t()
 
 
+class Batch:
+    """Many independent systems filtered together (abi_cheb_filter_batch)."""
+
+    def __init__(self, systems, precision=ABI_PREC_MIXED):
+        holders = [_DescHolder.from_system(s, precision) for s in systems]
+        n = len(holders)
+        arr = (Desc * n)(*[h.desc for h in holders])
+        handle = c_void_p()
+        _check(lib().abi_set_system_batch(ctypes.cast(arr, c_void_p), n, _stream(),
+                                          ctypes.byref(handle)))
+        self._h = handle
+        self.systems = []
+        for i in range(n):
+            hi = c_void_p()
+            _check(lib().abi_batch_system(self._h, i, ctypes.byref(hi)))
+            self.systems.append(System._borrow(hi, self))
+
+    def __len__(self):
+        return len(self.systems)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            for s in self.systems:
+                s._h = None
+            _check(lib().abi_destroy_batch(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _args(self, Xs, out, bounds):
+        n = len(self.systems)
+        if len(Xs) != n or len(bounds) != n:
+            raise ValueError("one block and one (a, b, a0) per system")
+        if out is None:
+            out = [self.systems[i]._out_like(Xs[i], None) for i in range(n)]
+        xs, ys = (c_void_p * n)(), (c_void_p * n)()
+        nb, ld = (c_int64 * n)(), (c_int64 * n)()
+        a, b, a0 = (c_double * n)(), (c_double * n)(), (c_double * n)()
+        code = None
+        for i in range(n):
+            px, nbi, ldi, ci = _block(Xs[i], self.systems[i].npw)
+            self.systems[i]._out_like(Xs[i], out[i])
+            py, _, _, _ = _block(out[i], self.systems[i].npw)
+            if code is None:
+                code = ci
+            elif ci != code:
+                raise TypeError("all blocks of a batch must share one dtype")
+            xs[i], ys[i], nb[i], ld[i] = px, py, nbi, ldi
+            a[i], b[i], a0[i] = (float(v) for v in bounds[i])
+        return out, (xs, ys, nb, ld, code, a, b, a0)
+
+    def cheb_filter(self, Xs, degree, bounds, out=None):
+        """[Y_i] = degree-m filters of the blocks [X_i] with bounds [(a, b, a0)_i]."""
+        out, (xs, ys, nb, ld, code, a, b, a0) = self._args(Xs, out, bounds)
+        _check(lib().abi_cheb_filter_batch(self._h, ctypes.cast(xs, c_void_p),
+                                           ctypes.cast(ys, c_void_p), ctypes.cast(nb, c_void_p),
+                                           ctypes.cast(ld, c_void_p), code, int(degree),
+                                           ctypes.cast(a, c_void_p), ctypes.cast(b, c_void_p),
+                                           ctypes.cast(a0, c_void_p), _stream()))
+        return out
+
+    def autotune(self, Xs, degree, bounds, out=None):
+        """Times the launch variants on these arguments and keeps the fastest."""
+        out, (xs, ys, nb, ld, code, a, b, a0) = self._args(Xs, out, bounds)
+        ch = (c_int32 * 4)()
+        _check(lib().abi_batch_autotune(self._h, ctypes.cast(xs, c_void_p),
+                                        ctypes.cast(ys, c_void_p), ctypes.cast(nb, c_void_p),
+                                        ctypes.cast(ld, c_void_p), code, int(degree),
+                                        ctypes.cast(a, c_void_p), ctypes.cast(b, c_void_p),
+                                        ctypes.cast(a0, c_void_p), ctypes.cast(ch, c_void_p),
+                                        _stream()))
+        return {"fft_threads": ch[0], "proj_threads": ch[1], "radix_descending": bool(ch[2]),
+                "variants_timed": ch[3]}
+
+    def use_graph(self, on=True):
+        _check(lib().abi_batch_use_graph(self._h, 1 if on else 0))
+
+
 def _make_autograd():
     import torch
 
     class ChebFilterFunction(torch.autograd.Function):
         """Y = p(H[vloc, dij]) X with the library's adjoint as its backward.
 
-        Inputs X (complex128 (nband, npw)), vloc (float64, n1*n2*n3) and dij
-        (complex128 (natom, 4, 4)) are differentiable; the bounds are constants.
+        Inputs X (complex128 (nband, npw), or complex64 on a mixed-precision
+        handle), vloc (float64, n1*n2*n3) and dij (complex128 (natom, 4, 4))
+        are differentiable; the bounds are constants.
         """
 
         @staticmethod

@@ -1,0 +1,297 @@
+// Batched Chebyshev filter over many independent systems (cells and k-points
+// of uneven plane-wave counts and FFT boxes) in one set of launches.
+//
+// The paper batches the bands of one system into one FFT call (section "Batch
+// processing"); here the batch spans systems as well.  One filter step of
+// every system is four launches, each a flat, grid-stride ("persistent") loop
+// over the work items of all systems:
+//   K1 proj   (system, band):     C = P^H Y_k (all projectors of the band),
+//                                 C' = alpha D C per atom;
+//   K2 pass A (system, band, i3): sphere plane -> inverse xy FFT -> box;
+//   K3 pass B (system, band, i2): z FFT, * V, z FFT;
+//   K4 pass C (system, band, i3): forward xy FFT -> gather, kinetic term,
+//                                 nonlocal expansion P C' of the plane's
+//                                 sphere points, three-term recurrence.
+// The nonlocal products are tiny here (4-32 projectors), so they are folded
+// into these memory-bound passes instead of MFMA tiles.  Per-system tables,
+// per-step pointers and coefficients are read from device descriptors, so the
+// 4 x degree launches are captured once into a HIP graph and replayed.
+#include <algorithm>
+#include <cstring>
+
+#include "cplx.h"
+#include "fft_dev.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace chebfi {
+
+namespace {
+
+// item -> system by a scan of the prefix offsets off[0..nsys]
+__device__ __forceinline__ int find_sys(const int64_t *off, int nsys, int64_t item) {
+  int s = 0;
+  while (s + 1 < nsys && item >= off[s + 1]) ++s;
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ C2<T> wave_sum(C2<T> v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o, 64);
+    v.y += __shfl_xor(v.y, o, 64);
+  }
+  return v;
+}
+
+// K1: C = P^H Y_k for one band, then C' = alpha D C (per atom 4 x 4).
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void bproj_kernel(const BatchSys *__restrict__ sys,
+                                                   const BatchStep *__restrict__ step,
+                                                   const int64_t *__restrict__ off, int nsys) {
+  __shared__ C2<T> part[NT / 64][kBatchMaxProj];
+  __shared__ double2 csum[kBatchMaxProj];
+  const int64_t total = off[nsys];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const int s = find_sys(off, nsys, item);
+    const BatchSys &d = sys[s];
+    const BatchStep &st = step[s];
+    const int64_t b = item - off[s];
+    const int np = d.nproj;
+    const int64_t npw = d.npw;
+    const C2<T> *y = reinterpret_cast<const C2<T> *>(st.yk) + b * st.ldk;
+    const C2<T> *P = reinterpret_cast<const C2<T> *>(d.P);
+    C2<T> acc[kBatchMaxProj];
+#pragma unroll
+    for (int j = 0; j < kBatchMaxProj; ++j) acc[j] = C2<T>{0, 0};
+    for (int64_t g = threadIdx.x; g < npw; g += NT) {
+      const C2<T> x = y[g];
+#pragma unroll
+      for (int j = 0; j < kBatchMaxProj; ++j) {
+        if (j < np) {
+          const C2<T> p = P[g + (int64_t)j * npw];
+          // conj(p) x
+          acc[j].x += p.x * x.x + p.y * x.y;
+          acc[j].y += p.x * x.y - p.y * x.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kBatchMaxProj; ++j) {
+      if (j < np) {
+        const C2<T> v = wave_sum<T>(acc[j]);
+        if (lane == 0) part[wave][j] = v;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < np) {
+      double sx = 0.0, sy = 0.0;
+      for (int w = 0; w < NT / 64; ++w) {
+        sx += (double)part[w][threadIdx.x].x;
+        sy += (double)part[w][threadIdx.x].y;
+      }
+      csum[threadIdx.x] = double2{sx, sy};
+    }
+    __syncthreads();
+    if (threadIdx.x < np) {
+      const int j = threadIdx.x, R = j >> 2, i = j & 3;
+      const double2 *Dm = d.D + 16 * R + 4 * i;
+      double2 v{0, 0};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v = cadd(v, cmul(Dm[q], csum[4 * R + q]));
+      C2<T> *cp = reinterpret_cast<C2<T> *>(d.Cp) + b * np;
+      cp[j] = C2<T>{(T)(st.alpha * v.x), (T)(st.alpha * v.y)};
+    }
+    __syncthreads();
+  }
+}
+
+// K2: pass A over (system, band, i3).
+template <typename T>
+__global__ __launch_bounds__(512) void bpass_a_kernel(const BatchSys *__restrict__ sys,
+                                                      const BatchStep *__restrict__ step,
+                                                      const int64_t *__restrict__ off, int nsys) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
+  const int64_t total = off[nsys];
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const int s = find_sys(off, nsys, item);
+    const BatchSys &d = sys[s];
+    const BatchStep &st = step[s];
+    const int n1 = d.plan.d[0].n, n2 = d.plan.d[1].n, n3 = d.plan.d[2].n;
+    const int nxy = n1 * n2;
+    const int64_t loc = item - off[s];
+    const int64_t b = loc / n3;
+    const int i3 = (int)(loc - b * n3);
+    C2<T> *tw1 = buf + nxy;
+    C2<T> *tw2 = tw1 + n1;
+    load_twiddles<T>(tw1, d.tw, n1);
+    load_twiddles<T>(tw2, d.tw + kMaxN, n2);
+    for (int i = threadIdx.x; i < nxy; i += blockDim.x) buf[i] = C2<T>{0, 0};
+    __syncthreads();
+    const int s0 = d.plane[i3], s1 = d.plane[i3 + 1];
+    const C2<T> *xb = reinterpret_cast<const C2<T> *>(st.yk) + b * st.ldk;
+    const int offp = i3 * nxy;
+    for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x)
+      buf[d.box_index[idx] - offp] = xb[idx];
+    __syncthreads();
+    lds_fft<T>(buf, d.plan.d[0], 1, n2, n1, tw1, +1);
+    lds_fft<T>(buf, d.plan.d[1], n1, n1, 1, tw2, +1);
+    C2<T> *dst = reinterpret_cast<C2<T> *>(d.box) + b * (int64_t)nxy * n3 + offp;
+    for (int i = threadIdx.x; i < nxy; i += blockDim.x) dst[i] = buf[i];
+    __syncthreads();
+  }
+}
+
+// K3: pass B over (system, band, i2).
+template <typename T>
+__global__ __launch_bounds__(512) void bpass_b_kernel(const BatchSys *__restrict__ sys,
+                                                      const int64_t *__restrict__ off, int nsys) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
+  const int64_t total = off[nsys];
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const int s = find_sys(off, nsys, item);
+    const BatchSys &d = sys[s];
+    const int n1 = d.plan.d[0].n, n2 = d.plan.d[1].n, n3 = d.plan.d[2].n;
+    const int nxz = n1 * n3;
+    const int64_t loc = item - off[s];
+    const int64_t b = loc / n2;
+    const int i2 = (int)(loc - b * n2);
+    C2<T> *tw3 = buf + nxz;
+    load_twiddles<T>(tw3, d.tw + 2 * kMaxN, n3);
+    C2<T> *src = reinterpret_cast<C2<T> *>(d.box) + b * (int64_t)n1 * n2 * n3;
+    const T *V = reinterpret_cast<const T *>(d.V);
+    for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
+      const int i1 = i % n1, i3 = i / n1;
+      buf[i] = src[i1 + n1 * (i2 + n2 * i3)];
+    }
+    __syncthreads();
+    lds_fft<T>(buf, d.plan.d[2], n1, n1, 1, tw3, +1);
+    for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
+      const int i1 = i % n1, i3 = i / n1;
+      buf[i] = cscale(buf[i], V[i1 + n1 * (i2 + n2 * i3)]);
+    }
+    __syncthreads();
+    lds_fft<T>(buf, d.plan.d[2], n1, n1, 1, tw3, -1);
+    for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
+      const int i1 = i % n1, i3 = i / n1;
+      src[i1 + n1 * (i2 + n2 * i3)] = buf[i];
+    }
+    __syncthreads();
+  }
+}
+
+// K4: pass C over (system, band, i3) with the nonlocal expansion and the
+// recurrence: out = alpha (local + (kin - c) y_k) + P C' - beta y_prev.
+template <typename T>
+__global__ __launch_bounds__(512) void bpass_c_kernel(const BatchSys *__restrict__ sys,
+                                                      const BatchStep *__restrict__ step,
+                                                      const int64_t *__restrict__ off, int nsys) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
+  const int64_t total = off[nsys];
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const int s = find_sys(off, nsys, item);
+    const BatchSys &d = sys[s];
+    const BatchStep &st = step[s];
+    const int n1 = d.plan.d[0].n, n2 = d.plan.d[1].n, n3 = d.plan.d[2].n;
+    const int nxy = n1 * n2;
+    const int64_t loc = item - off[s];
+    const int64_t b = loc / n3;
+    const int i3 = (int)(loc - b * n3);
+    const int np = d.nproj;
+    C2<T> *tw1 = buf + nxy;
+    C2<T> *tw2 = tw1 + n1;
+    C2<T> *cp = tw2 + n2;
+    load_twiddles<T>(tw1, d.tw, n1);
+    load_twiddles<T>(tw2, d.tw + kMaxN, n2);
+    if (threadIdx.x < np)
+      cp[threadIdx.x] = reinterpret_cast<const C2<T> *>(d.Cp)[b * np + threadIdx.x];
+    const int offp = i3 * nxy;
+    const C2<T> *src = reinterpret_cast<const C2<T> *>(d.box) + b * (int64_t)nxy * n3 + offp;
+    for (int i = threadIdx.x; i < nxy; i += blockDim.x) buf[i] = src[i];
+    __syncthreads();
+    lds_fft<T>(buf, d.plan.d[1], n1, n1, 1, tw2, -1);
+    lds_fft<T>(buf, d.plan.d[0], 1, n2, n1, tw1, -1);
+    const int s0 = d.plane[i3], s1 = d.plane[i3 + 1];
+    const C2<T> *yk = reinterpret_cast<const C2<T> *>(st.yk) + b * st.ldk;
+    const C2<T> *yp =
+        st.yprev ? reinterpret_cast<const C2<T> *>(st.yprev) + b * st.ldp : nullptr;
+    C2<T> *out = reinterpret_cast<C2<T> *>(st.out) + b * st.ldo;
+    const C2<T> *P = reinterpret_cast<const C2<T> *>(d.P);
+    const T alpha = (T)st.alpha, cshift = (T)st.cshift, beta = (T)st.beta;
+    const T scale = (T)(1.0 / ((double)nxy * n3));
+    for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x) {
+      const C2<T> lc = cscale(buf[d.box_index[idx] - offp], scale);
+      const C2<T> x = yk[idx];
+      const T kd = (T)d.kin[idx] - cshift;
+      const C2<T> h = cadd(lc, cscale(x, kd));
+      C2<T> nl{0, 0};
+      for (int j = 0; j < np; ++j) nl = cadd(nl, cmul(P[idx + (int64_t)j * d.npw], cp[j]));
+      C2<T> o{alpha * h.x + nl.x, alpha * h.y + nl.y};
+      if (yp) {
+        const C2<T> p = yp[idx];
+        o.x -= beta * p.x;
+        o.y -= beta * p.y;
+      }
+      out[idx] = o;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename F> void set_lds_b(F kernel, size_t bytes) {
+  CHEBFI_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+}  // namespace
+
+// Host side: launches of one filter step for all systems.
+template <typename T>
+void batch_step(const BatchLaunch &L, int j, hipStream_t st) {
+  const BatchStep *stp = L.d_steps + (size_t)j * L.nsys;
+  const int64_t *offP = L.d_off;
+  const int64_t *offA = L.d_off + (L.nsys + 1);
+  const int64_t *offB = L.d_off + 2 * (L.nsys + 1);
+  auto grid = [&](int64_t items) {
+    return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(items, L.max_wgs)));
+  };
+  if (L.any_proj) {
+    if (L.proj_threads == 128)
+      hipLaunchKernelGGL((bproj_kernel<T, 128>), grid(L.items_p), dim3(128), 0, st, L.d_sys, stp,
+                         offP, L.nsys);
+    else
+      hipLaunchKernelGGL((bproj_kernel<T, 256>), grid(L.items_p), dim3(256), 0, st, L.d_sys, stp,
+                         offP, L.nsys);
+    CHEBFI_HIP(hipGetLastError());
+  }
+  const size_t e = sizeof(C2<T>);
+  hipLaunchKernelGGL(bpass_a_kernel<T>, grid(L.items_a), dim3(L.fft_threads), e * L.lds_a, st,
+                     L.d_sys, stp, offA, L.nsys);
+  CHEBFI_HIP(hipGetLastError());
+  hipLaunchKernelGGL(bpass_b_kernel<T>, grid(L.items_b), dim3(L.fft_threads), e * L.lds_b, st,
+                     L.d_sys, offB, L.nsys);
+  CHEBFI_HIP(hipGetLastError());
+  hipLaunchKernelGGL(bpass_c_kernel<T>, grid(L.items_a), dim3(L.fft_threads), e * L.lds_c, st,
+                     L.d_sys, stp, offA, L.nsys);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+template <typename T>
+void batch_prepare(const BatchLaunch &L) {
+  const size_t e = sizeof(C2<T>);
+  set_lds_b(bpass_a_kernel<T>, e * L.lds_a);
+  set_lds_b(bpass_b_kernel<T>, e * L.lds_b);
+  set_lds_b(bpass_c_kernel<T>, e * L.lds_c);
+}
+
+template void batch_step<float>(const BatchLaunch &, int, hipStream_t);
+template void batch_step<double>(const BatchLaunch &, int, hipStream_t);
+template void batch_prepare<float>(const BatchLaunch &);
+template void batch_prepare<double>(const BatchLaunch &);
+
+}  // namespace chebfi

@@ -6,6 +6,7 @@
 // (section "Main computational kernels"), the Chebyshev filter loop of
 // Algorithm "Parallel Chebyshev filtering of degree k" and the S-ortho / RR
 // algorithms of section "Parallel implementation design" with S = I.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -54,7 +55,8 @@ hipEvent_t Profiler::take() {
 
 int Profiler::begin(int cls, double w, hipStream_t st) {
   if (!on) return -1;
-  if (cls <= PROF_DAPPLY && !in_filter) return -1;  // H-application classes: filter only
+  // H-application classes: filter only
+  if ((cls <= PROF_DAPPLY || cls == PROF_SPLIT) && !in_filter) return -1;
   Rec r{cls, take(), take(), w};
   CHEBFI_HIP(hipEventRecord(r.a, st));
   pending.push_back(r);
@@ -214,12 +216,17 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
     cprime = (V2 *)s->cprime.get(sizeof(V2) * (size_t)nproj * nband);
     // C = P^H X (split along the plane waves), C' = alpha D C
     const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
+    void *xpl = nullptr;
+    if (planes) {
+      xpl = s->planes.get(8 * (size_t)s->ldPA * nband);
+      const int tk = s->prof.begin(PROF_SPLIT, 16.0 * (double)npw * (double)nband, st);
+      split_planes(npw, nband, X, ldx, xpl, s->ldPA, st);
+      s->prof.end(tk, st);
+    }
     int tok = s->prof.begin(PROF_PROJ, flops, st);
     if (single)
       proj_gemv(npw, nproj, P, X, cpart, st);
-    else if (fp32 && s->mixed_gemm == 0) {
-      void *xpl = s->planes.get(8 * (size_t)s->ldPA * nband);
-      split_planes(npw, nband, X, ldx, xpl, s->ldPA, st);
+    else if (planes) {
       proj_gemm_planes(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, xpl,
                        s->ldPA, s->ldPA * nband, cpart, splits, st, s->pl_proj);
     } else if (fp32 && s->mixed_gemm == 2)
@@ -350,6 +357,232 @@ void rr_core(abi_system_s *s, double2 *Y, int64_t ld, double2 *HPsi, int64_t ldh
 }
 
 }  // namespace
+
+// ---- batched filter (host side) --------------------------------------------------
+struct abi_batch_s {
+  std::vector<abi_system_s *> sys;
+  int precision = ABI_PREC_FP64;
+  hipStream_t cap = nullptr;  // capture stream of the graphs
+  chebfi::DevBuf d_tab, work;   // device tables [systems | steps | offsets], workspace
+  void *h_tab = nullptr;        // pinned staging copy of the tables
+  size_t h_tab_bytes = 0;
+  hipEvent_t tab_copied = nullptr;  // the last table upload has left h_tab
+  std::vector<chebfi::BatchSys> hsys;
+  std::vector<chebfi::BatchStep> hsteps;
+  std::vector<int64_t> hoff;
+  int fft_threads = 256, proj_threads = 256, radix_desc = 0, fft_min_threads = 256;
+  bool use_graph = true;
+  // the captured graph and what it was captured for
+  hipGraphExec_t gexec = nullptr;
+  std::vector<int64_t> g_nband;
+  int g_degree = -1, g_dtype = -1, g_fft = 0, g_proj = 0;
+  const void *g_sys = nullptr, *g_steps = nullptr, *g_off = nullptr;
+};
+
+namespace chebfi {
+namespace {
+
+BoxPlan ordered_plan(const BoxPlan &p, bool descending) {
+  BoxPlan q = p;
+  if (descending)
+    for (int d = 0; d < 3; ++d) std::reverse(q.d[d].radix, q.d[d].radix + q.d[d].nstage);
+  return q;
+}
+
+template <typename T>
+void batch_run(abi_batch_s *B, const BatchLaunch &L, int degree, int32_t dtype,
+               const std::vector<int64_t> &nb, hipStream_t st) {
+  batch_prepare<T>(L);
+  if (!B->use_graph) {
+    for (int j = 0; j < degree; ++j) batch_step<T>(L, j, st);
+    return;
+  }
+  const bool same = B->gexec && B->g_nband == nb && B->g_degree == degree && B->g_dtype == dtype &&
+                    B->g_fft == L.fft_threads && B->g_proj == L.proj_threads &&
+                    B->g_sys == L.d_sys && B->g_steps == L.d_steps && B->g_off == L.d_off;
+  if (!same) {
+    if (B->gexec) {
+      CHEBFI_HIP(hipGraphExecDestroy(B->gexec));
+      B->gexec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    CHEBFI_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+    try {
+      for (int j = 0; j < degree; ++j) batch_step<T>(L, j, B->cap);
+    } catch (...) {
+      (void)hipStreamEndCapture(B->cap, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    CHEBFI_HIP(hipStreamEndCapture(B->cap, &g));
+    const hipError_t e = hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    CHEBFI_HIP(e);
+    B->g_nband = nb;
+    B->g_degree = degree;
+    B->g_dtype = dtype;
+    B->g_fft = L.fft_threads;
+    B->g_proj = L.proj_threads;
+    B->g_sys = L.d_sys;
+    B->g_steps = L.d_steps;
+    B->g_off = L.d_off;
+  }
+  CHEBFI_HIP(hipGraphLaunch(B->gexec, st));
+}
+
+}  // namespace
+
+void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const int64_t *nband,
+                  const int64_t *ld, int32_t dtype, int32_t degree, const double *a,
+                  const double *b, const double *a0, hipStream_t st) {
+  CHEBFI_REQUIRE(B != nullptr, ABI_ERR_ARG, "batch is NULL");
+  CHEBFI_REQUIRE(X && Y && nband && ld && a && b && a0, ABI_ERR_ARG, "NULL argument array");
+  CHEBFI_REQUIRE(degree >= 1, ABI_ERR_ARG, "degree must be >= 1");
+  const int nsys = (int)B->sys.size();
+  const bool fp32 = (dtype == ABI_C64);
+  for (int i = 0; i < nsys; ++i) {
+    check_block(B->sys[i], X[i], nband[i], ld[i], dtype);
+    CHEBFI_REQUIRE(Y[i] != nullptr && Y[i] != X[i], ABI_ERR_ARG, "Y must be a separate block");
+    CHEBFI_REQUIRE(std::isfinite(a[i]) && std::isfinite(b[i]) && std::isfinite(a0[i]),
+                   ABI_ERR_ARG, "bounds must be finite");
+    CHEBFI_REQUIRE(b[i] > a[i], ABI_ERR_ARG, "need b > a");
+    CHEBFI_REQUIRE(a0[i] <= a[i], ABI_ERR_ARG, "need a0 <= a");
+  }
+  const size_t esz = elem_bytes(dtype);
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  // workspace: boxes, C', two iterate slots per system
+  std::vector<size_t> o_box(nsys), o_cp(nsys), o_slot(nsys);
+  size_t tot = 0;
+  int min_threads = 256;
+  size_t lds_a = 0, lds_b = 0;
+  bool any_proj = false;
+  for (int i = 0; i < nsys; ++i) {
+    const abi_system_s *s = B->sys[i];
+    const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
+    o_box[i] = tot;
+    tot += al(esz * (size_t)nbox * nband[i]);
+    o_cp[i] = tot;
+    tot += al(esz * (size_t)std::max(s->nproj, 1) * nband[i]);
+    o_slot[i] = tot;
+    if (degree >= 2) tot += 2 * al(esz * (size_t)s->npw * nband[i]);
+    min_threads = std::max({min_threads, fft_stage_threads(s->plan.d[0], s->n2),
+                            fft_stage_threads(s->plan.d[1], s->n1),
+                            fft_stage_threads(s->plan.d[2], s->n1)});
+    lds_a = std::max(lds_a, (size_t)(s->n1 * s->n2 + s->n1 + s->n2));
+    lds_b = std::max(lds_b, (size_t)(s->n1 * s->n3 + s->n3));
+    any_proj = any_proj || s->nproj > 0;
+  }
+  CHEBFI_REQUIRE(min_threads <= 512, ABI_ERR_GRID, "FFT plane too large for one workgroup");
+  B->fft_min_threads = min_threads;
+  if (B->fft_threads < min_threads) B->fft_threads = min_threads <= 256 ? 256 : 512;
+  char *ws = (char *)B->work.get(tot);
+  // per-system descriptors and item offsets
+  B->hoff.assign(3 * (size_t)(nsys + 1), 0);
+  int64_t *offP = B->hoff.data(), *offA = offP + (nsys + 1), *offB = offA + (nsys + 1);
+  for (int i = 0; i < nsys; ++i) {
+    const abi_system_s *s = B->sys[i];
+    BatchSys &d = B->hsys[i];
+    d.plan = ordered_plan(s->plan, B->radix_desc != 0);
+    d.npw = s->npw;
+    d.nproj = s->nproj;
+    d.box_index = s->d_box;
+    d.plane = s->d_plane;
+    d.kin = s->d_kin;
+    d.V = fp32 ? (const void *)s->d_Vf : (const void *)s->d_V;
+    d.tw = reinterpret_cast<const double2 *>(s->d_tw);
+    d.P = fp32 ? (const void *)s->d_Pf : (const void *)s->d_P;
+    d.D = reinterpret_cast<const double2 *>(s->d_D);
+    d.box = ws + o_box[i];
+    d.Cp = ws + o_cp[i];
+    offP[i + 1] = offP[i] + nband[i];
+    offA[i + 1] = offA[i] + nband[i] * s->n3;
+    offB[i + 1] = offB[i] + nband[i] * s->n2;
+  }
+  // step table: Y_0 = X, Y_m = Y, Y_j (0 < j < m) in slot j % 2 (the update of
+  // step j reads Y_{j-2} and writes Y_j element by element in the same thread)
+  B->hsteps.assign((size_t)degree * nsys, BatchStep{});
+  for (int i = 0; i < nsys; ++i) {
+    const abi_system_s *s = B->sys[i];
+    const double e = (b[i] - a[i]) / 2.0, c = (b[i] + a[i]) / 2.0, s1 = e / (a0[i] - c);
+    const int64_t npw = s->npw;
+    auto iter = [&](int j, int64_t *ldj) -> void * {
+      if (j == 0) {
+        *ldj = ld[i];
+        return const_cast<void *>(X[i]);
+      }
+      if (j == degree) {
+        *ldj = ld[i];
+        return Y[i];
+      }
+      *ldj = npw;
+      return ws + o_slot[i] + (size_t)(j % 2) * al(esz * (size_t)npw * nband[i]);
+    };
+    double sk = s1;
+    for (int j = 1; j <= degree; ++j) {
+      BatchStep &p = B->hsteps[(size_t)(j - 1) * nsys + i];
+      p.yk = iter(j - 1, &p.ldk);
+      p.out = iter(j, &p.ldo);
+      p.cshift = c;
+      if (j == 1) {
+        p.alpha = s1 / e;
+        p.beta = 0.0;
+        p.yprev = nullptr;
+        p.ldp = 0;
+      } else {
+        const double sk1 = 1.0 / (2.0 / s1 - sk);
+        p.alpha = 2.0 * sk1 / e;
+        p.beta = sk * sk1;
+        sk = sk1;
+        p.yprev = iter(j - 2, &p.ldp);
+      }
+    }
+  }
+  // one upload of the tables from a pinned staging buffer, ordered on the
+  // caller's stream after the previous filter of this batch
+  const size_t t_sys = al(sizeof(BatchSys) * (size_t)nsys);
+  const size_t t_steps = al(sizeof(BatchStep) * B->hsteps.size());
+  const size_t t_off = al(sizeof(int64_t) * B->hoff.size());
+  const size_t t_all = t_sys + t_steps + t_off;
+  if (B->tab_copied) CHEBFI_HIP(hipEventSynchronize(B->tab_copied));
+  if (B->h_tab_bytes < t_all) {
+    if (B->h_tab) CHEBFI_HIP(hipHostFree(B->h_tab));
+    B->h_tab = nullptr;
+    B->h_tab_bytes = 0;
+    CHEBFI_HIP(hipHostMalloc(&B->h_tab, t_all, hipHostMallocDefault));
+    B->h_tab_bytes = t_all;
+  }
+  if (!B->tab_copied) CHEBFI_HIP(hipEventCreateWithFlags(&B->tab_copied, hipEventDisableTiming));
+  char *ht = (char *)B->h_tab;
+  std::memcpy(ht, B->hsys.data(), sizeof(BatchSys) * (size_t)nsys);
+  std::memcpy(ht + t_sys, B->hsteps.data(), sizeof(BatchStep) * B->hsteps.size());
+  std::memcpy(ht + t_sys + t_steps, B->hoff.data(), sizeof(int64_t) * B->hoff.size());
+  char *dt = (char *)B->d_tab.get(t_all);
+  CHEBFI_HIP(hipMemcpyAsync(dt, ht, t_all, hipMemcpyHostToDevice, st));
+  CHEBFI_HIP(hipEventRecord(B->tab_copied, st));
+  void *dsys = dt, *dsteps = dt + t_sys, *doff = dt + t_sys + t_steps;
+  BatchLaunch L;
+  L.nsys = nsys;
+  L.d_sys = (const BatchSys *)dsys;
+  L.d_steps = (const BatchStep *)dsteps;
+  L.d_off = (const int64_t *)doff;
+  L.items_p = offP[nsys];
+  L.items_a = offA[nsys];
+  L.items_b = offB[nsys];
+  L.max_wgs = 2048;
+  L.fft_threads = B->fft_threads;
+  L.proj_threads = B->proj_threads;
+  L.lds_a = lds_a;
+  L.lds_b = lds_b;
+  L.lds_c = lds_a + kBatchMaxProj;
+  L.any_proj = any_proj;
+  std::vector<int64_t> nb(nband, nband + nsys);
+  if (fp32)
+    batch_run<float>(B, L, degree, dtype, nb, st);
+  else
+    batch_run<double>(B, L, degree, dtype, nb, st);
+}
+
+}  // namespace chebfi
 
 extern "C" {
 
@@ -674,7 +907,6 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
                                void *stream) {
   return guarded([&] {
     check_block(s, X, nband, ld, dtype);
-    CHEBFI_REQUIRE(dtype == ABI_C128, ABI_ERR_STATE, "the adjoint runs on complex128 blocks");
     CHEBFI_REQUIRE(W != nullptr, ABI_ERR_ARG, "W is NULL");
     CHEBFI_REQUIRE(dV != nullptr, ABI_ERR_ARG, "dV is NULL");
     CHEBFI_REQUIRE(dD != nullptr || s->natom == 0, ABI_ERR_ARG, "dD is NULL");
@@ -685,6 +917,7 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
     CHEBFI_REQUIRE(a0 <= a, ABI_ERR_ARG, "need a0 <= a");
     CHEBFI_REQUIRE(ckpt_every >= 0, ABI_ERR_ARG, "ckpt_every must be >= 0");
     hipStream_t st = S(stream);
+    const bool fp32 = (dtype == ABI_C64);
     const int64_t npw = s->npw;
     const int nproj = s->nproj, natom = s->natom;
     const int m = degree;
@@ -705,16 +938,16 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
     std::vector<int> starts;  // segment starts 0, cseg, 2 cseg, ... < m
     for (int s0 = 0; s0 < m; s0 += cseg) starts.push_back(s0);
     const int nck = (int)starts.size() - 1;  // checkpoint pairs (Y_{s-1}, Y_s), s > 0
-    const size_t blk = sizeof(double2) * (size_t)npw * nband;
+    const size_t esz = elem_bytes(dtype);
+    const size_t blk = esz * (size_t)npw * nband;
     const int nblocks = 2 * nck + cseg + 3;
     char *base = (char *)s->adj.get(blk * (size_t)nblocks);
-    auto block = [&](int i) { return (double2 *)(base + blk * (size_t)i); };
+    auto block = [&](int i) { return (void *)(base + blk * (size_t)i); };
     auto ck_prev = [&](int j) { return block(2 * (j - 1)); };  // Y_{s_j - 1}
     auto ck_cur = [&](int j) { return block(2 * (j - 1) + 1); };  // Y_{s_j}
-    double2 *seg0 = block(2 * nck);
-    auto seg = [&](int i) { return seg0 + (size_t)npw * nband * i; };
-    double2 *abuf[3] = {block(2 * nck + cseg), block(2 * nck + cseg + 1),
-                        block(2 * nck + cseg + 2)};
+    char *seg0 = (char *)block(2 * nck);
+    auto seg = [&](int i) { return (void *)(seg0 + blk * (size_t)i); };
+    void *abuf[3] = {block(2 * nck + cseg), block(2 * nck + cseg + 1), block(2 * nck + cseg + 2)};
     const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
     // small accumulators: dV (nbox), dD (natom*16 complex), CA, CY (nproj*nband), C'
     const size_t small_bytes = sizeof(double) * (size_t)nbox + sizeof(double2) * 16 * (size_t)natom +
@@ -731,9 +964,28 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
     auto step_fwd = [&](int j, const void *ym1, int64_t ld1, const void *ym2, int64_t ld2,
                         void *dst) {  // Y_j from Y_{j-1} (and Y_{j-2})
       if (j == 1)
-        apply_core(s, ym1, ld1, nullptr, 0, dst, npw, nband, gam[0], c, 0.0, st);
+        apply_core(s, ym1, ld1, nullptr, 0, dst, npw, nband, gam[0], c, 0.0, st, dtype);
       else
-        apply_core(s, ym1, ld1, ym2, ld2, dst, npw, nband, gam[j - 1], c, del[j - 1], st);
+        apply_core(s, ym1, ld1, ym2, ld2, dst, npw, nband, gam[j - 1], c, del[j - 1], st, dtype);
+    };
+    // raw projections out = P^H Z (nproj x nband, contiguous), in the block's precision
+    const bool planes = fp32 && s->mixed_gemm == 0;
+    auto project = [&](const void *Z, int64_t ldz, void *out) {
+      if (planes) {
+        const int splits = proj_planes_splits(s->pl_proj, nproj, nband, npw);
+        void *part = s->cpart.get(sizeof(float2) * (size_t)splits * nproj * nband);
+        void *zpl = s->planes.get(8 * (size_t)s->ldPA * nband);
+        split_planes(npw, nband, Z, ldz, zpl, s->ldPA, st);
+        proj_gemm_planes(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, zpl,
+                         s->ldPA, s->ldPA * nband, part, splits, st, s->pl_proj);
+        launch_sum_parts(nproj, nband, part, splits, out, st, true);
+      } else {
+        const int splits = zgemm_splits(nproj, nband, npw);
+        void *part = s->cpart.get(esz * (size_t)splits * nproj * nband);
+        proj_gemm(nproj, nband, npw, fp32 ? (const void *)s->d_Pf : (const void *)s->d_P, Z, ldz,
+                  part, splits, st, fp32);
+        launch_sum_parts(nproj, nband, part, splits, out, st, fp32);
+      }
     };
     // forward sweep: keep the checkpoint pairs
     {
@@ -749,10 +1001,10 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
           if (j == starts[q] - 1) slots.push_back(ck_prev(q));
           if (j == starts[q]) slots.push_back(ck_cur(q));
         }
-        void *dst = slots.empty() ? (void *)abuf[j % 3] : slots[0];
+        void *dst = slots.empty() ? abuf[j % 3] : slots[0];
         step_fwd(j, p1, l1, p2, l2, dst);
         for (size_t t = 1; t < slots.size(); ++t)
-          launch_copy_block(npw, nband, dst, npw, slots[t], npw, st);
+          launch_copy_block(npw, nband, dst, npw, slots[t], npw, st, fp32);
         p2 = p1;
         l2 = l1;
         p1 = dst;
@@ -760,9 +1012,9 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
       }
     }
     // reverse sweep, one segment at a time
-    const int fb = (int)std::min<int64_t>(s->fft_batch, nband);
-    void *box1 = s->box.get(sizeof(double2) * (size_t)nbox * fb);
-    void *box2 = s->box2.get(sizeof(double2) * (size_t)nbox * fb);
+    const int fb = (int)std::min<int64_t>(s->fft_batch * (fp32 ? 2 : 1), nband);
+    void *box1 = s->box.get(esz * (size_t)nbox * fb);
+    void *box2 = s->box2.get(esz * (size_t)nbox * fb);
     for (int q = (int)starts.size() - 1; q >= 0; --q) {
       const int s0 = starts[q];
       const int s1e = std::min(s0 + cseg, m);  // iterates Y_{s0} .. Y_{s1e-1}
@@ -792,32 +1044,44 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
         const void *Yk = yk(k, &ldy);
         const void *Ak1 = (k + 1 == m) ? W : (const void *)abuf[(k + 1) % 3];
         const int64_t lda1 = (k + 1 == m) ? ld : npw;
-        double2 *Ak = abuf[k % 3];
+        void *Ak = abuf[k % 3];
         const bool acc = (k + 1 < m);
         if (nproj > 0) {
-          const int splits = zgemm_splits(nproj, nband, npw);
-          void *part = s->cpart.get(sizeof(double2) * (size_t)splits * nproj * nband);
-          proj_gemm(nproj, nband, npw, s->d_P, Ak1, lda1, part, splits, st);
-          zsum_parts(nproj, nband, part, splits, CA, nproj, double2{1, 0}, double2{0, 0}, st);
-          proj_gemm(nproj, nband, npw, s->d_P, Yk, ldy, part, splits, st);
-          zsum_parts(nproj, nband, part, splits, CY, nproj, double2{1, 0}, double2{0, 0}, st);
-          launch_dd_accum(natom, nband, CA, CY, gam[k], dD_acc, st);
-          launch_dapply(natom, nband, CA, 1, s->d_D, gam[k], Cp, st);
+          project(Ak1, lda1, CA);
+          project(Yk, ldy, CY);
+          launch_dd_accum(natom, nband, CA, CY, gam[k], dD_acc, st, fp32);
+          launch_dapply(natom, nband, CA, 1, s->d_D, gam[k], Cp, st, fp32);
+          if (planes)
+            split_planes(nproj, nband, Cp, nproj, s->cplanes.get(8 * (size_t)s->ldPB * nband),
+                         s->ldPB, st);
         }
         for (int64_t b0 = 0; b0 < nband; b0 += fb) {
           const int nb = (int)std::min<int64_t>(fb, nband - b0);
-          launch_adjoint_local<double>(s, Ak1, lda1, Yk, ldy, Ak, npw, acc, (int)b0, nb, box1, box2,
-                                       s->d_V, gam[k], c, dV_acc, st);
+          if (fp32)
+            launch_adjoint_local<float>(s, Ak1, lda1, Yk, ldy, Ak, npw, acc, (int)b0, nb, box1,
+                                        box2, s->d_Vf, gam[k], c, dV_acc, st);
+          else
+            launch_adjoint_local<double>(s, Ak1, lda1, Yk, ldy, Ak, npw, acc, (int)b0, nb, box1,
+                                         box2, s->d_V, gam[k], c, dV_acc, st);
         }
-        if (nproj > 0) expand_gemm(npw, nband, nproj, s->d_P, Cp, Ak, npw, st);
-        if (k >= 1) launch_scale_neg(npw, nband, Ak1, lda1, del[k], abuf[(k + 2) % 3], npw, st);
+        if (nproj > 0) {
+          if (planes)
+            expand_gemm_planes(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB,
+                               s->cplanes.ptr, s->ldPB, s->ldPB * nband, Ak, npw, st,
+                               s->pl_expand);
+          else
+            expand_gemm(npw, nband, nproj, fp32 ? (const void *)s->d_Pf : (const void *)s->d_P,
+                        Cp, Ak, npw, st, fp32);
+        }
+        if (k >= 1)
+          launch_scale_neg(npw, nband, Ak1, lda1, del[k], abuf[(k + 2) % 3], npw, st, fp32);
       }
     }
     CHEBFI_HIP(hipMemcpyAsync(dV, dV_acc, sizeof(double) * nbox, hipMemcpyDeviceToDevice, st));
     if (natom > 0)
       CHEBFI_HIP(hipMemcpyAsync(dD, dD_acc, sizeof(double2) * 16 * (size_t)natom,
                                 hipMemcpyDeviceToDevice, st));
-    if (dX) launch_copy_block(npw, nband, abuf[0], npw, dX, ld, st);
+    if (dX) launch_copy_block(npw, nband, abuf[0], npw, dX, ld, st, fp32);
   });
 }
 
@@ -900,6 +1164,142 @@ abi_status abi_zheev(int64_t m, void *A, int64_t lda, double *w, void *Z, int64_
       throw;
     }
     (void)hipFree(work);
+  });
+}
+
+// ---- batching -----------------------------------------------------------------
+
+abi_status abi_set_system_batch(const abi_system_desc *descs, int32_t nsys, void *stream,
+                                abi_batch *out) {
+  abi_batch_s *B = nullptr;
+  abi_status rc = guarded([&] {
+    CHEBFI_REQUIRE(descs != nullptr && out != nullptr, ABI_ERR_ARG, "descs or out is NULL");
+    CHEBFI_REQUIRE(nsys >= 1 && nsys <= kBatchMaxSys, ABI_ERR_ARG, "nsys out of range");
+    for (int i = 0; i < nsys; ++i) {
+      CHEBFI_REQUIRE(descs[i].natom >= 0 && 4 * descs[i].natom <= kBatchMaxProj, ABI_ERR_ARG,
+                     "a batched system has more than 8 atoms");
+      CHEBFI_REQUIRE(descs[i].precision == descs[0].precision, ABI_ERR_ARG,
+                     "all systems of a batch need the same precision");
+    }
+    B = new abi_batch_s();
+    B->precision = descs[0].precision;
+    for (int i = 0; i < nsys; ++i) {
+      abi_system h = nullptr;
+      const abi_status st = abi_set_system(&descs[i], stream, &h);
+      if (st != ABI_OK) throw Error{st, "system " + std::to_string(i) + ": " + g_last_error};
+      B->sys.push_back(h);
+    }
+    B->hsys.resize(nsys);
+    CHEBFI_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+  });
+  if (rc != ABI_OK) {
+    if (B) {
+      for (abi_system h : B->sys) (void)abi_destroy(h);
+      if (B->cap) (void)hipStreamDestroy(B->cap);
+      delete B;
+    }
+    return rc;
+  }
+  *out = B;
+  return ABI_OK;
+}
+
+abi_status abi_batch_system(abi_batch B, int32_t i, abi_system *out) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(B != nullptr && out != nullptr, ABI_ERR_ARG, "batch or out is NULL");
+    CHEBFI_REQUIRE(i >= 0 && i < (int32_t)B->sys.size(), ABI_ERR_ARG, "system index out of range");
+    *out = B->sys[i];
+  });
+}
+
+abi_status abi_batch_use_graph(abi_batch B, int32_t on) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(B != nullptr, ABI_ERR_ARG, "batch is NULL");
+    B->use_graph = (on != 0);
+  });
+}
+
+abi_status abi_cheb_filter_batch(abi_batch B, const void *const *X, void *const *Y,
+                                 const int64_t *nband, const int64_t *ld, int32_t dtype,
+                                 int32_t degree, const double *a, const double *b,
+                                 const double *a0, void *stream) {
+  return guarded([&] {
+    batch_filter(B, X, Y, nband, ld, dtype, degree, a, b, a0, S(stream));
+  });
+}
+
+abi_status abi_batch_autotune(abi_batch B, const void *const *X, void *const *Y,
+                              const int64_t *nband, const int64_t *ld, int32_t dtype,
+                              int32_t degree, const double *a, const double *b, const double *a0,
+                              int32_t *choice, void *stream) {
+  return guarded([&] {
+    hipStream_t st = S(stream);
+    batch_filter(B, X, Y, nband, ld, dtype, degree, a, b, a0, st);  // validates, warms up
+    const bool graph = B->use_graph;
+    B->use_graph = false;
+    hipEvent_t e0, e1;
+    CHEBFI_HIP(hipEventCreate(&e0));
+    CHEBFI_HIP(hipEventCreate(&e1));
+    float best = -1.f;
+    int bf = B->fft_threads, bp = B->proj_threads, br = B->radix_desc, tried = 0;
+    try {
+      for (int rd = 0; rd < 2; ++rd)
+        for (int ft : {256, 512}) {
+          if (ft < B->fft_min_threads) continue;
+          for (int pt : {128, 256}) {
+            B->fft_threads = ft;
+            B->proj_threads = pt;
+            B->radix_desc = rd;
+            batch_filter(B, X, Y, nband, ld, dtype, degree, a, b, a0, st);  // warm-up
+            CHEBFI_HIP(hipEventRecord(e0, st));
+            for (int r = 0; r < 2; ++r)
+              batch_filter(B, X, Y, nband, ld, dtype, degree, a, b, a0, st);
+            CHEBFI_HIP(hipEventRecord(e1, st));
+            CHEBFI_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            CHEBFI_HIP(hipEventElapsedTime(&ms, e0, e1));
+            ++tried;
+            if (best < 0.f || ms < best) {
+              best = ms;
+              bf = ft;
+              bp = pt;
+              br = rd;
+            }
+          }
+        }
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      B->use_graph = graph;
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    B->fft_threads = bf;
+    B->proj_threads = bp;
+    B->radix_desc = br;
+    B->use_graph = graph;
+    batch_filter(B, X, Y, nband, ld, dtype, degree, a, b, a0, st);
+    CHEBFI_HIP(hipStreamSynchronize(st));
+    if (choice) {
+      choice[0] = bf;
+      choice[1] = bp;
+      choice[2] = br;
+      choice[3] = tried;
+    }
+  });
+}
+
+abi_status abi_destroy_batch(abi_batch B) {
+  return guarded([&] {
+    if (!B) return;
+    (void)hipDeviceSynchronize();
+    if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+    if (B->cap) (void)hipStreamDestroy(B->cap);
+    if (B->tab_copied) (void)hipEventDestroy(B->tab_copied);
+    if (B->h_tab) (void)hipHostFree(B->h_tab);
+    for (abi_system h : B->sys) (void)abi_destroy(h);
+    delete B;
   });
 }
 

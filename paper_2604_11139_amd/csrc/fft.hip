@@ -22,181 +22,11 @@
 #include "cplx.h"
 #include "internal.h"
 #include "kernels.h"
+#include "fft_dev.h"
 
 namespace chebfi {
 
 namespace {
-
-constexpr int kMaxB = 4;  // butterflies per thread per stage
-
-// Radix-R DFT in registers; sgn = -1 forward (e^{-}), +1 inverse (e^{+}).
-template <typename T, int R> struct Dft;
-
-template <typename T> struct Dft<T, 2> {
-  static __device__ __forceinline__ void run(C2<T> *x, int) {
-    C2<T> a = x[0], b = x[1];
-    x[0] = cadd(a, b);
-    x[1] = csub(a, b);
-  }
-};
-
-template <typename T> struct Dft<T, 4> {
-  static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
-    C2<T> s02 = cadd(x[0], x[2]), d02 = csub(x[0], x[2]);
-    C2<T> s13 = cadd(x[1], x[3]), d13 = cmul_i(csub(x[1], x[3]), sgn);
-    x[0] = cadd(s02, s13);
-    x[2] = csub(s02, s13);
-    x[1] = cadd(d02, d13);
-    x[3] = csub(d02, d13);
-  }
-};
-
-template <typename T> struct Dft<T, 3> {
-  static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
-    const T h = (T)0.86602540378443864676;  // sin(2 pi / 3)
-    C2<T> t1 = cadd(x[1], x[2]);
-    C2<T> t2 = cmul_i(cscale(csub(x[1], x[2]), h), sgn);
-    C2<T> m = csub(x[0], cscale(t1, (T)0.5));
-    x[0] = cadd(x[0], t1);
-    x[1] = cadd(m, t2);
-    x[2] = csub(m, t2);
-  }
-};
-
-template <typename T> struct Dft<T, 5> {
-  static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
-    const T c1 = (T)0.30901699437494742410;   // cos(2 pi / 5)
-    const T c2 = (T)-0.80901699437494742410;  // cos(4 pi / 5)
-    const T s1 = (T)0.95105651629515357212;   // sin(2 pi / 5)
-    const T s2 = (T)0.58778525229247312917;   // sin(4 pi / 5)
-    C2<T> t1 = cadd(x[1], x[4]), t2 = cadd(x[2], x[3]);
-    C2<T> t3 = csub(x[1], x[4]), t4 = csub(x[2], x[3]);
-    C2<T> a1 = cadd(x[0], cadd(cscale(t1, c1), cscale(t2, c2)));
-    C2<T> a2 = cadd(x[0], cadd(cscale(t1, c2), cscale(t2, c1)));
-    C2<T> b1 = cmul_i(cadd(cscale(t3, s1), cscale(t4, s2)), sgn);
-    C2<T> b2 = cmul_i(csub(cscale(t3, s2), cscale(t4, s1)), sgn);
-    x[0] = cadd(x[0], cadd(t1, t2));
-    x[1] = cadd(a1, b1);
-    x[4] = csub(a1, b1);
-    x[2] = cadd(a2, b2);
-    x[3] = csub(a2, b2);
-  }
-};
-
-template <typename T> struct Dft<T, 6> {
-  // even/odd split: two radix-3 DFTs combined with w6^k = e^{sgn i pi k/3}
-  static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
-    C2<T> e[3] = {x[0], x[2], x[4]}, o[3] = {x[1], x[3], x[5]};
-    Dft<T, 3>::run(e, sgn);
-    Dft<T, 3>::run(o, sgn);
-    const T h = (T)0.86602540378443864676;
-    const C2<T> w1{(T)0.5, (T)sgn * h}, w2{(T)-0.5, (T)sgn * h};
-    const C2<T> t1 = cmul(o[1], w1), t2 = cmul(o[2], w2);
-    x[0] = cadd(e[0], o[0]);
-    x[3] = csub(e[0], o[0]);
-    x[1] = cadd(e[1], t1);
-    x[4] = csub(e[1], t1);
-    x[2] = cadd(e[2], t2);
-    x[5] = csub(e[2], t2);
-  }
-};
-
-template <typename T> struct Dft<T, 8> {
-  // even/odd split: two radix-4 DFTs combined with w8^k = e^{sgn i pi k/4}
-  static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
-    C2<T> e[4] = {x[0], x[2], x[4], x[6]}, o[4] = {x[1], x[3], x[5], x[7]};
-    Dft<T, 4>::run(e, sgn);
-    Dft<T, 4>::run(o, sgn);
-    const T c = (T)0.70710678118654752440;
-    const C2<T> t1{c * (o[1].x - sgn * o[1].y), c * (o[1].y + sgn * o[1].x)};
-    const C2<T> t2 = cmul_i(o[2], sgn);
-    const C2<T> t3{c * (-o[3].x - sgn * o[3].y), c * (-o[3].y + sgn * o[3].x)};
-    x[0] = cadd(e[0], o[0]);
-    x[4] = csub(e[0], o[0]);
-    x[1] = cadd(e[1], t1);
-    x[5] = csub(e[1], t1);
-    x[2] = cadd(e[2], t2);
-    x[6] = csub(e[2], t2);
-    x[3] = cadd(e[3], t3);
-    x[7] = csub(e[3], t3);
-  }
-};
-
-// One Stockham stage of radix R over `npen` pencils of length n held in LDS.
-// Element e of pencil q sits at buf[q*pstride + e*estride].  p is the product
-// of the radices already applied.
-template <typename T, int R>
-__device__ void stage(C2<T> *buf, int n, int estride, int npen, int pstride, int p,
-                      const C2<T> *tw, int sgn) {
-  const int nbf = n / R;
-  const int total = npen * nbf;
-  const int m = n / (p * R);
-  const bool pen_fast = (pstride == 1);
-  C2<T> y[kMaxB][R];
-  int dst[kMaxB];
-#pragma unroll
-  for (int c = 0; c < kMaxB; ++c) {
-    const int i = threadIdx.x + c * blockDim.x;
-    dst[c] = -1;
-    if (i < total) {
-      int pen, bf;
-      if (pen_fast) {
-        pen = i % npen;
-        bf = i / npen;
-      } else {
-        bf = i % nbf;
-        pen = i / nbf;
-      }
-      const int base = pen * pstride;
-      C2<T> x[R];
-#pragma unroll
-      for (int t = 0; t < R; ++t) x[t] = buf[base + (bf + t * nbf) * estride];
-      const int k = bf % p;
-#pragma unroll
-      for (int t = 1; t < R; ++t) {
-        C2<T> w = tw[t * k * m];
-        if (sgn > 0) w.y = -w.y;
-        x[t] = cmul(x[t], w);
-      }
-      Dft<T, R>::run(x, sgn);
-#pragma unroll
-      for (int t = 0; t < R; ++t) y[c][t] = x[t];
-      dst[c] = base + ((bf - k) * R + k) * estride;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < kMaxB; ++c) {
-    if (dst[c] >= 0) {
-#pragma unroll
-      for (int t = 0; t < R; ++t) buf[dst[c] + t * p * estride] = y[c][t];
-    }
-  }
-  __syncthreads();
-}
-
-template <typename T>
-__device__ void lds_fft(C2<T> *buf, const Plan1D &pl, int estride, int npen, int pstride,
-                        const C2<T> *tw, int sgn) {
-  int p = 1;
-  for (int s = 0; s < pl.nstage; ++s) {
-    const int r = pl.radix[s];
-    if (r == 4)
-      stage<T, 4>(buf, pl.n, estride, npen, pstride, p, tw, sgn);
-    else if (r == 2)
-      stage<T, 2>(buf, pl.n, estride, npen, pstride, p, tw, sgn);
-    else if (r == 3)
-      stage<T, 3>(buf, pl.n, estride, npen, pstride, p, tw, sgn);
-    else
-      stage<T, 5>(buf, pl.n, estride, npen, pstride, p, tw, sgn);
-    p *= r;
-  }
-}
-
-template <typename T>
-__device__ void load_twiddles(C2<T> *dst, const double2 *src, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = to_c2<T>(src[i]);
-}
 
 // ---- pass A: sphere plane -> inverse xy FFT -> box plane -------------------
 template <typename T>
@@ -406,7 +236,10 @@ __global__ __launch_bounds__(256) void rho_accum_kernel(int64_t nbox, int nb, in
 // ---- compile-time specialised passes for cubic boxes ------------------------
 // Same three passes as above with the box edge N, the radix sequence, the
 // pencil strides and the thread count known at compile time, so that all
-// index arithmetic reduces to constant multiplies and shifts.
+// index arithmetic reduces to constant multiplies and shifts.  A plane sits in
+// LDS with a row stride of N + 1 elements, and the lanes of a wave take
+// consecutive pencils in both directions: pencils along a row are then an odd
+// stride apart, which spreads a wave's accesses over all LDS banks.
 template <int N> struct CPlan;
 #define CHEBFI_CPLAN(N_, NS_, R0_, R1_, R2_)                              \
   template <> struct CPlan<N_> {                                          \
@@ -445,14 +278,7 @@ __device__ __forceinline__ void cstage(C2<T> *buf, const C2<T> *tw) {
     const int i = threadIdx.x + c * kCT;
     dst[c] = -1;
     if (TOTAL % kCT == 0 || i < TOTAL) {
-      int pen, bf;
-      if (PS == 1) {
-        pen = i % NPEN;
-        bf = i / NPEN;
-      } else {
-        bf = i % NBF;
-        pen = i / NBF;
-      }
+      const int pen = i % NPEN, bf = i / NPEN;
       const int base = pen * PS;
       C2<T> x[R];
 #pragma unroll
@@ -498,31 +324,34 @@ __global__ __launch_bounds__(kCT) void cpass_a_kernel(const C2<T> *__restrict__ 
                                                       const int32_t *__restrict__ plane,
                                                       const double2 *__restrict__ twg,
                                                       C2<T> *__restrict__ box) {
-  constexpr int NXY = N * N;
-  __shared__ C2<T> buf[NXY];
+  constexpr int NXY = N * N, LD = N + 1;
+  __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
   const int i3 = blockIdx.x;
   const int bl = blockIdx.y;
   for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(twg[i]);
-  for (int i = threadIdx.x; i < NXY; i += kCT) buf[i] = C2<T>{0, 0};
+  for (int i = threadIdx.x; i < N * LD; i += kCT) buf[i] = C2<T>{0, 0};
   __syncthreads();
   const int s0 = plane[i3], s1 = plane[i3 + 1];
   const C2<T> *xb = X + (int64_t)(band0 + bl) * ldx;
   const int off = i3 * NXY;
-  for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) buf[box_index[idx] - off] = xb[idx];
+  for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
+    const int e = box_index[idx] - off;
+    buf[e + e / N] = xb[idx];
+  }
   __syncthreads();
-  cfft<T, N, 0, 1, N, 1, N, +1>(buf, tw);  // x: N pencils of stride-1 elements
-  cfft<T, N, 0, 1, N, N, 1, +1>(buf, tw);  // y
+  cfft<T, N, 0, 1, N, 1, LD, +1>(buf, tw);  // x: N pencils of stride-1 elements
+  cfft<T, N, 0, 1, N, LD, 1, +1>(buf, tw);  // y
   C2<T> *dst = box + (int64_t)bl * NXY * N + off;
-  for (int i = threadIdx.x; i < NXY; i += kCT) dst[i] = buf[i];
+  for (int i = threadIdx.x; i < NXY; i += kCT) dst[i] = buf[i + i / N];
 }
 
 template <typename T, typename VT, int N>
 __global__ __launch_bounds__(kCT) void cpass_b_kernel(C2<T> *__restrict__ box,
                                                       const VT *__restrict__ V,
                                                       const double2 *__restrict__ twg) {
-  constexpr int NXZ = N * N;
-  __shared__ C2<T> buf[NXZ];
+  constexpr int NXZ = N * N, LD = N + 1;
+  __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
   const int i2 = blockIdx.x;
   const int bl = blockIdx.y;
@@ -530,19 +359,19 @@ __global__ __launch_bounds__(kCT) void cpass_b_kernel(C2<T> *__restrict__ box,
   C2<T> *src = box + (int64_t)bl * N * N * N;
   for (int i = threadIdx.x; i < NXZ; i += kCT) {
     const int i1 = i % N, i3 = i / N;
-    buf[i] = src[i1 + N * (i2 + N * i3)];
+    buf[i3 * LD + i1] = src[i1 + N * (i2 + N * i3)];
   }
   __syncthreads();
-  cfft<T, N, 0, 1, N, N, 1, +1>(buf, tw);
+  cfft<T, N, 0, 1, N, LD, 1, +1>(buf, tw);
   for (int i = threadIdx.x; i < NXZ; i += kCT) {
     const int i1 = i % N, i3 = i / N;
-    buf[i] = cscale(buf[i], (T)V[i1 + N * (i2 + N * i3)]);
+    buf[i3 * LD + i1] = cscale(buf[i3 * LD + i1], (T)V[i1 + N * (i2 + N * i3)]);
   }
   __syncthreads();
-  cfft<T, N, 0, 1, N, N, 1, -1>(buf, tw);
+  cfft<T, N, 0, 1, N, LD, 1, -1>(buf, tw);
   for (int i = threadIdx.x; i < NXZ; i += kCT) {
     const int i1 = i % N, i3 = i / N;
-    src[i1 + N * (i2 + N * i3)] = buf[i];
+    src[i1 + N * (i2 + N * i3)] = buf[i3 * LD + i1];
   }
 }
 
@@ -553,18 +382,18 @@ __global__ __launch_bounds__(kCT) void cpass_c_kernel(
     const double *__restrict__ kin, int band0, const C2<T> *__restrict__ Yk, int64_t ldk,
     const C2<T> *__restrict__ Yprev, int64_t ldp, C2<T> *__restrict__ Out, int64_t ldo, T alpha,
     T cshift, T beta, T scale) {
-  constexpr int NXY = N * N;
-  __shared__ C2<T> buf[NXY];
+  constexpr int NXY = N * N, LD = N + 1;
+  __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
   const int i3 = blockIdx.x;
   const int bl = blockIdx.y;
   for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(twg[i]);
   const int off = i3 * NXY;
   const C2<T> *src = box + (int64_t)bl * NXY * N + off;
-  for (int i = threadIdx.x; i < NXY; i += kCT) buf[i] = src[i];
+  for (int i = threadIdx.x; i < NXY; i += kCT) buf[i + i / N] = src[i];
   __syncthreads();
-  cfft<T, N, 0, 1, N, N, 1, -1>(buf, tw);
-  cfft<T, N, 0, 1, N, 1, N, -1>(buf, tw);
+  cfft<T, N, 0, 1, N, LD, 1, -1>(buf, tw);
+  cfft<T, N, 0, 1, N, 1, LD, -1>(buf, tw);
   const int s0 = plane[i3], s1 = plane[i3 + 1];
   const int64_t b = band0 + bl;
   const C2<T> *yk = Yk + b * ldk;
@@ -572,7 +401,8 @@ __global__ __launch_bounds__(kCT) void cpass_c_kernel(
   if (Yprev != nullptr) {
     const C2<T> *yp = Yprev + b * ldp;
     for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
-      const C2<T> loc = cscale(buf[box_index[idx] - off], scale);
+      const int e = box_index[idx] - off;
+      const C2<T> loc = cscale(buf[e + e / N], scale);
       const C2<T> x = yk[idx];
       const T kd = (T)kin[idx] - cshift;
       const C2<T> h = cadd(loc, cscale(x, kd));
@@ -581,7 +411,8 @@ __global__ __launch_bounds__(kCT) void cpass_c_kernel(
     }
   } else {
     for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
-      const C2<T> loc = cscale(buf[box_index[idx] - off], scale);
+      const int e = box_index[idx] - off;
+      const C2<T> loc = cscale(buf[e + e / N], scale);
       const C2<T> x = yk[idx];
       const T kd = (T)kin[idx] - cshift;
       out[idx] = cscale(cadd(loc, cscale(x, kd)), alpha);
@@ -650,19 +481,6 @@ bool try_cubic(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Y
       return false;
   }
 #undef CHEBFI_CUBIC
-}
-
-int stage_threads(const Plan1D &pl, int npen) {
-  // smallest multiple of 64 threads with total butterflies <= kMaxB * threads
-  int need = 64;
-  for (int s = 0; s < pl.nstage; ++s) {
-    const int total = npen * (pl.n / pl.radix[s]);
-    const int t = (total + kMaxB - 1) / kMaxB;
-    if (t > need) need = t;
-  }
-  need = (need + 63) / 64 * 64;
-  if (need < 256) need = 256;
-  return need;
 }
 
 template <typename F> void set_lds(F kernel, size_t bytes) {
@@ -801,6 +619,10 @@ template void launch_adjoint_local<double>(const abi_system_s *, const void *, i
                                            int64_t, void *, int64_t, bool, int, int, void *,
                                            void *, const void *, double, double, double *,
                                            hipStream_t);
+template void launch_adjoint_local<float>(const abi_system_s *, const void *, int64_t, const void *,
+                                           int64_t, void *, int64_t, bool, int, int, void *,
+                                           void *, const void *, double, double, double *,
+                                           hipStream_t);
 
 template void launch_local_potential<double>(const abi_system_s *, const void *, int64_t,
                                              const void *, int64_t, void *, int64_t, int, int,
@@ -810,5 +632,7 @@ template void launch_local_potential<float>(const abi_system_s *, const void *, 
                                             const void *, int64_t, void *, int64_t, int, int,
                                             void *, const void *, double, double, double,
                                             hipStream_t, Profiler *);
+
+int fft_stage_threads(const Plan1D &pl, int npen) { return stage_threads(pl, npen); }
 
 }  // namespace chebfi

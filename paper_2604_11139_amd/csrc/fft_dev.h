@@ -1,0 +1,199 @@
+// Device building blocks of the LDS-resident FFTs: radix-2/3/4/5/6/8 DFTs in
+// registers, one Stockham stage over a set of pencils held in LDS, a 1D FFT
+// from a radix plan, twiddle loading; and the host rule for the thread count
+// of a stage.  Shared by the single-system passes and the batched passes.
+#pragma once
+
+#include "cplx.h"
+#include "internal.h"
+
+namespace chebfi {
+namespace {
+
+constexpr int kMaxB = 4;  // butterflies per thread per stage
+
+// Radix-R DFT in registers; sgn = -1 forward (e^{-}), +1 inverse (e^{+}).
+template <typename T, int R> struct Dft;
+
+template <typename T> struct Dft<T, 2> {
+  static __device__ __forceinline__ void run(C2<T> *x, int) {
+    C2<T> a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  }
+};
+
+template <typename T> struct Dft<T, 4> {
+  static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
+    C2<T> s02 = cadd(x[0], x[2]), d02 = csub(x[0], x[2]);
+    C2<T> s13 = cadd(x[1], x[3]), d13 = cmul_i(csub(x[1], x[3]), sgn);
+    x[0] = cadd(s02, s13);
+    x[2] = csub(s02, s13);
+    x[1] = cadd(d02, d13);
+    x[3] = csub(d02, d13);
+  }
+};
+
+template <typename T> struct Dft<T, 3> {
+  static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
+    const T h = (T)0.86602540378443864676;  // sin(2 pi / 3)
+    C2<T> t1 = cadd(x[1], x[2]);
+    C2<T> t2 = cmul_i(cscale(csub(x[1], x[2]), h), sgn);
+    C2<T> m = csub(x[0], cscale(t1, (T)0.5));
+    x[0] = cadd(x[0], t1);
+    x[1] = cadd(m, t2);
+    x[2] = csub(m, t2);
+  }
+};
+
+template <typename T> struct Dft<T, 5> {
+  static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
+    const T c1 = (T)0.30901699437494742410;   // cos(2 pi / 5)
+    const T c2 = (T)-0.80901699437494742410;  // cos(4 pi / 5)
+    const T s1 = (T)0.95105651629515357212;   // sin(2 pi / 5)
+    const T s2 = (T)0.58778525229247312917;   // sin(4 pi / 5)
+    C2<T> t1 = cadd(x[1], x[4]), t2 = cadd(x[2], x[3]);
+    C2<T> t3 = csub(x[1], x[4]), t4 = csub(x[2], x[3]);
+    C2<T> a1 = cadd(x[0], cadd(cscale(t1, c1), cscale(t2, c2)));
+    C2<T> a2 = cadd(x[0], cadd(cscale(t1, c2), cscale(t2, c1)));
+    C2<T> b1 = cmul_i(cadd(cscale(t3, s1), cscale(t4, s2)), sgn);
+    C2<T> b2 = cmul_i(csub(cscale(t3, s2), cscale(t4, s1)), sgn);
+    x[0] = cadd(x[0], cadd(t1, t2));
+    x[1] = cadd(a1, b1);
+    x[4] = csub(a1, b1);
+    x[2] = cadd(a2, b2);
+    x[3] = csub(a2, b2);
+  }
+};
+
+template <typename T> struct Dft<T, 6> {
+  // even/odd split: two radix-3 DFTs combined with w6^k = e^{sgn i pi k/3}
+  static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
+    C2<T> e[3] = {x[0], x[2], x[4]}, o[3] = {x[1], x[3], x[5]};
+    Dft<T, 3>::run(e, sgn);
+    Dft<T, 3>::run(o, sgn);
+    const T h = (T)0.86602540378443864676;
+    const C2<T> w1{(T)0.5, (T)sgn * h}, w2{(T)-0.5, (T)sgn * h};
+    const C2<T> t1 = cmul(o[1], w1), t2 = cmul(o[2], w2);
+    x[0] = cadd(e[0], o[0]);
+    x[3] = csub(e[0], o[0]);
+    x[1] = cadd(e[1], t1);
+    x[4] = csub(e[1], t1);
+    x[2] = cadd(e[2], t2);
+    x[5] = csub(e[2], t2);
+  }
+};
+
+template <typename T> struct Dft<T, 8> {
+  // even/odd split: two radix-4 DFTs combined with w8^k = e^{sgn i pi k/4}
+  static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
+    C2<T> e[4] = {x[0], x[2], x[4], x[6]}, o[4] = {x[1], x[3], x[5], x[7]};
+    Dft<T, 4>::run(e, sgn);
+    Dft<T, 4>::run(o, sgn);
+    const T c = (T)0.70710678118654752440;
+    const C2<T> t1{c * (o[1].x - sgn * o[1].y), c * (o[1].y + sgn * o[1].x)};
+    const C2<T> t2 = cmul_i(o[2], sgn);
+    const C2<T> t3{c * (-o[3].x - sgn * o[3].y), c * (-o[3].y + sgn * o[3].x)};
+    x[0] = cadd(e[0], o[0]);
+    x[4] = csub(e[0], o[0]);
+    x[1] = cadd(e[1], t1);
+    x[5] = csub(e[1], t1);
+    x[2] = cadd(e[2], t2);
+    x[6] = csub(e[2], t2);
+    x[3] = cadd(e[3], t3);
+    x[7] = csub(e[3], t3);
+  }
+};
+
+// One Stockham stage of radix R over `npen` pencils of length n held in LDS.
+// Element e of pencil q sits at buf[q*pstride + e*estride].  p is the product
+// of the radices already applied.
+template <typename T, int R>
+__device__ void stage(C2<T> *buf, int n, int estride, int npen, int pstride, int p,
+                      const C2<T> *tw, int sgn) {
+  const int nbf = n / R;
+  const int total = npen * nbf;
+  const int m = n / (p * R);
+  const bool pen_fast = (pstride == 1);
+  C2<T> y[kMaxB][R];
+  int dst[kMaxB];
+#pragma unroll
+  for (int c = 0; c < kMaxB; ++c) {
+    const int i = threadIdx.x + c * blockDim.x;
+    dst[c] = -1;
+    if (i < total) {
+      int pen, bf;
+      if (pen_fast) {
+        pen = i % npen;
+        bf = i / npen;
+      } else {
+        bf = i % nbf;
+        pen = i / nbf;
+      }
+      const int base = pen * pstride;
+      C2<T> x[R];
+#pragma unroll
+      for (int t = 0; t < R; ++t) x[t] = buf[base + (bf + t * nbf) * estride];
+      const int k = bf % p;
+#pragma unroll
+      for (int t = 1; t < R; ++t) {
+        C2<T> w = tw[t * k * m];
+        if (sgn > 0) w.y = -w.y;
+        x[t] = cmul(x[t], w);
+      }
+      Dft<T, R>::run(x, sgn);
+#pragma unroll
+      for (int t = 0; t < R; ++t) y[c][t] = x[t];
+      dst[c] = base + ((bf - k) * R + k) * estride;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < kMaxB; ++c) {
+    if (dst[c] >= 0) {
+#pragma unroll
+      for (int t = 0; t < R; ++t) buf[dst[c] + t * p * estride] = y[c][t];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void lds_fft(C2<T> *buf, const Plan1D &pl, int estride, int npen, int pstride,
+                        const C2<T> *tw, int sgn) {
+  int p = 1;
+  for (int s = 0; s < pl.nstage; ++s) {
+    const int r = pl.radix[s];
+    if (r == 4)
+      stage<T, 4>(buf, pl.n, estride, npen, pstride, p, tw, sgn);
+    else if (r == 2)
+      stage<T, 2>(buf, pl.n, estride, npen, pstride, p, tw, sgn);
+    else if (r == 3)
+      stage<T, 3>(buf, pl.n, estride, npen, pstride, p, tw, sgn);
+    else
+      stage<T, 5>(buf, pl.n, estride, npen, pstride, p, tw, sgn);
+    p *= r;
+  }
+}
+
+template <typename T>
+__device__ void load_twiddles(C2<T> *dst, const double2 *src, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = to_c2<T>(src[i]);
+}
+
+
+inline int stage_threads(const Plan1D &pl, int npen) {
+  // smallest multiple of 64 threads with total butterflies <= kMaxB * threads
+  int need = 64;
+  for (int s = 0; s < pl.nstage; ++s) {
+    const int total = npen * (pl.n / pl.radix[s]);
+    const int t = (total + kMaxB - 1) / kMaxB;
+    if (t > need) need = t;
+  }
+  need = (need + 63) / 64 * 64;
+  if (need < 256) need = 256;
+  return need;
+}
+
+}  // namespace
+}  // namespace chebfi

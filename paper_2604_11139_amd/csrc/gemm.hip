@@ -649,11 +649,37 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl_kernel(
       }
 }
 
+// Tile of this workgroup in the grid (tiles along x = rows, y = columns,
+// z = K chunks).  Workgroups are handed to the eight XCDs round robin by linear
+// id, so the first 8*floor(T/8) ids are remapped to give each XCD one
+// contiguous range of a linear tile order (the rest keep their id).  That order
+// runs over K chunks slowest, then over groups of `gm` row panels; within a
+// group the row panel varies fastest, then the column.  The workgroups an XCD
+// runs together then share a few A and B panels in its L2.
+__device__ __forceinline__ void grouped_tile(unsigned gm, unsigned &tm, unsigned &tn,
+                                             unsigned &tz) {
+  const unsigned ntm = gridDim.x, ntn = gridDim.y;
+  const unsigned lid = blockIdx.x + ntm * (blockIdx.y + ntn * blockIdx.z);
+  const unsigned q = (ntm * ntn * gridDim.z) >> 3;
+  const unsigned L = lid < 8u * q ? (lid & 7u) * q + (lid >> 3) : lid;
+  const unsigned per_z = ntm * ntn;
+  tz = L / per_z;
+  const unsigned r = L - tz * per_z;
+  const unsigned g = r / (gm * ntn);
+  const unsigned rows = min(gm, ntm - g * gm);
+  const unsigned rr = r - g * gm * ntn;
+  tm = g * gm + rr % rows;
+  tn = rr / rows;
+}
+
 // Double-buffered form of the planes x planes kernel: two LDS stages of
 // 32-element K slices without padding; the 16-byte chunk kc of row i is
-// stored at chunk position kc ^ ((i >> 2) & 3), which keeps the 16-lane
-// ds_read_b128 groups on distinct banks.  One barrier per K step: the next
-// slice is written into the other stage while this one is multiplied.
+// stored at chunk position kc ^ ((i >> 1) & 3).  With that swizzle the
+// 128-bit fragment reads (16 rows x 4 chunks per wave) and the staging
+// writes (four lanes per row, consecutive rows of one plane) are free of
+// bank conflicts on gfx950 (measured with the LDS conflict counters).  One
+// barrier per K step: the next slice is written into the other stage while
+// this one is multiplied.
 template <int BM, int BN, int NWM, int NWN, bool CONJ, bool SPLIT>
 __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl2_kernel(
     int64_t m, int64_t n, int64_t k, const u16 *__restrict__ Apl, int64_t lda, int64_t psa,
@@ -667,21 +693,10 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl2_kernel(
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % NWM, wn = wave / NWM;
-  const unsigned ntn = gridDim.y, ntm = gridDim.x;
-  const unsigned wid = blockIdx.x + ntm * blockIdx.y;
-  const unsigned full = ntm & ~7u;
-  unsigned tm, tn;
-  if (wid < full * ntn) {
-    const unsigned xcd = wid & 7u, loc = wid >> 3;
-    tm = (loc / ntn) * 8u + xcd;
-    tn = loc % ntn;
-  } else {
-    const unsigned r = wid - full * ntn, rest = ntm - full;
-    tm = full + r % rest;
-    tn = r / rest;
-  }
+  unsigned tm, tn, tz;
+  grouped_tile(SPLIT ? gridDim.x : 4u, tm, tn, tz);
   const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
-  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kbeg = (int64_t)tz * kchunk;
   const int64_t kend = (kbeg + kchunk < k) ? kbeg + kchunk : k;
 
   v4f acc[SM][SN][2];
@@ -694,13 +709,15 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl2_kernel(
     }
 
   uint4 ra[CA], rb[CB];
+  // chunk idx of a staged slice with R rows: K chunk idx & 3, row
+  // (idx >> 2) % R, plane (idx >> 2) / R
   auto load_chunk = [&](const u16 *base, int64_t ld, int64_t ps, int64_t lim, int idx,
-                        int64_t r0, int64_t k0) -> uint4 {
-    const int kc = idx & 3, rr = (idx >> 2), i = rr >> 2;
+                        int64_t r0, int64_t k0, int R) -> uint4 {
+    const int kc = idx & 3, i = (idx >> 2) % R, pl = (idx >> 2) / R;
     const int64_t gr = r0 + i, ks = k0 + 8 * kc;
     uint4 v = make_uint4(0, 0, 0, 0);
     if (gr < lim && ks < kend) {
-      const u16 *src = base + (int64_t)(rr & 3) * ps + gr * ld + ks;
+      const u16 *src = base + (int64_t)pl * ps + gr * ld + ks;
       if (ks + 8 <= kend) {
         v = *reinterpret_cast<const uint4 *>(src);
       } else {
@@ -714,20 +731,22 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl2_kernel(
   };
   auto load_tiles = [&](int64_t k0) {
 #pragma unroll
-    for (int c = 0; c < CA; ++c) ra[c] = load_chunk(Apl, lda, psa, m, tid + NT * c, row0, k0);
+    for (int c = 0; c < CA; ++c)
+      ra[c] = load_chunk(Apl, lda, psa, m, tid + NT * c, row0, k0, BM);
 #pragma unroll
-    for (int c = 0; c < CB; ++c) rb[c] = load_chunk(Bpl, ldb, psb, n, tid + NT * c, col0, k0);
+    for (int c = 0; c < CB; ++c)
+      rb[c] = load_chunk(Bpl, ldb, psb, n, tid + NT * c, col0, k0, BN);
   };
   auto store_tiles = [&](int st) {
 #pragma unroll
     for (int c = 0; c < CA; ++c) {
-      const int idx = tid + NT * c, kc = idx & 3, rr = idx >> 2, i = rr >> 2;
-      *reinterpret_cast<uint4 *>(&As[st][rr & 3][i][8 * (kc ^ ((i >> 2) & 3))]) = ra[c];
+      const int idx = tid + NT * c, kc = idx & 3, i = (idx >> 2) % BM, pl = (idx >> 2) / BM;
+      *reinterpret_cast<uint4 *>(&As[st][pl][i][8 * (kc ^ ((i >> 1) & 3))]) = ra[c];
     }
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
-      const int idx = tid + NT * c, kc = idx & 3, rr = idx >> 2, i = rr >> 2;
-      *reinterpret_cast<uint4 *>(&Bs[st][rr & 3][i][8 * (kc ^ ((i >> 2) & 3))]) = rb[c];
+      const int idx = tid + NT * c, kc = idx & 3, i = (idx >> 2) % BN, pl = (idx >> 2) / BN;
+      *reinterpret_cast<uint4 *>(&Bs[st][pl][i][8 * (kc ^ ((i >> 1) & 3))]) = rb[c];
     }
   };
 
@@ -745,7 +764,7 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl2_kernel(
 #pragma unroll
     for (int i = 0; i < SM; ++i) {
       const int ii = wm * (BM / NWM) + i * 16 + (lane & 15);
-      const int kb = 8 * (kq ^ ((ii >> 2) & 3));
+      const int kb = 8 * (kq ^ ((ii >> 1) & 3));
 #pragma unroll
       for (int p = 0; p < 4; ++p) a[i][p] = *reinterpret_cast<const v8bf *>(&As[cur][p][ii][kb]);
       if (CONJ) {
@@ -756,7 +775,7 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl2_kernel(
 #pragma unroll
     for (int j = 0; j < SN; ++j) {
       const int jj = wn * (BN / NWN) + j * 16 + (lane & 15);
-      const int kb = 8 * (kq ^ ((jj >> 2) & 3));
+      const int kb = 8 * (kq ^ ((jj >> 1) & 3));
 #pragma unroll
       for (int p = 0; p < 4; ++p) b[j][p] = *reinterpret_cast<const v8bf *>(&Bs[cur][p][jj][kb]);
       if (!CONJ) {
@@ -812,7 +831,7 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl2_kernel(
         if (row < m && col < n) {
           const float2 v{acc[i][j][0][r], acc[i][j][1][r]};
           if (SPLIT) {
-            part[(int64_t)blockIdx.z * m * n + row + col * m] = v;
+            part[(int64_t)tz * m * n + row + col * m] = v;
           } else {
             float2 o = C[row + col * ldc];
             o.x += v.x;

@@ -82,7 +82,8 @@ enum ProfClass {
   PROF_CHOL = 7,     // Cholesky + triangular inverse + reduction to U^-H H_s U^-1
   PROF_EIG = 8,      // Hermitian eigensolver
   PROF_ROT = 9,      // Psi = Y W, H Psi = (H Y) W
-  PROF_NCLASS = 10
+  PROF_SPLIT = 10,   // complex64 block -> bf16 hi/lo planes (split-BF16 products)
+  PROF_NCLASS = 11
 };
 
 struct Profiler {
@@ -107,6 +108,50 @@ struct Profiler {
 };
 void reciprocal(const double lattice[9], double B[9]);
 void build_projectors(const abi_system_desc *d, const Sphere &s, std::vector<double> *P);
+
+// ---- batched filter over many systems ---------------------------------------
+constexpr int kBatchMaxProj = 32;  // projectors per system in the batched path (8 atoms)
+constexpr int kBatchMaxSys = 1024;
+
+// Per-system device descriptor of the batched passes (plain data).
+struct BatchSys {
+  BoxPlan plan;               // radix order chosen for the batch
+  int64_t npw = 0;
+  int nproj = 0;
+  const int32_t *box_index = nullptr;
+  const int32_t *plane = nullptr;
+  const double *kin = nullptr;
+  const void *V = nullptr;    // float (complex64 blocks) or double
+  const double2 *tw = nullptr;
+  const void *P = nullptr;    // npw x nproj complex float or double, column-major
+  const double2 *D = nullptr;
+  void *box = nullptr;        // nband boxes
+  void *Cp = nullptr;         // nproj x nband
+};
+
+// Per (filter step, system): Out = alpha (H - cshift) Y_k - beta Y_prev.
+struct BatchStep {
+  const void *yk = nullptr;
+  int64_t ldk = 0;
+  const void *yprev = nullptr;  // NULL on the first step
+  int64_t ldp = 0;
+  void *out = nullptr;
+  int64_t ldo = 0;
+  double alpha = 0, cshift = 0, beta = 0;
+};
+
+// What one batched step launches (device pointers and launch shapes).
+struct BatchLaunch {
+  int nsys = 0;
+  const BatchSys *d_sys = nullptr;
+  const BatchStep *d_steps = nullptr;  // degree x nsys
+  const int64_t *d_off = nullptr;      // prefix offsets: bands, bands*n3, bands*n2
+  int64_t items_p = 0, items_a = 0, items_b = 0;
+  int max_wgs = 2048;
+  int fft_threads = 256, proj_threads = 256;
+  size_t lds_a = 0, lds_b = 0, lds_c = 0;  // dynamic LDS of the passes, in elements
+  bool any_proj = false;
+};
 
 }  // namespace chebfi
 

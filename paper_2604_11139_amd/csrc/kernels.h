@@ -67,7 +67,7 @@ void expand_gemm_bf16x3(int64_t npw, int64_t nband, int64_t nproj, const void *A
 // (column j = band j, contraction index contiguous, stride ld, plane stride ps).
 void split_planes(int64_t rows, int64_t cols, const void *X, int64_t ld, void *planes,
                   int64_t ldp, hipStream_t st);
-// `variant` selects the tile shape (0..3, see gemm.hip); proj_planes_splits
+// `variant` selects the tile shape (0..4, see gemm.hip); proj_planes_splits
 // gives the K split count that fills the chip for that shape.
 int proj_planes_splits(int variant, int64_t nproj, int64_t nband, int64_t npw);
 void proj_gemm_planes(int64_t nproj, int64_t nband, int64_t npw, const void *Apl, int64_t lda,
@@ -119,12 +119,16 @@ void launch_scale_inv(int64_t npw, const double *s, const void *x, void *y, hipS
 void launch_tridiag_bound(int k, const double *alpha, const double *beta, int add_last,
                           double *out, hipStream_t st);
 
-// dD[R][i][j] += gamma sum_b CA[4R+i, b] conj(CY[4R+j, b])  (raw projections)
+// dD[R][i][j] += gamma sum_b CA[4R+i, b] conj(CY[4R+j, b])  (raw projections,
+// complex double or, with fp32, complex float; dD is complex double)
 void launch_dd_accum(int natom, int64_t nband, const void *CA, const void *CY, double gamma,
-                     void *dD, hipStream_t st);
-// out = -delta * in  (complex double blocks)
+                     void *dD, hipStream_t st, bool fp32 = false);
+// out = -delta * in  (complex double or, with fp32, complex float blocks)
 void launch_scale_neg(int64_t npw, int64_t nband, const void *in, int64_t ldi, double delta,
-                      void *out, int64_t ldo, hipStream_t st);
+                      void *out, int64_t ldo, hipStream_t st, bool fp32 = false);
+// out (m x n, contiguous) = sum over the `splits` partial products of a split-K GEMM
+void launch_sum_parts(int64_t m, int64_t n, const void *part, int splits, void *out,
+                      hipStream_t st, bool fp32);
 void launch_fill_zero(int64_t count_doubles, double *p, hipStream_t st);
 void launch_d2f(int64_t n, const double *src, float *dst, hipStream_t st);
 
@@ -136,7 +140,7 @@ void launch_residual_norms(int64_t npw, int64_t nband, const void *Psi, int64_t 
 // dense helpers (m x m complex double)
 void launch_hermitize(int64_t m, void *A, int64_t lda, hipStream_t st);  // A = (A + A^H)/2
 void launch_copy_block(int64_t rows, int64_t cols, const void *src, int64_t lds, void *dst,
-                       int64_t ldd, hipStream_t st);
+                       int64_t ldd, hipStream_t st, bool fp32 = false);
 void launch_zero_lower(int64_t m, void *A, int64_t lda, hipStream_t st);
 
 // ---- dense.hip ----------------------------------------------------------------
@@ -151,5 +155,15 @@ size_t ztrtri_work_bytes(int64_t m);
 void zheev(int64_t m, void *A, int64_t lda, double *w, void *Z, int64_t ldz, void *work,
            hipStream_t st);
 size_t zheev_work_bytes(int64_t m);
+
+// Threads per workgroup that one Stockham stage over npen pencils of the plan needs.
+int fft_stage_threads(const Plan1D &pl, int npen);
+
+// ---- batch.hip ------------------------------------------------------------------
+// One filter step (index j of the step table) of every system of a batch:
+// projection + D, FFT passes A, B, C (with expansion and recurrence).
+template <typename T> void batch_step(const BatchLaunch &L, int j, hipStream_t st);
+// Sets the dynamic LDS limits of the batched kernels (call outside graph capture).
+template <typename T> void batch_prepare(const BatchLaunch &L);
 
 }  // namespace chebfi

@@ -257,8 +257,9 @@ __global__ void hermitize_kernel(int64_t m, double2 *__restrict__ A, int64_t lda
   A[j + i * lda] = double2{v.x, -v.y};
 }
 
-__global__ void copy_block_kernel(int64_t rows, int64_t cols, const double2 *__restrict__ src,
-                                  int64_t lds, double2 *__restrict__ dst, int64_t ldd) {
+template <typename V2>
+__global__ void copy_block_kernel(int64_t rows, int64_t cols, const V2 *__restrict__ src,
+                                  int64_t lds, V2 *__restrict__ dst, int64_t ldd) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= rows * cols) return;
   const int64_t i = idx % rows, j = idx / rows;
@@ -272,10 +273,11 @@ __global__ void zero_lower_kernel(int64_t m, double2 *__restrict__ A, int64_t ld
   if (i > j) A[i + j * lda] = double2{0, 0};
 }
 
-// One workgroup per atom: 16 complex sums over the bands.
+// One workgroup per atom: 16 complex sums over the bands (in FP64).
+template <typename T>
 __global__ __launch_bounds__(256) void dd_accum_kernel(int natom, int64_t nband,
-                                                       const double2 *__restrict__ CA,
-                                                       const double2 *__restrict__ CY, double gamma,
+                                                       const C2<T> *__restrict__ CA,
+                                                       const C2<T> *__restrict__ CY, double gamma,
                                                        double2 *__restrict__ dD) {
   __shared__ double scratch[16];
   const int R = blockIdx.x;
@@ -287,8 +289,9 @@ __global__ __launch_bounds__(256) void dd_accum_kernel(int natom, int64_t nband,
     double2 a[4], y[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      a[i] = CA[(4 * R + i) + b * np];
-      y[i] = CY[(4 * R + i) + b * np];
+      const C2<T> u = CA[(4 * R + i) + b * np], v = CY[(4 * R + i) + b * np];
+      a[i] = double2{(double)u.x, (double)u.y};
+      y[i] = double2{(double)v.x, (double)v.y};
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -311,14 +314,31 @@ __global__ __launch_bounds__(256) void dd_accum_kernel(int natom, int64_t nband,
   }
 }
 
-__global__ void scale_neg_kernel(int64_t npw, int64_t nband, const double2 *__restrict__ in,
-                                 int64_t ldi, double delta, double2 *__restrict__ out,
+template <typename T>
+__global__ void scale_neg_kernel(int64_t npw, int64_t nband, const C2<T> *__restrict__ in,
+                                 int64_t ldi, double delta, C2<T> *__restrict__ out,
                                  int64_t ldo) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= npw * nband) return;
   const int64_t i = idx % npw, b = idx / npw;
-  const double2 v = in[i + b * ldi];
-  out[i + b * ldo] = double2{-delta * v.x, -delta * v.y};
+  const C2<T> v = in[i + b * ldi];
+  const T d = (T)delta;
+  out[i + b * ldo] = C2<T>{-d * v.x, -d * v.y};
+}
+
+// out[i + j m] = sum_z part[z][i + j m] (summed in FP64, in z order).
+template <typename T>
+__global__ void sum_parts_kernel(int64_t mn, int splits, const C2<T> *__restrict__ part,
+                                 C2<T> *__restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= mn) return;
+  double sx = 0.0, sy = 0.0;
+  for (int z = 0; z < splits; ++z) {
+    const C2<T> v = part[(int64_t)z * mn + idx];
+    sx += (double)v.x;
+    sy += (double)v.y;
+  }
+  out[idx] = C2<T>{(T)sx, (T)sy};
 }
 
 __global__ void fill_zero_kernel(int64_t n, double *__restrict__ p) {
@@ -336,17 +356,38 @@ inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 }  // namespace
 
 void launch_dd_accum(int natom, int64_t nband, const void *CA, const void *CY, double gamma,
-                     void *dD, hipStream_t st) {
+                     void *dD, hipStream_t st, bool fp32) {
   if (natom <= 0) return;
-  hipLaunchKernelGGL(dd_accum_kernel, dim3((unsigned)natom), dim3(256), 0, st, natom, nband,
-                     (const double2 *)CA, (const double2 *)CY, gamma, (double2 *)dD);
+  if (fp32)
+    hipLaunchKernelGGL(dd_accum_kernel<float>, dim3((unsigned)natom), dim3(256), 0, st, natom,
+                       nband, (const float2 *)CA, (const float2 *)CY, gamma, (double2 *)dD);
+  else
+    hipLaunchKernelGGL(dd_accum_kernel<double>, dim3((unsigned)natom), dim3(256), 0, st, natom,
+                       nband, (const double2 *)CA, (const double2 *)CY, gamma, (double2 *)dD);
   CHEBFI_HIP(hipGetLastError());
 }
 
 void launch_scale_neg(int64_t npw, int64_t nband, const void *in, int64_t ldi, double delta,
-                      void *out, int64_t ldo, hipStream_t st) {
-  hipLaunchKernelGGL(scale_neg_kernel, dim3(nblk(npw * nband, 256)), dim3(256), 0, st, npw, nband,
-                     (const double2 *)in, ldi, delta, (double2 *)out, ldo);
+                      void *out, int64_t ldo, hipStream_t st, bool fp32) {
+  if (fp32)
+    hipLaunchKernelGGL(scale_neg_kernel<float>, dim3(nblk(npw * nband, 256)), dim3(256), 0, st,
+                       npw, nband, (const float2 *)in, ldi, delta, (float2 *)out, ldo);
+  else
+    hipLaunchKernelGGL(scale_neg_kernel<double>, dim3(nblk(npw * nband, 256)), dim3(256), 0, st,
+                       npw, nband, (const double2 *)in, ldi, delta, (double2 *)out, ldo);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_sum_parts(int64_t m, int64_t n, const void *part, int splits, void *out,
+                      hipStream_t st, bool fp32) {
+  const int64_t mn = m * n;
+  if (mn <= 0) return;
+  if (fp32)
+    hipLaunchKernelGGL(sum_parts_kernel<float>, dim3(nblk(mn, 256)), dim3(256), 0, st, mn, splits,
+                       (const float2 *)part, (float2 *)out);
+  else
+    hipLaunchKernelGGL(sum_parts_kernel<double>, dim3(nblk(mn, 256)), dim3(256), 0, st, mn,
+                       splits, (const double2 *)part, (double2 *)out);
   CHEBFI_HIP(hipGetLastError());
 }
 
@@ -470,10 +511,14 @@ void launch_hermitize(int64_t m, void *A, int64_t lda, hipStream_t st) {
 }
 
 void launch_copy_block(int64_t rows, int64_t cols, const void *src, int64_t lds, void *dst,
-                       int64_t ldd, hipStream_t st) {
+                       int64_t ldd, hipStream_t st, bool fp32) {
   if (rows * cols <= 0) return;
-  hipLaunchKernelGGL(copy_block_kernel, dim3(nblk(rows * cols, 256)), dim3(256), 0, st, rows,
-                     cols, (const double2 *)src, lds, (double2 *)dst, ldd);
+  if (fp32)
+    hipLaunchKernelGGL(copy_block_kernel<float2>, dim3(nblk(rows * cols, 256)), dim3(256), 0, st,
+                       rows, cols, (const float2 *)src, lds, (float2 *)dst, ldd);
+  else
+    hipLaunchKernelGGL(copy_block_kernel<double2>, dim3(nblk(rows * cols, 256)), dim3(256), 0, st,
+                       rows, cols, (const double2 *)src, lds, (double2 *)dst, ldd);
   CHEBFI_HIP(hipGetLastError());
 }
 

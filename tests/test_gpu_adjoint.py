@@ -8,7 +8,13 @@
   directional derivative <= 1e-6 for V (16 directions), D real and imaginary
   parts and X (the FD error budget: h^2 L''' + eps |L| / h is below 1e-7 of
   the derivatives measured here);
-* the torch.autograd.Function returns the same gradients.
+* the torch.autograd.Function returns the same gradients;
+* the mixed form (complex64 blocks on a mixed-precision handle) against the
+  oracle run on the complex64-rounded inputs: max |diff| <= 1e-5 x degree x
+  max |ref| for dV, dD and dX.  The forward filter's per-step budget is 5e-6
+  (FP32 recurrence and FFT, split-BF16 products); the adjoint recomputes the
+  forward iterates and runs a reverse recurrence of the same length, and dV,
+  dD are bilinear in the two, hence twice the forward budget.
 """
 import numpy as np
 import pytest
@@ -148,3 +154,68 @@ def test_autograd_function():
     assert _rel(V.grad.cpu().numpy(), dV) <= 1e-9
     assert _rel(D.grad.cpu().numpy(), dD) <= 1e-9
     assert _rel(to_host(Xd.grad), dX) <= 1e-9
+
+
+def _c64(Z):
+    return Z.astype(np.complex64).astype(np.complex128)
+
+
+@pytest.mark.parametrize("name,degree", [("tiny_k", 1), ("odd15", 3), ("n27", 5), ("c1", 8)])
+def test_backward_mixed_matches_oracle(name, degree):
+    import torch
+    H = hamiltonian(name)
+    s = system(name)
+    X = _c64(W.random_block(H.npw, s.nband, s.tag))
+    Wt = _c64(W.random_block(H.npw, s.nband, s.tag, stream=W.systems.WBLOCK))
+    v0 = W.random_vector(H.npw, s.tag)
+    a, b, a0 = O.filter_bounds(H, X, v0)
+    dV, dD, dX = O.filter_backward(H, X, Wt, degree, a, b, a0)
+    with B.System(s, precision=B.ABI_PREC_MIXED) as g:
+        Xd = to_dev(X).to(torch.complex64)
+        Wd = to_dev(Wt).to(torch.complex64)
+        gV, gD, gX = g.filter_backward(Xd, Wd, degree, a, b, a0, ckpt_every=2)
+        assert gX.dtype == torch.complex64
+    tol = 1e-5 * degree
+    assert _rel(gV.cpu().numpy(), dV) <= tol
+    assert _rel(gD.cpu().numpy(), dD) <= tol
+    assert _rel(to_host(gX).astype(np.complex128), dX) <= tol
+
+
+def test_mixed_checkpoint_interval_is_bitwise_neutral():
+    import torch
+    H = hamiltonian("n27")
+    s = system("n27")
+    X = W.random_block(H.npw, s.nband, 15)
+    Wt = W.random_block(H.npw, s.nband, 16)
+    a, b, a0 = 0.5, 9.0, -1.5
+    outs = []
+    with B.System(s, precision=B.ABI_PREC_MIXED) as g:
+        Xd = to_dev(X).to(torch.complex64)
+        Wd = to_dev(Wt).to(torch.complex64)
+        for ck in (0, 1, 3):
+            gV, gD, gX = g.filter_backward(Xd, Wd, 6, a, b, a0, ckpt_every=ck)
+            outs.append((gV.cpu().numpy(), gD.cpu().numpy(), to_host(gX)))
+    for o in outs[1:]:
+        for x, y in zip(o, outs[0]):
+            assert np.array_equal(x, y)
+
+
+def test_autograd_function_mixed():
+    import torch
+    H = hamiltonian("n27")
+    s = system("n27")
+    X = _c64(W.random_block(H.npw, s.nband, 18))
+    Wt = _c64(W.random_block(H.npw, s.nband, 19))
+    a, b, a0 = 0.5, 9.0, -1.5
+    dV, dD, dX = O.filter_backward(H, X, Wt, 6, a, b, a0)
+    with B.System(s, precision=B.ABI_PREC_MIXED) as g:
+        Xd = to_dev(X).to(torch.complex64).requires_grad_(True)
+        V = torch.from_numpy(s.vloc).cuda().requires_grad_(True)
+        D = torch.from_numpy(s.dij).cuda().requires_grad_(True)
+        Y = B.cheb_filter_autograd(Xd, V, D, g, 6, a, b, a0, 3)
+        assert Y.dtype == torch.complex64
+        L = (to_dev(Wt).to(torch.complex64).conj() * Y).sum().real
+        L.backward()
+    assert _rel(V.grad.cpu().numpy(), dV) <= 6e-5
+    assert _rel(D.grad.cpu().numpy(), dD) <= 6e-5
+    assert _rel(to_host(Xd.grad).astype(np.complex128), dX) <= 6e-5

@@ -10,7 +10,12 @@ call); the oracle checks sampled outputs it can compute one by one:
   a and a0 must bracket the Rayleigh quotients of sampled bands;
 * Rayleigh-Ritz: for sampled Ritz vectors the oracle recomputes the Rayleigh
   quotient psi^H H psi (= the Ritz value, <= 1e-8 Ha) and the residual norm
-  (= the GPU's, <= 1e-8); sampled columns are orthonormal to 1e-10.
+  (= the GPU's, <= 1e-8); sampled columns are orthonormal to 1e-10;
+* adjoint of the filter (checkpoints every 4th step): the loss is a sum over
+  bands and the filter acts band by band, so with W supported on the sampled
+  columns the oracle's adjoint of those columns alone gives the exact dV, dD
+  and dX (FP64 <= 1e-9, mixed <= 1e-5 x degree of max |ref|); the other
+  columns of dX must be exactly zero.
 """
 import functools
 
@@ -96,3 +101,42 @@ def test_rayleigh_ritz_fullsize_properties():
     r = np.linalg.norm(HPsi - Psi * ev[cols][None, :], axis=0)
     assert np.abs(r - res[cols]).max() <= 1e-8
     assert np.abs(Psi.conj().T @ Psi - np.eye(len(cols))).max() <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_adjoint_sampled_columns(precision):
+    import torch
+    s, H, X, v0 = _case()
+    mixed = precision == "mixed"
+    prec = B.ABI_PREC_MIXED if mixed else B.ABI_PREC_FP64
+    Wc = W.random_block(H.npw, len(COLS), s.tag, stream=W.systems.WBLOCK)
+    Xs = X[:, COLS]
+    if mixed:
+        Wc = Wc.astype(np.complex64).astype(np.complex128)
+        Xs = Xs.astype(np.complex64).astype(np.complex128)
+    with B.System(s, precision=prec) as g:
+        Xd = to_dev(X)
+        bounds = g.spectral_bounds(Xd, to_dev(v0))
+        Wd = torch.zeros_like(Xd)
+        Wd[COLS] = to_dev(Wc)
+        if mixed:
+            Xd = Xd.to(torch.complex64)
+            Wd = Wd.to(torch.complex64)
+        gV, gD, gX = g.filter_backward(Xd, Wd, s.degree, *bounds, ckpt_every=4)
+        del Xd, Wd
+        gV = gV.cpu().numpy()
+        gD = gD.cpu().numpy()
+        keep = torch.ones(s.nband, dtype=torch.bool, device=gX.device)
+        keep[COLS] = False
+        assert int(torch.count_nonzero(gX[keep]).item()) == 0
+        gXs = gX[COLS].cpu().numpy().T.astype(np.complex128)
+        del gX
+    dV, dD, dX = O.filter_backward(H, Xs, Wc, s.degree, *bounds)
+    tol = 1e-5 * s.degree if mixed else 1e-9
+
+    def rel(got, ref):
+        return float(np.abs(got - ref).max() / np.abs(ref).max())
+
+    assert rel(gV, dV) <= tol
+    assert rel(gD, dD) <= tol
+    assert rel(gXs, dX) <= tol

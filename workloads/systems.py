@@ -179,6 +179,44 @@ def make_system(
     )
 
 
+# The batched workload: independent small cells with k-point offsets (uneven
+# plane-wave counts), as many k-points and cells handled in one launch.
+BATCH = dict(tag=4, nsys=16, a=(8, 16), ecut=12.0, natom=(1, 8), nband=(32, 64, 128, 256),
+             degree=8)
+BATCH_TAG0 = 4000  # system i of the batch draws from tag BATCH_TAG0 + i
+
+
+def smooth_235(m: int) -> int:
+    """Smallest integer >= m whose only prime factors are 2, 3 and 5."""
+    n = max(int(m), 1)
+    while True:
+        r = n
+        for p in (2, 3, 5):
+            while r % p == 0:
+                r //= p
+        if r == 1:
+            return n
+        n += 1
+
+
+def make_batch(nsys: Optional[int] = None) -> list:
+    """The batched workload: `nsys` (16) cubic cells, a ~ U{8..16} bohr,
+    E_cut 12 Ha, k ~ U[0, 0.5)^3 (reduced), grid n = smallest {2,3,5}-smooth
+    >= 3a, 1-8 atoms, nband in {32, 64, 128, 256}, degree 8."""
+    nsys = BATCH["nsys"] if nsys is None else int(nsys)
+    rng = streams(BATCH["tag"])[EXTRA]
+    out = []
+    for i in range(nsys):
+        a = int(rng.integers(BATCH["a"][0], BATCH["a"][1] + 1))
+        k = rng.uniform(0.0, 0.5, size=3)
+        natom = int(rng.integers(BATCH["natom"][0], BATCH["natom"][1] + 1))
+        nband = int(rng.choice(BATCH["nband"]))
+        out.append(make_system(BATCH_TAG0 + i, a=float(a), ecut=BATCH["ecut"],
+                               n=smooth_235(3 * a), natom=natom, nband=nband,
+                               degree=BATCH["degree"], cycles=1, kpt_red=tuple(k)))
+    return out
+
+
 def random_block(npw: int, nband: int, tag: int, stream: int = XBLOCK) -> np.ndarray:
     """complex128 (npw, nband), column-major, N(0,1) real and imaginary parts."""
     rng = streams(tag)[stream]
