@@ -46,7 +46,83 @@ def parse():
                     help="run one device copy of this many MiB first (counter calibration)")
     ap.add_argument("--cpu-bands", type=int, default=160,
                     help="bands in the oracle's timed sample (0 skips the CPU baseline)")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the measured copy / vendor-GEMM ceilings")
     return ap.parse_args()
+
+
+# kernel class -> (kernel name in the counter summary, source file it is built from)
+CLASS_KERNELS = {
+    "proj_gemm": ("zgemm_pl2_kernel<128, 128, 2, 4, true, true, 1>", "gemm.hip"),
+    "expand_gemm": ("zgemm_pl2_kernel<128, 128, 2, 4, false, false, 1>", "gemm.hip"),
+    "fft_a": ("cpass_a_kernel<float, 64>", "fft.hip"),
+    "fft_b": ("cpass_b_kernel<float, float, 64>", "fft.hip"),
+    "fft_c": ("cpass_c_kernel<float, 64>", "fft.hip"),
+    "split": ("split_planes_kernel", "gemm.hip"),
+}
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_config3_mixed.md")
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of the class's kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
+    for a plain device copy of known size), or None if there is none or the
+    kernel's source has changed since the counters were taken."""
+    import hashlib
+    import re
+    if cls not in CLASS_KERNELS or not os.path.exists(COUNTERS_FILE):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(COUNTERS_FILE).read(), re.S)
+    if not m:
+        return None
+    data = json.loads(m.group(1))
+    kname, src = CLASS_KERNELS[cls]
+    path = os.path.join(ROOT, "paper_2604_11139_amd", "csrc", src)
+    sha = hashlib.sha256(open(path, "rb").read()).hexdigest()
+    if data.get("source_sha256", {}).get(src) != sha:
+        return None
+    k = data.get("kernels", {}).get(kname)
+    if not k:
+        return None
+    return float(k["hbm_bytes_per_dispatch"])
+
+
+def ceilings():
+    """Practical ceilings of this GPU, for context beside the published peaks:
+    a 2 GiB device copy (HBM), torch's bf16 and fp64 GEMMs (the vendor BLAS)."""
+    import torch
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    t = timed(lambda: dst.copy_(src), 5)
+    out = {"hbm_copy_gbs": round(2 * 8 * n / t / 1e9, 1)}
+    del src, dst
+    a = torch.randn(8192, 8192, device="cuda", dtype=torch.bfloat16)
+    b = torch.randn(8192, 8192, device="cuda", dtype=torch.bfloat16)
+    t = timed(lambda: a @ b, 10)
+    out["bf16_gemm_tflops"] = round(2 * 8192 ** 3 / t / 1e12, 1)
+    del a, b
+    a = torch.randn(4096, 4096, device="cuda", dtype=torch.float64)
+    b = torch.randn(4096, 4096, device="cuda", dtype=torch.float64)
+    t = timed(lambda: a @ b, 5)
+    out["fp64_gemm_tflops"] = round(2 * 4096 ** 3 / t / 1e12, 1)
+    out["how"] = ("2 GiB device copy (read + write), torch.matmul bf16 8192^3 and fp64 "
+                  "4096^3 (vendor BLAS), timed with HIP events")
+    torch.cuda.synchronize()
+    return out
 
 
 def cpu_baseline(s, degree, bounds, nbands):
@@ -79,7 +155,7 @@ def cpu_baseline(s, degree, bounds, nbands):
     }
 
 
-def roofline_of(prof, peak_mfma, mfma_label, gemm_work_factor=1.0):
+def roofline_of(prof, peak_mfma, mfma_label, gemm_work_factor=1.0, mixed=False):
     """Dominant H-application kernel class (by time) and its live achieved rate.
 
     GEMM work is the complex product's 8 N_pw N_proj flops per band times
@@ -102,8 +178,13 @@ def roofline_of(prof, peak_mfma, mfma_label, gemm_work_factor=1.0):
         achieved = per_launch / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4)}
+    # the committed counter summary covers the mixed form's kernels
+    traffic = measured_traffic(dom) if mixed else None
     roof.update({"kernel": dom, "launches": cnt, "avg_launch_ms": round(avg_s * 1e3, 4),
-                 "work_per_launch": per_launch, "traffic": None})
+                 "work_per_launch": per_launch,
+                 "traffic": None if traffic is None else round(traffic)})
+    if mixed and dom in CLASS_KERNELS:
+        roof["kernel_name"] = CLASS_KERNELS[dom][0]
     return roof
 
 
@@ -187,6 +268,7 @@ def main():
     from paper_2604_11139_amd import binding as B
 
     torch.cuda.set_device(0)
+    ceil = None if args.no_ceilings else ceilings()
     if args.copy_mib > 0:
         # a plain device copy of known size: its FETCH_SIZE / WRITE_SIZE counters
         # calibrate the per-dispatch traffic of the path's kernels
@@ -250,10 +332,17 @@ def main():
         "cycle_band_apps_per_s": round(head["cycle_band_apps_per_s"], 2),
         "setup_s": round(t_setup, 2),
         "max_residual_last_step": float(head["res"].max()),
-        "roofline": (roofline_of(head["prof"], PEAK_BF16_TFLOPS, "bf16 MFMA (split-BF16 x3)", 3.0)
+        "roofline": (roofline_of(head["prof"], PEAK_BF16_TFLOPS, "bf16 MFMA (split-BF16 x3)", 3.0,
+                                 mixed=True)
                      if mixed else roofline_of(head["prof"], PEAK_FP64_TFLOPS, "fp64 MFMA")),
         "kernel_classes": class_table(head["prof"]),
     }
+    if ceil:
+        out["ceilings"] = ceil
+        r = out["roofline"]
+        ref = (ceil["hbm_copy_gbs"] if r["bound"] == "hbm" else
+               ceil["bf16_gemm_tflops"] if mixed else ceil["fp64_gemm_tflops"])
+        r["frac_of_measured_ceiling"] = round(r["achieved"] / ref, 4)
     if "fp64" in runs and mixed:
         f = runs["fp64"]
         out["fp64"] = {

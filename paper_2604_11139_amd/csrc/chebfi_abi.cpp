@@ -694,10 +694,10 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
       // 0: split-BF16 planes x planes (default), 1: FP32 MFMA, 2: split-BF16 with the
       // block split while staged
       if (const char *e = std::getenv("CHEBFI_MIXED_GEMM")) s->mixed_gemm = std::atoi(e);
-      // tile variants of the split-BF16 products (tuning knobs, 0..4)
+      // tile variants of the split-BF16 products (tuning knobs, 0..7)
       s->pl_proj = s->pl_expand = 4;
-      if (const char *e = std::getenv("CHEBFI_PL_PROJ")) s->pl_proj = std::min(4, std::max(0, std::atoi(e)));
-      if (const char *e = std::getenv("CHEBFI_PL_EXPAND")) s->pl_expand = std::min(4, std::max(0, std::atoi(e)));
+      if (const char *e = std::getenv("CHEBFI_PL_PROJ")) s->pl_proj = std::min(7, std::max(0, std::atoi(e)));
+      if (const char *e = std::getenv("CHEBFI_PL_EXPAND")) s->pl_expand = std::min(7, std::max(0, std::atoi(e)));
     }
     // bands per FFT batch: keep the box buffer near 128 MiB (env override)
     int64_t fb = (int64_t)((128ll << 20) / (sizeof(double2) * nbox));

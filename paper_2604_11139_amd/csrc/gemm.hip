@@ -680,16 +680,17 @@ __device__ __forceinline__ void grouped_tile(unsigned gm, unsigned &tm, unsigned
 // bank conflicts on gfx950 (measured with the LDS conflict counters).  One
 // barrier per K step: the next slice is written into the other stage while
 // this one is multiplied.
-template <int BM, int BN, int NWM, int NWN, bool CONJ, bool SPLIT>
-__global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl2_kernel(
+template <int BM, int BN, int NWM, int NWN, bool CONJ, bool SPLIT, int DEPTH>
+__global__ __launch_bounds__(64 * NWM * NWN, 2) void zgemm_pl2_kernel(
     int64_t m, int64_t n, int64_t k, const u16 *__restrict__ Apl, int64_t lda, int64_t psa,
     const u16 *__restrict__ Bpl, int64_t ldb, int64_t psb, float2 *__restrict__ C, int64_t ldc,
     int64_t kchunk, float2 *__restrict__ part) {
   constexpr int NT = 64 * NWM * NWN;
   constexpr int SM = BM / NWM / 16, SN = BN / NWN / 16;
   constexpr int CA = 16 * BM / NT, CB = 16 * BN / NT;
-  __shared__ __align__(16) u16 As[2][4][BM][XBK];
-  __shared__ __align__(16) u16 Bs[2][4][BN][XBK];
+  constexpr int NST = DEPTH == 0 ? 1 : 2;  // LDS stages
+  __shared__ __align__(16) u16 As[NST][4][BM][XBK];
+  __shared__ __align__(16) u16 Bs[NST][4][BN][XBK];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % NWM, wn = wave / NWM;
@@ -708,7 +709,7 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl2_kernel(
       acc[i][j][1] = v4f{0, 0, 0, 0};
     }
 
-  uint4 ra[CA], rb[CB];
+  uint4 ra[DEPTH == 0 ? 1 : DEPTH][CA], rb[DEPTH == 0 ? 1 : DEPTH][CB];
   // chunk idx of a staged slice with R rows: K chunk idx & 3, row
   // (idx >> 2) % R, plane (idx >> 2) / R
   auto load_chunk = [&](const u16 *base, int64_t ld, int64_t ps, int64_t lim, int idx,
@@ -729,95 +730,126 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl2_kernel(
     }
     return v;
   };
-  auto load_tiles = [&](int64_t k0) {
+  auto load_tiles = [&](int r, int64_t k0) {
 #pragma unroll
     for (int c = 0; c < CA; ++c)
-      ra[c] = load_chunk(Apl, lda, psa, m, tid + NT * c, row0, k0, BM);
+      ra[r][c] = load_chunk(Apl, lda, psa, m, tid + NT * c, row0, k0, BM);
 #pragma unroll
     for (int c = 0; c < CB; ++c)
-      rb[c] = load_chunk(Bpl, ldb, psb, n, tid + NT * c, col0, k0, BN);
+      rb[r][c] = load_chunk(Bpl, ldb, psb, n, tid + NT * c, col0, k0, BN);
   };
-  auto store_tiles = [&](int st) {
+  auto store_tiles = [&](int r, int st) {
 #pragma unroll
     for (int c = 0; c < CA; ++c) {
       const int idx = tid + NT * c, kc = idx & 3, i = (idx >> 2) % BM, pl = (idx >> 2) / BM;
-      *reinterpret_cast<uint4 *>(&As[st][pl][i][8 * (kc ^ ((i >> 1) & 3))]) = ra[c];
+      *reinterpret_cast<uint4 *>(&As[st][pl][i][8 * (kc ^ ((i >> 1) & 3))]) = ra[r][c];
     }
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
       const int idx = tid + NT * c, kc = idx & 3, i = (idx >> 2) % BN, pl = (idx >> 2) / BN;
-      *reinterpret_cast<uint4 *>(&Bs[st][pl][i][8 * (kc ^ ((i >> 1) & 3))]) = rb[c];
+      *reinterpret_cast<uint4 *>(&Bs[st][pl][i][8 * (kc ^ ((i >> 1) & 3))]) = rb[r][c];
     }
   };
 
-  int cur = 0;
-  if (kbeg < kend) {
-    load_tiles(kbeg);
-    store_tiles(0);
-  }
-  __syncthreads();
   const int kq = lane >> 4;
-  for (int64_t k0 = kbeg; k0 < kend; k0 += XBK) {
-    const bool more = k0 + XBK < kend;
-    if (more) load_tiles(k0 + XBK);
-    v8bf a[SM][6], b[SN][6];
-#pragma unroll
-    for (int i = 0; i < SM; ++i) {
-      const int ii = wm * (BM / NWM) + i * 16 + (lane & 15);
-      const int kb = 8 * (kq ^ ((ii >> 1) & 3));
-#pragma unroll
-      for (int p = 0; p < 4; ++p) a[i][p] = *reinterpret_cast<const v8bf *>(&As[cur][p][ii][kb]);
-      if (CONJ) {
-        a[i][4] = bf16_neg(a[i][1]);
-        a[i][5] = bf16_neg(a[i][3]);
-      }
-    }
+  // multiply-accumulate of the K slice held in LDS stage st
+  auto mma = [&](int st) {
+    // negated imaginary planes of A (a[4], a[5]) carry the minus signs of the
+    // complex product in both forms, so B needs no negated copies
+    v8bf b[SN][4];
 #pragma unroll
     for (int j = 0; j < SN; ++j) {
       const int jj = wn * (BN / NWN) + j * 16 + (lane & 15);
       const int kb = 8 * (kq ^ ((jj >> 1) & 3));
 #pragma unroll
-      for (int p = 0; p < 4; ++p) b[j][p] = *reinterpret_cast<const v8bf *>(&Bs[cur][p][jj][kb]);
-      if (!CONJ) {
-        b[j][4] = bf16_neg(b[j][1]);
-        b[j][5] = bf16_neg(b[j][3]);
-      }
+      for (int p = 0; p < 4; ++p) b[j][p] = *reinterpret_cast<const v8bf *>(&Bs[st][p][jj][kb]);
     }
 #pragma unroll
-    for (int i = 0; i < SM; ++i)
+    for (int i = 0; i < SM; ++i) {
+      v8bf a[6];
+      const int ii = wm * (BM / NWM) + i * 16 + (lane & 15);
+      const int kb = 8 * (kq ^ ((ii >> 1) & 3));
+#pragma unroll
+      for (int p = 0; p < 4; ++p) a[p] = *reinterpret_cast<const v8bf *>(&As[st][p][ii][kb]);
+      a[4] = bf16_neg(a[1]);
+      a[5] = bf16_neg(a[3]);
 #pragma unroll
       for (int j = 0; j < SN; ++j) {
         v4f re = acc[i][j][0], im = acc[i][j][1];
-        re = mfma_bf16(b[j][0], a[i][0], re);
-        re = mfma_bf16(b[j][2], a[i][0], re);
-        re = mfma_bf16(b[j][0], a[i][2], re);
-        if (CONJ) {
-          re = mfma_bf16(b[j][1], a[i][1], re);
-          re = mfma_bf16(b[j][3], a[i][1], re);
-          re = mfma_bf16(b[j][1], a[i][3], re);
-        } else {
-          re = mfma_bf16(b[j][4], a[i][1], re);
-          re = mfma_bf16(b[j][5], a[i][1], re);
-          re = mfma_bf16(b[j][4], a[i][3], re);
-        }
-        im = mfma_bf16(b[j][1], a[i][0], im);
-        im = mfma_bf16(b[j][3], a[i][0], im);
-        im = mfma_bf16(b[j][1], a[i][2], im);
-        if (CONJ) {
-          im = mfma_bf16(b[j][0], a[i][4], im);
-          im = mfma_bf16(b[j][2], a[i][4], im);
-          im = mfma_bf16(b[j][0], a[i][5], im);
-        } else {
-          im = mfma_bf16(b[j][0], a[i][1], im);
-          im = mfma_bf16(b[j][2], a[i][1], im);
-          im = mfma_bf16(b[j][0], a[i][3], im);
-        }
+        // Re: hi*hi + lo*hi + hi*lo of Re x Re, then -/+ Im x Im
+        re = mfma_bf16(b[j][0], a[0], re);
+        re = mfma_bf16(b[j][2], a[0], re);
+        re = mfma_bf16(b[j][0], a[2], re);
+        re = mfma_bf16(b[j][1], a[CONJ ? 1 : 4], re);
+        re = mfma_bf16(b[j][3], a[CONJ ? 1 : 4], re);
+        re = mfma_bf16(b[j][1], a[CONJ ? 3 : 5], re);
+        // Im: Im(B) Re(A) then +/- Re(B) Im(A)
+        im = mfma_bf16(b[j][1], a[0], im);
+        im = mfma_bf16(b[j][3], a[0], im);
+        im = mfma_bf16(b[j][1], a[2], im);
+        im = mfma_bf16(b[j][0], a[CONJ ? 4 : 1], im);
+        im = mfma_bf16(b[j][2], a[CONJ ? 4 : 1], im);
+        im = mfma_bf16(b[j][0], a[CONJ ? 5 : 3], im);
         acc[i][j][0] = re;
         acc[i][j][1] = im;
       }
-    if (more) store_tiles(cur ^ 1);
+    }
+  };
+
+  if constexpr (DEPTH == 0) {
+    // one LDS stage (so that two workgroups fit a CU): registers carry slice
+    // k+1 while slice k is multiplied; two barriers per K step
+    if (kbeg < kend) {
+      load_tiles(0, kbeg);
+      store_tiles(0, 0);
+    }
     __syncthreads();
-    cur ^= 1;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += XBK) {
+      const bool more = k0 + XBK < kend;
+      if (more) load_tiles(0, k0 + XBK);
+      mma(0);
+      __syncthreads();
+      if (more) {
+        store_tiles(0, 0);
+        __syncthreads();
+      }
+    }
+  } else if constexpr (DEPTH == 1) {
+    // loads for slice k+1 are issued before slice k is multiplied
+    int cur = 0;
+    if (kbeg < kend) {
+      load_tiles(0, kbeg);
+      store_tiles(0, 0);
+    }
+    __syncthreads();
+    for (int64_t k0 = kbeg; k0 < kend; k0 += XBK) {
+      const bool more = k0 + XBK < kend;
+      if (more) load_tiles(0, k0 + XBK);
+      mma(cur);
+      if (more) store_tiles(0, cur ^ 1);
+      __syncthreads();
+      cur ^= 1;
+    }
+  } else {
+    // two register sets: loads for slice k+2 are issued before slice k is
+    // multiplied, and slice k+1 (loaded one step earlier) is staged after it
+    if (kbeg < kend) {
+      load_tiles(0, kbeg);
+      store_tiles(0, 0);
+    }
+    if (kbeg + XBK < kend) load_tiles(1, kbeg + XBK);
+    __syncthreads();
+    for (int64_t k0 = kbeg; k0 < kend; k0 += 2 * XBK) {
+      if (k0 + 2 * XBK < kend) load_tiles(0, k0 + 2 * XBK);
+      mma(0);
+      if (k0 + XBK < kend) store_tiles(1, 1);
+      __syncthreads();
+      if (k0 + XBK >= kend) break;
+      if (k0 + 3 * XBK < kend) load_tiles(1, k0 + 3 * XBK);
+      mma(1);
+      if (k0 + 2 * XBK < kend) store_tiles(0, 0);
+      __syncthreads();
+    }
   }
 
 #pragma unroll
@@ -889,6 +921,9 @@ void split_planes(int64_t rows, int64_t cols, const void *X, int64_t ld, void *p
 //   2:  64 x  64, 2 x 2 waves (32 x 32 per wave)
 //   3:  64 x 128, 1 x 4 waves (64 x 32 per wave)
 //   4: 128 x 128, 2 x 4 waves, double-buffered LDS (default)
+//   5: as 4 with the global loads issued two K slices ahead
+//   6: 128 x 128, 2 x 2 waves, one LDS stage (two workgroups per CU)
+//   7: 128 x  64, 2 x 2 waves, one LDS stage
 template <bool CONJ, bool SPLIT>
 static void launch_pl(int variant, dim3 grid_mn_z, int64_t m, int64_t n, int64_t k,
                       const void *Apl, int64_t lda, int64_t psa, const void *Bpl, int64_t ldb,
@@ -903,14 +938,17 @@ static void launch_pl(int variant, dim3 grid_mn_z, int64_t m, int64_t n, int64_t
     case 1: go(zgemm_pl_kernel<128, 128, 2, 2, CONJ, SPLIT>, 128, 128, 256); break;
     case 2: go(zgemm_pl_kernel<64, 64, 2, 2, CONJ, SPLIT>, 64, 64, 256); break;
     case 3: go(zgemm_pl_kernel<64, 128, 1, 4, CONJ, SPLIT>, 64, 128, 256); break;
-    case 4: go(zgemm_pl2_kernel<128, 128, 2, 4, CONJ, SPLIT>, 128, 128, 512); break;
+    case 4: go(zgemm_pl2_kernel<128, 128, 2, 4, CONJ, SPLIT, 1>, 128, 128, 512); break;
+    case 5: go(zgemm_pl2_kernel<128, 128, 2, 4, CONJ, SPLIT, 2>, 128, 128, 512); break;
+    case 6: go(zgemm_pl2_kernel<128, 128, 2, 2, CONJ, SPLIT, 0>, 128, 128, 256); break;
+    case 7: go(zgemm_pl2_kernel<128, 64, 2, 2, CONJ, SPLIT, 0>, 128, 64, 256); break;
     default: go(zgemm_pl_kernel<128, 128, 2, 4, CONJ, SPLIT>, 128, 128, 512); break;
   }
   CHEBFI_HIP(hipGetLastError());
 }
 
 static int pl_bm(int variant) { return (variant == 2 || variant == 3) ? 64 : 128; }
-static int pl_bn(int variant) { return variant == 2 ? 64 : 128; }
+static int pl_bn(int variant) { return (variant == 2 || variant == 7) ? 64 : 128; }
 
 int proj_planes_splits(int variant, int64_t nproj, int64_t nband, int64_t npw) {
   // about four workgroups per CU, at least 1024 plane waves per chunk
