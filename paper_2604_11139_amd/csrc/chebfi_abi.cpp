@@ -148,6 +148,11 @@ template <typename T> T *upload(const T *host, size_t count) {
 }
 
 void free_tables(abi_system_s *s) {
+  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+  if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+  if (s->aux) (void)hipStreamDestroy(s->aux);
+  s->ev_fork = s->ev_join = nullptr;
+  s->aux = nullptr;
   void *ptrs[] = {s->d_kin, s->d_box, s->d_plane, s->d_P, s->d_D, s->d_V,
                   s->d_tw,  s->d_Pf,  s->d_Vf,    s->d_PA, s->d_PB};
   for (void *p : ptrs)
@@ -208,6 +213,25 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
   V2 *cpart = nullptr, *cprime = nullptr;
   const bool single = (nband == 1) && !fp32;
   const bool planes = fp32 && s->mixed_gemm == 0;
+  // local part, kinetic term and recurrence: Out = alpha (local + (kin - c) X) - beta Xprev,
+  // on the second stream when it can run beside the projection
+  const bool side = s->overlap && nproj > 0 && !single && s->aux;
+  hipStream_t fst = side ? s->aux : st;
+  if (side) {
+    CHEBFI_HIP(hipEventRecord(s->ev_fork, st));
+    CHEBFI_HIP(hipStreamWaitEvent(s->aux, s->ev_fork, 0));
+  }
+  {
+    const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
+    const int fb = (int)std::min<int64_t>(s->fft_batch * (fp32 ? 2 : 1), nband);
+    void *box = s->box.get(sizeof(V2) * (size_t)nbox * fb);
+    for (int64_t b0 = 0; b0 < nband; b0 += fb) {
+      const int nb = (int)std::min<int64_t>(fb, nband - b0);
+      launch_local_potential<T>(s, X, ldx, Xprev, ldp, Out, ldo, (int)b0, nb, box, V, alpha,
+                                cshift, beta, fst, s->prof.on ? &s->prof : nullptr);
+    }
+  }
+  if (side) CHEBFI_HIP(hipEventRecord(s->ev_join, s->aux));
   if (nproj > 0) {
     splits = single ? 1
              : planes ? proj_planes_splits(s->pl_proj, nproj, nband, npw)
@@ -242,14 +266,7 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
                    s->ldPB, st);
     s->prof.end(tok, st);
   }
-  const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
-  const int fb = (int)std::min<int64_t>(s->fft_batch * (fp32 ? 2 : 1), nband);
-  void *box = s->box.get(sizeof(V2) * (size_t)nbox * fb);
-  for (int64_t b0 = 0; b0 < nband; b0 += fb) {
-    const int nb = (int)std::min<int64_t>(fb, nband - b0);
-    launch_local_potential<T>(s, X, ldx, Xprev, ldp, Out, ldo, (int)b0, nb, box, V, alpha, cshift,
-                              beta, st, s->prof.on ? &s->prof : nullptr);
-  }
+  if (side) CHEBFI_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
   if (nproj > 0) {
     // Out += P C'
     const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
@@ -703,6 +720,12 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
     int64_t fb = (int64_t)((128ll << 20) / (sizeof(double2) * nbox));
     if (const char *e = std::getenv("CHEBFI_FFT_BATCH")) fb = std::atoll(e);
     s->fft_batch = (int)std::max<int64_t>(1, std::min<int64_t>(fb, 4096));
+    // FFT passes beside the projection GEMM on a second stream (default priority)
+    CHEBFI_HIP(hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking));
+    CHEBFI_HIP(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+    CHEBFI_HIP(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
+    s->overlap = 1;
+    if (const char *e = std::getenv("CHEBFI_OVERLAP")) s->overlap = std::atoi(e) != 0;
     CHEBFI_HIP(hipStreamSynchronize(S(stream)));
     *out = s;
   });
@@ -1046,6 +1069,23 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
         const int64_t lda1 = (k + 1 == m) ? ld : npw;
         void *Ak = abuf[k % 3];
         const bool acc = (k + 1 < m);
+        // the adjoint local part runs beside the projections, as in the forward step
+        const bool side = s->overlap && nproj > 0 && s->aux;
+        hipStream_t fst = side ? s->aux : st;
+        if (side) {
+          CHEBFI_HIP(hipEventRecord(s->ev_fork, st));
+          CHEBFI_HIP(hipStreamWaitEvent(s->aux, s->ev_fork, 0));
+        }
+        for (int64_t b0 = 0; b0 < nband; b0 += fb) {
+          const int nb = (int)std::min<int64_t>(fb, nband - b0);
+          if (fp32)
+            launch_adjoint_local<float>(s, Ak1, lda1, Yk, ldy, Ak, npw, acc, (int)b0, nb, box1,
+                                        box2, s->d_Vf, gam[k], c, dV_acc, fst);
+          else
+            launch_adjoint_local<double>(s, Ak1, lda1, Yk, ldy, Ak, npw, acc, (int)b0, nb, box1,
+                                         box2, s->d_V, gam[k], c, dV_acc, fst);
+        }
+        if (side) CHEBFI_HIP(hipEventRecord(s->ev_join, s->aux));
         if (nproj > 0) {
           project(Ak1, lda1, CA);
           project(Yk, ldy, CY);
@@ -1055,15 +1095,7 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
             split_planes(nproj, nband, Cp, nproj, s->cplanes.get(8 * (size_t)s->ldPB * nband),
                          s->ldPB, st);
         }
-        for (int64_t b0 = 0; b0 < nband; b0 += fb) {
-          const int nb = (int)std::min<int64_t>(fb, nband - b0);
-          if (fp32)
-            launch_adjoint_local<float>(s, Ak1, lda1, Yk, ldy, Ak, npw, acc, (int)b0, nb, box1,
-                                        box2, s->d_Vf, gam[k], c, dV_acc, st);
-          else
-            launch_adjoint_local<double>(s, Ak1, lda1, Yk, ldy, Ak, npw, acc, (int)b0, nb, box1,
-                                         box2, s->d_V, gam[k], c, dV_acc, st);
-        }
+        if (side) CHEBFI_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
         if (nproj > 0) {
           if (planes)
             expand_gemm_planes(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB,

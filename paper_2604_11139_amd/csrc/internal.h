@@ -188,5 +188,10 @@ struct abi_system_s {
   chebfi::DevBuf eig1, eig2, eig3, blk4, box2, adj, adjsmall, planes, cplanes;
 
   int fft_batch = 0;  // bands per FFT batch (box buffer holds this many boxes)
+  // second stream: the FFT passes of an H application run on it beside the
+  // projection GEMM (they are independent until the expansion)
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int overlap = 1;
   chebfi::Profiler prof;
 };

@@ -106,6 +106,25 @@ def test_cheb_filter(name, degree):
     assert col_rel_err(got, ref) <= 1e-9
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_filter_overlap_is_bitwise_neutral(precision, monkeypatch):
+    """The FFT passes on a second stream beside the projection give the same bits."""
+    import torch
+    s = system("n25")
+    H = hamiltonian("n25")
+    X = W.random_block(H.npw, s.nband, 31)
+    prec = B.ABI_PREC_MIXED if precision == "mixed" else B.ABI_PREC_FP64
+    outs = []
+    for ov in ("0", "1"):
+        monkeypatch.setenv("CHEBFI_OVERLAP", ov)
+        with B.System(s, precision=prec) as g:
+            Xd = to_dev(X)
+            if precision == "mixed":
+                Xd = Xd.to(torch.complex64)
+            outs.append(g.cheb_filter(Xd, 7, 0.5, 9.0, -1.5).cpu())
+    assert torch.equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("name", ["tiny_k", "n25", "c1"])
 def test_spectral_bounds(name):
     H = hamiltonian(name)
