@@ -158,6 +158,28 @@ abi_status abi_rayleigh_ritz(abi_system sys, void *Y, void *HPsi, int64_t nband,
                              int32_t dtype, double *eval, double *resnorm, void *coef,
                              int32_t *flags, void *stream);
 
+/* The eigensolver loop: cycles of spectral bounds (10 Lanczos steps from v0),
+ * degree-m filter and Rayleigh-Ritz on the block X, the Ritz vectors of a cycle
+ * being the next cycle's block (the subspace iteration of Algorithm "Parallel
+ * Chebyshev filtering of degree k", repeated), until the residual norms of the
+ * lowest nconv Ritz pairs are all <= tol or max_cycles cycles have run.
+ * X (in: start block; out: Ritz vectors, ascending Ritz values) is npw x nband
+ * (ld) of `dtype`; v0: device, npw complex128.  With dtype ABI_C64 and
+ * refine_degree > 0, the mixed cycles hand over to FP64 cycles of degree
+ * refine_degree on the promoted block (a residual-driven refinement) when a
+ * cycle improves the worst of those residuals by less than 10%, or after half
+ * of max_cycles; X then receives the complex64 rounding of the FP64 Ritz
+ * vectors.  eval, resnorm (host, nband; resnorm may be NULL): the last cycle's
+ * Ritz values and residual norms.  info (host, 4 entries, may be NULL): cycles
+ * in the block's precision, FP64 refinement cycles, converged (0/1), 0.
+ * Synchronises the stream.  Errors: those of the calls it makes; ABI_ERR_ARG
+ * for nconv outside 1..nband, tol <= 0, refinement asked for a complex128
+ * block. */
+abi_status abi_chebfi_solve(abi_system sys, void *X, int64_t nband, int64_t ld, int32_t dtype,
+                            const void *v0, int32_t degree, int32_t max_cycles, int32_t nconv,
+                            double tol, int32_t refine_degree, double *eval, double *resnorm,
+                            int32_t *info, void *stream);
+
 /* Replaces V_loc (device, n1*n2*n3 doubles, i1 fastest) and/or D (device,
  * natom*16 complex doubles, row-major per atom); a NULL pointer keeps the old
  * table.  Stream-ordered; for differentiation and finite differences. */

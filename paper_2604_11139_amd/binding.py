@@ -38,7 +38,7 @@ EXPORTS = [
     "abi_zheev", "abi_profile_enable", "abi_profile_read", "abi_update_potential",
     "abi_filter_backward", "abi_density", "abi_last_error", "abi_set_system_batch",
     "abi_batch_system", "abi_cheb_filter_batch", "abi_batch_autotune", "abi_batch_use_graph",
-    "abi_destroy_batch",
+    "abi_destroy_batch", "abi_chebfi_solve",
 ]
 
 PROFILE_CLASSES = ["proj_gemm", "expand_gemm", "fft_a", "fft_b", "fft_c", "dapply", "gram",
@@ -107,6 +107,8 @@ def lib():
         "abi_batch_autotune": [vp, vp, vp, vp, vp, c_int32, c_int32, vp, vp, vp, vp, vp],
         "abi_batch_use_graph": [vp, c_int32],
         "abi_destroy_batch": [vp],
+        "abi_chebfi_solve": [vp, vp, c_int64, c_int64, c_int32, vp, c_int32, c_int32, c_int32,
+                             c_double, c_int32, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -346,6 +348,24 @@ class System:
         _check(lib().abi_density(self._h, pp, nb, ld, code, pw, c_void_p(rho.data_ptr()),
                                  _stream()))
         return rho
+
+    def solve(self, X, v0, degree, max_cycles, nconv, tol, refine_degree=0):
+        """In place: X <- Ritz vectors after cycles of bounds, filter and
+        Rayleigh-Ritz until the lowest nconv residuals are <= tol.  Returns
+        (eval, resnorm, info dict)."""
+        px, nb, ld, code = _block(X, self.npw)
+        pv, _, _, vcode = _block(v0.reshape(1, -1) if v0.dim() == 1 else v0, self.npw)
+        if vcode != ABI_C128:
+            raise TypeError("v0 must be complex128")
+        ev = np.zeros(nb)
+        res = np.zeros(nb)
+        info = np.zeros(4, dtype=np.int32)
+        _check(lib().abi_chebfi_solve(self._h, px, nb, ld, code, pv, int(degree), int(max_cycles),
+                                      int(nconv), float(tol), int(refine_degree),
+                                      ev.ctypes.data_as(c_void_p), res.ctypes.data_as(c_void_p),
+                                      info.ctypes.data_as(c_void_p), _stream()))
+        return ev, res, {"cycles": int(info[0]), "refine_cycles": int(info[1]),
+                         "converged": bool(info[2])}
 
     def profile(self, on=True):
         _check(lib().abi_profile_enable(self._h, 1 if on else 0))

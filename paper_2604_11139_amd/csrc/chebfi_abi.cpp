@@ -909,6 +909,87 @@ abi_status abi_rayleigh_ritz(abi_system s, void *Y, void *HPsi, int64_t nband, i
   });
 }
 
+abi_status abi_chebfi_solve(abi_system s, void *X, int64_t nband, int64_t ld, int32_t dtype,
+                            const void *v0, int32_t degree, int32_t max_cycles, int32_t nconv,
+                            double tol, int32_t refine_degree, double *eval, double *resnorm,
+                            int32_t *info, void *stream) {
+  return guarded([&] {
+    check_block(s, X, nband, ld, dtype);
+    CHEBFI_REQUIRE(v0 != nullptr && eval != nullptr, ABI_ERR_ARG, "v0 or eval is NULL");
+    CHEBFI_REQUIRE(degree >= 1 && max_cycles >= 1, ABI_ERR_ARG,
+                   "degree and max_cycles must be >= 1");
+    CHEBFI_REQUIRE(nconv >= 1 && nconv <= nband, ABI_ERR_ARG, "need 1 <= nconv <= nband");
+    CHEBFI_REQUIRE(tol > 0.0 && std::isfinite(tol), ABI_ERR_ARG, "tol must be positive");
+    CHEBFI_REQUIRE(refine_degree >= 0, ABI_ERR_ARG, "refine_degree must be >= 0");
+    CHEBFI_REQUIRE(refine_degree == 0 || dtype == ABI_C64, ABI_ERR_ARG,
+                   "the FP64 refinement applies to complex64 blocks");
+    auto call = [](abi_status rc) {
+      if (rc != ABI_OK) throw Error{rc, g_last_error};
+    };
+    hipStream_t st = S(stream);
+    const int64_t npw = s->npw;
+    std::vector<double> res((size_t)nband, 0.0);
+    auto worst = [&]() {
+      double m = 0.0;
+      for (int i = 0; i < nconv; ++i) m = std::max(m, res[i]);
+      return m;
+    };
+    // one cycle: bounds of A, filter A -> B, Rayleigh-Ritz in place on B
+    auto cycle = [&](void *A, void *Bk, int64_t l, int32_t dt, int32_t m) {
+      double bd[3];
+      call(abi_spectral_bounds(s, A, nband, l, dt, v0, 10, bd, stream));
+      call(abi_cheb_filter(s, A, Bk, nband, l, dt, m, bd[0], bd[1], bd[2], stream));
+      int32_t flags = 0;
+      call(abi_rayleigh_ritz(s, Bk, nullptr, nband, l, dt, eval, res.data(), nullptr, &flags,
+                             stream));
+    };
+    const bool refine = refine_degree > 0;
+    // the mixed cycles hand over to the FP64 refinement when they stall (a cycle
+    // that improves the worst residual by less than 10%) or after half the budget
+    const int first_budget = refine ? std::max(1, max_cycles / 2) : max_cycles;
+    void *bufA = X;
+    void *bufB = s->solve1.get(elem_bytes(dtype) * (size_t)ld * nband);
+    int cycles = 0, rcycles = 0, converged = 0;
+    double prev = HUGE_VAL;
+    while (cycles < first_budget) {
+      cycle(bufA, bufB, ld, dtype, degree);
+      std::swap(bufA, bufB);
+      ++cycles;
+      const double cur = worst();
+      if (cur <= tol) {
+        converged = 1;
+        break;
+      }
+      if (refine && cur > 0.9 * prev) break;
+      prev = cur;
+    }
+    if (bufA != X) launch_copy_block(npw, nband, bufA, ld, X, ld, st, dtype == ABI_C64);
+    if (refine && !converged) {
+      void *A = s->solve2.get(sizeof(double2) * (size_t)npw * nband);
+      void *Bk = s->solve3.get(sizeof(double2) * (size_t)npw * nband);
+      launch_c64_to_c128(npw, nband, X, ld, A, npw, st);
+      while (cycles + rcycles < max_cycles) {
+        cycle(A, Bk, npw, ABI_C128, refine_degree);
+        std::swap(A, Bk);
+        ++rcycles;
+        if (worst() <= tol) {
+          converged = 1;
+          break;
+        }
+      }
+      launch_c128_to_c64(npw, nband, A, npw, X, ld, st);
+    }
+    CHEBFI_HIP(hipStreamSynchronize(st));
+    if (resnorm) std::memcpy(resnorm, res.data(), sizeof(double) * (size_t)nband);
+    if (info) {
+      info[0] = cycles;
+      info[1] = rcycles;
+      info[2] = converged;
+      info[3] = 0;
+    }
+  });
+}
+
 abi_status abi_update_potential(abi_system s, const double *vloc, const void *dij, void *stream) {
   return guarded([&] {
     CHEBFI_REQUIRE(s != nullptr, ABI_ERR_ARG, "system handle is NULL");

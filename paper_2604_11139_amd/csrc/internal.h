@@ -186,6 +186,7 @@ struct abi_system_s {
   // work buffers
   chebfi::DevBuf box, cpart, cprime, blk1, blk2, blk3, small1, small2, small3, small4, scal;
   chebfi::DevBuf eig1, eig2, eig3, blk4, box2, adj, adjsmall, planes, cplanes;
+  chebfi::DevBuf solve1, solve2, solve3;  // blocks of the multi-cycle driver
 
   int fft_batch = 0;  // bands per FFT batch (box buffer holds this many boxes)
   // second stream: the FFT passes of an H application run on it beside the

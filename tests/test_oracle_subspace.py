@@ -77,3 +77,22 @@ def test_higher_degree_smaller_residual():
         rr = O.rayleigh_ritz(H, Y)
         worst.append(O.residual_norms(rr["Psi"], rr["HPsi"], rr["eval"])[:4].max())
     assert worst[1] < worst[0]
+
+
+def test_repeated_cycles_converge_to_dense_spectrum():
+    """Subspace iteration (bounds from the current block, filter, Rayleigh-Ritz,
+    repeated) converges to the lowest eigenpairs of the dense operator."""
+    s = tiny(tag=124, nband=10)
+    H = O.Hamiltonian.from_system(s)
+    lam = np.linalg.eigvalsh(H.dense())
+    X = W.random_block(H.npw, 10, 124)
+    v0 = W.random_vector(H.npw, 124)
+    for _ in range(30):
+        a, b, a0 = O.filter_bounds(H, X, v0)
+        rr = O.rayleigh_ritz(H, O.cheb_filter(H, X, 8, a, b, a0))
+        X = rr["Psi"]
+        res = O.residual_norms(rr["Psi"], rr["HPsi"], rr["eval"])
+        if res[:6].max() < 1e-10:
+            break
+    assert res[:6].max() < 1e-10
+    assert np.abs(rr["eval"][:6] - lam[:6]).max() < 1e-12
