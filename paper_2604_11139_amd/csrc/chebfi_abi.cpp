@@ -273,7 +273,7 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
     int tok = s->prof.begin(PROF_EXPAND, flops, st);
     if (single)
       expand_gemv(npw, nproj, P, cprime, Out, st);
-    else if (fp32 && s->mixed_gemm == 0)
+    else if (planes)
       expand_gemm_planes(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB, s->cplanes.ptr,
                          s->ldPB, s->ldPB * nband, Out, ldo, st, s->pl_expand);
     else if (fp32 && s->mixed_gemm == 2)
@@ -387,7 +387,7 @@ struct abi_batch_s {
   std::vector<chebfi::BatchSys> hsys;
   std::vector<chebfi::BatchStep> hsteps;
   std::vector<int64_t> hoff;
-  int fft_threads = 256, proj_threads = 256, radix_desc = 0, fft_min_threads = 256;
+  int fft_threads = 512, proj_threads = 256, radix_desc = 0, fft_min_threads = 64;
   bool use_graph = true;
   // the captured graph and what it was captured for
   hipGraphExec_t gexec = nullptr;
@@ -470,7 +470,7 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
   // workspace: boxes, C', two iterate slots per system
   std::vector<size_t> o_box(nsys), o_cp(nsys), o_slot(nsys);
   size_t tot = 0;
-  int min_threads = 256;
+  int min_threads = 64;
   size_t lds_a = 0, lds_b = 0;
   bool any_proj = false;
   for (int i = 0; i < nsys; ++i) {
@@ -711,10 +711,10 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
       // 0: split-BF16 planes x planes (default), 1: FP32 MFMA, 2: split-BF16 with the
       // block split while staged
       if (const char *e = std::getenv("CHEBFI_MIXED_GEMM")) s->mixed_gemm = std::atoi(e);
-      // tile variants of the split-BF16 products (tuning knobs, 0..7)
+      // tile variants of the split-BF16 products (tuning knobs, 0..6)
       s->pl_proj = s->pl_expand = 4;
-      if (const char *e = std::getenv("CHEBFI_PL_PROJ")) s->pl_proj = std::min(7, std::max(0, std::atoi(e)));
-      if (const char *e = std::getenv("CHEBFI_PL_EXPAND")) s->pl_expand = std::min(7, std::max(0, std::atoi(e)));
+      if (const char *e = std::getenv("CHEBFI_PL_PROJ")) s->pl_proj = std::min(6, std::max(0, std::atoi(e)));
+      if (const char *e = std::getenv("CHEBFI_PL_EXPAND")) s->pl_expand = std::min(6, std::max(0, std::atoi(e)));
     }
     // bands per FFT batch: keep the box buffer near 128 MiB (env override)
     int64_t fb = (int64_t)((128ll << 20) / (sizeof(double2) * nbox));

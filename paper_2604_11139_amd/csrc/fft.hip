@@ -263,7 +263,7 @@ CHEBFI_CPLAN(48, 2, 8, 6, 1)
 CHEBFI_CPLAN(64, 2, 8, 8, 1)
 #undef CHEBFI_CPLAN
 
-constexpr int kCT = 256;  // threads of the specialised passes
+constexpr int kCT = 512;  // threads of the specialised passes (16 waves per CU per 4 planes)
 
 template <typename T, int N, int R, int P, int NPEN, int ES, int PS, int SGN>
 __device__ __forceinline__ void cstage(C2<T> *buf, const C2<T> *tw) {
@@ -633,6 +633,6 @@ template void launch_local_potential<float>(const abi_system_s *, const void *, 
                                             void *, const void *, double, double, double,
                                             hipStream_t, Profiler *);
 
-int fft_stage_threads(const Plan1D &pl, int npen) { return stage_threads(pl, npen); }
+int fft_stage_threads(const Plan1D &pl, int npen) { return stage_need(pl, npen); }
 
 }  // namespace chebfi

@@ -182,17 +182,23 @@ __device__ void load_twiddles(C2<T> *dst, const double2 *src, int n) {
 }
 
 
-inline int stage_threads(const Plan1D &pl, int npen) {
-  // smallest multiple of 64 threads with total butterflies <= kMaxB * threads
+// Smallest multiple of 64 threads with at most kMaxB butterflies per thread in
+// every stage of the plan over npen pencils.
+inline int stage_need(const Plan1D &pl, int npen) {
   int need = 64;
   for (int s = 0; s < pl.nstage; ++s) {
     const int total = npen * (pl.n / pl.radix[s]);
     const int t = (total + kMaxB - 1) / kMaxB;
     if (t > need) need = t;
   }
-  need = (need + 63) / 64 * 64;
-  if (need < 256) need = 256;
-  return need;
+  return (need + 63) / 64 * 64;
+}
+
+// Threads of the runtime-size passes: 512 (the most a pass may use); the
+// extra waves per CU hide the latency of the plane loads and stores.
+inline int stage_threads(const Plan1D &pl, int npen) {
+  const int need = stage_need(pl, npen);
+  return need > 512 ? need : 512;
 }
 
 }  // namespace

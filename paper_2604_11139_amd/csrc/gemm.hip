@@ -922,8 +922,7 @@ void split_planes(int64_t rows, int64_t cols, const void *X, int64_t ld, void *p
 //   3:  64 x 128, 1 x 4 waves (64 x 32 per wave)
 //   4: 128 x 128, 2 x 4 waves, double-buffered LDS (default)
 //   5: as 4 with the global loads issued two K slices ahead
-//   6: 128 x 128, 2 x 2 waves, one LDS stage (two workgroups per CU)
-//   7: 128 x  64, 2 x 2 waves, one LDS stage
+//   6: 128 x  64, 2 x 2 waves, one LDS stage (two workgroups per CU)
 template <bool CONJ, bool SPLIT>
 static void launch_pl(int variant, dim3 grid_mn_z, int64_t m, int64_t n, int64_t k,
                       const void *Apl, int64_t lda, int64_t psa, const void *Bpl, int64_t ldb,
@@ -940,15 +939,14 @@ static void launch_pl(int variant, dim3 grid_mn_z, int64_t m, int64_t n, int64_t
     case 3: go(zgemm_pl_kernel<64, 128, 1, 4, CONJ, SPLIT>, 64, 128, 256); break;
     case 4: go(zgemm_pl2_kernel<128, 128, 2, 4, CONJ, SPLIT, 1>, 128, 128, 512); break;
     case 5: go(zgemm_pl2_kernel<128, 128, 2, 4, CONJ, SPLIT, 2>, 128, 128, 512); break;
-    case 6: go(zgemm_pl2_kernel<128, 128, 2, 2, CONJ, SPLIT, 0>, 128, 128, 256); break;
-    case 7: go(zgemm_pl2_kernel<128, 64, 2, 2, CONJ, SPLIT, 0>, 128, 64, 256); break;
+    case 6: go(zgemm_pl2_kernel<128, 64, 2, 2, CONJ, SPLIT, 0>, 128, 64, 256); break;
     default: go(zgemm_pl_kernel<128, 128, 2, 4, CONJ, SPLIT>, 128, 128, 512); break;
   }
   CHEBFI_HIP(hipGetLastError());
 }
 
 static int pl_bm(int variant) { return (variant == 2 || variant == 3) ? 64 : 128; }
-static int pl_bn(int variant) { return (variant == 2 || variant == 7) ? 64 : 128; }
+static int pl_bn(int variant) { return (variant == 2 || variant == 6) ? 64 : 128; }
 
 int proj_planes_splits(int variant, int64_t nproj, int64_t nband, int64_t npw) {
   // about four workgroups per CU, at least 1024 plane waves per chunk

@@ -67,7 +67,7 @@ void expand_gemm_bf16x3(int64_t npw, int64_t nband, int64_t nproj, const void *A
 // (column j = band j, contraction index contiguous, stride ld, plane stride ps).
 void split_planes(int64_t rows, int64_t cols, const void *X, int64_t ld, void *planes,
                   int64_t ldp, hipStream_t st);
-// `variant` selects the tile shape (0..7, see gemm.hip); proj_planes_splits
+// `variant` selects the tile shape (0..6, see gemm.hip); proj_planes_splits
 // gives the K split count that fills the chip for that shape.
 int proj_planes_splits(int variant, int64_t nproj, int64_t nband, int64_t npw);
 void proj_gemm_planes(int64_t nproj, int64_t nband, int64_t npw, const void *Apl, int64_t lda,
@@ -156,7 +156,8 @@ void zheev(int64_t m, void *A, int64_t lda, double *w, void *Z, int64_t ldz, voi
            hipStream_t st);
 size_t zheev_work_bytes(int64_t m);
 
-// Threads per workgroup that one Stockham stage over npen pencils of the plan needs.
+// Threads per workgroup that one Stockham stage over npen pencils of the plan needs
+// (at most 4 butterflies per thread; a multiple of 64).
 int fft_stage_threads(const Plan1D &pl, int npen);
 
 // ---- batch.hip ------------------------------------------------------------------
