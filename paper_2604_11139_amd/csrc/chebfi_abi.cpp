@@ -240,8 +240,11 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
     cprime = (V2 *)s->cprime.get(sizeof(V2) * (size_t)nproj * nband);
     // C = P^H X (split along the plane waves), C' = alpha D C
     const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
+    // the default split-BF16 projection splits the block into planes while staging it;
+    // the other tile variants read planes made by a separate pass
+    const bool staged = planes && s->pl_proj == 4;
     void *xpl = nullptr;
-    if (planes) {
+    if (planes && !staged) {
       xpl = s->planes.get(8 * (size_t)s->ldPA * nband);
       const int tk = s->prof.begin(PROF_SPLIT, 16.0 * (double)npw * (double)nband, st);
       split_planes(npw, nband, X, ldx, xpl, s->ldPA, st);
@@ -250,6 +253,9 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
     int tok = s->prof.begin(PROF_PROJ, flops, st);
     if (single)
       proj_gemv(npw, nproj, P, X, cpart, st);
+    else if (staged)
+      proj_gemm_planes_f32(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, X, ldx,
+                           cpart, splits, st);
     else if (planes) {
       proj_gemm_planes(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, xpl,
                        s->ldPA, s->ldPA * nband, cpart, splits, st, s->pl_proj);
@@ -1078,10 +1084,15 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
       if (planes) {
         const int splits = proj_planes_splits(s->pl_proj, nproj, nband, npw);
         void *part = s->cpart.get(sizeof(float2) * (size_t)splits * nproj * nband);
-        void *zpl = s->planes.get(8 * (size_t)s->ldPA * nband);
-        split_planes(npw, nband, Z, ldz, zpl, s->ldPA, st);
-        proj_gemm_planes(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, zpl,
-                         s->ldPA, s->ldPA * nband, part, splits, st, s->pl_proj);
+        if (s->pl_proj == 4) {
+          proj_gemm_planes_f32(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, Z,
+                               ldz, part, splits, st);
+        } else {
+          void *zpl = s->planes.get(8 * (size_t)s->ldPA * nband);
+          split_planes(npw, nband, Z, ldz, zpl, s->ldPA, st);
+          proj_gemm_planes(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, zpl,
+                           s->ldPA, s->ldPA * nband, part, splits, st, s->pl_proj);
+        }
         launch_sum_parts(nproj, nband, part, splits, out, st, true);
       } else {
         const int splits = zgemm_splits(nproj, nband, npw);

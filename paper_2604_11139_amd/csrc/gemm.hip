@@ -680,7 +680,7 @@ __device__ __forceinline__ void grouped_tile(unsigned gm, unsigned &tm, unsigned
 // bank conflicts on gfx950 (measured with the LDS conflict counters).  One
 // barrier per K step: the next slice is written into the other stage while
 // this one is multiplied.
-template <int BM, int BN, int NWM, int NWN, bool CONJ, bool SPLIT, int DEPTH>
+template <int BM, int BN, int NWM, int NWN, bool CONJ, bool SPLIT, int DEPTH, bool BF32 = false>
 __global__ __launch_bounds__(64 * NWM * NWN, 2) void zgemm_pl2_kernel(
     int64_t m, int64_t n, int64_t k, const u16 *__restrict__ Apl, int64_t lda, int64_t psa,
     const u16 *__restrict__ Bpl, int64_t ldb, int64_t psb, float2 *__restrict__ C, int64_t ldc,
@@ -730,13 +730,43 @@ __global__ __launch_bounds__(64 * NWM * NWN, 2) void zgemm_pl2_kernel(
     }
     return v;
   };
+  // BF32: B is a complex float block (column j = band j, ld ldb in complex
+  // elements) split into its bf16 planes while staged.  Super-chunk sidx covers
+  // 8 consecutive K elements (kc = sidx & 3) of row sidx >> 2 and is held raw
+  // in four uint4 of rb.
+  constexpr int CBF = 4 * BN / NT;
+  static_assert(!BF32 || 4 * CBF == CB, "raw super-chunks must fill the B registers");
+  auto load_b32 = [&](int r, int c, int64_t k0) {
+    const int sidx = tid + NT * c, kc = sidx & 3, i = sidx >> 2;
+    const int64_t gr = col0 + i, ks = k0 + 8 * kc;
+    uint2 t[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[e] = make_uint2(0, 0);
+    if (gr < n && ks < kend) {
+      const uint2 *src = reinterpret_cast<const uint2 *>(Bpl) + gr * ldb + ks;
+      if (ks + 8 <= kend) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[e] = src[e];
+      } else {
+        for (int e = 0; e < 8 && ks + e < kend; ++e) t[e] = src[e];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      rb[r][4 * c + q] = make_uint4(t[2 * q].x, t[2 * q].y, t[2 * q + 1].x, t[2 * q + 1].y);
+  };
   auto load_tiles = [&](int r, int64_t k0) {
 #pragma unroll
     for (int c = 0; c < CA; ++c)
       ra[r][c] = load_chunk(Apl, lda, psa, m, tid + NT * c, row0, k0, BM);
+    if constexpr (BF32) {
 #pragma unroll
-    for (int c = 0; c < CB; ++c)
-      rb[r][c] = load_chunk(Bpl, ldb, psb, n, tid + NT * c, col0, k0, BN);
+      for (int c = 0; c < CBF; ++c) load_b32(r, c, k0);
+    } else {
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+        rb[r][c] = load_chunk(Bpl, ldb, psb, n, tid + NT * c, col0, k0, BN);
+    }
   };
   auto store_tiles = [&](int r, int st) {
 #pragma unroll
@@ -744,10 +774,34 @@ __global__ __launch_bounds__(64 * NWM * NWN, 2) void zgemm_pl2_kernel(
       const int idx = tid + NT * c, kc = idx & 3, i = (idx >> 2) % BM, pl = (idx >> 2) / BM;
       *reinterpret_cast<uint4 *>(&As[st][pl][i][8 * (kc ^ ((i >> 1) & 3))]) = ra[r][c];
     }
+    if constexpr (BF32) {
 #pragma unroll
-    for (int c = 0; c < CB; ++c) {
-      const int idx = tid + NT * c, kc = idx & 3, i = (idx >> 2) % BN, pl = (idx >> 2) / BN;
-      *reinterpret_cast<uint4 *>(&Bs[st][pl][i][8 * (kc ^ ((i >> 1) & 3))]) = rb[r][c];
+      for (int c = 0; c < CBF; ++c) {
+        const int sidx = tid + NT * c, kc = sidx & 3, i = sidx >> 2;
+        unsigned w[4][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint4 u = rb[r][4 * c + q];
+          const float re0 = __uint_as_float(u.x), im0 = __uint_as_float(u.y);
+          const float re1 = __uint_as_float(u.z), im1 = __uint_as_float(u.w);
+          const u16 hr0 = bf16_rn(re0), hi0 = bf16_rn(im0), hr1 = bf16_rn(re1),
+                    hi1 = bf16_rn(im1);
+          w[0][q] = hr0 | ((unsigned)hr1 << 16);
+          w[1][q] = hi0 | ((unsigned)hi1 << 16);
+          w[2][q] = bf16_rn(re0 - bf16_val(hr0)) | ((unsigned)bf16_rn(re1 - bf16_val(hr1)) << 16);
+          w[3][q] = bf16_rn(im0 - bf16_val(hi0)) | ((unsigned)bf16_rn(im1 - bf16_val(hi1)) << 16);
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          *reinterpret_cast<uint4 *>(&Bs[st][p][i][8 * (kc ^ ((i >> 1) & 3))]) =
+              make_uint4(w[p][0], w[p][1], w[p][2], w[p][3]);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        const int idx = tid + NT * c, kc = idx & 3, i = (idx >> 2) % BN, pl = (idx >> 2) / BN;
+        *reinterpret_cast<uint4 *>(&Bs[st][pl][i][8 * (kc ^ ((i >> 1) & 3))]) = rb[r][c];
+      }
     }
   };
 
@@ -966,6 +1020,17 @@ void proj_gemm_planes(int64_t nproj, int64_t nband, int64_t npw, const void *Apl
   const int64_t chunk = ((npw + splits - 1) / splits + XBK - 1) / XBK * XBK;
   launch_pl<true, true>(variant, dim3(1, 1, (unsigned)splits), nproj, nband, npw, Apl, lda, psa,
                         Ypl, ldy, psy, nullptr, 0, chunk, part, st);
+}
+
+void proj_gemm_planes_f32(int64_t nproj, int64_t nband, int64_t npw, const void *Apl, int64_t lda,
+                          int64_t psa, const void *Y, int64_t ldy, void *part, int splits,
+                          hipStream_t st) {
+  const int64_t chunk = ((npw + splits - 1) / splits + XBK - 1) / XBK * XBK;
+  dim3 grid((unsigned)((nproj + 127) / 128), (unsigned)((nband + 127) / 128), (unsigned)splits);
+  hipLaunchKernelGGL((zgemm_pl2_kernel<128, 128, 2, 4, true, true, 1, true>), grid, dim3(512), 0,
+                     st, nproj, nband, npw, (const u16 *)Apl, lda, psa, (const u16 *)Y, ldy,
+                     (int64_t)0, (float2 *)nullptr, (int64_t)0, chunk, (float2 *)part);
+  CHEBFI_HIP(hipGetLastError());
 }
 
 void expand_gemm_planes(int64_t npw, int64_t nband, int64_t nproj, const void *Apl, int64_t lda,

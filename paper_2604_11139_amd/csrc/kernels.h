@@ -73,6 +73,11 @@ int proj_planes_splits(int variant, int64_t nproj, int64_t nband, int64_t npw);
 void proj_gemm_planes(int64_t nproj, int64_t nband, int64_t npw, const void *Apl, int64_t lda,
                       int64_t psa, const void *Ypl, int64_t ldy, int64_t psy, void *part,
                       int splits, hipStream_t st, int variant);
+// part[z] = P^H Y for a complex float block Y (ld ldy), split into bf16 planes
+// inside the kernel while staged (the 128 x 128 double-buffered tile).
+void proj_gemm_planes_f32(int64_t nproj, int64_t nband, int64_t npw, const void *Apl, int64_t lda,
+                          int64_t psa, const void *Y, int64_t ldy, void *part, int splits,
+                          hipStream_t st);
 void expand_gemm_planes(int64_t npw, int64_t nband, int64_t nproj, const void *Apl, int64_t lda,
                         int64_t psa, const void *Cpl, int64_t ldc_pl, int64_t psc, void *Out,
                         int64_t ldo, hipStream_t st, int variant);
