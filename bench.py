@@ -48,6 +48,8 @@ def parse():
                     help="bands in the oracle's timed sample (0 skips the CPU baseline)")
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the measured copy / vendor-GEMM ceilings")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the adjoint and batched-workload legs")
     return ap.parse_args()
 
 
@@ -85,6 +87,82 @@ def measured_traffic(cls):
     if not k:
         return None
     return float(k["hbm_bytes_per_dispatch"])
+
+
+def _timed_ms(fn, reps=1):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def adjoint_leg(g, X32, v0, degree):
+    """The adjoint of the mixed filter (checkpoints every 4th step) on the same block,
+    timed beside one forward filter with the same bounds."""
+    import torch
+    bounds = g.spectral_bounds(X32, v0)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2604_11139_5)
+    Wt = torch.randn(X32.shape, dtype=torch.complex64, device="cuda", generator=gen)
+    Y = torch.empty_like(X32)
+    g.filter_backward(X32, Wt, degree, *bounds, ckpt_every=4)
+    fwd = _timed_ms(lambda: g.cheb_filter(X32, degree, *bounds, out=Y))
+    adj = _timed_ms(lambda: g.filter_backward(X32, Wt, degree, *bounds, ckpt_every=4))
+    nband = X32.shape[0]
+    del Wt, Y
+    return {"workload": "the large workload's mixed filter, gradients w.r.t. V_loc, D and X, "
+                        "iterates recomputed from checkpoints every 4th step",
+            "ms": round(adj, 2), "forward_ms": round(fwd, 2),
+            "ratio_to_forward": round(adj / fwd, 3),
+            "band_apps_per_s_forward_equivalent": round(degree * nband / (adj / 1e3), 1)}
+
+
+def batch_leg():
+    """The batched workload: 16 cells of uneven sizes (1014-6695 plane waves,
+    24^3-45^3 grids, 1856 bands), complex64, degree 8, filtered in one set of
+    launches replayed from a HIP graph after autotuning; beside it the same 16
+    filters one system at a time."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2604_11139_amd import binding as B
+
+    systems = W.make_batch()
+    with B.Batch(systems, precision=B.ABI_PREC_MIXED) as bt:
+        Xs, bounds = [], []
+        for s, m in zip(systems, bt.systems):
+            X = torch.from_numpy(W.random_block(m.npw, s.nband, s.tag).T).to("cuda")
+            v0 = torch.from_numpy(W.random_vector(m.npw, s.tag)).to("cuda")
+            X = X.to(torch.complex64)
+            Xs.append(X)
+            bounds.append(m.spectral_bounds(X, v0))
+        deg = W.BATCH["degree"]
+        choice = bt.autotune(Xs, deg, bounds)
+        Ys = bt.cheb_filter(Xs, deg, bounds)
+        torch.cuda.synchronize()
+        graph_ms = _timed_ms(lambda: bt.cheb_filter(Xs, deg, bounds, out=Ys), reps=5)
+        bt.use_graph(False)
+        eager_ms = _timed_ms(lambda: bt.cheb_filter(Xs, deg, bounds, out=Ys), reps=5)
+        single = [torch.empty_like(X) for X in Xs]
+
+        def one_by_one():
+            for m, X, Y, bd in zip(bt.systems, Xs, single, bounds):
+                m.cheb_filter(X, deg, *bd, out=Y)
+        one_by_one()
+        single_ms = _timed_ms(one_by_one, reps=3)
+        nb = int(np.sum([s.nband for s in systems]))
+    return {"workload": "16 cubic cells a=8..15 bohr, Ecut=12 Ha, k-point offsets, "
+                        "1014-6695 plane waves, 24^3-45^3 grids, 1-8 atoms, 1856 bands, "
+                        "complex64, degree 8",
+            "value": round(deg * nb / (graph_ms / 1e3), 1), "unit": "band-apps/s",
+            "ms_per_filter_graph": round(graph_ms, 3), "ms_per_filter_eager": round(eager_ms, 3),
+            "ms_one_system_at_a_time": round(single_ms, 3), "autotune": choice}
 
 
 def ceilings():
@@ -366,6 +444,9 @@ def main():
                 cmp[name] = {"max_abs_ha": float(dd.max()),
                              "lower_half_max_abs_ha": float(dd[: nband // 2].max())}
             out["eval_vs_oracle"] = cmp
+    if not args.no_extras and mixed:
+        out["adjoint"] = adjoint_leg(g, X32, v0, degree)
+        out["batch"] = batch_leg()
     if args.cpu_bands > 0:
         out["cpu_baseline"] = cpu_baseline(s, degree, head["bounds"], args.cpu_bands)
     print(json.dumps(out), flush=True)

@@ -28,6 +28,9 @@ namespace chebfi {
 
 namespace {
 
+// cubic edges with specialised batched passes
+#define CHEBFI_BATCH_SIZES(X) X(24) X(25) X(27) X(30) X(32) X(36) X(40) X(45) X(48) X(64)
+
 // item -> system by a scan of the prefix offsets off[0..nsys]
 __device__ __forceinline__ int find_sys(const int64_t *off, int nsys, int64_t item) {
   int s = 0;
@@ -121,26 +124,28 @@ __global__ __launch_bounds__(512) void bpass_a_kernel(const BatchSys *__restrict
     const BatchSys &d = sys[s];
     const BatchStep &st = step[s];
     const int n1 = d.plan.d[0].n, n2 = d.plan.d[1].n, n3 = d.plan.d[2].n;
-    const int nxy = n1 * n2;
+    const int nxy = n1 * n2, L1 = n1 + 1;  // LDS plane rows padded to n1 + 1
     const int64_t loc = item - off[s];
     const int64_t b = loc / n3;
     const int i3 = (int)(loc - b * n3);
-    C2<T> *tw1 = buf + nxy;
+    C2<T> *tw1 = buf + n2 * L1;
     C2<T> *tw2 = tw1 + n1;
     load_twiddles<T>(tw1, d.tw, n1);
     load_twiddles<T>(tw2, d.tw + kMaxN, n2);
-    for (int i = threadIdx.x; i < nxy; i += blockDim.x) buf[i] = C2<T>{0, 0};
+    for (int i = threadIdx.x; i < n2 * L1; i += blockDim.x) buf[i] = C2<T>{0, 0};
     __syncthreads();
     const int s0 = d.plane[i3], s1 = d.plane[i3 + 1];
     const C2<T> *xb = reinterpret_cast<const C2<T> *>(st.yk) + b * st.ldk;
     const int offp = i3 * nxy;
-    for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x)
-      buf[d.box_index[idx] - offp] = xb[idx];
+    for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x) {
+      const int e = d.box_index[idx] - offp;
+      buf[e + e / n1] = xb[idx];
+    }
     __syncthreads();
-    lds_fft<T>(buf, d.plan.d[0], 1, n2, n1, tw1, +1);
-    lds_fft<T>(buf, d.plan.d[1], n1, n1, 1, tw2, +1);
+    lds_fft<T>(buf, d.plan.d[0], 1, n2, L1, tw1, +1);
+    lds_fft<T>(buf, d.plan.d[1], L1, n1, 1, tw2, +1);
     C2<T> *dst = reinterpret_cast<C2<T> *>(d.box) + b * (int64_t)nxy * n3 + offp;
-    for (int i = threadIdx.x; i < nxy; i += blockDim.x) dst[i] = buf[i];
+    for (int i = threadIdx.x; i < nxy; i += blockDim.x) dst[i] = buf[i + i / n1];
     __syncthreads();
   }
 }
@@ -156,29 +161,29 @@ __global__ __launch_bounds__(512) void bpass_b_kernel(const BatchSys *__restrict
     const int s = find_sys(off, nsys, item);
     const BatchSys &d = sys[s];
     const int n1 = d.plan.d[0].n, n2 = d.plan.d[1].n, n3 = d.plan.d[2].n;
-    const int nxz = n1 * n3;
+    const int nxz = n1 * n3, L1 = n1 + 1;  // LDS slab rows padded to n1 + 1
     const int64_t loc = item - off[s];
     const int64_t b = loc / n2;
     const int i2 = (int)(loc - b * n2);
-    C2<T> *tw3 = buf + nxz;
+    C2<T> *tw3 = buf + n3 * L1;
     load_twiddles<T>(tw3, d.tw + 2 * kMaxN, n3);
     C2<T> *src = reinterpret_cast<C2<T> *>(d.box) + b * (int64_t)n1 * n2 * n3;
     const T *V = reinterpret_cast<const T *>(d.V);
     for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
       const int i1 = i % n1, i3 = i / n1;
-      buf[i] = src[i1 + n1 * (i2 + n2 * i3)];
+      buf[i3 * L1 + i1] = src[i1 + n1 * (i2 + n2 * i3)];
     }
     __syncthreads();
-    lds_fft<T>(buf, d.plan.d[2], n1, n1, 1, tw3, +1);
+    lds_fft<T>(buf, d.plan.d[2], L1, n1, 1, tw3, +1);
     for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
       const int i1 = i % n1, i3 = i / n1;
-      buf[i] = cscale(buf[i], V[i1 + n1 * (i2 + n2 * i3)]);
+      buf[i3 * L1 + i1] = cscale(buf[i3 * L1 + i1], V[i1 + n1 * (i2 + n2 * i3)]);
     }
     __syncthreads();
-    lds_fft<T>(buf, d.plan.d[2], n1, n1, 1, tw3, -1);
+    lds_fft<T>(buf, d.plan.d[2], L1, n1, 1, tw3, -1);
     for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
       const int i1 = i % n1, i3 = i / n1;
-      src[i1 + n1 * (i2 + n2 * i3)] = buf[i];
+      src[i1 + n1 * (i2 + n2 * i3)] = buf[i3 * L1 + i1];
     }
     __syncthreads();
   }
@@ -198,12 +203,12 @@ __global__ __launch_bounds__(512) void bpass_c_kernel(const BatchSys *__restrict
     const BatchSys &d = sys[s];
     const BatchStep &st = step[s];
     const int n1 = d.plan.d[0].n, n2 = d.plan.d[1].n, n3 = d.plan.d[2].n;
-    const int nxy = n1 * n2;
+    const int nxy = n1 * n2, L1 = n1 + 1;  // LDS plane rows padded to n1 + 1
     const int64_t loc = item - off[s];
     const int64_t b = loc / n3;
     const int i3 = (int)(loc - b * n3);
     const int np = d.nproj;
-    C2<T> *tw1 = buf + nxy;
+    C2<T> *tw1 = buf + n2 * L1;
     C2<T> *tw2 = tw1 + n1;
     C2<T> *cp = tw2 + n2;
     load_twiddles<T>(tw1, d.tw, n1);
@@ -212,10 +217,10 @@ __global__ __launch_bounds__(512) void bpass_c_kernel(const BatchSys *__restrict
       cp[threadIdx.x] = reinterpret_cast<const C2<T> *>(d.Cp)[b * np + threadIdx.x];
     const int offp = i3 * nxy;
     const C2<T> *src = reinterpret_cast<const C2<T> *>(d.box) + b * (int64_t)nxy * n3 + offp;
-    for (int i = threadIdx.x; i < nxy; i += blockDim.x) buf[i] = src[i];
+    for (int i = threadIdx.x; i < nxy; i += blockDim.x) buf[i + i / n1] = src[i];
     __syncthreads();
-    lds_fft<T>(buf, d.plan.d[1], n1, n1, 1, tw2, -1);
-    lds_fft<T>(buf, d.plan.d[0], 1, n2, n1, tw1, -1);
+    lds_fft<T>(buf, d.plan.d[1], L1, n1, 1, tw2, -1);
+    lds_fft<T>(buf, d.plan.d[0], 1, n2, L1, tw1, -1);
     const int s0 = d.plane[i3], s1 = d.plane[i3 + 1];
     const C2<T> *yk = reinterpret_cast<const C2<T> *>(st.yk) + b * st.ldk;
     const C2<T> *yp =
@@ -225,7 +230,147 @@ __global__ __launch_bounds__(512) void bpass_c_kernel(const BatchSys *__restrict
     const T alpha = (T)st.alpha, cshift = (T)st.cshift, beta = (T)st.beta;
     const T scale = (T)(1.0 / ((double)nxy * n3));
     for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x) {
-      const C2<T> lc = cscale(buf[d.box_index[idx] - offp], scale);
+      const int e = d.box_index[idx] - offp;
+      const C2<T> lc = cscale(buf[e + e / n1], scale);
+      const C2<T> x = yk[idx];
+      const T kd = (T)d.kin[idx] - cshift;
+      const C2<T> h = cadd(lc, cscale(x, kd));
+      C2<T> nl{0, 0};
+      for (int j = 0; j < np; ++j) nl = cadd(nl, cmul(P[idx + (int64_t)j * d.npw], cp[j]));
+      C2<T> o{alpha * h.x + nl.x, alpha * h.y + nl.y};
+      if (yp) {
+        const C2<T> p = yp[idx];
+        o.x -= beta * p.x;
+        o.y -= beta * p.y;
+      }
+      out[idx] = o;
+    }
+    __syncthreads();
+  }
+}
+
+// ---- specialised passes for the systems of one cubic edge N ----------------
+// Same three passes as above over the items of the systems listed in gsys
+// (prefix offsets goff: bands x N items each), with N, the radix sequence and
+// the plane strides known at compile time (the cubic building blocks).
+
+// item -> (system, band, plane) inside one edge group
+__device__ __forceinline__ int group_item(const int32_t *gsys, const int64_t *goff, int gns,
+                                          int64_t item, int N, int64_t *b, int *pl) {
+  const int q = find_sys(goff, gns, item);
+  const int64_t loc = item - goff[q];
+  *b = loc / N;
+  *pl = (int)(loc - *b * N);
+  return gsys[q];
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(kCT) void bcpass_a_kernel(const BatchSys *__restrict__ sys,
+                                                       const BatchStep *__restrict__ step,
+                                                       const int32_t *__restrict__ gsys,
+                                                       const int64_t *__restrict__ goff, int gns) {
+  constexpr int NXY = N * N, LD = N + 1;
+  __shared__ C2<T> buf[N * LD];
+  __shared__ C2<T> tw[N];
+  const int64_t total = goff[gns];
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    int64_t b;
+    int i3;
+    const int s = group_item(gsys, goff, gns, item, N, &b, &i3);
+    const BatchSys &d = sys[s];
+    const BatchStep &st = step[s];
+    for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(d.tw[i]);
+    for (int i = threadIdx.x; i < N * LD; i += kCT) buf[i] = C2<T>{0, 0};
+    __syncthreads();
+    const int s0 = d.plane[i3], s1 = d.plane[i3 + 1];
+    const C2<T> *xb = reinterpret_cast<const C2<T> *>(st.yk) + b * st.ldk;
+    const int off = i3 * NXY;
+    for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
+      const int e = d.box_index[idx] - off;
+      buf[e + e / N] = xb[idx];
+    }
+    __syncthreads();
+    cfft<T, N, 0, 1, N, 1, LD, +1>(buf, tw);
+    cfft<T, N, 0, 1, N, LD, 1, +1>(buf, tw);
+    C2<T> *dst = reinterpret_cast<C2<T> *>(d.box) + b * (int64_t)NXY * N + off;
+    for (int i = threadIdx.x; i < NXY; i += kCT) dst[i] = buf[i + i / N];
+    __syncthreads();
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(kCT) void bcpass_b_kernel(const BatchSys *__restrict__ sys,
+                                                       const int32_t *__restrict__ gsys,
+                                                       const int64_t *__restrict__ goff, int gns) {
+  constexpr int NXZ = N * N, LD = N + 1;
+  __shared__ C2<T> buf[N * LD];
+  __shared__ C2<T> tw[N];
+  const int64_t total = goff[gns];
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    int64_t b;
+    int i2;
+    const int s = group_item(gsys, goff, gns, item, N, &b, &i2);
+    const BatchSys &d = sys[s];
+    for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(d.tw[2 * kMaxN + i]);
+    C2<T> *src = reinterpret_cast<C2<T> *>(d.box) + b * (int64_t)N * N * N;
+    const T *V = reinterpret_cast<const T *>(d.V);
+    for (int i = threadIdx.x; i < NXZ; i += kCT) {
+      const int i1 = i % N, i3 = i / N;
+      buf[i3 * LD + i1] = src[i1 + N * (i2 + N * i3)];
+    }
+    __syncthreads();
+    cfft<T, N, 0, 1, N, LD, 1, +1>(buf, tw);
+    for (int i = threadIdx.x; i < NXZ; i += kCT) {
+      const int i1 = i % N, i3 = i / N;
+      buf[i3 * LD + i1] = cscale(buf[i3 * LD + i1], V[i1 + N * (i2 + N * i3)]);
+    }
+    __syncthreads();
+    cfft<T, N, 0, 1, N, LD, 1, -1>(buf, tw);
+    for (int i = threadIdx.x; i < NXZ; i += kCT) {
+      const int i1 = i % N, i3 = i / N;
+      src[i1 + N * (i2 + N * i3)] = buf[i3 * LD + i1];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(kCT) void bcpass_c_kernel(const BatchSys *__restrict__ sys,
+                                                       const BatchStep *__restrict__ step,
+                                                       const int32_t *__restrict__ gsys,
+                                                       const int64_t *__restrict__ goff, int gns) {
+  constexpr int NXY = N * N, LD = N + 1;
+  __shared__ C2<T> buf[N * LD];
+  __shared__ C2<T> tw[N];
+  __shared__ C2<T> cp[kBatchMaxProj];
+  const int64_t total = goff[gns];
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    int64_t b;
+    int i3;
+    const int s = group_item(gsys, goff, gns, item, N, &b, &i3);
+    const BatchSys &d = sys[s];
+    const BatchStep &st = step[s];
+    const int np = d.nproj;
+    for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(d.tw[i]);
+    if (threadIdx.x < np)
+      cp[threadIdx.x] = reinterpret_cast<const C2<T> *>(d.Cp)[b * np + threadIdx.x];
+    const int off = i3 * NXY;
+    const C2<T> *src = reinterpret_cast<const C2<T> *>(d.box) + b * (int64_t)NXY * N + off;
+    for (int i = threadIdx.x; i < NXY; i += kCT) buf[i + i / N] = src[i];
+    __syncthreads();
+    cfft<T, N, 0, 1, N, LD, 1, -1>(buf, tw);
+    cfft<T, N, 0, 1, N, 1, LD, -1>(buf, tw);
+    const int s0 = d.plane[i3], s1 = d.plane[i3 + 1];
+    const C2<T> *yk = reinterpret_cast<const C2<T> *>(st.yk) + b * st.ldk;
+    const C2<T> *yp =
+        st.yprev ? reinterpret_cast<const C2<T> *>(st.yprev) + b * st.ldp : nullptr;
+    C2<T> *out = reinterpret_cast<C2<T> *>(st.out) + b * st.ldo;
+    const C2<T> *P = reinterpret_cast<const C2<T> *>(d.P);
+    const T alpha = (T)st.alpha, cshift = (T)st.cshift, beta = (T)st.beta;
+    const T scale = (T)(1.0 / ((double)NXY * N));
+    for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
+      const int e = d.box_index[idx] - off;
+      const C2<T> lc = cscale(buf[e + e / N], scale);
       const C2<T> x = yk[idx];
       const T kd = (T)d.kin[idx] - cshift;
       const C2<T> h = cadd(lc, cscale(x, kd));
@@ -270,15 +415,61 @@ void batch_step(const BatchLaunch &L, int j, hipStream_t st) {
     CHEBFI_HIP(hipGetLastError());
   }
   const size_t e = sizeof(C2<T>);
-  hipLaunchKernelGGL(bpass_a_kernel<T>, grid(L.items_a), dim3(L.fft_threads), e * L.lds_a, st,
-                     L.d_sys, stp, offA, L.nsys);
-  CHEBFI_HIP(hipGetLastError());
-  hipLaunchKernelGGL(bpass_b_kernel<T>, grid(L.items_b), dim3(L.fft_threads), e * L.lds_b, st,
-                     L.d_sys, offB, L.nsys);
-  CHEBFI_HIP(hipGetLastError());
-  hipLaunchKernelGGL(bpass_c_kernel<T>, grid(L.items_a), dim3(L.fft_threads), e * L.lds_c, st,
-                     L.d_sys, stp, offA, L.nsys);
-  CHEBFI_HIP(hipGetLastError());
+  // systems on cubic boxes with specialised passes: one launch per edge and pass
+  auto cubic = [&](int pass) {
+    for (int gi = 0; gi < L.ngroups; ++gi) {
+      const BatchGroup &G = L.groups[gi];
+      const dim3 gr = grid(G.items);
+#define CHEBFI_CASE(N_)                                                                       \
+  case N_:                                                                                    \
+    if (pass == 0)                                                                            \
+      hipLaunchKernelGGL((bcpass_a_kernel<T, N_>), gr, dim3(kCT), 0, st, L.d_sys, stp, G.gsys, \
+                         G.goff, G.nsys);                                                     \
+    else if (pass == 1)                                                                       \
+      hipLaunchKernelGGL((bcpass_b_kernel<T, N_>), gr, dim3(kCT), 0, st, L.d_sys, G.gsys,      \
+                         G.goff, G.nsys);                                                     \
+    else                                                                                      \
+      hipLaunchKernelGGL((bcpass_c_kernel<T, N_>), gr, dim3(kCT), 0, st, L.d_sys, stp, G.gsys, \
+                         G.goff, G.nsys);                                                     \
+    break;
+      switch (G.n) {
+        CHEBFI_BATCH_SIZES(CHEBFI_CASE)
+        default:
+          break;
+      }
+#undef CHEBFI_CASE
+      CHEBFI_HIP(hipGetLastError());
+    }
+  };
+  cubic(0);
+  if (L.items_a > 0) {
+    hipLaunchKernelGGL(bpass_a_kernel<T>, grid(L.items_a), dim3(L.fft_threads), e * L.lds_a, st,
+                       L.d_sys, stp, offA, L.nsys);
+    CHEBFI_HIP(hipGetLastError());
+  }
+  cubic(1);
+  if (L.items_b > 0) {
+    hipLaunchKernelGGL(bpass_b_kernel<T>, grid(L.items_b), dim3(L.fft_threads), e * L.lds_b, st,
+                       L.d_sys, offB, L.nsys);
+    CHEBFI_HIP(hipGetLastError());
+  }
+  cubic(2);
+  if (L.items_a > 0) {
+    hipLaunchKernelGGL(bpass_c_kernel<T>, grid(L.items_a), dim3(L.fft_threads), e * L.lds_c, st,
+                       L.d_sys, stp, offA, L.nsys);
+    CHEBFI_HIP(hipGetLastError());
+  }
+}
+
+bool batch_edge_specialised(int n) {
+  switch (n) {
+#define CHEBFI_CASE(N_) case N_:
+    CHEBFI_BATCH_SIZES(CHEBFI_CASE)
+#undef CHEBFI_CASE
+    return true;
+    default:
+      return false;
+  }
 }
 
 template <typename T>

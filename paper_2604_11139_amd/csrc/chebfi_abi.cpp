@@ -491,8 +491,8 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
     min_threads = std::max({min_threads, fft_stage_threads(s->plan.d[0], s->n2),
                             fft_stage_threads(s->plan.d[1], s->n1),
                             fft_stage_threads(s->plan.d[2], s->n1)});
-    lds_a = std::max(lds_a, (size_t)(s->n1 * s->n2 + s->n1 + s->n2));
-    lds_b = std::max(lds_b, (size_t)(s->n1 * s->n3 + s->n3));
+    lds_a = std::max(lds_a, (size_t)(s->n2 * (s->n1 + 1) + s->n1 + s->n2));
+    lds_b = std::max(lds_b, (size_t)(s->n3 * (s->n1 + 1) + s->n3));
     any_proj = any_proj || s->nproj > 0;
   }
   CHEBFI_REQUIRE(min_threads <= 512, ABI_ERR_GRID, "FFT plane too large for one workgroup");
@@ -518,8 +518,40 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
     d.box = ws + o_box[i];
     d.Cp = ws + o_cp[i];
     offP[i + 1] = offP[i] + nband[i];
-    offA[i + 1] = offA[i] + nband[i] * s->n3;
-    offB[i + 1] = offB[i] + nband[i] * s->n2;
+    // systems on cubic boxes with specialised passes go to their edge group and
+    // contribute no items to the runtime-size passes
+    const bool grouped = s->n1 == s->n2 && s->n1 == s->n3 && batch_edge_specialised(s->n1) &&
+                         !std::getenv("CHEBFI_GENERIC_FFT");
+    offA[i + 1] = offA[i] + (grouped ? 0 : nband[i] * s->n3);
+    offB[i + 1] = offB[i] + (grouped ? 0 : nband[i] * s->n2);
+  }
+  // edge groups: system lists and item offsets (appended to the device table)
+  std::vector<int> gedge;
+  std::vector<std::vector<int32_t>> glist;
+  for (int i = 0; i < nsys; ++i) {
+    const abi_system_s *s = B->sys[i];
+    if (offA[i + 1] != offA[i] || !(s->n1 == s->n2 && s->n1 == s->n3)) continue;
+    if (!batch_edge_specialised(s->n1) || std::getenv("CHEBFI_GENERIC_FFT")) continue;
+    size_t g = 0;
+    while (g < gedge.size() && gedge[g] != s->n1) ++g;
+    if (g == gedge.size()) {
+      gedge.push_back(s->n1);
+      glist.emplace_back();
+    }
+    glist[g].push_back(i);
+  }
+  CHEBFI_REQUIRE((int)gedge.size() <= kBatchMaxGroups, ABI_ERR_ARG, "too many box sizes");
+  std::vector<int32_t> hgsys;
+  std::vector<int64_t> hgoff;
+  std::vector<size_t> gsys_at, goff_at;
+  for (size_t g = 0; g < gedge.size(); ++g) {
+    gsys_at.push_back(hgsys.size());
+    goff_at.push_back(hgoff.size());
+    hgoff.push_back(0);
+    for (int32_t i : glist[g]) {
+      hgsys.push_back(i);
+      hgoff.push_back(hgoff.back() + nband[i] * gedge[g]);
+    }
   }
   // step table: Y_0 = X, Y_m = Y, Y_j (0 < j < m) in slot j % 2 (the update of
   // step j reads Y_{j-2} and writes Y_j element by element in the same thread)
@@ -565,7 +597,9 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
   const size_t t_sys = al(sizeof(BatchSys) * (size_t)nsys);
   const size_t t_steps = al(sizeof(BatchStep) * B->hsteps.size());
   const size_t t_off = al(sizeof(int64_t) * B->hoff.size());
-  const size_t t_all = t_sys + t_steps + t_off;
+  const size_t t_gsys = al(sizeof(int32_t) * std::max<size_t>(hgsys.size(), 1));
+  const size_t t_goff = al(sizeof(int64_t) * std::max<size_t>(hgoff.size(), 1));
+  const size_t t_all = t_sys + t_steps + t_off + t_gsys + t_goff;
   if (B->tab_copied) CHEBFI_HIP(hipEventSynchronize(B->tab_copied));
   if (B->h_tab_bytes < t_all) {
     if (B->h_tab) CHEBFI_HIP(hipHostFree(B->h_tab));
@@ -579,6 +613,11 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
   std::memcpy(ht, B->hsys.data(), sizeof(BatchSys) * (size_t)nsys);
   std::memcpy(ht + t_sys, B->hsteps.data(), sizeof(BatchStep) * B->hsteps.size());
   std::memcpy(ht + t_sys + t_steps, B->hoff.data(), sizeof(int64_t) * B->hoff.size());
+  if (!hgsys.empty())
+    std::memcpy(ht + t_sys + t_steps + t_off, hgsys.data(), sizeof(int32_t) * hgsys.size());
+  if (!hgoff.empty())
+    std::memcpy(ht + t_sys + t_steps + t_off + t_gsys, hgoff.data(),
+                sizeof(int64_t) * hgoff.size());
   char *dt = (char *)B->d_tab.get(t_all);
   CHEBFI_HIP(hipMemcpyAsync(dt, ht, t_all, hipMemcpyHostToDevice, st));
   CHEBFI_HIP(hipEventRecord(B->tab_copied, st));
@@ -592,6 +631,15 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
   L.items_a = offA[nsys];
   L.items_b = offB[nsys];
   L.max_wgs = 2048;
+  L.ngroups = (int)gedge.size();
+  for (size_t g = 0; g < gedge.size(); ++g) {
+    BatchGroup &G = L.groups[g];
+    G.n = gedge[g];
+    G.nsys = (int)glist[g].size();
+    G.gsys = (const int32_t *)(dt + t_sys + t_steps + t_off) + gsys_at[g];
+    G.goff = (const int64_t *)(dt + t_sys + t_steps + t_off + t_gsys) + goff_at[g];
+    G.items = hgoff[goff_at[g] + G.nsys];
+  }
   L.fft_threads = B->fft_threads;
   L.proj_threads = B->proj_threads;
   L.lds_a = lds_a;

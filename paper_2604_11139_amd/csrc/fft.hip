@@ -37,24 +37,27 @@ __global__ __launch_bounds__(512) void pass_a_kernel(const C2<T> *__restrict__ X
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
   const int n1 = plan.d[0].n, n2 = plan.d[1].n, n3 = plan.d[2].n;
-  const int nxy = n1 * n2;
-  C2<T> *tw1 = buf + nxy;
+  const int nxy = n1 * n2, L1 = n1 + 1;  // LDS plane rows padded to n1 + 1
+  C2<T> *tw1 = buf + n2 * L1;
   C2<T> *tw2 = tw1 + n1;
   const int i3 = blockIdx.x;
   const int bl = blockIdx.y;
   load_twiddles<T>(tw1, twg, n1);
   load_twiddles<T>(tw2, twg + kMaxN, n2);
-  for (int i = threadIdx.x; i < nxy; i += blockDim.x) buf[i] = C2<T>{0, 0};
+  for (int i = threadIdx.x; i < n2 * L1; i += blockDim.x) buf[i] = C2<T>{0, 0};
   __syncthreads();
   const int s0 = plane[i3], s1 = plane[i3 + 1];
   const C2<T> *xb = X + (int64_t)(band0 + bl) * ldx;
   const int off = i3 * nxy;
-  for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x) buf[box_index[idx] - off] = xb[idx];
+  for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x) {
+    const int e = box_index[idx] - off;
+    buf[e + e / n1] = xb[idx];
+  }
   __syncthreads();
-  lds_fft<T>(buf, plan.d[0], 1, n2, n1, tw1, +1);
-  lds_fft<T>(buf, plan.d[1], n1, n1, 1, tw2, +1);
+  lds_fft<T>(buf, plan.d[0], 1, n2, L1, tw1, +1);
+  lds_fft<T>(buf, plan.d[1], L1, n1, 1, tw2, +1);
   C2<T> *dst = box + (int64_t)bl * nxy * n3 + off;
-  for (int i = threadIdx.x; i < nxy; i += blockDim.x) dst[i] = buf[i];
+  for (int i = threadIdx.x; i < nxy; i += blockDim.x) dst[i] = buf[i + i / n1];
 }
 
 // ---- pass B: z pencils of one i2 slab, inverse FFT, * V, forward FFT -------
@@ -64,27 +67,27 @@ __global__ __launch_bounds__(512) void pass_b_kernel(C2<T> *__restrict__ box, co
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
   const int n1 = plan.d[0].n, n2 = plan.d[1].n, n3 = plan.d[2].n;
-  const int nxz = n1 * n3;
-  C2<T> *tw3 = buf + nxz;
+  const int nxz = n1 * n3, L1 = n1 + 1;  // LDS slab rows padded to n1 + 1
+  C2<T> *tw3 = buf + n3 * L1;
   const int i2 = blockIdx.x;
   const int bl = blockIdx.y;
   load_twiddles<T>(tw3, twg + 2 * kMaxN, n3);
   C2<T> *src = box + (int64_t)bl * n1 * n2 * n3;
   for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
     const int i1 = i % n1, i3 = i / n1;
-    buf[i] = src[i1 + n1 * (i2 + n2 * i3)];
+    buf[i3 * L1 + i1] = src[i1 + n1 * (i2 + n2 * i3)];
   }
   __syncthreads();
-  lds_fft<T>(buf, plan.d[2], n1, n1, 1, tw3, +1);
+  lds_fft<T>(buf, plan.d[2], L1, n1, 1, tw3, +1);
   for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
     const int i1 = i % n1, i3 = i / n1;
-    buf[i] = cscale(buf[i], (T)V[i1 + n1 * (i2 + n2 * i3)]);
+    buf[i3 * L1 + i1] = cscale(buf[i3 * L1 + i1], (T)V[i1 + n1 * (i2 + n2 * i3)]);
   }
   __syncthreads();
-  lds_fft<T>(buf, plan.d[2], n1, n1, 1, tw3, -1);
+  lds_fft<T>(buf, plan.d[2], L1, n1, 1, tw3, -1);
   for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
     const int i1 = i % n1, i3 = i / n1;
-    src[i1 + n1 * (i2 + n2 * i3)] = buf[i];
+    src[i1 + n1 * (i2 + n2 * i3)] = buf[i3 * L1 + i1];
   }
 }
 
@@ -101,8 +104,8 @@ __global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ b
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
   const int n1 = plan.d[0].n, n2 = plan.d[1].n;
-  const int nxy = n1 * n2;
-  C2<T> *tw1 = buf + nxy;
+  const int nxy = n1 * n2, L1 = n1 + 1;  // LDS plane rows padded to n1 + 1
+  C2<T> *tw1 = buf + n2 * L1;
   C2<T> *tw2 = tw1 + n1;
   const int i3 = blockIdx.x;
   const int bl = blockIdx.y;
@@ -110,10 +113,10 @@ __global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ b
   load_twiddles<T>(tw2, twg + kMaxN, n2);
   const int off = i3 * nxy;
   const C2<T> *src = box + (int64_t)bl * nxy * plan.d[2].n + off;
-  for (int i = threadIdx.x; i < nxy; i += blockDim.x) buf[i] = src[i];
+  for (int i = threadIdx.x; i < nxy; i += blockDim.x) buf[i + i / n1] = src[i];
   __syncthreads();
-  lds_fft<T>(buf, plan.d[1], n1, n1, 1, tw2, -1);
-  lds_fft<T>(buf, plan.d[0], 1, n2, n1, tw1, -1);
+  lds_fft<T>(buf, plan.d[1], L1, n1, 1, tw2, -1);
+  lds_fft<T>(buf, plan.d[0], 1, n2, L1, tw1, -1);
   const int s0 = plane[i3], s1 = plane[i3 + 1];
   const int64_t b = band0 + bl;
   const C2<T> *yk = Yk + b * ldk;
@@ -121,7 +124,8 @@ __global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ b
   if (Yprev != nullptr) {
     const C2<T> *yp = Yprev + b * ldp;
     for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x) {
-      C2<T> loc = cscale(buf[box_index[idx] - off], scale);
+      const int e = box_index[idx] - off;
+      C2<T> loc = cscale(buf[e + e / n1], scale);
       C2<T> x = yk[idx];
       const T kd = (T)kin[idx] - cshift;
       C2<T> h = cadd(loc, cscale(x, kd));
@@ -130,7 +134,8 @@ __global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ b
     }
   } else {
     for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x) {
-      C2<T> loc = cscale(buf[box_index[idx] - off], scale);
+      const int e = box_index[idx] - off;
+      C2<T> loc = cscale(buf[e + e / n1], scale);
       C2<T> x = yk[idx];
       const T kd = (T)kin[idx] - cshift;
       C2<T> h = cadd(loc, cscale(x, kd));
@@ -147,21 +152,21 @@ __global__ __launch_bounds__(512) void pass_b_inv_kernel(C2<T> *__restrict__ box
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
   const int n1 = plan.d[0].n, n2 = plan.d[1].n, n3 = plan.d[2].n;
-  const int nxz = n1 * n3;
-  C2<T> *tw3 = buf + nxz;
+  const int nxz = n1 * n3, L1 = n1 + 1;  // LDS slab rows padded to n1 + 1
+  C2<T> *tw3 = buf + n3 * L1;
   const int i2 = blockIdx.x;
   const int bl = blockIdx.y;
   load_twiddles<T>(tw3, twg + 2 * kMaxN, n3);
   C2<T> *src = box + (int64_t)bl * n1 * n2 * n3;
   for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
     const int i1 = i % n1, i3 = i / n1;
-    buf[i] = src[i1 + n1 * (i2 + n2 * i3)];
+    buf[i3 * L1 + i1] = src[i1 + n1 * (i2 + n2 * i3)];
   }
   __syncthreads();
-  lds_fft<T>(buf, plan.d[2], n1, n1, 1, tw3, +1);
+  lds_fft<T>(buf, plan.d[2], L1, n1, 1, tw3, +1);
   for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
     const int i1 = i % n1, i3 = i / n1;
-    src[i1 + n1 * (i2 + n2 * i3)] = buf[i];
+    src[i1 + n1 * (i2 + n2 * i3)] = buf[i3 * L1 + i1];
   }
 }
 
@@ -176,8 +181,8 @@ __global__ __launch_bounds__(512) void pass_b_adj_kernel(C2<T> *__restrict__ box
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
   const int n1 = plan.d[0].n, n2 = plan.d[1].n, n3 = plan.d[2].n;
-  const int nxz = n1 * n3;
-  C2<T> *tw3 = buf + nxz;
+  const int nxz = n1 * n3, L1 = n1 + 1;  // LDS slab rows padded to n1 + 1
+  C2<T> *tw3 = buf + n3 * L1;
   const int i2 = blockIdx.x;
   const int bl = blockIdx.y;
   load_twiddles<T>(tw3, twg + 2 * kMaxN, n3);
@@ -185,22 +190,22 @@ __global__ __launch_bounds__(512) void pass_b_adj_kernel(C2<T> *__restrict__ box
   C2<T> *fw = fwd + (int64_t)bl * n1 * n2 * n3;
   for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
     const int i1 = i % n1, i3 = i / n1;
-    buf[i] = src[i1 + n1 * (i2 + n2 * i3)];
+    buf[i3 * L1 + i1] = src[i1 + n1 * (i2 + n2 * i3)];
   }
   __syncthreads();
-  lds_fft<T>(buf, plan.d[2], n1, n1, 1, tw3, +1);
+  lds_fft<T>(buf, plan.d[2], L1, n1, 1, tw3, +1);
   for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
     const int i1 = i % n1, i3 = i / n1;
     const int64_t r = i1 + n1 * (i2 + n2 * i3);
-    const C2<T> a = buf[i], y = fw[r];
+    const C2<T> a = buf[i3 * L1 + i1], y = fw[r];
     fw[r] = C2<T>{a.x * y.x + a.y * y.y, (T)0};
-    buf[i] = cscale(a, V[r]);
+    buf[i3 * L1 + i1] = cscale(a, V[r]);
   }
   __syncthreads();
-  lds_fft<T>(buf, plan.d[2], n1, n1, 1, tw3, -1);
+  lds_fft<T>(buf, plan.d[2], L1, n1, 1, tw3, -1);
   for (int i = threadIdx.x; i < nxz; i += blockDim.x) {
     const int i1 = i % n1, i3 = i / n1;
-    src[i1 + n1 * (i2 + n2 * i3)] = buf[i];
+    src[i1 + n1 * (i2 + n2 * i3)] = buf[i3 * L1 + i1];
   }
 }
 
@@ -233,90 +238,7 @@ __global__ __launch_bounds__(256) void rho_accum_kernel(int64_t nbox, int nb, in
   rho[r] += scale * acc;
 }
 
-// ---- compile-time specialised passes for cubic boxes ------------------------
-// Same three passes as above with the box edge N, the radix sequence, the
-// pencil strides and the thread count known at compile time, so that all
-// index arithmetic reduces to constant multiplies and shifts.  A plane sits in
-// LDS with a row stride of N + 1 elements, and the lanes of a wave take
-// consecutive pencils in both directions: pencils along a row are then an odd
-// stride apart, which spreads a wave's accesses over all LDS banks.
-template <int N> struct CPlan;
-#define CHEBFI_CPLAN(N_, NS_, R0_, R1_, R2_)                              \
-  template <> struct CPlan<N_> {                                          \
-    static constexpr int ns = NS_;                                        \
-    static constexpr int r[3] = {R0_, R1_, R2_};                          \
-  };
-CHEBFI_CPLAN(12, 2, 4, 3, 1)
-CHEBFI_CPLAN(15, 2, 5, 3, 1)
-CHEBFI_CPLAN(16, 2, 4, 4, 1)
-CHEBFI_CPLAN(18, 2, 6, 3, 1)
-CHEBFI_CPLAN(20, 2, 5, 4, 1)
-CHEBFI_CPLAN(24, 2, 8, 3, 1)
-CHEBFI_CPLAN(25, 2, 5, 5, 1)
-CHEBFI_CPLAN(27, 3, 3, 3, 3)
-CHEBFI_CPLAN(30, 2, 6, 5, 1)
-CHEBFI_CPLAN(32, 2, 8, 4, 1)
-CHEBFI_CPLAN(36, 2, 6, 6, 1)
-CHEBFI_CPLAN(40, 2, 8, 5, 1)
-CHEBFI_CPLAN(45, 3, 5, 3, 3)
-CHEBFI_CPLAN(48, 2, 8, 6, 1)
-CHEBFI_CPLAN(64, 2, 8, 8, 1)
-#undef CHEBFI_CPLAN
-
-constexpr int kCT = 512;  // threads of the specialised passes (16 waves per CU per 4 planes)
-
-template <typename T, int N, int R, int P, int NPEN, int ES, int PS, int SGN>
-__device__ __forceinline__ void cstage(C2<T> *buf, const C2<T> *tw) {
-  constexpr int NBF = N / R;
-  constexpr int TOTAL = NPEN * NBF;
-  constexpr int M = N / (P * R);
-  constexpr int MAXB = (TOTAL + kCT - 1) / kCT;
-  C2<T> y[MAXB][R];
-  int dst[MAXB];
-#pragma unroll
-  for (int c = 0; c < MAXB; ++c) {
-    const int i = threadIdx.x + c * kCT;
-    dst[c] = -1;
-    if (TOTAL % kCT == 0 || i < TOTAL) {
-      const int pen = i % NPEN, bf = i / NPEN;
-      const int base = pen * PS;
-      C2<T> x[R];
-#pragma unroll
-      for (int t = 0; t < R; ++t) x[t] = buf[base + (bf + t * NBF) * ES];
-      const int k = bf % P;
-      if (P > 1) {
-#pragma unroll
-        for (int t = 1; t < R; ++t) {
-          C2<T> w = tw[t * k * M];
-          if (SGN > 0) w.y = -w.y;
-          x[t] = cmul(x[t], w);
-        }
-      }
-      Dft<T, R>::run(x, SGN);
-#pragma unroll
-      for (int t = 0; t < R; ++t) y[c][t] = x[t];
-      dst[c] = base + ((bf - k) * R + k) * ES;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < MAXB; ++c) {
-    if (TOTAL % kCT == 0 || dst[c] >= 0) {
-#pragma unroll
-      for (int t = 0; t < R; ++t) buf[dst[c] + t * P * ES] = y[c][t];
-    }
-  }
-  __syncthreads();
-}
-
-template <typename T, int N, int S, int P, int NPEN, int ES, int PS, int SGN>
-__device__ __forceinline__ void cfft(C2<T> *buf, const C2<T> *tw) {
-  if constexpr (S < CPlan<N>::ns) {
-    constexpr int R = CPlan<N>::r[S];
-    cstage<T, N, R, P, NPEN, ES, PS, SGN>(buf, tw);
-    cfft<T, N, S + 1, P * R, NPEN, ES, PS, SGN>(buf, tw);
-  }
-}
+// ---- compile-time specialised passes for cubic boxes (building blocks in fft_dev.h) ----
 
 template <typename T, int N>
 __global__ __launch_bounds__(kCT) void cpass_a_kernel(const C2<T> *__restrict__ X, int64_t ldx,
@@ -366,6 +288,66 @@ __global__ __launch_bounds__(kCT) void cpass_b_kernel(C2<T> *__restrict__ box,
   for (int i = threadIdx.x; i < NXZ; i += kCT) {
     const int i1 = i % N, i3 = i / N;
     buf[i3 * LD + i1] = cscale(buf[i3 * LD + i1], (T)V[i1 + N * (i2 + N * i3)]);
+  }
+  __syncthreads();
+  cfft<T, N, 0, 1, N, LD, 1, -1>(buf, tw);
+  for (int i = threadIdx.x; i < NXZ; i += kCT) {
+    const int i1 = i % N, i3 = i / N;
+    src[i1 + N * (i2 + N * i3)] = buf[i3 * LD + i1];
+  }
+}
+
+// z-inverse FFT only (the box then holds the bands in real space).
+template <typename T, int N>
+__global__ __launch_bounds__(kCT) void cpass_b_inv_kernel(C2<T> *__restrict__ box,
+                                                          const double2 *__restrict__ twg) {
+  constexpr int NXZ = N * N, LD = N + 1;
+  __shared__ C2<T> buf[N * LD];
+  __shared__ C2<T> tw[N];
+  const int i2 = blockIdx.x;
+  const int bl = blockIdx.y;
+  for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(twg[2 * kMaxN + i]);
+  C2<T> *src = box + (int64_t)bl * N * N * N;
+  for (int i = threadIdx.x; i < NXZ; i += kCT) {
+    const int i1 = i % N, i3 = i / N;
+    buf[i3 * LD + i1] = src[i1 + N * (i2 + N * i3)];
+  }
+  __syncthreads();
+  cfft<T, N, 0, 1, N, LD, 1, +1>(buf, tw);
+  for (int i = threadIdx.x; i < NXZ; i += kCT) {
+    const int i1 = i % N, i3 = i / N;
+    src[i1 + N * (i2 + N * i3)] = buf[i3 * LD + i1];
+  }
+}
+
+// Adjoint pass B: z-inverse of the adjoint band, Re[conj(adjoint) * forward]
+// written over the forward band's real-space box (real part), then * V and the
+// z-forward FFT of the adjoint band.
+template <typename T, typename VT, int N>
+__global__ __launch_bounds__(kCT) void cpass_b_adj_kernel(C2<T> *__restrict__ box,
+                                                          C2<T> *__restrict__ fwd,
+                                                          const VT *__restrict__ V,
+                                                          const double2 *__restrict__ twg) {
+  constexpr int NXZ = N * N, LD = N + 1;
+  __shared__ C2<T> buf[N * LD];
+  __shared__ C2<T> tw[N];
+  const int i2 = blockIdx.x;
+  const int bl = blockIdx.y;
+  for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(twg[2 * kMaxN + i]);
+  C2<T> *src = box + (int64_t)bl * N * N * N;
+  C2<T> *fw = fwd + (int64_t)bl * N * N * N;
+  for (int i = threadIdx.x; i < NXZ; i += kCT) {
+    const int i1 = i % N, i3 = i / N;
+    buf[i3 * LD + i1] = src[i1 + N * (i2 + N * i3)];
+  }
+  __syncthreads();
+  cfft<T, N, 0, 1, N, LD, 1, +1>(buf, tw);
+  for (int i = threadIdx.x; i < NXZ; i += kCT) {
+    const int i1 = i % N, i3 = i / N;
+    const int64_t r = i1 + N * (i2 + N * i3);
+    const C2<T> a = buf[i3 * LD + i1], y = fw[r];
+    fw[r] = C2<T>{a.x * y.x + a.y * y.y, (T)0};
+    buf[i3 * LD + i1] = cscale(a, (T)V[r]);
   }
   __syncthreads();
   cfft<T, N, 0, 1, N, LD, 1, -1>(buf, tw);
@@ -449,6 +431,90 @@ void launch_cubic(const abi_system_s *s, const void *Yk, int64_t ldk, const void
   if (prof) prof->end(tok, st);
 }
 
+template <typename T, int N>
+void adjoint_cubic(const abi_system_s *s, const void *Ak1, int64_t lda1, const void *Yk,
+                   int64_t ldy, void *Ak, int64_t ldak, bool accumulate, int band0, int nb,
+                   void *box1, void *box2, const void *V, double gamma, double cshift, double *dV,
+                   hipStream_t st) {
+  typedef C2<T> V2;
+  typedef typename std::conditional<std::is_same<T, double>::value, double, float>::type VT;
+  const double2 *tw = reinterpret_cast<const double2 *>(s->d_tw);
+  V2 *b1 = reinterpret_cast<V2 *>(box1);
+  V2 *b2 = reinterpret_cast<V2 *>(box2);
+  hipLaunchKernelGGL((cpass_a_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st,
+                     reinterpret_cast<const V2 *>(Ak1), lda1, band0, s->d_box, s->d_plane, tw, b1);
+  hipLaunchKernelGGL((cpass_a_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st,
+                     reinterpret_cast<const V2 *>(Yk), ldy, band0, s->d_box, s->d_plane, tw, b2);
+  hipLaunchKernelGGL((cpass_b_inv_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st, b2, tw);
+  hipLaunchKernelGGL((cpass_b_adj_kernel<T, VT, N>), dim3(N, nb), dim3(kCT), 0, st, b1, b2,
+                     reinterpret_cast<const VT *>(V), tw);
+  const int64_t nbox = (int64_t)N * N * N;
+  hipLaunchKernelGGL(dv_reduce_kernel<T>, dim3((unsigned)((nbox + 255) / 256)), dim3(256), 0, st,
+                     nbox, nb, (const V2 *)b2, gamma / (double)nbox, dV);
+  const T scale = (T)(1.0 / (double)nbox);
+  hipLaunchKernelGGL((cpass_c_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st, b1, tw, s->d_box,
+                     s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Ak1), lda1,
+                     accumulate ? reinterpret_cast<const V2 *>(Ak) : (const V2 *)nullptr, ldak,
+                     reinterpret_cast<V2 *>(Ak), ldak, (T)gamma, (T)cshift, (T)-1, scale);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+template <typename T, int N>
+void density_cubic(const abi_system_s *s, const void *Psi, int64_t ld, int band0, int nb,
+                   void *box, const double *w, double *rho, hipStream_t st) {
+  typedef C2<T> V2;
+  const double2 *tw = reinterpret_cast<const double2 *>(s->d_tw);
+  V2 *bx = reinterpret_cast<V2 *>(box);
+  hipLaunchKernelGGL((cpass_a_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st,
+                     reinterpret_cast<const V2 *>(Psi), ld, band0, s->d_box, s->d_plane, tw, bx);
+  hipLaunchKernelGGL((cpass_b_inv_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st, bx, tw);
+  const int64_t nbox = (int64_t)N * N * N;
+  hipLaunchKernelGGL(rho_accum_kernel<T>, dim3((unsigned)((nbox + 255) / 256)), dim3(256), 0, st,
+                     nbox, nb, band0, (const V2 *)bx, w, 1.0 / (double)nbox, rho);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+// Edges with compile-time specialised passes (cubic boxes).
+#define CHEBFI_CUBIC_SIZES(X) \
+  X(12) X(15) X(16) X(18) X(20) X(24) X(25) X(27) X(30) X(32) X(36) X(40) X(45) X(48) X(64)
+
+template <typename T>
+bool try_cubic_adjoint(const abi_system_s *s, const void *Ak1, int64_t lda1, const void *Yk,
+                       int64_t ldy, void *Ak, int64_t ldak, bool accumulate, int band0, int nb,
+                       void *box1, void *box2, const void *V, double gamma, double cshift,
+                       double *dV, hipStream_t st) {
+  if (s->n1 != s->n2 || s->n1 != s->n3) return false;
+  if (std::getenv("CHEBFI_GENERIC_FFT")) return false;
+#define CHEBFI_CASE(N_)                                                                      \
+  case N_:                                                                                   \
+    adjoint_cubic<T, N_>(s, Ak1, lda1, Yk, ldy, Ak, ldak, accumulate, band0, nb, box1, box2, \
+                         V, gamma, cshift, dV, st);                                          \
+    return true;
+  switch (s->n1) {
+    CHEBFI_CUBIC_SIZES(CHEBFI_CASE)
+    default:
+      return false;
+  }
+#undef CHEBFI_CASE
+}
+
+template <typename T>
+bool try_cubic_density(const abi_system_s *s, const void *Psi, int64_t ld, int band0, int nb,
+                       void *box, const double *w, double *rho, hipStream_t st) {
+  if (s->n1 != s->n2 || s->n1 != s->n3) return false;
+  if (std::getenv("CHEBFI_GENERIC_FFT")) return false;
+#define CHEBFI_CASE(N_)                                                       \
+  case N_:                                                                    \
+    density_cubic<T, N_>(s, Psi, ld, band0, nb, box, w, rho, st);             \
+    return true;
+  switch (s->n1) {
+    CHEBFI_CUBIC_SIZES(CHEBFI_CASE)
+    default:
+      return false;
+  }
+#undef CHEBFI_CASE
+}
+
 template <typename T>
 bool try_cubic(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Yprev, int64_t ldp,
                void *Out, int64_t ldo, int band0, int nb, void *box, const void *V, double alpha,
@@ -502,8 +568,8 @@ void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, 
   const int tA = std::max(stage_threads(plan.d[0], n2), stage_threads(plan.d[1], n1));
   const int tB = stage_threads(plan.d[2], n1);
   CHEBFI_REQUIRE(tA <= 512 && tB <= 512, ABI_ERR_GRID, "FFT plane too large for one workgroup");
-  const size_t ldsA = sizeof(V2) * (size_t)(n1 * n2 + n1 + n2);
-  const size_t ldsB = sizeof(V2) * (size_t)(n1 * n3 + n3);
+  const size_t ldsA = sizeof(V2) * (size_t)(n2 * (n1 + 1) + n1 + n2);
+  const size_t ldsB = sizeof(V2) * (size_t)(n3 * (n1 + 1) + n3);
   set_lds(pass_a_kernel<T>, ldsA);
   set_lds(pass_c_kernel<T>, ldsA);
   if (std::is_same<T, double>::value)
@@ -550,14 +616,17 @@ void launch_adjoint_local(const abi_system_s *s, const void *Ak1, int64_t lda1, 
                           void *box1, void *box2, const void *V, double gamma, double cshift,
                           double *dV, hipStream_t st) {
   using V2 = C2<T>;
+  if (try_cubic_adjoint<T>(s, Ak1, lda1, Yk, ldy, Ak, ldak, accumulate, band0, nb, box1, box2, V,
+                           gamma, cshift, dV, st))
+    return;
   const BoxPlan &plan = s->plan;
   const int n1 = plan.d[0].n, n2 = plan.d[1].n, n3 = plan.d[2].n;
   const double2 *tw = reinterpret_cast<const double2 *>(s->d_tw);
   const int tA = std::max(stage_threads(plan.d[0], n2), stage_threads(plan.d[1], n1));
   const int tB = stage_threads(plan.d[2], n1);
   CHEBFI_REQUIRE(tA <= 512 && tB <= 512, ABI_ERR_GRID, "FFT plane too large for one workgroup");
-  const size_t ldsA = sizeof(V2) * (size_t)(n1 * n2 + n1 + n2);
-  const size_t ldsB = sizeof(V2) * (size_t)(n1 * n3 + n3);
+  const size_t ldsA = sizeof(V2) * (size_t)(n2 * (n1 + 1) + n1 + n2);
+  const size_t ldsB = sizeof(V2) * (size_t)(n3 * (n1 + 1) + n3);
   set_lds(pass_a_kernel<T>, ldsA);
   set_lds(pass_c_kernel<T>, ldsA);
   set_lds(pass_b_inv_kernel<T>, ldsB);
@@ -589,14 +658,15 @@ template <typename T>
 void launch_density(const abi_system_s *s, const void *Psi, int64_t ld, int band0, int nb,
                     void *box, const double *w, double *rho, hipStream_t st) {
   using V2 = C2<T>;
+  if (try_cubic_density<T>(s, Psi, ld, band0, nb, box, w, rho, st)) return;
   const BoxPlan &plan = s->plan;
   const int n1 = plan.d[0].n, n2 = plan.d[1].n, n3 = plan.d[2].n;
   const double2 *tw = reinterpret_cast<const double2 *>(s->d_tw);
   const int tA = std::max(stage_threads(plan.d[0], n2), stage_threads(plan.d[1], n1));
   const int tB = stage_threads(plan.d[2], n1);
   CHEBFI_REQUIRE(tA <= 512 && tB <= 512, ABI_ERR_GRID, "FFT plane too large for one workgroup");
-  const size_t ldsA = sizeof(V2) * (size_t)(n1 * n2 + n1 + n2);
-  const size_t ldsB = sizeof(V2) * (size_t)(n1 * n3 + n3);
+  const size_t ldsA = sizeof(V2) * (size_t)(n2 * (n1 + 1) + n1 + n2);
+  const size_t ldsB = sizeof(V2) * (size_t)(n3 * (n1 + 1) + n3);
   set_lds(pass_a_kernel<T>, ldsA);
   set_lds(pass_b_inv_kernel<T>, ldsB);
   V2 *bx = reinterpret_cast<V2 *>(box);

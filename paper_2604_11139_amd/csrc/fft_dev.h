@@ -114,7 +114,6 @@ __device__ void stage(C2<T> *buf, int n, int estride, int npen, int pstride, int
   const int nbf = n / R;
   const int total = npen * nbf;
   const int m = n / (p * R);
-  const bool pen_fast = (pstride == 1);
   C2<T> y[kMaxB][R];
   int dst[kMaxB];
 #pragma unroll
@@ -122,14 +121,9 @@ __device__ void stage(C2<T> *buf, int n, int estride, int npen, int pstride, int
     const int i = threadIdx.x + c * blockDim.x;
     dst[c] = -1;
     if (i < total) {
-      int pen, bf;
-      if (pen_fast) {
-        pen = i % npen;
-        bf = i / npen;
-      } else {
-        bf = i % nbf;
-        pen = i / nbf;
-      }
+      // consecutive lanes take consecutive pencils: with an odd pencil stride
+      // (padded planes) or a unit one their accesses spread over all LDS banks
+      const int pen = i % npen, bf = i / npen;
       const int base = pen * pstride;
       C2<T> x[R];
 #pragma unroll
@@ -200,6 +194,92 @@ inline int stage_threads(const Plan1D &pl, int npen) {
   const int need = stage_need(pl, npen);
   return need > 512 ? need : 512;
 }
+
+// ---- compile-time specialised passes for cubic boxes ------------------------
+// Same three passes as above with the box edge N, the radix sequence, the
+// pencil strides and the thread count known at compile time, so that all
+// index arithmetic reduces to constant multiplies and shifts.  A plane sits in
+// LDS with a row stride of N + 1 elements, and the lanes of a wave take
+// consecutive pencils in both directions: pencils along a row are then an odd
+// stride apart, which spreads a wave's accesses over all LDS banks.
+template <int N> struct CPlan;
+#define CHEBFI_CPLAN(N_, NS_, R0_, R1_, R2_)                              \
+  template <> struct CPlan<N_> {                                          \
+    static constexpr int ns = NS_;                                        \
+    static constexpr int r[3] = {R0_, R1_, R2_};                          \
+  };
+CHEBFI_CPLAN(12, 2, 4, 3, 1)
+CHEBFI_CPLAN(15, 2, 5, 3, 1)
+CHEBFI_CPLAN(16, 2, 4, 4, 1)
+CHEBFI_CPLAN(18, 2, 6, 3, 1)
+CHEBFI_CPLAN(20, 2, 5, 4, 1)
+CHEBFI_CPLAN(24, 2, 8, 3, 1)
+CHEBFI_CPLAN(25, 2, 5, 5, 1)
+CHEBFI_CPLAN(27, 3, 3, 3, 3)
+CHEBFI_CPLAN(30, 2, 6, 5, 1)
+CHEBFI_CPLAN(32, 2, 8, 4, 1)
+CHEBFI_CPLAN(36, 2, 6, 6, 1)
+CHEBFI_CPLAN(40, 2, 8, 5, 1)
+CHEBFI_CPLAN(45, 3, 5, 3, 3)
+CHEBFI_CPLAN(48, 2, 8, 6, 1)
+CHEBFI_CPLAN(64, 2, 8, 8, 1)
+#undef CHEBFI_CPLAN
+
+constexpr int kCT = 512;  // threads of the specialised passes (16 waves per CU per 4 planes)
+
+template <typename T, int N, int R, int P, int NPEN, int ES, int PS, int SGN>
+__device__ __forceinline__ void cstage(C2<T> *buf, const C2<T> *tw) {
+  constexpr int NBF = N / R;
+  constexpr int TOTAL = NPEN * NBF;
+  constexpr int M = N / (P * R);
+  constexpr int MAXB = (TOTAL + kCT - 1) / kCT;
+  C2<T> y[MAXB][R];
+  int dst[MAXB];
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    const int i = threadIdx.x + c * kCT;
+    dst[c] = -1;
+    if (TOTAL % kCT == 0 || i < TOTAL) {
+      const int pen = i % NPEN, bf = i / NPEN;
+      const int base = pen * PS;
+      C2<T> x[R];
+#pragma unroll
+      for (int t = 0; t < R; ++t) x[t] = buf[base + (bf + t * NBF) * ES];
+      const int k = bf % P;
+      if (P > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) {
+          C2<T> w = tw[t * k * M];
+          if (SGN > 0) w.y = -w.y;
+          x[t] = cmul(x[t], w);
+        }
+      }
+      Dft<T, R>::run(x, SGN);
+#pragma unroll
+      for (int t = 0; t < R; ++t) y[c][t] = x[t];
+      dst[c] = base + ((bf - k) * R + k) * ES;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    if (TOTAL % kCT == 0 || dst[c] >= 0) {
+#pragma unroll
+      for (int t = 0; t < R; ++t) buf[dst[c] + t * P * ES] = y[c][t];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int N, int S, int P, int NPEN, int ES, int PS, int SGN>
+__device__ __forceinline__ void cfft(C2<T> *buf, const C2<T> *tw) {
+  if constexpr (S < CPlan<N>::ns) {
+    constexpr int R = CPlan<N>::r[S];
+    cstage<T, N, R, P, NPEN, ES, PS, SGN>(buf, tw);
+    cfft<T, N, S + 1, P * R, NPEN, ES, PS, SGN>(buf, tw);
+  }
+}
+
 
 }  // namespace
 }  // namespace chebfi

@@ -140,6 +140,16 @@ struct BatchStep {
   double alpha = 0, cshift = 0, beta = 0;
 };
 
+// Systems of one cubic edge n with specialised passes: their indices and the
+// prefix offsets of their items (bands x n per system).
+struct BatchGroup {
+  int n = 0, nsys = 0;
+  const int32_t *gsys = nullptr;
+  const int64_t *goff = nullptr;
+  int64_t items = 0;
+};
+constexpr int kBatchMaxGroups = 16;
+
 // What one batched step launches (device pointers and launch shapes).
 struct BatchLaunch {
   int nsys = 0;
@@ -151,6 +161,8 @@ struct BatchLaunch {
   int fft_threads = 256, proj_threads = 256;
   size_t lds_a = 0, lds_b = 0, lds_c = 0;  // dynamic LDS of the passes, in elements
   bool any_proj = false;
+  int ngroups = 0;  // edge groups with specialised passes (their items are not in items_a/b)
+  BatchGroup groups[kBatchMaxGroups];
 };
 
 }  // namespace chebfi

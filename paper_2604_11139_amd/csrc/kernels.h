@@ -169,6 +169,8 @@ int fft_stage_threads(const Plan1D &pl, int npen);
 // One filter step (index j of the step table) of every system of a batch:
 // projection + D, FFT passes A, B, C (with expansion and recurrence).
 template <typename T> void batch_step(const BatchLaunch &L, int j, hipStream_t st);
+// True if batched systems on a cubic box of this edge get specialised passes.
+bool batch_edge_specialised(int n);
 // Sets the dynamic LDS limits of the batched kernels (call outside graph capture).
 template <typename T> void batch_prepare(const BatchLaunch &L);
 
