@@ -5,7 +5,8 @@ bench's ``cpu_baseline`` leg may import this package; the product path (the HIP
 library and its Python binding) never calls it and shares no code with it.
 
 Each function follows a passage of the paper (arXiv 2604.11139): the problem
-statement H psi = lambda S psi with S = I (section "Problem setup"), the
+statement H psi = lambda S psi (section "Problem setup"), with S = I or the
+projector overlap S = I + P Q P^H and its Woodbury inverse (module overlap), the
 matrix-free Hamiltonian with FFT local part and projector nonlocal part
 (sections "Main computational kernels" and "Low-level operations"), the
 Chebyshev spectral filter with Rayleigh-quotient bounds (Algorithm
@@ -36,3 +37,13 @@ from .subspace import (  # noqa: F401
     residual_norms,
 )
 from .adjoint import filter_backward, filter_coefficients, filter_iterates, filter_loss  # noqa: F401,E402
+from .overlap import (  # noqa: F401,E402
+    Overlap,
+    filter_bounds_gen,
+    lanczos_gen,
+    lanczos_upper_bound_gen,
+    rayleigh_quotients_gen,
+    rayleigh_ritz_gen,
+    residual_norms_gen,
+    sinv_h,
+)

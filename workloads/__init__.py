@@ -6,6 +6,7 @@ eigensolver's arithmetic (no sphere, no projector, no Hamiltonian, no filter).
 from .systems import (  # noqa: F401
     BATCH,
     CONFIGS,
+    PAW_Q_SCALE,
     System,
     make_batch,
     make_system,

@@ -27,13 +27,15 @@ from typing import Dict, Optional, Sequence
 import numpy as np
 
 # Stream indices of SeedSequence(...).spawn(N_STREAMS).
-ATOMS, DMAT, XBLOCK, WBLOCK, V0, FD, EXTRA = range(7)
-N_STREAMS = 7
+ATOMS, DMAT, XBLOCK, WBLOCK, V0, FD, EXTRA, QMAT = range(8)
+N_STREAMS = 8
 
 WELL_DEPTH = -4.0
 WELL_SIGMA = 0.8
 MIN_SEPARATION = 3.0
 PROJ_RC = 1.0
+Q_SHIFT = 1.5
+PAW_Q_SCALE = 10.0  # q_scale of the PAW-like variants: S spectrum about [0.8, 1.8]
 
 # The workloads: sizes follow the paper's regime of a few percent of bands per
 # plane wave; ids 1-3 are single systems of growing size.
@@ -60,6 +62,7 @@ class System:
     degree: int
     cycles: int
     tag: int
+    qij: Optional[np.ndarray] = None  # (natom, 4, 4) complex128, Hermitian; None: S = I
 
     @property
     def lattice(self) -> np.ndarray:
@@ -145,12 +148,15 @@ def make_system(
     kpt_red=(0.0, 0.0, 0.0),
     vloc_scale: float = 1.0,
     d_scale: float = 1.0,
+    q_scale: float = 0.0,
 ) -> System:
     """Build a seeded system.  ``tag`` selects the workload and the seed.
 
     Keyword overrides make small variants (test systems) from the same recipe;
     ``vloc_scale`` / ``d_scale`` scale the potential and D (0 gives the free
-    electron, 100 makes the weak nonlocal term visible).
+    electron, 100 makes the weak nonlocal term visible); ``q_scale`` > 0 adds
+    the overlap matrices Q_R = q_scale (H_R + Q_SHIFT I) of a PAW-like system
+    (H_R drawn like D), otherwise S = I.
     """
     base = dict(CONFIGS.get(tag, CONFIGS[1]))
     for k, v in dict(a=a, ecut=ecut, n=n, natom=natom, nband=nband, degree=degree,
@@ -176,6 +182,8 @@ def make_system(
         degree=int(base["degree"]),
         cycles=int(base["cycles"]),
         tag=int(tag),
+        qij=(_hermitian_d(rngs[QMAT], int(base["natom"])) + Q_SHIFT * np.eye(4)) * q_scale
+        if q_scale > 0 else None,
     )
 
 
