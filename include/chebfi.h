@@ -2,12 +2,15 @@
  * chebfi.h - C ABI of the MI355X Chebyshev-filter eigensolver hot path.
  *
  * The library finds the lowest M eigenpairs of a plane-wave Kohn-Sham
- * Hamiltonian H psi = lambda psi (S = I) on an N x M block of wave functions
- * kept in GPU memory, as stated in arXiv 2604.11139, section "Problem setup".
+ * problem H psi = lambda S psi on an N x M block of wave functions kept in GPU
+ * memory, as stated in arXiv 2604.11139, section "Problem setup".
  * H = 0.5|k+G|^2 (diagonal) + V_loc (applied on the FFT grid) + sum_R P_R D_R P_R^H
- * (section "Low-level operations").  The block is filtered by a Chebyshev
- * polynomial of H (Algorithm "Parallel Chebyshev filtering of degree k"),
- * orthonormalised through the Cholesky factor of its Gram matrix (Algorithm
+ * (section "Low-level operations").  S = I (norm-conserving), or, for PAW and
+ * ultrasoft systems, the overlap S = I + sum_R P_R Q_R P_R^H with its inverse
+ * applied by the Woodbury formula (sections "Introduction" and "Main
+ * computational kernels").  The block is filtered by a Chebyshev polynomial of
+ * S^-1 H (Algorithm "Parallel Chebyshev filtering of degree k"),
+ * orthonormalised through the Cholesky factor of its S-Gram matrix (Algorithm
  * "S-ortho") and rotated by Rayleigh-Ritz (Algorithm "RR").  Only eigenvalues
  * and scalars come back to the host (section "Host-device memory transfers").
  *
@@ -57,7 +60,7 @@ typedef struct abi_system_s *abi_system;
 
 /* One Hamiltonian.  Host pointers are read during abi_set_system only. */
 typedef struct {
-  int32_t abi_version;   /* must be 1 */
+  int32_t abi_version;   /* 1, or 2 to pass qij (version 1 callers omit the field) */
   double lattice[9];     /* rows a1, a2, a3 in bohr */
   double kpt_red[3];     /* k-point in reduced coordinates of the reciprocal basis */
   double ecut;           /* Ha; basis = {G : 0.5|k+G|^2 < ecut} (strict) */
@@ -68,6 +71,12 @@ typedef struct {
   double rc;             /* projector Gaussian width, bohr (> 0) */
   const double *dij;     /* natom*4*4 complex (re,im interleaved), row-major D_R[i][j], Hermitian */
   int32_t precision;     /* ABI_PREC_FP64 or ABI_PREC_MIXED */
+  /* abi_version 2 only.  natom*4*4 complex (re,im interleaved), row-major Q_R[i][j],
+   * Hermitian, or NULL: the overlap S = I + sum_R P_R Q_R P_R^H of PAW/ultrasoft
+   * systems (NULL or natom = 0: S = I).  Q_R may be indefinite; S must be
+   * positive definite (abi_set_system fails with ABI_ERR_NOT_HPD otherwise, and
+   * when the projectors are linearly dependent). */
+  const double *qij;
 } abi_system_desc;
 
 /* ---- host-only helpers (no GPU needed) ------------------------------------ */
@@ -105,6 +114,15 @@ abi_status abi_get_projectors(abi_system sys, void *P_out, void *stream);
 
 abi_status abi_destroy(abi_system sys);
 
+/* Overlap of the handle: *has_overlap = 1 when S != I, *s_min = the smallest
+ * eigenvalue of S (1 when S = I).  Either pointer may be NULL.  With S != I,
+ * abi_set_system forms B = P^H P, its Cholesky factor B = R^H R and the
+ * eigen-decomposition R Q R^H = Z diag(mu) Z^H (FP64, on the device); S has
+ * the eigenvalues 1 and 1 + mu_i, and S^-1 = I - P K P^H with
+ * K = W diag(mu / (1 + mu)) W^H, W = R^-1 Z (the Woodbury formula of the Sinv
+ * kernel, section "Main computational kernels"). */
+abi_status abi_overlap_info(abi_system sys, int32_t *has_overlap, double *s_min);
+
 /* ---- hot path ------------------------------------------------------------- */
 
 /* HX = H X for nband columns (matrix-free H application of section "Main
@@ -116,34 +134,47 @@ abi_status abi_destroy(abi_system sys);
 abi_status abi_apply_H(abi_system sys, const void *X, void *HX, int64_t nband, int64_t ld,
                        int32_t dtype, void *stream);
 
+/* SX = S X and Y = S^-1 X (the HX_SX and Sinv kernels of section "Main
+ * computational kernels"; S^-1 X = X - P (K (P^H X)), O(N_projs N) per band).
+ * Blocks and dtype as for abi_apply_H; the output must not overlap X.  With
+ * S = I both copy X.  The small product K (P^H X) is taken in FP64 for both
+ * dtypes. */
+abi_status abi_apply_S(abi_system sys, const void *X, void *SX, int64_t nband, int64_t ld,
+                       int32_t dtype, void *stream);
+abi_status abi_apply_Sinv(abi_system sys, const void *X, void *Y, int64_t nband, int64_t ld,
+                          int32_t dtype, void *stream);
+
 /* Bounds of the Chebyshev filter (Algorithm "Parallel Chebyshev filtering of
  * degree k", Rayleigh-quotient step): out[0] = a = max_i RQ_i,
- * out[2] = a0 = min_i RQ_i with RQ_i = Re(x_i^H H x_i)/(x_i^H x_i), and
+ * out[2] = a0 = min_i RQ_i with RQ_i = Re(x_i^H H x_i)/Re(x_i^H S x_i), and
  * out[1] = b = theta_max(T) + beta_last from `nlanczos` (1..64) Lanczos steps
- * with full reorthogonalisation started from the device vector v0 (npw
- * complex doubles, always FP64); the run stops early with b = theta_max when
- * beta_j <= 1e-12 max(1, |alpha_j|).  `out` is a host array of 3 doubles.
- * Synchronises `stream`. */
+ * on S^-1 H with full reorthogonalisation in the S inner product u^H S v,
+ * started from the device vector v0 (npw complex doubles, always FP64); the
+ * run stops early with b = theta_max when beta_j <= 1e-12 max(1, |alpha_j|).
+ * `out` is a host array of 3 doubles.  Synchronises `stream`. */
 abi_status abi_spectral_bounds(abi_system sys, const void *X, int64_t nband, int64_t ld,
                                int32_t dtype, const void *v0, int32_t nlanczos, double *out,
                                void *stream);
 
-/* Y = T_m((H - c)/e) X / T_m((a0 - c)/e), e = (b-a)/2, c = (b+a)/2, by the
- * scaled three-term recurrence (the "axpy" recurrence of section "Parallel
- * implementation design"): Y_1 = (s_1/e)(H - c)X,
- * Y_{k+1} = (2 s_{k+1}/e)(H - c)Y_k - s_k s_{k+1} Y_{k-1}, s_1 = e/(a0 - c),
- * s_{k+1} = 1/(2/s_1 - s_k).  degree = m >= 1 H applications; requires b > a
- * and a0 <= a.  X and Y (both npw x nband, leading dimension ld) must not
- * overlap; X is not modified.  dtype as for abi_apply_H. */
+/* Y = T_m((A - c)/e) X / T_m((a0 - c)/e), A = S^-1 H, e = (b-a)/2, c = (b+a)/2,
+ * by the scaled three-term recurrence (the "axpy" recurrence of section
+ * "Parallel implementation design"): Y_1 = (s_1/e)(A - c)X,
+ * Y_{k+1} = (2 s_{k+1}/e)(A - c)Y_k - s_k s_{k+1} Y_{k-1}, s_1 = e/(a0 - c),
+ * s_{k+1} = 1/(2/s_1 - s_k).  degree = m >= 1 applications of A; requires
+ * b > a and a0 <= a.  X and Y (both npw x nband, leading dimension ld) must
+ * not overlap; X is not modified.  dtype as for abi_apply_H.  With S != I each
+ * step still projects and expands the block once: the projections P^H Y_k are
+ * carried along (FP64) and the Woodbury correction is formed from them by
+ * nproj x nproj products. */
 abi_status abi_cheb_filter(abi_system sys, const void *X, void *Y, int64_t nband, int64_t ld,
                            int32_t dtype, int32_t degree, double a, double b, double a0,
                            void *stream);
 
-/* Rayleigh-Ritz on the filtered block (Algorithms "S-ortho" and "RR" with
- * S = I): G = Y^H Y = U^H U (Cholesky, FP64), H_s = Y^H (H Y),
- * U^-H H_s U^-1 = Z Lambda Z^H, Psi = Y U^-1 Z, H Psi = (H Y) U^-1 Z, and the
- * residual norms ||H psi_n - lambda_n psi_n|| (Algorithm "Parallel Chebyshev
- * filtering of degree k", last two steps).  Always computed in FP64: a
+/* Rayleigh-Ritz on the filtered block (Algorithms "S-ortho" and "RR"):
+ * G = Y^H S Y = U^H U (Cholesky, FP64), H_s = Y^H (H Y),
+ * U^-H H_s U^-1 = Z Lambda Z^H, Psi = Y U^-1 Z (S-orthonormal),
+ * H Psi = (H Y) U^-1 Z, and the residual norms ||H psi_n - lambda_n S psi_n||
+ * (Algorithm "Parallel Chebyshev filtering of degree k", last two steps).  Always computed in FP64: a
  * complex64 block (dtype ABI_C64, mixed handles) is promoted, processed and
  * rounded back, so the eigenvalues are those of the FP64 pencil of the block.
  * Y (npw x nband, ld): in: filtered block; out: Ritz vectors Psi.
@@ -186,7 +217,8 @@ abi_status abi_chebfi_solve(abi_system sys, void *X, int64_t nband, int64_t ld, 
 abi_status abi_update_potential(abi_system sys, const double *vloc, const void *dij,
                                 void *stream);
 
-/* Adjoint of abi_cheb_filter for the loss L = sum_n Re<W_n, Y_n>, Y = the
+/* Adjoint of abi_cheb_filter (handles with S = I; ABI_ERR_STATE otherwise)
+ * for the loss L = sum_n Re<W_n, Y_n>, Y = the
  * filter output (reverse mode of the filter recurrence; the paper's solver is
  * not differentiated, so this is the derivative of the operation
  * abi_cheb_filter computes).  With gamma_0 = s_1/e, gamma_k = 2 s_{k+1}/e and
@@ -246,7 +278,7 @@ abi_status abi_zheev(int64_t m, void *A, int64_t lda, double *w, void *Z, int64_
  * fused into the last), each a grid-stride loop over the work items of all
  * systems; the 4 x degree launches of a filter are captured into a HIP graph
  * on first use and replayed.  Limits: at most 1024 systems, at most 8 atoms
- * (32 projectors) per system, FFT edges up to 64. */
+ * (32 projectors) per system, FFT edges up to 64, S = I (no Q). */
 typedef struct abi_batch_s *abi_batch;
 
 /* Builds the nsys systems of `descs` (as abi_set_system; all with the same

@@ -38,7 +38,7 @@ EXPORTS = [
     "abi_zheev", "abi_profile_enable", "abi_profile_read", "abi_update_potential",
     "abi_filter_backward", "abi_density", "abi_last_error", "abi_set_system_batch",
     "abi_batch_system", "abi_cheb_filter_batch", "abi_batch_autotune", "abi_batch_use_graph",
-    "abi_destroy_batch", "abi_chebfi_solve",
+    "abi_destroy_batch", "abi_chebfi_solve", "abi_apply_S", "abi_apply_Sinv", "abi_overlap_info",
 ]
 
 PROFILE_CLASSES = ["proj_gemm", "expand_gemm", "fft_a", "fft_b", "fft_c", "dapply", "gram",
@@ -64,6 +64,7 @@ class Desc(ctypes.Structure):
         ("rc", c_double),
         ("dij", POINTER(c_double)),
         ("precision", c_int32),
+        ("qij", POINTER(c_double)),
     ]
 
 
@@ -109,6 +110,9 @@ def lib():
         "abi_destroy_batch": [vp],
         "abi_chebfi_solve": [vp, vp, c_int64, c_int64, c_int32, vp, c_int32, c_int32, c_int32,
                              c_double, c_int32, vp, vp, vp, vp],
+        "abi_apply_S": [vp, vp, vp, c_int64, c_int64, c_int32, vp],
+        "abi_apply_Sinv": [vp, vp, vp, c_int64, c_int64, c_int32, vp],
+        "abi_overlap_info": [vp, POINTER(c_int32), POINTER(c_double)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -154,7 +158,7 @@ def _block(t, npw: int):
 class _DescHolder:
     """Keeps the numpy arrays referenced by a Desc alive."""
 
-    def __init__(self, lattice, kpt_red, ecut, ngrid, vloc, tau, dij, rc, precision):
+    def __init__(self, lattice, kpt_red, ecut, ngrid, vloc, tau, dij, rc, precision, qij=None):
         self.vloc = np.ascontiguousarray(np.asarray(vloc, dtype=np.float64).reshape(-1))
         self.tau = np.ascontiguousarray(np.asarray(tau, dtype=np.float64).reshape(-1, 3))
         d = np.ascontiguousarray(np.asarray(dij, dtype=np.complex128).reshape(-1, 4, 4))
@@ -174,10 +178,19 @@ class _DescHolder:
         self.desc.rc = float(rc)
         self.desc.dij = self.dij.ctypes.data_as(POINTER(c_double))
         self.desc.precision = int(precision)
+        self.qij = None
+        if qij is not None:
+            q = np.ascontiguousarray(np.asarray(qij, dtype=np.complex128).reshape(-1, 4, 4))
+            if q.shape[0] != self.desc.natom:
+                raise ValueError("qij needs one 4x4 matrix per atom")
+            self.qij = np.ascontiguousarray(q.view(np.float64).reshape(-1))
+            self.desc.abi_version = 2
+            self.desc.qij = self.qij.ctypes.data_as(POINTER(c_double))
 
     @classmethod
     def from_system(cls, s, precision=ABI_PREC_FP64):
-        return cls(s.lattice, s.kpt_red, s.ecut, s.ngrid, s.vloc, s.tau, s.dij, s.rc, precision)
+        return cls(s.lattice, s.kpt_red, s.ecut, s.ngrid, s.vloc, s.tau, s.dij, s.rc, precision,
+                   getattr(s, "qij", None))
 
 
 def gsphere_host(s):
@@ -271,6 +284,27 @@ class System:
         po, _, _, _ = _block(out, self.npw)
         _check(lib().abi_apply_H(self._h, px, po, nb, ld, code, _stream()))
         return out
+
+    def apply_S(self, X, out=None):
+        px, nb, ld, code = _block(X, self.npw)
+        out = self._out_like(X, out)
+        po, _, _, _ = _block(out, self.npw)
+        _check(lib().abi_apply_S(self._h, px, po, nb, ld, code, _stream()))
+        return out
+
+    def apply_Sinv(self, X, out=None):
+        px, nb, ld, code = _block(X, self.npw)
+        out = self._out_like(X, out)
+        po, _, _, _ = _block(out, self.npw)
+        _check(lib().abi_apply_Sinv(self._h, px, po, nb, ld, code, _stream()))
+        return out
+
+    def overlap_info(self):
+        """(has_overlap, smallest eigenvalue of S)."""
+        h = c_int32(0)
+        m = c_double(0.0)
+        _check(lib().abi_overlap_info(self._h, ctypes.byref(h), ctypes.byref(m)))
+        return bool(h.value), float(m.value)
 
     def cheb_filter(self, X, degree, a, b, a0, out=None):
         px, nb, ld, code = _block(X, self.npw)

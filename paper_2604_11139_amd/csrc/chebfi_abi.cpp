@@ -116,7 +116,8 @@ inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 void check_desc(const abi_system_desc *d) {
   CHEBFI_REQUIRE(d != nullptr, ABI_ERR_ARG, "desc is NULL");
-  CHEBFI_REQUIRE(d->abi_version == 1, ABI_ERR_ARG, "abi_version must be 1");
+  CHEBFI_REQUIRE(d->abi_version == 1 || d->abi_version == 2, ABI_ERR_ARG,
+                 "abi_version must be 1 or 2");
   CHEBFI_REQUIRE(d->ecut > 0.0 && std::isfinite(d->ecut), ABI_ERR_ARG, "ecut must be > 0");
   for (int c = 0; c < 3; ++c) {
     const int n = d->ngrid[c];
@@ -153,10 +154,12 @@ void free_tables(abi_system_s *s) {
   if (s->aux) (void)hipStreamDestroy(s->aux);
   s->ev_fork = s->ev_join = nullptr;
   s->aux = nullptr;
-  void *ptrs[] = {s->d_kin, s->d_box, s->d_plane, s->d_P, s->d_D, s->d_V,
-                  s->d_tw,  s->d_Pf,  s->d_Vf,    s->d_PA, s->d_PB};
+  void *ptrs[] = {s->d_kin, s->d_box, s->d_plane, s->d_P, s->d_D, s->d_V, s->d_tw,
+                  s->d_Pf,  s->d_Vf,  s->d_PA,    s->d_PB, s->d_Q, s->d_B, s->d_K};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  s->d_Q = s->d_B = s->d_K = nullptr;
+  s->has_S = false;
   s->d_kin = nullptr;
   s->d_box = nullptr;
   s->d_plane = nullptr;
@@ -196,6 +199,100 @@ void check_block(const abi_system_s *s, const void *p, int64_t nband, int64_t ld
 
 inline size_t elem_bytes(int32_t dtype) { return dtype == ABI_C64 ? sizeof(float2) : sizeof(double2); }
 
+// Projector products of a block: part[z] = P^H X over plane-wave chunk z
+// (returns the chunk count).  T = double: FP64 MFMA (a matrix-vector product
+// for one band); T = float: complex64 block, split-BF16 MFMA (FP32 MFMA with
+// mixed_gemm = 1), FP32 partials.
+template <typename T>
+int project_t(abi_system_s *s, const void *X, int64_t ldx, int64_t nband, hipStream_t st,
+              C2<T> **part_out) {
+  typedef C2<T> V2;
+  const bool fp32 = std::is_same<T, float>::value;
+  const void *P = fp32 ? (const void *)s->d_Pf : (const void *)s->d_P;
+  const int64_t npw = s->npw;
+  const int nproj = s->nproj;
+  const bool single = (nband == 1) && !fp32;
+  const bool planes = fp32 && s->mixed_gemm == 0;
+  const int splits = single ? 1
+                     : planes ? proj_planes_splits(s->pl_proj, nproj, nband, npw)
+                              : zgemm_splits(nproj, nband, npw);
+  V2 *cpart = (V2 *)s->cpart.get(sizeof(V2) * (size_t)splits * nproj * nband);
+  const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
+  // the default split-BF16 projection splits the block into planes while staging it;
+  // the other tile variants read planes made by a separate pass
+  const bool staged = planes && s->pl_proj == 4;
+  void *xpl = nullptr;
+  if (planes && !staged) {
+    xpl = s->planes.get(8 * (size_t)s->ldPA * nband);
+    const int tk = s->prof.begin(PROF_SPLIT, 16.0 * (double)npw * (double)nband, st);
+    split_planes(npw, nband, X, ldx, xpl, s->ldPA, st);
+    s->prof.end(tk, st);
+  }
+  const int tok = s->prof.begin(PROF_PROJ, flops, st);
+  if (single)
+    proj_gemv(npw, nproj, P, X, cpart, st);
+  else if (staged)
+    proj_gemm_planes_f32(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, X, ldx,
+                         cpart, splits, st);
+  else if (planes)
+    proj_gemm_planes(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, xpl,
+                     s->ldPA, s->ldPA * nband, cpart, splits, st, s->pl_proj);
+  else if (fp32 && s->mixed_gemm == 2)
+    proj_gemm_bf16x3(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, X, ldx,
+                     cpart, splits, st);
+  else
+    proj_gemm(nproj, nband, npw, P, X, ldx, cpart, splits, st, fp32);
+  s->prof.end(tok, st);
+  *part_out = cpart;
+  return splits;
+}
+
+// Out += P C' for nproj x nband coefficients C' (ld nproj) of the block's type.
+template <typename T>
+void expand_t(abi_system_s *s, const C2<T> *cprime, void *Out, int64_t ldo, int64_t nband,
+              hipStream_t st) {
+  const bool fp32 = std::is_same<T, float>::value;
+  const void *P = fp32 ? (const void *)s->d_Pf : (const void *)s->d_P;
+  const int64_t npw = s->npw;
+  const int nproj = s->nproj;
+  const bool single = (nband == 1) && !fp32;
+  const bool planes = fp32 && s->mixed_gemm == 0;
+  if (planes)
+    split_planes(nproj, nband, cprime, nproj, s->cplanes.get(8 * (size_t)s->ldPB * nband),
+                 s->ldPB, st);
+  const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
+  const int tok = s->prof.begin(PROF_EXPAND, flops, st);
+  if (single)
+    expand_gemv(npw, nproj, P, cprime, Out, st);
+  else if (planes)
+    expand_gemm_planes(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB, s->cplanes.ptr,
+                       s->ldPB, s->ldPB * nband, Out, ldo, st, s->pl_expand);
+  else if (fp32 && s->mixed_gemm == 2)
+    expand_gemm_bf16x3(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB, cprime, Out, ldo, st);
+  else
+    expand_gemm(npw, nband, nproj, P, cprime, Out, ldo, st, fp32);
+  s->prof.end(tok, st);
+}
+
+// Local part, kinetic term and recurrence on the FFT grid:
+// Out = alpha ((0.5|k+G|^2 + V_loc) X - cshift X) - beta Xprev   (Xprev may be null).
+template <typename T>
+void local_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
+             void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
+             hipStream_t st) {
+  typedef C2<T> V2;
+  const bool fp32 = std::is_same<T, float>::value;
+  const void *V = fp32 ? (const void *)s->d_Vf : (const void *)s->d_V;
+  const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
+  const int fb = (int)std::min<int64_t>(s->fft_batch * (fp32 ? 2 : 1), nband);
+  void *box = s->box.get(sizeof(V2) * (size_t)nbox * fb);
+  for (int64_t b0 = 0; b0 < nband; b0 += fb) {
+    const int nb = (int)std::min<int64_t>(fb, nband - b0);
+    launch_local_potential<T>(s, X, ldx, Xprev, ldp, Out, ldo, (int)b0, nb, box, V, alpha, cshift,
+                              beta, st, s->prof.on ? &s->prof : nullptr);
+  }
+}
+
 // Out = alpha * (H - cshift) X - beta * Xprev   (Xprev may be null).
 // T = double: FP64 tables, FP64 MFMA; T = float: complex64 blocks, FP32 FFT
 // passes and FP32 MFMA projector products (mixed form).
@@ -205,90 +302,29 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
                   hipStream_t st) {
   typedef C2<T> V2;
   const bool fp32 = std::is_same<T, float>::value;
-  const void *P = fp32 ? (const void *)s->d_Pf : (const void *)s->d_P;
-  const void *V = fp32 ? (const void *)s->d_Vf : (const void *)s->d_V;
-  const int64_t npw = s->npw;
   const int nproj = s->nproj;
-  int splits = 1;
-  V2 *cpart = nullptr, *cprime = nullptr;
   const bool single = (nband == 1) && !fp32;
-  const bool planes = fp32 && s->mixed_gemm == 0;
-  // local part, kinetic term and recurrence: Out = alpha (local + (kin - c) X) - beta Xprev,
-  // on the second stream when it can run beside the projection
+  // the FFT passes run on the second stream beside the projection when they can
   const bool side = s->overlap && nproj > 0 && !single && s->aux;
-  hipStream_t fst = side ? s->aux : st;
   if (side) {
     CHEBFI_HIP(hipEventRecord(s->ev_fork, st));
     CHEBFI_HIP(hipStreamWaitEvent(s->aux, s->ev_fork, 0));
   }
-  {
-    const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
-    const int fb = (int)std::min<int64_t>(s->fft_batch * (fp32 ? 2 : 1), nband);
-    void *box = s->box.get(sizeof(V2) * (size_t)nbox * fb);
-    for (int64_t b0 = 0; b0 < nband; b0 += fb) {
-      const int nb = (int)std::min<int64_t>(fb, nband - b0);
-      launch_local_potential<T>(s, X, ldx, Xprev, ldp, Out, ldo, (int)b0, nb, box, V, alpha,
-                                cshift, beta, fst, s->prof.on ? &s->prof : nullptr);
-    }
-  }
+  local_t<T>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, side ? s->aux : st);
   if (side) CHEBFI_HIP(hipEventRecord(s->ev_join, s->aux));
+  V2 *cprime = nullptr;
   if (nproj > 0) {
-    splits = single ? 1
-             : planes ? proj_planes_splits(s->pl_proj, nproj, nband, npw)
-                      : zgemm_splits(nproj, nband, npw);
-    cpart = (V2 *)s->cpart.get(sizeof(V2) * (size_t)splits * nproj * nband);
+    // C = P^H X, C' = alpha D C
+    V2 *cpart = nullptr;
+    const int splits = project_t<T>(s, X, ldx, nband, st, &cpart);
     cprime = (V2 *)s->cprime.get(sizeof(V2) * (size_t)nproj * nband);
-    // C = P^H X (split along the plane waves), C' = alpha D C
-    const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
-    // the default split-BF16 projection splits the block into planes while staging it;
-    // the other tile variants read planes made by a separate pass
-    const bool staged = planes && s->pl_proj == 4;
-    void *xpl = nullptr;
-    if (planes && !staged) {
-      xpl = s->planes.get(8 * (size_t)s->ldPA * nband);
-      const int tk = s->prof.begin(PROF_SPLIT, 16.0 * (double)npw * (double)nband, st);
-      split_planes(npw, nband, X, ldx, xpl, s->ldPA, st);
-      s->prof.end(tk, st);
-    }
-    int tok = s->prof.begin(PROF_PROJ, flops, st);
-    if (single)
-      proj_gemv(npw, nproj, P, X, cpart, st);
-    else if (staged)
-      proj_gemm_planes_f32(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, X, ldx,
-                           cpart, splits, st);
-    else if (planes) {
-      proj_gemm_planes(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, xpl,
-                       s->ldPA, s->ldPA * nband, cpart, splits, st, s->pl_proj);
-    } else if (fp32 && s->mixed_gemm == 2)
-      proj_gemm_bf16x3(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, X, ldx,
-                       cpart, splits, st);
-    else
-      proj_gemm(nproj, nband, npw, P, X, ldx, cpart, splits, st, fp32);
-    s->prof.end(tok, st);
-    tok = s->prof.begin(PROF_DAPPLY, (double)sizeof(V2) * nproj * nband * (splits + 1), st);
+    const int tok =
+        s->prof.begin(PROF_DAPPLY, (double)sizeof(V2) * nproj * nband * (splits + 1), st);
     launch_dapply(s->natom, nband, cpart, splits, s->d_D, alpha, cprime, st, fp32);
-    if (fp32 && s->mixed_gemm == 0)
-      split_planes(nproj, nband, cprime, nproj, s->cplanes.get(8 * (size_t)s->ldPB * nband),
-                   s->ldPB, st);
     s->prof.end(tok, st);
   }
   if (side) CHEBFI_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
-  if (nproj > 0) {
-    // Out += P C'
-    const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
-    int tok = s->prof.begin(PROF_EXPAND, flops, st);
-    if (single)
-      expand_gemv(npw, nproj, P, cprime, Out, st);
-    else if (planes)
-      expand_gemm_planes(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB, s->cplanes.ptr,
-                         s->ldPB, s->ldPB * nband, Out, ldo, st, s->pl_expand);
-    else if (fp32 && s->mixed_gemm == 2)
-      expand_gemm_bf16x3(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB, cprime, Out, ldo,
-                         st);
-    else
-      expand_gemm(npw, nband, nproj, P, cprime, Out, ldo, st, fp32);
-    s->prof.end(tok, st);
-  }
+  if (nproj > 0) expand_t<T>(s, cprime, Out, ldo, nband, st);  // Out += P C'
 }
 
 void apply_core(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
@@ -298,6 +334,189 @@ void apply_core(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, 
     apply_core_t<float>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, st);
   else
     apply_core_t<double>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, st);
+}
+
+// ---- overlap S = I + P Q P^H and its Woodbury inverse ----------------------------
+
+// Out = S X = X + P (Q (P^H X))  (Out must not overlap X).
+template <typename T>
+void apply_S_t(abi_system_s *s, const void *X, int64_t ldx, void *Out, int64_t ldo,
+               int64_t nband, hipStream_t st) {
+  typedef C2<T> V2;
+  const bool fp32 = std::is_same<T, float>::value;
+  launch_copy_block(s->npw, nband, X, ldx, Out, ldo, st, fp32);
+  if (!s->has_S) return;
+  V2 *cpart = nullptr;
+  const int splits = project_t<T>(s, X, ldx, nband, st, &cpart);
+  V2 *cprime = (V2 *)s->cprime.get(sizeof(V2) * (size_t)s->nproj * nband);
+  launch_dapply(s->natom, nband, cpart, splits, s->d_Q, 1.0, cprime, st, fp32);
+  expand_t<T>(s, cprime, Out, ldo, nband, st);
+}
+
+// Out = S^-1 X = X - P (K (P^H X))  (the Sinv kernel; Out must not overlap X).
+template <typename T>
+void apply_Sinv_t(abi_system_s *s, const void *X, int64_t ldx, void *Out, int64_t ldo,
+                  int64_t nband, hipStream_t st) {
+  typedef C2<T> V2;
+  const bool fp32 = std::is_same<T, float>::value;
+  launch_copy_block(s->npw, nband, X, ldx, Out, ldo, st, fp32);
+  if (!s->has_S) return;
+  const int n = s->nproj;
+  V2 *cpart = nullptr;
+  const int splits = project_t<T>(s, X, ldx, nband, st, &cpart);
+  double2 *C = (double2 *)s->gen_e.get(sizeof(double2) * (size_t)n * nband);
+  double2 *F = (double2 *)s->gen_f.get(sizeof(double2) * (size_t)n * nband);
+  const int tok = s->prof.begin(PROF_DAPPLY, 8.0 * (double)n * n * nband, st);
+  launch_parts_to_c128(n, nband, cpart, splits, fp32, C, st);
+  zgemm(OP_N, OP_N, n, nband, n, s->d_K, n, C, n, F, n, double2{-1, 0}, double2{0, 0}, st);
+  const V2 *fp = (const V2 *)F;
+  if (fp32) {
+    float2 *Ff = (float2 *)s->gen_ff.get(sizeof(float2) * (size_t)n * nband);
+    launch_d2f(2 * (int64_t)n * nband, (const double *)F, (float *)Ff, st);
+    fp = (const V2 *)Ff;
+  }
+  s->prof.end(tok, st);
+  expand_t<T>(s, fp, Out, ldo, nband, st);
+}
+
+void apply_S(abi_system_s *s, const void *X, int64_t ldx, void *Out, int64_t ldo, int64_t nband,
+             hipStream_t st, int32_t dtype = ABI_C128) {
+  if (dtype == ABI_C64)
+    apply_S_t<float>(s, X, ldx, Out, ldo, nband, st);
+  else
+    apply_S_t<double>(s, X, ldx, Out, ldo, nband, st);
+}
+
+void apply_Sinv(abi_system_s *s, const void *X, int64_t ldx, void *Out, int64_t ldo,
+                int64_t nband, hipStream_t st, int32_t dtype = ABI_C128) {
+  if (dtype == ABI_C64)
+    apply_Sinv_t<float>(s, X, ldx, Out, ldo, nband, st);
+  else
+    apply_Sinv_t<double>(s, X, ldx, Out, ldo, nband, st);
+}
+
+// One step of the filter on S^-1 H:
+//   Out = alpha (S^-1 H - cshift) X - beta Xprev,   Cnext = P^H Out,
+// given Ck = P^H X and Ckm1 = P^H Xprev (complex double, nproj x nband; Ckm1 null
+// on the first step).  With H X = T + P D Ck (T: kinetic and local part) and
+// S^-1 = I - P K P^H:  S^-1 H X = T + P F,  F = D Ck - K (P^H T + B D Ck).
+// The local passes write Out = alpha (T - c X) - beta Xprev; its projection G
+// gives P^H T = G / alpha + c Ck + (beta / alpha) Ckm1 without projecting T
+// itself; then Out += alpha P F and Cnext = G + alpha B F.  One projection and
+// one expansion of the block per step, as for S = I, plus three nproj x nproj
+// products by nband.
+template <typename T>
+void gen_step_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
+                void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
+                const double2 *Ck, const double2 *Ckm1, double2 *Cnext, hipStream_t st) {
+  typedef C2<T> V2;
+  const bool fp32 = std::is_same<T, float>::value;
+  const int n = s->nproj;
+  local_t<T>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, st);
+  V2 *cpart = nullptr;
+  const int splits = project_t<T>(s, Out, ldo, nband, st, &cpart);
+  double2 *E = (double2 *)s->gen_e.get(sizeof(double2) * (size_t)n * nband);
+  double2 *F = (double2 *)s->gen_f.get(sizeof(double2) * (size_t)n * nband);
+  const int tok = s->prof.begin(PROF_DAPPLY, 24.0 * (double)n * n * nband, st);
+  launch_gen_combine(n, nband, cpart, splits, fp32, Ck, Ckm1, alpha, cshift, beta, E, Cnext, st);
+  launch_dapply(s->natom, nband, Ck, 1, s->d_D, 1.0, F, st, false);  // F = D Ck
+  zgemm(OP_N, OP_N, n, nband, n, s->d_B, n, F, n, E, n, double2{1, 0}, double2{1, 0}, st);
+  zgemm(OP_N, OP_N, n, nband, n, s->d_K, n, E, n, F, n, double2{-alpha, 0}, double2{alpha, 0},
+        st);  // F = alpha (D Ck - K E)
+  zgemm(OP_N, OP_N, n, nband, n, s->d_B, n, F, n, Cnext, n, double2{1, 0}, double2{1, 0}, st);
+  const V2 *fp = (const V2 *)F;
+  if (fp32) {
+    float2 *Ff = (float2 *)s->gen_ff.get(sizeof(float2) * (size_t)n * nband);
+    launch_d2f(2 * (int64_t)n * nband, (const double *)F, (float *)Ff, st);
+    fp = (const V2 *)Ff;
+  }
+  s->prof.end(tok, st);
+  expand_t<T>(s, fp, Out, ldo, nband, st);
+}
+
+// Ck = P^H X in complex double (the first coefficients of a generalised filter).
+template <typename T>
+void project_c128_t(abi_system_s *s, const void *X, int64_t ldx, int64_t nband, double2 *C,
+                    hipStream_t st) {
+  C2<T> *cpart = nullptr;
+  const int splits = project_t<T>(s, X, ldx, nband, st, &cpart);
+  launch_parts_to_c128(s->nproj, nband, cpart, splits, std::is_same<T, float>::value, C, st);
+}
+
+// Builds the overlap tables from Q (host, natom*16 complex): B = P^H P,
+// B = R^H R (Cholesky), R Q R^H = Z diag(mu) Z^H, so that S has the eigenvalues
+// 1 and 1 + mu_i and S^-1 = I - P K P^H with K = W diag(mu/(1+mu)) W^H, W = R^-1 Z
+// (the Woodbury formula, written through the eigenvalues of the small pencil so
+// that an indefinite Q is allowed as long as S stays positive definite).
+void setup_overlap(abi_system_s *s, const double *qij, hipStream_t st) {
+  const int n = s->nproj;
+  if (n == 0 || qij == nullptr) return;
+  s->d_Q = upload(qij, (size_t)s->natom * 32);
+  std::vector<double> Qd((size_t)2 * n * n, 0.0);
+  for (int R = 0; R < s->natom; ++R)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        // column-major dense Q, Q[4R+i, 4R+j] = Q_R[i][j]
+        const size_t dst = 2 * ((size_t)(4 * R + i) + (size_t)(4 * R + j) * n);
+        Qd[dst] = qij[32 * R + 2 * (4 * i + j)];
+        Qd[dst + 1] = qij[32 * R + 2 * (4 * i + j) + 1];
+      }
+  const size_t mm = sizeof(double2) * (size_t)n * n;
+  double2 *Q = upload((const double2 *)Qd.data(), (size_t)n * n);
+  DevBuf w1, w2, w3, wz, ws;
+  double2 *R = (double2 *)w1.get(mm), *T = (double2 *)w2.get(mm), *A = (double2 *)w3.get(mm);
+  double2 *Z = (double2 *)wz.get(mm);
+  double *mu = (double *)ws.get(sizeof(double) * (size_t)n + 64);
+  int *info = (int *)(mu + n);
+  s->d_B = (double *)upload<double2>(nullptr, (size_t)n * n);
+  s->d_K = (double *)upload<double2>(nullptr, (size_t)n * n);
+  try {
+    {
+      const int splits = zgemm_splits(n, n, s->npw);
+      DevBuf part;
+      void *pp = part.get(sizeof(double2) * (size_t)splits * n * n);
+      zgemm(OP_C, OP_N, n, n, s->npw, s->d_P, s->npw, s->d_P, s->npw, nullptr, 0, double2{1, 0},
+            double2{0, 0}, st, pp, splits);
+      zsum_parts(n, n, pp, splits, s->d_B, n, double2{1, 0}, double2{0, 0}, st);
+      CHEBFI_HIP(hipStreamSynchronize(st));
+    }
+    launch_hermitize(n, s->d_B, n, st);
+    launch_copy_block(n, n, s->d_B, n, R, n, st);
+    DevBuf pw;
+    zpotrf_upper(n, R, n, info, pw.get(zpotrf_work_bytes(n)), st);
+    int hinfo = 0;
+    CHEBFI_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, st));
+    CHEBFI_HIP(hipStreamSynchronize(st));
+    if (hinfo != 0)
+      throw Error{ABI_ERR_NOT_HPD, "projector Gram matrix P^H P is singular (pivot " +
+                                       std::to_string(hinfo) + ")"};
+    // A = R Q R^H
+    zgemm(OP_N, OP_C, n, n, n, Q, n, R, n, T, n, double2{1, 0}, double2{0, 0}, st);
+    zgemm(OP_N, OP_N, n, n, n, R, n, T, n, A, n, double2{1, 0}, double2{0, 0}, st);
+    DevBuf ew;
+    zheev(n, A, n, mu, Z, n, ew.get(zheev_work_bytes(n)), st);
+    std::vector<double> hmu(n);
+    CHEBFI_HIP(hipMemcpyAsync(hmu.data(), mu, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    CHEBFI_HIP(hipStreamSynchronize(st));
+    s->s_min = std::min(1.0, 1.0 + hmu[0]);
+    if (!(1.0 + hmu[0] > 1e-10))
+      throw Error{ABI_ERR_NOT_HPD, "overlap operator S = I + P Q P^H is not positive definite "
+                                   "(smallest eigenvalue " + std::to_string(1.0 + hmu[0]) + ")"};
+    // W = R^-1 Z, K = W diag(mu / (1 + mu)) W^H
+    DevBuf tw;
+    ztrtri_upper(n, R, n, tw.get(ztrtri_work_bytes(n)), st);
+    zgemm(OP_N, OP_N, n, n, n, R, n, Z, n, T, n, double2{1, 0}, double2{0, 0}, st);
+    launch_woodbury_scale(n, T, n, mu, A, n, st);
+    zgemm(OP_N, OP_C, n, n, n, A, n, T, n, s->d_K, n, double2{1, 0}, double2{0, 0}, st);
+    launch_hermitize(n, s->d_K, n, st);
+    CHEBFI_HIP(hipStreamSynchronize(st));
+  } catch (...) {
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(Q);
+    throw;
+  }
+  CHEBFI_HIP(hipFree(Q));
+  s->has_S = true;
 }
 
 // FP64 Rayleigh-Ritz on a complex128 block Y (in: filtered block, out: Psi).
@@ -313,12 +532,27 @@ void rr_core(abi_system_s *s, double2 *Y, int64_t ld, double2 *HPsi, int64_t ldh
   double *w_dev = scal + 160;
   double *r_dev = w_dev + M;
   int *info = (int *)(r_dev + M);
-  // Gram G = Y^H Y -> U (Cholesky, upper)
+  // Gram G = Y^H (S Y) -> U (Cholesky, upper); with S != I, S Y = Y + P Q C_Y from
+  // the projections C_Y = P^H Y, which also give S Psi after the rotation
+  const bool gen = s->has_S;
+  const int n = s->nproj;
+  double2 *CY = nullptr, *SY = Y;
+  int64_t lds = ld;
+  if (gen) {
+    CY = (double2 *)s->gen_c.get(sizeof(double2) * (size_t)n * M);
+    double2 *QC = (double2 *)s->gen_f.get(sizeof(double2) * (size_t)n * M);
+    SY = (double2 *)s->blk5.get(sizeof(double2) * (size_t)npw * M);
+    lds = npw;
+    project_c128_t<double>(s, Y, ld, M, CY, st);
+    launch_dapply(s->natom, M, CY, 1, s->d_Q, 1.0, QC, st, false);
+    launch_copy_block(npw, M, Y, ld, SY, lds, st);
+    expand_t<double>(s, QC, SY, lds, M, st);
+  }
   int splits = zgemm_splits(M, M, npw);
   void *part = s->cpart.get(sizeof(double2) * (size_t)splits * M * M);
   const double gflops = 8.0 * (double)M * M * npw;
   int tok = s->prof.begin(PROF_GRAM, gflops, st);
-  zgemm(OP_C, OP_N, M, M, npw, Y, ld, Y, ld, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
+  zgemm(OP_C, OP_N, M, M, npw, Y, ld, SY, lds, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
         splits);
   zsum_parts(M, M, part, splits, G, M, double2{1, 0}, double2{0, 0}, st);
   s->prof.end(tok, st);
@@ -372,7 +606,18 @@ void rr_core(abi_system_s *s, double2 *Y, int64_t ld, double2 *HPsi, int64_t ldh
   s->prof.end(tok, st);
   if (coef) launch_copy_block(M, M, T, M, coef, M, st);
   launch_copy_block(npw, M, Psi, npw, Y, ld, st);
-  launch_residual_norms(npw, M, Y, ld, HP, ldh, w_dev, r_dev, st);
+  if (gen) {
+    // S Psi = Psi + P Q (C_Y W): residuals || H psi - lambda S psi ||
+    double2 *CP = (double2 *)s->gen_e.get(sizeof(double2) * (size_t)n * M);
+    double2 *QC = (double2 *)s->gen_f.get(sizeof(double2) * (size_t)n * M);
+    zgemm(OP_N, OP_N, n, M, M, CY, n, T, M, CP, n, double2{1, 0}, double2{0, 0}, st);
+    launch_dapply(s->natom, M, CP, 1, s->d_Q, 1.0, QC, st, false);
+    launch_copy_block(npw, M, Psi, npw, SY, lds, st);
+    expand_t<double>(s, QC, SY, lds, M, st);
+    launch_residual_norms(npw, M, SY, lds, HP, ldh, w_dev, r_dev, st);
+  } else {
+    launch_residual_norms(npw, M, Y, ld, HP, ldh, w_dev, r_dev, st);
+  }
   CHEBFI_HIP(hipMemcpyAsync(eval, w_dev, sizeof(double) * M, hipMemcpyDeviceToHost, st));
   if (resnorm)
     CHEBFI_HIP(hipMemcpyAsync(resnorm, r_dev, sizeof(double) * M, hipMemcpyDeviceToHost, st));
@@ -780,6 +1025,7 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
     CHEBFI_HIP(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
     s->overlap = 1;
     if (const char *e = std::getenv("CHEBFI_OVERLAP")) s->overlap = std::atoi(e) != 0;
+    if (desc->abi_version >= 2 && desc->qij != nullptr) setup_overlap(s, desc->qij, S(stream));
     CHEBFI_HIP(hipStreamSynchronize(S(stream)));
     *out = s;
   });
@@ -867,6 +1113,37 @@ abi_status abi_cheb_filter(abi_system s, const void *X, void *Y, int64_t nband, 
       explicit Scope(Profiler &q) : p(q) { p.in_filter = true; }
       ~Scope() { p.in_filter = false; }
     } scope(s->prof);
+    if (s->has_S) {
+      // polynomial of S^-1 H; C_j = P^H Y_j rides along in Cs[j % 3]
+      const size_t nc = (size_t)s->nproj * nband;
+      double2 *cbase = (double2 *)s->gen_c.get(3 * sizeof(double2) * nc);
+      double2 *Cs[3] = {cbase, cbase + nc, cbase + 2 * nc};
+      if (dtype == ABI_C64)
+        project_c128_t<float>(s, X, ld, nband, Cs[0], st);
+      else
+        project_c128_t<double>(s, X, ld, nband, Cs[0], st);
+      auto step = [&](const void *yk, int64_t ldk, const void *yp, int64_t ldp, void *out,
+                      int64_t ldo, double al, double be, int j) {
+        const double2 *cm1 = yp ? Cs[(j + 2) % 3] : nullptr;
+        if (dtype == ABI_C64)
+          gen_step_t<float>(s, yk, ldk, yp, ldp, out, ldo, nband, al, c, be, Cs[j % 3], cm1,
+                            Cs[(j + 1) % 3], st);
+        else
+          gen_step_t<double>(s, yk, ldk, yp, ldp, out, ldo, nband, al, c, be, Cs[j % 3], cm1,
+                             Cs[(j + 1) % 3], st);
+      };
+      step(X, ld, nullptr, 0, bufs[slot(1)], lds[slot(1)], s1 / e, 0.0, 0);
+      double sk = s1;
+      for (int j = 1; j < degree; ++j) {
+        const double sk1 = 1.0 / (2.0 / s1 - sk);
+        const void *yp = (j == 1) ? X : bufs[slot(j - 1)];
+        const int64_t ldp = (j == 1) ? ld : lds[slot(j - 1)];
+        step(bufs[slot(j)], lds[slot(j)], yp, ldp, bufs[slot(j + 1)], lds[slot(j + 1)],
+             2.0 * sk1 / e, sk * sk1, j);
+        sk = sk1;
+      }
+      return;
+    }
     // Y_1 = (s1/e)(H - c) X
     apply_core(s, X, ld, nullptr, 0, bufs[slot(1)], lds[slot(1)], nband, s1 / e, c, 0.0, st,
                dtype);
@@ -898,35 +1175,78 @@ abi_status abi_spectral_bounds(abi_system s, const void *X, int64_t nband, int64
     double *scal = (double *)s->scal.get(sizeof(double) * (size_t)(160 + nband));
     double *alpha = scal + 8, *beta = scal + 80, *rq = scal + 160;
     apply_core(s, X, ld, nullptr, 0, HX, npw, nband, 1.0, 0.0, 0.0, st, dtype);
-    launch_rayleigh_quotients(npw, nband, X, ld, HX, npw, rq, st, dtype == ABI_C64);
+    if (s->has_S) {
+      // generalised quotients Re(x^H H x) / Re(x^H S x)
+      void *SX = s->blk5.get(elem_bytes(dtype) * (size_t)npw * nband);
+      apply_S(s, X, ld, SX, npw, nband, st, dtype);
+      launch_rayleigh_quotients(npw, nband, X, ld, HX, npw, rq, st, dtype == ABI_C64, SX, npw);
+    } else {
+      launch_rayleigh_quotients(npw, nband, X, ld, HX, npw, rq, st, dtype == ABI_C64);
+    }
     launch_minmax(nband, rq, scal, st);
     // Lanczos basis V (npw x (nl+1)), residual w, projections h
     const int nl = nlanczos;
     double2 *V = (double2 *)s->blk2.get(sizeof(double2) * (size_t)npw * (nl + 2));
     double2 *w = V + (size_t)npw * (nl + 1);
     double2 *h = (double2 *)s->small4.get(sizeof(double2) * 128);
-    launch_norm(npw, v0, scal + 3, st);
-    launch_scale_inv(npw, scal + 3, v0, V, st);
     int k = nl;
     int add_last = 1;
-    for (int j = 0; j < nl; ++j) {
-      apply_core(s, V + (size_t)j * npw, npw, nullptr, 0, w, npw, 1, 1.0, 0.0, 0.0, st);
-      if (j > 0) launch_axpy_dev(npw, beta + (j - 1), -1.0, V + (size_t)(j - 1) * npw, w, st);
-      launch_dot_re(npw, V + (size_t)j * npw, w, alpha + j, st);
-      launch_axpy_dev(npw, alpha + j, -1.0, V + (size_t)j * npw, w, st);
-      launch_multi_dot(npw, j + 1, V, npw, w, h, st);
-      launch_multi_axpy(npw, j + 1, V, npw, h, w, st);
-      launch_norm(npw, w, beta + j, st);
-      double ab[2];
-      CHEBFI_HIP(hipMemcpyAsync(&ab[0], alpha + j, sizeof(double), hipMemcpyDeviceToHost, st));
-      CHEBFI_HIP(hipMemcpyAsync(&ab[1], beta + j, sizeof(double), hipMemcpyDeviceToHost, st));
-      CHEBFI_HIP(hipStreamSynchronize(st));
-      if (ab[1] <= 1e-12 * std::max(1.0, std::fabs(ab[0]))) {
-        k = j + 1;
-        add_last = 0;
-        break;
+    if (s->has_S) {
+      // Lanczos on S^-1 H in the S inner product: SV holds S v_j beside v_j
+      double2 *SV = (double2 *)s->blk6.get(sizeof(double2) * (size_t)npw * (nl + 3));
+      double2 *u = SV + (size_t)npw * (nl + 1);
+      double2 *sw = u + npw;
+      apply_S(s, v0, npw, sw, npw, 1, st);
+      launch_dot_re(npw, v0, sw, scal + 4, st);
+      launch_sqrt_scalar(scal + 4, scal + 3, st);
+      launch_scale_inv(npw, scal + 3, v0, V, st);
+      launch_scale_inv(npw, scal + 3, sw, SV, st);
+      for (int j = 0; j < nl; ++j) {
+        double2 *vj = V + (size_t)j * npw;
+        apply_core(s, vj, npw, nullptr, 0, u, npw, 1, 1.0, 0.0, 0.0, st);
+        apply_Sinv(s, u, npw, w, npw, 1, st);
+        if (j > 0) launch_axpy_dev(npw, beta + (j - 1), -1.0, V + (size_t)(j - 1) * npw, w, st);
+        launch_dot_re(npw, SV + (size_t)j * npw, w, alpha + j, st);
+        launch_axpy_dev(npw, alpha + j, -1.0, vj, w, st);
+        launch_multi_dot(npw, j + 1, SV, npw, w, h, st);
+        launch_multi_axpy(npw, j + 1, V, npw, h, w, st);
+        apply_S(s, w, npw, sw, npw, 1, st);
+        launch_dot_re(npw, w, sw, scal + 4, st);
+        launch_sqrt_scalar(scal + 4, beta + j, st);
+        double ab[2];
+        CHEBFI_HIP(hipMemcpyAsync(&ab[0], alpha + j, sizeof(double), hipMemcpyDeviceToHost, st));
+        CHEBFI_HIP(hipMemcpyAsync(&ab[1], beta + j, sizeof(double), hipMemcpyDeviceToHost, st));
+        CHEBFI_HIP(hipStreamSynchronize(st));
+        if (ab[1] <= 1e-12 * std::max(1.0, std::fabs(ab[0]))) {
+          k = j + 1;
+          add_last = 0;
+          break;
+        }
+        launch_scale_inv(npw, beta + j, w, V + (size_t)(j + 1) * npw, st);
+        launch_scale_inv(npw, beta + j, sw, SV + (size_t)(j + 1) * npw, st);
       }
-      launch_scale_inv(npw, beta + j, w, V + (size_t)(j + 1) * npw, st);
+    } else {
+      launch_norm(npw, v0, scal + 3, st);
+      launch_scale_inv(npw, scal + 3, v0, V, st);
+      for (int j = 0; j < nl; ++j) {
+        apply_core(s, V + (size_t)j * npw, npw, nullptr, 0, w, npw, 1, 1.0, 0.0, 0.0, st);
+        if (j > 0) launch_axpy_dev(npw, beta + (j - 1), -1.0, V + (size_t)(j - 1) * npw, w, st);
+        launch_dot_re(npw, V + (size_t)j * npw, w, alpha + j, st);
+        launch_axpy_dev(npw, alpha + j, -1.0, V + (size_t)j * npw, w, st);
+        launch_multi_dot(npw, j + 1, V, npw, w, h, st);
+        launch_multi_axpy(npw, j + 1, V, npw, h, w, st);
+        launch_norm(npw, w, beta + j, st);
+        double ab[2];
+        CHEBFI_HIP(hipMemcpyAsync(&ab[0], alpha + j, sizeof(double), hipMemcpyDeviceToHost, st));
+        CHEBFI_HIP(hipMemcpyAsync(&ab[1], beta + j, sizeof(double), hipMemcpyDeviceToHost, st));
+        CHEBFI_HIP(hipStreamSynchronize(st));
+        if (ab[1] <= 1e-12 * std::max(1.0, std::fabs(ab[0]))) {
+          k = j + 1;
+          add_last = 0;
+          break;
+        }
+        launch_scale_inv(npw, beta + j, w, V + (size_t)(j + 1) * npw, st);
+      }
     }
     launch_tridiag_bound(k, alpha, beta, add_last, scal, st);
     double host[3];
@@ -1044,6 +1364,32 @@ abi_status abi_chebfi_solve(abi_system s, void *X, int64_t nband, int64_t ld, in
   });
 }
 
+abi_status abi_apply_S(abi_system s, const void *X, void *SX, int64_t nband, int64_t ld,
+                       int32_t dtype, void *stream) {
+  return guarded([&] {
+    check_block(s, X, nband, ld, dtype);
+    CHEBFI_REQUIRE(SX != nullptr && SX != X, ABI_ERR_ARG, "SX must be a separate block");
+    apply_S(s, X, ld, SX, ld, nband, S(stream), dtype);
+  });
+}
+
+abi_status abi_apply_Sinv(abi_system s, const void *X, void *Y, int64_t nband, int64_t ld,
+                          int32_t dtype, void *stream) {
+  return guarded([&] {
+    check_block(s, X, nband, ld, dtype);
+    CHEBFI_REQUIRE(Y != nullptr && Y != X, ABI_ERR_ARG, "Y must be a separate block");
+    apply_Sinv(s, X, ld, Y, ld, nband, S(stream), dtype);
+  });
+}
+
+abi_status abi_overlap_info(abi_system s, int32_t *has_overlap, double *s_min) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(s != nullptr, ABI_ERR_ARG, "system handle is NULL");
+    if (has_overlap) *has_overlap = s->has_S ? 1 : 0;
+    if (s_min) *s_min = s->s_min;
+  });
+}
+
 abi_status abi_update_potential(abi_system s, const double *vloc, const void *dij, void *stream) {
   return guarded([&] {
     CHEBFI_REQUIRE(s != nullptr, ABI_ERR_ARG, "system handle is NULL");
@@ -1064,6 +1410,8 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
                                double a0, int32_t ckpt_every, double *dV, void *dD, void *dX,
                                void *stream) {
   return guarded([&] {
+    CHEBFI_REQUIRE(s == nullptr || !s->has_S, ABI_ERR_STATE,
+                   "the filter adjoint is provided for S = I only");
     check_block(s, X, nband, ld, dtype);
     CHEBFI_REQUIRE(W != nullptr, ABI_ERR_ARG, "W is NULL");
     CHEBFI_REQUIRE(dV != nullptr, ABI_ERR_ARG, "dV is NULL");
@@ -1352,6 +1700,8 @@ abi_status abi_set_system_batch(const abi_system_desc *descs, int32_t nsys, void
                      "a batched system has more than 8 atoms");
       CHEBFI_REQUIRE(descs[i].precision == descs[0].precision, ABI_ERR_ARG,
                      "all systems of a batch need the same precision");
+      CHEBFI_REQUIRE(descs[i].abi_version < 2 || descs[i].qij == nullptr, ABI_ERR_ARG,
+                     "the batched filter takes systems with S = I (no Q)");
     }
     B = new abi_batch_s();
     B->precision = descs[0].precision;

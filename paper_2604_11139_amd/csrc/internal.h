@@ -192,6 +192,13 @@ struct abi_system_s {
   uint16_t *d_PA = nullptr;        // rows = projectors, k = plane waves (stride ldPA)
   uint16_t *d_PB = nullptr;        // rows = plane waves, k = projectors (stride ldPB)
   int64_t ldPA = 0, ldPB = 0;
+  // overlap S = I + sum_R P_R Q_R P_R^H (descriptions with Q): Q per atom, the
+  // projector Gram B = P^H P and the Woodbury kernel K with S^-1 = I - P K P^H
+  // (nproj x nproj complex, ld nproj); s_min is the smallest eigenvalue of S
+  bool has_S = false;
+  double *d_Q = nullptr;           // natom*16 complex, row-major per atom
+  double *d_B = nullptr, *d_K = nullptr;
+  double s_min = 1.0;
   int mixed_gemm = 0;              // 0: split-BF16 MFMA, 1: FP32 MFMA projector products
   int pl_proj = 0, pl_expand = 0;  // tile variants of the split-BF16 products
 
@@ -199,6 +206,7 @@ struct abi_system_s {
   chebfi::DevBuf box, cpart, cprime, blk1, blk2, blk3, small1, small2, small3, small4, scal;
   chebfi::DevBuf eig1, eig2, eig3, blk4, box2, adj, adjsmall, planes, cplanes;
   chebfi::DevBuf solve1, solve2, solve3;  // blocks of the multi-cycle driver
+  chebfi::DevBuf gen_c, gen_e, gen_f, gen_ff, blk5, blk6;  // overlap path
 
   int fft_batch = 0;  // bands per FFT batch (box buffer holds this many boxes)
   // second stream: the FFT passes of an H application run on it beside the

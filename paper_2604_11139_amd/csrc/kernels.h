@@ -98,10 +98,24 @@ void zsum_parts(int64_t m, int64_t n, const void *part, int splits, void *C, int
 void launch_dapply(int natom, int64_t nband, const void *part, int splits, const void *D,
                    double alpha, void *Cprime, hipStream_t st, bool fp32 = false);
 
-// rq[b] = Re(x_b^H hx_b) / (x_b^H x_b)
+// rq[b] = Re(x_b^H hx_b) / Re(x_b^H sx_b); sx_b = x_b when SX is null
 void launch_rayleigh_quotients(int64_t npw, int64_t nband, const void *X, int64_t ldx,
                                const void *HX, int64_t ldh, double *rq, hipStream_t st,
-                               bool fp32 = false);
+                               bool fp32 = false, const void *SX = nullptr, int64_t lds = 0);
+// Small-matrix part of a generalised filter step (m x n complex double, ld m):
+// G = sum of the split partials of P^H Out (complex float with fp32),
+// E = G / alpha + cshift Ck + (beta / alpha) Ckm1 (Ckm1 may be null), Cnext = G.
+void launch_gen_combine(int64_t m, int64_t n, const void *part, int splits, bool fp32,
+                        const void *Ck, const void *Ckm1, double alpha, double cshift,
+                        double beta, void *E, void *Cnext, hipStream_t st);
+// out (m x n complex double, contiguous) = sum of the split partials
+void launch_parts_to_c128(int64_t m, int64_t n, const void *part, int splits, bool fp32,
+                          void *out, hipStream_t st);
+// out[:, j] = W[:, j] mu_j / (1 + mu_j)  (m x m complex double)
+void launch_woodbury_scale(int64_t m, const void *W, int64_t ldw, const double *mu, void *out,
+                           int64_t ldo, hipStream_t st);
+// *out = sqrt(max(*in, 0))
+void launch_sqrt_scalar(const double *in, double *out, hipStream_t st);
 // complex block precision conversions (round to nearest when narrowing)
 void launch_c64_to_c128(int64_t rows, int64_t cols, const void *src, int64_t lds, void *dst,
                         int64_t ldd, hipStream_t st);

@@ -65,18 +65,21 @@ __global__ void dapply_kernel(int natom, int64_t nband, const C2<T> *__restrict_
   }
 }
 
+// rq[b] = Re(x^H hx) / Re(x^H sx), sx = x when SX is null (S = I)
 template <typename T>
 __global__ void rq_kernel(int64_t npw, const C2<T> *__restrict__ X, int64_t ldx,
-                          const C2<T> *__restrict__ HX, int64_t ldh, double *__restrict__ rq) {
+                          const C2<T> *__restrict__ HX, int64_t ldh,
+                          const C2<T> *__restrict__ SX, int64_t lds, double *__restrict__ rq) {
   __shared__ double scratch[16];
   const int64_t b = blockIdx.x;
   const C2<T> *x = X + b * ldx;
   const C2<T> *h = HX + b * ldh;
+  const C2<T> *sx = SX ? SX + b * lds : x;
   double num = 0, den = 0;
   for (int64_t i = threadIdx.x; i < npw; i += blockDim.x) {
-    const C2<T> xv = x[i], hv = h[i];
+    const C2<T> xv = x[i], hv = h[i], sv = sx[i];
     num += (double)xv.x * hv.x + (double)xv.y * hv.y;
-    den += (double)xv.x * xv.x + (double)xv.y * xv.y;
+    den += (double)xv.x * sv.x + (double)xv.y * sv.y;
   }
   num = block_sum(num, scratch);
   den = block_sum(den, scratch);
@@ -351,6 +354,66 @@ __global__ void d2f_kernel(int64_t n, const double *__restrict__ s, float *__res
   if (i < n) d[i] = (float)s[i];
 }
 
+// Generalised filter step, small-matrix part (n projectors x nband, complex
+// double, ld n): with G = sum_z part[z] = P^H Out (Out = alpha (T - c Y_k) -
+// beta Y_{k-1} after the local passes, T the kinetic + local part of H Y_k),
+// E = P^H T = G / alpha + c C_k + (beta / alpha) C_{k-1} and Cnext = G.
+template <typename T>
+__global__ void gen_combine_kernel(int64_t mn, int splits, const C2<T> *__restrict__ part,
+                                   const double2 *__restrict__ Ck,
+                                   const double2 *__restrict__ Ckm1, double alpha, double cshift,
+                                   double beta, double2 *__restrict__ E,
+                                   double2 *__restrict__ Cnext) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= mn) return;
+  double gx = 0.0, gy = 0.0;
+  for (int z = 0; z < splits; ++z) {
+    const C2<T> v = part[(int64_t)z * mn + idx];
+    gx += (double)v.x;
+    gy += (double)v.y;
+  }
+  const double inv = 1.0 / alpha;
+  const double2 ck = Ck[idx];
+  double ex = gx * inv + cshift * ck.x, ey = gy * inv + cshift * ck.y;
+  if (Ckm1) {
+    const double2 cp = Ckm1[idx];
+    ex += beta * inv * cp.x;
+    ey += beta * inv * cp.y;
+  }
+  E[idx] = double2{ex, ey};
+  Cnext[idx] = double2{gx, gy};
+}
+
+// out = sum_z part[z] in complex double (partials complex float or double)
+template <typename T>
+__global__ void parts_to_c128_kernel(int64_t mn, int splits, const C2<T> *__restrict__ part,
+                                     double2 *__restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= mn) return;
+  double sx = 0.0, sy = 0.0;
+  for (int z = 0; z < splits; ++z) {
+    const C2<T> v = part[(int64_t)z * mn + idx];
+    sx += (double)v.x;
+    sy += (double)v.y;
+  }
+  out[idx] = double2{sx, sy};
+}
+
+// out[:, j] = W[:, j] * mu_j / (1 + mu_j)   (m x m, Woodbury kernel of S^-1)
+__global__ void woodbury_scale_kernel(int64_t m, const double2 *__restrict__ W, int64_t ldw,
+                                      const double *__restrict__ mu, double2 *__restrict__ out,
+                                      int64_t ldo) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * m) return;
+  const int64_t i = idx % m, j = idx / m;
+  const double f = mu[j] / (1.0 + mu[j]);
+  out[i + j * ldo] = cscale(W[i + j * ldw], f);
+}
+
+__global__ void sqrt_scalar_kernel(const double *__restrict__ in, double *__restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = sqrt(fmax(*in, 0.0));
+}
+
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -420,13 +483,57 @@ void launch_dapply(int natom, int64_t nband, const void *part, int splits, const
 
 void launch_rayleigh_quotients(int64_t npw, int64_t nband, const void *X, int64_t ldx,
                                const void *HX, int64_t ldh, double *rq, hipStream_t st,
-                               bool fp32) {
+                               bool fp32, const void *SX, int64_t lds) {
   if (fp32)
     hipLaunchKernelGGL(rq_kernel<float>, dim3((unsigned)nband), dim3(kRedThreads), 0, st, npw,
-                       (const float2 *)X, ldx, (const float2 *)HX, ldh, rq);
+                       (const float2 *)X, ldx, (const float2 *)HX, ldh, (const float2 *)SX, lds,
+                       rq);
   else
     hipLaunchKernelGGL(rq_kernel<double>, dim3((unsigned)nband), dim3(kRedThreads), 0, st, npw,
-                       (const double2 *)X, ldx, (const double2 *)HX, ldh, rq);
+                       (const double2 *)X, ldx, (const double2 *)HX, ldh, (const double2 *)SX,
+                       lds, rq);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_gen_combine(int64_t m, int64_t n, const void *part, int splits, bool fp32,
+                        const void *Ck, const void *Ckm1, double alpha, double cshift,
+                        double beta, void *E, void *Cnext, hipStream_t st) {
+  const int64_t mn = m * n;
+  if (mn <= 0) return;
+  if (fp32)
+    hipLaunchKernelGGL(gen_combine_kernel<float>, dim3(nblk(mn, 256)), dim3(256), 0, st, mn,
+                       splits, (const float2 *)part, (const double2 *)Ck, (const double2 *)Ckm1,
+                       alpha, cshift, beta, (double2 *)E, (double2 *)Cnext);
+  else
+    hipLaunchKernelGGL(gen_combine_kernel<double>, dim3(nblk(mn, 256)), dim3(256), 0, st, mn,
+                       splits, (const double2 *)part, (const double2 *)Ck, (const double2 *)Ckm1,
+                       alpha, cshift, beta, (double2 *)E, (double2 *)Cnext);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_parts_to_c128(int64_t m, int64_t n, const void *part, int splits, bool fp32,
+                          void *out, hipStream_t st) {
+  const int64_t mn = m * n;
+  if (mn <= 0) return;
+  if (fp32)
+    hipLaunchKernelGGL(parts_to_c128_kernel<float>, dim3(nblk(mn, 256)), dim3(256), 0, st, mn,
+                       splits, (const float2 *)part, (double2 *)out);
+  else
+    hipLaunchKernelGGL(parts_to_c128_kernel<double>, dim3(nblk(mn, 256)), dim3(256), 0, st, mn,
+                       splits, (const double2 *)part, (double2 *)out);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_woodbury_scale(int64_t m, const void *W, int64_t ldw, const double *mu, void *out,
+                           int64_t ldo, hipStream_t st) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(woodbury_scale_kernel, dim3(nblk(m * m, 256)), dim3(256), 0, st, m,
+                     (const double2 *)W, ldw, mu, (double2 *)out, ldo);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_sqrt_scalar(const double *in, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(sqrt_scalar_kernel, dim3(1), dim3(64), 0, st, in, out);
   CHEBFI_HIP(hipGetLastError());
 }
 
