@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the measured copy / vendor-GEMM ceilings")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the adjoint and batched-workload legs")
+                    help="skip the adjoint, batched-workload and PAW legs")
     return ap.parse_args()
 
 
@@ -163,6 +163,45 @@ def batch_leg():
             "value": round(deg * nb / (graph_ms / 1e3), 1), "unit": "band-apps/s",
             "ms_per_filter_graph": round(graph_ms, 3), "ms_per_filter_eager": round(eager_ms, 3),
             "ms_one_system_at_a_time": round(single_ms, 3), "autotune": choice}
+
+
+def paw_leg(config, identity_filter_ms):
+    """The large workload with a PAW-like overlap S = I + P Q P^H (seeded indefinite
+    Q per atom, S spectrum about [0.8, 1.8]): cycles of S-Lanczos bounds, the filter
+    on S^-1 H and the S-Gram Rayleigh-Ritz, mixed and FP64, timed like the head line."""
+    import torch
+
+    import workloads as W
+    from paper_2604_11139_amd import binding as B
+
+    s = W.make_system(config, q_scale=W.PAW_Q_SCALE)
+    out = {"workload": f"config{config} with the overlap S = I + sum_R P_R Q_R P_R^H "
+                       f"(Q_R = {W.PAW_Q_SCALE:g} (H_R + {W.systems.Q_SHIFT:g} I), H_R Hermitian "
+                       "U[-1,1]; S spectrum about [0.8, 1.8]), filter on S^-1 H, degree "
+                       f"{s.degree}"}
+    for name, prec in (("mixed", B.ABI_PREC_MIXED), ("fp64", B.ABI_PREC_FP64)):
+        t0 = time.perf_counter()
+        g = B.System(s, precision=prec)
+        setup = time.perf_counter() - t0
+        X = torch.from_numpy(W.random_block(g.npw, s.nband, s.tag).T).to("cuda")
+        v0 = torch.from_numpy(W.random_vector(g.npw, s.tag)).to("cuda")
+        if name == "mixed":
+            X = X.to(torch.complex64)
+        r = run_cycles(g, X, v0, s.degree, 1, 1)
+        out[name] = {"value": round(r["value"], 2), "unit": "band-apps/s",
+                     "filter_ms_per_step": round(r["filter_ms_per_step"], 2),
+                     "ms_per_cycle": round(r["ms_per_step"], 2), "setup_s": round(setup, 2),
+                     "s_min": g.overlap_info()[1],
+                     "max_residual_second_cycle": float(r["res"].max()),
+                     "kernel_classes": class_table(r["prof"])}
+        if name == "mixed":
+            out["value"] = out[name]["value"]
+            out["filter_time_over_s_identity"] = round(
+                r["filter_ms_per_step"] / identity_filter_ms, 3)
+        g.close()
+        del X
+        torch.cuda.synchronize()
+    return out
 
 
 def ceilings():
@@ -447,6 +486,7 @@ def main():
     if not args.no_extras and mixed:
         out["adjoint"] = adjoint_leg(g, X32, v0, degree)
         out["batch"] = batch_leg()
+        out["paw"] = paw_leg(args.config, head["filter_ms_per_step"])
     if args.cpu_bands > 0:
         out["cpu_baseline"] = cpu_baseline(s, degree, head["bounds"], args.cpu_bands)
     print(json.dumps(out), flush=True)
