@@ -151,6 +151,8 @@ template <typename T> T *upload(const T *host, size_t count) {
 void free_tables(abi_system_s *s) {
   if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
   if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+  if (s->ev_half) (void)hipEventDestroy(s->ev_half);
+  s->ev_half = nullptr;
   if (s->aux) (void)hipStreamDestroy(s->aux);
   s->ev_fork = s->ev_join = nullptr;
   s->aux = nullptr;
@@ -405,6 +407,10 @@ void apply_Sinv(abi_system_s *s, const void *X, int64_t ldx, void *Out, int64_t 
 // itself; then Out += alpha P F and Cnext = G + alpha B F.  One projection and
 // one expansion of the block per step, as for S = I, plus three nproj x nproj
 // products by nband.
+// The projection reads the local passes' output, so the two are pipelined over
+// two halves of the bands: the passes of the second half (second stream) run
+// beside the projection of the first, and D Ck, B D Ck beside the first half's
+// passes.
 template <typename T>
 void gen_step_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
                 void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
@@ -412,15 +418,46 @@ void gen_step_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, 
   typedef C2<T> V2;
   const bool fp32 = std::is_same<T, float>::value;
   const int n = s->nproj;
-  local_t<T>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, st);
-  V2 *cpart = nullptr;
-  const int splits = project_t<T>(s, Out, ldo, nband, st, &cpart);
+  const size_t eb = sizeof(V2);
+  const bool side = s->overlap && s->aux && nband >= 128;
+  // band ranges [0, h) and [h, nband)
+  const int64_t h = side ? (nband / 2 + 31) / 32 * 32 : nband;
+  auto at = [&](const void *p, int64_t ld, int64_t b) -> const void * {
+    return p ? (const void *)((const char *)p + eb * (size_t)(b * ld)) : nullptr;
+  };
+  auto local_range = [&](int64_t b0, int64_t nb, hipStream_t sst) {
+    local_t<T>(s, at(X, ldx, b0), ldx, at(Xprev, ldp, b0), ldp,
+               (void *)at(Out, ldo, b0), ldo, nb, alpha, cshift, beta, sst);
+  };
+  if (side) {
+    CHEBFI_HIP(hipEventRecord(s->ev_fork, st));
+    CHEBFI_HIP(hipStreamWaitEvent(s->aux, s->ev_fork, 0));
+    local_range(0, h, s->aux);
+    CHEBFI_HIP(hipEventRecord(s->ev_half, s->aux));
+    local_range(h, nband - h, s->aux);
+    CHEBFI_HIP(hipEventRecord(s->ev_join, s->aux));
+  } else {
+    local_range(0, nband, st);
+  }
   double2 *E = (double2 *)s->gen_e.get(sizeof(double2) * (size_t)n * nband);
   double2 *F = (double2 *)s->gen_f.get(sizeof(double2) * (size_t)n * nband);
-  const int tok = s->prof.begin(PROF_DAPPLY, 24.0 * (double)n * n * nband, st);
-  launch_gen_combine(n, nband, cpart, splits, fp32, Ck, Ckm1, alpha, cshift, beta, E, Cnext, st);
+  int tok = s->prof.begin(PROF_DAPPLY, 8.0 * (double)n * n * nband, st);
   launch_dapply(s->natom, nband, Ck, 1, s->d_D, 1.0, F, st, false);  // F = D Ck
-  zgemm(OP_N, OP_N, n, nband, n, s->d_B, n, F, n, E, n, double2{1, 0}, double2{1, 0}, st);
+  zgemm(OP_N, OP_N, n, nband, n, s->d_B, n, F, n, E, n, double2{1, 0}, double2{0, 0},
+        st);  // E = B D Ck
+  s->prof.end(tok, st);
+  // G = P^H Out per band range; E += G / alpha + c Ck + (beta / alpha) Ckm1, Cnext = G
+  for (int part = 0; part < 2; ++part) {
+    const int64_t b0 = part == 0 ? 0 : h, nb = part == 0 ? h : nband - h;
+    if (nb <= 0) continue;
+    if (side) CHEBFI_HIP(hipStreamWaitEvent(st, part == 0 ? s->ev_half : s->ev_join, 0));
+    V2 *cpart = nullptr;
+    const int splits = project_t<T>(s, at(Out, ldo, b0), ldo, nb, st, &cpart);
+    const size_t off = (size_t)n * b0;
+    launch_gen_combine(n, nb, cpart, splits, fp32, Ck + off, Ckm1 ? Ckm1 + off : nullptr, alpha,
+                       cshift, beta, E + off, Cnext + off, st);
+  }
+  tok = s->prof.begin(PROF_DAPPLY, 16.0 * (double)n * n * nband, st);
   zgemm(OP_N, OP_N, n, nband, n, s->d_K, n, E, n, F, n, double2{-alpha, 0}, double2{alpha, 0},
         st);  // F = alpha (D Ck - K E)
   zgemm(OP_N, OP_N, n, nband, n, s->d_B, n, F, n, Cnext, n, double2{1, 0}, double2{1, 0}, st);
@@ -1023,6 +1060,7 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
     CHEBFI_HIP(hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking));
     CHEBFI_HIP(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
     CHEBFI_HIP(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
+    CHEBFI_HIP(hipEventCreateWithFlags(&s->ev_half, hipEventDisableTiming));
     s->overlap = 1;
     if (const char *e = std::getenv("CHEBFI_OVERLAP")) s->overlap = std::atoi(e) != 0;
     if (desc->abi_version >= 2 && desc->qij != nullptr) setup_overlap(s, desc->qij, S(stream));

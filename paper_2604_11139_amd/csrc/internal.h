@@ -212,7 +212,7 @@ struct abi_system_s {
   // second stream: the FFT passes of an H application run on it beside the
   // projection GEMM (they are independent until the expansion)
   hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_half = nullptr;
   int overlap = 1;
   chebfi::Profiler prof;
 };

@@ -104,7 +104,7 @@ void launch_rayleigh_quotients(int64_t npw, int64_t nband, const void *X, int64_
                                bool fp32 = false, const void *SX = nullptr, int64_t lds = 0);
 // Small-matrix part of a generalised filter step (m x n complex double, ld m):
 // G = sum of the split partials of P^H Out (complex float with fp32),
-// E = G / alpha + cshift Ck + (beta / alpha) Ckm1 (Ckm1 may be null), Cnext = G.
+// E += G / alpha + cshift Ck + (beta / alpha) Ckm1 (Ckm1 may be null), Cnext = G.
 void launch_gen_combine(int64_t m, int64_t n, const void *part, int splits, bool fp32,
                         const void *Ck, const void *Ckm1, double alpha, double cshift,
                         double beta, void *E, void *Cnext, hipStream_t st);

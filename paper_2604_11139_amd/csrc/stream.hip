@@ -357,7 +357,7 @@ __global__ void d2f_kernel(int64_t n, const double *__restrict__ s, float *__res
 // Generalised filter step, small-matrix part (n projectors x nband, complex
 // double, ld n): with G = sum_z part[z] = P^H Out (Out = alpha (T - c Y_k) -
 // beta Y_{k-1} after the local passes, T the kinetic + local part of H Y_k),
-// E = P^H T = G / alpha + c C_k + (beta / alpha) C_{k-1} and Cnext = G.
+// E += P^H T = G / alpha + c C_k + (beta / alpha) C_{k-1} and Cnext = G.
 template <typename T>
 __global__ void gen_combine_kernel(int64_t mn, int splits, const C2<T> *__restrict__ part,
                                    const double2 *__restrict__ Ck,
@@ -373,14 +373,14 @@ __global__ void gen_combine_kernel(int64_t mn, int splits, const C2<T> *__restri
     gy += (double)v.y;
   }
   const double inv = 1.0 / alpha;
-  const double2 ck = Ck[idx];
+  const double2 ck = Ck[idx], e0 = E[idx];
   double ex = gx * inv + cshift * ck.x, ey = gy * inv + cshift * ck.y;
   if (Ckm1) {
     const double2 cp = Ckm1[idx];
     ex += beta * inv * cp.x;
     ey += beta * inv * cp.y;
   }
-  E[idx] = double2{ex, ey};
+  E[idx] = double2{e0.x + ex, e0.y + ey};
   Cnext[idx] = double2{gx, gy};
 }
 
