@@ -47,3 +47,4 @@ from .overlap import (  # noqa: F401,E402
     residual_norms_gen,
     sinv_h,
 )
+from .lobpcg import lobpcg_pass, tpa_precondition  # noqa: F401,E402
