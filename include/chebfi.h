@@ -211,6 +211,30 @@ abi_status abi_chebfi_solve(abi_system sys, void *X, int64_t nband, int64_t ld, 
                             double tol, int32_t refine_degree, double *eval, double *resnorm,
                             int32_t *info, void *stream);
 
+/* Block LOBPCG, the solver the paper compares the Chebyshev filter with
+ * (Algorithm "Parallel LOBPCG with b blocks and k line minimizations"), built on
+ * the same kernels: passes over the nblocks blocks of nband/nblocks bands, each
+ * block S-deflated against the blocks before it (X <- X - Q (Q^H S X)),
+ * orthonormalised and rotated by Rayleigh-Ritz, then up to nline line
+ * minimisations: W = (H - Lambda S) Psi (the block stops once all its residual
+ * norms are <= tol), W <- K W with the Teter-Payne-Allan diagonal
+ * K_G = p(x)/(p(x) + 16x^4), p = 27 + 18x + 12x^2 + 8x^3, x = 0.5|k+G|^2 / E_kin(psi),
+ * S-deflation of W, H W and S W, columns of W and P scaled to unit S-norm,
+ * S-ortho + Rayleigh-Ritz of [Psi, W] (first step) or [Psi, W, P] (falling
+ * back to [Psi, W] when that Gram is not positive definite), P <- W C_W + P C_P,
+ * Psi <- Psi C_Psi + P; with nblocks > 1 a global S-ortho + Rayleigh-Ritz ends the
+ * pass.  Passes repeat until the lowest nconv residual norms are <= tol or
+ * max_passes have run.  FP64 only: X (in: start block, out: Ritz vectors) is a
+ * complex128 npw x nband block (ld).  eval, resnorm (host, nband; resnorm may be
+ * NULL): the last pass's Ritz values (ascending) and ||H psi - lambda S psi||.
+ * info (host, 4 entries, may be NULL): passes, line minimisations run (summed
+ * over blocks and passes), converged (0/1), 0.  Synchronises the stream.
+ * ABI_ERR_NOT_HPD if the Gram of a block or of [Psi, W] breaks down. */
+abi_status abi_lobpcg_solve(abi_system sys, void *X, int64_t nband, int64_t ld, int32_t dtype,
+                            int32_t nblocks, int32_t nline, int32_t max_passes, int32_t nconv,
+                            double tol, double *eval, double *resnorm, int32_t *info,
+                            void *stream);
+
 /* Replaces V_loc (device, n1*n2*n3 doubles, i1 fastest) and/or D (device,
  * natom*16 complex doubles, row-major per atom); a NULL pointer keeps the old
  * table.  Stream-ordered; for differentiation and finite differences. */

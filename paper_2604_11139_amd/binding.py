@@ -39,6 +39,7 @@ EXPORTS = [
     "abi_filter_backward", "abi_density", "abi_last_error", "abi_set_system_batch",
     "abi_batch_system", "abi_cheb_filter_batch", "abi_batch_autotune", "abi_batch_use_graph",
     "abi_destroy_batch", "abi_chebfi_solve", "abi_apply_S", "abi_apply_Sinv", "abi_overlap_info",
+    "abi_lobpcg_solve",
 ]
 
 PROFILE_CLASSES = ["proj_gemm", "expand_gemm", "fft_a", "fft_b", "fft_c", "dapply", "gram",
@@ -113,6 +114,8 @@ def lib():
         "abi_apply_S": [vp, vp, vp, c_int64, c_int64, c_int32, vp],
         "abi_apply_Sinv": [vp, vp, vp, c_int64, c_int64, c_int32, vp],
         "abi_overlap_info": [vp, POINTER(c_int32), POINTER(c_double)],
+        "abi_lobpcg_solve": [vp, vp, c_int64, c_int64, c_int32, c_int32, c_int32, c_int32,
+                             c_int32, c_double, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -399,6 +402,21 @@ class System:
                                       ev.ctypes.data_as(c_void_p), res.ctypes.data_as(c_void_p),
                                       info.ctypes.data_as(c_void_p), _stream()))
         return ev, res, {"cycles": int(info[0]), "refine_cycles": int(info[1]),
+                         "converged": bool(info[2])}
+
+    def lobpcg(self, X, nblocks, nline, max_passes=1, nconv=None, tol=0.0):
+        """In place: X <- Ritz vectors after passes of block LOBPCG (complex128).
+        Returns (eval, resnorm, info dict)."""
+        px, nb, ld, code = _block(X, self.npw)
+        nconv = nb if nconv is None else int(nconv)
+        ev = np.zeros(nb)
+        res = np.zeros(nb)
+        info = np.zeros(4, dtype=np.int32)
+        _check(lib().abi_lobpcg_solve(self._h, px, nb, ld, code, int(nblocks), int(nline),
+                                      int(max_passes), nconv, float(tol),
+                                      ev.ctypes.data_as(c_void_p), res.ctypes.data_as(c_void_p),
+                                      info.ctypes.data_as(c_void_p), _stream()))
+        return ev, res, {"passes": int(info[0]), "line_steps": int(info[1]),
                          "converged": bool(info[2])}
 
     def profile(self, on=True):

@@ -207,6 +207,8 @@ struct abi_system_s {
   chebfi::DevBuf eig1, eig2, eig3, blk4, box2, adj, adjsmall, planes, cplanes;
   chebfi::DevBuf solve1, solve2, solve3;  // blocks of the multi-cycle driver
   chebfi::DevBuf gen_c, gen_e, gen_f, gen_ff, blk5, blk6;  // overlap path
+  chebfi::DevBuf lob_z, lob_hz, lob_sz, lob_t1, lob_t2, lob_t3, lob_psi, lob_hp, lob_sp, lob_c,
+      lob_g, lob_v;  // block LOBPCG
 
   int fft_batch = 0;  // bands per FFT batch (box buffer holds this many boxes)
   // second stream: the FFT passes of an H application run on it beside the

@@ -116,6 +116,15 @@ void launch_woodbury_scale(int64_t m, const void *W, int64_t ldw, const double *
                            int64_t ldo, hipStream_t st);
 // *out = sqrt(max(*in, 0))
 void launch_sqrt_scalar(const double *in, double *out, hipStream_t st);
+// LOBPCG block helpers (npw x m complex double blocks, one column per band):
+// W = HX - lam_b SX with res[b] = ||W_b||;  W_b *= Teter-Payne-Allan diagonal of X_b;
+// columns of W, HW (, SW) scaled to unit S-norm (SW null: S = I).
+void launch_resid_block(int64_t npw, int64_t m, const void *HX, const void *SX, int64_t ld,
+                        const double *lam, void *W, int64_t ldw, double *res, hipStream_t st);
+void launch_tpa(int64_t npw, int64_t m, const double *kin, const void *X, int64_t ldx, void *W,
+                int64_t ldw, hipStream_t st);
+void launch_snorm_scale(int64_t npw, int64_t m, void *W, void *HW, void *SW, int64_t ld,
+                        hipStream_t st);
 // complex block precision conversions (round to nearest when narrowing)
 void launch_c64_to_c128(int64_t rows, int64_t cols, const void *src, int64_t lds, void *dst,
                         int64_t ldd, hipStream_t st);

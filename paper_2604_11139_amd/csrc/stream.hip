@@ -414,6 +414,79 @@ __global__ void sqrt_scalar_kernel(const double *__restrict__ in, double *__rest
   if (threadIdx.x == 0 && blockIdx.x == 0) *out = sqrt(fmax(*in, 0.0));
 }
 
+// LOBPCG block kernels (complex double, one workgroup per column b).
+// W = HX - lam_b SX and res[b] = ||W_b||.
+__global__ void resid_block_kernel(int64_t npw, const double2 *__restrict__ HX,
+                                   const double2 *__restrict__ SX, int64_t ld,
+                                   const double *__restrict__ lam, double2 *__restrict__ W,
+                                   int64_t ldw, double *__restrict__ res) {
+  __shared__ double scratch[16];
+  const int64_t b = blockIdx.x;
+  const double l = lam[b];
+  const double2 *h = HX + b * ld;
+  const double2 *sx = SX + b * ld;
+  double2 *w = W + b * ldw;
+  double acc = 0;
+  for (int64_t i = threadIdx.x; i < npw; i += blockDim.x) {
+    const double2 hv = h[i], sv = sx[i];
+    const double2 r{hv.x - l * sv.x, hv.y - l * sv.y};
+    w[i] = r;
+    acc += r.x * r.x + r.y * r.y;
+  }
+  acc = block_sum(acc, scratch);
+  if (threadIdx.x == 0) res[b] = sqrt(acc);
+}
+
+// Teter-Payne-Allan diagonal: W_b *= p(x) / (p(x) + 16 x^4), x = kin / E_kin(X_b),
+// p(x) = 27 + 18 x + 12 x^2 + 8 x^3.
+__global__ void tpa_kernel(int64_t npw, const double *__restrict__ kin,
+                           const double2 *__restrict__ X, int64_t ldx, double2 *__restrict__ W,
+                           int64_t ldw) {
+  __shared__ double scratch[16];
+  const int64_t b = blockIdx.x;
+  const double2 *x = X + b * ldx;
+  double2 *w = W + b * ldw;
+  double num = 0, den = 0;
+  for (int64_t i = threadIdx.x; i < npw; i += blockDim.x) {
+    const double2 v = x[i];
+    const double a2 = v.x * v.x + v.y * v.y;
+    num += kin[i] * a2;
+    den += a2;
+  }
+  num = block_sum(num, scratch);
+  den = block_sum(den, scratch);
+  const double inv_ek = den / num;
+  for (int64_t i = threadIdx.x; i < npw; i += blockDim.x) {
+    const double t = kin[i] * inv_ek;
+    const double p = 27.0 + t * (18.0 + t * (12.0 + t * 8.0));
+    const double t2 = t * t;
+    w[i] = cscale(w[i], p / (p + 16.0 * t2 * t2));
+  }
+}
+
+// Scales column b of W, HW (and SW when given) by 1 / sqrt(Re(w^H sw)), sw = w when
+// SW is null.
+__global__ void snorm_scale_kernel(int64_t npw, double2 *__restrict__ W, double2 *__restrict__ HW,
+                                   double2 *__restrict__ SW, int64_t ld) {
+  __shared__ double scratch[16];
+  const int64_t b = blockIdx.x;
+  double2 *w = W + b * ld;
+  double2 *hw = HW + b * ld;
+  double2 *sw = SW ? SW + b * ld : nullptr;
+  double acc = 0;
+  for (int64_t i = threadIdx.x; i < npw; i += blockDim.x) {
+    const double2 a = w[i], c = sw ? sw[i] : a;
+    acc += a.x * c.x + a.y * c.y;
+  }
+  acc = block_sum(acc, scratch);
+  const double f = 1.0 / sqrt(acc);
+  for (int64_t i = threadIdx.x; i < npw; i += blockDim.x) {
+    w[i] = cscale(w[i], f);
+    hw[i] = cscale(hw[i], f);
+    if (sw) sw[i] = cscale(sw[i], f);
+  }
+}
+
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -632,6 +705,30 @@ void launch_copy_block(int64_t rows, int64_t cols, const void *src, int64_t lds,
 void launch_zero_lower(int64_t m, void *A, int64_t lda, hipStream_t st) {
   hipLaunchKernelGGL(zero_lower_kernel, dim3(nblk(m * m, 256)), dim3(256), 0, st, m,
                      (double2 *)A, lda);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_resid_block(int64_t npw, int64_t m, const void *HX, const void *SX, int64_t ld,
+                        const double *lam, void *W, int64_t ldw, double *res, hipStream_t st) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(resid_block_kernel, dim3((unsigned)m), dim3(kRedThreads), 0, st, npw,
+                     (const double2 *)HX, (const double2 *)SX, ld, lam, (double2 *)W, ldw, res);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_tpa(int64_t npw, int64_t m, const double *kin, const void *X, int64_t ldx, void *W,
+                int64_t ldw, hipStream_t st) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(tpa_kernel, dim3((unsigned)m), dim3(kRedThreads), 0, st, npw, kin,
+                     (const double2 *)X, ldx, (double2 *)W, ldw);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_snorm_scale(int64_t npw, int64_t m, void *W, void *HW, void *SW, int64_t ld,
+                        hipStream_t st) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(snorm_scale_kernel, dim3((unsigned)m), dim3(kRedThreads), 0, st, npw,
+                     (double2 *)W, (double2 *)HW, (double2 *)SW, ld);
   CHEBFI_HIP(hipGetLastError());
 }
 
