@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--paw", action="store_true",
                     help="time the workload with the PAW-like overlap S (filter on S^-1 H)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the adjoint, batched-workload, PAW and solver-comparison legs")
+                    help="skip the adjoint, batched, PAW, solver-comparison and SCF legs")
     return ap.parse_args()
 
 
@@ -238,6 +238,34 @@ def solver_comparison_leg():
     out["lobpcg_over_chebfi_time"] = round(out["lobpcg_b4_k4"]["wall_s"]
                                            / out["chebfi_degree12"]["wall_s"], 2)
     return out
+
+
+def scf_leg():
+    """Outer SCF iterations on the medium workload (22119 plane waves, 512 bands,
+    64 atoms, 36^3 grid, FP64): 256 electrons, kT = 0.01 Ha, two cycles of the
+    degree-10 filter loop per iteration, Kerker mixing (alpha 0.5, q0 = 0.8 / bohr),
+    until max |V_out - V_in| <= 1e-4 Ha."""
+    import torch
+
+    import workloads as W
+    from paper_2604_11139_amd import binding as B
+
+    s = W.make_system(2)
+    with B.System(s) as g:
+        X = torch.from_numpy(W.random_block(g.npw, s.nband, s.tag).T).to("cuda")
+        v0 = torch.from_numpy(W.random_vector(g.npw, s.tag)).to("cuda")
+        vion = torch.from_numpy(s.vloc).to("cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, rho, dv, info = g.scf(X, v0, vion, 256.0, 0.01, 0.5, 10, 2, 80, 1e-4, q0=0.8)
+        wall = time.perf_counter() - t0
+        pot_ms = _timed_ms(lambda: g.scf_potential(rho, vion), reps=10)
+    return {"workload": "config2 (22119 plane waves, 512 bands, 36^3 grid), 256 electrons, "
+                        "kT 0.01 Ha, 2 filter cycles (degree 10) per SCF iteration, Kerker "
+                        "mixing alpha 0.5, q0 0.8/bohr, tol 1e-4 Ha on max |V_out - V_in|, FP64",
+            **info, "final_dv": dv, "wall_s": round(wall, 3),
+            "s_per_iteration": round(wall / max(info["iterations"], 1), 4),
+            "potential_ms": round(pot_ms, 4), "electrons": float(rho.sum())}
 
 
 def ceilings():
@@ -526,6 +554,7 @@ def main():
         if not args.paw:
             out["paw"] = paw_leg(args.config, head["filter_ms_per_step"])
         out["solver_comparison"] = solver_comparison_leg()
+        out["scf"] = scf_leg()
     if args.cpu_bands > 0:
         out["cpu_baseline"] = cpu_baseline(s, degree, head["bounds"], args.cpu_bands)
     print(json.dumps(out), flush=True)

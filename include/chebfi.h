@@ -241,6 +241,9 @@ abi_status abi_lobpcg_solve(abi_system sys, void *X, int64_t nband, int64_t ld, 
 abi_status abi_update_potential(abi_system sys, const double *vloc, const void *dij,
                                 void *stream);
 
+/* Copies the handle's V_loc (FP64, n1*n2*n3, i1 fastest) to a device array. */
+abi_status abi_get_potential(abi_system sys, double *vloc, void *stream);
+
 /* Adjoint of abi_cheb_filter (handles with S = I; ABI_ERR_STATE otherwise)
  * for the loss L = sum_n Re<W_n, Y_n>, Y = the
  * filter output (reverse mode of the filter recurrence; the paper's solver is
@@ -277,6 +280,52 @@ abi_status abi_filter_backward(abi_system sys, const void *X, const void *W, int
  * overwritten (FP64 accumulation in a fixed band order). */
 abi_status abi_density(abi_system sys, const void *Psi, int64_t nband, int64_t ld, int32_t dtype,
                        const double *weights, double *rho, void *stream);
+
+/* As abi_density, but adds to rho instead of overwriting it: the density of
+ * several k-points (handles on the same FFT box) accumulated into one grid,
+ * each call with its own weights (occupation times k-point weight). */
+abi_status abi_density_add(abi_system sys, const void *Psi, int64_t nband, int64_t ld,
+                           int32_t dtype, const double *weights, double *rho, void *stream);
+
+/* ---- outer SCF step (Algorithm "Self-consistent field in DFT") ----------------
+ * The paper computes the occupations from the eigenvalues on the host and the
+ * density with FFTs on the GPU; the potential of the next iteration is the host
+ * code's part and is defined here as V = V_ion + V_H[n] + v_x[n] with
+ * n(r) = rho(r) n1 n2 n3 / Omega (rho the grid density of abi_density),
+ * V_H(G) = 4 pi n(G) / |G|^2 (V_H(0) = 0, G in the box window of the sphere),
+ * v_x = -(3 n / pi)^(1/3) (LDA exchange; 0 where n <= 0). */
+
+/* Host only.  Fermi-Dirac occupations f_i = occ_max / (1 + exp((eval_i - mu)/kT))
+ * of n states with mu found by bisection so that sum_i f_i = nelec (requires
+ * kT > 0 and 0 <= nelec <= occ_max n).  f: host array of n; mu may be NULL. */
+abi_status abi_occupations(int64_t n, const double *eval, double nelec, double kT, double occ_max,
+                           double *f, double *mu);
+
+/* vout = V_ion + V_H[n] + v_x[n] for the grid density rho (device arrays of
+ * n1*n2*n3 doubles, i1 fastest; vout may alias neither input).  FP64 FFTs of
+ * the whole box on the device.  Stream-ordered. */
+abi_status abi_scf_potential(abi_system sys, const double *rho, const double *vion, double *vout,
+                             void *stream);
+
+/* SCF iterations at the handle's potential V_in (its current V_loc): cycles_per_iter
+ * cycles of abi_chebfi_solve's loop on X (bounds from v0, degree-`degree` filter,
+ * Rayleigh-Ritz), occupations of the nband Ritz values (occ_max 2, temperature
+ * kT), the density, V_out = abi_scf_potential(rho, vion), then stop when
+ * max_r |V_out - V_in| <= tol, else V_loc <- V_in + K (V_out - V_in) and repeat,
+ * at most max_iter times.  K = alpha (linear mixing, q0 = 0) or, with q0 > 0,
+ * Kerker's preconditioner K(G) = alpha |G|^2 / (|G|^2 + q0^2) (alpha at G = 0),
+ * which damps the long-wavelength charge sloshing of large cells.  X, v0, dtype as for
+ * abi_chebfi_solve (X keeps the Ritz vectors); vion: device, n1*n2*n3 doubles.
+ * eval (host, nband): the last Ritz values.  rho_out (device, n1*n2*n3, or NULL):
+ * the last density.  dv_out (host, or NULL): the last max |V_out - V_in|.
+ * info (host, 4 entries, or NULL): iterations, converged (0/1), 0, 0.  On return
+ * the handle's V_loc is the last V_in (the converged potential when converged).
+ * Synchronises the stream. */
+abi_status abi_scf_solve(abi_system sys, void *X, int64_t nband, int64_t ld, int32_t dtype,
+                         const void *v0, const double *vion, double nelec, double kT,
+                         double alpha, double q0, int32_t degree, int32_t cycles_per_iter,
+                         int32_t max_iter, double tol, double *eval, double *rho_out,
+                         double *dv_out, int32_t *info, void *stream);
 
 /* ---- dense FP64 building blocks of the Rayleigh-Ritz step ---------------------
  * Column-major complex double matrices in device memory, leading dimension lda. */

@@ -48,4 +48,4 @@ from .overlap import (  # noqa: F401,E402
     sinv_h,
 )
 from .lobpcg import lobpcg_pass, tpa_precondition  # noqa: F401,E402
-from .scf import hartree, lda_exchange, occupations, scf_iteration, scf_potential  # noqa: F401,E402
+from .scf import hartree, lda_exchange, mix, occupations, scf_iteration, scf_potential  # noqa: F401,E402

@@ -18,8 +18,10 @@ Readings where the paper is silent:
   n(G) = n^-3 sum_r n(r) e^{-i G.r}, G = sum_d m_d b_d with the box window of
   the sphere (m_d in [-n_d/2, n_d/2 - 1] for even n_d), and the LDA
   (Slater) exchange v_x = -(3 n / pi)^(1/3) (n <= 0 gives 0);
-* linear mixing V_in <- V_in + alpha (V_out - V_in); converged when
-  max_r |V_out - V_in| <= tol.
+* mixing V_in <- V_in + K (V_out - V_in): K = alpha (linear mixing) or, with a
+  screening wave number q0 > 0, Kerker's preconditioner (Kerker, 1981)
+  K(G) = alpha |G|^2 / (|G|^2 + q0^2) for G != 0 and K(0) = alpha, applied on the
+  FFT box; converged when max_r |V_out - V_in| <= tol.
 """
 from __future__ import annotations
 
@@ -86,7 +88,19 @@ def scf_potential(rho, vion, lattice, ngrid) -> np.ndarray:
     return np.asarray(vion) + hartree(n_r, lattice, ngrid) + lda_exchange(n_r)
 
 
-def scf_iteration(H: Hamiltonian, Psi, vion, nelec, kT, alpha, solve):
+def mix(vin, vout, alpha, q0, lattice, ngrid) -> np.ndarray:
+    """V_in + K (V_out - V_in) with the linear (q0 = 0) or Kerker factor K(G)."""
+    d = np.asarray(vout, dtype=np.float64) - np.asarray(vin, dtype=np.float64)
+    if q0 <= 0.0:
+        return np.asarray(vin) + alpha * d
+    n1, n2, n3 = ngrid
+    dG = scipy.fft.fftn(d.reshape(n3, n2, n1))
+    g2 = g_squared(lattice, ngrid)
+    k = np.where(g2 > 0, alpha * g2 / (g2 + q0 * q0), alpha)
+    return np.asarray(vin) + np.real(scipy.fft.ifftn(k * dG)).reshape(-1)
+
+
+def scf_iteration(H: Hamiltonian, Psi, vion, nelec, kT, alpha, solve, q0=0.0):
     """One SCF iteration at the potential H.vloc: (Psi, eval, rho, V_out, V_next, dv).
 
     `solve(H, Psi) -> (eval, Psi)` runs the eigensolver at fixed potential."""
@@ -95,5 +109,5 @@ def scf_iteration(H: Hamiltonian, Psi, vion, nelec, kT, alpha, solve):
     rho = density(H, Psi, f)
     vout = scf_potential(rho, vion, H.lattice, H.ngrid)
     dv = float(np.abs(vout - H.vloc).max())
-    vnext = H.vloc + alpha * (vout - H.vloc)
+    vnext = mix(H.vloc, vout, alpha, q0, H.lattice, H.ngrid)
     return Psi, ev, rho, vout, vnext, dv

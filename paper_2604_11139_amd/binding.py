@@ -39,7 +39,8 @@ EXPORTS = [
     "abi_filter_backward", "abi_density", "abi_last_error", "abi_set_system_batch",
     "abi_batch_system", "abi_cheb_filter_batch", "abi_batch_autotune", "abi_batch_use_graph",
     "abi_destroy_batch", "abi_chebfi_solve", "abi_apply_S", "abi_apply_Sinv", "abi_overlap_info",
-    "abi_lobpcg_solve",
+    "abi_lobpcg_solve", "abi_density_add", "abi_occupations", "abi_scf_potential", "abi_scf_solve",
+    "abi_get_potential",
 ]
 
 PROFILE_CLASSES = ["proj_gemm", "expand_gemm", "fft_a", "fft_b", "fft_c", "dapply", "gram",
@@ -116,6 +117,12 @@ def lib():
         "abi_overlap_info": [vp, POINTER(c_int32), POINTER(c_double)],
         "abi_lobpcg_solve": [vp, vp, c_int64, c_int64, c_int32, c_int32, c_int32, c_int32,
                              c_int32, c_double, vp, vp, vp, vp],
+        "abi_density_add": [vp, vp, c_int64, c_int64, c_int32, vp, vp, vp],
+        "abi_occupations": [c_int64, vp, c_double, c_double, c_double, vp, vp],
+        "abi_scf_potential": [vp, vp, vp, vp, vp],
+        "abi_get_potential": [vp, vp, vp],
+        "abi_scf_solve": [vp, vp, c_int64, c_int64, c_int32, vp, vp, c_double, c_double, c_double,
+                          c_double, c_int32, c_int32, c_int32, c_double, vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -386,6 +393,58 @@ class System:
                                  _stream()))
         return rho
 
+    def density_add(self, Psi, rho, weights=None):
+        """rho += sum_n w_n |psi~_n(r)|^2 / n^3 (rho: float64 CUDA tensor of n1*n2*n3)."""
+        import torch
+        pp, nb, ld, code = _block(Psi, self.npw)
+        pw = c_void_p(0)
+        w = None
+        if weights is not None:
+            w = torch.as_tensor(weights, dtype=torch.float64, device=Psi.device).contiguous()
+            pw = c_void_p(w.data_ptr())
+        _check(lib().abi_density_add(self._h, pp, nb, ld, code, pw, c_void_p(rho.data_ptr()),
+                                     _stream()))
+        return rho
+
+    def potential(self):
+        """The handle's V_loc (float64 CUDA tensor, n1*n2*n3, i1 fastest)."""
+        import torch
+        v = torch.empty(self.ngrid[0] * self.ngrid[1] * self.ngrid[2], dtype=torch.float64,
+                        device="cuda")
+        _check(lib().abi_get_potential(self._h, c_void_p(v.data_ptr()), _stream()))
+        return v
+
+    def scf_potential(self, rho, vion):
+        """V_ion + V_H[rho] + v_x[rho] on the grid (float64 CUDA tensors)."""
+        import torch
+        rho = rho.contiguous()
+        vion = vion.contiguous()
+        vout = torch.empty_like(rho)
+        _check(lib().abi_scf_potential(self._h, c_void_p(rho.data_ptr()),
+                                       c_void_p(vion.data_ptr()), c_void_p(vout.data_ptr()),
+                                       _stream()))
+        return vout
+
+    def scf(self, X, v0, vion, nelec, kT, alpha, degree, cycles_per_iter, max_iter, tol, q0=0.0):
+        """SCF iterations in place on X and on the handle's V_loc.  Returns
+        (eval, rho, dv, info dict)."""
+        import torch
+        px, nb, ld, code = _block(X, self.npw)
+        pv, _, _, _ = _block(v0.reshape(1, -1) if v0.dim() == 1 else v0, self.npw)
+        vion = vion.contiguous()
+        rho = torch.empty(self.ngrid[0] * self.ngrid[1] * self.ngrid[2], dtype=torch.float64,
+                          device=X.device)
+        ev = np.zeros(nb)
+        dv = c_double(0.0)
+        info = np.zeros(4, dtype=np.int32)
+        _check(lib().abi_scf_solve(self._h, px, nb, ld, code, pv, c_void_p(vion.data_ptr()),
+                                   float(nelec), float(kT), float(alpha), float(q0), int(degree),
+                                   int(cycles_per_iter), int(max_iter), float(tol),
+                                   ev.ctypes.data_as(c_void_p), c_void_p(rho.data_ptr()),
+                                   ctypes.byref(dv), info.ctypes.data_as(c_void_p), _stream()))
+        return ev, rho, float(dv.value), {"iterations": int(info[0]),
+                                          "converged": bool(info[1])}
+
     def solve(self, X, v0, degree, max_cycles, nconv, tol, refine_degree=0):
         """In place: X <- Ritz vectors after cycles of bounds, filter and
         Rayleigh-Ritz until the lowest nconv residuals are <= tol.  Returns
@@ -455,6 +514,16 @@ class System:
         if want_coef:
             return ev, rn, fl.value, coef.t()  # stored column-major
         return ev, rn, fl.value
+
+
+def occupations(eval, nelec, kT, occ_max=2.0):
+    """(f, mu): Fermi-Dirac occupations with sum f = nelec (host computation)."""
+    e = np.ascontiguousarray(np.asarray(eval, dtype=np.float64))
+    f = np.zeros_like(e)
+    mu = c_double(0.0)
+    _check(lib().abi_occupations(e.size, e.ctypes.data_as(c_void_p), float(nelec), float(kT),
+                                 float(occ_max), f.ctypes.data_as(c_void_p), ctypes.byref(mu)))
+    return f, float(mu.value)
 
 
 # -- dense building blocks (matrices as torch (m, m) tensors, math layout) ------

@@ -1164,6 +1164,12 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
     s->natom = desc->natom;
     s->nproj = 4 * desc->natom;
     s->precision = desc->precision;
+    for (int i = 0; i < 9; ++i) s->lattice[i] = desc->lattice[i];
+    {
+      const double *a = desc->lattice;
+      s->omega = std::fabs(a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                           a[2] * (a[3] * a[7] - a[4] * a[6]));
+    }
     std::string err;
     abi_status st = build_sphere(desc, &s->sphere, &err);
     if (st != ABI_OK) throw Error{st, err};
@@ -1650,6 +1656,15 @@ abi_status abi_lobpcg_solve(abi_system s, void *X, int64_t nband, int64_t ld, in
   });
 }
 
+abi_status abi_get_potential(abi_system s, double *vloc, void *stream) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(s != nullptr && vloc != nullptr, ABI_ERR_ARG, "NULL argument");
+    const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
+    CHEBFI_HIP(hipMemcpyAsync(vloc, s->d_V, sizeof(double) * nbox, hipMemcpyDeviceToDevice,
+                              S(stream)));
+  });
+}
+
 abi_status abi_update_potential(abi_system s, const double *vloc, const void *dij, void *stream) {
   return guarded([&] {
     CHEBFI_REQUIRE(s != nullptr, ABI_ERR_ARG, "system handle is NULL");
@@ -1882,6 +1897,132 @@ abi_status abi_density(abi_system s, const void *Psi, int64_t nband, int64_t ld,
         launch_density<float>(s, Psi, ld, (int)b0, nb, box, weights, rho, st);
       else
         launch_density<double>(s, Psi, ld, (int)b0, nb, box, weights, rho, st);
+    }
+  });
+}
+
+abi_status abi_density_add(abi_system s, const void *Psi, int64_t nband, int64_t ld,
+                           int32_t dtype, const double *weights, double *rho, void *stream) {
+  return guarded([&] {
+    check_block(s, Psi, nband, ld, dtype);
+    CHEBFI_REQUIRE(rho != nullptr, ABI_ERR_ARG, "rho is NULL");
+    hipStream_t st = S(stream);
+    const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
+    const size_t es = elem_bytes(dtype);
+    const int fb = (int)std::min<int64_t>(s->fft_batch * (dtype == ABI_C64 ? 2 : 1), nband);
+    void *box = s->box.get(es * (size_t)nbox * fb);
+    for (int64_t b0 = 0; b0 < nband; b0 += fb) {
+      const int nb = (int)std::min<int64_t>(fb, nband - b0);
+      if (dtype == ABI_C64)
+        launch_density<float>(s, Psi, ld, (int)b0, nb, box, weights, rho, st);
+      else
+        launch_density<double>(s, Psi, ld, (int)b0, nb, box, weights, rho, st);
+    }
+  });
+}
+
+abi_status abi_occupations(int64_t n, const double *eval, double nelec, double kT, double occ_max,
+                           double *f, double *mu) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(n >= 1 && eval != nullptr && f != nullptr, ABI_ERR_ARG, "NULL argument");
+    CHEBFI_REQUIRE(kT > 0.0 && occ_max > 0.0, ABI_ERR_ARG, "kT and occ_max must be > 0");
+    CHEBFI_REQUIRE(nelec >= 0.0 && nelec <= occ_max * (double)n, ABI_ERR_ARG,
+                   "nelec must be in [0, occ_max n]");
+    double emin = eval[0], emax = eval[0];
+    for (int64_t i = 0; i < n; ++i) {
+      CHEBFI_REQUIRE(std::isfinite(eval[i]), ABI_ERR_ARG, "eigenvalues must be finite");
+      emin = std::min(emin, eval[i]);
+      emax = std::max(emax, eval[i]);
+    }
+    auto occ = [&](double e, double m) {
+      const double x = std::max(-700.0, std::min(700.0, (e - m) / kT));
+      return occ_max / (1.0 + std::exp(x));
+    };
+    auto total = [&](double m) {
+      double t = 0.0;
+      for (int64_t i = 0; i < n; ++i) t += occ(eval[i], m);
+      return t;
+    };
+    double lo = emin - 50.0 * kT - 1.0, hi = emax + 50.0 * kT + 1.0;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (total(mid) < nelec)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const double m = 0.5 * (lo + hi);
+    for (int64_t i = 0; i < n; ++i) f[i] = occ(eval[i], m);
+    if (mu) *mu = m;
+  });
+}
+
+abi_status abi_scf_potential(abi_system s, const double *rho, const double *vion, double *vout,
+                             void *stream) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(s != nullptr && rho && vion && vout, ABI_ERR_ARG, "NULL argument");
+    const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
+    void *box = s->scf_box.get(sizeof(double2) * (size_t)nbox);
+    launch_scf_potential(s, rho, vion, vout, box, S(stream));
+  });
+}
+
+abi_status abi_scf_solve(abi_system s, void *X, int64_t nband, int64_t ld, int32_t dtype,
+                         const void *v0, const double *vion, double nelec, double kT,
+                         double alpha, double q0, int32_t degree, int32_t cycles_per_iter,
+                         int32_t max_iter, double tol, double *eval, double *rho_out,
+                         double *dv_out, int32_t *info, void *stream) {
+  return guarded([&] {
+    check_block(s, X, nband, ld, dtype);
+    CHEBFI_REQUIRE(v0 && vion && eval, ABI_ERR_ARG, "v0, vion or eval is NULL");
+    CHEBFI_REQUIRE(alpha > 0.0 && alpha <= 1.0, ABI_ERR_ARG, "alpha must be in (0, 1]");
+    CHEBFI_REQUIRE(q0 >= 0.0 && std::isfinite(q0), ABI_ERR_ARG, "q0 must be >= 0");
+    CHEBFI_REQUIRE(degree >= 1 && cycles_per_iter >= 1 && max_iter >= 1, ABI_ERR_ARG,
+                   "degree, cycles_per_iter and max_iter must be >= 1");
+    CHEBFI_REQUIRE(tol > 0.0 && std::isfinite(tol), ABI_ERR_ARG, "tol must be positive");
+    auto call = [](abi_status rc) {
+      if (rc != ABI_OK) throw Error{rc, g_last_error};
+    };
+    hipStream_t st = S(stream);
+    const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
+    double *rho = (double *)s->scf_rho.get(sizeof(double) * (size_t)nbox);
+    double *vbuf = (double *)s->scf_v.get(sizeof(double) * (size_t)(2 * nbox + 8));
+    double *vout = vbuf, *vnext = vbuf + nbox, *dv_dev = vbuf + 2 * nbox;
+    double *w_dev = (double *)s->scf_w.get(sizeof(double) * (size_t)nband);
+    std::vector<double> f((size_t)nband);
+    int iters = 0, converged = 0;
+    double dv = HUGE_VAL;
+    while (iters < max_iter) {
+      // solve at the current potential: cycles_per_iter cycles of bounds, filter, RR
+      call(abi_chebfi_solve(s, X, nband, ld, dtype, v0, degree, cycles_per_iter, (int32_t)nband,
+                            1e-300, 0, eval, nullptr, nullptr, stream));
+      call(abi_occupations(nband, eval, nelec, kT, 2.0, f.data(), nullptr));
+      CHEBFI_HIP(hipMemcpyAsync(w_dev, f.data(), sizeof(double) * (size_t)nband,
+                                hipMemcpyHostToDevice, st));
+      call(abi_density(s, X, nband, ld, dtype, w_dev, rho, stream));
+      call(abi_scf_potential(s, rho, vion, vout, stream));
+      launch_mix(s, s->d_V, vout, alpha, q0, vnext, dv_dev,
+                 s->scf_box.get(sizeof(double2) * (size_t)nbox), st);
+      CHEBFI_HIP(hipMemcpyAsync(&dv, dv_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+      CHEBFI_HIP(hipStreamSynchronize(st));
+      ++iters;
+      if (dv <= tol) {
+        converged = 1;
+        break;
+      }
+      call(abi_update_potential(s, vnext, nullptr, stream));
+    }
+    if (rho_out)
+      CHEBFI_HIP(hipMemcpyAsync(rho_out, rho, sizeof(double) * (size_t)nbox,
+                                hipMemcpyDeviceToDevice, st));
+    CHEBFI_HIP(hipStreamSynchronize(st));
+    if (dv_out) *dv_out = dv;
+    if (info) {
+      info[0] = iters;
+      info[1] = converged;
+      info[2] = 0;
+      info[3] = 0;
     }
   });
 }

@@ -174,6 +174,8 @@ struct abi_system_s {
   int64_t npw = 0;
   int natom = 0, nproj = 0;
   int precision = ABI_PREC_FP64;
+  double lattice[9] = {0};  // rows a1, a2, a3 (bohr)
+  double omega = 0.0;       // cell volume (bohr^3)
   chebfi::Sphere sphere;
   chebfi::BoxPlan plan;
 
@@ -209,6 +211,7 @@ struct abi_system_s {
   chebfi::DevBuf gen_c, gen_e, gen_f, gen_ff, blk5, blk6;  // overlap path
   chebfi::DevBuf lob_z, lob_hz, lob_sz, lob_t1, lob_t2, lob_t3, lob_psi, lob_hp, lob_sp, lob_c,
       lob_g, lob_v;  // block LOBPCG
+  chebfi::DevBuf scf_rho, scf_v, scf_box, scf_w;  // SCF step
 
   int fft_batch = 0;  // bands per FFT batch (box buffer holds this many boxes)
   // second stream: the FFT passes of an H application run on it beside the

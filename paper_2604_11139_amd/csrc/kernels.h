@@ -188,6 +188,18 @@ size_t zheev_work_bytes(int64_t m);
 // (at most 4 butterflies per thread; a multiple of 64).
 int fft_stage_threads(const Plan1D &pl, int npen);
 
+// ---- scf.hip --------------------------------------------------------------------
+// vout = vion + V_H + v_x of the grid density rho (sum_r rho = N_el): density per
+// volume n = rho n1 n2 n3 / Omega, V_H(G) = 4 pi n(G) / |G|^2 by FFTs of the whole
+// box (box: n1 n2 n3 complex doubles of work space), v_x = -(3 n / pi)^(1/3).
+void launch_scf_potential(const abi_system_s *s, const double *rho, const double *vion,
+                          double *vout, void *box, hipStream_t st);
+// vnext = vin + K (vout - vin) with K = alpha (q0 <= 0) or Kerker's
+// alpha |G|^2 / (|G|^2 + q0^2) (alpha at G = 0) applied through box FFTs (box:
+// n1 n2 n3 complex doubles of work space); *dv = max |vout - vin| (device scalar).
+void launch_mix(const abi_system_s *s, const double *vin, const double *vout, double alpha,
+                double q0, double *vnext, double *dv, void *box, hipStream_t st);
+
 // ---- batch.hip ------------------------------------------------------------------
 // One filter step (index j of the step table) of every system of a batch:
 // projection + D, FFT passes A, B, C (with expansion and recurrence).

@@ -63,3 +63,18 @@ def test_grid_errors():
     with pytest.raises(B.ChebfiError) as e:
         B.gsphere_host(s)
     assert e.value.code == B.ABI_ERR_GRID
+
+
+def test_occupations_host_call():
+    """Fermi-Dirac occupations are a host computation: library vs oracle."""
+    import oracle as O
+    from paper_2604_11139_amd import binding as B
+    rng = np.random.default_rng(8)
+    e = np.sort(rng.uniform(-1.0, 1.0, 37))
+    for nelec, kT in ((10.0, 0.01), (7.3, 0.2), (0.0, 0.05), (74.0, 0.05)):
+        f, mu = B.occupations(e, nelec, kT)
+        fo, muo = O.occupations(e, nelec, kT)
+        assert abs(f.sum() - nelec) <= 1e-10
+        assert np.abs(f - fo).max() <= 1e-10
+    with pytest.raises(B.ChebfiError):
+        B.occupations(e, 75.0, 0.01)

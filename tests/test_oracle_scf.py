@@ -9,6 +9,8 @@
 * LDA exchange: v_x(pi/3) = -1, v_x(8 pi/3) = -2, zero for n <= 0;
 * normalisation: a grid density with sum_r rho = N is N / Omega per volume, and
   the potential of a modulated density is V_ion + the closed-form V_H + v_x;
+* Kerker mixing: q0 = 0 is linear mixing; a plane-wave potential residual is
+  scaled by alpha G0^2/(G0^2 + q0^2), a constant one by alpha;
 * the loop's fixed point: iterated on a tiny cell until max |V_out - V_in| is
   below 1e-7, the eigenvalues equal those of the dense H at that potential and
   the potential reproduces itself.
@@ -17,7 +19,8 @@ import numpy as np
 
 import oracle as O
 import workloads as W
-from oracle.scf import g_squared, hartree, lda_exchange, occupations, scf_iteration, scf_potential
+from oracle.scf import (g_squared, hartree, lda_exchange, mix, occupations, scf_iteration,
+                        scf_potential)
 
 
 def test_occupations():
@@ -92,3 +95,20 @@ def test_fixed_point_of_the_loop():
     assert dv < 1e-7
     assert np.abs(ev - np.linalg.eigvalsh(H.dense())[:8]).max() < 1e-12
     assert np.abs(scf_potential(rho, vion, H.lattice, H.ngrid) - H.vloc).max() < 1e-7
+
+
+def test_kerker_mixing():
+    lat = np.array([[6.0, 0.0, 0.0], [1.0, 7.0, 0.0], [0.0, 0.5, 8.0]])
+    ngrid = (10, 12, 15)
+    n1, n2, n3 = ngrid
+    i3, i2, i1 = np.meshgrid(np.arange(n3), np.arange(n2), np.arange(n1), indexing="ij")
+    r = np.stack([i1 / n1, i2 / n2, i3 / n3], axis=-1) @ lat
+    G0 = np.array([2, 1, -1]) @ O.reciprocal_vectors(lat)
+    vin = np.linspace(-1, 1, n1 * n2 * n3)
+    d = (0.3 + 0.7 * np.cos(r @ G0)).reshape(-1)
+    alpha, q0 = 0.4, 1.3
+    got = mix(vin, vin + d, alpha, q0, lat, ngrid)
+    g2 = G0 @ G0
+    ref = vin + alpha * 0.3 + alpha * g2 / (g2 + q0 ** 2) * 0.7 * np.cos(r @ G0).reshape(-1)
+    assert np.abs(got - ref).max() < 1e-13
+    assert np.abs(mix(vin, vin + d, alpha, 0.0, lat, ngrid) - (vin + alpha * d)).max() < 1e-15
