@@ -1249,7 +1249,7 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
     CHEBFI_HIP(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
     CHEBFI_HIP(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
     CHEBFI_HIP(hipEventCreateWithFlags(&s->ev_half, hipEventDisableTiming));
-    s->overlap = 1;
+    s->overlap = 0;
     if (const char *e = std::getenv("CHEBFI_OVERLAP")) s->overlap = std::atoi(e) != 0;
     if (desc->abi_version >= 2 && desc->qij != nullptr) setup_overlap(s, desc->qij, S(stream));
     CHEBFI_HIP(hipStreamSynchronize(S(stream)));

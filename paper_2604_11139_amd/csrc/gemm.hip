@@ -215,14 +215,49 @@ void launch_t(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda, const
 
 }  // namespace
 
+// Compute units of the current device (cached per device).
+static int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        v <= 0)
+      v = 256;
+    cus[dev] = v;
+  }
+  return cus[dev];
+}
+
+// Split-K count for `tiles` output tiles when `per_cu` workgroups fit on a CU:
+// the launch runs in ceil(tiles * s / slots) rounds of slots = CUs x per_cu
+// workgroups, each 1/s of the K range long, so s minimises ceil(tiles s / slots) / s
+// (the tail round of a launch that does not fill the chip costs a whole round),
+// with at least 4 workgroups per slot-round in total and at most kmax chunks.
+static int best_splits(int64_t tiles, int64_t kmax, int per_cu) {
+  const int64_t slots = (int64_t)device_cus() * per_cu;
+  if (kmax < 1) kmax = 1;
+  const int64_t smax = std::min<int64_t>(64, kmax);
+  int64_t best = 1;
+  double best_cost = 1e300;
+  for (int64_t sp = 1; sp <= smax; ++sp) {
+    const int64_t wgs = tiles * sp;
+    const double cost = (double)((wgs + slots - 1) / slots) / (double)sp;
+    // prefer fewer chunks unless a larger count is clearly better (fewer partials)
+    if (cost < best_cost * (1.0 - 1e-9)) {
+      best_cost = cost;
+      best = sp;
+    }
+    if (wgs >= 8 * slots) break;
+  }
+  return (int)best;
+}
+
 int zgemm_splits(int64_t m, int64_t n, int64_t k) {
   const int64_t tiles = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
-  int64_t s = (1024 + tiles - 1) / tiles;
-  const int64_t kmax = (k + 511) / 512;  // keep at least ~512 K per chunk
-  if (s > kmax) s = kmax;
-  if (s > 64) s = 64;
-  if (s < 1) s = 1;
-  return (int)s;
+  // keep at least ~512 K per chunk; two 256-thread workgroups per CU (66 KB LDS each)
+  return best_splits(tiles, (k + 511) / 512, 2);
 }
 
 void zgemm(Op opa, Op opb, int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
@@ -1003,15 +1038,12 @@ static int pl_bm(int variant) { return (variant == 2 || variant == 3) ? 64 : 128
 static int pl_bn(int variant) { return (variant == 2 || variant == 6) ? 64 : 128; }
 
 int proj_planes_splits(int variant, int64_t nproj, int64_t nband, int64_t npw) {
-  // about four workgroups per CU, at least 1024 plane waves per chunk
+  // at least 1024 plane waves per chunk; the double-buffered 128 x 128 tiles hold
+  // 128 KB of LDS (one workgroup per CU), the single-stage ones two per CU
   const int64_t tiles = ((nproj + pl_bm(variant) - 1) / pl_bm(variant)) *
                         ((nband + pl_bn(variant) - 1) / pl_bn(variant));
-  int64_t sp = (1024 + tiles - 1) / tiles;
-  const int64_t kmax = (npw + 1023) / 1024;
-  if (sp > kmax) sp = kmax;
-  if (sp > 64) sp = 64;
-  if (sp < 1) sp = 1;
-  return (int)sp;
+  const int per_cu = (variant == 4 || variant == 5) ? 1 : 2;
+  return best_splits(tiles, (npw + 1023) / 1024, per_cu);
 }
 
 void proj_gemm_planes(int64_t nproj, int64_t nband, int64_t npw, const void *Apl, int64_t lda,

@@ -214,10 +214,12 @@ struct abi_system_s {
   chebfi::DevBuf scf_rho, scf_v, scf_box, scf_w;  // SCF step
 
   int fft_batch = 0;  // bands per FFT batch (box buffer holds this many boxes)
-  // second stream: the FFT passes of an H application run on it beside the
-  // projection GEMM (they are independent until the expansion)
+  // second stream: with overlap = 1 (CHEBFI_OVERLAP=1) the FFT passes of an H
+  // application run on it beside the projection GEMM (they are independent until
+  // the expansion).  Off by default: the GEMM workgroups hold 128 KB of LDS, so an
+  // FFT workgroup cannot share a CU with one and the two only time-slice the chip.
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_half = nullptr;
-  int overlap = 1;
+  int overlap = 0;
   chebfi::Profiler prof;
 };
