@@ -58,7 +58,7 @@ def parse():
 # kernel class -> (kernel name in the counter summary, source file it is built from)
 CLASS_KERNELS = {
     "proj_gemm": ("zgemm_pl2_kernel<128, 128, 2, 4, true, true, 1, true>", "gemm.hip"),
-    "expand_gemm": ("zgemm_pl2_kernel<128, 128, 2, 4, false, false, 1, false>", "gemm.hip"),
+    "expand_gemm": ("zgemm_pl2_kernel<128, 64, 2, 2, false, false, 0, false>", "gemm.hip"),
     "fft_a": ("cpass_a_kernel<float, 64>", "fft.hip"),
     "fft_b": ("cpass_b_kernel<float, float, 64>", "fft.hip"),
     "fft_c": ("cpass_c_kernel<float, 64>", "fft.hip"),

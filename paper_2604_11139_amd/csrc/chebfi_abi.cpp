@@ -1236,7 +1236,10 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
       // block split while staged
       if (const char *e = std::getenv("CHEBFI_MIXED_GEMM")) s->mixed_gemm = std::atoi(e);
       // tile variants of the split-BF16 products (tuning knobs, 0..6)
-      s->pl_proj = s->pl_expand = 4;
+      // projection: the double-buffered 128 x 128 tile with the block split while
+      // staged; expansion: the single-stage 128 x 64 tile, two workgroups per CU
+      s->pl_proj = 4;
+      s->pl_expand = 6;
       if (const char *e = std::getenv("CHEBFI_PL_PROJ")) s->pl_proj = std::min(6, std::max(0, std::atoi(e)));
       if (const char *e = std::getenv("CHEBFI_PL_EXPAND")) s->pl_expand = std::min(6, std::max(0, std::atoi(e)));
     }
