@@ -17,7 +17,9 @@ of R Q R^H), on the PAW-like variants of the small systems:
 * full size (115313 plane waves, 2048 bands, degree 12, 864 projectors):
   sampled filter columns against the oracle (column-independent filter);
 * errors: an S that is not positive definite, the adjoint and the batched
-  filter with S != I are refused.
+  filter with S != I are refused;
+* one band (matrix-vector products) and a ragged band count; the band halves
+  pipelined on two streams give the one-stream result bit for bit.
 """
 import functools
 
@@ -235,3 +237,41 @@ def test_fullsize_filter_sampled_columns():
     Xs = _r64(X[:, COLS])
     ref = O.cheb_filter(O.sinv_h(H, S), Xs, s.degree, *bounds)
     assert col_rel_err(got, ref) <= 5e-6 * s.degree
+
+
+@pytest.mark.parametrize("nband", [1, 37])
+def test_filter_single_and_ragged(nband):
+    """One band (the matrix-vector products) and a ragged band count."""
+    H, S = oracle_pair("n27")
+    s = paw("n27")
+    X = W.random_block(H.npw, nband, 61)
+    v0 = W.random_vector(H.npw, 61)
+    a, b, a0 = O.filter_bounds_gen(H, S, X, v0)
+    ref = O.cheb_filter(O.sinv_h(H, S), X, 5, a, b, a0)
+    with B.System(s) as g:
+        got = to_host(g.cheb_filter(to_dev(X), 5, a, b, a0))
+        gs = to_host(g.apply_Sinv(to_dev(X)))
+    assert col_rel_err(got, ref) <= 1e-9
+    assert col_rel_err(gs, S.inv_apply(X)) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_two_stream_halves_match_one_stream(precision, monkeypatch):
+    """The pipelined band halves on two streams (130 bands: halves of 96 and 34) give the
+    one-stream result bit for bit."""
+    import torch
+    H, S = oracle_pair("n27")
+    s = paw("n27")
+    X = W.random_block(H.npw, 130, 62)
+    if precision == "mixed":
+        X = _r64(X)
+    prec = B.ABI_PREC_MIXED if precision == "mixed" else B.ABI_PREC_FP64
+    outs = []
+    for ov in ("0", "1"):
+        monkeypatch.setenv("CHEBFI_OVERLAP", ov)
+        with B.System(s, precision=prec) as g:
+            Xd = to_dev(X)
+            if precision == "mixed":
+                Xd = Xd.to(torch.complex64)
+            outs.append(to_host(g.cheb_filter(Xd, 4, 1.0, 9.0, -0.5)))
+    assert np.array_equal(outs[0], outs[1])

@@ -7,6 +7,8 @@
   Kerker (q0 = 1) mixing 0.3, 8 electrons, kT = 0.01) from the same block and v0 as the
   oracle's iterations: Ritz values <= 1e-8 Ha, density <= 1e-8 relative,
   potential <= 1e-8;
+* complex64 blocks on a mixed handle follow the FP64 loop (1e-6 Ha after four
+  iterations);
 * iterated to max |V_out - V_in| <= 1e-7: the potential reproduces itself under
   the oracle's potential map and the Ritz values are the dense H's at that
   potential (1e-8 Ha).
@@ -114,3 +116,25 @@ def test_scf_fixed_point():
     H.vloc = v
     lam = np.linalg.eigvalsh(H.dense())
     assert np.abs(ev[:8] - lam[:8]).max() <= 1e-8
+
+
+def test_scf_mixed_blocks_follow_fp64():
+    """The SCF loop on complex64 blocks (mixed handle): after four iterations the Ritz
+    values are within the mixed filter's accuracy of the FP64 loop's (1e-6 Ha)."""
+    import torch
+    s = W.make_system(1)
+    H = O.Hamiltonian.from_system(s)
+    vion = s.vloc.copy()
+    X = W.random_block(H.npw, s.nband, s.tag)
+    v0 = W.random_vector(H.npw, s.tag)
+    res = {}
+    for name, prec in (("fp64", B.ABI_PREC_FP64), ("mixed", B.ABI_PREC_MIXED)):
+        with B.System(s, precision=prec) as g:
+            Xd = to_dev(X)
+            if name == "mixed":
+                Xd = Xd.to(torch.complex64)
+            ev, rho, dv, info = g.scf(Xd, to_dev(v0), _t(vion), 8.0, 0.01, 0.3, 8, 3, 4, 1e-12,
+                                      q0=1.0)
+            res[name] = (ev, rho.cpu().numpy())
+    assert np.abs(res["mixed"][0][:8] - res["fp64"][0][:8]).max() <= 1e-6
+    assert np.abs(res["mixed"][1] - res["fp64"][1]).max() <= 1e-5 * np.abs(res["fp64"][1]).max()
