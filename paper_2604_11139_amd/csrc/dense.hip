@@ -29,6 +29,9 @@ namespace {
 
 constexpr int NB = 32;           // Cholesky / trtri block size
 constexpr int kEigMaxM = 2560;   // LDS-resident inverse iteration limit
+constexpr int kBtBlock = 64;     // reflectors per block of the back-transformation
+constexpr int kBtMinM = 96;      // smaller problems apply the reflectors one at a time
+constexpr int kBtSplits = 8;     // most K chunks of the V^H Z product
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -535,6 +538,39 @@ __global__ __launch_bounds__(256) void load_u_kernel(int64_t m, const double2 *_
   u[i] = (i == j + 1) ? double2{1.0, 0.0} : A[i + j * lda];
 }
 
+// V (Lr x nb, ld Lr) of the reflectors j0 .. j0+nb-1 on rows j0+1 .. m-1:
+// V[i, k] = 0 above row j0+k+1, 1 on it, A[r, j0+k] below (r = j0 + 1 + i).
+__global__ __launch_bounds__(256) void build_v_kernel(int64_t m, const double2 *__restrict__ A,
+                                                      int64_t lda, int64_t j0, int nb,
+                                                      double2 *__restrict__ V) {
+  const int64_t Lr = m - j0 - 1;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= Lr * nb) return;
+  const int64_t i = idx % Lr, k = idx / Lr;
+  const int64_t r = j0 + 1 + i, top = j0 + k + 1;
+  V[idx] = r < top ? double2{0.0, 0.0} : (r == top ? double2{1.0, 0.0} : A[r + (j0 + k) * lda]);
+}
+
+// Upper triangular T with H_{j0} H_{j0+1} ... H_{j0+nb-1} = I - V T V^H (forward
+// accumulation of the block reflector), from G = V^H V: T[k][k] = tau_k and
+// T[i][k] = -tau_k sum_{l=i}^{k-1} T[i][l] G[l][k].  Thread i owns row i.
+__global__ void larft_kernel(int nb, const double2 *__restrict__ G, const double2 *__restrict__ tau,
+                             double2 *__restrict__ T) {
+  const int i = threadIdx.x;
+  if (i >= nb) return;
+  for (int k = 0; k < nb; ++k) T[i + k * nb] = double2{0.0, 0.0};
+  for (int k = i; k < nb; ++k) {
+    if (k == i) {
+      T[i + k * nb] = tau[k];
+      continue;
+    }
+    double2 acc{0.0, 0.0};
+    for (int l = i; l < k; ++l) acc = cadd(acc, cmul(T[i + l * nb], G[l + k * nb]));
+    const double2 t = cmul(tau[k], acc);
+    T[i + k * nb] = double2{-t.x, -t.y};
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- drivers ----
@@ -581,11 +617,13 @@ void ztrtri_upper(int64_t m, void *Av, int64_t lda, void *work, hipStream_t st) 
 }
 
 size_t zheev_work_bytes(int64_t m) {
-  // d, e, e2, w-tmp, stats, tau, u, wv, wrow, hemv parts, S (real m x m)
-  const size_t ks = 64;
+  // d, e, e2, w-tmp, stats, tau, u, wv, wrow, hemv parts, S (real m x m), and the
+  // blocked back-transformation's V (m x nb), G, T (nb x nb), W1, W2 (nb x m)
+  const size_t ks = 64, nb = kBtBlock;
   return sizeof(double) * (size_t)(4 * m + 8) + sizeof(double2) * (size_t)(4 * m) +
          sizeof(double2) * ks * (size_t)m + sizeof(double) * (size_t)m * m +
-         16 * 256;  // each of the 11 sub-buffers is rounded up to 256 bytes
+         sizeof(double2) * ((3 + kBtSplits) * nb * (size_t)m + 2 * nb * nb) +
+         24 * 256;  // each of the 16 sub-buffers is rounded up to 256 bytes
 }
 
 void zheev(int64_t m, void *Av, int64_t lda, double *wout, void *Zv, int64_t ldz, void *work,
@@ -646,13 +684,42 @@ void zheev(int64_t m, void *Av, int64_t lda, double *wout, void *Zv, int64_t ldz
   CHEBFI_HIP(hipGetLastError());
   hipLaunchKernelGGL(real_to_complex_kernel, dim3(nblk(m * m, 256)), dim3(256), 0, st, m, S, m, Z,
                      ldz);
-  // back-transformation Z = H_0 H_1 ... H_{m-2} S
-  for (int64_t j = m - 2; j >= 0; --j) {
-    const int64_t L = m - j - 1;
-    hipLaunchKernelGGL(load_u_kernel, dim3(nblk(L, 256)), dim3(256), 0, st, m, A, lda, j, u);
-    hipLaunchKernelGGL(bt_dot_kernel, dim3((unsigned)m), dim3(256), 0, st, m, j, u, Z, ldz, wrow);
-    hipLaunchKernelGGL(bt_update_kernel, dim3(nblk(L, 256), (unsigned)m), dim3(256), 0, st, m, j,
-                       tau, u, wrow, Z, ldz);
+  // back-transformation Z = H_0 H_1 ... H_{m-2} S, in blocks of kBtBlock reflectors
+  // from the last: Z <- (I - V T V^H) Z = Z - V (T (V^H Z)) on rows j0+1 .. m-1
+  const int64_t nref = m - 1;
+  const int64_t nb0 = std::min<int64_t>(kBtBlock, std::max<int64_t>(nref, 1));
+  if (m >= kBtMinM) {
+    double2 *V = (double2 *)take(sizeof(double2) * (size_t)m * nb0);
+    double2 *G = (double2 *)take(sizeof(double2) * (size_t)nb0 * nb0);
+    double2 *T = (double2 *)take(sizeof(double2) * (size_t)nb0 * nb0);
+    double2 *W1 = (double2 *)take(sizeof(double2) * (size_t)nb0 * m);
+    double2 *W2 = (double2 *)take(sizeof(double2) * (size_t)nb0 * m);
+    double2 *Wp = (double2 *)take(sizeof(double2) * (size_t)kBtSplits * nb0 * m);
+    for (int64_t jend = nref; jend > 0; jend -= nb0) {
+      const int64_t j0 = std::max<int64_t>(0, jend - nb0);
+      const int nb = (int)(jend - j0);
+      const int64_t Lr = m - j0 - 1;
+      double2 *Zr = Z + (j0 + 1);
+      hipLaunchKernelGGL(build_v_kernel, dim3(nblk(Lr * nb, 256)), dim3(256), 0, st, m, A, lda, j0,
+                         nb, V);
+      zgemm(OP_C, OP_N, nb, nb, Lr, V, Lr, V, Lr, G, nb, double2{1, 0}, double2{0, 0}, st);
+      hipLaunchKernelGGL(larft_kernel, dim3(1), dim3(64), 0, st, nb, G, tau + j0, T);
+      const int sp = std::min(kBtSplits, zgemm_splits(nb, m, Lr));
+      zgemm(OP_C, OP_N, nb, m, Lr, V, Lr, Zr, ldz, nullptr, 0, double2{1, 0}, double2{0, 0}, st, Wp,
+            sp);
+      zsum_parts(nb, m, Wp, sp, W1, nb, double2{1, 0}, double2{0, 0}, st);
+      zgemm(OP_N, OP_N, nb, m, nb, T, nb, W1, nb, W2, nb, double2{1, 0}, double2{0, 0}, st);
+      zgemm(OP_N, OP_N, Lr, m, nb, V, Lr, W2, nb, Zr, ldz, double2{-1, 0}, double2{1, 0}, st);
+    }
+  } else {
+    for (int64_t j = m - 2; j >= 0; --j) {
+      const int64_t L = m - j - 1;
+      hipLaunchKernelGGL(load_u_kernel, dim3(nblk(L, 256)), dim3(256), 0, st, m, A, lda, j, u);
+      hipLaunchKernelGGL(bt_dot_kernel, dim3((unsigned)m), dim3(256), 0, st, m, j, u, Z, ldz,
+                         wrow);
+      hipLaunchKernelGGL(bt_update_kernel, dim3(nblk(L, 256), (unsigned)m), dim3(256), 0, st, m, j,
+                         tau, u, wrow, Z, ldz);
+    }
   }
   CHEBFI_HIP(hipGetLastError());
 }
