@@ -298,10 +298,12 @@ void local_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int
 // Out = alpha * (H - cshift) X - beta * Xprev   (Xprev may be null).
 // T = double: FP64 tables, FP64 MFMA; T = float: complex64 blocks, FP32 FFT
 // passes and FP32 MFMA projector products (mixed form).
+// Craw (optional): receives the raw projections P^H X (nproj x nband, contiguous, in the
+// block's precision), the sum of the same split-K partials the D application reads.
 template <typename T>
 void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
                   void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
-                  hipStream_t st) {
+                  hipStream_t st, void *Craw = nullptr) {
   typedef C2<T> V2;
   const bool fp32 = std::is_same<T, float>::value;
   const int nproj = s->nproj;
@@ -319,6 +321,7 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
     // C = P^H X, C' = alpha D C
     V2 *cpart = nullptr;
     const int splits = project_t<T>(s, X, ldx, nband, st, &cpart);
+    if (Craw) launch_sum_parts(nproj, nband, cpart, splits, Craw, st, fp32);
     cprime = (V2 *)s->cprime.get(sizeof(V2) * (size_t)nproj * nband);
     const int tok =
         s->prof.begin(PROF_DAPPLY, (double)sizeof(V2) * nproj * nband * (splits + 1), st);
@@ -331,11 +334,11 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
 
 void apply_core(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
                 void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
-                hipStream_t st, int32_t dtype = ABI_C128) {
+                hipStream_t st, int32_t dtype = ABI_C128, void *Craw = nullptr) {
   if (dtype == ABI_C64)
-    apply_core_t<float>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, st);
+    apply_core_t<float>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, st, Craw);
   else
-    apply_core_t<double>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, st);
+    apply_core_t<double>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, st, Craw);
 }
 
 // ---- overlap S = I + P Q P^H and its Woodbury inverse ----------------------------
@@ -1745,12 +1748,23 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
     launch_fill_zero(nbox, dV_acc, st);
     launch_fill_zero(32 * (int64_t)natom, (double *)dD_acc, st);
 
+    // raw projections P^H Y_k kept from the steps that apply H to Y_k (the reverse step
+    // needs them for dD); kept only where the step projects with the same kernel and
+    // split count as the reverse step (not the one-band FP64 step, not the FP32-MFMA
+    // tuning forms), so the gradients do not change
+    const bool keep_c = nproj > 0 && (fp32 ? s->mixed_gemm == 0 : nband > 1);
+    char *cst = keep_c ? (char *)s->adjc.get(esz * (size_t)nproj * nband * m) : nullptr;
+    auto cslot = [&](int k) { return (void *)(cst + esz * (size_t)nproj * nband * k); };
+    std::vector<char> have_c(m, 0);
     auto step_fwd = [&](int j, const void *ym1, int64_t ld1, const void *ym2, int64_t ld2,
                         void *dst) {  // Y_j from Y_{j-1} (and Y_{j-2})
+      void *craw = keep_c ? cslot(j - 1) : nullptr;
       if (j == 1)
-        apply_core(s, ym1, ld1, nullptr, 0, dst, npw, nband, gam[0], c, 0.0, st, dtype);
+        apply_core(s, ym1, ld1, nullptr, 0, dst, npw, nband, gam[0], c, 0.0, st, dtype, craw);
       else
-        apply_core(s, ym1, ld1, ym2, ld2, dst, npw, nband, gam[j - 1], c, del[j - 1], st, dtype);
+        apply_core(s, ym1, ld1, ym2, ld2, dst, npw, nband, gam[j - 1], c, del[j - 1], st, dtype,
+                   craw);
+      if (keep_c) have_c[j - 1] = 1;
     };
     // raw projections out = P^H Z (nproj x nband, contiguous), in the block's precision
     const bool planes = fp32 && s->mixed_gemm == 0;
@@ -1854,8 +1868,12 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
         if (side) CHEBFI_HIP(hipEventRecord(s->ev_join, s->aux));
         if (nproj > 0) {
           project(Ak1, lda1, CA);
-          project(Yk, ldy, CY);
-          launch_dd_accum(natom, nband, CA, CY, gam[k], dD_acc, st, fp32);
+          const void *cy = CY;
+          if (have_c[k])
+            cy = cslot(k);
+          else
+            project(Yk, ldy, CY);
+          launch_dd_accum(natom, nband, CA, cy, gam[k], dD_acc, st, fp32);
           launch_dapply(natom, nband, CA, 1, s->d_D, gam[k], Cp, st, fp32);
           if (planes)
             split_planes(nproj, nband, Cp, nproj, s->cplanes.get(8 * (size_t)s->ldPB * nband),

@@ -206,7 +206,7 @@ struct abi_system_s {
 
   // work buffers
   chebfi::DevBuf box, cpart, cprime, blk1, blk2, blk3, small1, small2, small3, small4, scal;
-  chebfi::DevBuf eig1, eig2, eig3, blk4, box2, adj, adjsmall, planes, cplanes;
+  chebfi::DevBuf eig1, eig2, eig3, blk4, box2, adj, adjsmall, adjc, planes, cplanes;
   chebfi::DevBuf solve1, solve2, solve3;  // blocks of the multi-cycle driver
   chebfi::DevBuf gen_c, gen_e, gen_f, gen_ff, blk5, blk6;  // overlap path
   chebfi::DevBuf lob_z, lob_hz, lob_sz, lob_t1, lob_t2, lob_t3, lob_psi, lob_hp, lob_sp, lob_c,
