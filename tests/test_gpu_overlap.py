@@ -15,7 +15,8 @@ of R Q R^H), on the PAW-like variants of the small systems:
 * Q = 0 through the generalised path equals the S = I path to rounding;
 * the solver loop converges to the lowest pairs of the dense pencil (H, S);
 * full size (115313 plane waves, 2048 bands, degree 12, 864 projectors):
-  sampled filter columns against the oracle (column-independent filter);
+  sampled filter columns against the oracle (column-independent filter), and
+  the FP64 S-Lanczos bound and sampled Ritz pairs' properties;
 * errors: an S that is not positive definite, the adjoint and the batched
   filter with S != I are refused;
 * one band (matrix-vector products) and a ragged band count; the band halves
@@ -275,3 +276,34 @@ def test_two_stream_halves_match_one_stream(precision, monkeypatch):
                 Xd = Xd.to(torch.complex64)
             outs.append(to_host(g.cheb_filter(Xd, 4, 1.0, 9.0, -0.5)))
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_fullsize_bounds_and_rayleigh_ritz_properties():
+    """The large workload with the overlap, FP64: the S-Lanczos bound depends on v0 only
+    (oracle 1e-10); after a filter and the S-Gram Rayleigh-Ritz, sampled Ritz vectors
+    have generalised Rayleigh quotients equal to their Ritz values (1e-8 Ha), the
+    library's residual norms ||H psi - lambda S psi|| (1e-8) and S-orthonormality
+    (1e-10)."""
+    s = W.make_system(3, q_scale=W.PAW_Q_SCALE)
+    H = O.Hamiltonian.from_system(s)
+    S = O.Overlap.from_system(H, s)
+    X = W.random_block(H.npw, s.nband, s.tag)
+    v0 = W.random_vector(H.npw, s.tag)
+    cols = [0, 1, 2, 1024, 2046, 2047]
+    with B.System(s) as g:
+        Xd = to_dev(X)
+        a, b, a0 = g.spectral_bounds(Xd, to_dev(v0))
+        Yd = g.cheb_filter(Xd, s.degree, a, b, a0)
+        del Xd
+        ev, res, flags = g.rayleigh_ritz(Yd)
+        Psi = Yd[cols].cpu().numpy().T
+        del Yd
+    ref_b, _, _ = O.lanczos_upper_bound_gen(H.apply, S.apply, S.inv_apply, v0, 10)
+    assert abs(b - ref_b) <= 1e-10 * abs(ref_b)
+    assert flags == 0 and np.all(np.diff(ev) >= 0)
+    HPsi, SPsi = H(Psi), S.apply(Psi)
+    rq = O.rayleigh_quotients_gen(Psi, HPsi, SPsi)
+    assert np.abs(rq - ev[cols]).max() <= 1e-8
+    r = np.linalg.norm(HPsi - SPsi * ev[cols][None, :], axis=0)
+    assert np.abs(r - res[cols]).max() <= 1e-8
+    assert np.abs(Psi.conj().T @ SPsi - np.eye(len(cols))).max() <= 1e-10
