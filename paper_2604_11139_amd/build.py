@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchebfi.so")
 
-SOURCES = ["system.cpp", "chebfi_abi.cpp", "fft.hip", "gemm.hip", "stream.hip", "dense.hip",
+SOURCES = ["system.cpp", "chebfi_abi.cpp", "driver.cpp", "lobpcg.cpp", "fft.hip", "gemm.hip", "stream.hip", "dense.hip",
            "batch.hip", "scf.hip"]
 ARCH = "gfx950"
 

@@ -5,7 +5,10 @@
 // order of operations follows arXiv 2604.11139: the matrix-free H application
 // (section "Main computational kernels"), the Chebyshev filter loop of
 // Algorithm "Parallel Chebyshev filtering of degree k" and the S-ortho / RR
-// algorithms of section "Parallel implementation design" with S = I.
+// algorithms of section "Parallel implementation design".  The drivers of the
+// H / S applications, the generalised filter step and Rayleigh-Ritz live in
+// driver.cpp, block LOBPCG in lobpcg.cpp; the batched filter's host side and
+// the eigensolver and SCF loops are here.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -13,6 +16,7 @@
 #include <new>
 
 #include "cplx.h"
+#include "driver.h"
 #include "kernels.h"
 
 namespace chebfi {
@@ -137,16 +141,6 @@ void check_desc(const abi_system_desc *d) {
   for (double b : B) CHEBFI_REQUIRE(std::isfinite(b), ABI_ERR_ARG, "singular lattice");
 }
 
-template <typename T> T *upload(const T *host, size_t count) {
-  T *dev = nullptr;
-  if (count == 0) count = 1;
-  if (hipMalloc(&dev, sizeof(T) * count) != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error{ABI_ERR_NOMEM, "hipMalloc failed during set_system"};
-  }
-  if (host) CHEBFI_HIP(hipMemcpy(dev, host, sizeof(T) * count, hipMemcpyHostToDevice));
-  return dev;
-}
 
 void free_tables(abi_system_s *s) {
   if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
@@ -199,652 +193,6 @@ void check_block(const abi_system_s *s, const void *p, int64_t nband, int64_t ld
                  "complex64 blocks need a handle built with ABI_PREC_MIXED");
 }
 
-inline size_t elem_bytes(int32_t dtype) { return dtype == ABI_C64 ? sizeof(float2) : sizeof(double2); }
-
-// Projector products of a block: part[z] = P^H X over plane-wave chunk z
-// (returns the chunk count).  T = double: FP64 MFMA (a matrix-vector product
-// for one band); T = float: complex64 block, split-BF16 MFMA (FP32 MFMA with
-// mixed_gemm = 1), FP32 partials.
-template <typename T>
-int project_t(abi_system_s *s, const void *X, int64_t ldx, int64_t nband, hipStream_t st,
-              C2<T> **part_out) {
-  typedef C2<T> V2;
-  const bool fp32 = std::is_same<T, float>::value;
-  const void *P = fp32 ? (const void *)s->d_Pf : (const void *)s->d_P;
-  const int64_t npw = s->npw;
-  const int nproj = s->nproj;
-  const bool single = (nband == 1) && !fp32;
-  const bool planes = fp32 && s->mixed_gemm == 0;
-  const int splits = single ? 1
-                     : planes ? proj_planes_splits(s->pl_proj, nproj, nband, npw)
-                              : zgemm_splits(nproj, nband, npw);
-  V2 *cpart = (V2 *)s->cpart.get(sizeof(V2) * (size_t)splits * nproj * nband);
-  const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
-  // the default split-BF16 projection splits the block into planes while staging it;
-  // the other tile variants read planes made by a separate pass
-  const bool staged = planes && s->pl_proj == 4;
-  void *xpl = nullptr;
-  if (planes && !staged) {
-    xpl = s->planes.get(8 * (size_t)s->ldPA * nband);
-    const int tk = s->prof.begin(PROF_SPLIT, 16.0 * (double)npw * (double)nband, st);
-    split_planes(npw, nband, X, ldx, xpl, s->ldPA, st);
-    s->prof.end(tk, st);
-  }
-  const int tok = s->prof.begin(PROF_PROJ, flops, st);
-  if (single)
-    proj_gemv(npw, nproj, P, X, cpart, st);
-  else if (staged)
-    proj_gemm_planes_f32(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, X, ldx,
-                         cpart, splits, st);
-  else if (planes)
-    proj_gemm_planes(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, xpl,
-                     s->ldPA, s->ldPA * nband, cpart, splits, st, s->pl_proj);
-  else if (fp32 && s->mixed_gemm == 2)
-    proj_gemm_bf16x3(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, X, ldx,
-                     cpart, splits, st);
-  else
-    proj_gemm(nproj, nband, npw, P, X, ldx, cpart, splits, st, fp32);
-  s->prof.end(tok, st);
-  *part_out = cpart;
-  return splits;
-}
-
-// Out += P C' for nproj x nband coefficients C' (ld nproj) of the block's type.
-template <typename T>
-void expand_t(abi_system_s *s, const C2<T> *cprime, void *Out, int64_t ldo, int64_t nband,
-              hipStream_t st) {
-  const bool fp32 = std::is_same<T, float>::value;
-  const void *P = fp32 ? (const void *)s->d_Pf : (const void *)s->d_P;
-  const int64_t npw = s->npw;
-  const int nproj = s->nproj;
-  const bool single = (nband == 1) && !fp32;
-  const bool planes = fp32 && s->mixed_gemm == 0;
-  if (planes)
-    split_planes(nproj, nband, cprime, nproj, s->cplanes.get(8 * (size_t)s->ldPB * nband),
-                 s->ldPB, st);
-  const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
-  const int tok = s->prof.begin(PROF_EXPAND, flops, st);
-  if (single)
-    expand_gemv(npw, nproj, P, cprime, Out, st);
-  else if (planes)
-    expand_gemm_planes(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB, s->cplanes.ptr,
-                       s->ldPB, s->ldPB * nband, Out, ldo, st, s->pl_expand);
-  else if (fp32 && s->mixed_gemm == 2)
-    expand_gemm_bf16x3(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB, cprime, Out, ldo, st);
-  else
-    expand_gemm(npw, nband, nproj, P, cprime, Out, ldo, st, fp32);
-  s->prof.end(tok, st);
-}
-
-// Local part, kinetic term and recurrence on the FFT grid:
-// Out = alpha ((0.5|k+G|^2 + V_loc) X - cshift X) - beta Xprev   (Xprev may be null).
-template <typename T>
-void local_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
-             void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
-             hipStream_t st) {
-  typedef C2<T> V2;
-  const bool fp32 = std::is_same<T, float>::value;
-  const void *V = fp32 ? (const void *)s->d_Vf : (const void *)s->d_V;
-  const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
-  const int fb = (int)std::min<int64_t>(s->fft_batch * (fp32 ? 2 : 1), nband);
-  void *box = s->box.get(sizeof(V2) * (size_t)nbox * fb);
-  for (int64_t b0 = 0; b0 < nband; b0 += fb) {
-    const int nb = (int)std::min<int64_t>(fb, nband - b0);
-    launch_local_potential<T>(s, X, ldx, Xprev, ldp, Out, ldo, (int)b0, nb, box, V, alpha, cshift,
-                              beta, st, s->prof.on ? &s->prof : nullptr);
-  }
-}
-
-// Out = alpha * (H - cshift) X - beta * Xprev   (Xprev may be null).
-// T = double: FP64 tables, FP64 MFMA; T = float: complex64 blocks, FP32 FFT
-// passes and FP32 MFMA projector products (mixed form).
-// Craw (optional): receives the raw projections P^H X (nproj x nband, contiguous, in the
-// block's precision), the sum of the same split-K partials the D application reads.
-template <typename T>
-void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
-                  void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
-                  hipStream_t st, void *Craw = nullptr) {
-  typedef C2<T> V2;
-  const bool fp32 = std::is_same<T, float>::value;
-  const int nproj = s->nproj;
-  const bool single = (nband == 1) && !fp32;
-  // the FFT passes run on the second stream beside the projection when they can
-  const bool side = s->overlap && nproj > 0 && !single && s->aux;
-  if (side) {
-    CHEBFI_HIP(hipEventRecord(s->ev_fork, st));
-    CHEBFI_HIP(hipStreamWaitEvent(s->aux, s->ev_fork, 0));
-  }
-  local_t<T>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, side ? s->aux : st);
-  if (side) CHEBFI_HIP(hipEventRecord(s->ev_join, s->aux));
-  V2 *cprime = nullptr;
-  if (nproj > 0) {
-    // C = P^H X, C' = alpha D C
-    V2 *cpart = nullptr;
-    const int splits = project_t<T>(s, X, ldx, nband, st, &cpart);
-    if (Craw) launch_sum_parts(nproj, nband, cpart, splits, Craw, st, fp32);
-    cprime = (V2 *)s->cprime.get(sizeof(V2) * (size_t)nproj * nband);
-    const int tok =
-        s->prof.begin(PROF_DAPPLY, (double)sizeof(V2) * nproj * nband * (splits + 1), st);
-    launch_dapply(s->natom, nband, cpart, splits, s->d_D, alpha, cprime, st, fp32);
-    s->prof.end(tok, st);
-  }
-  if (side) CHEBFI_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
-  if (nproj > 0) expand_t<T>(s, cprime, Out, ldo, nband, st);  // Out += P C'
-}
-
-void apply_core(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
-                void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
-                hipStream_t st, int32_t dtype = ABI_C128, void *Craw = nullptr) {
-  if (dtype == ABI_C64)
-    apply_core_t<float>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, st, Craw);
-  else
-    apply_core_t<double>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, st, Craw);
-}
-
-// ---- overlap S = I + P Q P^H and its Woodbury inverse ----------------------------
-
-// Out = S X = X + P (Q (P^H X))  (Out must not overlap X).
-template <typename T>
-void apply_S_t(abi_system_s *s, const void *X, int64_t ldx, void *Out, int64_t ldo,
-               int64_t nband, hipStream_t st) {
-  typedef C2<T> V2;
-  const bool fp32 = std::is_same<T, float>::value;
-  launch_copy_block(s->npw, nband, X, ldx, Out, ldo, st, fp32);
-  if (!s->has_S) return;
-  V2 *cpart = nullptr;
-  const int splits = project_t<T>(s, X, ldx, nband, st, &cpart);
-  V2 *cprime = (V2 *)s->cprime.get(sizeof(V2) * (size_t)s->nproj * nband);
-  launch_dapply(s->natom, nband, cpart, splits, s->d_Q, 1.0, cprime, st, fp32);
-  expand_t<T>(s, cprime, Out, ldo, nband, st);
-}
-
-// Out = S^-1 X = X - P (K (P^H X))  (the Sinv kernel; Out must not overlap X).
-template <typename T>
-void apply_Sinv_t(abi_system_s *s, const void *X, int64_t ldx, void *Out, int64_t ldo,
-                  int64_t nband, hipStream_t st) {
-  typedef C2<T> V2;
-  const bool fp32 = std::is_same<T, float>::value;
-  launch_copy_block(s->npw, nband, X, ldx, Out, ldo, st, fp32);
-  if (!s->has_S) return;
-  const int n = s->nproj;
-  V2 *cpart = nullptr;
-  const int splits = project_t<T>(s, X, ldx, nband, st, &cpart);
-  double2 *C = (double2 *)s->gen_e.get(sizeof(double2) * (size_t)n * nband);
-  double2 *F = (double2 *)s->gen_f.get(sizeof(double2) * (size_t)n * nband);
-  const int tok = s->prof.begin(PROF_DAPPLY, 8.0 * (double)n * n * nband, st);
-  launch_parts_to_c128(n, nband, cpart, splits, fp32, C, st);
-  zgemm(OP_N, OP_N, n, nband, n, s->d_K, n, C, n, F, n, double2{-1, 0}, double2{0, 0}, st);
-  const V2 *fp = (const V2 *)F;
-  if (fp32) {
-    float2 *Ff = (float2 *)s->gen_ff.get(sizeof(float2) * (size_t)n * nband);
-    launch_d2f(2 * (int64_t)n * nband, (const double *)F, (float *)Ff, st);
-    fp = (const V2 *)Ff;
-  }
-  s->prof.end(tok, st);
-  expand_t<T>(s, fp, Out, ldo, nband, st);
-}
-
-void apply_S(abi_system_s *s, const void *X, int64_t ldx, void *Out, int64_t ldo, int64_t nband,
-             hipStream_t st, int32_t dtype = ABI_C128) {
-  if (dtype == ABI_C64)
-    apply_S_t<float>(s, X, ldx, Out, ldo, nband, st);
-  else
-    apply_S_t<double>(s, X, ldx, Out, ldo, nband, st);
-}
-
-void apply_Sinv(abi_system_s *s, const void *X, int64_t ldx, void *Out, int64_t ldo,
-                int64_t nband, hipStream_t st, int32_t dtype = ABI_C128) {
-  if (dtype == ABI_C64)
-    apply_Sinv_t<float>(s, X, ldx, Out, ldo, nband, st);
-  else
-    apply_Sinv_t<double>(s, X, ldx, Out, ldo, nband, st);
-}
-
-// One step of the filter on S^-1 H:
-//   Out = alpha (S^-1 H - cshift) X - beta Xprev,   Cnext = P^H Out,
-// given Ck = P^H X and Ckm1 = P^H Xprev (complex double, nproj x nband; Ckm1 null
-// on the first step).  With H X = T + P D Ck (T: kinetic and local part) and
-// S^-1 = I - P K P^H:  S^-1 H X = T + P F,  F = D Ck - K (P^H T + B D Ck).
-// The local passes write Out = alpha (T - c X) - beta Xprev; its projection G
-// gives P^H T = G / alpha + c Ck + (beta / alpha) Ckm1 without projecting T
-// itself; then Out += alpha P F and Cnext = G + alpha B F.  One projection and
-// one expansion of the block per step, as for S = I, plus three nproj x nproj
-// products by nband.
-// The projection reads the local passes' output, so the two are pipelined over
-// two halves of the bands: the passes of the second half (second stream) run
-// beside the projection of the first, and D Ck, B D Ck beside the first half's
-// passes.
-template <typename T>
-void gen_step_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
-                void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
-                const double2 *Ck, const double2 *Ckm1, double2 *Cnext, hipStream_t st) {
-  typedef C2<T> V2;
-  const bool fp32 = std::is_same<T, float>::value;
-  const int n = s->nproj;
-  const size_t eb = sizeof(V2);
-  const bool side = s->overlap && s->aux && nband >= 128;
-  // band ranges [0, h) and [h, nband)
-  const int64_t h = side ? (nband / 2 + 31) / 32 * 32 : nband;
-  auto at = [&](const void *p, int64_t ld, int64_t b) -> const void * {
-    return p ? (const void *)((const char *)p + eb * (size_t)(b * ld)) : nullptr;
-  };
-  auto local_range = [&](int64_t b0, int64_t nb, hipStream_t sst) {
-    local_t<T>(s, at(X, ldx, b0), ldx, at(Xprev, ldp, b0), ldp,
-               (void *)at(Out, ldo, b0), ldo, nb, alpha, cshift, beta, sst);
-  };
-  if (side) {
-    CHEBFI_HIP(hipEventRecord(s->ev_fork, st));
-    CHEBFI_HIP(hipStreamWaitEvent(s->aux, s->ev_fork, 0));
-    local_range(0, h, s->aux);
-    CHEBFI_HIP(hipEventRecord(s->ev_half, s->aux));
-    local_range(h, nband - h, s->aux);
-    CHEBFI_HIP(hipEventRecord(s->ev_join, s->aux));
-  } else {
-    local_range(0, nband, st);
-  }
-  double2 *E = (double2 *)s->gen_e.get(sizeof(double2) * (size_t)n * nband);
-  double2 *F = (double2 *)s->gen_f.get(sizeof(double2) * (size_t)n * nband);
-  int tok = s->prof.begin(PROF_DAPPLY, 8.0 * (double)n * n * nband, st);
-  launch_dapply(s->natom, nband, Ck, 1, s->d_D, 1.0, F, st, false);  // F = D Ck
-  zgemm(OP_N, OP_N, n, nband, n, s->d_B, n, F, n, E, n, double2{1, 0}, double2{0, 0},
-        st);  // E = B D Ck
-  s->prof.end(tok, st);
-  // G = P^H Out per band range; E += G / alpha + c Ck + (beta / alpha) Ckm1, Cnext = G
-  for (int part = 0; part < 2; ++part) {
-    const int64_t b0 = part == 0 ? 0 : h, nb = part == 0 ? h : nband - h;
-    if (nb <= 0) continue;
-    if (side) CHEBFI_HIP(hipStreamWaitEvent(st, part == 0 ? s->ev_half : s->ev_join, 0));
-    V2 *cpart = nullptr;
-    const int splits = project_t<T>(s, at(Out, ldo, b0), ldo, nb, st, &cpart);
-    const size_t off = (size_t)n * b0;
-    launch_gen_combine(n, nb, cpart, splits, fp32, Ck + off, Ckm1 ? Ckm1 + off : nullptr, alpha,
-                       cshift, beta, E + off, Cnext + off, st);
-  }
-  tok = s->prof.begin(PROF_DAPPLY, 16.0 * (double)n * n * nband, st);
-  zgemm(OP_N, OP_N, n, nband, n, s->d_K, n, E, n, F, n, double2{-alpha, 0}, double2{alpha, 0},
-        st);  // F = alpha (D Ck - K E)
-  zgemm(OP_N, OP_N, n, nband, n, s->d_B, n, F, n, Cnext, n, double2{1, 0}, double2{1, 0}, st);
-  const V2 *fp = (const V2 *)F;
-  if (fp32) {
-    float2 *Ff = (float2 *)s->gen_ff.get(sizeof(float2) * (size_t)n * nband);
-    launch_d2f(2 * (int64_t)n * nband, (const double *)F, (float *)Ff, st);
-    fp = (const V2 *)Ff;
-  }
-  s->prof.end(tok, st);
-  expand_t<T>(s, fp, Out, ldo, nband, st);
-}
-
-// Ck = P^H X in complex double (the first coefficients of a generalised filter).
-template <typename T>
-void project_c128_t(abi_system_s *s, const void *X, int64_t ldx, int64_t nband, double2 *C,
-                    hipStream_t st) {
-  C2<T> *cpart = nullptr;
-  const int splits = project_t<T>(s, X, ldx, nband, st, &cpart);
-  launch_parts_to_c128(s->nproj, nband, cpart, splits, std::is_same<T, float>::value, C, st);
-}
-
-// Builds the overlap tables from Q (host, natom*16 complex): B = P^H P,
-// B = R^H R (Cholesky), R Q R^H = Z diag(mu) Z^H, so that S has the eigenvalues
-// 1 and 1 + mu_i and S^-1 = I - P K P^H with K = W diag(mu/(1+mu)) W^H, W = R^-1 Z
-// (the Woodbury formula, written through the eigenvalues of the small pencil so
-// that an indefinite Q is allowed as long as S stays positive definite).
-void setup_overlap(abi_system_s *s, const double *qij, hipStream_t st) {
-  const int n = s->nproj;
-  if (n == 0 || qij == nullptr) return;
-  s->d_Q = upload(qij, (size_t)s->natom * 32);
-  std::vector<double> Qd((size_t)2 * n * n, 0.0);
-  for (int R = 0; R < s->natom; ++R)
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) {
-        // column-major dense Q, Q[4R+i, 4R+j] = Q_R[i][j]
-        const size_t dst = 2 * ((size_t)(4 * R + i) + (size_t)(4 * R + j) * n);
-        Qd[dst] = qij[32 * R + 2 * (4 * i + j)];
-        Qd[dst + 1] = qij[32 * R + 2 * (4 * i + j) + 1];
-      }
-  const size_t mm = sizeof(double2) * (size_t)n * n;
-  double2 *Q = upload((const double2 *)Qd.data(), (size_t)n * n);
-  DevBuf w1, w2, w3, wz, ws;
-  double2 *R = (double2 *)w1.get(mm), *T = (double2 *)w2.get(mm), *A = (double2 *)w3.get(mm);
-  double2 *Z = (double2 *)wz.get(mm);
-  double *mu = (double *)ws.get(sizeof(double) * (size_t)n + 64);
-  int *info = (int *)(mu + n);
-  s->d_B = (double *)upload<double2>(nullptr, (size_t)n * n);
-  s->d_K = (double *)upload<double2>(nullptr, (size_t)n * n);
-  try {
-    {
-      const int splits = zgemm_splits(n, n, s->npw);
-      DevBuf part;
-      void *pp = part.get(sizeof(double2) * (size_t)splits * n * n);
-      zgemm(OP_C, OP_N, n, n, s->npw, s->d_P, s->npw, s->d_P, s->npw, nullptr, 0, double2{1, 0},
-            double2{0, 0}, st, pp, splits);
-      zsum_parts(n, n, pp, splits, s->d_B, n, double2{1, 0}, double2{0, 0}, st);
-      CHEBFI_HIP(hipStreamSynchronize(st));
-    }
-    launch_hermitize(n, s->d_B, n, st);
-    launch_copy_block(n, n, s->d_B, n, R, n, st);
-    DevBuf pw;
-    zpotrf_upper(n, R, n, info, pw.get(zpotrf_work_bytes(n)), st);
-    int hinfo = 0;
-    CHEBFI_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, st));
-    CHEBFI_HIP(hipStreamSynchronize(st));
-    if (hinfo != 0)
-      throw Error{ABI_ERR_NOT_HPD, "projector Gram matrix P^H P is singular (pivot " +
-                                       std::to_string(hinfo) + ")"};
-    // A = R Q R^H
-    zgemm(OP_N, OP_C, n, n, n, Q, n, R, n, T, n, double2{1, 0}, double2{0, 0}, st);
-    zgemm(OP_N, OP_N, n, n, n, R, n, T, n, A, n, double2{1, 0}, double2{0, 0}, st);
-    DevBuf ew;
-    zheev(n, A, n, mu, Z, n, ew.get(zheev_work_bytes(n)), st);
-    std::vector<double> hmu(n);
-    CHEBFI_HIP(hipMemcpyAsync(hmu.data(), mu, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-    CHEBFI_HIP(hipStreamSynchronize(st));
-    s->s_min = std::min(1.0, 1.0 + hmu[0]);
-    if (!(1.0 + hmu[0] > 1e-10))
-      throw Error{ABI_ERR_NOT_HPD, "overlap operator S = I + P Q P^H is not positive definite "
-                                   "(smallest eigenvalue " + std::to_string(1.0 + hmu[0]) + ")"};
-    // W = R^-1 Z, K = W diag(mu / (1 + mu)) W^H
-    DevBuf tw;
-    ztrtri_upper(n, R, n, tw.get(ztrtri_work_bytes(n)), st);
-    zgemm(OP_N, OP_N, n, n, n, R, n, Z, n, T, n, double2{1, 0}, double2{0, 0}, st);
-    launch_woodbury_scale(n, T, n, mu, A, n, st);
-    zgemm(OP_N, OP_C, n, n, n, A, n, T, n, s->d_K, n, double2{1, 0}, double2{0, 0}, st);
-    launch_hermitize(n, s->d_K, n, st);
-    CHEBFI_HIP(hipStreamSynchronize(st));
-  } catch (...) {
-    (void)hipStreamSynchronize(st);
-    (void)hipFree(Q);
-    throw;
-  }
-  CHEBFI_HIP(hipFree(Q));
-  s->has_S = true;
-}
-
-// FP64 Rayleigh-Ritz on a complex128 block Y (in: filtered block, out: Psi).
-void rr_core(abi_system_s *s, double2 *Y, int64_t ld, double2 *HPsi, int64_t ldh_in, int64_t M,
-             double *eval, double *resnorm, void *coef, hipStream_t st) {
-  const int64_t npw = s->npw;
-  const size_t mm = sizeof(double2) * (size_t)M * M;
-  double2 *G = (double2 *)s->small1.get(mm);
-  double2 *Hs = (double2 *)s->small2.get(mm);
-  double2 *T = (double2 *)s->small3.get(mm);
-  double2 *Z = (double2 *)s->small4.get(mm);
-  double *scal = (double *)s->scal.get(sizeof(double) * (size_t)(160 + 3 * M + 64));
-  double *w_dev = scal + 160;
-  double *r_dev = w_dev + M;
-  int *info = (int *)(r_dev + M);
-  // Gram G = Y^H (S Y) -> U (Cholesky, upper); with S != I, S Y = Y + P Q C_Y from
-  // the projections C_Y = P^H Y, which also give S Psi after the rotation
-  const bool gen = s->has_S;
-  const int n = s->nproj;
-  double2 *CY = nullptr, *SY = Y;
-  int64_t lds = ld;
-  if (gen) {
-    CY = (double2 *)s->gen_c.get(sizeof(double2) * (size_t)n * M);
-    double2 *QC = (double2 *)s->gen_f.get(sizeof(double2) * (size_t)n * M);
-    SY = (double2 *)s->blk5.get(sizeof(double2) * (size_t)npw * M);
-    lds = npw;
-    project_c128_t<double>(s, Y, ld, M, CY, st);
-    launch_dapply(s->natom, M, CY, 1, s->d_Q, 1.0, QC, st, false);
-    launch_copy_block(npw, M, Y, ld, SY, lds, st);
-    expand_t<double>(s, QC, SY, lds, M, st);
-  }
-  int splits = zgemm_splits(M, M, npw);
-  void *part = s->cpart.get(sizeof(double2) * (size_t)splits * M * M);
-  const double gflops = 8.0 * (double)M * M * npw;
-  int tok = s->prof.begin(PROF_GRAM, gflops, st);
-  zgemm(OP_C, OP_N, M, M, npw, Y, ld, SY, lds, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
-        splits);
-  zsum_parts(M, M, part, splits, G, M, double2{1, 0}, double2{0, 0}, st);
-  s->prof.end(tok, st);
-  launch_hermitize(M, G, M, st);
-  tok = s->prof.begin(PROF_CHOL, 4.0 / 3.0 * (double)M * M * M, st);
-  zpotrf_upper(M, G, M, info, nullptr, st);
-  s->prof.end(tok, st);
-  int hinfo = 0;
-  CHEBFI_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, st));
-  CHEBFI_HIP(hipStreamSynchronize(st));
-  if (hinfo != 0)
-    throw Error{ABI_ERR_NOT_HPD,
-                "Gram matrix not positive definite at pivot " + std::to_string(hinfo)};
-  // H Y and H_s = Y^H (H Y)
-  double2 *HY = (double2 *)s->blk1.get(sizeof(double2) * (size_t)npw * M);
-  apply_core(s, Y, ld, nullptr, 0, HY, npw, M, 1.0, 0.0, 0.0, st);
-  part = s->cpart.get(sizeof(double2) * (size_t)splits * M * M);  // apply_core may regrow it
-  tok = s->prof.begin(PROF_GRAM, gflops, st);
-  zgemm(OP_C, OP_N, M, M, npw, Y, ld, HY, npw, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
-        splits);
-  zsum_parts(M, M, part, splits, Hs, M, double2{1, 0}, double2{0, 0}, st);
-  s->prof.end(tok, st);
-  launch_hermitize(M, Hs, M, st);
-  // U^-1 and the reduced matrix U^-H H_s U^-1
-  tok = s->prof.begin(PROF_CHOL, 16.0 * (double)M * M * M, st);
-  void *trw = s->eig2.get(ztrtri_work_bytes(M));
-  ztrtri_upper(M, G, M, trw, st);
-  zgemm(OP_N, OP_N, M, M, M, Hs, M, G, M, T, M, double2{1, 0}, double2{0, 0}, st);
-  zgemm(OP_C, OP_N, M, M, M, G, M, T, M, Hs, M, double2{1, 0}, double2{0, 0}, st);
-  s->prof.end(tok, st);
-  // eigen-decomposition (Hs overwritten), W = U^-1 Z
-  void *ew = s->eig1.get(zheev_work_bytes(M));
-  tok = s->prof.begin(PROF_EIG, 16.0 / 3.0 * (double)M * M * M, st);
-  zheev(M, Hs, M, w_dev, Z, M, ew, st);
-  s->prof.end(tok, st);
-  tok = s->prof.begin(PROF_ROT, 8.0 * (double)M * M * M + 16.0 * (double)npw * M * M, st);
-  zgemm(OP_N, OP_N, M, M, M, G, M, Z, M, T, M, double2{1, 0}, double2{0, 0}, st);
-  // Psi = Y W, H Psi = (H Y) W
-  double2 *Psi = (double2 *)s->blk2.get(sizeof(double2) * (size_t)npw * M);
-  zgemm(OP_N, OP_N, npw, M, M, Y, ld, T, M, Psi, npw, double2{1, 0}, double2{0, 0}, st);
-  double2 *HP;
-  int64_t ldh;
-  if (HPsi) {
-    HP = HPsi;
-    ldh = ldh_in;
-  } else {
-    HP = (double2 *)s->blk3.get(sizeof(double2) * (size_t)npw * M);
-    ldh = npw;
-  }
-  zgemm(OP_N, OP_N, npw, M, M, HY, npw, T, M, HP, ldh, double2{1, 0}, double2{0, 0}, st);
-  s->prof.end(tok, st);
-  if (coef) launch_copy_block(M, M, T, M, coef, M, st);
-  launch_copy_block(npw, M, Psi, npw, Y, ld, st);
-  if (gen) {
-    // S Psi = Psi + P Q (C_Y W): residuals || H psi - lambda S psi ||
-    double2 *CP = (double2 *)s->gen_e.get(sizeof(double2) * (size_t)n * M);
-    double2 *QC = (double2 *)s->gen_f.get(sizeof(double2) * (size_t)n * M);
-    zgemm(OP_N, OP_N, n, M, M, CY, n, T, M, CP, n, double2{1, 0}, double2{0, 0}, st);
-    launch_dapply(s->natom, M, CP, 1, s->d_Q, 1.0, QC, st, false);
-    launch_copy_block(npw, M, Psi, npw, SY, lds, st);
-    expand_t<double>(s, QC, SY, lds, M, st);
-    launch_residual_norms(npw, M, SY, lds, HP, ldh, w_dev, r_dev, st);
-  } else {
-    launch_residual_norms(npw, M, Y, ld, HP, ldh, w_dev, r_dev, st);
-  }
-  CHEBFI_HIP(hipMemcpyAsync(eval, w_dev, sizeof(double) * M, hipMemcpyDeviceToHost, st));
-  if (resnorm)
-    CHEBFI_HIP(hipMemcpyAsync(resnorm, r_dev, sizeof(double) * M, hipMemcpyDeviceToHost, st));
-  CHEBFI_HIP(hipStreamSynchronize(st));
-}
-
-// ---- block LOBPCG (the paper's comparison solver) ---------------------------------
-
-// S-ortho + Rayleigh-Ritz of a basis Z (npw x k, ld): Z^H S Z = U^H U,
-// U^-H (Z^H H Z) U^-1 = Y diag(w) Y^H, C = U^-1 Y[:, :mout] (k x mout, ld k), w on the
-// device (k values, ascending).  Returns false, with nothing else written, when the
-// Gram is not positive definite.
-bool ortho_rr_basis(abi_system_s *s, int64_t k, int64_t mout, const double2 *Z,
-                    const double2 *HZ, const double2 *SZ, int64_t ld, double *w_dev, double2 *C,
-                    hipStream_t st) {
-  const int64_t npw = s->npw;
-  const size_t kk = sizeof(double2) * (size_t)k * k;
-  double2 *G = (double2 *)s->small1.get(kk);
-  double2 *Hs = (double2 *)s->small2.get(kk);
-  double2 *T = (double2 *)s->small3.get(kk);
-  double2 *Y = (double2 *)s->small4.get(kk);
-  int *info = (int *)s->lob_g.get(sizeof(double2) * 16);
-  const int splits = zgemm_splits(k, k, npw);
-  const double gflops = 8.0 * (double)k * k * npw;
-  void *part = s->cpart.get(sizeof(double2) * (size_t)splits * k * k);
-  int tok = s->prof.begin(PROF_GRAM, gflops, st);
-  zgemm(OP_C, OP_N, k, k, npw, Z, ld, SZ, ld, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
-        splits);
-  zsum_parts(k, k, part, splits, G, k, double2{1, 0}, double2{0, 0}, st);
-  s->prof.end(tok, st);
-  launch_hermitize(k, G, k, st);
-  tok = s->prof.begin(PROF_CHOL, 4.0 / 3.0 * (double)k * k * k, st);
-  zpotrf_upper(k, G, k, info, nullptr, st);
-  s->prof.end(tok, st);
-  int h = 0;
-  CHEBFI_HIP(hipMemcpyAsync(&h, info, sizeof(int), hipMemcpyDeviceToHost, st));
-  CHEBFI_HIP(hipStreamSynchronize(st));
-  if (h != 0) return false;
-  tok = s->prof.begin(PROF_GRAM, gflops, st);
-  zgemm(OP_C, OP_N, k, k, npw, Z, ld, HZ, ld, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
-        splits);
-  zsum_parts(k, k, part, splits, Hs, k, double2{1, 0}, double2{0, 0}, st);
-  s->prof.end(tok, st);
-  launch_hermitize(k, Hs, k, st);
-  tok = s->prof.begin(PROF_CHOL, 16.0 * (double)k * k * k, st);
-  ztrtri_upper(k, G, k, s->eig2.get(ztrtri_work_bytes(k)), st);
-  zgemm(OP_N, OP_N, k, k, k, Hs, k, G, k, T, k, double2{1, 0}, double2{0, 0}, st);
-  zgemm(OP_C, OP_N, k, k, k, G, k, T, k, Hs, k, double2{1, 0}, double2{0, 0}, st);
-  s->prof.end(tok, st);
-  tok = s->prof.begin(PROF_EIG, 16.0 / 3.0 * (double)k * k * k, st);
-  zheev(k, Hs, k, w_dev, Y, k, s->eig1.get(zheev_work_bytes(k)), st);
-  s->prof.end(tok, st);
-  zgemm(OP_N, OP_N, k, mout, k, G, k, Y, k, C, k, double2{1, 0}, double2{0, 0}, st);
-  return true;
-}
-
-// X <- X - Q (Q^H S X) for the S-orthonormal bands Q (npw x nq) and a block X
-// (npw x m); SX is work space that receives S X first (unused when S = I).
-void s_deflate(abi_system_s *s, const double2 *Q, int64_t nq, double2 *X, double2 *SX, int64_t m,
-               hipStream_t st) {
-  const int64_t npw = s->npw;
-  if (nq == 0) return;
-  const double2 *sx = X;
-  if (s->has_S) {
-    apply_S(s, X, npw, SX, npw, m, st);
-    sx = SX;
-  }
-  double2 *G = (double2 *)s->lob_g.get(sizeof(double2) * (size_t)nq * m);
-  const int splits = zgemm_splits(nq, m, npw);
-  void *part = s->cpart.get(sizeof(double2) * (size_t)splits * nq * m);
-  zgemm(OP_C, OP_N, nq, m, npw, Q, npw, sx, npw, nullptr, 0, double2{1, 0}, double2{0, 0}, st,
-        part, splits);
-  zsum_parts(nq, m, part, splits, G, nq, double2{1, 0}, double2{0, 0}, st);
-  zgemm(OP_N, OP_N, npw, m, nq, Q, npw, G, nq, X, npw, double2{-1, 0}, double2{1, 0}, st);
-}
-
-// One pass of block LOBPCG (Algorithm "Parallel LOBPCG with b blocks and k line
-// minimizations") on the block Psi (npw x M, ld), in place; returns the Ritz values and
-// residual norms ||H psi - lambda S psi|| (host arrays of M) and the line minimisations
-// each block ran.  FP64 throughout.
-void lobpcg_pass_core(abi_system_s *s, double2 *Psi_io, int64_t ldio, int64_t M, int nblocks,
-                      int nline, double tol, double *eval, double *res, int *steps,
-                      hipStream_t st) {
-  const int64_t npw = s->npw, m = M / nblocks;
-  const bool gen = s->has_S;
-  const size_t col = sizeof(double2) * (size_t)npw;
-  double2 *Psi = (double2 *)s->lob_psi.get(col * M);
-  double2 *HPsi = (double2 *)s->lob_hp.get(col * M);
-  double2 *SPsi = gen ? (double2 *)s->lob_sp.get(col * M) : Psi;
-  double2 *Z = (double2 *)s->lob_z.get(col * 3 * m);  // [X | W | P]
-  double2 *HZ = (double2 *)s->lob_hz.get(col * 3 * m);
-  double2 *SZ = gen ? (double2 *)s->lob_sz.get(col * 3 * m) : Z;
-  double2 *T1 = (double2 *)s->lob_t1.get(col * m);
-  double2 *T2 = (double2 *)s->lob_t2.get(col * m);
-  double2 *C = (double2 *)s->lob_c.get(sizeof(double2) * (size_t)std::max(3 * m * m, M * M));
-  // w: Ritz values of the last Rayleigh-Ritz (up to max(3m, M)), lam: current block's,
-  // resd: residual norms
-  double *w = (double *)s->lob_v.get(sizeof(double) * (size_t)(3 * M + 3 * m + 64));
-  double *lam = w + std::max(3 * m, M);
-  double *resd = lam + M;
-  launch_copy_block(npw, M, Psi_io, ldio, Psi, npw, st);
-  const size_t blk = (size_t)npw * m;
-  std::vector<double> hres(M);
-  auto rotate = [&](double2 *A, int64_t k) {
-    // P <- A[:, m:k] C[m:k, :], X <- A[:, 0:k] C
-    zgemm(OP_N, OP_N, npw, m, k - m, A + blk, npw, C + m, k, T1, npw, double2{1, 0},
-          double2{0, 0}, st);
-    zgemm(OP_N, OP_N, npw, m, k, A, npw, C, k, T2, npw, double2{1, 0}, double2{0, 0}, st);
-    launch_copy_block(npw, m, T2, npw, A, npw, st);
-    launch_copy_block(npw, m, T1, npw, A + 2 * blk, npw, st);
-  };
-  for (int i = 0; i < nblocks; ++i) {
-    double2 *X = Z, *HX = HZ, *SX = SZ;
-    double2 *W = Z + blk, *HW = HZ + blk, *SW = SZ + blk;
-    double2 *P = Z + 2 * blk, *HP = HZ + 2 * blk, *SP = SZ + 2 * blk;
-    launch_copy_block(npw, m, Psi + (size_t)i * blk, npw, X, npw, st);
-    s_deflate(s, Psi, (int64_t)i * m, X, SX, m, st);
-    apply_core(s, X, npw, nullptr, 0, HX, npw, m, 1.0, 0.0, 0.0, st);
-    if (gen) apply_S(s, X, npw, SX, npw, m, st);
-    if (!ortho_rr_basis(s, m, m, X, HX, SX, npw, w, C, st))
-      throw Error{ABI_ERR_NOT_HPD, "LOBPCG: block Gram matrix not positive definite"};
-    // X, HX (, SX) <- (.) C
-    double2 *rot1[3] = {X, HX, SX};
-    for (int r = 0; r < (gen ? 3 : 2); ++r) {
-      zgemm(OP_N, OP_N, npw, m, m, rot1[r], npw, C, m, T2, npw, double2{1, 0}, double2{0, 0}, st);
-      launch_copy_block(npw, m, T2, npw, rot1[r], npw, st);
-    }
-    CHEBFI_HIP(hipMemcpyAsync(lam, w, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
-    bool have_p = false;
-    int done = 0;
-    for (int n = 0; n < nline; ++n) {
-      launch_resid_block(npw, m, HX, SX, npw, lam, W, npw, resd, st);
-      CHEBFI_HIP(hipMemcpyAsync(hres.data(), resd, sizeof(double) * m, hipMemcpyDeviceToHost, st));
-      CHEBFI_HIP(hipStreamSynchronize(st));
-      double worst = 0.0;
-      for (int64_t j = 0; j < m; ++j) worst = std::max(worst, hres[j]);
-      if (worst <= tol) break;
-      launch_tpa(npw, m, s->d_kin, X, npw, W, npw, st);
-      s_deflate(s, Psi, (int64_t)i * m, W, SW, m, st);
-      apply_core(s, W, npw, nullptr, 0, HW, npw, m, 1.0, 0.0, 0.0, st);
-      if (gen) apply_S(s, W, npw, SW, npw, m, st);
-      launch_snorm_scale(npw, m, W, HW, gen ? SW : nullptr, npw, st);
-      int64_t k = 0;
-      if (have_p) {
-        launch_snorm_scale(npw, m, P, HP, gen ? SP : nullptr, npw, st);
-        if (ortho_rr_basis(s, 3 * m, m, Z, HZ, SZ, npw, w, C, st)) k = 3 * m;
-      }
-      if (k == 0) {
-        if (!ortho_rr_basis(s, 2 * m, m, Z, HZ, SZ, npw, w, C, st))
-          throw Error{ABI_ERR_NOT_HPD, "LOBPCG: Gram matrix of [Psi, W] not positive definite"};
-        k = 2 * m;
-      }
-      const int tok = s->prof.begin(PROF_ROT, 8.0 * (double)npw * m * (2 * k - m) * (gen ? 3 : 2),
-                                    st);
-      rotate(Z, k);
-      rotate(HZ, k);
-      if (gen) rotate(SZ, k);
-      s->prof.end(tok, st);
-      CHEBFI_HIP(hipMemcpyAsync(lam, w, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
-      have_p = true;
-      ++done;
-    }
-    launch_copy_block(npw, m, X, npw, Psi + (size_t)i * blk, npw, st);
-    launch_copy_block(npw, m, HX, npw, HPsi + (size_t)i * blk, npw, st);
-    if (gen) launch_copy_block(npw, m, SX, npw, SPsi + (size_t)i * blk, npw, st);
-    if (steps) steps[i] = done;
-  }
-  double2 *Wres = (double2 *)s->lob_t3.get(col * M);
-  if (nblocks > 1) {
-    // global S-ortho + Rayleigh-Ritz of all M bands
-    double2 *CM = (double2 *)s->lob_c.get(sizeof(double2) * (size_t)std::max(3 * m * m, M * M));
-    if (!ortho_rr_basis(s, M, M, Psi, HPsi, SPsi, npw, w, CM, st))
-      throw Error{ABI_ERR_NOT_HPD, "LOBPCG: global Gram matrix not positive definite"};
-    double2 *rot2[3] = {Psi, HPsi, SPsi};
-    for (int r = 0; r < (gen ? 3 : 2); ++r) {
-      zgemm(OP_N, OP_N, npw, M, M, rot2[r], npw, CM, M, Wres, npw, double2{1, 0}, double2{0, 0},
-            st);
-      launch_copy_block(npw, M, Wres, npw, rot2[r], npw, st);
-    }
-    CHEBFI_HIP(hipMemcpyAsync(lam, w, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
-  }
-  launch_resid_block(npw, M, HPsi, SPsi, npw, lam, Wres, npw, resd, st);
-  launch_copy_block(npw, M, Psi, npw, Psi_io, ldio, st);
-  CHEBFI_HIP(hipMemcpyAsync(eval, lam, sizeof(double) * M, hipMemcpyDeviceToHost, st));
-  CHEBFI_HIP(hipMemcpyAsync(res, resd, sizeof(double) * M, hipMemcpyDeviceToHost, st));
-  CHEBFI_HIP(hipStreamSynchronize(st));
-}
 
 }  // namespace
 
@@ -1350,19 +698,12 @@ abi_status abi_cheb_filter(abi_system s, const void *X, void *Y, int64_t nband, 
       const size_t nc = (size_t)s->nproj * nband;
       double2 *cbase = (double2 *)s->gen_c.get(3 * sizeof(double2) * nc);
       double2 *Cs[3] = {cbase, cbase + nc, cbase + 2 * nc};
-      if (dtype == ABI_C64)
-        project_c128_t<float>(s, X, ld, nband, Cs[0], st);
-      else
-        project_c128_t<double>(s, X, ld, nband, Cs[0], st);
+      project_c128(s, X, ld, nband, Cs[0], st, dtype);
       auto step = [&](const void *yk, int64_t ldk, const void *yp, int64_t ldp, void *out,
                       int64_t ldo, double al, double be, int j) {
         const double2 *cm1 = yp ? Cs[(j + 2) % 3] : nullptr;
-        if (dtype == ABI_C64)
-          gen_step_t<float>(s, yk, ldk, yp, ldp, out, ldo, nband, al, c, be, Cs[j % 3], cm1,
-                            Cs[(j + 1) % 3], st);
-        else
-          gen_step_t<double>(s, yk, ldk, yp, ldp, out, ldo, nband, al, c, be, Cs[j % 3], cm1,
-                             Cs[(j + 1) % 3], st);
+        gen_step(s, yk, ldk, yp, ldp, out, ldo, nband, al, c, be, Cs[j % 3], cm1,
+                 Cs[(j + 1) % 3], st, dtype);
       };
       step(X, ld, nullptr, 0, bufs[slot(1)], lds[slot(1)], s1 / e, 0.0, 0);
       double sk = s1;

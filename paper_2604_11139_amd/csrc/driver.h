@@ -1,0 +1,64 @@
+// Host-side drivers shared by the entry points (driver.cpp, lobpcg.cpp).
+#pragma once
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace chebfi {
+
+// Device copy of `count` host elements (allocation only when host is null);
+// throws ABI_ERR_NOMEM on allocation failure.
+template <typename T> inline T *upload(const T *host, size_t count) {
+  T *dev = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&dev, sizeof(T) * count) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{ABI_ERR_NOMEM, "hipMalloc failed during set_system"};
+  }
+  if (host) CHEBFI_HIP(hipMemcpy(dev, host, sizeof(T) * count, hipMemcpyHostToDevice));
+  return dev;
+}
+
+inline size_t elem_bytes(int32_t dtype) { return dtype == ABI_C64 ? sizeof(float2) : sizeof(double2); }
+
+// Out = alpha (H - cshift) X - beta Xprev (Xprev may be null).  dtype ABI_C128: FP64;
+// ABI_C64: complex64 blocks, FP32 FFT passes, split-BF16 MFMA projector products.
+// Craw (optional) receives the raw projections P^H X (nproj x nband, contiguous, in
+// the block's precision).
+void apply_core(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
+                void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
+                hipStream_t st, int32_t dtype = ABI_C128, void *Craw = nullptr);
+
+// Out = S X and Out = S^-1 X (copies of X when S = I); Out must not overlap X.
+void apply_S(abi_system_s *s, const void *X, int64_t ldx, void *Out, int64_t ldo, int64_t nband,
+             hipStream_t st, int32_t dtype = ABI_C128);
+void apply_Sinv(abi_system_s *s, const void *X, int64_t ldx, void *Out, int64_t ldo,
+                int64_t nband, hipStream_t st, int32_t dtype = ABI_C128);
+
+// One step of the filter on S^-1 H: Out = alpha (S^-1 H - cshift) X - beta Xprev and
+// Cnext = P^H Out, given Ck = P^H X and Ckm1 = P^H Xprev (complex double, nproj x nband;
+// Ckm1 null on the first step).
+void gen_step(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
+              void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
+              const double2 *Ck, const double2 *Ckm1, double2 *Cnext, hipStream_t st,
+              int32_t dtype);
+
+// C = P^H X in complex double (nproj x nband, contiguous).
+void project_c128(abi_system_s *s, const void *X, int64_t ldx, int64_t nband, double2 *C,
+                  hipStream_t st, int32_t dtype);
+
+// Overlap tables from Q (host, natom*16 complex): B = P^H P and the Woodbury kernel K.
+void setup_overlap(abi_system_s *s, const double *qij, hipStream_t st);
+
+// FP64 Rayleigh-Ritz on a complex128 block Y (in: filtered block, out: Psi).
+void rr_core(abi_system_s *s, double2 *Y, int64_t ld, double2 *HPsi, int64_t ldh_in, int64_t M,
+             double *eval, double *resnorm, void *coef, hipStream_t st);
+
+// One pass of block LOBPCG on Psi (npw x M, ld) in place (FP64); host eval, res (M)
+// and the line minimisations of each block (steps, nblocks entries, or null).
+void lobpcg_pass_core(abi_system_s *s, double2 *Psi_io, int64_t ldio, int64_t M, int nblocks,
+                      int nline, double tol, double *eval, double *res, int *steps,
+                      hipStream_t st);
+
+}  // namespace chebfi
