@@ -162,20 +162,80 @@ __global__ __launch_bounds__(256) void trtri_diag_kernel(int nb, double2 *__rest
 }
 
 // ------------------------------------------------------ tridiagonalisation --
-// Householder vector of column j below the diagonal (LAPACK-style larfg):
-// H^H (alpha, x) = (beta, 0), H = I - tau u u^H, u = (1, x/(alpha-beta)).
-__global__ __launch_bounds__(256) void house_kernel(int64_t m, double2 *__restrict__ A, int64_t lda, int64_t j,
-                             double *__restrict__ d, double *__restrict__ e,
-                             double2 *__restrict__ tau, double2 *__restrict__ u) {
+// Step j of the reduction uses the reflector H_j = I - tau_j u_j u_j^H of
+// column j (u_j[j+1] = 1, zero above), the product p_j = tau_j A22 u_j with the
+// trailing matrix A22 = A[j+1:, j+1:], a2_j = -tau_j (p_j^H u_j) / 2 and
+// w_j = p_j + a2_j u_j; the two-sided application is the rank-2 update
+// A22 -= u_j w_j^H + w_j u_j^H.  Each step is two launches: the rank-2 update
+// of step j-1 is applied lazily, to column j in tri_col_kernel and to the
+// columns right of it in tri_trail_kernel, which computes p_j from the updated
+// values in the same pass.  u and p alternate between two buffers.
+
+constexpr int kTriColThreads = 512;
+
+__device__ __forceinline__ double2 conj2(double2 a) { return double2{a.x, -a.y}; }
+
+// Column j, one workgroup.  For j >= 1: a2_{j-1} over rows j .. m-1, then
+// column j (rows j .. m-1) receives step j-1's rank-2 update.  For j <= m-2:
+// the Householder vector of column j below its subdiagonal (LAPACK-style
+// larfg: H^H (alpha, x) = (beta, 0) with beta real, u = (1, x / (alpha - beta)));
+// the scaled x is stored in A (the back-transformation reads it there) and in
+// ucur.  d[j] takes the updated diagonal.
+__global__ __launch_bounds__(kTriColThreads) void tri_col_kernel(
+    int64_t m, double2 *__restrict__ A, int64_t lda, int64_t j, const double2 *__restrict__ uprev,
+    const double2 *__restrict__ pprev, double2 *__restrict__ a2s, double *__restrict__ d,
+    double *__restrict__ e, double2 *__restrict__ tau, double2 *__restrict__ ucur) {
+  constexpr int NT = kTriColThreads, Q = (kEigMaxM + NT - 1) / NT;
+  static_assert(NT >= 64 && NT % 64 == 0, "whole waves");
   __shared__ double scratch[16];
+  __shared__ double2 sh_alpha;
+  const int tid = threadIdx.x;
   double2 *col = A + j * lda;
-  const double2 alpha = col[j + 1];
-  double s = 0;
-  for (int64_t i = j + 2 + threadIdx.x; i < m; i += blockDim.x) {
-    const double2 v = col[i];
-    s += v.x * v.x + v.y * v.y;
+  double2 c[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t r = j + tid + (int64_t)NT * q;
+    c[q] = r < m ? col[r] : double2{0.0, 0.0};
   }
-  const double xnorm2 = block_sum(s, scratch);
+  if (j >= 1) {
+    double sr = 0, si = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t r = j + tid + (int64_t)NT * q;
+      if (r < m) {
+        const double2 pv = pprev[r], uv = uprev[r];
+        sr += pv.x * uv.x + pv.y * uv.y;  // conj(p) u
+        si += pv.x * uv.y - pv.y * uv.x;
+      }
+    }
+    sr = block_sum(sr, scratch);
+    si = block_sum(si, scratch);
+    const double2 a2 = cscale(cmul(tau[j - 1], double2{sr, si}), -0.5);
+    const double2 uj = uprev[j];
+    const double2 cwj = conj2(cadd(pprev[j], cmul(a2, uj))), cuj = conj2(uj);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t r = j + tid + (int64_t)NT * q;
+      if (r < m) {
+        const double2 ur = uprev[r], wr = cadd(pprev[r], cmul(a2, ur));
+        c[q] = csub(c[q], cadd(cmul(ur, cwj), cmul(wr, cuj)));
+      }
+    }
+    if (tid == 0) a2s[j - 1] = a2;
+  }
+  if (j + 1 >= m) {
+    if (tid == 0) d[j] = c[0].x;
+    return;
+  }
+  if (tid == 1) sh_alpha = c[0];  // row j + 1
+  double s = 0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t r = j + tid + (int64_t)NT * q;
+    if (r >= j + 2 && r < m) s += c[q].x * c[q].x + c[q].y * c[q].y;
+  }
+  const double xnorm2 = block_sum(s, scratch);  // its barriers also publish sh_alpha
+  const double2 alpha = sh_alpha;
   double beta, tr, ti;
   double2 scal{0, 0};
   if (xnorm2 == 0.0 && alpha.y == 0.0) {
@@ -191,87 +251,58 @@ __global__ __launch_bounds__(256) void house_kernel(int64_t m, double2 *__restri
     const double dd = den.x * den.x + den.y * den.y;
     scal = double2{den.x / dd, -den.y / dd};
   }
-  for (int64_t i = j + 2 + threadIdx.x; i < m; i += blockDim.x) {
-    const double2 v = cmul(col[i], scal);
-    col[i] = v;
-    u[i] = v;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t r = j + tid + (int64_t)NT * q;
+    if (r >= j + 2 && r < m) {
+      const double2 v = cmul(c[q], scal);
+      col[r] = v;
+      ucur[r] = v;
+    }
   }
-  if (threadIdx.x == 0) {
-    u[j + 1] = double2{1.0, 0.0};
-    d[j] = col[j].x;
+  if (tid == 0) {
+    ucur[j + 1] = double2{1.0, 0.0};
+    d[j] = c[0].x;
     e[j] = beta;
     tau[j] = double2{tr, ti};
   }
 }
 
-// part[ks][i] = sum_{k in chunk ks} A22[i][k] u[k]   (A22 = A[j+1:, j+1:])
-__global__ __launch_bounds__(256) void hemv_part_kernel(int64_t m, const double2 *__restrict__ A, int64_t lda, int64_t j,
-                                 const double2 *__restrict__ u, int64_t kchunk,
-                                 double2 *__restrict__ part) {
-  const int64_t L = m - j - 1;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t ks = blockIdx.y;
-  const int64_t k0 = ks * kchunk, k1 = (k0 + kchunk < L) ? k0 + kchunk : L;
-  if (i >= L) return;
-  const double2 *a = A + (j + 1) + (j + 1) * lda;
-  double2 s{0, 0};
-  for (int64_t k = k0; k < k1; ++k) s = cadd(s, cmul(a[i + k * lda], u[j + 1 + k]));
-  part[ks * L + i] = s;
-}
-
-// p = tau sum_ks part (many workgroups)
-__global__ __launch_bounds__(256) void hemv_reduce_kernel(int64_t m, int64_t j,
-                                                          const double2 *__restrict__ part, int ksn,
-                                                          const double2 *__restrict__ tau,
-                                                          double2 *__restrict__ p) {
-  const int64_t L = m - j - 1;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= L) return;
-  double2 v{0, 0};
-  for (int ks = 0; ks < ksn; ++ks) v = cadd(v, part[(int64_t)ks * L + i]);
-  p[j + 1 + i] = cmul(tau[j], v);
-}
-
-// a2 = -0.5 tau (p^H u)   (one workgroup); w = p + a2 u is formed inside her2
-__global__ __launch_bounds__(256) void hemv_dot_kernel(int64_t m, int64_t j,
-                                                       const double2 *__restrict__ p,
-                                                       const double2 *__restrict__ tau,
-                                                       const double2 *__restrict__ u,
-                                                       double2 *__restrict__ a2) {
+// Columns j+1 .. m-1, one workgroup per column: for j >= 1, rows j+1 .. m-1
+// of the column receive step j-1's rank-2 update and are stored; p_j[i] =
+// tau_j times the conjugated (updated) column i dotted with u_j, which is row i
+// of A22 u_j because A22 is Hermitian.  Row j of these columns is not
+// updated: no later step reads it.
+__global__ __launch_bounds__(256) void tri_trail_kernel(
+    int64_t m, double2 *__restrict__ A, int64_t lda, int64_t j, const double2 *__restrict__ uprev,
+    const double2 *__restrict__ pprev, const double2 *__restrict__ a2s,
+    const double2 *__restrict__ ucur, const double2 *__restrict__ tau, double2 *__restrict__ pcur) {
   __shared__ double scratch[16];
-  const int64_t L = m - j - 1;
+  const int64_t ci = j + 1 + (int64_t)blockIdx.x;
+  double2 *col = A + ci * lda;
+  const bool upd = j >= 1;
+  double2 a2{0, 0}, cwi{0, 0}, cui{0, 0};
+  if (upd) {
+    a2 = a2s[j - 1];
+    const double2 ui = uprev[ci];
+    cwi = conj2(cadd(pprev[ci], cmul(a2, ui)));
+    cui = conj2(ui);
+  }
   double sr = 0, si = 0;
-  for (int64_t i = threadIdx.x; i < L; i += blockDim.x) {
-    const double2 pv = p[j + 1 + i], uv = u[j + 1 + i];
-    sr += pv.x * uv.x + pv.y * uv.y;  // conj(p) u
-    si += pv.x * uv.y - pv.y * uv.x;
+  for (int64_t r = j + 1 + threadIdx.x; r < m; r += blockDim.x) {
+    double2 a = col[r];
+    if (upd) {
+      const double2 ur = uprev[r], wr = cadd(pprev[r], cmul(a2, ur));
+      a = csub(a, cadd(cmul(ur, cwi), cmul(wr, cui)));
+      col[r] = a;
+    }
+    const double2 v = ucur[r];
+    sr += a.x * v.x + a.y * v.y;  // conj(a) v
+    si += a.x * v.y - a.y * v.x;
   }
   sr = block_sum(sr, scratch);
   si = block_sum(si, scratch);
-  if (threadIdx.x == 0) *a2 = cscale(cmul(tau[j], double2{sr, si}), -0.5);
-}
-
-// A22 -= u w^H + w u^H with w = p + a2 u
-__global__ __launch_bounds__(256) void her2_kernel(int64_t m, double2 *__restrict__ A, int64_t lda,
-                                                   int64_t j, const double2 *__restrict__ u,
-                                                   const double2 *__restrict__ p,
-                                                   const double2 *__restrict__ a2p) {
-  const int64_t L = m - j - 1;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t k = blockIdx.y;
-  if (i >= L || k >= L) return;
-  const double2 a2 = *a2p;
-  const double2 ui = u[j + 1 + i], uk = u[j + 1 + k];
-  const double2 wi = cadd(p[j + 1 + i], cmul(a2, ui));
-  const double2 wk = cadd(p[j + 1 + k], cmul(a2, uk));
-  const double2 cwk{wk.x, -wk.y}, cuk{uk.x, -uk.y};
-  double2 *q = A + (j + 1 + i) + (j + 1 + k) * lda;
-  *q = csub(*q, cadd(cmul(ui, cwk), cmul(wi, cuk)));
-}
-
-__global__ void last_diag_kernel(int64_t m, const double2 *__restrict__ A, int64_t lda,
-                                 double *__restrict__ d) {
-  if (threadIdx.x == 0) d[m - 1] = A[(m - 1) + (m - 1) * lda].x;
+  if (threadIdx.x == 0) pcur[ci] = cmul(tau[j], double2{sr, si});
 }
 
 // ---------------------------------------------------------------- bisection --
@@ -325,23 +356,36 @@ __global__ __launch_bounds__(256) void tri_prep_kernel(int64_t m, const double *
   }
 }
 
-__global__ __launch_bounds__(64) void bisect_kernel(int64_t m, const double *__restrict__ d, const double *__restrict__ e2,
-                              const double *__restrict__ stats, double *__restrict__ w) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
+// Eigenvalue i (ascending) by multisection: one wave per eigenvalue, its 64
+// lanes take Sturm counts at 64 interior points of the bracket [lo, hi], which
+// shrinks to the sub-interval where the count first reaches i + 1 (65 times
+// narrower per round), until it is below the tolerance or no representable
+// point is left inside.
+__global__ __launch_bounds__(256) void bisect_kernel(int64_t m, const double *__restrict__ d,
+                                                     const double *__restrict__ e2,
+                                                     const double *__restrict__ stats,
+                                                     double *__restrict__ w) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= m) return;  // uniform per wave
   double lo = stats[0], hi = stats[1];
   const double pivmin = stats[3];
   const double tol = 2.0 * DBL_EPSILON * stats[2];
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
+  for (int it = 0; it < 64; ++it) {
     if (hi - lo <= tol) break;
-    if (sturm_less(m, d, e2, mid, pivmin) >= i + 1)
-      hi = mid;
-    else
-      lo = mid;
+    const double x = lo + (hi - lo) * ((double)(lane + 1) * (1.0 / 65.0));
+    const bool inside = x > lo && x < hi;
+    if (__ballot(inside) == 0ull) break;
+    const bool above = inside ? sturm_less(m, d, e2, x, pivmin) >= i + 1 : x >= hi;
+    const unsigned long long mask = __ballot(above);
+    const int k = mask ? __ffsll((long long)mask) - 1 : 64;
+    const double xk = __shfl(x, k < 64 ? k : 63, 64), xk1 = __shfl(x, k > 0 ? k - 1 : 0, 64);
+    const double nlo = k == 0 ? lo : xk1;
+    const double nhi = k == 64 ? hi : xk;
+    lo = nlo;
+    hi = nhi;
   }
-  w[i] = 0.5 * (lo + hi);
+  if (lane == 0) w[i] = 0.5 * (lo + hi);
 }
 
 // ------------------------------------------------------- inverse iteration --
@@ -554,21 +598,30 @@ __global__ __launch_bounds__(256) void build_v_kernel(int64_t m, const double2 *
 // Upper triangular T with H_{j0} H_{j0+1} ... H_{j0+nb-1} = I - V T V^H (forward
 // accumulation of the block reflector), from G = V^H V: T[k][k] = tau_k and
 // T[i][k] = -tau_k sum_{l=i}^{k-1} T[i][l] G[l][k].  Thread i owns row i.
-__global__ void larft_kernel(int nb, const double2 *__restrict__ G, const double2 *__restrict__ tau,
-                             double2 *__restrict__ T) {
+__global__ __launch_bounds__(64) void larft_kernel(int nb, const double2 *__restrict__ G,
+                                                   const double2 *__restrict__ tau,
+                                                   double2 *__restrict__ T) {
+  // row i of T depends only on row i and G: thread i runs its row's
+  // recurrence with G and its row held in LDS (column-major, conflict-free)
+  __shared__ double2 Gs[kBtBlock * kBtBlock];
+  __shared__ double2 Ts[kBtBlock * kBtBlock];
   const int i = threadIdx.x;
-  if (i >= nb) return;
-  for (int k = 0; k < nb; ++k) T[i + k * nb] = double2{0.0, 0.0};
-  for (int k = i; k < nb; ++k) {
-    if (k == i) {
-      T[i + k * nb] = tau[k];
-      continue;
-    }
-    double2 acc{0.0, 0.0};
-    for (int l = i; l < k; ++l) acc = cadd(acc, cmul(T[i + l * nb], G[l + k * nb]));
-    const double2 t = cmul(tau[k], acc);
-    T[i + k * nb] = double2{-t.x, -t.y};
+  for (int idx = i; idx < nb * nb; idx += blockDim.x) {
+    Gs[idx] = G[idx];
+    Ts[idx] = double2{0.0, 0.0};
   }
+  __syncthreads();
+  if (i < nb) {
+    Ts[i + i * nb] = tau[i];
+    for (int k = i + 1; k < nb; ++k) {
+      double2 acc{0.0, 0.0};
+      for (int l = i; l < k; ++l) acc = cadd(acc, cmul(Ts[i + l * nb], Gs[l + k * nb]));
+      const double2 t = cmul(tau[k], acc);
+      Ts[i + k * nb] = double2{-t.x, -t.y};
+    }
+  }
+  __syncthreads();
+  for (int idx = i; idx < nb * nb; idx += blockDim.x) T[idx] = Ts[idx];
 }
 
 }  // namespace
@@ -617,11 +670,12 @@ void ztrtri_upper(int64_t m, void *Av, int64_t lda, void *work, hipStream_t st) 
 }
 
 size_t zheev_work_bytes(int64_t m) {
-  // d, e, e2, w-tmp, stats, tau, u, wv, wrow, hemv parts, S (real m x m), and the
-  // blocked back-transformation's V (m x nb), G, T (nb x nb), W1, W2 (nb x m)
-  const size_t ks = 64, nb = kBtBlock;
-  return sizeof(double) * (size_t)(4 * m + 8) + sizeof(double2) * (size_t)(4 * m) +
-         sizeof(double2) * ks * (size_t)m + sizeof(double) * (size_t)m * m +
+  // d, e, e2, w-tmp, stats, tau, u, wrow, two u and two p buffers, a2, S (real
+  // m x m), and the blocked back-transformation's V (m x nb), G, T (nb x nb),
+  // W1, W2 (nb x m)
+  const size_t nb = kBtBlock;
+  return sizeof(double) * (size_t)(4 * m + 8) + sizeof(double2) * (size_t)(8 * m) +
+         sizeof(double) * (size_t)m * m +
          sizeof(double2) * ((3 + kBtSplits) * nb * (size_t)m + 2 * nb * nb) +
          24 * 256;  // each of the 16 sub-buffers is rounded up to 256 bytes
 }
@@ -643,37 +697,27 @@ void zheev(int64_t m, void *Av, int64_t lda, double *wout, void *Zv, int64_t ldz
   double *stats = (double *)take(sizeof(double) * 8);
   double2 *tau = (double2 *)take(sizeof(double2) * m);
   double2 *u = (double2 *)take(sizeof(double2) * m);
-  double2 *wv = (double2 *)take(sizeof(double2) * m);
   double2 *wrow = (double2 *)take(sizeof(double2) * m);
-  const int ks_max = 64;
-  double2 *part = (double2 *)take(sizeof(double2) * (size_t)ks_max * m);
+  double2 *ub = (double2 *)take(sizeof(double2) * 2 * m);
+  double2 *pb = (double2 *)take(sizeof(double2) * 2 * m);
+  double2 *a2s = (double2 *)take(sizeof(double2) * m);
   double *S = (double *)take(sizeof(double) * (size_t)m * m);
 
   launch_hermitize(m, A, lda, st);
-  // reduction to tridiagonal form
-  for (int64_t j = 0; j + 1 < m; ++j) {
+  // reduction to tridiagonal form: two launches per column, then the last diagonal
+  for (int64_t j = 0; j < m; ++j) {
+    const int cur = (int)(j & 1), prev = cur ^ 1;
+    hipLaunchKernelGGL(tri_col_kernel, dim3(1), dim3(kTriColThreads), 0, st, m, A, lda, j,
+                       ub + prev * m, pb + prev * m, a2s, d, e, tau, ub + cur * m);
     const int64_t L = m - j - 1;
-    hipLaunchKernelGGL(house_kernel, dim3(1), dim3(256), 0, st, m, A, lda, j, d, e, tau, u);
-    const int64_t rb = (L + 255) / 256;
-    int ks = (int)std::min<int64_t>(ks_max, std::max<int64_t>(1, 512 / rb));
-    int64_t kchunk = (L + ks - 1) / ks;
-    if (kchunk < 16) {
-      kchunk = 16;
-      ks = (int)((L + kchunk - 1) / kchunk);
-    }
-    hipLaunchKernelGGL(hemv_part_kernel, dim3((unsigned)rb, (unsigned)ks), dim3(256), 0, st, m, A,
-                       lda, j, u, kchunk, part);
-    hipLaunchKernelGGL(hemv_reduce_kernel, dim3((unsigned)rb), dim3(256), 0, st, m, j, part, ks,
-                       tau, wv);
-    hipLaunchKernelGGL(hemv_dot_kernel, dim3(1), dim3(256), 0, st, m, j, wv, tau, u, wrow);
-    hipLaunchKernelGGL(her2_kernel, dim3((unsigned)rb, (unsigned)L), dim3(256), 0, st, m, A, lda, j,
-                       u, wv, wrow);
+    if (L > 0)
+      hipLaunchKernelGGL(tri_trail_kernel, dim3((unsigned)L), dim3(256), 0, st, m, A, lda, j,
+                         ub + prev * m, pb + prev * m, a2s, ub + cur * m, tau, pb + cur * m);
   }
   CHEBFI_HIP(hipGetLastError());
-  hipLaunchKernelGGL(last_diag_kernel, dim3(1), dim3(64), 0, st, m, A, lda, d);
   // eigenvalues of the tridiagonal
   hipLaunchKernelGGL(tri_prep_kernel, dim3(1), dim3(256), 0, st, m, d, e, e2, stats);
-  hipLaunchKernelGGL(bisect_kernel, dim3(nblk(m, 64)), dim3(64), 0, st, m, d, e2, stats, wout);
+  hipLaunchKernelGGL(bisect_kernel, dim3(nblk(m, 4)), dim3(256), 0, st, m, d, e2, stats, wout);
   CHEBFI_HIP(hipGetLastError());
   // eigenvectors of the tridiagonal
   const size_t lds_bytes = sizeof(double) * 7 * (size_t)m + (size_t)m + 64;
