@@ -398,6 +398,15 @@ __device__ __forceinline__ double hash_uniform(uint64_t a, uint64_t b) {
   return ((double)(z >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
 }
 
+// Value of a wave-uniform lane k (k a compile-time constant in the unrolled
+// sequential loops below).
+__device__ __forceinline__ double lane_val(double v, int k) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, k);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // One workgroup per cluster of eigenvalues closer than `gaptol`; the group
 // leader (first index of the cluster) computes all members in order.
 // S (m x m, real, column-major, lds) receives the tridiagonal eigenvectors.
@@ -414,13 +423,14 @@ __global__ __launch_bounds__(256) void invit_kernel(int64_t m, const double *__r
 
   double *sd = reinterpret_cast<double *>(smem_raw);
   double *se = sd + m;
-  double *ud = se + m;   // U diagonal
-  double *u1 = ud + m;   // first superdiagonal
+  double *rud = se + m;  // reciprocals of U's diagonal
+  double *u1 = rud + m;  // first superdiagonal
   double *u2 = u1 + m;   // second superdiagonal
   double *lm = u2 + m;   // multipliers
   double *x = lm + m;
   unsigned char *swp = reinterpret_cast<unsigned char *>(x + m);
   __shared__ double scratch[16];
+  __shared__ int sh_idx[16];
   __shared__ double sh_coef;
 
   for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
@@ -435,53 +445,97 @@ __global__ __launch_bounds__(256) void invit_kernel(int64_t m, const double *__r
     double shift = w[q];
     if (q > c0 && shift - shift_prev < pert) shift = shift_prev + pert;
     shift_prev = shift;
-    // LU with partial pivoting of T - shift I (thread 0, sequential)
-    if (threadIdx.x == 0) {
+    // LU with partial pivoting of T - shift I.  The recurrence is sequential:
+    // wave 0 loads the operands of 64 steps at once (one per lane), runs the
+    // 64 steps on lane-broadcast values in registers, and lane k keeps the
+    // factors of step k; the reciprocal pivots follow in a parallel pass.
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
       double a = sd[0] - shift;
       double cc = (m > 1) ? se[0] : 0.0;  // current superdiagonal of row i
-      for (int64_t i = 0; i < m - 1; ++i) {
-        const double b = se[i];               // subdiagonal (row i+1, col i)
-        const double an = sd[i + 1] - shift;  // diagonal of row i+1
-        const double cn = (i + 1 < m - 1) ? se[i + 1] : 0.0;
-        if (fabs(a) >= fabs(b)) {
-          const double l = (a != 0.0) ? b / a : 0.0;
-          ud[i] = a;
-          u1[i] = cc;
-          u2[i] = 0.0;
-          lm[i] = l;
-          swp[i] = 0;
-          a = an - l * cc;
-          cc = cn;
-        } else {
-          const double l = a / b;
-          ud[i] = b;
-          u1[i] = an;
-          u2[i] = cn;
-          lm[i] = l;
-          swp[i] = 1;
-          a = cc - l * an;
-          cc = -l * cn;
+      for (int64_t i0 = 0; i0 < m - 1; i0 += 64) {
+        const int64_t ii = i0 + lane;
+        const double Bv = (ii < m - 1) ? se[ii] : 0.0;        // subdiagonal (row i+1, col i)
+        const double Dv = (ii + 1 < m) ? sd[ii + 1] : 0.0;    // diagonal of row i+1
+        const double Ev = (ii + 1 < m - 1) ? se[ii + 1] : 0.0;  // superdiagonal of row i+1
+        double P = 0.0, Lo = 0.0, V1 = 0.0, V2 = 0.0;
+        int SW = 0;
+#pragma unroll
+        for (int k = 0; k < 64; ++k) {
+          if (i0 + k >= m - 1) break;
+          const double b = lane_val(Bv, k), an = lane_val(Dv, k) - shift, cn = lane_val(Ev, k);
+          const bool keep = fabs(a) >= fabs(b);
+          const double num = keep ? b : a, den = keep ? a : b;
+          const double l = (den != 0.0) ? num / den : 0.0;
+          const double na = keep ? an - l * cc : cc - l * an;
+          const double ncc = keep ? cn : -l * cn;
+          if (lane == k) {
+            P = den;
+            Lo = l;
+            V1 = keep ? cc : an;
+            V2 = keep ? 0.0 : cn;
+            SW = keep ? 0 : 1;
+          }
+          a = na;
+          cc = ncc;
         }
-        if (fabs(ud[i]) < tiny) ud[i] = (ud[i] < 0.0) ? -tiny : tiny;
+        if (ii < m - 1) {
+          rud[ii] = (fabs(P) < tiny) ? ((P < 0.0) ? -tiny : tiny) : P;
+          lm[ii] = Lo;
+          u1[ii] = V1;
+          u2[ii] = V2;
+          swp[ii] = (unsigned char)SW;
+        }
       }
-      ud[m - 1] = (fabs(a) < tiny) ? ((a < 0.0) ? -tiny : tiny) : a;
+      if (lane == 0) rud[m - 1] = (fabs(a) < tiny) ? ((a < 0.0) ? -tiny : tiny) : a;
     }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) rud[i] = 1.0 / rud[i];
     for (int64_t i = threadIdx.x; i < m; i += blockDim.x) x[i] = hash_uniform(q, i);
     __syncthreads();
     for (int it = 0; it < 3; ++it) {
-      if (threadIdx.x == 0) {
-        for (int64_t i = 0; i < m - 1; ++i) {
-          if (swp[i]) {
-            const double t = x[i];
-            x[i] = x[i + 1];
-            x[i + 1] = t;
+      if (threadIdx.x < 64) {
+        // forward: row swaps and L, 64 steps per block as in the factorisation
+        // (each block reads x[i0+1 .. i0+64] before writing x[i0 .. i0+63])
+        const int lane = threadIdx.x;
+        double cur = x[0];
+        for (int64_t i0 = 0; i0 < m - 1; i0 += 64) {
+          const int64_t ii = i0 + lane;
+          const double Xv = (ii + 1 < m) ? x[ii + 1] : 0.0;
+          const double Lv = (ii < m - 1) ? lm[ii] : 0.0;
+          const int Sv = (ii < m - 1) ? (int)swp[ii] : 0;
+          double out = 0.0;
+#pragma unroll
+          for (int k = 0; k < 64; ++k) {
+            if (i0 + k >= m - 1) break;
+            const double nx = lane_val(Xv, k), l = lane_val(Lv, k);
+            const bool sw = __builtin_amdgcn_readlane(Sv, k) != 0;
+            const double c = sw ? nx : cur;
+            const double n = (sw ? cur : nx) - l * c;
+            if (lane == k) out = c;
+            cur = n;
           }
-          x[i + 1] -= lm[i] * x[i];
+          if (ii < m - 1) x[ii] = out;
         }
-        x[m - 1] = x[m - 1] / ud[m - 1];
-        if (m > 1) x[m - 2] = (x[m - 2] - u1[m - 2] * x[m - 1]) / ud[m - 2];
-        for (int64_t i = m - 3; i >= 0; --i)
-          x[i] = (x[i] - u1[i] * x[i + 1] - u2[i] * x[i + 2]) / ud[i];
+        // backward: U with the reciprocal pivots, 64 rows per block from the bottom
+        double x1 = cur * rud[m - 1], x2 = 0.0;
+        if (lane == 0) x[m - 1] = x1;
+        for (int64_t i1 = m - 2; i1 >= 0; i1 -= 64) {
+          const int64_t ii = i1 - lane;
+          const double Xv = (ii >= 0) ? x[ii] : 0.0, U1 = (ii >= 0) ? u1[ii] : 0.0;
+          const double U2 = (ii >= 0) ? u2[ii] : 0.0, Rv = (ii >= 0) ? rud[ii] : 0.0;
+          double out = 0.0;
+#pragma unroll
+          for (int k = 0; k < 64; ++k) {
+            if (i1 - k < 0) break;
+            const double x0 =
+                (lane_val(Xv, k) - lane_val(U1, k) * x1 - lane_val(U2, k) * x2) * lane_val(Rv, k);
+            if (lane == k) out = x0;
+            x2 = x1;
+            x1 = x0;
+          }
+          if (ii >= 0) x[ii] = out;
+        }
       }
       __syncthreads();
       // scale to avoid overflow, then MGS against earlier members of the cluster
@@ -515,16 +569,39 @@ __global__ __launch_bounds__(256) void invit_kernel(int64_t m, const double *__r
       for (int64_t i = threadIdx.x; i < m; i += blockDim.x) x[i] *= invn;
       __syncthreads();
     }
-    // sign: largest-magnitude component (first on ties) made positive
-    if (threadIdx.x == 0) {
-      int64_t jm = 0;
-      double best = -1;
-      for (int64_t i = 0; i < m; ++i)
+    // sign: largest-magnitude component (first on ties) made positive; the
+    // first index of the maximum is found by a block reduction
+    {
+      double best = -1.0;
+      int64_t bi = m;
+      for (int64_t i = threadIdx.x; i < m; i += blockDim.x)
         if (fabs(x[i]) > best) {
           best = fabs(x[i]);
-          jm = i;
+          bi = i;
         }
-      sh_coef = (x[jm] < 0) ? -1.0 : 1.0;
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int64_t oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if ((threadIdx.x & 63) == 0) {
+        scratch[threadIdx.x >> 6] = best;
+        sh_idx[threadIdx.x >> 6] = (int)bi;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double b0 = scratch[0];
+        int i0 = sh_idx[0];
+        for (int wv = 1; wv < (int)((blockDim.x + 63) >> 6); ++wv)
+          if (scratch[wv] > b0 || (scratch[wv] == b0 && sh_idx[wv] < i0)) {
+            b0 = scratch[wv];
+            i0 = sh_idx[wv];
+          }
+        sh_coef = (x[i0] < 0) ? -1.0 : 1.0;
+      }
     }
     __syncthreads();
     const double sg = sh_coef;

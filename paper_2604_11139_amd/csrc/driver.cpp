@@ -407,13 +407,12 @@ void rr_core(abi_system_s *s, double2 *Y, int64_t ld, double2 *HPsi, int64_t ldh
     launch_copy_block(npw, M, Y, ld, SY, lds, st);
     expand_t<double>(s, QC, SY, lds, M, st);
   }
-  int splits = zgemm_splits(M, M, npw);
+  // both products are Hermitian: only the tiles on and above the diagonal are formed
+  const int splits = zgemm_herm_splits(M, npw);
   void *part = s->cpart.get(sizeof(double2) * (size_t)splits * M * M);
   const double gflops = 8.0 * (double)M * M * npw;
   int tok = s->prof.begin(PROF_GRAM, gflops, st);
-  zgemm(OP_C, OP_N, M, M, npw, Y, ld, SY, lds, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
-        splits);
-  zsum_parts(M, M, part, splits, G, M, double2{1, 0}, double2{0, 0}, st);
+  zgemm_herm(M, npw, Y, ld, SY, lds, G, M, st, part, splits);
   s->prof.end(tok, st);
   launch_hermitize(M, G, M, st);
   tok = s->prof.begin(PROF_CHOL, 4.0 / 3.0 * (double)M * M * M, st);
@@ -430,9 +429,7 @@ void rr_core(abi_system_s *s, double2 *Y, int64_t ld, double2 *HPsi, int64_t ldh
   apply_core(s, Y, ld, nullptr, 0, HY, npw, M, 1.0, 0.0, 0.0, st);
   part = s->cpart.get(sizeof(double2) * (size_t)splits * M * M);  // apply_core may regrow it
   tok = s->prof.begin(PROF_GRAM, gflops, st);
-  zgemm(OP_C, OP_N, M, M, npw, Y, ld, HY, npw, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
-        splits);
-  zsum_parts(M, M, part, splits, Hs, M, double2{1, 0}, double2{0, 0}, st);
+  zgemm_herm(M, npw, Y, ld, HY, npw, Hs, M, st, part, splits);
   s->prof.end(tok, st);
   launch_hermitize(M, Hs, M, st);
   // U^-1 and the reduced matrix U^-H H_s U^-1

@@ -41,9 +41,21 @@ template <> struct Mma<float> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
+// Tile (ti, tj), ti <= tj, of the t-th upper-triangle tile in column order
+// (t = tj (tj + 1) / 2 + ti).
+__device__ __forceinline__ void upper_tile(int64_t t, int64_t &ti, int64_t &tj) {
+  int64_t j = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((j + 1) * (j + 2) / 2 <= t) ++j;
+  while (j * (j + 1) / 2 > t) --j;
+  tj = j;
+  ti = t - j * (j + 1) / 2;
+}
+
 // TAG only separates instantiations (1 = projector products of the H
 // application) so that kernel traces report them apart from the dense ones.
-template <typename T, int OPA, int OPB, bool SPLIT, int TAG>
+// TRI: square product known to be Hermitian; the 1-D grid enumerates only the
+// tiles on and above the diagonal (the split-K sum mirrors the rest).
+template <typename T, int OPA, int OPB, bool SPLIT, int TAG, bool TRI = false>
 __global__ __launch_bounds__(256) void zgemm_kernel(int64_t m, int64_t n, int64_t k,
                                                     const C2<T> *__restrict__ A, int64_t lda,
                                                     const C2<T> *__restrict__ B, int64_t ldb,
@@ -57,7 +69,14 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int64_t m, int64_t n, int64_
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  const int64_t row0 = (int64_t)blockIdx.x * BM, col0 = (int64_t)blockIdx.y * BN;
+  int64_t row0 = (int64_t)blockIdx.x * BM, col0 = (int64_t)blockIdx.y * BN;
+  if constexpr (TRI) {
+    static_assert(BM == BN, "square tiles");
+    int64_t ti, tj;
+    upper_tile(blockIdx.x, ti, tj);
+    row0 = ti * BM;
+    col0 = tj * BN;
+  }
   const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
   const int64_t kend = (kbeg + kchunk < k) ? kbeg + kchunk : k;
 
@@ -192,6 +211,36 @@ __global__ void zsum_parts_kernel(int64_t m, int64_t n, const double2 *__restric
   C[row + col * ldc] = o;
 }
 
+// Hermitian split-K sum: 32 x 32 blocks (bi <= bj) of the m x m parts are
+// summed and written, and their conjugate transposes written to (bj, bi)
+// through LDS, so that C is exactly Hermitian and only parts of tiles on and
+// above the diagonal are read.
+__global__ __launch_bounds__(256) void zsum_herm_kernel(int64_t m, const double2 *__restrict__ part,
+                                                        int splits, double2 *__restrict__ C,
+                                                        int64_t ldc) {
+  __shared__ double2 t[32][33];
+  int64_t bi, bj;
+  upper_tile(blockIdx.x, bi, bj);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int c = ty; c < 32; c += 8) {
+    const int64_t row = bi * 32 + tx, col = bj * 32 + c;
+    double2 v{0, 0};
+    if (row < m && col < m) {
+      for (int z = 0; z < splits; ++z) v = cadd(v, part[(int64_t)z * m * m + row + col * m]);
+      if (bi < bj || tx <= c) C[row + col * ldc] = v;
+    }
+    t[c][tx] = v;  // element (bi*32 + tx, bj*32 + c)
+  }
+  __syncthreads();
+  for (int c = ty; c < 32; c += 8) {
+    const int64_t row = bj * 32 + tx, col = bi * 32 + c;  // mirror of (col, row)
+    if (row < m && col < m && (bi < bj || tx > c)) {
+      const double2 v = t[tx][c];
+      C[row + col * ldc] = double2{v.x, -v.y};
+    }
+  }
+}
+
 template <typename T, int OPA, int OPB, int TAG>
 void launch_t(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
               int64_t ldb, void *C, int64_t ldc, double2 alpha, double2 beta, hipStream_t st,
@@ -252,6 +301,28 @@ static int best_splits(int64_t tiles, int64_t kmax, int per_cu) {
     if (wgs >= 8 * slots) break;
   }
   return (int)best;
+}
+
+int zgemm_herm_splits(int64_t m, int64_t k) {
+  const int64_t nt = (m + BM - 1) / BM;
+  return best_splits(nt * (nt + 1) / 2, (k + 511) / 512, 2);
+}
+
+void zgemm_herm(int64_t m, int64_t k, const void *A, int64_t lda, const void *B, int64_t ldb,
+                void *C, int64_t ldc, hipStream_t st, void *part, int splits) {
+  if (m <= 0) return;
+  CHEBFI_REQUIRE(part != nullptr && splits >= 1, ABI_ERR_ARG, "Hermitian product needs parts");
+  const int64_t nt = (m + BM - 1) / BM;
+  const int64_t chunk = ((k + splits - 1) / splits + BK - 1) / BK * BK;
+  hipLaunchKernelGGL((zgemm_kernel<double, OP_C, OP_N, true, 0, true>),
+                     dim3((unsigned)(nt * (nt + 1) / 2), 1, (unsigned)splits), dim3(256), 0, st, m,
+                     m, k, (const double2 *)A, lda, (const double2 *)B, ldb, (double2 *)nullptr,
+                     (int64_t)0, double2{1, 0}, double2{0, 0}, chunk, (double2 *)part);
+  CHEBFI_HIP(hipGetLastError());
+  const int64_t nb = (m + 31) / 32;
+  hipLaunchKernelGGL(zsum_herm_kernel, dim3((unsigned)(nb * (nb + 1) / 2)), dim3(256), 0, st, m,
+                     (const double2 *)part, splits, (double2 *)C, ldc);
+  CHEBFI_HIP(hipGetLastError());
 }
 
 int zgemm_splits(int64_t m, int64_t n, int64_t k) {

@@ -87,6 +87,12 @@ void expand_gemv(int64_t npw, int nproj, const void *P, const void *c, void *out
 
 // Number of K splits that fills the chip for an m x n output.
 int zgemm_splits(int64_t m, int64_t n, int64_t k);
+// C (m x m, ldc) = A^H B for a product known to be Hermitian (Gram matrices):
+// only the 64 x 64 tiles on and above the diagonal are multiplied (split-K
+// into `part`, splits x m x m), the lower triangle is the conjugate mirror.
+int zgemm_herm_splits(int64_t m, int64_t k);
+void zgemm_herm(int64_t m, int64_t k, const void *A, int64_t lda, const void *B, int64_t ldb,
+                void *C, int64_t ldc, hipStream_t st, void *part, int splits);
 
 // C = alpha * sum_z part[z] + beta C  (m x n, part ld = m)
 void zsum_parts(int64_t m, int64_t n, const void *part, int splits, void *C, int64_t ldc,

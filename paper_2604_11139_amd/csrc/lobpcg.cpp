@@ -27,13 +27,12 @@ bool ortho_rr_basis(abi_system_s *s, int64_t k, int64_t mout, const double2 *Z,
   double2 *T = (double2 *)s->small3.get(kk);
   double2 *Y = (double2 *)s->small4.get(kk);
   int *info = (int *)s->lob_g.get(sizeof(double2) * 16);
-  const int splits = zgemm_splits(k, k, npw);
+  // Z^H S Z and Z^H H Z are Hermitian: only the upper tiles are formed
+  const int splits = zgemm_herm_splits(k, npw);
   const double gflops = 8.0 * (double)k * k * npw;
   void *part = s->cpart.get(sizeof(double2) * (size_t)splits * k * k);
   int tok = s->prof.begin(PROF_GRAM, gflops, st);
-  zgemm(OP_C, OP_N, k, k, npw, Z, ld, SZ, ld, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
-        splits);
-  zsum_parts(k, k, part, splits, G, k, double2{1, 0}, double2{0, 0}, st);
+  zgemm_herm(k, npw, Z, ld, SZ, ld, G, k, st, part, splits);
   s->prof.end(tok, st);
   launch_hermitize(k, G, k, st);
   tok = s->prof.begin(PROF_CHOL, 4.0 / 3.0 * (double)k * k * k, st);
@@ -44,9 +43,7 @@ bool ortho_rr_basis(abi_system_s *s, int64_t k, int64_t mout, const double2 *Z,
   CHEBFI_HIP(hipStreamSynchronize(st));
   if (h != 0) return false;
   tok = s->prof.begin(PROF_GRAM, gflops, st);
-  zgemm(OP_C, OP_N, k, k, npw, Z, ld, HZ, ld, nullptr, 0, double2{1, 0}, double2{0, 0}, st, part,
-        splits);
-  zsum_parts(k, k, part, splits, Hs, k, double2{1, 0}, double2{0, 0}, st);
+  zgemm_herm(k, npw, Z, ld, HZ, ld, Hs, k, st, part, splits);
   s->prof.end(tok, st);
   launch_hermitize(k, Hs, k, st);
   tok = s->prof.begin(PROF_CHOL, 16.0 * (double)k * k * k, st);

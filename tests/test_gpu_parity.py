@@ -229,6 +229,51 @@ def test_zheev_degenerate():
     assert np.abs(Z.conj().T @ Z - np.eye(m)).max() <= 1e-11
 
 
+@pytest.mark.parametrize("m", [2048, 2560])
+def test_zheev_large(m):
+    """The Rayleigh-Ritz size of the large workload and the largest size the
+    eigensolver accepts (one past it is an argument error)."""
+    import torch
+    rng = np.random.default_rng(m)
+    A = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    A = A + A.conj().T
+    w, Z = B.zheev(torch.from_numpy(A).cuda())
+    w = w.cpu().numpy()
+    Z = Z.cpu().numpy()
+    ref = np.linalg.eigvalsh(A)
+    scale = np.abs(ref).max()
+    assert np.all(np.diff(w) >= 0)
+    assert np.abs(w - ref).max() <= 1e-12 * scale * np.sqrt(m)
+    assert np.abs(A @ Z - Z * w[None, :]).max() <= 1e-11 * scale
+    assert np.abs(Z.conj().T @ Z - np.eye(m)).max() <= 1e-11
+    if m == 2560:
+        with pytest.raises(B.ChebfiError) as e:
+            B.zheev(torch.zeros((m + 1, m + 1), dtype=torch.complex128, device="cuda"))
+        assert e.value.code == B.ABI_ERR_ARG
+
+
+@pytest.mark.parametrize("kind", ["repeated", "near"])
+def test_zheev_clusters_large(kind):
+    """Wide clusters: 12 eigenvalues of multiplicity 50 (exactly repeated), or
+    spread by 1e-10 inside each cluster (closer than the inverse iteration's
+    cluster gap, distinct to the multisection)."""
+    import torch
+    rng = np.random.default_rng(11)
+    m = 600
+    Q, _ = np.linalg.qr(rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)))
+    lam = np.repeat(np.arange(12, dtype=np.float64) - 5.5, 50)
+    if kind == "near":
+        lam = lam + 1e-10 * np.tile(np.arange(50), 12)
+    A = (Q * lam[None, :]) @ Q.conj().T
+    A = 0.5 * (A + A.conj().T)
+    w, Z = B.zheev(torch.from_numpy(A).cuda())
+    w = w.cpu().numpy()
+    Z = Z.cpu().numpy()
+    assert np.abs(w - np.sort(lam)).max() <= 1e-12 * 6 * np.sqrt(m)
+    assert np.abs(A @ Z - Z * w[None, :]).max() <= 1e-11 * 6
+    assert np.abs(Z.conj().T @ Z - np.eye(m)).max() <= 1e-11
+
+
 @pytest.mark.parametrize("m", [1, 31, 33, 100, 257])
 def test_zpotrf(m):
     import scipy.linalg
