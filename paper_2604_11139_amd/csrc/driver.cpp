@@ -66,16 +66,19 @@ int project_t(abi_system_s *s, const void *X, int64_t ldx, int64_t nband, hipStr
   return splits;
 }
 
-// Out += P C' for nproj x nband coefficients C' (ld nproj) of the block's type.
+// Out += P C' for nproj x nband coefficients C' (ld nproj) of the block's type;
+// store_only (split-BF16 products only): Out = P C'.
 template <typename T>
 void expand_t(abi_system_s *s, const C2<T> *cprime, void *Out, int64_t ldo, int64_t nband,
-              hipStream_t st) {
+              hipStream_t st, bool store_only = false) {
   const bool fp32 = std::is_same<T, float>::value;
   const void *P = fp32 ? (const void *)s->d_Pf : (const void *)s->d_P;
   const int64_t npw = s->npw;
   const int nproj = s->nproj;
   const bool single = (nband == 1) && !fp32;
   const bool planes = fp32 && s->mixed_gemm == 0;
+  CHEBFI_REQUIRE(!store_only || (planes && !single), ABI_ERR_STATE,
+                 "store-only expansion needs the split-BF16 products");
   if (planes)
     split_planes(nproj, nband, cprime, nproj, s->cplanes.get(8 * (size_t)s->ldPB * nband),
                  s->ldPB, st);
@@ -85,7 +88,7 @@ void expand_t(abi_system_s *s, const C2<T> *cprime, void *Out, int64_t ldo, int6
     expand_gemv(npw, nproj, P, cprime, Out, st);
   else if (planes)
     expand_gemm_planes(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB, s->cplanes.ptr,
-                       s->ldPB, s->ldPB * nband, Out, ldo, st, s->pl_expand);
+                       s->ldPB, s->ldPB * nband, Out, ldo, st, s->pl_expand, !store_only);
   else if (fp32 && s->mixed_gemm == 2)
     expand_gemm_bf16x3(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB, cprime, Out, ldo, st);
   else
@@ -95,10 +98,11 @@ void expand_t(abi_system_s *s, const C2<T> *cprime, void *Out, int64_t ldo, int6
 
 // Local part, kinetic term and recurrence on the FFT grid:
 // Out = alpha ((0.5|k+G|^2 + V_loc) X - cshift X) - beta Xprev   (Xprev may be null).
+// E (optional, ld lde): the projector part P C', added to Out on the sphere.
 template <typename T>
 void local_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
              void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
-             hipStream_t st) {
+             hipStream_t st, const void *E = nullptr, int64_t lde = 0) {
   typedef C2<T> V2;
   const bool fp32 = std::is_same<T, float>::value;
   const void *V = fp32 ? (const void *)s->d_Vf : (const void *)s->d_V;
@@ -108,7 +112,7 @@ void local_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int
   for (int64_t b0 = 0; b0 < nband; b0 += fb) {
     const int nb = (int)std::min<int64_t>(fb, nband - b0);
     launch_local_potential<T>(s, X, ldx, Xprev, ldp, Out, ldo, (int)b0, nb, box, V, alpha, cshift,
-                              beta, st, s->prof.on ? &s->prof : nullptr);
+                              beta, st, s->prof.on ? &s->prof : nullptr, E, lde);
   }
 }
 
@@ -127,11 +131,16 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
   const bool single = (nband == 1) && !fp32;
   // the FFT passes run on the second stream beside the projection when they can
   const bool side = s->overlap && nproj > 0 && !single && s->aux;
+  // otherwise, with the split-BF16 products, the projector part goes first: the
+  // expansion stores E = P C' (no read of the output block) and the last FFT
+  // pass adds E while it writes Out
+  const bool pre = !side && nproj > 0 && fp32 && s->mixed_gemm == 0;
   if (side) {
     CHEBFI_HIP(hipEventRecord(s->ev_fork, st));
     CHEBFI_HIP(hipStreamWaitEvent(s->aux, s->ev_fork, 0));
   }
-  local_t<T>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, side ? s->aux : st);
+  if (!pre)
+    local_t<T>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, side ? s->aux : st);
   if (side) CHEBFI_HIP(hipEventRecord(s->ev_join, s->aux));
   V2 *cprime = nullptr;
   if (nproj > 0) {
@@ -146,7 +155,13 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
     s->prof.end(tok, st);
   }
   if (side) CHEBFI_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
-  if (nproj > 0) expand_t<T>(s, cprime, Out, ldo, nband, st);  // Out += P C'
+  if (pre) {
+    void *E = s->expout.get(sizeof(V2) * (size_t)s->npw * nband);
+    expand_t<T>(s, cprime, E, s->npw, nband, st, true);  // E = P C'
+    local_t<T>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, st, E, s->npw);
+  } else if (nproj > 0) {
+    expand_t<T>(s, cprime, Out, ldo, nband, st);  // Out += P C'
+  }
 }
 
 // ---- overlap S = I + P Q P^H and its Woodbury inverse ----------------------------

@@ -91,6 +91,13 @@ __global__ __launch_bounds__(512) void pass_b_kernel(C2<T> *__restrict__ box, co
   }
 }
 
+// a + b rounded on its own (never fused with the multiply that produced a), so
+// that adding a precomputed block E equals storing the value and adding E later
+template <typename V2> __device__ __forceinline__ V2 add_rounded(V2 a, V2 b) {
+#pragma clang fp contract(off)
+  return V2{a.x + b.x, a.y + b.y};
+}
+
 // ---- pass C: box plane -> forward xy FFT -> gather + recurrence combine ----
 template <typename T>
 __global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ box, BoxPlan plan,
@@ -100,7 +107,7 @@ __global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ b
                               int band0, const C2<T> *__restrict__ Yk, int64_t ldk,
                               const C2<T> *__restrict__ Yprev, int64_t ldp,
                               C2<T> *__restrict__ Out, int64_t ldo, T alpha, T cshift, T beta,
-                              T scale) {
+                              T scale, const C2<T> *__restrict__ E, int64_t lde) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
   const int n1 = plan.d[0].n, n2 = plan.d[1].n;
@@ -121,6 +128,7 @@ __global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ b
   const int64_t b = band0 + bl;
   const C2<T> *yk = Yk + b * ldk;
   C2<T> *out = Out + b * ldo;
+  const C2<T> *ex = E ? E + b * lde : nullptr;
   if (Yprev != nullptr) {
     const C2<T> *yp = Yprev + b * ldp;
     for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x) {
@@ -130,7 +138,9 @@ __global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ b
       const T kd = (T)kin[idx] - cshift;
       C2<T> h = cadd(loc, cscale(x, kd));
       C2<T> p = yp[idx];
-      out[idx] = C2<T>{alpha * h.x - beta * p.x, alpha * h.y - beta * p.y};
+      C2<T> o{alpha * h.x - beta * p.x, alpha * h.y - beta * p.y};
+      if (ex) o = add_rounded(o, ex[idx]);
+      out[idx] = o;
     }
   } else {
     for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x) {
@@ -139,7 +149,9 @@ __global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ b
       C2<T> x = yk[idx];
       const T kd = (T)kin[idx] - cshift;
       C2<T> h = cadd(loc, cscale(x, kd));
-      out[idx] = cscale(h, alpha);
+      C2<T> o = cscale(h, alpha);
+      if (ex) o = add_rounded(o, ex[idx]);
+      out[idx] = o;
     }
   }
 }
@@ -363,7 +375,7 @@ __global__ __launch_bounds__(kCT) void cpass_c_kernel(
     const int32_t *__restrict__ box_index, const int32_t *__restrict__ plane,
     const double *__restrict__ kin, int band0, const C2<T> *__restrict__ Yk, int64_t ldk,
     const C2<T> *__restrict__ Yprev, int64_t ldp, C2<T> *__restrict__ Out, int64_t ldo, T alpha,
-    T cshift, T beta, T scale) {
+    T cshift, T beta, T scale, const C2<T> *__restrict__ E, int64_t lde) {
   constexpr int NXY = N * N, LD = N + 1;
   __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
@@ -380,6 +392,7 @@ __global__ __launch_bounds__(kCT) void cpass_c_kernel(
   const int64_t b = band0 + bl;
   const C2<T> *yk = Yk + b * ldk;
   C2<T> *out = Out + b * ldo;
+  const C2<T> *ex = E ? E + b * lde : nullptr;
   if (Yprev != nullptr) {
     const C2<T> *yp = Yprev + b * ldp;
     for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
@@ -389,7 +402,9 @@ __global__ __launch_bounds__(kCT) void cpass_c_kernel(
       const T kd = (T)kin[idx] - cshift;
       const C2<T> h = cadd(loc, cscale(x, kd));
       const C2<T> p = yp[idx];
-      out[idx] = C2<T>{alpha * h.x - beta * p.x, alpha * h.y - beta * p.y};
+      C2<T> o{alpha * h.x - beta * p.x, alpha * h.y - beta * p.y};
+      if (ex) o = add_rounded(o, ex[idx]);
+      out[idx] = o;
     }
   } else {
     for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
@@ -397,7 +412,9 @@ __global__ __launch_bounds__(kCT) void cpass_c_kernel(
       const C2<T> loc = cscale(buf[e + e / N], scale);
       const C2<T> x = yk[idx];
       const T kd = (T)kin[idx] - cshift;
-      out[idx] = cscale(cadd(loc, cscale(x, kd)), alpha);
+      C2<T> o = cscale(cadd(loc, cscale(x, kd)), alpha);
+      if (ex) o = add_rounded(o, ex[idx]);
+      out[idx] = o;
     }
   }
 }
@@ -406,7 +423,7 @@ template <typename T, int N>
 void launch_cubic(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Yprev,
                   int64_t ldp, void *Out, int64_t ldo, int band0, int nb, void *box, const void *V,
                   double alpha, double cshift, double beta, hipStream_t st, Profiler *prof,
-                  double bytesA, double bytesB, double bytesC) {
+                  double bytesA, double bytesB, double bytesC, const void *E, int64_t lde) {
   typedef C2<T> V2;
   typedef typename std::conditional<std::is_same<T, double>::value, double, float>::type VT;
   const double2 *tw = reinterpret_cast<const double2 *>(s->d_tw);
@@ -426,7 +443,7 @@ void launch_cubic(const abi_system_s *s, const void *Yk, int64_t ldk, const void
   hipLaunchKernelGGL((cpass_c_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st, bx, tw, s->d_box,
                      s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Yk), ldk,
                      reinterpret_cast<const V2 *>(Yprev), ldp, reinterpret_cast<V2 *>(Out), ldo,
-                     (T)alpha, (T)cshift, (T)beta, scale);
+                     (T)alpha, (T)cshift, (T)beta, scale, reinterpret_cast<const V2 *>(E), lde);
   CHEBFI_HIP(hipGetLastError());
   if (prof) prof->end(tok, st);
 }
@@ -455,7 +472,8 @@ void adjoint_cubic(const abi_system_s *s, const void *Ak1, int64_t lda1, const v
   hipLaunchKernelGGL((cpass_c_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st, b1, tw, s->d_box,
                      s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Ak1), lda1,
                      accumulate ? reinterpret_cast<const V2 *>(Ak) : (const V2 *)nullptr, ldak,
-                     reinterpret_cast<V2 *>(Ak), ldak, (T)gamma, (T)cshift, (T)-1, scale);
+                     reinterpret_cast<V2 *>(Ak), ldak, (T)gamma, (T)cshift, (T)-1, scale,
+                     (const V2 *)nullptr, (int64_t)0);
   CHEBFI_HIP(hipGetLastError());
 }
 
@@ -519,13 +537,13 @@ template <typename T>
 bool try_cubic(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Yprev, int64_t ldp,
                void *Out, int64_t ldo, int band0, int nb, void *box, const void *V, double alpha,
                double cshift, double beta, hipStream_t st, Profiler *prof, double bA, double bB,
-               double bC) {
+               double bC, const void *E, int64_t lde) {
   if (s->n1 != s->n2 || s->n1 != s->n3) return false;
   if (std::getenv("CHEBFI_GENERIC_FFT")) return false;
 #define CHEBFI_CUBIC(N_)                                                                     \
   case N_:                                                                                   \
     launch_cubic<T, N_>(s, Yk, ldk, Yprev, ldp, Out, ldo, band0, nb, box, V, alpha, cshift,  \
-                        beta, st, prof, bA, bB, bC);                                         \
+                        beta, st, prof, bA, bB, bC, E, lde);                                 \
     return true;
   switch (s->n1) {
     CHEBFI_CUBIC(12)
@@ -560,7 +578,7 @@ template <typename T>
 void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Yprev,
                             int64_t ldp, void *Out, int64_t ldo, int band0, int nb, void *box,
                             const void *V, double alpha, double cshift, double beta,
-                            hipStream_t st, Profiler *prof) {
+                            hipStream_t st, Profiler *prof, const void *E, int64_t lde) {
   using V2 = C2<T>;
   const BoxPlan &plan = s->plan;
   const int n1 = plan.d[0].n, n2 = plan.d[1].n, n3 = plan.d[2].n;
@@ -581,9 +599,9 @@ void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, 
   const double es = (double)sizeof(V2), nbx = (double)n1 * n2 * n3, np = (double)s->npw;
   const double bytesA = nb * (np + nbx) * es;
   const double bytesB = nb * 2.0 * nbx * es + nbx * (double)sizeof(T);
-  const double bytesC = nb * (nbx + np * (Yprev ? 3.0 : 2.0)) * es;
+  const double bytesC = nb * (nbx + np * ((Yprev ? 3.0 : 2.0) + (E ? 1.0 : 0.0))) * es;
   if (try_cubic<T>(s, Yk, ldk, Yprev, ldp, Out, ldo, band0, nb, box, V, alpha, cshift, beta, st,
-                   prof, bytesA, bytesB, bytesC))
+                   prof, bytesA, bytesB, bytesC, E, lde))
     return;
   int tok = prof ? prof->begin(PROF_FFT_A, bytesA, st) : -1;
   hipLaunchKernelGGL(pass_a_kernel<T>, dim3(n3, nb), dim3(tA), ldsA, st,
@@ -605,7 +623,7 @@ void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, 
   hipLaunchKernelGGL(pass_c_kernel<T>, dim3(n3, nb), dim3(tA), ldsA, st, bx, plan, tw, s->d_box,
                      s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Yk), ldk,
                      reinterpret_cast<const V2 *>(Yprev), ldp, reinterpret_cast<V2 *>(Out), ldo,
-                     (T)alpha, (T)cshift, (T)beta, scale);
+                     (T)alpha, (T)cshift, (T)beta, scale, reinterpret_cast<const V2 *>(E), lde);
   CHEBFI_HIP(hipGetLastError());
   if (prof) prof->end(tok, st);
 }
@@ -650,7 +668,8 @@ void launch_adjoint_local(const abi_system_s *s, const void *Ak1, int64_t lda1, 
   hipLaunchKernelGGL(pass_c_kernel<T>, dim3(n3, nb), dim3(tA), ldsA, st, b1, plan, tw, s->d_box,
                      s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Ak1), lda1,
                      accumulate ? reinterpret_cast<const V2 *>(Ak) : (const V2 *)nullptr, ldak,
-                     reinterpret_cast<V2 *>(Ak), ldak, (T)gamma, (T)cshift, (T)-1, scale);
+                     reinterpret_cast<V2 *>(Ak), ldak, (T)gamma, (T)cshift, (T)-1, scale,
+                     (const V2 *)nullptr, (int64_t)0);
   CHEBFI_HIP(hipGetLastError());
 }
 
@@ -697,11 +716,11 @@ template void launch_adjoint_local<float>(const abi_system_s *, const void *, in
 template void launch_local_potential<double>(const abi_system_s *, const void *, int64_t,
                                              const void *, int64_t, void *, int64_t, int, int,
                                              void *, const void *, double, double, double,
-                                             hipStream_t, Profiler *);
+                                             hipStream_t, Profiler *, const void *, int64_t);
 template void launch_local_potential<float>(const abi_system_s *, const void *, int64_t,
-                                            const void *, int64_t, void *, int64_t, int, int,
-                                            void *, const void *, double, double, double,
-                                            hipStream_t, Profiler *);
+                                             const void *, int64_t, void *, int64_t, int, int,
+                                             void *, const void *, double, double, double,
+                                             hipStream_t, Profiler *, const void *, int64_t);
 
 int fft_stage_threads(const Plan1D &pl, int npen) { return stage_need(pl, npen); }
 

@@ -590,7 +590,7 @@ template <int BM, int BN, int NWM, int NWN, bool CONJ, bool SPLIT>
 __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl_kernel(
     int64_t m, int64_t n, int64_t k, const u16 *__restrict__ Apl, int64_t lda, int64_t psa,
     const u16 *__restrict__ Bpl, int64_t ldb, int64_t psb, float2 *__restrict__ C, int64_t ldc,
-    int64_t kchunk, float2 *__restrict__ part) {
+    int64_t kchunk, float2 *__restrict__ part, int accum) {
   constexpr int NT = 64 * NWM * NWN;
   constexpr int SM = BM / NWM / 16, SN = BN / NWN / 16;
   constexpr int CA = 16 * BM / NT, CB = 16 * BN / NT;  // 16-byte chunks per thread
@@ -746,10 +746,14 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_pl_kernel(
           if (SPLIT) {
             part[(int64_t)blockIdx.z * m * n + row + col * m] = v;
           } else {
-            float2 o = C[row + col * ldc];
-            o.x += v.x;
-            o.y += v.y;
-            C[row + col * ldc] = o;
+            if (accum) {
+              float2 o = C[row + col * ldc];
+              o.x += v.x;
+              o.y += v.y;
+              C[row + col * ldc] = o;
+            } else {
+              C[row + col * ldc] = v;
+            }
           }
         }
       }
@@ -790,7 +794,7 @@ template <int BM, int BN, int NWM, int NWN, bool CONJ, bool SPLIT, int DEPTH, bo
 __global__ __launch_bounds__(64 * NWM * NWN, 2) void zgemm_pl2_kernel(
     int64_t m, int64_t n, int64_t k, const u16 *__restrict__ Apl, int64_t lda, int64_t psa,
     const u16 *__restrict__ Bpl, int64_t ldb, int64_t psb, float2 *__restrict__ C, int64_t ldc,
-    int64_t kchunk, float2 *__restrict__ part) {
+    int64_t kchunk, float2 *__restrict__ part, int accum) {
   constexpr int NT = 64 * NWM * NWN;
   constexpr int SM = BM / NWM / 16, SN = BN / NWN / 16;
   constexpr int CA = 16 * BM / NT, CB = 16 * BN / NT;
@@ -1025,10 +1029,14 @@ __global__ __launch_bounds__(64 * NWM * NWN, 2) void zgemm_pl2_kernel(
           if (SPLIT) {
             part[(int64_t)tz * m * n + row + col * m] = v;
           } else {
-            float2 o = C[row + col * ldc];
-            o.x += v.x;
-            o.y += v.y;
-            C[row + col * ldc] = o;
+            if (accum) {
+              float2 o = C[row + col * ldc];
+              o.x += v.x;
+              o.y += v.y;
+              C[row + col * ldc] = o;
+            } else {
+              C[row + col * ldc] = v;
+            }
           }
         }
       }
@@ -1083,15 +1091,17 @@ void split_planes(int64_t rows, int64_t cols, const void *X, int64_t ld, void *p
 //   4: 128 x 128, 2 x 4 waves, double-buffered LDS (default)
 //   5: as 4 with the global loads issued two K slices ahead
 //   6: 128 x  64, 2 x 2 waves, one LDS stage (two workgroups per CU)
+// accum: C += A B (else C = A B) when not split
 template <bool CONJ, bool SPLIT>
 static void launch_pl(int variant, dim3 grid_mn_z, int64_t m, int64_t n, int64_t k,
                       const void *Apl, int64_t lda, int64_t psa, const void *Bpl, int64_t ldb,
                       int64_t psb, void *C, int64_t ldc, int64_t chunk, void *part,
-                      hipStream_t st) {
+                      hipStream_t st, bool accum = true) {
   auto go = [&](auto kern, int bm, int bn, int nt) {
     dim3 grid((unsigned)((m + bm - 1) / bm), (unsigned)((n + bn - 1) / bn), grid_mn_z.z);
     hipLaunchKernelGGL(kern, grid, dim3(nt), 0, st, m, n, k, (const u16 *)Apl, lda, psa,
-                       (const u16 *)Bpl, ldb, psb, (float2 *)C, ldc, chunk, (float2 *)part);
+                       (const u16 *)Bpl, ldb, psb, (float2 *)C, ldc, chunk, (float2 *)part,
+                       (int)accum);
   };
   switch (variant) {
     case 1: go(zgemm_pl_kernel<128, 128, 2, 2, CONJ, SPLIT>, 128, 128, 256); break;
@@ -1132,15 +1142,15 @@ void proj_gemm_planes_f32(int64_t nproj, int64_t nband, int64_t npw, const void 
   dim3 grid((unsigned)((nproj + 127) / 128), (unsigned)((nband + 127) / 128), (unsigned)splits);
   hipLaunchKernelGGL((zgemm_pl2_kernel<128, 128, 2, 4, true, true, 1, true>), grid, dim3(512), 0,
                      st, nproj, nband, npw, (const u16 *)Apl, lda, psa, (const u16 *)Y, ldy,
-                     (int64_t)0, (float2 *)nullptr, (int64_t)0, chunk, (float2 *)part);
+                     (int64_t)0, (float2 *)nullptr, (int64_t)0, chunk, (float2 *)part, 1);
   CHEBFI_HIP(hipGetLastError());
 }
 
 void expand_gemm_planes(int64_t npw, int64_t nband, int64_t nproj, const void *Apl, int64_t lda,
                         int64_t psa, const void *Cpl, int64_t ldc_pl, int64_t psc, void *Out,
-                        int64_t ldo, hipStream_t st, int variant) {
+                        int64_t ldo, hipStream_t st, int variant, bool accumulate) {
   launch_pl<false, false>(variant, dim3(1, 1, 1), npw, nband, nproj, Apl, lda, psa, Cpl, ldc_pl,
-                          psc, Out, ldo, nproj, nullptr, st);
+                          psc, Out, ldo, nproj, nullptr, st, accumulate);
 }
 
 void expand_gemm_bf16x3(int64_t npw, int64_t nband, int64_t nproj, const void *Apl, int64_t lda,

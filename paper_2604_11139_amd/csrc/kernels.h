@@ -17,11 +17,14 @@ enum Op { OP_N = 0, OP_C = 1 };  // op(X) = X or X^H
 // Out[:, b] = alpha * (V_loc Yk[:, b] + (kin - cshift) Yk[:, b]) - beta * Yprev[:, b]
 // for b in [band0, band0 + nb); Yprev may be null (then beta is ignored).
 // `box` holds nb boxes; V is double (T = double) or float (T = float).
+// E (optional, ld lde): a block added to Out on the sphere (the projector part
+// of H computed beforehand), with a plain rounded add after the local value.
 template <typename T>
 void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Yprev,
                             int64_t ldp, void *Out, int64_t ldo, int band0, int nb, void *box,
                             const void *V, double alpha, double cshift, double beta,
-                            hipStream_t st, Profiler *prof = nullptr);
+                            hipStream_t st, Profiler *prof = nullptr, const void *E = nullptr,
+                            int64_t lde = 0);
 
 // Local part of one reverse step of the filter adjoint for bands
 // [band0, band0+nb): dV += gamma/n^3 sum_b Re[conj(Ak1~) Yk~] and
@@ -78,9 +81,10 @@ void proj_gemm_planes(int64_t nproj, int64_t nband, int64_t npw, const void *Apl
 void proj_gemm_planes_f32(int64_t nproj, int64_t nband, int64_t npw, const void *Apl, int64_t lda,
                           int64_t psa, const void *Y, int64_t ldy, void *part, int splits,
                           hipStream_t st);
+// Out += P C' (accumulate) or Out = P C'
 void expand_gemm_planes(int64_t npw, int64_t nband, int64_t nproj, const void *Apl, int64_t lda,
                         int64_t psa, const void *Cpl, int64_t ldc_pl, int64_t psc, void *Out,
-                        int64_t ldo, hipStream_t st, int variant);
+                        int64_t ldo, hipStream_t st, int variant, bool accumulate = true);
 // Single-band forms: c = P^H x, out += P c.
 void proj_gemv(int64_t npw, int nproj, const void *P, const void *x, void *c, hipStream_t st);
 void expand_gemv(int64_t npw, int nproj, const void *P, const void *c, void *out, hipStream_t st);
