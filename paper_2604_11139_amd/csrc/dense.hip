@@ -407,6 +407,140 @@ __device__ __forceinline__ double lane_val(double v, int k) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// Inverse iteration for the eigenvalues with no neighbour within the cluster
+// gap (1e-6 |T|): one lane per eigenvalue, 64 per wave, each lane running the
+// same steps as the workgroup form below without the Gram-Schmidt (LU with
+// partial pivoting of T - lambda I, three solves from the same seeded start,
+// each followed by scaling to max 1 and normalisation; sign of the largest
+// component positive).  The factors and the iterate live in `work`, interleaved
+// by lane (element i of lane l at i * 64 + l within the wave's slab), so that
+// each sequential step of the 64 lanes is one coalesced access.
+__global__ __launch_bounds__(64) void invit_lane_kernel(
+    int64_t m, const double *__restrict__ d, const double *__restrict__ e,
+    const double *__restrict__ w, const double *__restrict__ stats, double *__restrict__ S,
+    int64_t lds, double *__restrict__ work, unsigned char *__restrict__ wswp) {
+  const int lane = threadIdx.x;
+  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+  const double scale = stats[2];
+  const double gaptol = 1e-6 * scale;
+  if (q >= m) return;
+  if (q > 0 && w[q] - w[q - 1] <= gaptol) return;         // in a cluster
+  if (q + 1 < m && w[q + 1] - w[q] <= gaptol) return;     // in a cluster
+  const int64_t slab = m * 64, nb = gridDim.x, b = blockIdx.x;
+  double *rud = work + (0 * nb + b) * slab + lane;
+  double *u1 = work + (1 * nb + b) * slab + lane;
+  double *u2 = work + (2 * nb + b) * slab + lane;
+  double *lm = work + (3 * nb + b) * slab + lane;
+  double *x = work + (4 * nb + b) * slab + lane;
+  unsigned char *swp = wswp + b * slab + lane;
+  const double tiny = DBL_EPSILON * scale;
+  const double shift = w[q];
+  // LU with partial pivoting of T - shift I
+  double a = d[0] - shift;
+  double cc = (m > 1) ? e[0] : 0.0;
+  for (int64_t i = 0; i < m - 1; ++i) {
+    const double bb = e[i], an = d[i + 1] - shift, cn = (i + 1 < m - 1) ? e[i + 1] : 0.0;
+    const bool keep = fabs(a) >= fabs(bb);
+    const double num = keep ? bb : a, den = keep ? a : bb;
+    const double l = (den != 0.0) ? num / den : 0.0;
+    double piv = den;
+    if (fabs(piv) < tiny) piv = (piv < 0.0) ? -tiny : tiny;
+    rud[i * 64] = 1.0 / piv;
+    u1[i * 64] = keep ? cc : an;
+    u2[i * 64] = keep ? 0.0 : cn;
+    lm[i * 64] = l;
+    swp[i * 64] = keep ? 0 : 1;
+    const double na = keep ? an - l * cc : cc - l * an;
+    cc = keep ? cn : -l * cn;
+    a = na;
+  }
+  rud[(m - 1) * 64] = 1.0 / ((fabs(a) < tiny) ? ((a < 0.0) ? -tiny : tiny) : a);
+  for (int64_t i = 0; i < m; ++i) x[i * 64] = hash_uniform(q, i);
+  // the solves load the operands of kB steps into registers before running them
+  // (one memory latency per block instead of per step)
+  constexpr int kB = 32;
+  for (int it = 0; it < 3; ++it) {
+    double cur = x[0];
+    int64_t i0 = 0;
+    for (; i0 + kB <= m - 1; i0 += kB) {
+      double nx[kB], l[kB];
+      unsigned char sw[kB];
+#pragma unroll
+      for (int k = 0; k < kB; ++k) {
+        nx[k] = x[(i0 + k + 1) * 64];
+        l[k] = lm[(i0 + k) * 64];
+        sw[k] = swp[(i0 + k) * 64];
+      }
+#pragma unroll
+      for (int k = 0; k < kB; ++k) {
+        const double c = sw[k] ? nx[k] : cur;
+        const double n = (sw[k] ? cur : nx[k]) - l[k] * c;
+        x[(i0 + k) * 64] = c;
+        cur = n;
+      }
+    }
+    for (int64_t i = i0; i < m - 1; ++i) {
+      const double nx = x[(i + 1) * 64], l = lm[i * 64];
+      const bool sw = swp[i * 64] != 0;
+      const double c = sw ? nx : cur;
+      const double n = (sw ? cur : nx) - l * c;
+      x[i * 64] = c;
+      cur = n;
+    }
+    double x1 = cur * rud[(m - 1) * 64], x2 = 0.0;
+    x[(m - 1) * 64] = x1;
+    double mx = fabs(x1);
+    int64_t i1 = m - 2;
+    for (; i1 - kB + 1 >= 0; i1 -= kB) {
+      double xv[kB], a1[kB], a2[kB], r[kB];
+#pragma unroll
+      for (int k = 0; k < kB; ++k) {
+        const int64_t i = i1 - k;
+        xv[k] = x[i * 64];
+        a1[k] = u1[i * 64];
+        a2[k] = u2[i * 64];
+        r[k] = rud[i * 64];
+      }
+#pragma unroll
+      for (int k = 0; k < kB; ++k) {
+        const double x0 = (xv[k] - a1[k] * x1 - a2[k] * x2) * r[k];
+        x[(i1 - k) * 64] = x0;
+        mx = fmax(mx, fabs(x0));
+        x2 = x1;
+        x1 = x0;
+      }
+    }
+    for (int64_t i = i1; i >= 0; --i) {
+      const double x0 = (x[i * 64] - u1[i * 64] * x1 - u2[i * 64] * x2) * rud[i * 64];
+      x[i * 64] = x0;
+      mx = fmax(mx, fabs(x0));
+      x2 = x1;
+      x1 = x0;
+    }
+    const double inv = (mx > 0) ? 1.0 / mx : 1.0;
+    double nn = 0;
+#pragma unroll 8
+    for (int64_t i = 0; i < m; ++i) {
+      const double v = x[i * 64] * inv;
+      x[i * 64] = v;
+      nn += v * v;
+    }
+    const double invn = (nn > 0) ? 1.0 / sqrt(nn) : 1.0;
+#pragma unroll 8
+    for (int64_t i = 0; i < m; ++i) x[i * 64] *= invn;
+  }
+  double best = -1.0;
+  int64_t bi = 0;
+  for (int64_t i = 0; i < m; ++i)
+    if (fabs(x[i * 64]) > best) {
+      best = fabs(x[i * 64]);
+      bi = i;
+    }
+  const double sg = (x[bi * 64] < 0) ? -1.0 : 1.0;
+  double *sq = S + q * lds;
+  for (int64_t i = 0; i < m; ++i) sq[i] = sg * x[i * 64];
+}
+
 // One workgroup per cluster of eigenvalues closer than `gaptol`; the group
 // leader (first index of the cluster) computes all members in order.
 // S (m x m, real, column-major, lds) receives the tridiagonal eigenvectors.
@@ -420,6 +554,7 @@ __global__ __launch_bounds__(256) void invit_kernel(int64_t m, const double *__r
   if (c0 > 0 && w[c0] - w[c0 - 1] <= gaptol) return;  // not a cluster leader
   int64_t c1 = c0 + 1;
   while (c1 < m && w[c1] - w[c1 - 1] <= gaptol) ++c1;
+  if (c1 == c0 + 1) return;  // a lone eigenvalue: invit_lane_kernel
 
   double *sd = reinterpret_cast<double *>(smem_raw);
   double *se = sd + m;
@@ -748,13 +883,15 @@ void ztrtri_upper(int64_t m, void *Av, int64_t lda, void *work, hipStream_t st) 
 
 size_t zheev_work_bytes(int64_t m) {
   // d, e, e2, w-tmp, stats, tau, u, wrow, two u and two p buffers, a2, S (real
-  // m x m), and the blocked back-transformation's V (m x nb), G, T (nb x nb),
-  // W1, W2 (nb x m)
+  // m x m), the lane-interleaved inverse iteration's five arrays and pivots
+  // (m x 64 per wave each), and the blocked back-transformation's V (m x nb),
+  // G, T (nb x nb), W1, W2 (nb x m)
   const size_t nb = kBtBlock;
+  const size_t lane_slab = (size_t)m * 64 * (size_t)((m + 63) / 64);
   return sizeof(double) * (size_t)(4 * m + 8) + sizeof(double2) * (size_t)(8 * m) +
-         sizeof(double) * (size_t)m * m +
+         sizeof(double) * (size_t)m * m + (5 * sizeof(double) + 1) * lane_slab +
          sizeof(double2) * ((3 + kBtSplits) * nb * (size_t)m + 2 * nb * nb) +
-         24 * 256;  // each of the 16 sub-buffers is rounded up to 256 bytes
+         24 * 256;  // each of the (at most 24) sub-buffers is rounded up to 256 bytes
 }
 
 void zheev(int64_t m, void *Av, int64_t lda, double *wout, void *Zv, int64_t ldz, void *work,
@@ -779,6 +916,9 @@ void zheev(int64_t m, void *Av, int64_t lda, double *wout, void *Zv, int64_t ldz
   double2 *pb = (double2 *)take(sizeof(double2) * 2 * m);
   double2 *a2s = (double2 *)take(sizeof(double2) * m);
   double *S = (double *)take(sizeof(double) * (size_t)m * m);
+  const size_t lane_slab = (size_t)m * 64 * nblk(m, 64);  // per array, all waves
+  double *lwork = (double *)take(sizeof(double) * 5 * lane_slab);
+  unsigned char *lswp = (unsigned char *)take(lane_slab);
 
   launch_hermitize(m, A, lda, st);
   // reduction to tridiagonal form: two launches per column, then the last diagonal
@@ -800,6 +940,8 @@ void zheev(int64_t m, void *Av, int64_t lda, double *wout, void *Zv, int64_t ldz
   const size_t lds_bytes = sizeof(double) * 7 * (size_t)m + (size_t)m + 64;
   CHEBFI_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(invit_kernel),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+  hipLaunchKernelGGL(invit_lane_kernel, dim3(nblk(m, 64)), dim3(64), 0, st, m, d, e, wout, stats,
+                     S, m, lwork, lswp);
   hipLaunchKernelGGL(invit_kernel, dim3((unsigned)m), dim3(256), lds_bytes, st, m, d, e, wout,
                      stats, S, m);
   CHEBFI_HIP(hipGetLastError());
