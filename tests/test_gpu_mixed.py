@@ -56,6 +56,31 @@ def test_mixed_apply_H(name):
     assert col_rel_err(got.astype(np.complex128), H(X)) <= 2e-6
 
 
+@pytest.mark.parametrize("name,generic", [("noncubic", False), ("n27", True), ("c1", True)])
+def test_mixed_apply_H_generic_fft(name, generic, monkeypatch):
+    """Runtime-size FFT passes in the mixed form (the last pass adds the projector
+    part computed before it): a non-cubic box, and cubic boxes forced onto them."""
+    if generic:
+        monkeypatch.setenv("CHEBFI_GENERIC_FFT", "1")
+    H = hamiltonian(name)
+    s = system(name)
+    X = W.random_block(H.npw, s.nband, 12).astype(np.complex64).astype(np.complex128)
+    with _mixed(name) as g:
+        got = to_host(g.apply_H(_c64(X)))
+    assert col_rel_err(got.astype(np.complex128), H(X)) <= 2e-6
+
+
+def test_mixed_apply_H_config2_ragged():
+    """77 bands of the medium workload: one full 64-band FFT batch and a ragged
+    one, a full and a ragged expansion tile (128 x 64)."""
+    s = W.make_system(2)
+    H = O.Hamiltonian.from_system(s)
+    X = W.random_block(H.npw, 77, 2).astype(np.complex64).astype(np.complex128)
+    with B.System(s, precision=B.ABI_PREC_MIXED) as g:
+        got = to_host(g.apply_H(_c64(X)))
+    assert col_rel_err(got.astype(np.complex128), H(X)) <= 2e-6
+
+
 @pytest.mark.parametrize("name,degree", [("odd15", 3), ("n27", 6), ("c1", 8)])
 def test_mixed_filter(name, degree):
     H = hamiltonian(name)
