@@ -12,12 +12,14 @@
 // * U^-1: blocked, diagonal blocks inverted in LDS, off-diagonal panels by GEMM;
 // * Hermitian eigensolver: Householder reduction to real symmetric tridiagonal
 //   form (reflectors H = I - tau u u^H with a real sub-diagonal, applied from
-//   both sides as a rank-2 update), eigenvalues by Sturm-count bisection (one
-//   thread per eigenvalue), eigenvectors of the tridiagonal by inverse
-//   iteration with partial-pivoting LU and modified Gram-Schmidt inside
-//   clusters of (nearly) equal eigenvalues, then the reflectors applied back.
-//   These are the classical Householder / bisection / inverse-iteration
-//   methods (Wilkinson; Golub & Van Loan, "Matrix Computations", chapter 8).
+//   both sides as a rank-2 update, applied lazily: two launches per column),
+//   eigenvalues by Sturm-count multisection (one wave per eigenvalue, 64
+//   points per round), eigenvectors of the tridiagonal by inverse iteration
+//   with partial-pivoting LU (one lane per isolated eigenvalue; one workgroup
+//   with modified Gram-Schmidt per cluster of (nearly) equal eigenvalues),
+//   then the reflectors applied back in blocks (compact WY).  These are the
+//   classical Householder / bisection / inverse-iteration methods (Wilkinson;
+//   Golub & Van Loan, "Matrix Computations", chapter 8).
 #include <cfloat>
 
 #include "cplx.h"
