@@ -52,6 +52,26 @@ __device__ double block_sum(double v, double *scratch) {
   return t;
 }
 
+// Block sum of a pair (one set of barriers; scratch holds 32 doubles).
+__device__ double2 block_sum2(double2 v, double *scratch) {
+  v.x = wave_sum(v.x);
+  v.y = wave_sum(v.y);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    scratch[2 * wave] = v.x;
+    scratch[2 * wave + 1] = v.y;
+  }
+  __syncthreads();
+  double2 t{0, 0};
+  for (int w = 0; w < nw; ++w) {
+    t.x += scratch[2 * w];
+    t.y += scratch[2 * w + 1];
+  }
+  return t;
+}
+
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 // ---------------------------------------------------------------- Cholesky --
@@ -189,7 +209,7 @@ __global__ __launch_bounds__(kTriColThreads) void tri_col_kernel(
     double *__restrict__ e, double2 *__restrict__ tau, double2 *__restrict__ ucur) {
   constexpr int NT = kTriColThreads, Q = (kEigMaxM + NT - 1) / NT;
   static_assert(NT >= 64 && NT % 64 == 0, "whole waves");
-  __shared__ double scratch[16];
+  __shared__ double scratch[32];
   __shared__ double2 sh_alpha;
   const int tid = threadIdx.x;
   double2 *col = A + j * lda;
@@ -210,9 +230,8 @@ __global__ __launch_bounds__(kTriColThreads) void tri_col_kernel(
         si += pv.x * uv.y - pv.y * uv.x;
       }
     }
-    sr = block_sum(sr, scratch);
-    si = block_sum(si, scratch);
-    const double2 a2 = cscale(cmul(tau[j - 1], double2{sr, si}), -0.5);
+    const double2 dot = block_sum2(double2{sr, si}, scratch);
+    const double2 a2 = cscale(cmul(tau[j - 1], dot), -0.5);
     const double2 uj = uprev[j];
     const double2 cwj = conj2(cadd(pprev[j], cmul(a2, uj))), cuj = conj2(uj);
 #pragma unroll
@@ -279,7 +298,7 @@ __global__ __launch_bounds__(256) void tri_trail_kernel(
     int64_t m, double2 *__restrict__ A, int64_t lda, int64_t j, const double2 *__restrict__ uprev,
     const double2 *__restrict__ pprev, const double2 *__restrict__ a2s,
     const double2 *__restrict__ ucur, const double2 *__restrict__ tau, double2 *__restrict__ pcur) {
-  __shared__ double scratch[16];
+  __shared__ double scratch[32];
   const int64_t ci = j + 1 + (int64_t)blockIdx.x;
   double2 *col = A + ci * lda;
   const bool upd = j >= 1;
@@ -302,9 +321,8 @@ __global__ __launch_bounds__(256) void tri_trail_kernel(
     sr += a.x * v.x + a.y * v.y;  // conj(a) v
     si += a.x * v.y - a.y * v.x;
   }
-  sr = block_sum(sr, scratch);
-  si = block_sum(si, scratch);
-  if (threadIdx.x == 0) pcur[ci] = cmul(tau[j], double2{sr, si});
+  const double2 dot = block_sum2(double2{sr, si}, scratch);
+  if (threadIdx.x == 0) pcur[ci] = cmul(tau[j], dot);
 }
 
 // ---------------------------------------------------------------- bisection --
