@@ -187,6 +187,28 @@ def test_rayleigh_ritz(name):
     assert _principal_sines(Psi[:, :p], rr["Psi"][:, :p]) <= 1e-7
 
 
+@pytest.mark.parametrize("nb", [77, 130])
+def test_rayleigh_ritz_ragged_tiles(nb):
+    """Rayleigh-Ritz of 77 and 130 bands of the medium workload: the Hermitian
+    Gram products span two and three 64-wide tiles with ragged last ones (only
+    the upper tiles are formed, the rest is mirrored)."""
+    s = W.make_system(2)
+    H = O.Hamiltonian.from_system(s)
+    X = W.random_block(H.npw, nb, 5)
+    rr = O.rayleigh_ritz(H, X)
+    res_ref = O.residual_norms(rr["Psi"], rr["HPsi"], rr["eval"])
+    import torch
+    with B.System(s) as g:
+        Yd = to_dev(X)
+        hp = torch.empty_like(Yd)
+        ev, res, flags = g.rayleigh_ritz(Yd, hp)
+        Psi = to_host(Yd)
+    assert flags == 0
+    assert np.abs(ev - rr["eval"]).max() <= 1e-8 * max(1.0, np.abs(rr["eval"]).max())
+    assert np.abs(Psi.conj().T @ Psi - np.eye(nb)).max() <= 1e-9
+    assert np.abs(res - res_ref).max() <= 1e-8 * max(1.0, np.abs(res_ref).max())
+
+
 def test_rayleigh_ritz_rank_deficient():
     s = system("tiny_k")
     H = hamiltonian("tiny_k")
