@@ -80,9 +80,9 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int nb, double2 *__rest
                                   int *__restrict__ info) {
   __shared__ double2 a[NB][NB + 1];  // a[i][j] = A(j0+i, j0+j)
   const int t = threadIdx.x;
-  for (int idx = t; idx < nb * nb; idx += blockDim.x) {
-    const int i = idx % nb, j = idx / nb;
-    a[i][j] = A[(j0 + i) + (j0 + j) * lda];
+  for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+    const int i = idx % NB, j = idx / NB;
+    if (i < nb && j < nb) a[i][j] = A[(j0 + i) + (j0 + j) * lda];
   }
   __syncthreads();
   for (int k = 0; k < nb; ++k) {
@@ -96,9 +96,9 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int nb, double2 *__rest
     }
     for (int j = k + 1 + t; j < nb; j += blockDim.x) a[k][j] = cscale(a[k][j], 1.0 / dk);
     __syncthreads();
-    for (int idx = t; idx < nb * nb; idx += blockDim.x) {
-      const int i = idx % nb, j = idx / nb;
-      if (i > k && j >= i) {
+    for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+      const int i = idx % NB, j = idx / NB;
+      if (i > k && j >= i && j < nb) {
         const double2 u = a[k][i], v = a[k][j];
         const double2 cu{u.x, -u.y};
         a[i][j] = csub(a[i][j], cmul(cu, v));
@@ -106,9 +106,9 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int nb, double2 *__rest
     }
     __syncthreads();
   }
-  for (int idx = t; idx < nb * nb; idx += blockDim.x) {
-    const int i = idx % nb, j = idx / nb;
-    if (i <= j) A[(j0 + i) + (j0 + j) * lda] = a[i][j];
+  for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+    const int i = idx % NB, j = idx / NB;
+    if (i <= j && j < nb) A[(j0 + i) + (j0 + j) * lda] = a[i][j];
   }
 }
 
@@ -153,33 +153,43 @@ __global__ void set_int_kernel(int *p, int v) {
 // ---------------------------------------------------------------- trtri ----
 // Invert the nb x nb upper triangular diagonal block in place (LDS).
 __global__ __launch_bounds__(256) void trtri_diag_kernel(int nb, double2 *__restrict__ A, int64_t lda, int64_t j0) {
+  static_assert(NB == 32, "one lane group of 32 per column block");
   __shared__ double2 a[NB][NB + 1];
   __shared__ double2 r[NB][NB + 1];
+  __shared__ double2 part[8][NB];
   const int t = threadIdx.x;
-  for (int idx = t; idx < nb * nb; idx += blockDim.x) {
-    const int i = idx % nb, j = idx / nb;
-    a[i][j] = (i <= j) ? A[(j0 + i) + (j0 + j) * lda] : double2{0, 0};
+  for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+    const int i = idx % NB, j = idx / NB;
+    if (i < nb && j < nb) a[i][j] = (i <= j) ? A[(j0 + i) + (j0 + j) * lda] : double2{0, 0};
   }
   __syncthreads();
-  // column j of the inverse: back substitution of U x = e_j (one thread per column)
-  if (t < nb) {
-    const int j = t;
-    for (int i = nb - 1; i >= 0; --i) {
-      double2 s = (i == j) ? double2{1.0, 0.0} : double2{0, 0};
-      if (i <= j) {
-        for (int k = i + 1; k <= j; ++k) s = csub(s, cmul(a[i][k], r[k][j]));
-        // divide by complex diagonal
+  // rows of R = U^-1 from the bottom: R[i][j] = (delta_ij - sum_{i<k<=j} U[i][k] R[k][j]) / U[i][i]
+  // for all j >= i at once; each column's sum is split over 8 groups of 32 threads
+  const int j = t & 31, g = t >> 5;
+  for (int i = nb - 1; i >= 0; --i) {
+    double2 s{0, 0};
+    if (j < nb && j > i)
+      for (int k = i + 1 + g; k <= j; k += 8) s = cadd(s, cmul(a[i][k], r[k][j]));
+    part[g][j] = s;
+    __syncthreads();
+    if (t < nb) {
+      double2 v{0, 0};
+      if (t >= i) {
+        double2 sum{0, 0};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sum = cadd(sum, part[q][t]);
+        v = csub((t == i) ? double2{1.0, 0.0} : double2{0, 0}, sum);
         const double2 d = a[i][i];
         const double den = d.x * d.x + d.y * d.y;
-        s = double2{(s.x * d.x + s.y * d.y) / den, (s.y * d.x - s.x * d.y) / den};
+        v = double2{(v.x * d.x + v.y * d.y) / den, (v.y * d.x - v.x * d.y) / den};
       }
-      r[i][j] = s;
+      r[i][t] = v;
     }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int idx = t; idx < nb * nb; idx += blockDim.x) {
-    const int i = idx % nb, j = idx / nb;
-    A[(j0 + i) + (j0 + j) * lda] = (i <= j) ? r[i][j] : double2{0, 0};
+  for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+    const int i = idx % NB, jj = idx / NB;
+    if (i < nb && jj < nb) A[(j0 + i) + (j0 + jj) * lda] = (i <= jj) ? r[i][jj] : double2{0, 0};
   }
 }
 
