@@ -70,6 +70,20 @@ def test_mixed_apply_H_generic_fft(name, generic, monkeypatch):
     assert col_rel_err(got.astype(np.complex128), H(X)) <= 2e-6
 
 
+@pytest.mark.parametrize("nb", [1, 2, 65])
+def test_mixed_apply_H_band_counts(nb):
+    """One, two and 65 bands: expansion tiles with one, two and one-past-a-tile
+    columns, FFT batches of one band."""
+    name = "n27"
+    H = hamiltonian(name)
+    s = system(name)
+    X = W.random_block(H.npw, nb, 13).astype(np.complex64).astype(np.complex128)
+    with _mixed(name) as g:
+        got = to_host(g.apply_H(_c64(X)))
+    assert got.shape == X.shape
+    assert col_rel_err(got.astype(np.complex128), H(X)) <= 2e-6
+
+
 def test_mixed_apply_H_config2_ragged():
     """77 bands of the medium workload: one full 64-band FFT batch and a ragged
     one, a full and a ragged expansion tile (128 x 64)."""
