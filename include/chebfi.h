@@ -193,7 +193,10 @@ abi_status abi_rayleigh_ritz(abi_system sys, void *Y, void *HPsi, int64_t nband,
  * degree-m filter and Rayleigh-Ritz on the block X, the Ritz vectors of a cycle
  * being the next cycle's block (the subspace iteration of Algorithm "Parallel
  * Chebyshev filtering of degree k", repeated), until the residual norms of the
- * lowest nconv Ritz pairs are all <= tol or max_cycles cycles have run.
+ * lowest nconv Ritz pairs are all <= tol or max_cycles cycles have run.  From
+ * the second cycle on, the bounds take the Rayleigh quotients of the block from
+ * the last Ritz values (they are equal for Ritz vectors) and keep the first
+ * cycle's Lanczos upper bound (H is fixed), so they apply no H.
  * X (in: start block; out: Ritz vectors, ascending Ritz values) is npw x nband
  * (ld) of `dtype`; v0: device, npw complex128.  With dtype ABI_C64 and
  * refine_degree > 0, the mixed cycles hand over to FP64 cycles of degree

@@ -881,14 +881,30 @@ abi_status abi_chebfi_solve(abi_system s, void *X, int64_t nband, int64_t ld, in
       for (int i = 0; i < nconv; ++i) m = std::max(m, res[i]);
       return m;
     };
-    // one cycle: bounds of A, filter A -> B, Rayleigh-Ritz in place on B
+    // one cycle: bounds of A, filter A -> B, Rayleigh-Ritz in place on B.  From the
+    // second cycle on, A holds Ritz vectors, whose Rayleigh quotients are their Ritz
+    // values (the last Rayleigh-Ritz step's eval), and H is fixed, so the first
+    // cycle's Lanczos upper bound still holds: the bounds need no H application.
+    bool have_ritz = false;
+    double b_upper = 0.0;
     auto cycle = [&](void *A, void *Bk, int64_t l, int32_t dt, int32_t m) {
-      double bd[3];
-      call(abi_spectral_bounds(s, A, nband, l, dt, v0, 10, bd, stream));
+      double bd[3] = {0.0, 0.0, 0.0};
+      bool reuse = false;
+      if (have_ritz) {
+        bd[0] = *std::max_element(eval, eval + nband);
+        bd[2] = *std::min_element(eval, eval + nband);
+        bd[1] = b_upper;
+        reuse = bd[1] > bd[0];
+      }
+      if (!reuse) {
+        call(abi_spectral_bounds(s, A, nband, l, dt, v0, 10, bd, stream));
+        b_upper = bd[1];
+      }
       call(abi_cheb_filter(s, A, Bk, nband, l, dt, m, bd[0], bd[1], bd[2], stream));
       int32_t flags = 0;
       call(abi_rayleigh_ritz(s, Bk, nullptr, nband, l, dt, eval, res.data(), nullptr, &flags,
                              stream));
+      have_ritz = true;
     };
     const bool refine = refine_degree > 0;
     // the mixed cycles hand over to the FP64 refinement when they stall (a cycle
