@@ -187,6 +187,26 @@ def test_rayleigh_ritz(name):
     assert _principal_sines(Psi[:, :p], rr["Psi"][:, :p]) <= 1e-7
 
 
+@pytest.mark.parametrize("nb", [1, 2])
+def test_rayleigh_ritz_one_and_two_bands(nb):
+    """The smallest blocks: 1 x 1 and 2 x 2 Hermitian Grams (one partial tile),
+    Cholesky and eigensolver of size 1 and 2."""
+    s = system("n27")
+    H = hamiltonian("n27")
+    X = W.random_block(H.npw, nb, 7)
+    rr = O.rayleigh_ritz(H, X)
+    res_ref = O.residual_norms(rr["Psi"], rr["HPsi"], rr["eval"])
+    import torch
+    with B.System(s) as g:
+        Yd = to_dev(X)
+        ev, res, flags = g.rayleigh_ritz(Yd)
+        Psi = to_host(Yd)
+    assert flags == 0
+    assert np.abs(ev - rr["eval"]).max() <= 1e-10 * max(1.0, np.abs(rr["eval"]).max())
+    assert np.abs(Psi.conj().T @ Psi - np.eye(nb)).max() <= 1e-12
+    assert np.abs(res - res_ref).max() <= 1e-9 * max(1.0, np.abs(res_ref).max())
+
+
 @pytest.mark.parametrize("nb", [77, 130])
 def test_rayleigh_ritz_ragged_tiles(nb):
     """Rayleigh-Ritz of 77 and 130 bands of the medium workload: the Hermitian
