@@ -400,6 +400,24 @@ abi_status abi_batch_use_graph(abi_batch batch, int32_t on);
 
 abi_status abi_destroy_batch(abi_batch batch);
 
+/* ---- tuning --------------------------------------------------------------------
+ * Launch choices of a handle's kernels.  Every choice computes the same
+ * product; variants of one class agree to rounding (the split-BF16 ones are
+ * bit for bit equal when they sum the same K chunks in the same order).
+ *   ABI_TUNE_PROJ      split-BF16 projection P^H X: 0..3, 5..8 tile variants on
+ *                      planes made by a split pass; 4 register-staged 128 x 128
+ *                      reading the complex64 block; 9, 10 direct-to-LDS 128 x 128
+ *                      reading the block (2 x 2 / 1 x 4 waves)
+ *   ABI_TUNE_EXPAND    split-BF16 expansion P C': 0..6 register-staged tiles,
+ *                      7, 8 direct-to-LDS 128 x 128 (2 x 2 / 1 x 4 waves)
+ *   ABI_TUNE_FFT_BATCH bands per FFT batch (1..4096)
+ *   ABI_TUNE_OVERLAP   0/1: FFT passes on a second stream beside the projection
+ * Fails with ABI_ERR_ARG for an unknown parameter or a value out of range, and
+ * with ABI_ERR_STATE for a split-BF16 parameter on an FP64 handle. */
+enum { ABI_TUNE_PROJ = 0, ABI_TUNE_EXPAND = 1, ABI_TUNE_FFT_BATCH = 2, ABI_TUNE_OVERLAP = 3 };
+abi_status abi_set_tuning(abi_system sys, int32_t param, int32_t value);
+abi_status abi_get_tuning(abi_system sys, int32_t param, int32_t *value);
+
 /* ---- timing ------------------------------------------------------------------
  * Per-kernel-class timing with HIP events recorded on the stream of each call
  * (the method of the paper's section "Single-step benchmarks: GPU kernel

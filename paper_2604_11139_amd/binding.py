@@ -40,7 +40,7 @@ EXPORTS = [
     "abi_batch_system", "abi_cheb_filter_batch", "abi_batch_autotune", "abi_batch_use_graph",
     "abi_destroy_batch", "abi_chebfi_solve", "abi_apply_S", "abi_apply_Sinv", "abi_overlap_info",
     "abi_lobpcg_solve", "abi_density_add", "abi_occupations", "abi_scf_potential", "abi_scf_solve",
-    "abi_get_potential",
+    "abi_get_potential", "abi_set_tuning", "abi_get_tuning",
 ]
 
 PROFILE_CLASSES = ["proj_gemm", "expand_gemm", "fft_a", "fft_b", "fft_c", "dapply", "gram",
@@ -69,6 +69,8 @@ class Desc(ctypes.Structure):
         ("qij", POINTER(c_double)),
     ]
 
+
+TUNE_PROJ, TUNE_EXPAND, TUNE_FFT_BATCH, TUNE_OVERLAP = 0, 1, 2, 3
 
 _lib = None
 
@@ -104,6 +106,8 @@ def lib():
         "abi_filter_backward": [vp, vp, vp, c_int64, c_int64, c_int32, c_int32, c_double,
                                 c_double, c_double, c_int32, vp, vp, vp, vp],
         "abi_profile_read": [vp, c_int32, vp, vp, vp],
+        "abi_set_tuning": [vp, c_int32, c_int32],
+        "abi_get_tuning": [vp, c_int32, POINTER(c_int32)],
         "abi_set_system_batch": [vp, c_int32, vp, POINTER(vp)],
         "abi_batch_system": [vp, c_int32, POINTER(vp)],
         "abi_cheb_filter_batch": [vp, vp, vp, vp, vp, c_int32, c_int32, vp, vp, vp, vp],
@@ -480,6 +484,15 @@ class System:
 
     def profile(self, on=True):
         _check(lib().abi_profile_enable(self._h, 1 if on else 0))
+
+    def set_tuning(self, param, value):
+        """Sets one launch choice (TUNE_* parameter) of this handle."""
+        _check(lib().abi_set_tuning(self._h, int(param), int(value)))
+
+    def get_tuning(self, param):
+        v = c_int32(0)
+        _check(lib().abi_get_tuning(self._h, int(param), ctypes.byref(v)))
+        return v.value
 
     def profile_read(self):
         """{class: (total_ms, work, count)} for the launches timed so far."""

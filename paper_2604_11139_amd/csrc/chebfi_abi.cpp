@@ -565,7 +565,7 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
       // split-BF16 planes in the two k-contiguous layouts the projector GEMMs read
       const int64_t npw = s->npw, np = s->nproj;
       s->ldPA = (npw + 63) / 64 * 64;
-      s->ldPB = (np + 7) / 8 * 8;
+      s->ldPB = (np + 31) / 32 * 32;  // zero planes up to the 32-wide K slices
       const size_t szA = (size_t)np * s->ldPA, szB = (size_t)npw * s->ldPB;
       std::vector<uint16_t> PA(4 * szA, 0), PB(4 * szB, 0);
       for (int64_t j = 0; j < np; ++j)
@@ -586,13 +586,14 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
       // 0: split-BF16 planes x planes (default), 1: FP32 MFMA, 2: split-BF16 with the
       // block split while staged
       if (const char *e = std::getenv("CHEBFI_MIXED_GEMM")) s->mixed_gemm = std::atoi(e);
-      // tile variants of the split-BF16 products (tuning knobs, 0..6)
-      // projection: the double-buffered 128 x 128 tile with the block split while
-      // staged; expansion: the single-stage 128 x 64 tile, two workgroups per CU
-      s->pl_proj = 4;
-      s->pl_expand = 6;
-      if (const char *e = std::getenv("CHEBFI_PL_PROJ")) s->pl_proj = std::min(6, std::max(0, std::atoi(e)));
-      if (const char *e = std::getenv("CHEBFI_PL_EXPAND")) s->pl_expand = std::min(6, std::max(0, std::atoi(e)));
+      // tile variants of the split-BF16 products (abi_set_tuning): both default to
+      // the direct-to-LDS 128 x 128 tile with eight waves and the scheduled
+      // fragment reads (the projection splits the block into planes as it reads
+      // its fragments)
+      s->pl_proj = 14;
+      s->pl_expand = 13;
+      if (const char *e = std::getenv("CHEBFI_PL_PROJ")) s->pl_proj = std::min(10, std::max(0, std::atoi(e)));
+      if (const char *e = std::getenv("CHEBFI_PL_EXPAND")) s->pl_expand = std::min(8, std::max(0, std::atoi(e)));
     }
     // bands per FFT batch: keep the box buffer near 128 MiB (env override)
     int64_t fb = (int64_t)((128ll << 20) / (sizeof(double2) * nbox));
@@ -1127,17 +1128,9 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
     const bool planes = fp32 && s->mixed_gemm == 0;
     auto project = [&](const void *Z, int64_t ldz, void *out) {
       if (planes) {
-        const int splits = proj_planes_splits(s->pl_proj, nproj, nband, npw);
+        const int splits = mixed_proj_splits(s, nband);
         void *part = s->cpart.get(sizeof(float2) * (size_t)splits * nproj * nband);
-        if (s->pl_proj == 4) {
-          proj_gemm_planes_f32(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, Z,
-                               ldz, part, splits, st);
-        } else {
-          void *zpl = s->planes.get(8 * (size_t)s->ldPA * nband);
-          split_planes(npw, nband, Z, ldz, zpl, s->ldPA, st);
-          proj_gemm_planes(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, zpl,
-                           s->ldPA, s->ldPA * nband, part, splits, st, s->pl_proj);
-        }
+        mixed_project(s, Z, ldz, nband, part, splits, st);
         launch_sum_parts(nproj, nband, part, splits, out, st, true);
       } else {
         const int splits = zgemm_splits(nproj, nband, npw);
@@ -1232,16 +1225,11 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
             project(Yk, ldy, CY);
           launch_dd_accum(natom, nband, CA, cy, gam[k], dD_acc, st, fp32);
           launch_dapply(natom, nband, CA, 1, s->d_D, gam[k], Cp, st, fp32);
-          if (planes)
-            split_planes(nproj, nband, Cp, nproj, s->cplanes.get(8 * (size_t)s->ldPB * nband),
-                         s->ldPB, st);
         }
         if (side) CHEBFI_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
         if (nproj > 0) {
           if (planes)
-            expand_gemm_planes(npw, nband, nproj, s->d_PB, s->ldPB, npw * s->ldPB,
-                               s->cplanes.ptr, s->ldPB, s->ldPB * nband, Ak, npw, st,
-                               s->pl_expand);
+            mixed_expand(s, Cp, Ak, npw, nband, st, true);
           else
             expand_gemm(npw, nband, nproj, fp32 ? (const void *)s->d_Pf : (const void *)s->d_P,
                         Cp, Ak, npw, st, fp32);
@@ -1401,6 +1389,48 @@ abi_status abi_scf_solve(abi_system s, void *X, int64_t nband, int64_t ld, int32
       info[1] = converged;
       info[2] = 0;
       info[3] = 0;
+    }
+  });
+}
+
+abi_status abi_set_tuning(abi_system s, int32_t param, int32_t value) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(s != nullptr, ABI_ERR_ARG, "system handle is NULL");
+    const bool mixed = s->precision == ABI_PREC_MIXED;
+    switch (param) {
+      case ABI_TUNE_PROJ:
+        CHEBFI_REQUIRE(mixed, ABI_ERR_STATE, "split-BF16 variants need a mixed handle");
+        CHEBFI_REQUIRE(value >= 0 && value <= 14, ABI_ERR_ARG, "projection variant out of range");
+        s->pl_proj = value;
+        break;
+      case ABI_TUNE_EXPAND:
+        CHEBFI_REQUIRE(mixed, ABI_ERR_STATE, "split-BF16 variants need a mixed handle");
+        CHEBFI_REQUIRE(value >= 0 && value <= 14, ABI_ERR_ARG, "expansion variant out of range");
+        s->pl_expand = value;
+        break;
+      case ABI_TUNE_FFT_BATCH:
+        CHEBFI_REQUIRE(value >= 1 && value <= 4096, ABI_ERR_ARG, "FFT batch out of range");
+        s->fft_batch = value;
+        break;
+      case ABI_TUNE_OVERLAP:
+        CHEBFI_REQUIRE(value == 0 || value == 1, ABI_ERR_ARG, "overlap is 0 or 1");
+        s->overlap = value;
+        break;
+      default:
+        CHEBFI_REQUIRE(false, ABI_ERR_ARG, "unknown tuning parameter");
+    }
+  });
+}
+
+abi_status abi_get_tuning(abi_system s, int32_t param, int32_t *value) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(s != nullptr && value != nullptr, ABI_ERR_ARG, "NULL argument");
+    switch (param) {
+      case ABI_TUNE_PROJ: *value = s->pl_proj; break;
+      case ABI_TUNE_EXPAND: *value = s->pl_expand; break;
+      case ABI_TUNE_FFT_BATCH: *value = s->fft_batch; break;
+      case ABI_TUNE_OVERLAP: *value = s->overlap; break;
+      default: CHEBFI_REQUIRE(false, ABI_ERR_ARG, "unknown tuning parameter");
     }
   });
 }

@@ -18,6 +18,51 @@
 namespace chebfi {
 namespace {
 
+// Projection variants 4 and 9..10 read the complex64 block itself (split into
+// bf16 planes while staged); the others read planes made by a separate pass.
+static bool proj_reads_block(int variant) { return variant == 4 || variant >= 9; }
+
+}  // namespace
+
+int mixed_proj_splits(abi_system_s *s, int64_t nband) {
+  // 9..12 share the 128 x 128 tile of planes variant 7, 13 the 128 x 256 one of 12
+  const int v = s->pl_proj == 13 ? 12 : s->pl_proj >= 9 ? 7 : s->pl_proj;  // 14: as 9
+  return proj_planes_splits(v, s->nproj, nband, s->npw);
+}
+
+void mixed_project(abi_system_s *s, const void *X, int64_t ldx, int64_t nband, void *part,
+                   int splits, hipStream_t st) {
+  const int64_t npw = s->npw;
+  const int nproj = s->nproj;
+  const int v = s->pl_proj;
+  const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
+  if (proj_reads_block(v)) {
+    const int tok = s->prof.begin(PROF_PROJ, flops, st);
+    proj_gemm_f32_variant(v == 4 ? 0 : v - 8, nproj, nband, npw, s->d_PA, s->ldPA,
+                          (int64_t)nproj * s->ldPA, X, ldx, part, splits, st);
+    s->prof.end(tok, st);
+    return;
+  }
+  void *xpl = s->planes.get(8 * (size_t)s->ldPA * nband);
+  const int tk = s->prof.begin(PROF_SPLIT, 16.0 * (double)npw * (double)nband, st);
+  split_planes(npw, nband, X, ldx, xpl, s->ldPA, st);
+  s->prof.end(tk, st);
+  const int tok = s->prof.begin(PROF_PROJ, flops, st);
+  proj_gemm_planes(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, xpl, s->ldPA,
+                   s->ldPA * nband, part, splits, st, v);
+  s->prof.end(tok, st);
+}
+
+void mixed_expand(abi_system_s *s, const void *Cp, void *Out, int64_t ldo, int64_t nband,
+                  hipStream_t st, bool accumulate) {
+  const int nproj = s->nproj;
+  split_planes(nproj, nband, Cp, nproj, s->cplanes.get(8 * (size_t)s->ldPB * nband), s->ldPB, st);
+  expand_gemm_planes(s->npw, nband, nproj, s->d_PB, s->ldPB, s->npw * s->ldPB, s->cplanes.ptr,
+                     s->ldPB, s->ldPB * nband, Out, ldo, st, s->pl_expand, accumulate);
+}
+
+namespace {
+
 // Projector products of a block: part[z] = P^H X over plane-wave chunk z
 // (returns the chunk count).  T = double: FP64 MFMA (a matrix-vector product
 // for one band); T = float: complex64 block, split-BF16 MFMA (FP32 MFMA with
@@ -33,29 +78,19 @@ int project_t(abi_system_s *s, const void *X, int64_t ldx, int64_t nband, hipStr
   const bool single = (nband == 1) && !fp32;
   const bool planes = fp32 && s->mixed_gemm == 0;
   const int splits = single ? 1
-                     : planes ? proj_planes_splits(s->pl_proj, nproj, nband, npw)
+                     : planes ? mixed_proj_splits(s, nband)
                               : zgemm_splits(nproj, nband, npw);
   V2 *cpart = (V2 *)s->cpart.get(sizeof(V2) * (size_t)splits * nproj * nband);
   const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
-  // the default split-BF16 projection splits the block into planes while staging it;
-  // the other tile variants read planes made by a separate pass
-  const bool staged = planes && s->pl_proj == 4;
-  void *xpl = nullptr;
-  if (planes && !staged) {
-    xpl = s->planes.get(8 * (size_t)s->ldPA * nband);
-    const int tk = s->prof.begin(PROF_SPLIT, 16.0 * (double)npw * (double)nband, st);
-    split_planes(npw, nband, X, ldx, xpl, s->ldPA, st);
-    s->prof.end(tk, st);
+  // the split-BF16 products time themselves (a planes variant's split pass apart)
+  if (planes) {
+    mixed_project(s, X, ldx, nband, cpart, splits, st);
+    *part_out = cpart;
+    return splits;
   }
   const int tok = s->prof.begin(PROF_PROJ, flops, st);
   if (single)
     proj_gemv(npw, nproj, P, X, cpart, st);
-  else if (staged)
-    proj_gemm_planes_f32(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, X, ldx,
-                         cpart, splits, st);
-  else if (planes)
-    proj_gemm_planes(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, xpl,
-                     s->ldPA, s->ldPA * nband, cpart, splits, st, s->pl_proj);
   else if (fp32 && s->mixed_gemm == 2)
     proj_gemm_bf16x3(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, X, ldx,
                      cpart, splits, st);

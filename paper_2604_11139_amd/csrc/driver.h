@@ -44,6 +44,17 @@ void gen_step(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, in
               const double2 *Ck, const double2 *Ckm1, double2 *Cnext, hipStream_t st,
               int32_t dtype);
 
+// Split-BF16 projector products of the mixed form with the handle's tile
+// variants (s->pl_proj, s->pl_expand).  mixed_proj_splits: K-split count of the
+// projection of nband bands; mixed_project: part[z] = P^H X over K chunk z
+// (complex float, splits x nproj x nband); mixed_expand: Out = P C' (or Out +=
+// P C' with accumulate) for complex float C' (nproj x nband, ld nproj).
+int mixed_proj_splits(abi_system_s *s, int64_t nband);
+void mixed_project(abi_system_s *s, const void *X, int64_t ldx, int64_t nband, void *part,
+                   int splits, hipStream_t st);
+void mixed_expand(abi_system_s *s, const void *Cp, void *Out, int64_t ldo, int64_t nband,
+                  hipStream_t st, bool accumulate);
+
 // C = P^H X in complex double (nproj x nband, contiguous).
 void project_c128(abi_system_s *s, const void *X, int64_t ldx, int64_t nband, double2 *C,
                   hipStream_t st, int32_t dtype);

@@ -11,6 +11,8 @@
 // while the current one is multiplied.  Tall-skinny products (K = npw) are
 // split along K; each chunk writes its own partial product and a separate pass
 // adds the chunks in a fixed order, so results do not depend on scheduling.
+#include <type_traits>
+
 #include "cplx.h"
 #include "kernels.h"
 
@@ -1042,16 +1044,639 @@ __global__ __launch_bounds__(64 * NWM * NWN, 2) void zgemm_pl2_kernel(
       }
 }
 
+// ---- split-BF16 products with direct global -> LDS staging -------------------
+// gfx950's global_load_lds moves 4 or 16 bytes per lane from global memory
+// straight into LDS (lane l's bytes land at the wave's LDS address + l * size).
+// Staging a K slice then takes no VGPRs and no ds_write instructions: the waves
+// issue the next slice's loads and go on multiplying the current one, and the
+// only wait is one vmcnt before the barrier that ends the step.
+//
+// Operands.  A: four bf16 planes, rows = output rows, K contiguous (row stride
+// lda, plane stride psa), zero beyond the true K up to kpad (a multiple of 32).
+// B (PLANES): the same layout with rows = output columns.  B (BF32): a complex
+// float block, column j = output column j, K contiguous (ld ldb); it is staged
+// raw and split into its four bf16 planes when a wave reads its fragment
+// (v_cvt_pk_bf16_f32: round to nearest even, the rounding of the planes of A).
+// K indices at or beyond kdata are read at kdata - 1 (a finite value that
+// meets a zero of A); rows and columns beyond m, n are read at m - 1, n - 1 and
+// their results are not stored.  So no load leaves the operands' storage.
+//
+// LDS, one stage: A as [plane][row][32] bf16 with the 16-byte chunk kc of row i
+// at position kc ^ ((i >> 1) & 3) (B planes alike); B32 as [column][32]
+// complex float with the 16-byte chunk c (two complex) of column j at position
+// c ^ (j & 7).  Both layouts make the fragment reads free of bank conflicts.
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void dma16(const void *g, unsigned char *lds) {
+  __builtin_amdgcn_global_load_lds(g, (lds_void_t *)lds, 16, 0, 0);
+}
+__device__ __forceinline__ void dma4(const void *g, unsigned char *lds) {
+  __builtin_amdgcn_global_load_lds(g, (lds_void_t *)lds, 4, 0, 0);
+}
+// s_waitcnt vmcnt(N) (gfx9 encoding: vmcnt[3:0] at bits 3:0, vmcnt[5:4] at
+// bits 15:14; expcnt and lgkmcnt left at their maxima)
+template <int N> __device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// x (two floats) -> hi = bf16(x), lo = bf16(x - hi), both round to nearest even
+__device__ __forceinline__ void split2(f2v_t x, bf2_t &hi, bf2_t &lo) {
+  hi = __builtin_convertvector(x, bf2_t);
+  lo = __builtin_convertvector(x - __builtin_convertvector(hi, f2v_t), bf2_t);
+}
+__device__ __forceinline__ v8bf cat4(bf2_t a, bf2_t b, bf2_t c, bf2_t d) {
+  typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
+  const bf4_t ab = __builtin_shufflevector(a, b, 0, 1, 2, 3);
+  const bf4_t cd = __builtin_shufflevector(c, d, 0, 1, 2, 3);
+  return __builtin_shufflevector(ab, cd, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+template <int BM, int BN, int NWM, int NWN, bool CONJ, bool SPLIT, bool BF32, bool PIPE = false>
+__global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl_kernel(
+    int64_t m, int64_t n, int64_t kdata, const u16 *__restrict__ Apl, int64_t lda, int64_t psa,
+    const void *__restrict__ Bsrc, int64_t ldb, int64_t psb, float2 *__restrict__ C,
+    int64_t ldc, int64_t kchunk, int64_t kpad, float2 *__restrict__ part, int accum) {
+  constexpr int NW = NWM * NWN;
+  constexpr int SM = BM / NWM / 16, SN = BN / NWN / 16;
+  constexpr int A_BYTES = 4 * BM * 64;                       // 4 planes x BM rows x 32 bf16
+  constexpr int B_BYTES = BF32 ? BN * 256 : 4 * BN * 64;     // BN columns x 32 complex float
+  constexpr int STAGE = A_BYTES + B_BYTES;
+  constexpr int QA = BM / 4 / NW;                    // 1 KB loads (16 rows of a plane) per wave
+  constexpr int QB = BF32 ? BN / NW : BN / 4 / NW;   // BF32: 256 B loads (one column) per wave
+  static_assert(QA * 4 * NW == BM && (BF32 ? QB * NW == BN : QB * 4 * NW == BN), "tile / waves");
+  static_assert(SM >= 1 && SN >= 1, "wave tile");
+  // the two stages are separate LDS objects, so that the compiler can tell the
+  // loads streaming into one stage from the fragment reads of the other (one
+  // array indexed by the step parity would make it wait for the loads first)
+  __shared__ __align__(16) unsigned char stage0[STAGE];
+  __shared__ __align__(16) unsigned char stage1[STAGE];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave % NWM, wn = wave / NWM;
+  unsigned tm, tn, tz;
+  grouped_tile(SPLIT ? gridDim.x : 4u, tm, tn, tz);
+  const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
+  const int64_t kbeg = (int64_t)tz * kchunk;
+  const int64_t kend = (kbeg + kchunk < kpad) ? kbeg + kchunk : kpad;
+  const int ns = kend > kbeg ? (int)((kend - kbeg) >> 5) : 0;
+
+  // Load addresses: a wave-uniform base (scalar registers) plus a 32-bit lane
+  // offset fixed for the tile.  Load q of A covers rows r0 .. r0 + 15 of plane
+  // p; lane l its row r0 + (l >> 2) (clamped to m - 1) and 16-byte chunk
+  // (l & 3) ^ ((row >> 1) & 3) (the same for every q, r0 being a multiple of
+  // 16).  B planes alike.  B32: load q covers column c = wave QB + q (clamped
+  // to n - 1; uniform), lane l the dword l & 3 of the 16-byte chunk at
+  // position l >> 2, which holds chunk (l >> 2) ^ (c & 7) of the column.
+  static_assert(!BF32 || QB % 8 == 0, "B32 lane patterns repeat every 8 columns");
+  const int kcl = (lane & 3) ^ ((lane >> 3) & 3);
+  uint32_t aofs[QA];  // byte offsets
+#pragma unroll
+  for (int q = 0; q < QA; ++q) {
+    const int r0 = ((wave * QA + q) % (BM / 16)) * 16, r = r0 + (lane >> 2);
+    const int64_t rr = row0 + r < m ? r : m - 1 - row0;
+    aofs[q] = (uint32_t)(2 * (rr * lda + 8 * kcl));
+  }
+  uint32_t bofs[BF32 ? 8 : QB];  // byte offsets
+  if constexpr (BF32) {
+#pragma unroll
+    for (int c8 = 0; c8 < 8; ++c8) {
+      const int ch = (lane >> 2) ^ c8, w = lane & 3;
+      bofs[c8] = (uint32_t)(4 * (2 * (2 * ch + (w >> 1)) + (w & 1)));
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int r0 = ((wave * QB + q) % (BN / 16)) * 16, r = r0 + (lane >> 2);
+      const int64_t rr = col0 + r < n ? r : n - 1 - col0;
+      bofs[q] = (uint32_t)(2 * (rr * ldb + 8 * kcl));
+    }
+  }
+  // (uniform base + zero-extended 32-bit byte offset: the scalar-base form of
+  // the load instruction)
+  auto issue_k = [&](int64_t k0, unsigned char *st, auto tail_c) {
+    constexpr bool TAIL = decltype(tail_c)::value;
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int qq = wave * QA + q, p = qq / (BM / 16), r0 = (qq % (BM / 16)) * 16;
+      const char *base = (const char *)(Apl + (int64_t)p * psa + row0 * lda + k0);
+      dma16(base + aofs[q], st + p * BM * 64 + r0 * 64);
+    }
+    if constexpr (BF32) {
+      const char *base = (const char *)((const float *)Bsrc + 2 * (col0 * ldb + k0));
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        const int c = wave * QB + q;
+        const uint32_t cofs = (uint32_t)(8 * (col0 + c < n ? c : n - 1 - col0) * ldb);
+        uint32_t off = bofs[q & 7];
+        if constexpr (TAIL) {
+          // complex index k0 + off / 8 past the data: read the last one
+          if (k0 + (off >> 3) >= kdata) off = (uint32_t)(8 * (kdata - 1 - k0)) + (off & 4);
+        }
+        dma4(base + (cofs + off), st + A_BYTES + c * 256);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        const int qq = wave * QB + q, p = qq / (BN / 16), r0 = (qq % (BN / 16)) * 16;
+        const char *base = (const char *)((const u16 *)Bsrc + (int64_t)p * psb + col0 * ldb + k0);
+        dma16(base + bofs[q], st + A_BYTES + p * BN * 64 + r0 * 64);
+      }
+    }
+  };
+  auto issue = [&](int s, unsigned char *st) {
+    const int64_t k0 = kbeg + 32 * (int64_t)s;
+    // only a B32 slice reaching past the data clamps its K indices
+    if (BF32 && k0 + 32 > kdata)
+      issue_k(k0, st, std::integral_constant<bool, true>{});
+    else
+      issue_k(k0, st, std::integral_constant<bool, false>{});
+  };
+
+  // PIPE: the product's minus sign rides on a third accumulator (subtracted in
+  // the epilogue) instead of negated planes, the A fragments of row block i + 1
+  // are read while row block i is multiplied, and the reads are spread over
+  // the MFMAs with scheduling groups
+  constexpr int NACC = PIPE ? 3 : 2;
+  v4f acc[SM][SN][NACC];
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j)
+#pragma unroll
+      for (int c = 0; c < NACC; ++c) acc[i][j][c] = v4f{0, 0, 0, 0};
+
+  const int kq = lane >> 4;
+  auto b_frag = [&](const unsigned char *st, int j, v8bf *b) {
+    const int jj = wn * (BN / NWN) + j * 16 + (lane & 15);
+    if constexpr (BF32) {
+      // eight complex of column jj (K 8 kq .. 8 kq + 7) -> four bf16 planes
+      float4 q4[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int off = A_BYTES + jj * 256 + 16 * ((4 * kq + t) ^ (jj & 7));
+        q4[t] = *reinterpret_cast<const float4 *>(st + off);
+      }
+      bf2_t rh[4], rl[4], ih[4], il[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        split2(f2v_t{q4[t].x, q4[t].z}, rh[t], rl[t]);
+        split2(f2v_t{q4[t].y, q4[t].w}, ih[t], il[t]);
+      }
+      b[0] = cat4(rh[0], rh[1], rh[2], rh[3]);
+      b[1] = cat4(ih[0], ih[1], ih[2], ih[3]);
+      b[2] = cat4(rl[0], rl[1], rl[2], rl[3]);
+      b[3] = cat4(il[0], il[1], il[2], il[3]);
+    } else {
+      const int kb = 16 * (kq ^ ((jj >> 1) & 3));
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        b[p] = *reinterpret_cast<const v8bf *>(st + (A_BYTES + p * BN * 64 + jj * 64 + kb));
+    }
+  };
+  auto a_frag = [&](const unsigned char *st, int i, v8bf *a) {
+    const int ii = wm * (BM / NWM) + i * 16 + (lane & 15);
+    const int kb = 16 * (kq ^ ((ii >> 1) & 3));
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+      a[p] = *reinterpret_cast<const v8bf *>(st + (p * BM * 64 + ii * 64 + kb));
+  };
+  auto mma = [&](const unsigned char *st) {
+    v8bf b[SN][4];
+#pragma unroll
+    for (int j = 0; j < SN; ++j) b_frag(st, j, b[j]);
+    if constexpr (PIPE) {
+      v8bf a[2][4];
+      a_frag(st, 0, a[0]);
+#pragma unroll
+      for (int i = 0; i < SM; ++i) {
+        if (i + 1 < SM) a_frag(st, i + 1, a[(i + 1) & 1]);
+        const v8bf *ai = a[i & 1];
+#pragma unroll
+        for (int j = 0; j < SN; ++j) {
+          // planes 0 Re hi, 1 Im hi, 2 Re lo, 3 Im lo; acc 0 / 1 Re / Im with
+          // plus signs, acc 2 the minus-signed product (Im A Im B for op(A) = A,
+          // Im A Re B for op(A) = A^H)
+          v4f re = acc[i][j][0], im = acc[i][j][1], ng = acc[i][j][2];
+          re = mfma_bf16(b[j][0], ai[0], re);
+          re = mfma_bf16(b[j][2], ai[0], re);
+          re = mfma_bf16(b[j][0], ai[2], re);
+          im = mfma_bf16(b[j][1], ai[0], im);
+          im = mfma_bf16(b[j][3], ai[0], im);
+          im = mfma_bf16(b[j][1], ai[2], im);
+          if (CONJ) {
+            re = mfma_bf16(b[j][1], ai[1], re);
+            re = mfma_bf16(b[j][3], ai[1], re);
+            re = mfma_bf16(b[j][1], ai[3], re);
+            ng = mfma_bf16(b[j][0], ai[1], ng);
+            ng = mfma_bf16(b[j][2], ai[1], ng);
+            ng = mfma_bf16(b[j][0], ai[3], ng);
+          } else {
+            ng = mfma_bf16(b[j][1], ai[1], ng);
+            ng = mfma_bf16(b[j][3], ai[1], ng);
+            ng = mfma_bf16(b[j][1], ai[3], ng);
+            im = mfma_bf16(b[j][0], ai[1], im);
+            im = mfma_bf16(b[j][2], ai[1], im);
+            im = mfma_bf16(b[j][0], ai[3], im);
+          }
+          acc[i][j][0] = re;
+          acc[i][j][1] = im;
+          acc[i][j][2] = ng;
+        }
+      }
+      // order: the step's first fragments, then per row block the next block's
+      // four reads spread over the first MFMAs, the conversions of BF32 B
+      // fragments with the MFMAs
+      constexpr int MF = 12 * SN;  // MFMAs per row block
+      __builtin_amdgcn_sched_group_barrier(0x100, 4 * SN + 4, 0);
+      if constexpr (BF32) {
+        // the conversions of column block j + 1 run under the MFMAs of block j
+        // in the first row block (about four VALU instructions per MFMA)
+        __builtin_amdgcn_sched_group_barrier(0x002, 48, 0);
+#pragma unroll
+        for (int j = 0; j + 1 < SN; ++j)
+#pragma unroll
+          for (int r = 0; r < 12; ++r) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+          }
+      }
+#pragma unroll
+      for (int i = 0; i < SM; ++i) {
+        if (BF32 && i == 0 && SM > 1) {
+          // last column block of the first row block, with the next A reads
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          }
+          __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+        } else if (i + 1 < SM) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          }
+          __builtin_amdgcn_sched_group_barrier(0x008, MF - 8, 0);
+        } else {
+          __builtin_amdgcn_sched_group_barrier(0x008, MF, 0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < SM; ++i) {
+        v8bf a[6];
+        a_frag(st, i, a);
+        a[4] = bf16_neg(a[1]);
+        a[5] = bf16_neg(a[3]);
+#pragma unroll
+        for (int j = 0; j < SN; ++j) {
+          v4f re = acc[i][j][0], im = acc[i][j][1];
+          re = mfma_bf16(b[j][0], a[0], re);
+          re = mfma_bf16(b[j][2], a[0], re);
+          re = mfma_bf16(b[j][0], a[2], re);
+          re = mfma_bf16(b[j][1], a[CONJ ? 1 : 4], re);
+          re = mfma_bf16(b[j][3], a[CONJ ? 1 : 4], re);
+          re = mfma_bf16(b[j][1], a[CONJ ? 3 : 5], re);
+          im = mfma_bf16(b[j][1], a[0], im);
+          im = mfma_bf16(b[j][3], a[0], im);
+          im = mfma_bf16(b[j][1], a[2], im);
+          im = mfma_bf16(b[j][0], a[CONJ ? 4 : 1], im);
+          im = mfma_bf16(b[j][2], a[CONJ ? 4 : 1], im);
+          im = mfma_bf16(b[j][0], a[CONJ ? 5 : 3], im);
+          acc[i][j][0] = re;
+          acc[i][j][1] = im;
+        }
+      }
+    }
+  };
+
+  // two stages: slice s + 1 streams into the other stage while slice s is
+  // multiplied; the barrier after the wait both publishes slice s + 1 and
+  // frees the stage that slice s + 2 will overwrite
+  if (ns > 0) issue(0, stage0);
+  for (int s = 0; s < ns; s += 2) {
+    wait_vmcnt<0>();
+    __syncthreads();
+    if (s + 1 < ns) issue(s + 1, stage1);
+    mma(stage0);
+    if (s + 1 >= ns) break;
+    wait_vmcnt<0>();
+    __syncthreads();
+    if (s + 2 < ns) issue(s + 2, stage0);
+    mma(stage1);
+  }
+
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + wm * (BM / NWM) + i * 16 + (lane & 15);
+        const int64_t col = col0 + wn * (BN / NWN) + j * 16 + 4 * (lane >> 4) + r;
+        if (row < m && col < n) {
+          float2 v{acc[i][j][0][r], acc[i][j][1][r]};
+          if constexpr (PIPE) {
+            if (CONJ)
+              v.y -= acc[i][j][NACC - 1][r];
+            else
+              v.x -= acc[i][j][NACC - 1][r];
+          }
+          if (SPLIT) {
+            part[(int64_t)tz * m * n + row + col * m] = v;
+          } else if (accum) {
+            float2 o = C[row + col * ldc];
+            o.x += v.x;
+            o.y += v.y;
+            C[row + col * ldc] = o;
+          } else {
+            C[row + col * ldc] = v;
+          }
+        }
+      }
+}
+
+// ---- three-stage form with 32 x 32 x 16 fragments ------------------------------
+// The same products as zgemm_dl_kernel with a larger workgroup tile: K slices
+// of 16 (v_mfma_f32_32x32x16_bf16), three LDS stages of 48 KB, eight waves of
+// 64 x 64 complex (two per SIMD).  Slice s + 2 streams in while slice s is
+// multiplied, so a step waits only for loads issued two steps earlier; the
+// barrier carries no memory fence (a release fence on LDS would wait for the
+// loads still streaming into the third stage) and the waits it needs are
+// explicit: vmcnt for this wave's loads of the slice about to be read, and
+// the LDS reads of the stage about to be refilled are complete because the
+// multiplications that consumed them precede the barrier.
+//
+// LDS, one stage: A as [plane][row][16] bf16 with the 16-byte half h of row r
+// at position h ^ ((r >> 2) & 1) (B planes alike); B32 as [column][16] complex
+// float with the 16-byte chunk c (two complex) of column j at position
+// c ^ (j & 7).  Lanes 8q .. 8q + 7 of a fragment read then hit eight
+// different 16-byte bank groups.
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ v16f mfma32_bf16(const v8bf &a, const v8bf &b, v16f c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+// workgroup barrier without a memory fence; the empty asm statements keep the
+// compiler from moving memory accesses across it
+__device__ __forceinline__ void bar_nofence() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+template <int BM, int BN, int NWM, int NWN, bool CONJ, bool SPLIT, bool BF32>
+__global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl3_kernel(
+    int64_t m, int64_t n, int64_t kdata, const u16 *__restrict__ Apl, int64_t lda, int64_t psa,
+    const void *__restrict__ Bsrc, int64_t ldb, int64_t psb, float2 *__restrict__ C,
+    int64_t ldc, int64_t kchunk, int64_t kpad, float2 *__restrict__ part, int accum) {
+  constexpr int NW = NWM * NWN;
+  constexpr int WM = BM / NWM, WN = BN / NWN;     // wave tile
+  constexpr int SM = WM / 32, SN = WN / 32;       // 32 x 32 blocks per wave
+  constexpr int A_BYTES = 4 * BM * 32;                    // 4 planes x BM rows x 16 bf16
+  constexpr int B_BYTES = BF32 ? BN * 128 : 4 * BN * 32;  // BN columns x 16 complex float
+  constexpr int STAGE = A_BYTES + B_BYTES;
+  constexpr int QA = BM / 8 / NW;                    // 1 KB loads (32 rows of a plane) per wave
+  constexpr int QB = BF32 ? BN / 2 / NW : BN / 8 / NW;  // BF32: 256 B loads (two columns)
+  constexpr int LOADS = QA + QB;                      // loads per wave per slice
+  static_assert(QA * 8 * NW == BM && (BF32 ? QB * 2 * NW == BN : QB * 8 * NW == BN),
+                "tile / waves");
+  static_assert(SM >= 1 && SN >= 1 && SM * 32 == WM && SN * 32 == WN, "wave tile");
+  __shared__ __align__(16) unsigned char stage0[STAGE];
+  __shared__ __align__(16) unsigned char stage1[STAGE];
+  __shared__ __align__(16) unsigned char stage2[STAGE];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave % NWM, wn = wave / NWM;
+  unsigned tm, tn, tz;
+  grouped_tile(SPLIT ? gridDim.x : 4u, tm, tn, tz);
+  const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
+  const int64_t kbeg = (int64_t)tz * kchunk;
+  const int64_t kend = (kbeg + kchunk < kpad) ? kbeg + kchunk : kpad;
+  const int ns = kend > kbeg ? (int)((kend - kbeg) >> 4) : 0;
+
+  const u16 *asrc[QA];
+  int aoff[QA];
+#pragma unroll
+  for (int q = 0; q < QA; ++q) {
+    const int qq = wave * QA + q, p = qq / (BM / 32), r0 = (qq % (BM / 32)) * 32;
+    const int r = r0 + (lane >> 1), h = (lane & 1) ^ ((r >> 2) & 1);
+    const int64_t gr = row0 + r < m ? row0 + r : m - 1;
+    asrc[q] = Apl + (int64_t)p * psa + gr * lda + 8 * h;
+    aoff[q] = p * BM * 32 + r0 * 32;
+  }
+  // B planes: per-load sources as for A.  B32: the column and the float index
+  // of a lane's dword are formed at issue time (they are cheap, and holding 16
+  // 64-bit sources would cost 32 VGPRs); load q of a wave covers columns
+  // 2 (wave QB + q) + {0, 1}, lane l column (l >> 5), 16-byte position
+  // (l >> 2) & 7, dword l & 3.
+  const u16 *bsrc[BF32 ? 1 : QB];
+  int boff[BF32 ? 1 : QB];
+  if constexpr (!BF32) {
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int qq = wave * QB + q, p = qq / (BN / 32), r0 = (qq % (BN / 32)) * 32;
+      const int r = r0 + (lane >> 1), h = (lane & 1) ^ ((r >> 2) & 1);
+      const int64_t gr = col0 + r < n ? col0 + r : n - 1;
+      bsrc[q] = (const u16 *)Bsrc + (int64_t)p * psb + gr * ldb + 8 * h;
+      boff[q] = A_BYTES + p * BN * 32 + r0 * 32;
+    }
+  }
+  auto issue = [&](int s, unsigned char *st) {
+    const int64_t k0 = kbeg + 16 * (int64_t)s;
+#pragma unroll
+    for (int q = 0; q < QA; ++q) dma16(asrc[q] + k0, st + aoff[q]);
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      if constexpr (BF32) {
+        const int c = (wave * QB + q) * 2 + (lane >> 5);
+        const int64_t gc = col0 + c < n ? col0 + c : n - 1;
+        const int ch = ((lane >> 2) & 7) ^ (c & 7), w = lane & 3;
+        int64_t kk = k0 + 2 * ch + (w >> 1);
+        if (kk >= kdata) kk = kdata - 1;
+        dma4((const float *)Bsrc + 2 * (gc * ldb + kk) + (w & 1),
+             st + A_BYTES + (wave * QB + q) * 256);
+      } else {
+        dma16(bsrc[q] + k0, st + boff[q]);
+      }
+    }
+  };
+
+  v16f acc[SM][SN][2];
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[i][j][c][e] = 0.f;
+
+  const int hh = lane >> 5;  // K half of this lane's fragments
+  auto b_frag = [&](const unsigned char *st, int j, v8bf *b) {
+    const int jj = wn * WN + j * 32 + (lane & 31);
+    if constexpr (BF32) {
+      float4 q4[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int off = A_BYTES + jj * 128 + 16 * ((4 * hh + t) ^ (jj & 7));
+        q4[t] = *reinterpret_cast<const float4 *>(st + off);
+      }
+      bf2_t rh[4], rl[4], ih[4], il[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        split2(f2v_t{q4[t].x, q4[t].z}, rh[t], rl[t]);
+        split2(f2v_t{q4[t].y, q4[t].w}, ih[t], il[t]);
+      }
+      b[0] = cat4(rh[0], rh[1], rh[2], rh[3]);
+      b[1] = cat4(ih[0], ih[1], ih[2], ih[3]);
+      b[2] = cat4(rl[0], rl[1], rl[2], rl[3]);
+      b[3] = cat4(il[0], il[1], il[2], il[3]);
+    } else {
+      const int kb = 16 * (hh ^ ((jj >> 2) & 1));
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        b[p] = *reinterpret_cast<const v8bf *>(st + (A_BYTES + p * BN * 32 + jj * 32 + kb));
+    }
+  };
+  auto a_frag = [&](const unsigned char *st, int i, v8bf *a) {
+    const int ii = wm * WM + i * 32 + (lane & 31);
+    const int kb = 16 * (hh ^ ((ii >> 2) & 1));
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+      a[p] = *reinterpret_cast<const v8bf *>(st + (p * BM * 32 + ii * 32 + kb));
+    a[4] = bf16_neg(a[1]);
+    a[5] = bf16_neg(a[3]);
+  };
+  auto mac = [&](const v8bf *a, const v8bf *b, v16f *q) {
+    v16f re = q[0], im = q[1];
+    re = mfma32_bf16(b[0], a[0], re);
+    re = mfma32_bf16(b[2], a[0], re);
+    re = mfma32_bf16(b[0], a[2], re);
+    re = mfma32_bf16(b[1], a[CONJ ? 1 : 4], re);
+    re = mfma32_bf16(b[3], a[CONJ ? 1 : 4], re);
+    re = mfma32_bf16(b[1], a[CONJ ? 3 : 5], re);
+    im = mfma32_bf16(b[1], a[0], im);
+    im = mfma32_bf16(b[3], a[0], im);
+    im = mfma32_bf16(b[1], a[2], im);
+    im = mfma32_bf16(b[0], a[CONJ ? 4 : 1], im);
+    im = mfma32_bf16(b[2], a[CONJ ? 4 : 1], im);
+    im = mfma32_bf16(b[0], a[CONJ ? 5 : 3], im);
+    q[0] = re;
+    q[1] = im;
+  };
+  auto mma = [&](const unsigned char *st) {
+    if constexpr (BF32) {
+      // A fragments of every row block, then one column block of B at a time
+      // (its converted fragments live only while its MFMAs run)
+      v8bf a[SM][6];
+#pragma unroll
+      for (int i = 0; i < SM; ++i) a_frag(st, i, a[i]);
+#pragma unroll
+      for (int j = 0; j < SN; ++j) {
+        v8bf b[4];
+        b_frag(st, j, b);
+#pragma unroll
+        for (int i = 0; i < SM; ++i) mac(a[i], b, acc[i][j]);
+      }
+    } else {
+      v8bf b[SN][4];
+#pragma unroll
+      for (int j = 0; j < SN; ++j) b_frag(st, j, b[j]);
+#pragma unroll
+      for (int i = 0; i < SM; ++i) {
+        v8bf a[6];
+        a_frag(st, i, a);
+#pragma unroll
+        for (int j = 0; j < SN; ++j) mac(a, b[j], acc[i][j]);
+      }
+    }
+  };
+
+  // step s: slice s (stage s % 3) is complete once at most the loads of
+  // slice s + 1 are outstanding; after the barrier every wave's part of it is
+  // in LDS and every wave has finished slice s - 1, whose stage slice s + 2
+  // then refills
+  // (the stage of each step is a compile-time choice, so that every LDS access
+  // names its stage array and the compiler can tell them apart)
+  // Every step issues one slice (past the end: the last slice again, into a
+  // stage no later step reads), so that the same vmcnt wait holds for every
+  // step and the waits need no branches.
+  auto step = [&](int s, auto cur_idx) {
+    constexpr int CI = decltype(cur_idx)::value;
+    wait_vmcnt<LOADS>();
+    bar_nofence();
+    issue(s + 2 < ns ? s + 2 : ns - 1, CI == 0 ? stage2 : CI == 1 ? stage0 : stage1);
+    // keep the loads at the head of the step (the longest lead on their data)
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (CI == 0)
+      mma(stage0);
+    else if constexpr (CI == 1)
+      mma(stage1);
+    else
+      mma(stage2);
+  };
+  if (ns > 0) {
+    issue(0, stage0);
+    issue(ns > 1 ? 1 : 0, stage1);
+    // all counters drained here: then the steady state's waits are exactly the
+    // explicit ones (with the prologue's loads in flight, or only vmcnt drained,
+    // the compiler adds a full vmcnt wait to the first step of every round of
+    // three)
+    __builtin_amdgcn_s_waitcnt(0);
+    for (int s = 0; s < ns; s += 3) {
+      step(s, std::integral_constant<int, 0>{});
+      if (s + 1 >= ns) break;
+      step(s + 1, std::integral_constant<int, 1>{});
+      if (s + 2 >= ns) break;
+      step(s + 2, std::integral_constant<int, 2>{});
+    }
+    // the last loads must land before the workgroup's LDS is released
+    wait_vmcnt<0>();
+  }
+
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        // B operand first: lane & 31 indexes output rows, the accumulator
+        // element e the column 8 (e / 4) + 4 (lane / 32) + e % 4
+        const int64_t row = row0 + wm * WM + i * 32 + (lane & 31);
+        const int64_t col = col0 + wn * WN + j * 32 + 8 * (e >> 2) + 4 * hh + (e & 3);
+        if (row < m && col < n) {
+          const float2 v{acc[i][j][0][e], acc[i][j][1][e]};
+          if (SPLIT) {
+            part[(int64_t)tz * m * n + row + col * m] = v;
+          } else if (accum) {
+            float2 o = C[row + col * ldc];
+            o.x += v.x;
+            o.y += v.y;
+            C[row + col * ldc] = o;
+          } else {
+            C[row + col * ldc] = v;
+          }
+        }
+      }
+}
+
 // complex float block (ld) -> four bf16 planes (Re hi, Im hi, Re lo, Im lo),
-// row-major per band with stride ldp.
+// row-major per band with stride ldp; rows .. ldp - 1 of each band are zero
+// (the K padding the split-BF16 products read).
 __global__ __launch_bounds__(256) void split_planes_kernel(int64_t rows, int64_t cols,
                                                            const float2 *__restrict__ X, int64_t ld,
                                                            u16 *__restrict__ pl, int64_t ldp,
                                                            int64_t ps) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= rows * cols) return;
-  const int64_t i = idx % rows, j = idx / rows;
-  const float2 v = X[i + j * ld];
+  if (idx >= ldp * cols) return;
+  const int64_t i = idx % ldp, j = idx / ldp;
+  const float2 v = i < rows ? X[i + j * ld] : float2{0.f, 0.f};
   const u16 hr = bf16_rn(v.x), hi = bf16_rn(v.y);
   const int64_t o = j * ldp + i;
   pl[o] = hr;
@@ -1076,7 +1701,7 @@ void proj_gemm_bf16x3(int64_t nproj, int64_t nband, int64_t npw, const void *Apl
 
 void split_planes(int64_t rows, int64_t cols, const void *X, int64_t ld, void *planes,
                   int64_t ldp, hipStream_t st) {
-  const int64_t total = rows * cols;
+  const int64_t total = ldp * cols;
   if (total <= 0) return;
   hipLaunchKernelGGL(split_planes_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                      rows, cols, (const float2 *)X, ld, (u16 *)planes, ldp, ldp * cols);
@@ -1103,6 +1728,20 @@ static void launch_pl(int variant, dim3 grid_mn_z, int64_t m, int64_t n, int64_t
                        (const u16 *)Bpl, ldb, psb, (float2 *)C, ldc, chunk, (float2 *)part,
                        (int)accum);
   };
+  // direct-to-LDS kernels: K runs to the next multiple of 32 (zero planes), in
+  // chunks of a multiple of 32
+  auto go_dl = [&](auto kern, int bm, int bn, int nt) {
+    dim3 grid((unsigned)((m + bm - 1) / bm), (unsigned)((n + bn - 1) / bn), grid_mn_z.z);
+    const int64_t kpad = (k + 31) / 32 * 32;
+    const int64_t kch = grid_mn_z.z == 1 ? kpad : (chunk + 31) / 32 * 32;
+    CHEBFI_REQUIRE(kpad <= lda && kpad <= ldb, ABI_ERR_ARG,
+                   "split-BF16 planes must be zero-padded to a multiple of 32");
+    CHEBFI_REQUIRE((int64_t)bm * lda < (1ll << 31) && (int64_t)bn * ldb < (1ll << 31), ABI_ERR_ARG,
+                   "split-BF16 tile spans more than 2^31 elements");
+    hipLaunchKernelGGL(kern, grid, dim3(nt), 0, st, m, n, k, (const u16 *)Apl, lda, psa,
+                       (const void *)Bpl, ldb, psb, (float2 *)C, ldc, kch, kpad, (float2 *)part,
+                       (int)accum);
+  };
   switch (variant) {
     case 1: go(zgemm_pl_kernel<128, 128, 2, 2, CONJ, SPLIT>, 128, 128, 256); break;
     case 2: go(zgemm_pl_kernel<64, 64, 2, 2, CONJ, SPLIT>, 64, 64, 256); break;
@@ -1110,20 +1749,29 @@ static void launch_pl(int variant, dim3 grid_mn_z, int64_t m, int64_t n, int64_t
     case 4: go(zgemm_pl2_kernel<128, 128, 2, 4, CONJ, SPLIT, 1>, 128, 128, 512); break;
     case 5: go(zgemm_pl2_kernel<128, 128, 2, 4, CONJ, SPLIT, 2>, 128, 128, 512); break;
     case 6: go(zgemm_pl2_kernel<128, 64, 2, 2, CONJ, SPLIT, 0>, 128, 64, 256); break;
+    case 7: go_dl(zgemm_dl_kernel<128, 128, 2, 2, CONJ, SPLIT, false>, 128, 128, 256); break;
+    case 8: go_dl(zgemm_dl_kernel<128, 128, 1, 4, CONJ, SPLIT, false>, 128, 128, 256); break;
+    case 9: go_dl(zgemm_dl_kernel<128, 128, 2, 4, CONJ, SPLIT, false>, 128, 128, 512); break;
+    case 10: go_dl(zgemm_dl_kernel<128, 128, 4, 2, CONJ, SPLIT, false>, 128, 128, 512); break;
+    case 11: go_dl(zgemm_dl3_kernel<256, 128, 4, 2, CONJ, SPLIT, false>, 256, 128, 512); break;
+    case 12: go_dl(zgemm_dl3_kernel<128, 256, 2, 4, CONJ, SPLIT, false>, 128, 256, 512); break;
+    case 13: go_dl(zgemm_dl_kernel<128, 128, 2, 4, CONJ, SPLIT, false, true>, 128, 128, 512); break;
+    case 14: go_dl(zgemm_dl_kernel<128, 128, 4, 2, CONJ, SPLIT, false, true>, 128, 128, 512); break;
     default: go(zgemm_pl_kernel<128, 128, 2, 4, CONJ, SPLIT>, 128, 128, 512); break;
   }
   CHEBFI_HIP(hipGetLastError());
 }
 
-static int pl_bm(int variant) { return (variant == 2 || variant == 3) ? 64 : 128; }
-static int pl_bn(int variant) { return (variant == 2 || variant == 6) ? 64 : 128; }
+static int pl_bm(int variant) { return (variant == 2 || variant == 3) ? 64 : variant == 11 ? 256 : 128; }
+static int pl_bn(int variant) { return (variant == 2 || variant == 6) ? 64 : variant == 12 ? 256 : 128; }
+static bool pl_one_per_cu(int variant) { return variant == 4 || variant == 5 || variant >= 7; }
 
 int proj_planes_splits(int variant, int64_t nproj, int64_t nband, int64_t npw) {
   // at least 1024 plane waves per chunk; the double-buffered 128 x 128 tiles hold
   // 128 KB of LDS (one workgroup per CU), the single-stage ones two per CU
   const int64_t tiles = ((nproj + pl_bm(variant) - 1) / pl_bm(variant)) *
                         ((nband + pl_bn(variant) - 1) / pl_bn(variant));
-  const int per_cu = (variant == 4 || variant == 5) ? 1 : 2;
+  const int per_cu = pl_one_per_cu(variant) ? 1 : 2;
   return best_splits(tiles, (npw + 1023) / 1024, per_cu);
 }
 
@@ -1143,6 +1791,49 @@ void proj_gemm_planes_f32(int64_t nproj, int64_t nband, int64_t npw, const void 
   hipLaunchKernelGGL((zgemm_pl2_kernel<128, 128, 2, 4, true, true, 1, true>), grid, dim3(512), 0,
                      st, nproj, nband, npw, (const u16 *)Apl, lda, psa, (const u16 *)Y, ldy,
                      (int64_t)0, (float2 *)nullptr, (int64_t)0, chunk, (float2 *)part, 1);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+// BF32 projection variants: 0 = double-buffered register-staged 128 x 128
+// (split while staged), 1 = direct-to-LDS 128 x 128 with 2 x 2 waves,
+// 2 = direct-to-LDS 128 x 128 with 1 x 4 waves.
+void proj_gemm_f32_variant(int variant, int64_t nproj, int64_t nband, int64_t npw,
+                           const void *Apl, int64_t lda, int64_t psa, const void *Y, int64_t ldy,
+                           void *part, int splits, hipStream_t st) {
+  if (variant == 0) {
+    proj_gemm_planes_f32(nproj, nband, npw, Apl, lda, psa, Y, ldy, part, splits, st);
+    return;
+  }
+  const int64_t chunk = ((npw + splits - 1) / splits + XBK - 1) / XBK * XBK;
+  const int64_t kpad = (npw + 31) / 32 * 32;
+  CHEBFI_REQUIRE(kpad <= lda, ABI_ERR_ARG, "projector planes must be zero-padded to 32");
+  CHEBFI_REQUIRE(128 * lda < (1ll << 31), ABI_ERR_ARG, "projector planes too long");
+  dim3 grid((unsigned)((nproj + 127) / 128), (unsigned)((nband + 127) / 128), (unsigned)splits);
+  if (variant == 2)
+    hipLaunchKernelGGL((zgemm_dl_kernel<128, 128, 1, 4, true, true, true>), grid, dim3(256), 0,
+                       st, nproj, nband, npw, (const u16 *)Apl, lda, psa, Y, ldy, (int64_t)0,
+                       (float2 *)nullptr, (int64_t)0, chunk, kpad, (float2 *)part, 1);
+  else if (variant == 3)
+    hipLaunchKernelGGL((zgemm_dl_kernel<128, 128, 2, 4, true, true, true>), grid, dim3(512), 0,
+                       st, nproj, nband, npw, (const u16 *)Apl, lda, psa, Y, ldy, (int64_t)0,
+                       (float2 *)nullptr, (int64_t)0, chunk, kpad, (float2 *)part, 1);
+  else if (variant == 4)
+    hipLaunchKernelGGL((zgemm_dl_kernel<128, 128, 4, 2, true, true, true>), grid, dim3(512), 0,
+                       st, nproj, nband, npw, (const u16 *)Apl, lda, psa, Y, ldy, (int64_t)0,
+                       (float2 *)nullptr, (int64_t)0, chunk, kpad, (float2 *)part, 1);
+  else if (variant == 6)
+    hipLaunchKernelGGL((zgemm_dl_kernel<128, 128, 2, 4, true, true, true, true>), grid, dim3(512),
+                       0, st, nproj, nband, npw, (const u16 *)Apl, lda, psa, Y, ldy, (int64_t)0,
+                       (float2 *)nullptr, (int64_t)0, chunk, kpad, (float2 *)part, 1);
+  else if (variant == 5)
+    hipLaunchKernelGGL((zgemm_dl3_kernel<128, 256, 2, 4, true, true, true>),
+                       dim3(grid.x, (unsigned)((nband + 255) / 256), grid.z), dim3(512), 0, st,
+                       nproj, nband, npw, (const u16 *)Apl, lda, psa, Y, ldy, (int64_t)0,
+                       (float2 *)nullptr, (int64_t)0, chunk, kpad, (float2 *)part, 1);
+  else
+    hipLaunchKernelGGL((zgemm_dl_kernel<128, 128, 2, 2, true, true, true>), grid, dim3(256), 0,
+                       st, nproj, nband, npw, (const u16 *)Apl, lda, psa, Y, ldy, (int64_t)0,
+                       (float2 *)nullptr, (int64_t)0, chunk, kpad, (float2 *)part, 1);
   CHEBFI_HIP(hipGetLastError());
 }
 

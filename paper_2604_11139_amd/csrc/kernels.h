@@ -81,6 +81,12 @@ void proj_gemm_planes(int64_t nproj, int64_t nband, int64_t npw, const void *Apl
 void proj_gemm_planes_f32(int64_t nproj, int64_t nband, int64_t npw, const void *Apl, int64_t lda,
                           int64_t psa, const void *Y, int64_t ldy, void *part, int splits,
                           hipStream_t st);
+// part[z] = P^H Y by BF32 projection variant (0: register-staged 128 x 128,
+// 1, 2: direct-to-LDS 128 x 128 with 2 x 2 / 1 x 4 waves; these need the planes
+// of P zero up to the next multiple of 32 plane waves).
+void proj_gemm_f32_variant(int variant, int64_t nproj, int64_t nband, int64_t npw,
+                           const void *Apl, int64_t lda, int64_t psa, const void *Y, int64_t ldy,
+                           void *part, int splits, hipStream_t st);
 // Out += P C' (accumulate) or Out = P C'
 void expand_gemm_planes(int64_t npw, int64_t nband, int64_t nproj, const void *Apl, int64_t lda,
                         int64_t psa, const void *Cpl, int64_t ldc_pl, int64_t psc, void *Out,
