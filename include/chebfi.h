@@ -400,6 +400,22 @@ abi_status abi_batch_use_graph(abi_batch batch, int32_t on);
 
 abi_status abi_destroy_batch(abi_batch batch);
 
+/* ---- no-allocation form ---------------------------------------------------------
+ * For callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same operation, arguments and results as abi_apply_H, but every work buffer
+ * (split-K parts, D C, the projector part of the mixed form, the FFT box batch)
+ * is a piece of one static 64 MiB scratch array per device, located when a
+ * handle is first set up on that device; the call allocates nothing.  The FFT
+ * passes take as many boxes per batch as fit.  Fails with ABI_ERR_NOMEM when
+ * the work buffers of the call do not fit in 64 MiB (e.g. 22119 plane waves x
+ * 512 bands in the mixed form: call it on fewer bands at a time), and with
+ * ABI_ERR_STATE while timing (abi_profile_enable) is on.  All calls on one
+ * device share its array: calls that overlap in time on one device (other
+ * streams, other handles, other host threads) race and must not be issued. */
+abi_status abi_apply_H_noalloc(abi_system sys, const void *X, void *HX, int64_t nband, int64_t ld,
+                               int32_t dtype, void *stream);
+
 /* ---- tuning --------------------------------------------------------------------
  * Launch choices of a handle's kernels.  Every choice computes the same
  * product; variants of one class agree to rounding (the split-BF16 ones are

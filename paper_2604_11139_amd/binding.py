@@ -40,7 +40,7 @@ EXPORTS = [
     "abi_batch_system", "abi_cheb_filter_batch", "abi_batch_autotune", "abi_batch_use_graph",
     "abi_destroy_batch", "abi_chebfi_solve", "abi_apply_S", "abi_apply_Sinv", "abi_overlap_info",
     "abi_lobpcg_solve", "abi_density_add", "abi_occupations", "abi_scf_potential", "abi_scf_solve",
-    "abi_get_potential", "abi_set_tuning", "abi_get_tuning",
+    "abi_get_potential", "abi_set_tuning", "abi_get_tuning", "abi_apply_H_noalloc",
 ]
 
 PROFILE_CLASSES = ["proj_gemm", "expand_gemm", "fft_a", "fft_b", "fft_c", "dapply", "gram",
@@ -107,6 +107,7 @@ def lib():
                                 c_double, c_double, c_int32, vp, vp, vp, vp],
         "abi_profile_read": [vp, c_int32, vp, vp, vp],
         "abi_set_tuning": [vp, c_int32, c_int32],
+        "abi_apply_H_noalloc": [vp, vp, vp, c_int64, c_int64, c_int32, vp],
         "abi_get_tuning": [vp, c_int32, POINTER(c_int32)],
         "abi_set_system_batch": [vp, c_int32, vp, POINTER(vp)],
         "abi_batch_system": [vp, c_int32, POINTER(vp)],
@@ -297,6 +298,16 @@ class System:
         out = self._out_like(X, out)
         po, _, _, _ = _block(out, self.npw)
         _check(lib().abi_apply_H(self._h, px, po, nb, ld, code, _stream()))
+        return out
+
+    def apply_H_noalloc(self, X, out):
+        """H X into the preallocated `out` through the entry point that allocates
+        nothing (work buffers in the library's per-device scratch array)."""
+        px, nb, ld, code = _block(X, self.npw)
+        po, nbo, ldo, codeo = _block(out, self.npw)
+        if (nbo, ldo, codeo) != (nb, ld, code):
+            raise ValueError("out must match X in bands, stride and dtype")
+        _check(lib().abi_apply_H_noalloc(self._h, px, po, nb, ld, code, _stream()))
         return out
 
     def apply_S(self, X, out=None):

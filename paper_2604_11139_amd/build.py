@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchebfi.so")
 
 SOURCES = ["system.cpp", "chebfi_abi.cpp", "driver.cpp", "lobpcg.cpp", "fft.hip", "gemm.hip", "stream.hip", "dense.hip",
-           "batch.hip", "scf.hip"]
+           "batch.hip", "scf.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 

@@ -25,8 +25,27 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string &msg) { g_last_error = msg; }
 
+thread_local ScratchArena *g_scratch_arena = nullptr;
+
+void *ScratchArena::take(DevBuf *b, size_t need) {
+  for (const Lent &l : lent)
+    if (l.buf == b && b->bytes >= need) return b->ptr;  // already lent, large enough
+  const size_t start = (used + 255) / 256 * 256;
+  CHEBFI_REQUIRE(start <= size && need <= size - start, ABI_ERR_NOMEM,
+                 "no-allocation call: its work buffers need more than the " +
+                     std::to_string(size >> 20) + " MiB scratch array");
+  bool seen = false;
+  for (const Lent &l : lent) seen = seen || l.buf == b;
+  if (!seen) lent.push_back(Lent{b, b->ptr, b->bytes});
+  used = start + need;
+  b->ptr = base + start;
+  b->bytes = need;
+  return b->ptr;
+}
+
 void *DevBuf::get(size_t need) {
   if (need == 0) need = 256;
+  if (g_scratch_arena) return g_scratch_arena->take(this, need);
   if (bytes >= need) return ptr;
   release();
   hipError_t e = hipMalloc(&ptr, need);
@@ -509,6 +528,7 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
     CHEBFI_REQUIRE(desc->vloc != nullptr, ABI_ERR_ARG, "vloc is NULL");
     s = new abi_system_s();
     CHEBFI_HIP(hipGetDevice(&s->device));
+    s->scratch = scratch_for_device(s->device);
     s->n1 = desc->ngrid[0];
     s->n2 = desc->ngrid[1];
     s->n3 = desc->ngrid[2];
@@ -664,6 +684,38 @@ abi_status abi_apply_H(abi_system s, const void *X, void *HX, int64_t nband, int
     CHEBFI_REQUIRE(HX != nullptr, ABI_ERR_ARG, "HX is NULL");
     CHEBFI_REQUIRE(HX != X, ABI_ERR_ARG, "X and HX must not overlap");
     apply_core(s, X, ld, nullptr, 0, HX, ld, nband, 1.0, 0.0, 0.0, S(stream), dtype);
+  });
+}
+
+abi_status abi_apply_H_noalloc(abi_system s, const void *X, void *HX, int64_t nband, int64_t ld,
+                               int32_t dtype, void *stream) {
+  return guarded([&] {
+    check_block(s, X, nband, ld, dtype);
+    CHEBFI_REQUIRE(HX != nullptr, ABI_ERR_ARG, "HX is NULL");
+    CHEBFI_REQUIRE(HX != X, ABI_ERR_ARG, "X and HX must not overlap");
+    CHEBFI_REQUIRE(!s->prof.on, ABI_ERR_STATE,
+                   "timing creates events: turn it off for the no-allocation call");
+    CHEBFI_REQUIRE(s->scratch != nullptr, ABI_ERR_STATE, "no scratch array on this device");
+    ScratchArena arena;
+    arena.base = (char *)s->scratch;
+    arena.size = scratch_bytes();
+    const bool fp32 = dtype == ABI_C64;
+    if (!fp32 && s->nproj > 0) {
+      // the FP64 path runs the FFT passes before the projector products: keep
+      // room for the split-K parts and C' behind the box batch
+      const int64_t splits = nband == 1 ? 1 : zgemm_splits(s->nproj, nband, s->npw);
+      arena.reserve = sizeof(double2) * (size_t)s->nproj * nband * (splits + 1) + 512;
+    }
+    const int overlap = s->overlap;
+    s->overlap = 0;  // one stream: the second one's events are not needed
+    try {
+      ArenaScope scope(&arena);
+      apply_core(s, X, ld, nullptr, 0, HX, ld, nband, 1.0, 0.0, 0.0, S(stream), dtype);
+    } catch (...) {
+      s->overlap = overlap;
+      throw;
+    }
+    s->overlap = overlap;
   });
 }
 

@@ -142,7 +142,12 @@ void local_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int
   const bool fp32 = std::is_same<T, float>::value;
   const void *V = fp32 ? (const void *)s->d_Vf : (const void *)s->d_V;
   const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
-  const int fb = (int)std::min<int64_t>(s->fft_batch * (fp32 ? 2 : 1), nband);
+  int fb = (int)std::min<int64_t>(s->fft_batch * (fp32 ? 2 : 1), nband);
+  if (ScratchArena *a = g_scratch_arena) {
+    // no-allocation call: as many boxes as the scratch array has room for
+    const size_t room = a->remaining() > a->reserve + 256 ? a->remaining() - a->reserve - 256 : 0;
+    fb = (int)std::max<int64_t>(1, std::min<int64_t>(fb, room / (sizeof(V2) * (size_t)nbox)));
+  }
   void *box = s->box.get(sizeof(V2) * (size_t)nbox * fb);
   for (int64_t b0 = 0; b0 < nband; b0 += fb) {
     const int nb = (int)std::min<int64_t>(fb, nband - b0);

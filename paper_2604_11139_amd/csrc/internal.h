@@ -42,6 +42,46 @@ struct DevBuf {
   ~DevBuf() { release(); }
 };
 
+// Work-buffer arena of a no-allocation call.  While one is installed on the
+// calling thread, DevBuf::get hands out 256-byte aligned pieces of it (the
+// device scratch array) instead of allocating, and fails with ABI_ERR_NOMEM
+// when the pieces do not fit.  The DevBufs it lends pieces to get their own
+// buffers back when the arena is removed.  `reserve` bytes are kept free by
+// the FFT passes, which size their box batch to what is left.
+struct ScratchArena {
+  char *base = nullptr;
+  size_t size = 0, used = 0, reserve = 0;
+  struct Lent {
+    DevBuf *buf;
+    void *ptr;
+    size_t bytes;
+  };
+  std::vector<Lent> lent;
+  void *take(DevBuf *b, size_t need);
+  size_t remaining() const { return size - used; }
+};
+extern thread_local ScratchArena *g_scratch_arena;
+
+// Installs an arena for the lifetime of the object and restores the lent
+// DevBufs when it ends (also on an error).
+struct ArenaScope {
+  ScratchArena *arena;
+  explicit ArenaScope(ScratchArena *a) : arena(a) { g_scratch_arena = a; }
+  ~ArenaScope() {
+    for (auto it = arena->lent.rbegin(); it != arena->lent.rend(); ++it) {
+      it->buf->ptr = it->ptr;
+      it->buf->bytes = it->bytes;
+    }
+    arena->lent.clear();
+    g_scratch_arena = nullptr;
+  }
+};
+
+// Device address of this library's scratch array on device `dev` (which must
+// be current), looked up once per device; scratch_bytes() is its size.
+void *scratch_for_device(int dev);
+size_t scratch_bytes();
+
 // ---- FFT plan -------------------------------------------------------------
 constexpr int kMaxN = 64;       // largest box edge handled by the LDS passes
 constexpr int kMaxStages = 6;   // radix stages per 1D transform
@@ -214,6 +254,7 @@ struct abi_system_s {
       lob_g, lob_v;  // block LOBPCG
   chebfi::DevBuf scf_rho, scf_v, scf_box, scf_w;  // SCF step
 
+  void *scratch = nullptr;  // this device's scratch array (no-allocation calls)
   int fft_batch = 0;  // bands per FFT batch (box buffer holds this many boxes)
   // second stream: with overlap = 1 (CHEBFI_OVERLAP=1) the FFT passes of an H
   // application run on it beside the projection GEMM (they are independent until
