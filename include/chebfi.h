@@ -422,17 +422,47 @@ abi_status abi_apply_H_noalloc(abi_system sys, const void *X, void *HX, int64_t 
  * bit for bit equal when they sum the same K chunks in the same order).
  *   ABI_TUNE_PROJ      split-BF16 projection P^H X: 0..3, 5..8 tile variants on
  *                      planes made by a split pass; 4 register-staged 128 x 128
- *                      reading the complex64 block; 9, 10 direct-to-LDS 128 x 128
- *                      reading the block (2 x 2 / 1 x 4 waves)
+ *                      reading the complex64 block; 9..14 direct-to-LDS tiles
+ *                      reading the block (14, the default: eight waves with
+ *                      scheduled fragment reads)
  *   ABI_TUNE_EXPAND    split-BF16 expansion P C': 0..6 register-staged tiles,
- *                      7, 8 direct-to-LDS 128 x 128 (2 x 2 / 1 x 4 waves)
+ *                      7..14 direct-to-LDS tiles (see gemm.hip), 15 the persistent
+ *                      direct-to-LDS 128 x 128 tile (default)
  *   ABI_TUNE_FFT_BATCH bands per FFT batch (1..4096)
  *   ABI_TUNE_OVERLAP   0/1: FFT passes on a second stream beside the projection
+ *   ABI_TUNE_GENERIC_FFT 0/1: runtime-size FFT passes also for cubic boxes that
+ *                      have compile-time specialised ones (for testing them)
+ *   ABI_TUNE_MIXED_GEMM form of the mixed projector products: 0 split-BF16
+ *                      (default), 1 FP32 MFMA, 2 split-BF16 single-buffered
+ *                      64 x 64 tile (comparison forms)
  * Fails with ABI_ERR_ARG for an unknown parameter or a value out of range, and
- * with ABI_ERR_STATE for a split-BF16 parameter on an FP64 handle. */
-enum { ABI_TUNE_PROJ = 0, ABI_TUNE_EXPAND = 1, ABI_TUNE_FFT_BATCH = 2, ABI_TUNE_OVERLAP = 3 };
+ * with ABI_ERR_STATE for a mixed-form parameter on an FP64 handle. */
+enum {
+  ABI_TUNE_PROJ = 0,
+  ABI_TUNE_EXPAND = 1,
+  ABI_TUNE_FFT_BATCH = 2,
+  ABI_TUNE_OVERLAP = 3,
+  ABI_TUNE_GENERIC_FFT = 4,
+  ABI_TUNE_MIXED_GEMM = 5
+};
 abi_status abi_set_tuning(abi_system sys, int32_t param, int32_t value);
 abi_status abi_get_tuning(abi_system sys, int32_t param, int32_t *value);
+
+/* Autotuner (section "Batch processing": FFT plans and tile shapes chosen per
+ * problem).  Times H applications of the `nband` bands of X (dtype; X is only
+ * read) with the launch choices above, one coordinate at a time from the
+ * current ones (projection tile 14 / 11 / 4 and expansion tile 15 / 13 / 9 / 6
+ * for complex64 blocks on a mixed handle, then the FFT batch halved / doubled,
+ * then the second stream), best of three timed applications each, and keeps
+ * the fastest.  With a cache file (cache_path, or if it is NULL the file named
+ * by the environment variable ABI_AUTOTUNE_CACHE; no file: no cache) the
+ * choice is first looked up under the key (GPU architecture, CU count, plane
+ * waves, projectors, bands, FFT box, dtype) and applied without timing
+ * (*from_cache = 1, may be NULL), else stored after tuning.  The cache is a
+ * JSON object of one entry per line that this call reads and rewrites.
+ * Synchronises the stream. */
+abi_status abi_autotune(abi_system sys, const void *X, int64_t nband, int64_t ld, int32_t dtype,
+                        const char *cache_path, int32_t *from_cache, void *stream);
 
 /* ---- timing ------------------------------------------------------------------
  * Per-kernel-class timing with HIP events recorded on the stream of each call

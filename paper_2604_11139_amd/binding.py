@@ -41,6 +41,7 @@ EXPORTS = [
     "abi_destroy_batch", "abi_chebfi_solve", "abi_apply_S", "abi_apply_Sinv", "abi_overlap_info",
     "abi_lobpcg_solve", "abi_density_add", "abi_occupations", "abi_scf_potential", "abi_scf_solve",
     "abi_get_potential", "abi_set_tuning", "abi_get_tuning", "abi_apply_H_noalloc",
+    "abi_autotune",
 ]
 
 PROFILE_CLASSES = ["proj_gemm", "expand_gemm", "fft_a", "fft_b", "fft_c", "dapply", "gram",
@@ -70,7 +71,7 @@ class Desc(ctypes.Structure):
     ]
 
 
-TUNE_PROJ, TUNE_EXPAND, TUNE_FFT_BATCH, TUNE_OVERLAP = 0, 1, 2, 3
+TUNE_PROJ, TUNE_EXPAND, TUNE_FFT_BATCH, TUNE_OVERLAP, TUNE_GENERIC_FFT, TUNE_MIXED_GEMM = range(6)
 
 _lib = None
 
@@ -108,6 +109,7 @@ def lib():
         "abi_profile_read": [vp, c_int32, vp, vp, vp],
         "abi_set_tuning": [vp, c_int32, c_int32],
         "abi_apply_H_noalloc": [vp, vp, vp, c_int64, c_int64, c_int32, vp],
+        "abi_autotune": [vp, vp, c_int64, c_int64, c_int32, c_char_p, POINTER(c_int32), vp],
         "abi_get_tuning": [vp, c_int32, POINTER(c_int32)],
         "abi_set_system_batch": [vp, c_int32, vp, POINTER(vp)],
         "abi_batch_system": [vp, c_int32, POINTER(vp)],
@@ -499,6 +501,18 @@ class System:
     def set_tuning(self, param, value):
         """Sets one launch choice (TUNE_* parameter) of this handle."""
         _check(lib().abi_set_tuning(self._h, int(param), int(value)))
+
+    def autotune(self, X, cache_path=None):
+        """Times the launch choices on H applications of X and keeps the fastest
+        (looked up in / stored to the cache file, if any).  Returns
+        ({param: value}, from_cache)."""
+        px, nb, ld, code = _block(X, self.npw)
+        fc = c_int32(0)
+        cp = None if cache_path is None else str(cache_path).encode()
+        _check(lib().abi_autotune(self._h, px, nb, ld, code, cp, ctypes.byref(fc), _stream()))
+        names = {"proj": TUNE_PROJ, "expand": TUNE_EXPAND, "fft_batch": TUNE_FFT_BATCH,
+                 "overlap": TUNE_OVERLAP}
+        return {k: self.get_tuning(v) for k, v in names.items()}, bool(fc.value)
 
     def get_tuning(self, param):
         v = c_int32(0)

@@ -13,7 +13,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <new>
+#include <sstream>
 
 #include "cplx.h"
 #include "driver.h"
@@ -355,7 +358,7 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
     // systems on cubic boxes with specialised passes go to their edge group and
     // contribute no items to the runtime-size passes
     const bool grouped = s->n1 == s->n2 && s->n1 == s->n3 && batch_edge_specialised(s->n1) &&
-                         !std::getenv("CHEBFI_GENERIC_FFT");
+                         !s->generic_fft;
     offA[i + 1] = offA[i] + (grouped ? 0 : nband[i] * s->n3);
     offB[i + 1] = offB[i] + (grouped ? 0 : nband[i] * s->n2);
   }
@@ -365,7 +368,7 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
   for (int i = 0; i < nsys; ++i) {
     const abi_system_s *s = B->sys[i];
     if (offA[i + 1] != offA[i] || !(s->n1 == s->n2 && s->n1 == s->n3)) continue;
-    if (!batch_edge_specialised(s->n1) || std::getenv("CHEBFI_GENERIC_FFT")) continue;
+    if (!batch_edge_specialised(s->n1) || s->generic_fft) continue;
     size_t g = 0;
     while (g < gedge.size() && gedge[g] != s->n1) ++g;
     if (g == gedge.size()) {
@@ -603,21 +606,16 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
         }
       s->d_PA = upload(PA.data(), PA.size());
       s->d_PB = upload(PB.data(), PB.size());
-      // 0: split-BF16 planes x planes (default), 1: FP32 MFMA, 2: split-BF16 with the
-      // block split while staged
-      if (const char *e = std::getenv("CHEBFI_MIXED_GEMM")) s->mixed_gemm = std::atoi(e);
-      // tile variants of the split-BF16 products (abi_set_tuning): both default to
-      // the direct-to-LDS 128 x 128 tile with eight waves and the scheduled
-      // fragment reads (the projection splits the block into planes as it reads
-      // its fragments)
+      // tile variants of the split-BF16 products (abi_set_tuning, abi_autotune):
+      // both default to the direct-to-LDS 128 x 128 tile with eight waves and the
+      // scheduled fragment reads (the projection splits the block into planes as
+      // it reads its fragments; the expansion's workgroups run through several
+      // tiles)
       s->pl_proj = 14;
-      s->pl_expand = 13;
-      if (const char *e = std::getenv("CHEBFI_PL_PROJ")) s->pl_proj = std::min(10, std::max(0, std::atoi(e)));
-      if (const char *e = std::getenv("CHEBFI_PL_EXPAND")) s->pl_expand = std::min(8, std::max(0, std::atoi(e)));
+      s->pl_expand = 15;
     }
-    // bands per FFT batch: keep the box buffer near 128 MiB (env override)
-    int64_t fb = (int64_t)((128ll << 20) / (sizeof(double2) * nbox));
-    if (const char *e = std::getenv("CHEBFI_FFT_BATCH")) fb = std::atoll(e);
+    // bands per FFT batch: keep the box buffer near 128 MiB
+    const int64_t fb = (int64_t)((128ll << 20) / (sizeof(double2) * nbox));
     s->fft_batch = (int)std::max<int64_t>(1, std::min<int64_t>(fb, 4096));
     // FFT passes beside the projection GEMM on a second stream (default priority)
     CHEBFI_HIP(hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking));
@@ -625,7 +623,6 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
     CHEBFI_HIP(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
     CHEBFI_HIP(hipEventCreateWithFlags(&s->ev_half, hipEventDisableTiming));
     s->overlap = 0;
-    if (const char *e = std::getenv("CHEBFI_OVERLAP")) s->overlap = std::atoi(e) != 0;
     if (desc->abi_version >= 2 && desc->qij != nullptr) setup_overlap(s, desc->qij, S(stream));
     CHEBFI_HIP(hipStreamSynchronize(S(stream)));
     *out = s;
@@ -1137,14 +1134,17 @@ abi_status abi_filter_backward(abi_system s, const void *X, const void *W, int64
     const int nck = (int)starts.size() - 1;  // checkpoint pairs (Y_{s-1}, Y_s), s > 0
     const size_t esz = elem_bytes(dtype);
     const size_t blk = esz * (size_t)npw * nband;
-    const int nblocks = 2 * nck + cseg + 3;
+    // blocks: the checkpoint pairs, the recomputed iterates Y_{s0+1} ..
+    // Y_{s0+cseg-1} of a segment (Y_{s0} is its checkpoint or X) and three
+    // adjoint iterates
+    const int nblocks = 2 * nck + (cseg - 1) + 3;
     char *base = (char *)s->adj.get(blk * (size_t)nblocks);
     auto block = [&](int i) { return (void *)(base + blk * (size_t)i); };
     auto ck_prev = [&](int j) { return block(2 * (j - 1)); };  // Y_{s_j - 1}
     auto ck_cur = [&](int j) { return block(2 * (j - 1) + 1); };  // Y_{s_j}
-    char *seg0 = (char *)block(2 * nck);
-    auto seg = [&](int i) { return (void *)(seg0 + blk * (size_t)i); };
-    void *abuf[3] = {block(2 * nck + cseg), block(2 * nck + cseg + 1), block(2 * nck + cseg + 2)};
+    auto seg = [&](int i) { return block(2 * nck + i - 1); };  // Y_{s0 + i}, i >= 1
+    const int ab = 2 * nck + cseg - 1;
+    void *abuf[3] = {block(ab), block(ab + 1), block(ab + 2)};
     const int64_t nbox = (int64_t)s->n1 * s->n2 * s->n3;
     // small accumulators: dV (nbox), dD (natom*16 complex), CA, CY (nproj*nband), C'
     const size_t small_bytes = sizeof(double) * (size_t)nbox + sizeof(double2) * 16 * (size_t)natom +
@@ -1457,7 +1457,7 @@ abi_status abi_set_tuning(abi_system s, int32_t param, int32_t value) {
         break;
       case ABI_TUNE_EXPAND:
         CHEBFI_REQUIRE(mixed, ABI_ERR_STATE, "split-BF16 variants need a mixed handle");
-        CHEBFI_REQUIRE(value >= 0 && value <= 14, ABI_ERR_ARG, "expansion variant out of range");
+        CHEBFI_REQUIRE(value >= 0 && value <= 15, ABI_ERR_ARG, "expansion variant out of range");
         s->pl_expand = value;
         break;
       case ABI_TUNE_FFT_BATCH:
@@ -1467,6 +1467,15 @@ abi_status abi_set_tuning(abi_system s, int32_t param, int32_t value) {
       case ABI_TUNE_OVERLAP:
         CHEBFI_REQUIRE(value == 0 || value == 1, ABI_ERR_ARG, "overlap is 0 or 1");
         s->overlap = value;
+        break;
+      case ABI_TUNE_GENERIC_FFT:
+        CHEBFI_REQUIRE(value == 0 || value == 1, ABI_ERR_ARG, "generic FFT is 0 or 1");
+        s->generic_fft = value;
+        break;
+      case ABI_TUNE_MIXED_GEMM:
+        CHEBFI_REQUIRE(mixed, ABI_ERR_STATE, "projector product forms need a mixed handle");
+        CHEBFI_REQUIRE(value >= 0 && value <= 2, ABI_ERR_ARG, "projector product form is 0..2");
+        s->mixed_gemm = value;
         break;
       default:
         CHEBFI_REQUIRE(false, ABI_ERR_ARG, "unknown tuning parameter");
@@ -1482,8 +1491,173 @@ abi_status abi_get_tuning(abi_system s, int32_t param, int32_t *value) {
       case ABI_TUNE_EXPAND: *value = s->pl_expand; break;
       case ABI_TUNE_FFT_BATCH: *value = s->fft_batch; break;
       case ABI_TUNE_OVERLAP: *value = s->overlap; break;
+      case ABI_TUNE_GENERIC_FFT: *value = s->generic_fft; break;
+      case ABI_TUNE_MIXED_GEMM: *value = s->mixed_gemm; break;
       default: CHEBFI_REQUIRE(false, ABI_ERR_ARG, "unknown tuning parameter");
     }
+  });
+}
+
+// ---- autotuner --------------------------------------------------------------
+namespace {
+
+struct TuneChoice {
+  int proj = 0, expand = 0, fft_batch = 1, overlap = 0;
+  double ms = 0.0;  // one H application with this choice
+};
+
+std::string tune_key(const abi_system_s *s, int64_t nband, int32_t dtype) {
+  hipDeviceProp_t prop;
+  CHEBFI_HIP(hipGetDeviceProperties(&prop, s->device));
+  std::string arch = prop.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
+  std::ostringstream k;
+  k << arch << " cus=" << prop.multiProcessorCount << " npw=" << s->npw << " nproj=" << s->nproj
+    << " nband=" << nband << " box=" << s->n1 << "x" << s->n2 << "x" << s->n3
+    << (dtype == ABI_C64 ? " c64" : " c128");
+  return k.str();
+}
+
+// The cache is a JSON object written by this library, one entry per line:
+//   "<key>": {"proj": P, "expand": E, "fft_batch": F, "overlap": O, "ms_per_apply": T}
+std::map<std::string, std::string> cache_read(const std::string &path) {
+  std::map<std::string, std::string> out;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t a = line.find('"');
+    const size_t b = a == std::string::npos ? a : line.find("\": {", a + 1);
+    if (a == std::string::npos || b == std::string::npos) continue;
+    std::string body = line.substr(b + 3);
+    while (!body.empty() && (body.back() == ',' || body.back() == ' ')) body.pop_back();
+    out[line.substr(a + 1, b - a - 1)] = body;
+  }
+  return out;
+}
+
+bool cache_parse(const std::string &body, TuneChoice *c) {
+  return std::sscanf(body.c_str(),
+                     "{\"proj\": %d, \"expand\": %d, \"fft_batch\": %d, \"overlap\": %d, "
+                     "\"ms_per_apply\": %lf}",
+                     &c->proj, &c->expand, &c->fft_batch, &c->overlap, &c->ms) == 5;
+}
+
+void cache_write(const std::string &path, const std::string &key, const TuneChoice &c) {
+  auto all = cache_read(path);
+  char body[256];
+  std::snprintf(body, sizeof body,
+                "{\"proj\": %d, \"expand\": %d, \"fft_batch\": %d, \"overlap\": %d, "
+                "\"ms_per_apply\": %.4f}",
+                c.proj, c.expand, c.fft_batch, c.overlap, c.ms);
+  all[key] = body;
+  const std::string tmp = path + ".tmp";
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    CHEBFI_REQUIRE(f.good(), ABI_ERR_ARG, "cannot write the autotune cache " + tmp);
+    f << "{\n";
+    size_t i = 0;
+    for (const auto &kv : all)
+      f << " \"" << kv.first << "\": " << kv.second << (++i < all.size() ? ",\n" : "\n");
+    f << "}\n";
+  }
+  CHEBFI_REQUIRE(std::rename(tmp.c_str(), path.c_str()) == 0, ABI_ERR_ARG,
+                 "cannot replace the autotune cache " + path);
+}
+
+}  // namespace
+
+abi_status abi_autotune(abi_system s, const void *X, int64_t nband, int64_t ld, int32_t dtype,
+                        const char *cache_path, int32_t *from_cache, void *stream) {
+  return guarded([&] {
+    check_block(s, X, nband, ld, dtype);
+    hipStream_t st = S(stream);
+    if (from_cache) *from_cache = 0;
+    std::string path = cache_path ? cache_path : "";
+    if (path.empty())
+      if (const char *e = std::getenv("ABI_AUTOTUNE_CACHE")) path = e;
+    const std::string key = tune_key(s, nband, dtype);
+    const bool split_bf16 = dtype == ABI_C64 && s->mixed_gemm == 0 && s->nproj > 0;
+    auto apply = [&](const TuneChoice &c) {
+      if (split_bf16) {
+        s->pl_proj = c.proj;
+        s->pl_expand = c.expand;
+      }
+      s->fft_batch = c.fft_batch;
+      s->overlap = c.overlap;
+    };
+    if (!path.empty()) {
+      const auto all = cache_read(path);
+      const auto it = all.find(key);
+      TuneChoice c;
+      if (it != all.end() && cache_parse(it->second, &c) && c.fft_batch >= 1 &&
+          c.fft_batch <= 4096 && (c.overlap == 0 || c.overlap == 1) &&
+          (!split_bf16 || (c.proj >= 0 && c.proj <= 14 && c.expand >= 0 && c.expand <= 15))) {
+        apply(c);
+        if (from_cache) *from_cache = 1;
+        return;
+      }
+    }
+    // time one H application per candidate (best of three after a warm-up),
+    // one coordinate at a time from the current choice
+    void *HX = s->tune_out.get(elem_bytes(dtype) * (size_t)s->npw * nband);
+    const bool prof = s->prof.on;
+    s->prof.on = false;
+    hipEvent_t e0, e1;
+    CHEBFI_HIP(hipEventCreate(&e0));
+    CHEBFI_HIP(hipEventCreate(&e1));
+    auto timed = [&](const TuneChoice &c) {
+      apply(c);
+      apply_core(s, X, ld, nullptr, 0, HX, s->npw, nband, 1.0, 0.0, 0.0, st, dtype);
+      float best = 1e30f;
+      for (int r = 0; r < 3; ++r) {
+        CHEBFI_HIP(hipEventRecord(e0, st));
+        apply_core(s, X, ld, nullptr, 0, HX, s->npw, nband, 1.0, 0.0, 0.0, st, dtype);
+        CHEBFI_HIP(hipEventRecord(e1, st));
+        CHEBFI_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        CHEBFI_HIP(hipEventElapsedTime(&ms, e0, e1));
+        best = std::min(best, ms);
+      }
+      return (double)best;
+    };
+    TuneChoice cur;
+    cur.proj = s->pl_proj;
+    cur.expand = s->pl_expand;
+    cur.fft_batch = s->fft_batch;
+    cur.overlap = s->overlap;
+    try {
+      cur.ms = timed(cur);
+      auto sweep = [&](int TuneChoice::*field, const std::vector<int> &vals) {
+        for (int v : vals) {
+          if (v == cur.*field) continue;
+          TuneChoice c = cur;
+          c.*field = v;
+          const double ms = timed(c);
+          if (ms < cur.ms) {
+            cur = c;
+            cur.ms = ms;
+          }
+        }
+      };
+      if (split_bf16) {
+        sweep(&TuneChoice::proj, {14, 11, 4});
+        sweep(&TuneChoice::expand, {15, 13, 9, 6});
+      }
+      const int fb = cur.fft_batch;
+      sweep(&TuneChoice::fft_batch,
+            {std::max(1, fb / 2), std::min(4096, 2 * fb)});
+      if (s->nproj > 0 && !(nband == 1 && dtype == ABI_C128)) sweep(&TuneChoice::overlap, {0, 1});
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      s->prof.on = prof;
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    s->prof.on = prof;
+    apply(cur);
+    if (!path.empty()) cache_write(path, key, cur);
   });
 }
 

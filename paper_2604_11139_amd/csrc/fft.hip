@@ -502,7 +502,7 @@ bool try_cubic_adjoint(const abi_system_s *s, const void *Ak1, int64_t lda1, con
                        void *box1, void *box2, const void *V, double gamma, double cshift,
                        double *dV, hipStream_t st) {
   if (s->n1 != s->n2 || s->n1 != s->n3) return false;
-  if (std::getenv("CHEBFI_GENERIC_FFT")) return false;
+  if (s->generic_fft) return false;
 #define CHEBFI_CASE(N_)                                                                      \
   case N_:                                                                                   \
     adjoint_cubic<T, N_>(s, Ak1, lda1, Yk, ldy, Ak, ldak, accumulate, band0, nb, box1, box2, \
@@ -520,7 +520,7 @@ template <typename T>
 bool try_cubic_density(const abi_system_s *s, const void *Psi, int64_t ld, int band0, int nb,
                        void *box, const double *w, double *rho, hipStream_t st) {
   if (s->n1 != s->n2 || s->n1 != s->n3) return false;
-  if (std::getenv("CHEBFI_GENERIC_FFT")) return false;
+  if (s->generic_fft) return false;
 #define CHEBFI_CASE(N_)                                                       \
   case N_:                                                                    \
     density_cubic<T, N_>(s, Psi, ld, band0, nb, box, w, rho, st);             \
@@ -539,7 +539,7 @@ bool try_cubic(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Y
                double cshift, double beta, hipStream_t st, Profiler *prof, double bA, double bB,
                double bC, const void *E, int64_t lde) {
   if (s->n1 != s->n2 || s->n1 != s->n3) return false;
-  if (std::getenv("CHEBFI_GENERIC_FFT")) return false;
+  if (s->generic_fft) return false;
 #define CHEBFI_CUBIC(N_)                                                                     \
   case N_:                                                                                   \
     launch_cubic<T, N_>(s, Yk, ldk, Yprev, ldp, Out, ldo, band0, nb, box, V, alpha, cshift,  \

@@ -11,6 +11,7 @@
 // while the current one is multiplied.  Tall-skinny products (K = npw) are
 // split along K; each chunk writes its own partial product and a separate pass
 // adds the chunks in a fixed order, so results do not depend on scheduling.
+#include <algorithm>
 #include <type_traits>
 
 #include "cplx.h"
@@ -1094,7 +1095,8 @@ __device__ __forceinline__ v8bf cat4(bf2_t a, bf2_t b, bf2_t c, bf2_t d) {
   return __builtin_shufflevector(ab, cd, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
-template <int BM, int BN, int NWM, int NWN, bool CONJ, bool SPLIT, bool BF32, bool PIPE = false>
+template <int BM, int BN, int NWM, int NWN, bool CONJ, bool SPLIT, bool BF32, bool PIPE = false,
+          bool PERSIST = false>
 __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl_kernel(
     int64_t m, int64_t n, int64_t kdata, const u16 *__restrict__ Apl, int64_t lda, int64_t psa,
     const void *__restrict__ Bsrc, int64_t ldb, int64_t psb, float2 *__restrict__ C,
@@ -1114,14 +1116,35 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl_kernel(
   __shared__ __align__(16) unsigned char stage0[STAGE];
   __shared__ __align__(16) unsigned char stage1[STAGE];
 
+  static_assert(!(PERSIST && SPLIT), "the persistent form writes whole products");
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave % NWM, wn = wave / NWM;
-  unsigned tm, tn, tz;
-  grouped_tile(SPLIT ? gridDim.x : 4u, tm, tn, tz);
-  const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
-  const int64_t kbeg = (int64_t)tz * kchunk;
-  const int64_t kend = (kbeg + kchunk < kpad) ? kbeg + kchunk : kpad;
+  // Tiles.  One tile per workgroup, or (PERSIST) a sequence of tiles per
+  // workgroup: the grid holds 8 W workgroups (W per XCD, the hardware handing
+  // workgroup ids to the XCDs round robin); round `it` gives XCD x the W
+  // consecutive tiles (row panel major) starting at (8 it + x) W, so that the
+  // workgroups an XCD runs together share their row panels in its L2.
+  const int ntm = (int)((m + BM - 1) / BM), ntn = (int)((n + BN - 1) / BN);
+  const int ntiles = ntm * ntn;
+  const int wpx = (int)(gridDim.x >> 3), xcd = (int)(blockIdx.x & 7), wj = (int)(blockIdx.x >> 3);
+  auto tile_of = [&](int it) -> int { return (it * 8 + xcd) * wpx + wj; };
+  int64_t row0, col0, kbeg = 0, kend, tzv = 0;
+  if constexpr (PERSIST) {
+    const int t = tile_of(0);
+    if (t >= ntiles) return;
+    row0 = (int64_t)(t / ntn) * BM;
+    col0 = (int64_t)(t % ntn) * BN;
+    kend = kpad;
+  } else {
+    unsigned tm, tn, tz;
+    grouped_tile(SPLIT ? gridDim.x : 4u, tm, tn, tz);
+    row0 = (int64_t)tm * BM;
+    col0 = (int64_t)tn * BN;
+    tzv = tz;
+    kbeg = (int64_t)tz * kchunk;
+    kend = (kbeg + kchunk < kpad) ? kbeg + kchunk : kpad;
+  }
   const int ns = kend > kbeg ? (int)((kend - kbeg) >> 5) : 0;
 
   // Load addresses: a wave-uniform base (scalar registers) plus a 32-bit lane
@@ -1133,47 +1156,53 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl_kernel(
   // position l >> 2, which holds chunk (l >> 2) ^ (c & 7) of the column.
   static_assert(!BF32 || QB % 8 == 0, "B32 lane patterns repeat every 8 columns");
   const int kcl = (lane & 3) ^ ((lane >> 3) & 3);
-  uint32_t aofs[QA];  // byte offsets
+  // byte offsets of this lane's loads within the tile being loaded (rows and
+  // columns past m, n read row m - 1 / column n - 1: their results are not
+  // stored); set when the loads move to a new tile
+  uint32_t aofs[QA];
+  uint32_t bofs[BF32 ? 8 : QB];
+  auto set_offsets = [&](int64_t r0t, int64_t c0t) {
 #pragma unroll
-  for (int q = 0; q < QA; ++q) {
-    const int r0 = ((wave * QA + q) % (BM / 16)) * 16, r = r0 + (lane >> 2);
-    const int64_t rr = row0 + r < m ? r : m - 1 - row0;
-    aofs[q] = (uint32_t)(2 * (rr * lda + 8 * kcl));
-  }
-  uint32_t bofs[BF32 ? 8 : QB];  // byte offsets
-  if constexpr (BF32) {
-#pragma unroll
-    for (int c8 = 0; c8 < 8; ++c8) {
-      const int ch = (lane >> 2) ^ c8, w = lane & 3;
-      bofs[c8] = (uint32_t)(4 * (2 * (2 * ch + (w >> 1)) + (w & 1)));
+    for (int q = 0; q < QA; ++q) {
+      const int64_t r = ((wave * QA + q) % (BM / 16)) * 16 + (lane >> 2);
+      const int64_t rr = r0t + r < m ? r : m - 1 - r0t;
+      aofs[q] = (uint32_t)(2 * (rr * lda + 8 * kcl));
     }
-  } else {
+    if constexpr (BF32) {
 #pragma unroll
-    for (int q = 0; q < QB; ++q) {
-      const int r0 = ((wave * QB + q) % (BN / 16)) * 16, r = r0 + (lane >> 2);
-      const int64_t rr = col0 + r < n ? r : n - 1 - col0;
-      bofs[q] = (uint32_t)(2 * (rr * ldb + 8 * kcl));
+      for (int c8 = 0; c8 < 8; ++c8) {
+        const int ch = (lane >> 2) ^ c8, w = lane & 3;
+        bofs[c8] = (uint32_t)(4 * (2 * (2 * ch + (w >> 1)) + (w & 1)));
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        const int64_t r = ((wave * QB + q) % (BN / 16)) * 16 + (lane >> 2);
+        const int64_t rr = c0t + r < n ? r : n - 1 - c0t;
+        bofs[q] = (uint32_t)(2 * (rr * ldb + 8 * kcl));
+      }
     }
-  }
+  };
+  set_offsets(row0, col0);
   // (uniform base + zero-extended 32-bit byte offset: the scalar-base form of
-  // the load instruction)
-  auto issue_k = [&](int64_t k0, unsigned char *st, auto tail_c) {
+  // the load instruction).  TAIL: a B32 slice reaching past the data reads the
+  // last complex of the column for K indices past it (meeting zeros of A).
+  auto issue_k = [&](int64_t r0t, int64_t c0t, int64_t k0, unsigned char *st, auto tail_c) {
     constexpr bool TAIL = decltype(tail_c)::value;
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int qq = wave * QA + q, p = qq / (BM / 16), r0 = (qq % (BM / 16)) * 16;
-      const char *base = (const char *)(Apl + (int64_t)p * psa + row0 * lda + k0);
+      const char *base = (const char *)(Apl + (int64_t)p * psa + r0t * lda + k0);
       dma16(base + aofs[q], st + p * BM * 64 + r0 * 64);
     }
     if constexpr (BF32) {
-      const char *base = (const char *)((const float *)Bsrc + 2 * (col0 * ldb + k0));
+      const char *base = (const char *)((const float *)Bsrc + 2 * (c0t * ldb + k0));
 #pragma unroll
       for (int q = 0; q < QB; ++q) {
         const int c = wave * QB + q;
-        const uint32_t cofs = (uint32_t)(8 * (col0 + c < n ? c : n - 1 - col0) * ldb);
+        const uint32_t cofs = (uint32_t)(8 * (c0t + c < n ? c : n - 1 - c0t) * ldb);
         uint32_t off = bofs[q & 7];
         if constexpr (TAIL) {
-          // complex index k0 + off / 8 past the data: read the last one
           if (k0 + (off >> 3) >= kdata) off = (uint32_t)(8 * (kdata - 1 - k0)) + (off & 4);
         }
         dma4(base + (cofs + off), st + A_BYTES + c * 256);
@@ -1182,19 +1211,19 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl_kernel(
 #pragma unroll
       for (int q = 0; q < QB; ++q) {
         const int qq = wave * QB + q, p = qq / (BN / 16), r0 = (qq % (BN / 16)) * 16;
-        const char *base = (const char *)((const u16 *)Bsrc + (int64_t)p * psb + col0 * ldb + k0);
+        const char *base = (const char *)((const u16 *)Bsrc + (int64_t)p * psb + c0t * ldb + k0);
         dma16(base + bofs[q], st + A_BYTES + p * BN * 64 + r0 * 64);
       }
     }
   };
-  auto issue = [&](int s, unsigned char *st) {
+  auto issue_t = [&](int64_t r0t, int64_t c0t, int s, unsigned char *st) {
     const int64_t k0 = kbeg + 32 * (int64_t)s;
-    // only a B32 slice reaching past the data clamps its K indices
     if (BF32 && k0 + 32 > kdata)
-      issue_k(k0, st, std::integral_constant<bool, true>{});
+      issue_k(r0t, c0t, k0, st, std::integral_constant<bool, true>{});
     else
-      issue_k(k0, st, std::integral_constant<bool, false>{});
+      issue_k(r0t, c0t, k0, st, std::integral_constant<bool, false>{});
   };
+  auto issue = [&](int s, unsigned char *st) { issue_t(row0, col0, s, st); };
 
   // PIPE: the product's minus sign rides on a third accumulator (subtracted in
   // the epilogue) instead of negated planes, the A fragments of row block i + 1
@@ -1357,47 +1386,95 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl_kernel(
   // two stages: slice s + 1 streams into the other stage while slice s is
   // multiplied; the barrier after the wait both publishes slice s + 1 and
   // frees the stage that slice s + 2 will overwrite
-  if (ns > 0) issue(0, stage0);
-  for (int s = 0; s < ns; s += 2) {
-    wait_vmcnt<0>();
-    __syncthreads();
-    if (s + 1 < ns) issue(s + 1, stage1);
-    mma(stage0);
-    if (s + 1 >= ns) break;
-    wait_vmcnt<0>();
-    __syncthreads();
-    if (s + 2 < ns) issue(s + 2, stage0);
-    mma(stage1);
-  }
-
+  auto epilogue = [&](int64_t row0, int64_t col0) {
 #pragma unroll
-  for (int i = 0; i < SM; ++i)
+    for (int i = 0; i < SM; ++i)
 #pragma unroll
-    for (int j = 0; j < SN; ++j)
+      for (int j = 0; j < SN; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = row0 + wm * (BM / NWM) + i * 16 + (lane & 15);
-        const int64_t col = col0 + wn * (BN / NWN) + j * 16 + 4 * (lane >> 4) + r;
-        if (row < m && col < n) {
-          float2 v{acc[i][j][0][r], acc[i][j][1][r]};
-          if constexpr (PIPE) {
-            if (CONJ)
-              v.y -= acc[i][j][NACC - 1][r];
-            else
-              v.x -= acc[i][j][NACC - 1][r];
-          }
-          if (SPLIT) {
-            part[(int64_t)tz * m * n + row + col * m] = v;
-          } else if (accum) {
-            float2 o = C[row + col * ldc];
-            o.x += v.x;
-            o.y += v.y;
-            C[row + col * ldc] = o;
-          } else {
-            C[row + col * ldc] = v;
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = row0 + wm * (BM / NWM) + i * 16 + (lane & 15);
+          const int64_t col = col0 + wn * (BN / NWN) + j * 16 + 4 * (lane >> 4) + r;
+          if (row < m && col < n) {
+            float2 v{acc[i][j][0][r], acc[i][j][1][r]};
+            if constexpr (PIPE) {
+              if (CONJ)
+                v.y -= acc[i][j][NACC - 1][r];
+              else
+                v.x -= acc[i][j][NACC - 1][r];
+            }
+            if (SPLIT) {
+              part[tzv * m * n + row + col * m] = v;
+            } else if (accum) {
+              float2 o = C[row + col * ldc];
+              o.x += v.x;
+              o.y += v.y;
+              C[row + col * ldc] = o;
+            } else {
+              C[row + col * ldc] = v;
+            }
           }
         }
+  };
+  if constexpr (PERSIST) {
+    // the steps of all the workgroup's tiles in one sequence: the last step of
+    // a tile streams in the first slice of the next one, whose multiplication
+    // then follows the stores of the finished tile
+    if (ns == 0) return;
+    int it = 0, sidx = 0;
+    int64_t nrow0 = row0, ncol0 = col0;
+    auto advance = [&]() -> bool {  // (tile, step) after the current one
+      if (sidx + 1 < ns) return true;
+      const int t = tile_of(it + 1);
+      if (t >= ntiles) return false;
+      nrow0 = (int64_t)(t / ntn) * BM;
+      ncol0 = (int64_t)(t % ntn) * BN;
+      set_offsets(nrow0, ncol0);  // the current tile issues no more loads
+      return true;
+    };
+    auto step = [&](unsigned char *cur, unsigned char *nxt) -> bool {
+      wait_vmcnt<0>();
+      __syncthreads();
+      const bool more = advance();
+      if (more) issue_t(nrow0, ncol0, sidx + 1 < ns ? sidx + 1 : 0, nxt);
+      mma(cur);
+      if (sidx + 1 < ns) {
+        ++sidx;
+        return true;
       }
+      epilogue(row0, col0);
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int j = 0; j < SN; ++j)
+#pragma unroll
+          for (int c = 0; c < NACC; ++c) acc[i][j][c] = v4f{0, 0, 0, 0};
+      if (!more) return false;
+      ++it;
+      sidx = 0;
+      row0 = nrow0;
+      col0 = ncol0;
+      return true;
+    };
+    issue(0, stage0);
+    while (step(stage0, stage1) && step(stage1, stage0)) {
+    }
+    wait_vmcnt<0>();
+  } else {
+    if (ns > 0) issue(0, stage0);
+    for (int s = 0; s < ns; s += 2) {
+      wait_vmcnt<0>();
+      __syncthreads();
+      if (s + 1 < ns) issue(s + 1, stage1);
+      mma(stage0);
+      if (s + 1 >= ns) break;
+      wait_vmcnt<0>();
+      __syncthreads();
+      if (s + 2 < ns) issue(s + 2, stage0);
+      mma(stage1);
+    }
+    epilogue(row0, col0);
+  }
 }
 
 // ---- three-stage form with 32 x 32 x 16 fragments ------------------------------
@@ -1757,6 +1834,25 @@ static void launch_pl(int variant, dim3 grid_mn_z, int64_t m, int64_t n, int64_t
     case 12: go_dl(zgemm_dl3_kernel<128, 256, 2, 4, CONJ, SPLIT, false>, 128, 256, 512); break;
     case 13: go_dl(zgemm_dl_kernel<128, 128, 2, 4, CONJ, SPLIT, false, true>, 128, 128, 512); break;
     case 14: go_dl(zgemm_dl_kernel<128, 128, 4, 2, CONJ, SPLIT, false, true>, 128, 128, 512); break;
+    case 15:
+      if constexpr (!SPLIT) {
+        // persistent: one workgroup per CU, a whole number per XCD
+        const int64_t tiles = ((m + 127) / 128) * ((n + 127) / 128);
+        const int64_t per_xcd = std::max<int64_t>(
+            1, std::min<int64_t>(device_cus() / 8, (tiles + 7) / 8));
+        const int64_t kpad = (k + 31) / 32 * 32;
+        CHEBFI_REQUIRE(kpad <= lda && kpad <= ldb, ABI_ERR_ARG,
+                       "split-BF16 planes must be zero-padded to a multiple of 32");
+        CHEBFI_REQUIRE(128 * lda < (1ll << 31) && 128 * ldb < (1ll << 31), ABI_ERR_ARG,
+                       "split-BF16 tile spans more than 2^31 elements");
+        hipLaunchKernelGGL((zgemm_dl_kernel<128, 128, 2, 4, CONJ, false, false, true, true>),
+                           dim3((unsigned)(8 * per_xcd)), dim3(512), 0, st, m, n, k,
+                           (const u16 *)Apl, lda, psa, (const void *)Bpl, ldb, psb, (float2 *)C,
+                           ldc, kpad, kpad, (float2 *)nullptr, (int)accum);
+      } else {
+        go_dl(zgemm_dl_kernel<128, 128, 2, 4, CONJ, SPLIT, false, true>, 128, 128, 512);
+      }
+      break;
     default: go(zgemm_pl_kernel<128, 128, 2, 4, CONJ, SPLIT>, 128, 128, 512); break;
   }
   CHEBFI_HIP(hipGetLastError());

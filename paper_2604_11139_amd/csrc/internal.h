@@ -242,6 +242,7 @@ struct abi_system_s {
   double *d_B = nullptr, *d_K = nullptr;
   double s_min = 1.0;
   int mixed_gemm = 0;              // 0: split-BF16 MFMA, 1: FP32 MFMA projector products
+  int generic_fft = 0;             // 1: runtime-size FFT passes also for cubic boxes
   int pl_proj = 0, pl_expand = 0;  // tile variants of the split-BF16 products
 
   // work buffers
@@ -249,6 +250,7 @@ struct abi_system_s {
   chebfi::DevBuf eig1, eig2, eig3, blk4, box2, adj, adjsmall, adjc, planes, cplanes;
   chebfi::DevBuf solve1, solve2, solve3;  // blocks of the multi-cycle driver
   chebfi::DevBuf expout;  // projector part P C' of the mixed H application
+  chebfi::DevBuf tune_out;  // output block of the autotuner's timed H applications
   chebfi::DevBuf gen_c, gen_e, gen_f, gen_ff, blk5, blk6;  // overlap path
   chebfi::DevBuf lob_z, lob_hz, lob_sz, lob_t1, lob_t2, lob_t3, lob_psi, lob_hp, lob_sp, lob_c,
       lob_g, lob_v;  // block LOBPCG

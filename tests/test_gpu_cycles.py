@@ -21,6 +21,14 @@ start the next cycle.
   differ by the filter term, which is bounded by the residuals of the lowest
   p Ritz pairs: |grad - rho_p| <= 4 max_{n<=p} ||r_n|| max rho at every stored
   point, and the gradient sums to p within the same bound.
+* The filter term itself, at full size: (1) the GPU adjoint with the GPU's own
+  W on three of its columns (the filter acts on each column alone) against the
+  oracle's adjoint of the same columns, <= 1e-5 m relative (the mixed adjoint
+  bar); (2) central differences (h = 1e-3 Ha) of sum_{n<=p} eps_n through the
+  mixed filter and the FP64 Rayleigh-Ritz from the same block and bounds, along
+  three seeded directions dV: <grad, dV> within 1e-6 relative, and, along the
+  direction where the filter term is largest, within 5% of that term, which
+  rho_p alone misses by more than half of it.
 """
 import functools
 import json
@@ -29,6 +37,7 @@ import os
 import numpy as np
 import pytest
 
+import oracle as O
 import workloads as W
 from paper_2604_11139_amd import binding as B
 
@@ -117,7 +126,44 @@ def test_mixed_cycles_and_gradient_vs_oracle():
         rho = g.density(Y[:p])
         grad = (rho + dV).cpu().numpy()
         rmax = float(res[:p].max())
+        dV = dV.cpu().numpy()
+        rho = rho.cpu().numpy()
+        # (1) three columns of the GPU's W alone
+        cols = [0, p // 2, p - 1]
+        Wc = torch.zeros_like(Wm)
+        Wc[cols] = Wm[cols]
+        dVc, _, _ = g.filter_backward(Xin, Wc.contiguous(), s.degree, *bounds, ckpt_every=4,
+                                      want_dx=False)
+        dVc = dVc.cpu().numpy()
+        Xc = Xin[cols].cpu().numpy().T.astype(np.complex128)
+        Wcc = Wm[cols].cpu().numpy().T.astype(np.complex128)
+        # (2) central differences of sum_{n<=p} eps_n along seeded directions
+        V0 = torch.from_numpy(np.ascontiguousarray(s.vloc.reshape(-1))).to("cuda")
+        rng = np.random.default_rng([2604, 11139, 55])
+        dirs = [rng.standard_normal(V0.numel()) for _ in range(3)]
+        h = 1e-3
+        fd = []
+        for dv in dirs:
+            vals = []
+            for t in (h, -h):
+                g.update_potential(vloc=V0 + t * torch.from_numpy(dv).to("cuda"))
+                Yt = g.cheb_filter(Xin, s.degree, *bounds)
+                evt, _, _ = g.rayleigh_ritz(Yt)
+                vals.append(float(np.sum(np.asarray(evt)[:p], dtype=np.float64)))
+                del Yt
+            fd.append((vals[0] - vals[1]) / (2 * h))
+        g.update_potential(vloc=V0)
     pts = np.array(ref["rho_points"])
     tol = 4.0 * rmax * ref["rho_max"]
     assert np.abs(grad[pts] - np.array(ref["rho_values"])).max() <= tol
     assert abs(grad.sum() - p) <= 4.0 * rmax * p
+    H = O.Hamiltonian.from_system(s)
+    dV_ref, _, _ = O.filter_backward(H, Xc, Wcc, s.degree, *bounds)
+    dV_ref = np.asarray(dV_ref).reshape(dVc.shape)
+    assert np.abs(dVc - dV_ref).max() <= 1e-5 * s.degree * np.abs(dV_ref).max()
+    chain = [float(np.dot(dV, dv)) for dv in dirs]
+    for f, dv in zip(fd, dirs):
+        assert abs(f - float(np.dot(grad, dv))) <= 1e-6 * abs(f)
+    k = int(np.argmax(np.abs(chain)))
+    assert abs(fd[k] - float(np.dot(grad, dirs[k]))) <= 0.05 * abs(chain[k])
+    assert abs(fd[k] - float(np.dot(rho, dirs[k]))) >= 0.5 * abs(chain[k])

@@ -57,15 +57,14 @@ def test_mixed_apply_H(name):
 
 
 @pytest.mark.parametrize("name,generic", [("noncubic", False), ("n27", True), ("c1", True)])
-def test_mixed_apply_H_generic_fft(name, generic, monkeypatch):
+def test_mixed_apply_H_generic_fft(name, generic):
     """Runtime-size FFT passes in the mixed form (the last pass adds the projector
     part computed before it): a non-cubic box, and cubic boxes forced onto them."""
-    if generic:
-        monkeypatch.setenv("CHEBFI_GENERIC_FFT", "1")
     H = hamiltonian(name)
     s = system(name)
     X = W.random_block(H.npw, s.nband, 12).astype(np.complex64).astype(np.complex128)
     with _mixed(name) as g:
+        g.set_tuning(B.TUNE_GENERIC_FFT, int(generic))
         got = to_host(g.apply_H(_c64(X)))
     assert col_rel_err(got.astype(np.complex128), H(X)) <= 2e-6
 

@@ -257,7 +257,7 @@ def test_filter_single_and_ragged(nband):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_two_stream_halves_match_one_stream(precision, monkeypatch):
+def test_two_stream_halves_match_one_stream(precision):
     """The pipelined band halves on two streams (130 bands: halves of 96 and 34) give the
     one-stream result bit for bit."""
     import torch
@@ -268,9 +268,9 @@ def test_two_stream_halves_match_one_stream(precision, monkeypatch):
         X = _r64(X)
     prec = B.ABI_PREC_MIXED if precision == "mixed" else B.ABI_PREC_FP64
     outs = []
-    for ov in ("0", "1"):
-        monkeypatch.setenv("CHEBFI_OVERLAP", ov)
+    for ov in (0, 1):
         with B.System(s, precision=prec) as g:
+            g.set_tuning(B.TUNE_OVERLAP, ov)
             Xd = to_dev(X)
             if precision == "mixed":
                 Xd = Xd.to(torch.complex64)

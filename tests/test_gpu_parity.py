@@ -71,14 +71,14 @@ def test_apply_H_parts(parts):
 
 
 @pytest.mark.parametrize("name,generic", [("noncubic", False), ("n27", True), ("c1", True)])
-def test_apply_H_generic_fft(name, generic, monkeypatch):
+def test_apply_H_generic_fft(name, generic):
     """Runtime-size FFT passes: a non-cubic box, and cubic boxes forced onto them."""
-    if generic:
-        monkeypatch.setenv("CHEBFI_GENERIC_FFT", "1")
     H = hamiltonian(name)
     s = system(name)
     X = W.random_block(H.npw, s.nband, 11)
     with B.System(s) as g:
+        g.set_tuning(B.TUNE_GENERIC_FFT, int(generic))
+        assert g.get_tuning(B.TUNE_GENERIC_FFT) == int(generic)
         got = to_host(g.apply_H(to_dev(X)))
     assert col_rel_err(got, H(X)) <= 1e-10
 
@@ -107,7 +107,7 @@ def test_cheb_filter(name, degree):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_filter_overlap_is_bitwise_neutral(precision, monkeypatch):
+def test_filter_overlap_is_bitwise_neutral(precision):
     """The FFT passes on a second stream beside the projection give the same bits."""
     import torch
     s = system("n25")
@@ -115,9 +115,9 @@ def test_filter_overlap_is_bitwise_neutral(precision, monkeypatch):
     X = W.random_block(H.npw, s.nband, 31)
     prec = B.ABI_PREC_MIXED if precision == "mixed" else B.ABI_PREC_FP64
     outs = []
-    for ov in ("0", "1"):
-        monkeypatch.setenv("CHEBFI_OVERLAP", ov)
+    for ov in (0, 1):
         with B.System(s, precision=prec) as g:
+            g.set_tuning(B.TUNE_OVERLAP, ov)
             Xd = to_dev(X)
             if precision == "mixed":
                 Xd = Xd.to(torch.complex64)
