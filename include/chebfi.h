@@ -174,17 +174,34 @@ abi_status abi_cheb_filter(abi_system sys, const void *X, void *Y, int64_t nband
  * G = Y^H S Y = U^H U (Cholesky, FP64), H_s = Y^H (H Y),
  * U^-H H_s U^-1 = Z Lambda Z^H, Psi = Y U^-1 Z (S-orthonormal),
  * H Psi = (H Y) U^-1 Z, and the residual norms ||H psi_n - lambda_n S psi_n||
- * (Algorithm "Parallel Chebyshev filtering of degree k", last two steps).  Always computed in FP64: a
- * complex64 block (dtype ABI_C64, mixed handles) is promoted, processed and
- * rounded back, so the eigenvalues are those of the FP64 pencil of the block.
+ * (Algorithm "Parallel Chebyshev filtering of degree k", last two steps).  By default computed
+ * in FP64: a complex64 block (dtype ABI_C64, mixed handles) is promoted,
+ * processed and rounded back, so the eigenvalues are those of the FP64 pencil
+ * of the block (see flags for the split-BF16 form).
  * Y (npw x nband, ld): in: filtered block; out: Ritz vectors Psi.
  * HPsi: optional output of the same dtype and ld, or NULL.
  * eval: host, nband doubles, ascending.  resnorm: host, nband doubles, or NULL.
  * coef: device nband x nband complex doubles (ld nband) receiving C = U^-1 Z,
  *   so that Psi = Y_in C (the coefficients of the Ritz vectors), or NULL.
- * flags: host int32 or NULL (bit 0 reserved for a mixed-precision fallback).
+ * flags: host int32 in/out, or NULL.  In: ABI_RR_LOWPREC asks, for a complex64
+ *   block on a mixed handle with S = I, for the split-BF16 form of the
+ *   intermediate cycles of the mixed solver: columns scaled to unit norm
+ *   (equilibration), G and H_s as split-BF16 MFMA products accumulated in
+ *   FP32, Cholesky, reduction and eigensolve in FP64, the two rotations as
+ *   split-BF16 products.  When the smallest squared pivot of the equilibrated
+ *   Gram matrix's Cholesky factor U1 is below 0.5, the block is first
+ *   orthonormalised (Q1 = Y E U1^-1, split-BF16) and the Gram matrix taken
+ *   again on Q1 (CholeskyQR2), so the split products' ~2^-17 relative error
+ *   is not magnified by the block's conditioning.  Ritz values then carry
+ *   absolute errors of about 1e-5 max|lambda| and the Ritz vectors
+ *   orthonormality errors of about 1e-5, which the next filter and a final
+ *   FP64 Rayleigh-Ritz remove.  Out: ABI_RR_LOWPREC if that form ran (with
+ *   ABI_RR_TWO_PASS when it took the second pass); ABI_RR_FELL_BACK if it was
+ *   asked for but a squared pivot fell below 1e-4 (too ill-conditioned for
+ *   the split products), in which case the FP64 form ran; 0 otherwise.
  * Fails with ABI_ERR_NOT_HPD if the Gram matrix is not positive definite.
  * Synchronises `stream`. */
+enum { ABI_RR_FELL_BACK = 1, ABI_RR_LOWPREC = 2, ABI_RR_TWO_PASS = 4 };
 abi_status abi_rayleigh_ritz(abi_system sys, void *Y, void *HPsi, int64_t nband, int64_t ld,
                              int32_t dtype, double *eval, double *resnorm, void *coef,
                              int32_t *flags, void *stream);
@@ -201,9 +218,11 @@ abi_status abi_rayleigh_ritz(abi_system sys, void *Y, void *HPsi, int64_t nband,
  * (ld) of `dtype`; v0: device, npw complex128.  With dtype ABI_C64 and
  * refine_degree > 0, the mixed cycles hand over to FP64 cycles of degree
  * refine_degree on the promoted block (a residual-driven refinement) when a
- * cycle improves the worst of those residuals by less than 10%, or after half
- * of max_cycles; X then receives the complex64 rounding of the FP64 Ritz
- * vectors.  eval, resnorm (host, nband; resnorm may be NULL): the last cycle's
+ * cycle improves the worst of those residuals by less than 10%, when they meet
+ * tol, or after half of max_cycles; X then receives the complex64 rounding of
+ * the FP64 Ritz vectors.  Those mixed cycles use the split-BF16 Rayleigh-Ritz
+ * (ABI_RR_LOWPREC of abi_rayleigh_ritz); without refinement they use the FP64
+ * one.  eval, resnorm (host, nband; resnorm may be NULL): the last cycle's
  * Ritz values and residual norms.  info (host, 4 entries, may be NULL): cycles
  * in the block's precision, FP64 refinement cycles, converged (0/1), 0.
  * Synchronises the stream.  Errors: those of the calls it makes; ABI_ERR_ARG

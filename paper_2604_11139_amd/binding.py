@@ -72,6 +72,7 @@ class Desc(ctypes.Structure):
 
 
 TUNE_PROJ, TUNE_EXPAND, TUNE_FFT_BATCH, TUNE_OVERLAP, TUNE_GENERIC_FFT, TUNE_MIXED_GEMM = range(6)
+RR_FELL_BACK, RR_LOWPREC, RR_TWO_PASS = 1, 2, 4
 
 _lib = None
 
@@ -529,9 +530,12 @@ class System:
                                       wk.ctypes.data_as(c_void_p), ct.ctypes.data_as(c_void_p)))
         return {c: (float(ms[i]), float(wk[i]), int(ct[i])) for i, c in enumerate(PROFILE_CLASSES)}
 
-    def rayleigh_ritz(self, Y, hpsi=None, want_coef=False):
+    def rayleigh_ritz(self, Y, hpsi=None, want_coef=False, lowprec=False):
         """In place: Y <- Ritz vectors.  Returns (eval, resnorm, flags) and, with
-        want_coef, the coefficient matrix C (torch (nband, nband), Psi = Y_in C)."""
+        want_coef, the coefficient matrix C (torch (nband, nband), Psi = Y_in C).
+        lowprec: the split-BF16 form for a complex64 block (RR_LOWPREC in flags
+        when it ran, with RR_TWO_PASS when it orthonormalised first;
+        RR_FELL_BACK when the FP64 form ran instead)."""
         import torch
         py, nb, ld, code = _block(Y, self.npw)
         ph = c_void_p(0)
@@ -540,7 +544,7 @@ class System:
             ph, _, _, _ = _block(hpsi, self.npw)
         ev = np.zeros(nb, dtype=np.float64)
         rn = np.zeros(nb, dtype=np.float64)
-        fl = c_int32(0)
+        fl = c_int32(RR_LOWPREC if lowprec else 0)
         coef = None
         pc = c_void_p(0)
         if want_coef:

@@ -890,7 +890,18 @@ abi_status abi_rayleigh_ritz(abi_system s, void *Y, void *HPsi, int64_t nband, i
     CHEBFI_REQUIRE(HPsi != Y, ABI_ERR_ARG, "HPsi must not alias Y");
     hipStream_t st = S(stream);
     const int64_t npw = s->npw, M = nband;
-    if (dtype == ABI_C128) {
+    const bool want_low = flags && (*flags & ABI_RR_LOWPREC) && dtype == ABI_C64 &&
+                          s->mixed_gemm == 0 && !s->has_S && s->precision == ABI_PREC_MIXED;
+    int32_t out_flags = 0;
+    bool done = false;
+    if (want_low) {
+      const int passes = rr_lowprec(s, Y, ld, HPsi, ld, M, eval, resnorm, coef, st);
+      done = passes > 0;
+      out_flags = !done ? ABI_RR_FELL_BACK
+                        : passes == 2 ? (ABI_RR_LOWPREC | ABI_RR_TWO_PASS) : ABI_RR_LOWPREC;
+    }
+    if (done) {
+    } else if (dtype == ABI_C128) {
       rr_core(s, (double2 *)Y, ld, (double2 *)HPsi, ld, M, eval, resnorm, coef, st);
     } else {
       // promote the complex64 block, run the FP64 Rayleigh-Ritz, round back
@@ -902,7 +913,7 @@ abi_status abi_rayleigh_ritz(abi_system s, void *Y, void *HPsi, int64_t nband, i
       if (HPsi) launch_c128_to_c64(npw, M, H2, npw, HPsi, ld, st);
       CHEBFI_HIP(hipStreamSynchronize(st));
     }
-    if (flags) *flags = 0;
+    if (flags) *flags = out_flags;
   });
 }
 
@@ -951,10 +962,13 @@ abi_status abi_chebfi_solve(abi_system s, void *X, int64_t nband, int64_t ld, in
         b_upper = bd[1];
       }
       call(abi_cheb_filter(s, A, Bk, nband, l, dt, m, bd[0], bd[1], bd[2], stream));
-      int32_t flags = 0;
+      // the mixed cycles ahead of an FP64 refinement use the split-BF16
+      // Rayleigh-Ritz (the refinement's FP64 cycles win the accuracy back)
+      int32_t flags = (dt == ABI_C64 && refine_degree > 0) ? ABI_RR_LOWPREC : 0;
       call(abi_rayleigh_ritz(s, Bk, nullptr, nband, l, dt, eval, res.data(), nullptr, &flags,
                              stream));
       have_ritz = true;
+      return (flags & ABI_RR_LOWPREC) != 0;
     };
     const bool refine = refine_degree > 0;
     // the mixed cycles hand over to the FP64 refinement when they stall (a cycle
@@ -965,12 +979,13 @@ abi_status abi_chebfi_solve(abi_system s, void *X, int64_t nband, int64_t ld, in
     int cycles = 0, rcycles = 0, converged = 0;
     double prev = HUGE_VAL;
     while (cycles < first_budget) {
-      cycle(bufA, bufB, ld, dtype, degree);
+      const bool low = cycle(bufA, bufB, ld, dtype, degree);
       std::swap(bufA, bufB);
       ++cycles;
       const double cur = worst();
       if (cur <= tol) {
-        converged = 1;
+        // residuals of the split-BF16 Rayleigh-Ritz are not final: refine
+        converged = low ? 0 : 1;
         break;
       }
       if (refine && cur > 0.9 * prev) break;

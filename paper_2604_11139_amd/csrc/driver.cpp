@@ -434,6 +434,152 @@ void setup_overlap(abi_system_s *s, const double *qij, hipStream_t st) {
 }
 
 // FP64 Rayleigh-Ritz on a complex128 block Y (in: filtered block, out: Psi).
+// Rayleigh-Ritz of a complex64 block with split-BF16 products (mixed form,
+// S = I): the columns are scaled to unit norm (Y_e = Y E, E = diag(1/||y_j||)),
+// G = Y_e^H Y_e and H_s = Y_e^H (H Y_e) are split-BF16 products accumulated in
+// FP32 (summed in FP64), the Cholesky factorisation, the reduction and the
+// eigensolve run in FP64, and the rotations Psi = Y_e T, H Psi = (H Y_e) T
+// (T = U^-1 Z) are split-BF16 products again.  The equilibrated Gram matrix of
+// a filtered block is well conditioned even when G is not; a pivot of its
+// Cholesky factor below kLowPivot (a condition number the split products'
+// ~1e-5 relative error cannot resolve) returns false and nothing is written.
+int rr_lowprec(abi_system_s *s, void *Y, int64_t ld, void *HPsi, int64_t ldh_in, int64_t M,
+               double *eval, double *resnorm, void *coef, hipStream_t st) {
+  // pivots^2 of the equilibrated Gram matrix's Cholesky factor: below kLowPivot
+  // the split products cannot resolve the block (FP64 form instead); below
+  // kTwoPass a second pass orthonormalises first (CholeskyQR2)
+  constexpr double kLowPivot = 1e-4, kTwoPass = 0.5;
+  const int64_t npw = s->npw;
+  const size_t mm = sizeof(double2) * (size_t)M * M;
+  double2 *G = (double2 *)s->small1.get(mm);
+  double2 *Hs = (double2 *)s->small2.get(mm);
+  double2 *T = (double2 *)s->small3.get(mm);
+  double2 *Z = (double2 *)s->small4.get(mm);
+  double *scal = (double *)s->scal.get(sizeof(double) * (size_t)(160 + 5 * M + 64));
+  double *w_dev = scal + 160;
+  double *r_dev = w_dev + M;
+  double *nrm = r_dev + M, *inv = nrm + M;
+  int *info = (int *)(inv + M);
+  const size_t blk = sizeof(float2) * (size_t)npw * M;
+  float2 *Ye = (float2 *)s->blk4.get(blk);
+  float2 *spare = (float2 *)s->blk1.get(blk);
+  const int64_t ldm = (M + 31) / 32 * 32;
+  const int splits = proj_planes_splits(7, M, M, npw);
+  const double gflops = 8.0 * (double)M * M * npw;
+  // (own planes buffer: a planes variant of the H application reuses s->planes)
+  void *ypl = s->rr_planes.get(8 * (size_t)s->ldPA * M);
+  void *part = nullptr;
+  // G = Ye^H Ye as split-BF16 products, its Cholesky factor in G; 0 if a pivot
+  // is too small, else the smallest pivot^2
+  auto gram_chol = [&](const float2 *B) -> double {
+    ypl = s->rr_planes.get(8 * (size_t)s->ldPA * M);
+    split_planes(npw, M, B, npw, ypl, s->ldPA, st);
+    part = s->cpart.get(sizeof(float2) * (size_t)splits * M * M);
+    int tok = s->prof.begin(PROF_GRAM, gflops, st);
+    rr_gram_f32(M, npw, ypl, s->ldPA, B, npw, part, splits, st);
+    launch_parts_to_c128(M, M, part, splits, true, G, st);
+    s->prof.end(tok, st);
+    launch_hermitize(M, G, M, st);
+    tok = s->prof.begin(PROF_CHOL, 4.0 / 3.0 * (double)M * M * M, st);
+    zpotrf_upper(M, G, M, info, nullptr, st);
+    s->prof.end(tok, st);
+    int hinfo = 0;
+    std::vector<double2> diag((size_t)M);
+    CHEBFI_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, st));
+    CHEBFI_HIP(hipMemcpy2DAsync(diag.data(), sizeof(double2), G, sizeof(double2) * (M + 1),
+                                sizeof(double2), (size_t)M, hipMemcpyDeviceToHost, st));
+    CHEBFI_HIP(hipStreamSynchronize(st));
+    if (hinfo != 0) return 0.0;
+    double pmin = HUGE_VAL;
+    for (const double2 &d : diag) pmin = std::min(pmin, d.x * d.x);
+    return pmin >= kLowPivot ? pmin : 0.0;
+  };
+  // Out = A C for the npw x M complex64 block A and the FP64 M x M matrix C
+  // (rounded to complex64), both split into BF16 planes
+  void *tpl = nullptr, *ytpl = nullptr;
+  auto split_coef = [&](const double2 *C) {
+    float2 *C32 = (float2 *)Hs;  // free whenever a coefficient matrix is split
+    launch_c128_to_c64(M, M, C, M, C32, M, st);
+    tpl = s->cplanes.get(8 * (size_t)ldm * M);
+    split_planes(M, M, C32, M, tpl, ldm, st);
+    ytpl = s->rr_planes.get(8 * (size_t)npw * ldm);
+  };
+  auto rotate = [&](const float2 *A, void *Out, int64_t ldo) {
+    split_planes_t(npw, M, A, npw, ytpl, ldm, st);
+    rr_rotate_planes(npw, M, ytpl, ldm, tpl, ldm, Out, ldo, st);
+  };
+  // equilibrated block Ye = Y E (E = diag of inverse column norms)
+  launch_col_norms(npw, M, Y, ld, nrm, inv, st, true);
+  launch_scale_cols_f(npw, M, Y, ld, inv, Ye, npw, st);
+  double pmin = gram_chol(Ye);
+  if (pmin == 0.0) return 0;
+  void *trw = s->eig2.get(ztrtri_work_bytes(M));
+  double2 *U1i = nullptr;
+  if (pmin < kTwoPass) {
+    // Q1 = Ye U1^-1, then the Gram matrix of Q1 (close to I)
+    U1i = (double2 *)s->small5.get(mm);
+    int tok = s->prof.begin(PROF_ROT, 16.0 * (double)npw * M * M, st);
+    ztrtri_upper(M, G, M, trw, st);
+    launch_copy_block(M, M, G, M, U1i, M, st);
+    split_coef(U1i);
+    rotate(Ye, spare, npw);
+    s->prof.end(tok, st);
+    std::swap(Ye, spare);
+    if (gram_chol(Ye) == 0.0) return 0;
+  }
+  // H Ye (mixed H application) and H_s = Ye^H (H Ye)
+  float2 *HYe = spare;
+  apply_core(s, Ye, npw, nullptr, 0, HYe, npw, M, 1.0, 0.0, 0.0, st, ABI_C64);
+  // (ypl still holds the planes of Ye from its Gram matrix)
+  part = s->cpart.get(sizeof(float2) * (size_t)splits * M * M);  // apply_core may regrow it
+  int tok = s->prof.begin(PROF_GRAM, gflops, st);
+  rr_gram_f32(M, npw, ypl, s->ldPA, HYe, npw, part, splits, st);
+  launch_parts_to_c128(M, M, part, splits, true, Hs, st);
+  s->prof.end(tok, st);
+  launch_hermitize(M, Hs, M, st);
+  tok = s->prof.begin(PROF_CHOL, 16.0 * (double)M * M * M, st);
+  ztrtri_upper(M, G, M, trw, st);
+  zgemm(OP_N, OP_N, M, M, M, Hs, M, G, M, T, M, double2{1, 0}, double2{0, 0}, st);
+  zgemm(OP_C, OP_N, M, M, M, G, M, T, M, Hs, M, double2{1, 0}, double2{0, 0}, st);
+  s->prof.end(tok, st);
+  void *ew = s->eig1.get(zheev_work_bytes(M));
+  tok = s->prof.begin(PROF_EIG, 16.0 / 3.0 * (double)M * M * M, st);
+  zheev(M, Hs, M, w_dev, Z, M, ew, st);
+  s->prof.end(tok, st);
+  // T = U^-1 Z; Psi = Ye T and H Psi = (H Ye) T as split-BF16 products
+  tok = s->prof.begin(PROF_ROT, 8.0 * (double)M * M * M + 16.0 * (double)npw * M * M, st);
+  zgemm(OP_N, OP_N, M, M, M, G, M, Z, M, T, M, double2{1, 0}, double2{0, 0}, st);
+  split_coef(T);
+  rotate(Ye, Y, ld);
+  void *HP;
+  int64_t ldh;
+  if (HPsi) {
+    HP = HPsi;
+    ldh = ldh_in;
+  } else {
+    HP = s->blk3.get(blk);
+    ldh = npw;
+  }
+  rotate(HYe, HP, ldh);
+  s->prof.end(tok, st);
+  if (coef) {
+    // Psi = Y_in E [U1^-1] T
+    const double2 *C = T;
+    if (U1i) {
+      zgemm(OP_N, OP_N, M, M, M, U1i, M, T, M, Z, M, double2{1, 0}, double2{0, 0}, st);
+      C = Z;
+    }
+    launch_copy_block(M, M, C, M, coef, M, st);
+    launch_scale_rows(M, M, coef, M, inv, st);
+  }
+  launch_residual_norms_f(npw, M, Y, ld, HP, ldh, w_dev, r_dev, st);
+  CHEBFI_HIP(hipMemcpyAsync(eval, w_dev, sizeof(double) * M, hipMemcpyDeviceToHost, st));
+  if (resnorm)
+    CHEBFI_HIP(hipMemcpyAsync(resnorm, r_dev, sizeof(double) * M, hipMemcpyDeviceToHost, st));
+  CHEBFI_HIP(hipStreamSynchronize(st));
+  return U1i ? 2 : 1;
+}
+
 void rr_core(abi_system_s *s, double2 *Y, int64_t ld, double2 *HPsi, int64_t ldh_in, int64_t M,
              double *eval, double *resnorm, void *coef, hipStream_t st) {
   const int64_t npw = s->npw;

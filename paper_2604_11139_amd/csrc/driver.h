@@ -62,6 +62,13 @@ void project_c128(abi_system_s *s, const void *X, int64_t ldx, int64_t nband, do
 // Overlap tables from Q (host, natom*16 complex): B = P^H P and the Woodbury kernel K.
 void setup_overlap(abi_system_s *s, const double *qij, hipStream_t st);
 
+// Split-BF16 Rayleigh-Ritz of a complex64 block (mixed handle, S = I): 0
+// (nothing written) when the equilibrated Gram matrix is not safely positive
+// definite at that precision, 1 after one Cholesky pass, 2 after two (the
+// block orthonormalised first).
+int rr_lowprec(abi_system_s *s, void *Y, int64_t ld, void *HPsi, int64_t ldh_in, int64_t M,
+                double *eval, double *resnorm, void *coef, hipStream_t st);
+
 // FP64 Rayleigh-Ritz on a complex128 block Y (in: filtered block, out: Psi).
 void rr_core(abi_system_s *s, double2 *Y, int64_t ld, double2 *HPsi, int64_t ldh_in, int64_t M,
              double *eval, double *resnorm, void *coef, hipStream_t st);

@@ -1095,8 +1095,10 @@ __device__ __forceinline__ v8bf cat4(bf2_t a, bf2_t b, bf2_t c, bf2_t d) {
   return __builtin_shufflevector(ab, cd, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
+// ROLE only names the instantiation: 0 for the filter's projector products, 1
+// for the Rayleigh-Ritz products (same code, told apart in kernel traces).
 template <int BM, int BN, int NWM, int NWN, bool CONJ, bool SPLIT, bool BF32, bool PIPE = false,
-          bool PERSIST = false>
+          bool PERSIST = false, int ROLE = 0>
 __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl_kernel(
     int64_t m, int64_t n, int64_t kdata, const u16 *__restrict__ Apl, int64_t lda, int64_t psa,
     const void *__restrict__ Bsrc, int64_t ldb, int64_t psb, float2 *__restrict__ C,
@@ -1776,6 +1778,44 @@ void proj_gemm_bf16x3(int64_t nproj, int64_t nband, int64_t npw, const void *Apl
   CHEBFI_HIP(hipGetLastError());
 }
 
+// Transposed split: tiles of 64 rows x 64 columns of X pass through LDS so that
+// both the reads (rows contiguous) and the plane writes (columns contiguous)
+// are coalesced.
+__global__ __launch_bounds__(256) void split_planes_t_kernel(int64_t rows, int64_t cols,
+                                                             const float2 *__restrict__ X,
+                                                             int64_t ld, u16 *__restrict__ pl,
+                                                             int64_t ldp, int64_t ps) {
+  __shared__ float2 t[64][65];
+  const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int ii = e & 63, jj = e >> 6;
+    const int64_t i = i0 + ii, j = j0 + jj;
+    t[jj][ii] = (i < rows && j < cols) ? X[i + j * ld] : float2{0.f, 0.f};
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int jj = e & 63, ii = e >> 6;
+    const int64_t i = i0 + ii, j = j0 + jj;
+    if (i >= rows || j >= ldp) continue;
+    const float2 v = t[jj][ii];  // zero past cols
+    const u16 hr = bf16_rn(v.x), hi = bf16_rn(v.y);
+    const int64_t o = i * ldp + j;
+    pl[o] = hr;
+    pl[ps + o] = hi;
+    pl[2 * ps + o] = bf16_rn(v.x - bf16_val(hr));
+    pl[3 * ps + o] = bf16_rn(v.y - bf16_val(hi));
+  }
+}
+
+void split_planes_t(int64_t rows, int64_t cols, const void *X, int64_t ld, void *planes,
+                    int64_t ldp, hipStream_t st) {
+  if (rows <= 0 || ldp <= 0) return;
+  dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((ldp + 63) / 64));
+  hipLaunchKernelGGL(split_planes_t_kernel, grid, dim3(256), 0, st, rows, cols,
+                     (const float2 *)X, ld, (u16 *)planes, ldp, ldp * rows);
+  CHEBFI_HIP(hipGetLastError());
+}
+
 void split_planes(int64_t rows, int64_t cols, const void *X, int64_t ld, void *planes,
                   int64_t ldp, hipStream_t st) {
   const int64_t total = ldp * cols;
@@ -1938,6 +1978,36 @@ void expand_gemm_planes(int64_t npw, int64_t nband, int64_t nproj, const void *A
                         int64_t ldo, hipStream_t st, int variant, bool accumulate) {
   launch_pl<false, false>(variant, dim3(1, 1, 1), npw, nband, nproj, Apl, lda, psa, Cpl, ldc_pl,
                           psc, Out, ldo, nproj, nullptr, st, accumulate);
+}
+
+void rr_gram_f32(int64_t m, int64_t npw, const void *Apl, int64_t lda, const void *Y,
+                 int64_t ldy, void *part, int splits, hipStream_t st) {
+  const int64_t chunk = ((npw + splits - 1) / splits + XBK - 1) / XBK * XBK;
+  const int64_t kpad = (npw + 31) / 32 * 32;
+  CHEBFI_REQUIRE(kpad <= lda, ABI_ERR_ARG, "block planes must be zero-padded to 32");
+  CHEBFI_REQUIRE(128 * lda < (1ll << 31), ABI_ERR_ARG, "block planes too long");
+  dim3 grid((unsigned)((m + 127) / 128), (unsigned)((m + 127) / 128), (unsigned)splits);
+  hipLaunchKernelGGL((zgemm_dl_kernel<128, 128, 2, 4, true, true, true, true, false, 1>), grid,
+                     dim3(512), 0, st, m, m, npw, (const u16 *)Apl, lda, m * lda, Y, ldy,
+                     (int64_t)0, (float2 *)nullptr, (int64_t)0, chunk, kpad, (float2 *)part, 1);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void rr_rotate_planes(int64_t npw, int64_t m, const void *Apl, int64_t lda, const void *Tpl,
+                      int64_t ldt, void *Out, int64_t ldo, hipStream_t st) {
+  const int64_t tiles = ((npw + 127) / 128) * ((m + 127) / 128);
+  const int64_t per_xcd =
+      std::max<int64_t>(1, std::min<int64_t>(device_cus() / 8, (tiles + 7) / 8));
+  const int64_t kpad = (m + 31) / 32 * 32;
+  CHEBFI_REQUIRE(kpad <= lda && kpad <= ldt, ABI_ERR_ARG,
+                 "split-BF16 planes must be zero-padded to a multiple of 32");
+  CHEBFI_REQUIRE(128 * lda < (1ll << 31) && 128 * ldt < (1ll << 31), ABI_ERR_ARG,
+                 "split-BF16 tile spans more than 2^31 elements");
+  hipLaunchKernelGGL((zgemm_dl_kernel<128, 128, 2, 4, false, false, false, true, true, 1>),
+                     dim3((unsigned)(8 * per_xcd)), dim3(512), 0, st, npw, m, m, (const u16 *)Apl,
+                     lda, npw * lda, (const void *)Tpl, ldt, ldt * m, (float2 *)Out, ldo, kpad,
+                     kpad, (float2 *)nullptr, 0);
+  CHEBFI_HIP(hipGetLastError());
 }
 
 void expand_gemm_bf16x3(int64_t npw, int64_t nband, int64_t nproj, const void *Apl, int64_t lda,

@@ -246,11 +246,12 @@ struct abi_system_s {
   int pl_proj = 0, pl_expand = 0;  // tile variants of the split-BF16 products
 
   // work buffers
-  chebfi::DevBuf box, cpart, cprime, blk1, blk2, blk3, small1, small2, small3, small4, scal;
+  chebfi::DevBuf box, cpart, cprime, blk1, blk2, blk3, small1, small2, small3, small4, small5, scal;
   chebfi::DevBuf eig1, eig2, eig3, blk4, box2, adj, adjsmall, adjc, planes, cplanes;
   chebfi::DevBuf solve1, solve2, solve3;  // blocks of the multi-cycle driver
   chebfi::DevBuf expout;  // projector part P C' of the mixed H application
   chebfi::DevBuf tune_out;  // output block of the autotuner's timed H applications
+  chebfi::DevBuf rr_planes;  // split-BF16 Rayleigh-Ritz: planes of the equilibrated block
   chebfi::DevBuf gen_c, gen_e, gen_f, gen_ff, blk5, blk6;  // overlap path
   chebfi::DevBuf lob_z, lob_hz, lob_sz, lob_t1, lob_t2, lob_t3, lob_psi, lob_hp, lob_sp, lob_c,
       lob_g, lob_v;  // block LOBPCG

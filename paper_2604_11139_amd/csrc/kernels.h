@@ -70,6 +70,12 @@ void expand_gemm_bf16x3(int64_t npw, int64_t nband, int64_t nproj, const void *A
 // (column j = band j, contraction index contiguous, stride ld, plane stride ps).
 void split_planes(int64_t rows, int64_t cols, const void *X, int64_t ld, void *planes,
                   int64_t ldp, hipStream_t st);
+// The transposed planes of a complex float block X (rows x cols, ld): plane p
+// holds row i of X as its row i with the column index contiguous (stride ldp
+// >= cols, zero from cols to ldp), plane stride ldp * rows: the A operand of
+// the expansion-form product X W.
+void split_planes_t(int64_t rows, int64_t cols, const void *X, int64_t ld, void *planes,
+                    int64_t ldp, hipStream_t st);
 // `variant` selects the tile shape (0..6, see gemm.hip); proj_planes_splits
 // gives the K split count that fills the chip for that shape.
 int proj_planes_splits(int variant, int64_t nproj, int64_t nband, int64_t npw);
@@ -91,6 +97,15 @@ void proj_gemm_f32_variant(int variant, int64_t nproj, int64_t nband, int64_t np
 void expand_gemm_planes(int64_t npw, int64_t nband, int64_t nproj, const void *Apl, int64_t lda,
                         int64_t psa, const void *Cpl, int64_t ldc_pl, int64_t psc, void *Out,
                         int64_t ldo, hipStream_t st, int variant, bool accumulate = true);
+// Split-BF16 products of the Rayleigh-Ritz step (FP32 accumulation):
+// part[z] = Y_pl^H Y over plane-wave chunk z (m x m per chunk; the planes of
+// Y_pl zero-padded to a multiple of 32, ld lda, Y complex64 with ld ldy), and
+// Out = A T from the transposed planes of A (npw x m, ld lda) and the planes of
+// T (m x m, ld ldt), both zero-padded along m.
+void rr_gram_f32(int64_t m, int64_t npw, const void *Apl, int64_t lda, const void *Y,
+                 int64_t ldy, void *part, int splits, hipStream_t st);
+void rr_rotate_planes(int64_t npw, int64_t m, const void *Apl, int64_t lda, const void *Tpl,
+                      int64_t ldt, void *Out, int64_t ldo, hipStream_t st);
 // Single-band forms: c = P^H x, out += P c.
 void proj_gemv(int64_t npw, int nproj, const void *P, const void *x, void *c, hipStream_t st);
 void expand_gemv(int64_t npw, int nproj, const void *P, const void *c, void *out, hipStream_t st);
@@ -180,6 +195,20 @@ void launch_d2f(int64_t n, const double *src, float *dst, hipStream_t st);
 void launch_residual_norms(int64_t npw, int64_t nband, const void *Psi, int64_t ldp,
                            const void *HPsi, int64_t ldh, const double *eval, double *res,
                            hipStream_t st);
+
+// the same for complex float blocks (FP64 sums)
+void launch_residual_norms_f(int64_t npw, int64_t nband, const void *Psi, int64_t ldp,
+                             const void *HPsi, int64_t ldh, const double *eval, double *res,
+                             hipStream_t st);
+// nrm[b] = ||X[:, b]||, inv[b] = 1 / nrm[b] (0 for a zero column)
+void launch_col_norms(int64_t npw, int64_t nband, const void *X, int64_t ldx, double *nrm,
+                      double *inv, hipStream_t st, bool fp32);
+// out[:, b] = sc[b] X[:, b] (complex float blocks)
+void launch_scale_cols_f(int64_t rows, int64_t cols, const void *X, int64_t ldx, const double *sc,
+                         void *out, int64_t ldo, hipStream_t st);
+// A[k, j] *= sc[k] (m x n complex double)
+void launch_scale_rows(int64_t m, int64_t n, void *A, int64_t lda, const double *sc,
+                       hipStream_t st);
 
 // dense helpers (m x m complex double)
 void launch_hermitize(int64_t m, void *A, int64_t lda, hipStream_t st);  // A = (A + A^H)/2

@@ -245,6 +245,68 @@ __global__ void residual_kernel(int64_t npw, const double2 *__restrict__ Psi, in
   if (threadIdx.x == 0) res[b] = sqrt(s);
 }
 
+// residual norms of a complex float block (FP64 sums)
+__global__ void residual_f_kernel(int64_t npw, const float2 *__restrict__ Psi, int64_t ldp,
+                                  const float2 *__restrict__ HPsi, int64_t ldh,
+                                  const double *__restrict__ eval, double *__restrict__ res) {
+  __shared__ double scratch[16];
+  const int64_t b = blockIdx.x;
+  const double lam = eval[b];
+  const float2 *p = Psi + b * ldp;
+  const float2 *h = HPsi + b * ldh;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < npw; i += blockDim.x) {
+    const float2 pv = p[i], hv = h[i];
+    const double rx = (double)hv.x - lam * pv.x, ry = (double)hv.y - lam * pv.y;
+    s += rx * rx + ry * ry;
+  }
+  s = block_sum(s, scratch);
+  if (threadIdx.x == 0) res[b] = sqrt(s);
+}
+
+// nrm[b] = ||X[:, b]|| and inv[b] = 1 / nrm[b] (0 for a zero column), FP64 sums
+template <typename V2>
+__global__ void col_norms_kernel(int64_t npw, const V2 *__restrict__ X, int64_t ldx,
+                                 double *__restrict__ nrm, double *__restrict__ inv) {
+  __shared__ double scratch[16];
+  const int64_t b = blockIdx.x;
+  const V2 *x = X + b * ldx;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < npw; i += blockDim.x) {
+    const double xr = x[i].x, xi = x[i].y;
+    s += xr * xr + xi * xi;
+  }
+  s = block_sum(s, scratch);
+  if (threadIdx.x == 0) {
+    const double r = sqrt(s);
+    nrm[b] = r;
+    inv[b] = r > 0.0 ? 1.0 / r : 0.0;
+  }
+}
+
+// out[:, b] = X[:, b] * sc[b] (complex float blocks, the scale rounded once)
+__global__ void scale_cols_f_kernel(int64_t rows, int64_t cols, const float2 *__restrict__ X,
+                                    int64_t ldx, const double *__restrict__ sc,
+                                    float2 *__restrict__ out, int64_t ldo) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t i = idx % rows, b = idx / rows;
+  const double f = sc[b];
+  const float2 v = X[i + b * ldx];
+  out[i + b * ldo] = float2{(float)(v.x * f), (float)(v.y * f)};
+}
+
+// A[k, j] *= sc[k] (m x n complex double, ld lda): the rows of a coefficient matrix
+__global__ void scale_rows_kernel(int64_t m, int64_t n, double2 *__restrict__ A, int64_t lda,
+                                  const double *__restrict__ sc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * n) return;
+  const int64_t k = idx % m, j = idx / m;
+  double2 &a = A[k + j * lda];
+  a.x *= sc[k];
+  a.y *= sc[k];
+}
+
 __global__ void hermitize_kernel(int64_t m, double2 *__restrict__ A, int64_t lda) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= m * m) return;
@@ -681,6 +743,41 @@ void launch_residual_norms(int64_t npw, int64_t nband, const void *Psi, int64_t 
                            hipStream_t st) {
   hipLaunchKernelGGL(residual_kernel, dim3((unsigned)nband), dim3(kRedThreads), 0, st, npw,
                      (const double2 *)Psi, ldp, (const double2 *)HPsi, ldh, eval, res);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_residual_norms_f(int64_t npw, int64_t nband, const void *Psi, int64_t ldp,
+                             const void *HPsi, int64_t ldh, const double *eval, double *res,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(residual_f_kernel, dim3((unsigned)nband), dim3(kRedThreads), 0, st, npw,
+                     (const float2 *)Psi, ldp, (const float2 *)HPsi, ldh, eval, res);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_col_norms(int64_t npw, int64_t nband, const void *X, int64_t ldx, double *nrm,
+                      double *inv, hipStream_t st, bool fp32) {
+  if (fp32)
+    hipLaunchKernelGGL(col_norms_kernel<float2>, dim3((unsigned)nband), dim3(kRedThreads), 0, st,
+                       npw, (const float2 *)X, ldx, nrm, inv);
+  else
+    hipLaunchKernelGGL(col_norms_kernel<double2>, dim3((unsigned)nband), dim3(kRedThreads), 0,
+                       st, npw, (const double2 *)X, ldx, nrm, inv);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_scale_cols_f(int64_t rows, int64_t cols, const void *X, int64_t ldx, const double *sc,
+                         void *out, int64_t ldo, hipStream_t st) {
+  if (rows * cols <= 0) return;
+  hipLaunchKernelGGL(scale_cols_f_kernel, dim3(nblk(rows * cols, 256)), dim3(256), 0, st, rows,
+                     cols, (const float2 *)X, ldx, sc, (float2 *)out, ldo);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_scale_rows(int64_t m, int64_t n, void *A, int64_t lda, const double *sc,
+                       hipStream_t st) {
+  if (m * n <= 0) return;
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(nblk(m * n, 256)), dim3(256), 0, st, m, n,
+                     (double2 *)A, lda, sc);
   CHEBFI_HIP(hipGetLastError());
 }
 

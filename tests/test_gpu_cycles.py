@@ -62,9 +62,11 @@ def _gpu():
     torch.cuda.synchronize()
 
 
-def _cycles(g, X, v0, s, ncyc, want_last=False):
+def _cycles(g, X, v0, s, ncyc, want_last=False, lowprec_cycles=0, flags=None):
     """Runs ncyc cycles in place on X; returns per-cycle (bounds, eval, res)
-    and, with want_last, the last cycle's input block and its outputs."""
+    and, with want_last, the last cycle's input block and its outputs.  The
+    first lowprec_cycles cycles ask for the split-BF16 Rayleigh-Ritz; their
+    flags are appended to the list flags."""
     import torch
     out = []
     last = None
@@ -77,7 +79,9 @@ def _cycles(g, X, v0, s, ncyc, want_last=False):
             ev, res, _, C = g.rayleigh_ritz(Y, hp, want_coef=True)
             last = (Xin, Y, hp, C, bounds)
         else:
-            ev, res, _ = g.rayleigh_ritz(Y)
+            ev, res, fl = g.rayleigh_ritz(Y, lowprec=c < lowprec_cycles)
+            if flags is not None and c < lowprec_cycles:
+                flags.append(fl)
         X.copy_(Y)
         del Y
         out.append((bounds, np.asarray(ev), np.asarray(res)))
@@ -167,3 +171,25 @@ def test_mixed_cycles_and_gradient_vs_oracle():
     k = int(np.argmax(np.abs(chain)))
     assert abs(fd[k] - float(np.dot(grad, dirs[k]))) <= 0.05 * abs(chain[k])
     assert abs(fd[k] - float(np.dot(rho, dirs[k]))) >= 0.5 * abs(chain[k])
+
+
+def test_mixed_lowprec_rr_cycles_vs_oracle():
+    """The mixed form as the solver runs it before an FP64 refinement: all but
+    the last cycle with the split-BF16 Rayleigh-Ritz, the last with the FP64
+    one.  Ritz values within the mixed form's 1e-6 Ha of the oracle's cycles."""
+    import torch
+    ref = _ref()
+    s = W.make_system(3)
+    ncyc = len(ref["cycles"])
+    flags = []
+    with B.System(s, precision=B.ABI_PREC_MIXED) as g:
+        X = to_dev(W.random_block(g.npw, s.nband, s.tag)).to(torch.complex64)
+        v0 = to_dev(W.random_vector(g.npw, s.tag))[0]
+        runs, _ = _cycles(g, X, v0, s, ncyc, lowprec_cycles=ncyc - 1, flags=flags)
+    assert all(f & B.RR_LOWPREC for f in flags) and len(flags) == ncyc - 1
+    for (bounds, ev, res), rc in zip(runs[:-1], ref["cycles"][:-1]):
+        # intermediate cycles: split-BF16 rounding of the Rayleigh-Ritz products
+        rv = np.array(rc["eval"])
+        assert np.abs(ev - rv).max() <= 1e-4 * np.abs(rv).max()
+    d = np.abs(runs[-1][1] - np.array(ref["cycles"][-1]["eval"]))
+    assert d.max() <= 1e-6, d.max()
