@@ -54,8 +54,13 @@ def parse():
                     help="skip the adjoint, batched, PAW, solver-comparison and SCF legs")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched leg and print its JSON (profiling)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint leg on the large workload (profiling)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch choices (no autotuning of the mixed form)")
+    ap.add_argument("--tuning", default="",
+                    help="fixed launch choices instead of the autotuner, e.g. "
+                         "proj=14,expand=15,fft_batch=64 (counter runs)")
     return ap.parse_args()
 
 
@@ -511,10 +516,6 @@ def main():
     from paper_2604_11139_amd import binding as B
 
     torch.cuda.set_device(0)
-    if args.batch_only:
-        print(json.dumps({"batch": batch_leg()}), flush=True)
-        return
-    ceil = None if args.no_ceilings else ceilings()
     if args.copy_mib > 0:
         # a plain device copy of known size: its FETCH_SIZE / WRITE_SIZE counters
         # calibrate the per-dispatch traffic of the path's kernels
@@ -524,6 +525,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.batch_only:
+        print(json.dumps({"batch": batch_leg()}), flush=True)
+        return
+    ceil = None if args.no_ceilings else ceilings()
     s = W.make_system(args.config, q_scale=W.PAW_Q_SCALE if args.paw else 0.0)
     degree = s.degree
     t_setup = time.perf_counter()
@@ -537,8 +542,24 @@ def main():
     X64 = torch.from_numpy(W.random_block(npw, nband, s.tag).T).to("cuda")
     v0 = torch.from_numpy(W.random_vector(npw, s.tag)).to("cuda")
     X32 = X64.to(torch.complex64)
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_leg(g, X32, v0, degree)}), flush=True)
+        return
     tune = None
-    if not args.no_tune and args.precision in ("both", "mixed"):
+    if args.tuning:
+        names = {"proj": B.TUNE_PROJ, "expand": B.TUNE_EXPAND, "fft_batch": B.TUNE_FFT_BATCH,
+                 "overlap": B.TUNE_OVERLAP}
+        choice = {}
+        for kv in args.tuning.split(","):
+            k, v = kv.split("=")
+            g.set_tuning(names[k], int(v))
+            choice[k] = int(v)
+        tune = {"choice": choice, "fixed": True}
+        if choice.get("proj") in PROJ_KERNELS:
+            CLASS_KERNELS["proj_gemm"] = (PROJ_KERNELS[choice["proj"]], "gemm.hip")
+        if choice.get("expand") in EXPAND_KERNELS:
+            CLASS_KERNELS["expand_gemm"] = (EXPAND_KERNELS[choice["expand"]], "gemm.hip")
+    elif not args.no_tune and args.precision in ("both", "mixed"):
         # the library's autotuner on the timed block (launch choices of the mixed
         # form; untimed)
         choice, cached = g.autotune(X32)

@@ -459,7 +459,8 @@ int rr_lowprec(abi_system_s *s, void *Y, int64_t ld, void *HPsi, int64_t ldh_in,
   double *w_dev = scal + 160;
   double *r_dev = w_dev + M;
   double *nrm = r_dev + M, *inv = nrm + M;
-  int *info = (int *)(inv + M);
+  double *pmin_dev = inv + M;
+  int *info = (int *)(pmin_dev + 1);
   const size_t blk = sizeof(float2) * (size_t)npw * M;
   float2 *Ye = (float2 *)s->blk4.get(blk);
   float2 *spare = (float2 *)s->blk1.get(blk);
@@ -483,15 +484,14 @@ int rr_lowprec(abi_system_s *s, void *Y, int64_t ld, void *HPsi, int64_t ldh_in,
     tok = s->prof.begin(PROF_CHOL, 4.0 / 3.0 * (double)M * M * M, st);
     zpotrf_upper(M, G, M, info, nullptr, st);
     s->prof.end(tok, st);
-    int hinfo = 0;
-    std::vector<double2> diag((size_t)M);
-    CHEBFI_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, st));
-    CHEBFI_HIP(hipMemcpy2DAsync(diag.data(), sizeof(double2), G, sizeof(double2) * (M + 1),
-                                sizeof(double2), (size_t)M, hipMemcpyDeviceToHost, st));
+    launch_diag_min_sq(M, G, M, pmin_dev, st);
+    // (the stream drained first, then blocking copies into host variables)
     CHEBFI_HIP(hipStreamSynchronize(st));
+    int hinfo = 0;
+    double pmin = 0.0;
+    CHEBFI_HIP(hipMemcpy(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost));
+    CHEBFI_HIP(hipMemcpy(&pmin, pmin_dev, sizeof(double), hipMemcpyDeviceToHost));
     if (hinfo != 0) return 0.0;
-    double pmin = HUGE_VAL;
-    for (const double2 &d : diag) pmin = std::min(pmin, d.x * d.x);
     return pmin >= kLowPivot ? pmin : 0.0;
   };
   // Out = A C for the npw x M complex64 block A and the FP64 M x M matrix C

@@ -203,6 +203,8 @@ void launch_residual_norms_f(int64_t npw, int64_t nband, const void *Psi, int64_
 // nrm[b] = ||X[:, b]||, inv[b] = 1 / nrm[b] (0 for a zero column)
 void launch_col_norms(int64_t npw, int64_t nband, const void *X, int64_t ldx, double *nrm,
                       double *inv, hipStream_t st, bool fp32);
+// *out = min_i (Re A[i, i])^2 (m x m complex double, one workgroup)
+void launch_diag_min_sq(int64_t m, const void *A, int64_t lda, double *out, hipStream_t st);
 // out[:, b] = sc[b] X[:, b] (complex float blocks)
 void launch_scale_cols_f(int64_t rows, int64_t cols, const void *X, int64_t ldx, const double *sc,
                          void *out, int64_t ldo, hipStream_t st);

@@ -284,6 +284,27 @@ __global__ void col_norms_kernel(int64_t npw, const V2 *__restrict__ X, int64_t 
   }
 }
 
+// *out = min_i (Re A[i, i])^2 over the diagonal of an m x m complex double matrix
+// (one workgroup)
+__global__ __launch_bounds__(kRedThreads) void diag_min_sq_kernel(int64_t m,
+                                                                  const double2 *__restrict__ A,
+                                                                  int64_t lda,
+                                                                  double *__restrict__ out) {
+  __shared__ double red[kRedThreads];
+  double v = HUGE_VAL;
+  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+    const double d = A[i + i * lda].x;
+    v = fmin(v, d * d);
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
 // out[:, b] = X[:, b] * sc[b] (complex float blocks, the scale rounded once)
 __global__ void scale_cols_f_kernel(int64_t rows, int64_t cols, const float2 *__restrict__ X,
                                     int64_t ldx, const double *__restrict__ sc,
@@ -762,6 +783,12 @@ void launch_col_norms(int64_t npw, int64_t nband, const void *X, int64_t ldx, do
   else
     hipLaunchKernelGGL(col_norms_kernel<double2>, dim3((unsigned)nband), dim3(kRedThreads), 0,
                        st, npw, (const double2 *)X, ldx, nrm, inv);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_diag_min_sq(int64_t m, const void *A, int64_t lda, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(diag_min_sq_kernel, dim3(1), dim3(kRedThreads), 0, st, m, (const double2 *)A,
+                     lda, out);
   CHEBFI_HIP(hipGetLastError());
 }
 
