@@ -1125,18 +1125,32 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl_kernel(
   // Tiles.  One tile per workgroup, or (PERSIST) a sequence of tiles per
   // workgroup: the grid holds 8 W workgroups (W per XCD, the hardware handing
   // workgroup ids to the XCDs round robin); round `it` gives XCD x the W
-  // consecutive tiles (row panel major) starting at (8 it + x) W, so that the
-  // workgroups an XCD runs together share their row panels in its L2.
+  // consecutive tiles starting at (8 it + x) W.  Tiles are numbered by blocks
+  // of PR row panels, column panel major inside a block, so that W = 32
+  // consecutive tiles cover 4 row x 8 column panels: the workgroups an XCD
+  // runs together share 4 A and 8 B panels in its L2 (2 and 16 in row panel
+  // major order).
+  constexpr int PR = 4;
   const int ntm = (int)((m + BM - 1) / BM), ntn = (int)((n + BN - 1) / BN);
   const int ntiles = ntm * ntn;
   const int wpx = (int)(gridDim.x >> 3), xcd = (int)(blockIdx.x & 7), wj = (int)(blockIdx.x >> 3);
   auto tile_of = [&](int it) -> int { return (it * 8 + xcd) * wpx + wj; };
+  // tile number -> (row panel, column panel)
+  auto tile_rc = [&](int t, int &tm, int &tn) {
+    const int b = t / (PR * ntn);
+    const int h = ntm - b * PR < PR ? ntm - b * PR : PR;
+    const int u = t - b * PR * ntn;
+    tn = u / h;
+    tm = b * PR + (u - tn * h);
+  };
   int64_t row0, col0, kbeg = 0, kend, tzv = 0;
   if constexpr (PERSIST) {
     const int t = tile_of(0);
     if (t >= ntiles) return;
-    row0 = (int64_t)(t / ntn) * BM;
-    col0 = (int64_t)(t % ntn) * BN;
+    int tm0, tn0;
+    tile_rc(t, tm0, tn0);
+    row0 = (int64_t)tm0 * BM;
+    col0 = (int64_t)tn0 * BN;
     kend = kpad;
   } else {
     unsigned tm, tn, tz;
@@ -1429,8 +1443,10 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl_kernel(
       if (sidx + 1 < ns) return true;
       const int t = tile_of(it + 1);
       if (t >= ntiles) return false;
-      nrow0 = (int64_t)(t / ntn) * BM;
-      ncol0 = (int64_t)(t % ntn) * BN;
+      int tm1, tn1;
+      tile_rc(t, tm1, tn1);
+      nrow0 = (int64_t)tm1 * BM;
+      ncol0 = (int64_t)tn1 * BN;
       set_offsets(nrow0, ncol0);  // the current tile issues no more loads
       return true;
     };
