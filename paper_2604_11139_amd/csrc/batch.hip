@@ -250,17 +250,20 @@ __global__ __launch_bounds__(512) void bpass_c_kernel(const BatchSys *__restrict
 }
 
 // ---- specialised passes for the systems of one cubic edge N ----------------
-// Same three passes as above over the items of the systems listed in gsys
-// (prefix offsets goff: bands x N items each), with N, the radix sequence and
-// the plane strides known at compile time (the cubic building blocks).
+// Same three passes as above over the items of the systems listed in gsys,
+// with N, the radix sequence and the plane strides known at compile time (the
+// cubic building blocks).  An item is NPL consecutive planes (pass B: x-z
+// slabs) of one band, stacked in LDS N (N + 1) elements apart, so that a
+// workgroup keeps about as much box data in flight on small boxes as one 64^2
+// plane; G = ceil(N / NPL) items per band (the last may hold fewer planes).
 
-// item -> (system, band, plane) inside one edge group
+// item -> (system, band, plane group) inside one edge group
 __device__ __forceinline__ int group_item(const int32_t *gsys, const int64_t *goff, int gns,
-                                          int64_t item, int N, int64_t *b, int *pl) {
+                                          int64_t item, int G, int64_t *b, int *grp) {
   const int q = find_sys(goff, gns, item);
   const int64_t loc = item - goff[q];
-  *b = loc / N;
-  *pl = (int)(loc - *b * N);
+  *b = loc / G;
+  *grp = (int)(loc - *b * G);
   return gsys[q];
 }
 
@@ -269,31 +272,35 @@ __global__ __launch_bounds__(kCT) void bcpass_a_kernel(const BatchSys *__restric
                                                        const BatchStep *__restrict__ step,
                                                        const int32_t *__restrict__ gsys,
                                                        const int64_t *__restrict__ goff, int gns) {
-  constexpr int NXY = N * N, LD = N + 1;
-  __shared__ C2<T> buf[N * LD];
+  constexpr int NXY = N * N, LD = N + 1, PL = N * LD;
+  constexpr int NPL = cplanes_per_item<T, N>(), G = (N + NPL - 1) / NPL;
+  __shared__ C2<T> buf[NPL * PL];
   __shared__ C2<T> tw[N];
   const int64_t total = goff[gns];
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     int64_t b;
-    int i3;
-    const int s = group_item(gsys, goff, gns, item, N, &b, &i3);
+    int g;
+    const int s = group_item(gsys, goff, gns, item, G, &b, &g);
+    const int i30 = g * NPL, np3 = N - i30 < NPL ? N - i30 : NPL;
     const BatchSys &d = sys[s];
     const BatchStep &st = step[s];
     for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(d.tw[i]);
-    for (int i = threadIdx.x; i < N * LD; i += kCT) buf[i] = C2<T>{0, 0};
+    for (int i = threadIdx.x; i < NPL * PL; i += kCT) buf[i] = C2<T>{0, 0};
     __syncthreads();
-    const int s0 = d.plane[i3], s1 = d.plane[i3 + 1];
+    // the sphere points of planes i30 .. i30 + np3 - 1 are contiguous; element
+    // e of the group (plane p, row r, column c) sits at e + e / N = p PL + r LD + c
+    const int s0 = d.plane[i30], s1 = d.plane[i30 + np3];
     const C2<T> *xb = reinterpret_cast<const C2<T> *>(st.yk) + b * st.ldk;
-    const int off = i3 * NXY;
+    const int off = i30 * NXY;
     for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
       const int e = d.box_index[idx] - off;
       buf[e + e / N] = xb[idx];
     }
     __syncthreads();
-    cfft<T, N, 0, 1, N, 1, LD, +1>(buf, tw);
-    cfft<T, N, 0, 1, N, LD, 1, +1>(buf, tw);
+    cfft<T, N, 0, 1, NPL * N, 1, LD, +1>(buf, tw);         // x: every row of every plane
+    cfft<T, N, 0, 1, N, LD, 1, +1, NPL, PL>(buf, tw);      // y: the columns of each plane
     C2<T> *dst = reinterpret_cast<C2<T> *>(d.box) + b * (int64_t)NXY * N + off;
-    for (int i = threadIdx.x; i < NXY; i += kCT) dst[i] = buf[i + i / N];
+    for (int i = threadIdx.x; i < np3 * NXY; i += kCT) dst[i] = buf[i + i / N];
     __syncthreads();
   }
 }
@@ -302,33 +309,42 @@ template <typename T, int N>
 __global__ __launch_bounds__(kCT) void bcpass_b_kernel(const BatchSys *__restrict__ sys,
                                                        const int32_t *__restrict__ gsys,
                                                        const int64_t *__restrict__ goff, int gns) {
-  constexpr int NXZ = N * N, LD = N + 1;
-  __shared__ C2<T> buf[N * LD];
+  constexpr int LD = N + 1, PL = N * LD;
+  constexpr int NPL = cplanes_per_item<T, N>(), G = (N + NPL - 1) / NPL;
+  __shared__ C2<T> buf[NPL * PL];
   __shared__ C2<T> tw[N];
   const int64_t total = goff[gns];
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     int64_t b;
-    int i2;
-    const int s = group_item(gsys, goff, gns, item, N, &b, &i2);
+    int g;
+    const int s = group_item(gsys, goff, gns, item, G, &b, &g);
+    const int i20 = g * NPL, np2 = N - i20 < NPL ? N - i20 : NPL;
     const BatchSys &d = sys[s];
     for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(d.tw[2 * kMaxN + i]);
-    C2<T> *src = reinterpret_cast<C2<T> *>(d.box) + b * (int64_t)N * N * N;
-    const T *V = reinterpret_cast<const T *>(d.V);
-    for (int i = threadIdx.x; i < NXZ; i += kCT) {
-      const int i1 = i % N, i3 = i / N;
-      buf[i3 * LD + i1] = src[i1 + N * (i2 + N * i3)];
+    // slabs i20 .. i20 + np2 - 1: for each i3 their rows are one contiguous run
+    // of np2 N elements in the box (q = p N + i1 along it)
+    C2<T> *src = reinterpret_cast<C2<T> *>(d.box) + b * (int64_t)N * N * N + (int64_t)i20 * N;
+    const T *V = reinterpret_cast<const T *>(d.V) + (int64_t)i20 * N;
+    const int run = np2 * N;
+    for (int i = threadIdx.x; i < run * N; i += kCT) {
+      const int q = i % run, i3 = i / run;
+      const int p = q / N, i1 = q - p * N;
+      buf[p * PL + i3 * LD + i1] = src[q + N * N * i3];
     }
     __syncthreads();
-    cfft<T, N, 0, 1, N, LD, 1, +1>(buf, tw);
-    for (int i = threadIdx.x; i < NXZ; i += kCT) {
-      const int i1 = i % N, i3 = i / N;
-      buf[i3 * LD + i1] = cscale(buf[i3 * LD + i1], V[i1 + N * (i2 + N * i3)]);
+    cfft<T, N, 0, 1, N, LD, 1, +1, NPL, PL>(buf, tw);
+    for (int i = threadIdx.x; i < run * N; i += kCT) {
+      const int q = i % run, i3 = i / run;
+      const int p = q / N, i1 = q - p * N;
+      const int o = p * PL + i3 * LD + i1;
+      buf[o] = cscale(buf[o], V[q + N * N * i3]);
     }
     __syncthreads();
-    cfft<T, N, 0, 1, N, LD, 1, -1>(buf, tw);
-    for (int i = threadIdx.x; i < NXZ; i += kCT) {
-      const int i1 = i % N, i3 = i / N;
-      src[i1 + N * (i2 + N * i3)] = buf[i3 * LD + i1];
+    cfft<T, N, 0, 1, N, LD, 1, -1, NPL, PL>(buf, tw);
+    for (int i = threadIdx.x; i < run * N; i += kCT) {
+      const int q = i % run, i3 = i / run;
+      const int p = q / N, i1 = q - p * N;
+      src[q + N * N * i3] = buf[p * PL + i3 * LD + i1];
     }
     __syncthreads();
   }
@@ -339,28 +355,30 @@ __global__ __launch_bounds__(kCT) void bcpass_c_kernel(const BatchSys *__restric
                                                        const BatchStep *__restrict__ step,
                                                        const int32_t *__restrict__ gsys,
                                                        const int64_t *__restrict__ goff, int gns) {
-  constexpr int NXY = N * N, LD = N + 1;
-  __shared__ C2<T> buf[N * LD];
+  constexpr int NXY = N * N, LD = N + 1, PL = N * LD;
+  constexpr int NPL = cplanes_per_item<T, N>(), G = (N + NPL - 1) / NPL;
+  __shared__ C2<T> buf[NPL * PL];
   __shared__ C2<T> tw[N];
   __shared__ C2<T> cp[kBatchMaxProj];
   const int64_t total = goff[gns];
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     int64_t b;
-    int i3;
-    const int s = group_item(gsys, goff, gns, item, N, &b, &i3);
+    int g;
+    const int s = group_item(gsys, goff, gns, item, G, &b, &g);
+    const int i30 = g * NPL, np3 = N - i30 < NPL ? N - i30 : NPL;
     const BatchSys &d = sys[s];
     const BatchStep &st = step[s];
     const int np = d.nproj;
     for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(d.tw[i]);
     if (threadIdx.x < np)
       cp[threadIdx.x] = reinterpret_cast<const C2<T> *>(d.Cp)[b * np + threadIdx.x];
-    const int off = i3 * NXY;
+    const int off = i30 * NXY;
     const C2<T> *src = reinterpret_cast<const C2<T> *>(d.box) + b * (int64_t)NXY * N + off;
-    for (int i = threadIdx.x; i < NXY; i += kCT) buf[i + i / N] = src[i];
+    for (int i = threadIdx.x; i < np3 * NXY; i += kCT) buf[i + i / N] = src[i];
     __syncthreads();
-    cfft<T, N, 0, 1, N, LD, 1, -1>(buf, tw);
-    cfft<T, N, 0, 1, N, 1, LD, -1>(buf, tw);
-    const int s0 = d.plane[i3], s1 = d.plane[i3 + 1];
+    cfft<T, N, 0, 1, N, LD, 1, -1, NPL, PL>(buf, tw);      // y: the columns of each plane
+    cfft<T, N, 0, 1, NPL * N, 1, LD, -1>(buf, tw);         // x: every row of every plane
+    const int s0 = d.plane[i30], s1 = d.plane[i30 + np3];
     const C2<T> *yk = reinterpret_cast<const C2<T> *>(st.yk) + b * st.ldk;
     const C2<T> *yp =
         st.yprev ? reinterpret_cast<const C2<T> *>(st.yprev) + b * st.ldp : nullptr;
@@ -459,6 +477,12 @@ void batch_step(const BatchLaunch &L, int j, hipStream_t st) {
                        L.d_sys, stp, offA, L.nsys);
     CHEBFI_HIP(hipGetLastError());
   }
+}
+
+int batch_item_planes(int n, bool fp32) {
+  // (the host side of cplanes_per_item)
+  const int per = 34000 / (n * (n + 1) * (fp32 ? 8 : 16));
+  return per > 1 ? per : 1;
 }
 
 bool batch_edge_specialised(int n) {

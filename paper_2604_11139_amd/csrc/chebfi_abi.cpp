@@ -385,9 +385,10 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
     gsys_at.push_back(hgsys.size());
     goff_at.push_back(hgoff.size());
     hgoff.push_back(0);
+    const int npl = batch_item_planes(gedge[g], fp32);
     for (int32_t i : glist[g]) {
       hgsys.push_back(i);
-      hgoff.push_back(hgoff.back() + nband[i] * gedge[g]);
+      hgoff.push_back(hgoff.back() + nband[i] * ((gedge[g] + npl - 1) / npl));
     }
   }
   // step table: Y_0 = X, Y_m = Y, Y_j (0 < j < m) in slot j % 2 (the update of

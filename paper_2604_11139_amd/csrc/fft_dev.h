@@ -84,6 +84,36 @@ template <typename T> struct Dft<T, 6> {
   }
 };
 
+template <typename T> struct Dft<T, 9> {
+  // 3 x 3: radix-3 DFTs of x[n2], x[n2+3], x[n2+6], twiddles w9^(n2 k1), then
+  // radix-3 DFTs across n2 (output k1 + 3 k2), w9 = e^{sgn 2 pi i / 9}
+  static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
+    C2<T> a[3][3];
+#pragma unroll
+    for (int n2 = 0; n2 < 3; ++n2) {
+      a[n2][0] = x[n2];
+      a[n2][1] = x[n2 + 3];
+      a[n2][2] = x[n2 + 6];
+      Dft<T, 3>::run(a[n2], sgn);
+    }
+    const T c1 = (T)0.76604444311897803520, s1 = (T)0.64278760968653932632;   // 2 pi / 9
+    const T c2 = (T)0.17364817766693034885, s2 = (T)0.98480775301220805936;   // 4 pi / 9
+    const T c4 = (T)-0.93969262078590838405, s4 = (T)0.34202014332566873304;  // 8 pi / 9
+    a[1][1] = cmul(a[1][1], C2<T>{c1, (T)sgn * s1});
+    a[1][2] = cmul(a[1][2], C2<T>{c2, (T)sgn * s2});
+    a[2][1] = cmul(a[2][1], C2<T>{c2, (T)sgn * s2});
+    a[2][2] = cmul(a[2][2], C2<T>{c4, (T)sgn * s4});
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      C2<T> b[3] = {a[0][k1], a[1][k1], a[2][k1]};
+      Dft<T, 3>::run(b, sgn);
+      x[k1] = b[0];
+      x[k1 + 3] = b[1];
+      x[k1 + 6] = b[2];
+    }
+  }
+};
+
 template <typename T> struct Dft<T, 8> {
   // even/odd split: two radix-4 DFTs combined with w8^k = e^{sgn i pi k/4}
   static __device__ __forceinline__ void run(C2<T> *x, int sgn) {
@@ -215,22 +245,26 @@ CHEBFI_CPLAN(18, 2, 6, 3, 1)
 CHEBFI_CPLAN(20, 2, 5, 4, 1)
 CHEBFI_CPLAN(24, 2, 8, 3, 1)
 CHEBFI_CPLAN(25, 2, 5, 5, 1)
-CHEBFI_CPLAN(27, 3, 3, 3, 3)
+CHEBFI_CPLAN(27, 2, 3, 9, 1)
 CHEBFI_CPLAN(30, 2, 6, 5, 1)
 CHEBFI_CPLAN(32, 2, 8, 4, 1)
 CHEBFI_CPLAN(36, 2, 6, 6, 1)
 CHEBFI_CPLAN(40, 2, 8, 5, 1)
-CHEBFI_CPLAN(45, 3, 5, 3, 3)
+CHEBFI_CPLAN(45, 2, 5, 9, 1)
 CHEBFI_CPLAN(48, 2, 8, 6, 1)
 CHEBFI_CPLAN(64, 2, 8, 8, 1)
 #undef CHEBFI_CPLAN
 
 constexpr int kCT = 512;  // threads of the specialised passes (16 waves per CU per 4 planes)
 
-template <typename T, int N, int R, int P, int NPEN, int ES, int PS, int SGN>
+// NG groups of NPEN pencils (group g's pencils start at g * GS): several
+// planes of one LDS buffer transformed by one pass over all their pencils.
+template <typename T, int N, int R, int P, int NPEN, int ES, int PS, int SGN, int NG = 1,
+          int GS = 0>
 __device__ __forceinline__ void cstage(C2<T> *buf, const C2<T> *tw) {
   constexpr int NBF = N / R;
-  constexpr int TOTAL = NPEN * NBF;
+  constexpr int NP = NG * NPEN;
+  constexpr int TOTAL = NP * NBF;
   constexpr int M = N / (P * R);
   constexpr int MAXB = (TOTAL + kCT - 1) / kCT;
   C2<T> y[MAXB][R];
@@ -240,8 +274,8 @@ __device__ __forceinline__ void cstage(C2<T> *buf, const C2<T> *tw) {
     const int i = threadIdx.x + c * kCT;
     dst[c] = -1;
     if (TOTAL % kCT == 0 || i < TOTAL) {
-      const int pen = i % NPEN, bf = i / NPEN;
-      const int base = pen * PS;
+      const int pa = i % NP, bf = i / NP;
+      const int base = NG == 1 ? pa * PS : (pa / NPEN) * GS + (pa % NPEN) * PS;
       C2<T> x[R];
 #pragma unroll
       for (int t = 0; t < R; ++t) x[t] = buf[base + (bf + t * NBF) * ES];
@@ -271,13 +305,24 @@ __device__ __forceinline__ void cstage(C2<T> *buf, const C2<T> *tw) {
   __syncthreads();
 }
 
-template <typename T, int N, int S, int P, int NPEN, int ES, int PS, int SGN>
+template <typename T, int N, int S, int P, int NPEN, int ES, int PS, int SGN, int NG = 1,
+          int GS = 0>
 __device__ __forceinline__ void cfft(C2<T> *buf, const C2<T> *tw) {
   if constexpr (S < CPlan<N>::ns) {
     constexpr int R = CPlan<N>::r[S];
-    cstage<T, N, R, P, NPEN, ES, PS, SGN>(buf, tw);
-    cfft<T, N, S + 1, P * R, NPEN, ES, PS, SGN>(buf, tw);
+    cstage<T, N, R, P, NPEN, ES, PS, SGN, NG, GS>(buf, tw);
+    cfft<T, N, S + 1, P * R, NPEN, ES, PS, SGN, NG, GS>(buf, tw);
   }
+}
+
+// Planes (or slabs) of one band that a batched pass keeps in LDS together:
+// about 34 KB of LDS per workgroup, so that four workgroups of kCT threads per
+// CU hold as much box data in flight as the 64^3 passes do.
+template <typename T, int N>
+constexpr int cplanes_per_item() {
+  return 34000 / (N * (N + 1) * (int)sizeof(C2<T>)) > 1
+             ? 34000 / (N * (N + 1) * (int)sizeof(C2<T>))
+             : 1;
 }
 
 

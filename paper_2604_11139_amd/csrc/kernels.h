@@ -253,6 +253,8 @@ void launch_mix(const abi_system_s *s, const double *vin, const double *vout, do
 template <typename T> void batch_step(const BatchLaunch &L, int j, hipStream_t st);
 // True if batched systems on a cubic box of this edge get specialised passes.
 bool batch_edge_specialised(int n);
+// planes (slabs) of one band per work item of the specialised batched passes
+int batch_item_planes(int n, bool fp32);
 // Sets the dynamic LDS limits of the batched kernels (call outside graph capture).
 template <typename T> void batch_prepare(const BatchLaunch &L);
 
