@@ -370,11 +370,11 @@ abi_status abi_zheev(int64_t m, void *A, int64_t lda, double *w, void *Z, int64_
  * The paper applies the operator to a whole block of bands per call instead
  * of band by band (section "Batch processing"); a batch extends this across
  * independent systems (cells, k-points) of uneven plane-wave counts and FFT
- * boxes.  One filter step of every system of the batch is four launches
- * (projection + D, the three FFT passes with the expansion and the recurrence
- * fused into the last), each a grid-stride loop over the work items of all
- * systems; the 4 x degree launches of a filter are captured into a HIP graph
- * on first use and replayed.  Limits: at most 1024 systems, at most 8 atoms
+ * boxes.  One filter step of every system of the batch is five launches per
+ * group of passes (projection + D and the expansion P C' in tiles of 32 bands,
+ * the three FFT passes with the recurrence fused into the last), each a
+ * grid-stride loop over the work items of all systems; the launches of a
+ * filter are captured into a HIP graph on first use and replayed.  Limits: at most 1024 systems, at most 8 atoms
  * (32 projectors) per system, FFT edges up to 64, S = I (no Q). */
 typedef struct abi_batch_s *abi_batch;
 
@@ -404,10 +404,10 @@ abi_status abi_cheb_filter_batch(abi_batch batch, const void *const *X, void *co
 
 /* Times the launch variants of the batched filter on the caller's arguments
  * (same as abi_cheb_filter_batch; Y is overwritten) and keeps the fastest:
- * FFT pass threads per workgroup (256 / 512 where the plans allow), projection
- * threads (128 / 256) and the radix order of the FFT plans (ascending /
- * descending).  choice (host, 4 entries, may be NULL) receives {fft threads,
- * projection threads, descending radix order (0/1), timed variants}.
+ * FFT pass threads per workgroup (256 / 512 where the plans allow) and the
+ * radix order of the FFT plans (ascending / descending).  choice (host, 4
+ * entries, may be NULL) receives {fft threads, projection threads (256: the
+ * tiled projector products), descending radix order (0/1), timed variants}.
  * Synchronises the stream. */
 abi_status abi_batch_autotune(abi_batch batch, const void *const *X, void *const *Y,
                               const int64_t *nband, const int64_t *ld, int32_t dtype,

@@ -5,15 +5,15 @@
 // processing"); here the batch spans systems as well.  One filter step of
 // every system is four launches, each a flat, grid-stride ("persistent") loop
 // over the work items of all systems:
-//   K1 proj   (system, band):     C = P^H Y_k (all projectors of the band),
-//                                 C' = alpha D C per atom;
-//   K2 pass A (system, band, i3): sphere plane -> inverse xy FFT -> box;
-//   K3 pass B (system, band, i2): z FFT, * V, z FFT;
-//   K4 pass C (system, band, i3): forward xy FFT -> gather, kinetic term,
-//                                 nonlocal expansion P C' of the plane's
-//                                 sphere points, three-term recurrence.
-// The nonlocal products are tiny here (4-32 projectors), so they are folded
-// into these memory-bound passes instead of MFMA tiles.  Per-system tables,
+//   K1 proj   (system, band tile, chunk):   partial sums of C = P^H Y_k;
+//   K1r       (system, band tile):          C' = alpha D C per atom;
+//   K1b expand (system, plane-wave tile, band tile): E = P C';
+//   K2 pass A (system, band, i3 group):     sphere planes -> inverse xy FFT -> box;
+//   K3 pass B (system, band, i2 group):     z FFT, * V, z FFT;
+//   K4 pass C (system, band, i3 group):     forward xy FFT -> gather, kinetic term,
+//                                           + E, three-term recurrence.
+// The nonlocal products are small here (4-32 projectors): plain FMA kernels
+// tiled over bands, so that P is read once per tile of 32 bands.  Per-system tables,
 // per-step pointers and coefficients are read from device descriptors, so the
 // 4 x degree launches are captured once into a HIP graph and replayed.
 #include <algorithm>
@@ -48,64 +48,165 @@ __device__ __forceinline__ C2<T> wave_sum(C2<T> v) {
   return v;
 }
 
-// K1: C = P^H Y_k for one band, then C' = alpha D C (per atom 4 x 4).
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void bproj_kernel(const BatchSys *__restrict__ sys,
-                                                   const BatchStep *__restrict__ step,
-                                                   const int64_t *__restrict__ off, int nsys) {
-  __shared__ C2<T> part[NT / 64][kBatchMaxProj];
-  __shared__ double2 csum[kBatchMaxProj];
+// K1: partial sums of C = P^H Y_k over one chunk of kBatchKC plane waves for a
+// tile of kBatchBT bands of one system.  The chunk streams through LDS in
+// pieces of KC, so each element of P is read once per band tile instead of
+// once per band; a thread holds 2 projectors x 2 bands, sums a piece in the
+// block's precision and adds the piece sums in FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void bproj_tile_kernel(const BatchSys *__restrict__ sys,
+                                                         const BatchStep *__restrict__ step,
+                                                         const int64_t *__restrict__ off,
+                                                         int nsys) {
+  constexpr int KC = sizeof(T) == 4 ? 64 : 32;
+  constexpr int NJ = kBatchMaxProj, NB = kBatchBT;
+  __shared__ C2<T> ps[KC][NJ + 1];
+  __shared__ C2<T> ys[KC][NB + 1];
+  const int t = threadIdx.x;
+  const int j0 = t & 15, bq = t >> 4;  // projectors j0, j0 + 16; bands bq, bq + 16
   const int64_t total = off[nsys];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int s = find_sys(off, nsys, item);
     const BatchSys &d = sys[s];
     const BatchStep &st = step[s];
-    const int64_t b = item - off[s];
-    const int np = d.nproj;
     const int64_t npw = d.npw;
-    const C2<T> *y = reinterpret_cast<const C2<T> *>(st.yk) + b * st.ldk;
+    const int64_t nch = (npw + kBatchKC - 1) / kBatchKC;
+    const int64_t loc = item - off[s];
+    const int64_t bt = loc / nch, ch = loc - bt * nch;
+    const int64_t b0 = bt * NB;
+    const int nb = d.nband - b0 < NB ? (int)(d.nband - b0) : NB;
+    const int np = d.nproj;
     const C2<T> *P = reinterpret_cast<const C2<T> *>(d.P);
-    C2<T> acc[kBatchMaxProj];
+    const C2<T> *y = reinterpret_cast<const C2<T> *>(st.yk) + b0 * st.ldk;
+    const int64_t kend = (ch + 1) * kBatchKC < npw ? (ch + 1) * kBatchKC : npw;
+    double2 tot[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
+    for (int64_t k0 = ch * kBatchKC; k0 < kend; k0 += KC) {
+      for (int e = t; e < KC * NJ; e += 256) {
+        const int k = e % KC, j = e / KC;
+        ps[k][j] = (j < np && k0 + k < kend) ? P[k0 + k + (int64_t)j * npw] : C2<T>{0, 0};
+      }
+      for (int e = t; e < KC * NB; e += 256) {
+        const int k = e % KC, b = e / KC;
+        ys[k][b] = (b < nb && k0 + k < kend) ? y[(int64_t)b * st.ldk + k0 + k] : C2<T>{0, 0};
+      }
+      __syncthreads();
+      C2<T> acc[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
+#pragma unroll 8
+      for (int k = 0; k < KC; ++k) {
+        const C2<T> p0 = ps[k][j0], p1 = ps[k][j0 + 16];
+        const C2<T> y0 = ys[k][bq], y1 = ys[k][bq + 16];
+        // conj(p) y
+        acc[0][0].x += p0.x * y0.x + p0.y * y0.y;
+        acc[0][0].y += p0.x * y0.y - p0.y * y0.x;
+        acc[0][1].x += p0.x * y1.x + p0.y * y1.y;
+        acc[0][1].y += p0.x * y1.y - p0.y * y1.x;
+        acc[1][0].x += p1.x * y0.x + p1.y * y0.y;
+        acc[1][0].y += p1.x * y0.y - p1.y * y0.x;
+        acc[1][1].x += p1.x * y1.x + p1.y * y1.y;
+        acc[1][1].y += p1.x * y1.y - p1.y * y1.x;
+      }
 #pragma unroll
-    for (int j = 0; j < kBatchMaxProj; ++j) acc[j] = C2<T>{0, 0};
-    for (int64_t g = threadIdx.x; g < npw; g += NT) {
-      const C2<T> x = y[g];
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int j = 0; j < kBatchMaxProj; ++j) {
-        if (j < np) {
-          const C2<T> p = P[g + (int64_t)j * npw];
-          // conj(p) x
-          acc[j].x += p.x * x.x + p.y * x.y;
-          acc[j].y += p.x * x.y - p.y * x.x;
+        for (int v = 0; v < 2; ++v) {
+          tot[u][v].x += (double)acc[u][v].x;
+          tot[u][v].y += (double)acc[u][v].y;
         }
-      }
+      __syncthreads();
     }
+    double2 *part = d.Cpart + (bt * nch + ch) * (NJ * NB);
 #pragma unroll
-    for (int j = 0; j < kBatchMaxProj; ++j) {
-      if (j < np) {
-        const C2<T> v = wave_sum<T>(acc[j]);
-        if (lane == 0) part[wave][j] = v;
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) part[(j0 + 16 * u) * NB + bq + 16 * v] = tot[u][v];
+  }
+}
+
+// K1r: C' = alpha D C for a tile of kBatchBT bands: the chunk sums added in a
+// fixed order (FP64), then the per-atom 4 x 4 D.
+template <typename T>
+__global__ __launch_bounds__(256) void bproj_reduce_kernel(const BatchSys *__restrict__ sys,
+                                                           const BatchStep *__restrict__ step,
+                                                           const int64_t *__restrict__ off,
+                                                           int nsys) {
+  constexpr int NJ = kBatchMaxProj, NB = kBatchBT;
+  __shared__ double2 cs[NJ][NB];
+  const int t = threadIdx.x;
+  const int64_t total = off[nsys];
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const int s = find_sys(off, nsys, item);
+    const BatchSys &d = sys[s];
+    const BatchStep &st = step[s];
+    const int64_t bt = item - off[s];
+    const int64_t b0 = bt * NB;
+    const int nb = d.nband - b0 < NB ? (int)(d.nband - b0) : NB;
+    const int np = d.nproj;
+    const int64_t nch = (d.npw + kBatchKC - 1) / kBatchKC;
+    const double2 *part = d.Cpart + bt * nch * (NJ * NB);
+    for (int e = t; e < NJ * NB; e += 256) {
+      double2 v{0, 0};
+      for (int64_t c = 0; c < nch; ++c) {
+        const double2 p = part[c * (NJ * NB) + e];
+        v.x += p.x;
+        v.y += p.y;
       }
+      cs[e / NB][e % NB] = v;
     }
     __syncthreads();
-    if (threadIdx.x < np) {
-      double sx = 0.0, sy = 0.0;
-      for (int w = 0; w < NT / 64; ++w) {
-        sx += (double)part[w][threadIdx.x].x;
-        sy += (double)part[w][threadIdx.x].y;
-      }
-      csum[threadIdx.x] = double2{sx, sy};
-    }
-    __syncthreads();
-    if (threadIdx.x < np) {
-      const int j = threadIdx.x, R = j >> 2, i = j & 3;
+    C2<T> *cp = reinterpret_cast<C2<T> *>(d.Cp);
+    for (int e = t; e < np * nb; e += 256) {
+      const int j = e % np, b = e / np, R = j >> 2, i = j & 3;
       const double2 *Dm = d.D + 16 * R + 4 * i;
       double2 v{0, 0};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v = cadd(v, cmul(Dm[q], csum[4 * R + q]));
-      C2<T> *cp = reinterpret_cast<C2<T> *>(d.Cp) + b * np;
-      cp[j] = C2<T>{(T)(st.alpha * v.x), (T)(st.alpha * v.y)};
+      for (int q = 0; q < 4; ++q) v = cadd(v, cmul(Dm[q], cs[4 * R + q][b]));
+      cp[(b0 + b) * np + j] = C2<T>{(T)(st.alpha * v.x), (T)(st.alpha * v.y)};
+    }
+    __syncthreads();
+  }
+}
+
+// K1b: E = P C' for kBatchEP plane waves x kBatchBT bands of one system (E:
+// npw x nband, ld npw; pass C adds it).  A thread holds the P row of its plane
+// wave in registers and applies it to every band of the tile.
+template <typename T>
+__global__ __launch_bounds__(kBatchEP) void bexpand_kernel(const BatchSys *__restrict__ sys,
+                                                           const int64_t *__restrict__ off,
+                                                           int nsys) {
+  constexpr int NJ = kBatchMaxProj, NB = kBatchBT;
+  __shared__ C2<T> cs[NJ][NB];
+  const int t = threadIdx.x;
+  const int64_t total = off[nsys];
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const int s = find_sys(off, nsys, item);
+    const BatchSys &d = sys[s];
+    const int64_t nbt = (d.nband + NB - 1) / NB;
+    const int64_t loc = item - off[s];
+    const int64_t pt = loc / nbt, bt = loc - pt * nbt;  // band tiles fastest
+    const int64_t b0 = bt * NB;
+    const int nb = d.nband - b0 < NB ? (int)(d.nband - b0) : NB;
+    const int np = d.nproj;
+    const int64_t npw = d.npw;
+    const C2<T> *cp = reinterpret_cast<const C2<T> *>(d.Cp);
+    for (int e = t; e < np * nb; e += kBatchEP) {
+      const int j = e % np, b = e / np;
+      cs[j][b] = cp[(b0 + b) * np + j];
+    }
+    __syncthreads();
+    const int64_t g = pt * kBatchEP + t;
+    if (g < npw) {
+      const C2<T> *P = reinterpret_cast<const C2<T> *>(d.P);
+      C2<T> pr[NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) pr[j] = j < np ? P[g + (int64_t)j * npw] : C2<T>{0, 0};
+      C2<T> *E = reinterpret_cast<C2<T> *>(d.E) + b0 * npw + g;
+      for (int b = 0; b < nb; ++b) {
+        C2<T> v{0, 0};
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+          if (j < np) v = cadd(v, cmul(pr[j], cs[j][b]));
+        E[(int64_t)b * npw] = v;
+      }
     }
     __syncthreads();
   }
@@ -210,11 +311,8 @@ __global__ __launch_bounds__(512) void bpass_c_kernel(const BatchSys *__restrict
     const int np = d.nproj;
     C2<T> *tw1 = buf + n2 * L1;
     C2<T> *tw2 = tw1 + n1;
-    C2<T> *cp = tw2 + n2;
     load_twiddles<T>(tw1, d.tw, n1);
     load_twiddles<T>(tw2, d.tw + kMaxN, n2);
-    if (threadIdx.x < np)
-      cp[threadIdx.x] = reinterpret_cast<const C2<T> *>(d.Cp)[b * np + threadIdx.x];
     const int offp = i3 * nxy;
     const C2<T> *src = reinterpret_cast<const C2<T> *>(d.box) + b * (int64_t)nxy * n3 + offp;
     for (int i = threadIdx.x; i < nxy; i += blockDim.x) buf[i + i / n1] = src[i];
@@ -226,7 +324,7 @@ __global__ __launch_bounds__(512) void bpass_c_kernel(const BatchSys *__restrict
     const C2<T> *yp =
         st.yprev ? reinterpret_cast<const C2<T> *>(st.yprev) + b * st.ldp : nullptr;
     C2<T> *out = reinterpret_cast<C2<T> *>(st.out) + b * st.ldo;
-    const C2<T> *P = reinterpret_cast<const C2<T> *>(d.P);
+    const C2<T> *E = np > 0 ? reinterpret_cast<const C2<T> *>(d.E) + b * d.npw : nullptr;
     const T alpha = (T)st.alpha, cshift = (T)st.cshift, beta = (T)st.beta;
     const T scale = (T)(1.0 / ((double)nxy * n3));
     for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x) {
@@ -235,8 +333,7 @@ __global__ __launch_bounds__(512) void bpass_c_kernel(const BatchSys *__restrict
       const C2<T> x = yk[idx];
       const T kd = (T)d.kin[idx] - cshift;
       const C2<T> h = cadd(lc, cscale(x, kd));
-      C2<T> nl{0, 0};
-      for (int j = 0; j < np; ++j) nl = cadd(nl, cmul(P[idx + (int64_t)j * d.npw], cp[j]));
+      const C2<T> nl = E ? E[idx] : C2<T>{0, 0};
       C2<T> o{alpha * h.x + nl.x, alpha * h.y + nl.y};
       if (yp) {
         const C2<T> p = yp[idx];
@@ -359,7 +456,6 @@ __global__ __launch_bounds__(kCT) void bcpass_c_kernel(const BatchSys *__restric
   constexpr int NPL = cplanes_per_item<T, N>(), G = (N + NPL - 1) / NPL;
   __shared__ C2<T> buf[NPL * PL];
   __shared__ C2<T> tw[N];
-  __shared__ C2<T> cp[kBatchMaxProj];
   const int64_t total = goff[gns];
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     int64_t b;
@@ -370,8 +466,6 @@ __global__ __launch_bounds__(kCT) void bcpass_c_kernel(const BatchSys *__restric
     const BatchStep &st = step[s];
     const int np = d.nproj;
     for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(d.tw[i]);
-    if (threadIdx.x < np)
-      cp[threadIdx.x] = reinterpret_cast<const C2<T> *>(d.Cp)[b * np + threadIdx.x];
     const int off = i30 * NXY;
     const C2<T> *src = reinterpret_cast<const C2<T> *>(d.box) + b * (int64_t)NXY * N + off;
     for (int i = threadIdx.x; i < np3 * NXY; i += kCT) buf[i + i / N] = src[i];
@@ -383,7 +477,7 @@ __global__ __launch_bounds__(kCT) void bcpass_c_kernel(const BatchSys *__restric
     const C2<T> *yp =
         st.yprev ? reinterpret_cast<const C2<T> *>(st.yprev) + b * st.ldp : nullptr;
     C2<T> *out = reinterpret_cast<C2<T> *>(st.out) + b * st.ldo;
-    const C2<T> *P = reinterpret_cast<const C2<T> *>(d.P);
+    const C2<T> *E = np > 0 ? reinterpret_cast<const C2<T> *>(d.E) + b * d.npw : nullptr;
     const T alpha = (T)st.alpha, cshift = (T)st.cshift, beta = (T)st.beta;
     const T scale = (T)(1.0 / ((double)NXY * N));
     for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
@@ -392,8 +486,7 @@ __global__ __launch_bounds__(kCT) void bcpass_c_kernel(const BatchSys *__restric
       const C2<T> x = yk[idx];
       const T kd = (T)d.kin[idx] - cshift;
       const C2<T> h = cadd(lc, cscale(x, kd));
-      C2<T> nl{0, 0};
-      for (int j = 0; j < np; ++j) nl = cadd(nl, cmul(P[idx + (int64_t)j * d.npw], cp[j]));
+      const C2<T> nl = E ? E[idx] : C2<T>{0, 0};
       C2<T> o{alpha * h.x + nl.x, alpha * h.y + nl.y};
       if (yp) {
         const C2<T> p = yp[idx];
@@ -420,16 +513,20 @@ void batch_step(const BatchLaunch &L, int j, hipStream_t st) {
   const int64_t *offP = L.d_off;
   const int64_t *offA = L.d_off + (L.nsys + 1);
   const int64_t *offB = L.d_off + 2 * (L.nsys + 1);
+  const int64_t *offE = L.d_off + 3 * (L.nsys + 1);
+  const int64_t *offR = L.d_off + 4 * (L.nsys + 1);
   auto grid = [&](int64_t items) {
     return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(items, L.max_wgs)));
   };
   if (L.any_proj) {
-    if (L.proj_threads == 128)
-      hipLaunchKernelGGL((bproj_kernel<T, 128>), grid(L.items_p), dim3(128), 0, st, L.d_sys, stp,
-                         offP, L.nsys);
-    else
-      hipLaunchKernelGGL((bproj_kernel<T, 256>), grid(L.items_p), dim3(256), 0, st, L.d_sys, stp,
-                         offP, L.nsys);
+    hipLaunchKernelGGL(bproj_tile_kernel<T>, grid(L.items_p), dim3(256), 0, st, L.d_sys, stp,
+                       offP, L.nsys);
+    CHEBFI_HIP(hipGetLastError());
+    hipLaunchKernelGGL(bproj_reduce_kernel<T>, grid(L.items_r), dim3(256), 0, st, L.d_sys, stp,
+                       offR, L.nsys);
+    CHEBFI_HIP(hipGetLastError());
+    hipLaunchKernelGGL(bexpand_kernel<T>, grid(L.items_e), dim3(kBatchEP), 0, st, L.d_sys, offE,
+                       L.nsys);
     CHEBFI_HIP(hipGetLastError());
   }
   const size_t e = sizeof(C2<T>);

@@ -310,8 +310,8 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
   }
   const size_t esz = elem_bytes(dtype);
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-  // workspace: boxes, C', two iterate slots per system
-  std::vector<size_t> o_box(nsys), o_cp(nsys), o_slot(nsys);
+  // workspace: boxes, C', E = P C', two iterate slots per system
+  std::vector<size_t> o_box(nsys), o_cp(nsys), o_e(nsys), o_part(nsys), o_slot(nsys);
   size_t tot = 0;
   int min_threads = 64;
   size_t lds_a = 0, lds_b = 0;
@@ -323,6 +323,12 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
     tot += al(esz * (size_t)nbox * nband[i]);
     o_cp[i] = tot;
     tot += al(esz * (size_t)std::max(s->nproj, 1) * nband[i]);
+    o_e[i] = tot;
+    if (s->nproj > 0) tot += al(esz * (size_t)s->npw * nband[i]);
+    o_part[i] = tot;
+    if (s->nproj > 0)
+      tot += al(sizeof(double2) * (size_t)((nband[i] + kBatchBT - 1) / kBatchBT) *
+                (size_t)((s->npw + kBatchKC - 1) / kBatchKC) * kBatchMaxProj * kBatchBT);
     o_slot[i] = tot;
     if (degree >= 2) tot += 2 * al(esz * (size_t)s->npw * nband[i]);
     min_threads = std::max({min_threads, fft_stage_threads(s->plan.d[0], s->n2),
@@ -337,8 +343,9 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
   if (B->fft_threads < min_threads) B->fft_threads = min_threads <= 256 ? 256 : 512;
   char *ws = (char *)B->work.get(tot);
   // per-system descriptors and item offsets
-  B->hoff.assign(3 * (size_t)(nsys + 1), 0);
+  B->hoff.assign(5 * (size_t)(nsys + 1), 0);
   int64_t *offP = B->hoff.data(), *offA = offP + (nsys + 1), *offB = offA + (nsys + 1);
+  int64_t *offE = offB + (nsys + 1), *offR = offE + (nsys + 1);
   for (int i = 0; i < nsys; ++i) {
     const abi_system_s *s = B->sys[i];
     BatchSys &d = B->hsys[i];
@@ -352,9 +359,17 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
     d.tw = reinterpret_cast<const double2 *>(s->d_tw);
     d.P = fp32 ? (const void *)s->d_Pf : (const void *)s->d_P;
     d.D = reinterpret_cast<const double2 *>(s->d_D);
+    d.nband = nband[i];
     d.box = ws + o_box[i];
     d.Cp = ws + o_cp[i];
-    offP[i + 1] = offP[i] + nband[i];
+    d.E = ws + o_e[i];
+    d.Cpart = (double2 *)(ws + o_part[i]);
+    // projector products in tiles of kBatchBT bands (x kBatchKC-wave chunks for
+    // the projection, x kBatchEP plane waves for the expansion)
+    const int64_t nbt = s->nproj > 0 ? (nband[i] + kBatchBT - 1) / kBatchBT : 0;
+    offP[i + 1] = offP[i] + nbt * ((s->npw + kBatchKC - 1) / kBatchKC);
+    offR[i + 1] = offR[i] + nbt;
+    offE[i + 1] = offE[i] + nbt * ((s->npw + kBatchEP - 1) / kBatchEP);
     // systems on cubic boxes with specialised passes go to their edge group and
     // contribute no items to the runtime-size passes
     const bool grouped = s->n1 == s->n2 && s->n1 == s->n3 && batch_edge_specialised(s->n1) &&
@@ -466,6 +481,8 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
   L.d_steps = (const BatchStep *)dsteps;
   L.d_off = (const int64_t *)doff;
   L.items_p = offP[nsys];
+  L.items_e = offE[nsys];
+  L.items_r = offR[nsys];
   L.items_a = offA[nsys];
   L.items_b = offB[nsys];
   L.max_wgs = 2048;
@@ -482,7 +499,7 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
   L.proj_threads = B->proj_threads;
   L.lds_a = lds_a;
   L.lds_b = lds_b;
-  L.lds_c = lds_a + kBatchMaxProj;
+  L.lds_c = lds_a;
   L.any_proj = any_proj;
   std::vector<int64_t> nb(nband, nband + nsys);
   if (fp32)
@@ -1816,10 +1833,11 @@ abi_status abi_batch_autotune(abi_batch B, const void *const *X, void *const *Y,
     float best = -1.f;
     int bf = B->fft_threads, bp = B->proj_threads, br = B->radix_desc, tried = 0;
     try {
+      // (the projector products are tiled kernels of a fixed 256 threads)
       for (int rd = 0; rd < 2; ++rd)
         for (int ft : {256, 512}) {
           if (ft < B->fft_min_threads) continue;
-          for (int pt : {128, 256}) {
+          for (int pt : {256}) {
             B->fft_threads = ft;
             B->proj_threads = pt;
             B->radix_desc = rd;

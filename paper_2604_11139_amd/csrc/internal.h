@@ -151,6 +151,9 @@ void build_projectors(const abi_system_desc *d, const Sphere &s, std::vector<dou
 
 // ---- batched filter over many systems ---------------------------------------
 constexpr int kBatchMaxProj = 32;  // projectors per system in the batched path (8 atoms)
+constexpr int kBatchBT = 32;       // bands per tile of the batched projector products
+constexpr int kBatchEP = 256;      // plane waves per tile of the batched expansion
+constexpr int kBatchKC = 256;      // plane waves per partial sum of the batched projection
 constexpr int kBatchMaxSys = 1024;
 
 // Per-system device descriptor of the batched passes (plain data).
@@ -165,8 +168,11 @@ struct BatchSys {
   const double2 *tw = nullptr;
   const void *P = nullptr;    // npw x nproj complex float or double, column-major
   const double2 *D = nullptr;
+  int64_t nband = 0;
   void *box = nullptr;        // nband boxes
   void *Cp = nullptr;         // nproj x nband
+  void *E = nullptr;          // npw x nband (ld npw): P C' of the current step
+  double2 *Cpart = nullptr;   // per band tile, per plane-wave chunk: P^H Y_k partial sums
 };
 
 // Per (filter step, system): Out = alpha (H - cshift) Y_k - beta Y_prev.
@@ -195,8 +201,10 @@ struct BatchLaunch {
   int nsys = 0;
   const BatchSys *d_sys = nullptr;
   const BatchStep *d_steps = nullptr;  // degree x nsys
-  const int64_t *d_off = nullptr;      // prefix offsets: bands, bands*n3, bands*n2
-  int64_t items_p = 0, items_a = 0, items_b = 0;
+  // prefix offsets: band tiles x plane-wave chunks, bands*n3, bands*n2,
+  // plane-wave tiles x band tiles, band tiles
+  const int64_t *d_off = nullptr;
+  int64_t items_p = 0, items_a = 0, items_b = 0, items_e = 0, items_r = 0;
   int max_wgs = 2048;
   int fft_threads = 256, proj_threads = 256;
   size_t lds_a = 0, lds_b = 0, lds_c = 0;  // dynamic LDS of the passes, in elements

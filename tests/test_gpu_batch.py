@@ -125,7 +125,7 @@ def test_autotune_keeps_results():
         g.use_graph(False)
         ref = [Y.clone() for Y in g.cheb_filter(Xd, DEGREE, bounds)]
         choice = g.autotune(Xd, DEGREE, bounds)
-        assert choice["fft_threads"] in (256, 512) and choice["proj_threads"] in (128, 256)
+        assert choice["fft_threads"] in (256, 512) and choice["proj_threads"] == 256
         assert choice["variants_timed"] >= 2
         Yd = g.cheb_filter(Xd, DEGREE, bounds)
         torch.cuda.synchronize()
