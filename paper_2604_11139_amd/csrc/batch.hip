@@ -122,35 +122,36 @@ __global__ __launch_bounds__(256) void bproj_tile_kernel(const BatchSys *__restr
   }
 }
 
-// K1r: C' = alpha D C for a tile of kBatchBT bands: the chunk sums added in a
+// K1r: C' = alpha D C for kBatchBR bands of a tile: the chunk sums added in a
 // fixed order (FP64), then the per-atom 4 x 4 D.
 template <typename T>
 __global__ __launch_bounds__(256) void bproj_reduce_kernel(const BatchSys *__restrict__ sys,
                                                            const BatchStep *__restrict__ step,
                                                            const int64_t *__restrict__ off,
                                                            int nsys) {
-  constexpr int NJ = kBatchMaxProj, NB = kBatchBT;
-  __shared__ double2 cs[NJ][NB];
+  constexpr int NJ = kBatchMaxProj, NB = kBatchBT, NR = kBatchBR;
+  __shared__ double2 cs[NJ][NR];
   const int t = threadIdx.x;
   const int64_t total = off[nsys];
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int s = find_sys(off, nsys, item);
     const BatchSys &d = sys[s];
     const BatchStep &st = step[s];
-    const int64_t bt = item - off[s];
-    const int64_t b0 = bt * NB;
-    const int nb = d.nband - b0 < NB ? (int)(d.nband - b0) : NB;
+    const int64_t b0 = (item - off[s]) * NR;  // first band of the item
+    const int64_t bt = b0 / NB, bl = b0 - bt * NB;
+    const int nb = d.nband - b0 < NR ? (int)(d.nband - b0) : NR;
     const int np = d.nproj;
     const int64_t nch = (d.npw + kBatchKC - 1) / kBatchKC;
     const double2 *part = d.Cpart + bt * nch * (NJ * NB);
-    for (int e = t; e < NJ * NB; e += 256) {
+    for (int e = t; e < NJ * NR; e += 256) {
+      const int j = e / NR, b = e % NR;
       double2 v{0, 0};
       for (int64_t c = 0; c < nch; ++c) {
-        const double2 p = part[c * (NJ * NB) + e];
+        const double2 p = part[c * (NJ * NB) + j * NB + bl + b];
         v.x += p.x;
         v.y += p.y;
       }
-      cs[e / NB][e % NB] = v;
+      cs[j][b] = v;
     }
     __syncthreads();
     C2<T> *cp = reinterpret_cast<C2<T> *>(d.Cp);

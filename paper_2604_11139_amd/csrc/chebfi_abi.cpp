@@ -368,7 +368,7 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
     // the projection, x kBatchEP plane waves for the expansion)
     const int64_t nbt = s->nproj > 0 ? (nband[i] + kBatchBT - 1) / kBatchBT : 0;
     offP[i + 1] = offP[i] + nbt * ((s->npw + kBatchKC - 1) / kBatchKC);
-    offR[i + 1] = offR[i] + nbt;
+    offR[i + 1] = offR[i] + (s->nproj > 0 ? (nband[i] + kBatchBR - 1) / kBatchBR : 0);
     offE[i + 1] = offE[i] + nbt * ((s->npw + kBatchEP - 1) / kBatchEP);
     // systems on cubic boxes with specialised passes go to their edge group and
     // contribute no items to the runtime-size passes

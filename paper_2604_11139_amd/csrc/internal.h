@@ -154,6 +154,7 @@ constexpr int kBatchMaxProj = 32;  // projectors per system in the batched path 
 constexpr int kBatchBT = 32;       // bands per tile of the batched projector products
 constexpr int kBatchEP = 256;      // plane waves per tile of the batched expansion
 constexpr int kBatchKC = 256;      // plane waves per partial sum of the batched projection
+constexpr int kBatchBR = 8;        // bands per item of the partial-sum reduction
 constexpr int kBatchMaxSys = 1024;
 
 // Per-system device descriptor of the batched passes (plain data).
