@@ -170,6 +170,18 @@ abi_status abi_cheb_filter(abi_system sys, const void *X, void *Y, int64_t nband
                            int32_t dtype, int32_t degree, double a, double b, double a0,
                            void *stream);
 
+/* abi_cheb_filter with H X supplied by the caller (HX: device, the dtype and
+ * leading dimension of X, not overlapping X or Y; not modified): the first
+ * step is then Y_1 = (s_1/e)(HX - c X), so the filter applies H degree - 1
+ * times.  This is the reuse of the Rayleigh-quotient H X (or of the H Psi of
+ * the last Rayleigh-Ritz step) behind the paper's count of k + 1 H
+ * applications per cycle (section "Arithmetic intensity").  Equal to
+ * abi_cheb_filter up to rounding when HX is H X.  S = I only (ABI_ERR_STATE
+ * on a handle with an overlap). */
+abi_status abi_cheb_filter_hx(abi_system sys, const void *X, const void *HX, void *Y,
+                              int64_t nband, int64_t ld, int32_t dtype, int32_t degree, double a,
+                              double b, double a0, void *stream);
+
 /* Rayleigh-Ritz on the filtered block (Algorithms "S-ortho" and "RR"):
  * G = Y^H S Y = U^H U (Cholesky, FP64), H_s = Y^H (H Y),
  * U^-H H_s U^-1 = Z Lambda Z^H, Psi = Y U^-1 Z (S-orthonormal),
@@ -213,7 +225,9 @@ abi_status abi_rayleigh_ritz(abi_system sys, void *Y, void *HPsi, int64_t nband,
  * lowest nconv Ritz pairs are all <= tol or max_cycles cycles have run.  From
  * the second cycle on, the bounds take the Rayleigh quotients of the block from
  * the last Ritz values (they are equal for Ritz vectors) and keep the first
- * cycle's Lanczos upper bound (H is fixed), so they apply no H.
+ * cycle's Lanczos upper bound (H is fixed), so they apply no H; and the filter
+ * starts from the H Psi the last Rayleigh-Ritz step formed (abi_cheb_filter_hx;
+ * S = I), so a cycle applies H degree times, the Rayleigh-Ritz's included.
  * X (in: start block; out: Ritz vectors, ascending Ritz values) is npw x nband
  * (ld) of `dtype`; v0: device, npw complex128.  With dtype ABI_C64 and
  * refine_degree > 0, the mixed cycles hand over to FP64 cycles of degree

@@ -34,7 +34,8 @@ ABI_PREC_MIXED = 1
 EXPORTS = [
     "abi_gsphere_count", "abi_gsphere_build", "abi_set_system", "abi_system_info",
     "abi_get_gsphere", "abi_get_projectors", "abi_destroy", "abi_apply_H",
-    "abi_spectral_bounds", "abi_cheb_filter", "abi_rayleigh_ritz", "abi_zpotrf_upper",
+    "abi_spectral_bounds", "abi_cheb_filter", "abi_cheb_filter_hx", "abi_rayleigh_ritz",
+    "abi_zpotrf_upper",
     "abi_zheev", "abi_profile_enable", "abi_profile_read", "abi_update_potential",
     "abi_filter_backward", "abi_density", "abi_last_error", "abi_set_system_batch",
     "abi_batch_system", "abi_cheb_filter_batch", "abi_batch_autotune", "abi_batch_use_graph",
@@ -99,6 +100,8 @@ def lib():
         "abi_spectral_bounds": [vp, vp, c_int64, c_int64, c_int32, vp, c_int32, vp, vp],
         "abi_cheb_filter": [vp, vp, vp, c_int64, c_int64, c_int32, c_int32, c_double, c_double,
                             c_double, vp],
+        "abi_cheb_filter_hx": [vp, vp, vp, vp, c_int64, c_int64, c_int32, c_int32, c_double,
+                               c_double, c_double, vp],
         "abi_rayleigh_ritz": [vp, vp, vp, c_int64, c_int64, c_int32, vp, vp, vp, vp, vp],
         "abi_zpotrf_upper": [c_int64, vp, c_int64, vp],
         "abi_zheev": [c_int64, vp, c_int64, vp, vp, c_int64, vp],
@@ -334,12 +337,20 @@ class System:
         _check(lib().abi_overlap_info(self._h, ctypes.byref(h), ctypes.byref(m)))
         return bool(h.value), float(m.value)
 
-    def cheb_filter(self, X, degree, a, b, a0, out=None):
+    def cheb_filter(self, X, degree, a, b, a0, out=None, hx=None):
+        """Degree-m filter of X; hx: H X of the same shape and dtype (its first
+        step then reuses it instead of applying H)."""
         px, nb, ld, code = _block(X, self.npw)
         out = self._out_like(X, out)
         po, _, _, _ = _block(out, self.npw)
-        _check(lib().abi_cheb_filter(self._h, px, po, nb, ld, code, int(degree), float(a),
-                                     float(b), float(a0), _stream()))
+        if hx is None:
+            _check(lib().abi_cheb_filter(self._h, px, po, nb, ld, code, int(degree), float(a),
+                                         float(b), float(a0), _stream()))
+        else:
+            self._out_like(X, hx)  # same shape, dtype and layout as X
+            ph, _, _, _ = _block(hx, self.npw)
+            _check(lib().abi_cheb_filter_hx(self._h, px, ph, po, nb, ld, code, int(degree),
+                                            float(a), float(b), float(a0), _stream()))
         return out
 
     def spectral_bounds(self, X, v0, nlanczos=10):

@@ -734,18 +734,25 @@ abi_status abi_apply_H_noalloc(abi_system s, const void *X, void *HX, int64_t nb
   });
 }
 
-abi_status abi_cheb_filter(abi_system s, const void *X, void *Y, int64_t nband, int64_t ld,
-                           int32_t dtype, int32_t degree, double a, double b, double a0,
-                           void *stream) {
-  return guarded([&] {
+namespace chebfi {
+namespace {
+
+// The filter; HX (ld ld, or NULL) is H X given by the caller, which turns the
+// first step into Y_1 = (s1/e)(HX - c X).
+void cheb_filter_impl(abi_system s, const void *X, const void *HX, void *Y, int64_t nband,
+                      int64_t ld, int32_t dtype, int32_t degree, double a, double b, double a0,
+                      hipStream_t st) {
     check_block(s, X, nband, ld, dtype);
     CHEBFI_REQUIRE(Y != nullptr && Y != X, ABI_ERR_ARG, "Y must be a separate block");
+    CHEBFI_REQUIRE(HX == nullptr || (HX != Y && HX != X), ABI_ERR_ARG,
+                   "HX must not alias X or Y");
+    CHEBFI_REQUIRE(HX == nullptr || !s->has_S, ABI_ERR_STATE,
+                   "a given H X serves the filter on H only (S = I)");
     CHEBFI_REQUIRE(degree >= 1, ABI_ERR_ARG, "degree must be >= 1");
     CHEBFI_REQUIRE(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0), ABI_ERR_ARG,
                    "bounds must be finite");
     CHEBFI_REQUIRE(b > a, ABI_ERR_ARG, "need b > a");
     CHEBFI_REQUIRE(a0 <= a, ABI_ERR_ARG, "need a0 <= a");
-    hipStream_t st = S(stream);
     const int64_t npw = s->npw;
     const double e = (b - a) / 2.0, c = (b + a) / 2.0;
     const double s1 = e / (a0 - c);
@@ -786,8 +793,12 @@ abi_status abi_cheb_filter(abi_system s, const void *X, void *Y, int64_t nband, 
       return;
     }
     // Y_1 = (s1/e)(H - c) X
-    apply_core(s, X, ld, nullptr, 0, bufs[slot(1)], lds[slot(1)], nband, s1 / e, c, 0.0, st,
-               dtype);
+    if (HX)
+      launch_cheb_first(npw, nband, X, ld, HX, ld, s1 / e, c, bufs[slot(1)], lds[slot(1)], st,
+                        dtype == ABI_C64);
+    else
+      apply_core(s, X, ld, nullptr, 0, bufs[slot(1)], lds[slot(1)], nband, s1 / e, c, 0.0, st,
+                 dtype);
     double sk = s1;
     for (int j = 1; j < degree; ++j) {
       const double sk1 = 1.0 / (2.0 / s1 - sk);
@@ -799,6 +810,25 @@ abi_status abi_cheb_filter(abi_system s, const void *X, void *Y, int64_t nband, 
                  c, sk * sk1, st, dtype);
       sk = sk1;
     }
+}
+
+}  // namespace
+}  // namespace chebfi
+
+abi_status abi_cheb_filter(abi_system s, const void *X, void *Y, int64_t nband, int64_t ld,
+                           int32_t dtype, int32_t degree, double a, double b, double a0,
+                           void *stream) {
+  return guarded([&] {
+    cheb_filter_impl(s, X, nullptr, Y, nband, ld, dtype, degree, a, b, a0, S(stream));
+  });
+}
+
+abi_status abi_cheb_filter_hx(abi_system s, const void *X, const void *HX, void *Y,
+                              int64_t nband, int64_t ld, int32_t dtype, int32_t degree, double a,
+                              double b, double a0, void *stream) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(HX != nullptr, ABI_ERR_ARG, "HX is NULL");
+    cheb_filter_impl(s, X, HX, Y, nband, ld, dtype, degree, a, b, a0, S(stream));
   });
 }
 
@@ -964,9 +994,12 @@ abi_status abi_chebfi_solve(abi_system s, void *X, int64_t nband, int64_t ld, in
     // second cycle on, A holds Ritz vectors, whose Rayleigh quotients are their Ritz
     // values (the last Rayleigh-Ritz step's eval), and H is fixed, so the first
     // cycle's Lanczos upper bound still holds: the bounds need no H application.
-    bool have_ritz = false;
+    // The Rayleigh-Ritz step also returns H Psi (HB), which the next cycle's
+    // filter takes as its first step (abi_cheb_filter_hx): a cycle then applies H
+    // degree times in all, the one of the Rayleigh-Ritz included.
+    bool have_ritz = false, have_h = false;
     double b_upper = 0.0;
-    auto cycle = [&](void *A, void *Bk, int64_t l, int32_t dt, int32_t m) {
+    auto cycle = [&](void *A, void *Bk, void *HA, void *HB, int64_t l, int32_t dt, int32_t m) {
       double bd[3] = {0.0, 0.0, 0.0};
       bool reuse = false;
       if (have_ritz) {
@@ -979,13 +1012,17 @@ abi_status abi_chebfi_solve(abi_system s, void *X, int64_t nband, int64_t ld, in
         call(abi_spectral_bounds(s, A, nband, l, dt, v0, 10, bd, stream));
         b_upper = bd[1];
       }
-      call(abi_cheb_filter(s, A, Bk, nband, l, dt, m, bd[0], bd[1], bd[2], stream));
+      if (have_h)
+        call(abi_cheb_filter_hx(s, A, HA, Bk, nband, l, dt, m, bd[0], bd[1], bd[2], stream));
+      else
+        call(abi_cheb_filter(s, A, Bk, nband, l, dt, m, bd[0], bd[1], bd[2], stream));
       // the mixed cycles ahead of an FP64 refinement use the split-BF16
       // Rayleigh-Ritz (the refinement's FP64 cycles win the accuracy back)
       int32_t flags = (dt == ABI_C64 && refine_degree > 0) ? ABI_RR_LOWPREC : 0;
-      call(abi_rayleigh_ritz(s, Bk, nullptr, nband, l, dt, eval, res.data(), nullptr, &flags,
+      call(abi_rayleigh_ritz(s, Bk, HB, nband, l, dt, eval, res.data(), nullptr, &flags,
                              stream));
       have_ritz = true;
+      have_h = HB != nullptr;
       return (flags & ABI_RR_LOWPREC) != 0;
     };
     const bool refine = refine_degree > 0;
@@ -994,11 +1031,15 @@ abi_status abi_chebfi_solve(abi_system s, void *X, int64_t nband, int64_t ld, in
     const int first_budget = refine ? std::max(1, max_cycles / 2) : max_cycles;
     void *bufA = X;
     void *bufB = s->solve1.get(elem_bytes(dtype) * (size_t)ld * nband);
+    // (with S != I the filter has no H X form: H Psi is not kept)
+    void *hA = s->has_S ? nullptr : s->solve4.get(elem_bytes(dtype) * (size_t)ld * nband);
+    void *hB = s->has_S ? nullptr : s->solve5.get(elem_bytes(dtype) * (size_t)ld * nband);
     int cycles = 0, rcycles = 0, converged = 0;
     double prev = HUGE_VAL;
     while (cycles < first_budget) {
-      const bool low = cycle(bufA, bufB, ld, dtype, degree);
+      const bool low = cycle(bufA, bufB, hA, hB, ld, dtype, degree);
       std::swap(bufA, bufB);
+      std::swap(hA, hB);
       ++cycles;
       const double cur = worst();
       if (cur <= tol) {
@@ -1014,9 +1055,14 @@ abi_status abi_chebfi_solve(abi_system s, void *X, int64_t nband, int64_t ld, in
       void *A = s->solve2.get(sizeof(double2) * (size_t)npw * nband);
       void *Bk = s->solve3.get(sizeof(double2) * (size_t)npw * nband);
       launch_c64_to_c128(npw, nband, X, ld, A, npw, st);
+      // H Psi of the last mixed cycle is complex64: the first FP64 cycle applies H
+      have_h = false;
+      void *rA = s->has_S ? nullptr : s->solve4.get(sizeof(double2) * (size_t)npw * nband);
+      void *rB = s->has_S ? nullptr : s->solve5.get(sizeof(double2) * (size_t)npw * nband);
       while (cycles + rcycles < max_cycles) {
-        cycle(A, Bk, npw, ABI_C128, refine_degree);
+        cycle(A, Bk, rA, rB, npw, ABI_C128, refine_degree);
         std::swap(A, Bk);
+        std::swap(rA, rB);
         ++rcycles;
         if (worst() <= tol) {
           converged = 1;

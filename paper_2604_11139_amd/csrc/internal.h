@@ -257,7 +257,7 @@ struct abi_system_s {
   // work buffers
   chebfi::DevBuf box, cpart, cprime, blk1, blk2, blk3, small1, small2, small3, small4, small5, scal;
   chebfi::DevBuf eig1, eig2, eig3, blk4, box2, adj, adjsmall, adjc, planes, cplanes;
-  chebfi::DevBuf solve1, solve2, solve3;  // blocks of the multi-cycle driver
+  chebfi::DevBuf solve1, solve2, solve3, solve4, solve5;  // blocks of the multi-cycle driver
   chebfi::DevBuf expout;  // projector part P C' of the mixed H application
   chebfi::DevBuf tune_out;  // output block of the autotuner's timed H applications
   chebfi::DevBuf rr_planes;  // split-BF16 Rayleigh-Ritz: planes of the equilibrated block

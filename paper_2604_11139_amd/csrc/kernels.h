@@ -203,6 +203,10 @@ void launch_residual_norms_f(int64_t npw, int64_t nband, const void *Psi, int64_
 // nrm[b] = ||X[:, b]||, inv[b] = 1 / nrm[b] (0 for a zero column)
 void launch_col_norms(int64_t npw, int64_t nband, const void *X, int64_t ldx, double *nrm,
                       double *inv, hipStream_t st, bool fp32);
+// out = alpha (HX - c X): the filter's first step from a given H X
+void launch_cheb_first(int64_t npw, int64_t nband, const void *X, int64_t ldx, const void *HX,
+                       int64_t ldh, double alpha, double c, void *out, int64_t ldo, hipStream_t st,
+                       bool fp32);
 // *out = min_i (Re A[i, i])^2 (m x m complex double, one workgroup)
 void launch_diag_min_sq(int64_t m, const void *A, int64_t lda, double *out, hipStream_t st);
 // out[:, b] = sc[b] X[:, b] (complex float blocks)

@@ -284,6 +284,21 @@ __global__ void col_norms_kernel(int64_t npw, const V2 *__restrict__ X, int64_t 
   }
 }
 
+// First step of the filter from a given H X: out = alpha (HX - c X), in the
+// block's precision (the arithmetic of the recurrence pass).
+template <typename V2>
+__global__ void cheb_first_kernel(int64_t npw, int64_t nband, const V2 *__restrict__ X,
+                                  int64_t ldx, const V2 *__restrict__ HX, int64_t ldh,
+                                  double alpha, double c, V2 *__restrict__ out, int64_t ldo) {
+  typedef decltype(V2{}.x) R;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= npw * nband) return;
+  const int64_t i = idx % npw, b = idx / npw;
+  const V2 x = X[i + b * ldx], h = HX[i + b * ldh];
+  const R a = (R)alpha, cc = (R)c;
+  out[i + b * ldo] = V2{a * (h.x - cc * x.x), a * (h.y - cc * x.y)};
+}
+
 // *out = min_i (Re A[i, i])^2 over the diagonal of an m x m complex double matrix
 // (one workgroup)
 __global__ __launch_bounds__(kRedThreads) void diag_min_sq_kernel(int64_t m,
@@ -783,6 +798,21 @@ void launch_col_norms(int64_t npw, int64_t nband, const void *X, int64_t ldx, do
   else
     hipLaunchKernelGGL(col_norms_kernel<double2>, dim3((unsigned)nband), dim3(kRedThreads), 0,
                        st, npw, (const double2 *)X, ldx, nrm, inv);
+  CHEBFI_HIP(hipGetLastError());
+}
+
+void launch_cheb_first(int64_t npw, int64_t nband, const void *X, int64_t ldx, const void *HX,
+                       int64_t ldh, double alpha, double c, void *out, int64_t ldo, hipStream_t st,
+                       bool fp32) {
+  const dim3 g(nblk(npw * nband, 256));
+  if (fp32)
+    hipLaunchKernelGGL(cheb_first_kernel<float2>, g, dim3(256), 0, st, npw, nband,
+                       (const float2 *)X, ldx, (const float2 *)HX, ldh, alpha, c, (float2 *)out,
+                       ldo);
+  else
+    hipLaunchKernelGGL(cheb_first_kernel<double2>, g, dim3(256), 0, st, npw, nband,
+                       (const double2 *)X, ldx, (const double2 *)HX, ldh, alpha, c,
+                       (double2 *)out, ldo);
   CHEBFI_HIP(hipGetLastError());
 }
 

@@ -32,6 +32,10 @@ def test_library_exports_every_declared_symbol():
     for n in sorted(names):
         assert hasattr(L, n), n
     assert set(B.EXPORTS) == names
+    # every entry point has its argument types declared to ctypes (a missing
+    # declaration passes Python floats as ints or fails at the call)
+    for n in sorted(names):
+        assert getattr(L, n).argtypes is not None, n
 
 
 @pytest.mark.parametrize("tag,kw", [

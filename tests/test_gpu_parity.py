@@ -106,6 +106,36 @@ def test_cheb_filter(name, degree):
     assert col_rel_err(got, ref) <= 1e-9
 
 
+@pytest.mark.parametrize("name,degree,precision", [("tiny_k", 1, "fp64"), ("n27", 4, "fp64"),
+                                                   ("c1", 8, "fp64"), ("n27", 6, "mixed"),
+                                                   ("c1", 8, "mixed")])
+def test_cheb_filter_from_given_hx(name, degree, precision):
+    """The filter started from a given H X (the oracle's, so independent of the
+    library's H application): the oracle's filter to 1e-9 (FP64) / the mixed
+    filter budget 5e-6 m."""
+    import torch
+    H = hamiltonian(name)
+    s = system(name)
+    X = W.random_block(H.npw, s.nband, s.tag)
+    if precision == "mixed":
+        X = X.astype(np.complex64).astype(np.complex128)
+    v0 = W.random_vector(H.npw, s.tag)
+    a, b, a0 = O.filter_bounds(H, X, v0)
+    ref = O.cheb_filter(H, X, degree, a, b, a0)
+    HX = H(X)
+    prec = B.ABI_PREC_MIXED if precision == "mixed" else B.ABI_PREC_FP64
+    with B.System(s, precision=prec) as g:
+        Xd, HXd = to_dev(X), to_dev(HX)
+        if precision == "mixed":
+            Xd, HXd = Xd.to(torch.complex64), HXd.to(torch.complex64)
+        got = to_host(g.cheb_filter(Xd, degree, a, b, a0, hx=HXd)).astype(np.complex128)
+        with pytest.raises(B.ChebfiError) as e:
+            g.cheb_filter(Xd, degree, a, b, a0, out=HXd, hx=HXd)  # HX aliasing Y
+        assert e.value.code == B.ABI_ERR_ARG
+    tol = 5e-6 * degree if precision == "mixed" else 1e-9
+    assert col_rel_err(got, ref) <= tol
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_filter_overlap_is_bitwise_neutral(precision):
     """The FFT passes on a second stream beside the projection give the same bits."""
