@@ -468,6 +468,19 @@ abi_status abi_apply_H_noalloc(abi_system sys, const void *X, void *HX, int64_t 
  *   ABI_TUNE_MIXED_GEMM form of the mixed projector products: 0 split-BF16
  *                      (default), 1 FP32 MFMA, 2 split-BF16 single-buffered
  *                      64 x 64 tile (comparison forms)
+ *   ABI_TUNE_FILTER_GRAPH 0/1 (default 0): abi_cheb_filter(_hx) records its
+ *                      launches into a HIP graph on the first call with given
+ *                      blocks, degree and launch choices (that call runs them
+ *                      eagerly too), and replays the graph on the caller's stream
+ *                      for later calls with the same blocks, degree and choices,
+ *                      taking each step's coefficients from a device table
+ *                      uploaded before the replay (so new bounds need no new
+ *                      graph).  Bit for bit the eager result.  A reallocation
+ *                      of any work buffer, the second stream, the profiler or
+ *                      a no-allocation call make the filter run eagerly.  (On
+ *                      one MI355X the kernels, not the launches, bound the
+ *                      filter down to the smallest workload: replays gain
+ *                      nothing there, so it is off by default.)
  * Fails with ABI_ERR_ARG for an unknown parameter or a value out of range, and
  * with ABI_ERR_STATE for a mixed-form parameter on an FP64 handle. */
 enum {
@@ -476,7 +489,8 @@ enum {
   ABI_TUNE_FFT_BATCH = 2,
   ABI_TUNE_OVERLAP = 3,
   ABI_TUNE_GENERIC_FFT = 4,
-  ABI_TUNE_MIXED_GEMM = 5
+  ABI_TUNE_MIXED_GEMM = 5,
+  ABI_TUNE_FILTER_GRAPH = 6
 };
 abi_status abi_set_tuning(abi_system sys, int32_t param, int32_t value);
 abi_status abi_get_tuning(abi_system sys, int32_t param, int32_t *value);

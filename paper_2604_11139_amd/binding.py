@@ -72,7 +72,8 @@ class Desc(ctypes.Structure):
     ]
 
 
-TUNE_PROJ, TUNE_EXPAND, TUNE_FFT_BATCH, TUNE_OVERLAP, TUNE_GENERIC_FFT, TUNE_MIXED_GEMM = range(6)
+(TUNE_PROJ, TUNE_EXPAND, TUNE_FFT_BATCH, TUNE_OVERLAP, TUNE_GENERIC_FFT, TUNE_MIXED_GEMM,
+ TUNE_FILTER_GRAPH) = range(7)
 RR_FELL_BACK, RR_LOWPREC, RR_TWO_PASS = 1, 2, 4
 
 _lib = None

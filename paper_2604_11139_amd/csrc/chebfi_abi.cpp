@@ -10,6 +10,7 @@
 // driver.cpp, block LOBPCG in lobpcg.cpp; the batched filter's host side and
 // the eigensolver and SCF loops are here.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -46,11 +47,18 @@ void *ScratchArena::take(DevBuf *b, size_t need) {
   return b->ptr;
 }
 
+namespace {
+std::atomic<uint64_t> g_devbuf_gen{0};
+}  // namespace
+
+uint64_t devbuf_generation() { return g_devbuf_gen.load(); }
+
 void *DevBuf::get(size_t need) {
   if (need == 0) need = 256;
   if (g_scratch_arena) return g_scratch_arena->take(this, need);
   if (bytes >= need) return ptr;
   release();
+  ++g_devbuf_gen;
   hipError_t e = hipMalloc(&ptr, need);
   if (e != hipSuccess) {
     ptr = nullptr;
@@ -63,7 +71,10 @@ void *DevBuf::get(size_t need) {
 }
 
 void DevBuf::release() {
-  if (ptr) (void)hipFree(ptr);
+  if (ptr) {
+    ++g_devbuf_gen;
+    (void)hipFree(ptr);
+  }
   ptr = nullptr;
   bytes = 0;
 }
@@ -164,7 +175,27 @@ void check_desc(const abi_system_desc *d) {
 }
 
 
+void free_graph_entry(abi_system_s::FilterGraph &f) {
+  if (f.exec) (void)hipGraphExecDestroy(f.exec);
+  if (f.graph) (void)hipGraphDestroy(f.graph);
+  f = abi_system_s::FilterGraph{};
+}
+
+void free_filter_graph(abi_system_s *s) {
+  for (auto &f : s->fg) free_graph_entry(f);
+  s->fg_next = 0;
+}
+
 void free_tables(abi_system_s *s) {
+  free_filter_graph(s);
+  if (s->coef_copied) (void)hipEventSynchronize(s->coef_copied);
+  if (s->coef_copied) (void)hipEventDestroy(s->coef_copied);
+  s->coef_copied = nullptr;
+  if (s->h_coef) (void)hipHostFree(s->h_coef);
+  s->h_coef = nullptr;
+  s->h_coef_n = 0;
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  s->cap_stream = nullptr;
   if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
   if (s->ev_join) (void)hipEventDestroy(s->ev_join);
   if (s->ev_half) (void)hipEventDestroy(s->ev_half);
@@ -792,24 +823,109 @@ void cheb_filter_impl(abi_system s, const void *X, const void *HX, void *Y, int6
       }
       return;
     }
-    // Y_1 = (s1/e)(H - c) X
-    if (HX)
-      launch_cheb_first(npw, nband, X, ld, HX, ld, s1 / e, c, bufs[slot(1)], lds[slot(1)], st,
-                        dtype == ABI_C64);
-    else
-      apply_core(s, X, ld, nullptr, 0, bufs[slot(1)], lds[slot(1)], nband, s1 / e, c, 0.0, st,
-                 dtype);
-    double sk = s1;
-    for (int j = 1; j < degree; ++j) {
-      const double sk1 = 1.0 / (2.0 / s1 - sk);
-      const void *yk = bufs[slot(j)];
-      const int64_t ldk = lds[slot(j)];
-      const void *yp = (j == 1) ? X : bufs[slot(j - 1)];
-      const int64_t ldp = (j == 1) ? ld : lds[slot(j - 1)];
-      apply_core(s, yk, ldk, yp, ldp, bufs[slot(j + 1)], lds[slot(j + 1)], nband, 2.0 * sk1 / e,
-                 c, sk * sk1, st, dtype);
-      sk = sk1;
+    // (alpha, cshift, beta) of steps 1 .. degree
+    std::vector<double> cf(3 * (size_t)degree);
+    {
+      cf[0] = s1 / e;
+      cf[1] = c;
+      cf[2] = 0.0;
+      double sk = s1;
+      for (int j = 1; j < degree; ++j) {
+        const double sk1 = 1.0 / (2.0 / s1 - sk);
+        cf[3 * j] = 2.0 * sk1 / e;
+        cf[3 * j + 1] = c;
+        cf[3 * j + 2] = sk * sk1;
+        sk = sk1;
+      }
     }
+    // The launches of the filter on stream q; with dc (device copy of cf) the
+    // kernels take each step's coefficients from it (same values, same bits).
+    auto run = [&](hipStream_t q, const double *dc) {
+      struct CoefScope {
+        abi_system_s *s;
+        ~CoefScope() { s->coef_dev = nullptr; }
+      } scope_c{s};
+      // Y_1 = (s1/e)(H - c) X
+      s->coef_dev = dc;
+      if (HX)
+        launch_cheb_first(npw, nband, X, ld, HX, ld, cf[0], c, bufs[slot(1)], lds[slot(1)], q,
+                          dtype == ABI_C64, dc);
+      else
+        apply_core(s, X, ld, nullptr, 0, bufs[slot(1)], lds[slot(1)], nband, cf[0], c, 0.0, q,
+                   dtype);
+      for (int j = 1; j < degree; ++j) {
+        const void *yk = bufs[slot(j)];
+        const int64_t ldk = lds[slot(j)];
+        const void *yp = (j == 1) ? X : bufs[slot(j - 1)];
+        const int64_t ldp = (j == 1) ? ld : lds[slot(j - 1)];
+        s->coef_dev = dc ? dc + 3 * j : nullptr;
+        apply_core(s, yk, ldk, yp, ldp, bufs[slot(j + 1)], lds[slot(j + 1)], nband, cf[3 * j], c,
+                   cf[3 * j + 2], q, dtype);
+      }
+    };
+    // captured form: not with the second stream, the profiler's events, or inside a
+    // no-allocation call
+    const bool graph = s->filter_graph && !(s->overlap && s->nproj > 0 && s->aux) &&
+                       !s->prof.on && g_scratch_arena == nullptr;
+    if (!graph) {
+      run(st, nullptr);
+      return;
+    }
+    // upload the coefficients through pinned memory (the previous upload is
+    // complete before the staging buffer is rewritten)
+    const size_t nc = cf.size();
+    if (!s->coef_copied)
+      CHEBFI_HIP(hipEventCreateWithFlags(&s->coef_copied, hipEventDisableTiming));
+    else
+      CHEBFI_HIP(hipEventSynchronize(s->coef_copied));
+    if (s->h_coef_n < nc) {
+      if (s->h_coef) CHEBFI_HIP(hipHostFree(s->h_coef));
+      s->h_coef = nullptr;
+      s->h_coef_n = 0;
+      CHEBFI_HIP(hipHostMalloc((void **)&s->h_coef, sizeof(double) * nc, hipHostMallocDefault));
+      s->h_coef_n = nc;
+    }
+    std::memcpy(s->h_coef, cf.data(), sizeof(double) * nc);
+    double *dc = (double *)s->coef.get(sizeof(double) * nc);
+    CHEBFI_HIP(hipMemcpyAsync(dc, s->h_coef, sizeof(double) * nc, hipMemcpyHostToDevice, st));
+    CHEBFI_HIP(hipEventRecord(s->coef_copied, st));
+    const uint64_t key[16] = {(uint64_t)(uintptr_t)X,  (uint64_t)(uintptr_t)HX,
+                              (uint64_t)(uintptr_t)Y,  (uint64_t)nband,
+                              (uint64_t)ld,            (uint64_t)dtype,
+                              (uint64_t)degree,        (uint64_t)s->pl_proj,
+                              (uint64_t)s->pl_expand,  (uint64_t)s->fft_batch,
+                              (uint64_t)s->generic_fft, (uint64_t)s->mixed_gemm,
+                              (uint64_t)s->overlap,    (uint64_t)(uintptr_t)dc,
+                              devbuf_generation(),     1};
+    for (auto &f : s->fg) {
+      if (f.exec && std::memcmp(key, f.key, sizeof(key)) == 0) {
+        CHEBFI_HIP(hipGraphLaunch(f.exec, st));
+        return;
+      }
+    }
+    // first call with these arguments: run eagerly (this also sizes every work
+    // buffer), then record the same launches on the capture stream
+    run(st, dc);
+    abi_system_s::FilterGraph &slotg = s->fg[s->fg_next];
+    s->fg_next = (s->fg_next + 1) % abi_system_s::kFilterGraphs;
+    free_graph_entry(slotg);
+    if (!s->cap_stream) CHEBFI_HIP(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    CHEBFI_HIP(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipGraph_t g = nullptr;
+    try {
+      run(s->cap_stream, dc);
+    } catch (...) {
+      (void)hipStreamEndCapture(s->cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      s->filter_graph = 0;  // (the result is in Y already; later calls run eagerly)
+      return;
+    }
+    CHEBFI_HIP(hipStreamEndCapture(s->cap_stream, &g));
+    slotg.graph = g;
+    CHEBFI_HIP(hipGraphInstantiate(&slotg.exec, slotg.graph, nullptr, nullptr, 0));
+    std::memcpy(slotg.key, key, sizeof(key));
+    slotg.key[14] = devbuf_generation();  // (unchanged unless the recording allocated)
 }
 
 }  // namespace
@@ -1556,6 +1672,11 @@ abi_status abi_set_tuning(abi_system s, int32_t param, int32_t value) {
         CHEBFI_REQUIRE(value >= 0 && value <= 2, ABI_ERR_ARG, "projector product form is 0..2");
         s->mixed_gemm = value;
         break;
+      case ABI_TUNE_FILTER_GRAPH:
+        CHEBFI_REQUIRE(value == 0 || value == 1, ABI_ERR_ARG, "filter graph is 0 or 1");
+        s->filter_graph = value;
+        if (!value) free_filter_graph(s);
+        break;
       default:
         CHEBFI_REQUIRE(false, ABI_ERR_ARG, "unknown tuning parameter");
     }
@@ -1572,6 +1693,7 @@ abi_status abi_get_tuning(abi_system s, int32_t param, int32_t *value) {
       case ABI_TUNE_OVERLAP: *value = s->overlap; break;
       case ABI_TUNE_GENERIC_FFT: *value = s->generic_fft; break;
       case ABI_TUNE_MIXED_GEMM: *value = s->mixed_gemm; break;
+      case ABI_TUNE_FILTER_GRAPH: *value = s->filter_graph; break;
       default: CHEBFI_REQUIRE(false, ABI_ERR_ARG, "unknown tuning parameter");
     }
   });

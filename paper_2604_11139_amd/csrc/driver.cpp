@@ -191,7 +191,7 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
     cprime = (V2 *)s->cprime.get(sizeof(V2) * (size_t)nproj * nband);
     const int tok =
         s->prof.begin(PROF_DAPPLY, (double)sizeof(V2) * nproj * nband * (splits + 1), st);
-    launch_dapply(s->natom, nband, cpart, splits, s->d_D, alpha, cprime, st, fp32);
+    launch_dapply(s->natom, nband, cpart, splits, s->d_D, alpha, cprime, st, fp32, s->coef_dev);
     s->prof.end(tok, st);
   }
   if (side) CHEBFI_HIP(hipStreamWaitEvent(st, s->ev_join, 0));

@@ -107,9 +107,15 @@ __global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ b
                               int band0, const C2<T> *__restrict__ Yk, int64_t ldk,
                               const C2<T> *__restrict__ Yprev, int64_t ldp,
                               C2<T> *__restrict__ Out, int64_t ldo, T alpha, T cshift, T beta,
-                              T scale, const C2<T> *__restrict__ E, int64_t lde) {
+                              T scale, const C2<T> *__restrict__ E, int64_t lde,
+                              const double *__restrict__ coef) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
+  if (coef) {  // (alpha, cshift, beta) of this step from device memory (captured filters)
+    alpha = (T)coef[0];
+    cshift = (T)coef[1];
+    beta = (T)coef[2];
+  }
   const int n1 = plan.d[0].n, n2 = plan.d[1].n;
   const int nxy = n1 * n2, L1 = n1 + 1;  // LDS plane rows padded to n1 + 1
   C2<T> *tw1 = buf + n2 * L1;
@@ -375,10 +381,16 @@ __global__ __launch_bounds__(kCT) void cpass_c_kernel(
     const int32_t *__restrict__ box_index, const int32_t *__restrict__ plane,
     const double *__restrict__ kin, int band0, const C2<T> *__restrict__ Yk, int64_t ldk,
     const C2<T> *__restrict__ Yprev, int64_t ldp, C2<T> *__restrict__ Out, int64_t ldo, T alpha,
-    T cshift, T beta, T scale, const C2<T> *__restrict__ E, int64_t lde) {
+    T cshift, T beta, T scale, const C2<T> *__restrict__ E, int64_t lde,
+    const double *__restrict__ coef) {
   constexpr int NXY = N * N, LD = N + 1;
   __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
+  if (coef) {  // (alpha, cshift, beta) of this step from device memory (captured filters)
+    alpha = (T)coef[0];
+    cshift = (T)coef[1];
+    beta = (T)coef[2];
+  }
   const int i3 = blockIdx.x;
   const int bl = blockIdx.y;
   for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(twg[i]);
@@ -443,7 +455,8 @@ void launch_cubic(const abi_system_s *s, const void *Yk, int64_t ldk, const void
   hipLaunchKernelGGL((cpass_c_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st, bx, tw, s->d_box,
                      s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Yk), ldk,
                      reinterpret_cast<const V2 *>(Yprev), ldp, reinterpret_cast<V2 *>(Out), ldo,
-                     (T)alpha, (T)cshift, (T)beta, scale, reinterpret_cast<const V2 *>(E), lde);
+                     (T)alpha, (T)cshift, (T)beta, scale, reinterpret_cast<const V2 *>(E), lde,
+                     s->coef_dev);
   CHEBFI_HIP(hipGetLastError());
   if (prof) prof->end(tok, st);
 }
@@ -473,7 +486,7 @@ void adjoint_cubic(const abi_system_s *s, const void *Ak1, int64_t lda1, const v
                      s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Ak1), lda1,
                      accumulate ? reinterpret_cast<const V2 *>(Ak) : (const V2 *)nullptr, ldak,
                      reinterpret_cast<V2 *>(Ak), ldak, (T)gamma, (T)cshift, (T)-1, scale,
-                     (const V2 *)nullptr, (int64_t)0);
+                     (const V2 *)nullptr, (int64_t)0, (const double *)nullptr);
   CHEBFI_HIP(hipGetLastError());
 }
 
@@ -623,7 +636,8 @@ void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, 
   hipLaunchKernelGGL(pass_c_kernel<T>, dim3(n3, nb), dim3(tA), ldsA, st, bx, plan, tw, s->d_box,
                      s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Yk), ldk,
                      reinterpret_cast<const V2 *>(Yprev), ldp, reinterpret_cast<V2 *>(Out), ldo,
-                     (T)alpha, (T)cshift, (T)beta, scale, reinterpret_cast<const V2 *>(E), lde);
+                     (T)alpha, (T)cshift, (T)beta, scale, reinterpret_cast<const V2 *>(E), lde,
+                     s->coef_dev);
   CHEBFI_HIP(hipGetLastError());
   if (prof) prof->end(tok, st);
 }
@@ -669,7 +683,7 @@ void launch_adjoint_local(const abi_system_s *s, const void *Ak1, int64_t lda1, 
                      s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Ak1), lda1,
                      accumulate ? reinterpret_cast<const V2 *>(Ak) : (const V2 *)nullptr, ldak,
                      reinterpret_cast<V2 *>(Ak), ldak, (T)gamma, (T)cshift, (T)-1, scale,
-                     (const V2 *)nullptr, (int64_t)0);
+                     (const V2 *)nullptr, (int64_t)0, (const double *)nullptr);
   CHEBFI_HIP(hipGetLastError());
 }
 

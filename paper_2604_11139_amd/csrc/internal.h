@@ -41,6 +41,9 @@ struct DevBuf {
   void release();
   ~DevBuf() { release(); }
 };
+// Counts device-buffer (re)allocations and releases in the process: a captured
+// graph is replayed only while it is unchanged (its buffers are all alive).
+uint64_t devbuf_generation();
 
 // Work-buffer arena of a no-allocation call.  While one is installed on the
 // calling thread, DevBuf::get hands out 256-byte aligned pieces of it (the
@@ -276,4 +279,25 @@ struct abi_system_s {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_half = nullptr;
   int overlap = 0;
   chebfi::Profiler prof;
+
+  // Captured filter: abi_cheb_filter records its launches once into a HIP graph
+  // (on cap_stream) and replays it on the caller's stream while the arguments,
+  // the launch choices and the work buffers (devbuf_generation) are unchanged;
+  // the coefficients of each step are read from `coef` (uploaded from h_coef
+  // before each replay), through coef_dev while the launches are recorded.
+  int filter_graph = 0;
+  hipStream_t cap_stream = nullptr;
+  struct FilterGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t key[16] = {0};
+  };
+  static constexpr int kFilterGraphs = 4;  // (a loop alternating two block pairs keeps both)
+  FilterGraph fg[kFilterGraphs];
+  int fg_next = 0;
+  chebfi::DevBuf coef;
+  double *h_coef = nullptr;
+  size_t h_coef_n = 0;
+  hipEvent_t coef_copied = nullptr;
+  const double *coef_dev = nullptr;
 };

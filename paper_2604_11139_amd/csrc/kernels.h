@@ -127,7 +127,8 @@ void zsum_parts(int64_t m, int64_t n, const void *part, int splits, void *C, int
 // Cprime[4R+i, b] = alpha * sum_j D_R[i][j] * sum_z part[z][4R+j, b]
 // (fp32: complex float partials and output, FP64 arithmetic inside)
 void launch_dapply(int natom, int64_t nband, const void *part, int splits, const void *D,
-                   double alpha, void *Cprime, hipStream_t st, bool fp32 = false);
+                   double alpha, void *Cprime, hipStream_t st, bool fp32 = false,
+                   const double *coef = nullptr);
 
 // rq[b] = Re(x_b^H hx_b) / Re(x_b^H sx_b); sx_b = x_b when SX is null
 void launch_rayleigh_quotients(int64_t npw, int64_t nband, const void *X, int64_t ldx,
@@ -206,7 +207,7 @@ void launch_col_norms(int64_t npw, int64_t nband, const void *X, int64_t ldx, do
 // out = alpha (HX - c X): the filter's first step from a given H X
 void launch_cheb_first(int64_t npw, int64_t nband, const void *X, int64_t ldx, const void *HX,
                        int64_t ldh, double alpha, double c, void *out, int64_t ldo, hipStream_t st,
-                       bool fp32);
+                       bool fp32, const double *coef = nullptr);
 // *out = min_i (Re A[i, i])^2 (m x m complex double, one workgroup)
 void launch_diag_min_sq(int64_t m, const void *A, int64_t lda, double *out, hipStream_t st);
 // out[:, b] = sc[b] X[:, b] (complex float blocks)

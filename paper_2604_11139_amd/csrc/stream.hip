@@ -38,7 +38,8 @@ __device__ double block_sum(double v, double *scratch) {
 template <typename T>
 __global__ void dapply_kernel(int natom, int64_t nband, const C2<T> *__restrict__ part,
                               int splits, const double2 *__restrict__ D, double alpha,
-                              C2<T> *__restrict__ Cp) {
+                              C2<T> *__restrict__ Cp, const double *__restrict__ coef) {
+  if (coef) alpha = coef[0];  // (this step's alpha from device memory: captured filters)
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)natom * nband) return;
   const int64_t R = idx % natom, b = idx / natom;
@@ -289,8 +290,13 @@ __global__ void col_norms_kernel(int64_t npw, const V2 *__restrict__ X, int64_t 
 template <typename V2>
 __global__ void cheb_first_kernel(int64_t npw, int64_t nband, const V2 *__restrict__ X,
                                   int64_t ldx, const V2 *__restrict__ HX, int64_t ldh,
-                                  double alpha, double c, V2 *__restrict__ out, int64_t ldo) {
+                                  double alpha, double c, V2 *__restrict__ out, int64_t ldo,
+                                  const double *__restrict__ coef) {
   typedef decltype(V2{}.x) R;
+  if (coef) {  // (alpha, c) from device memory (captured filters)
+    alpha = coef[0];
+    c = coef[1];
+  }
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= npw * nband) return;
   const int64_t i = idx % npw, b = idx / npw;
@@ -638,17 +644,17 @@ void launch_d2f(int64_t n, const double *src, float *dst, hipStream_t st) {
 }
 
 void launch_dapply(int natom, int64_t nband, const void *part, int splits, const void *D,
-                   double alpha, void *Cprime, hipStream_t st, bool fp32) {
+                   double alpha, void *Cprime, hipStream_t st, bool fp32, const double *coef) {
   const int64_t total = (int64_t)natom * nband;
   if (total <= 0) return;
   if (fp32)
     hipLaunchKernelGGL(dapply_kernel<float>, dim3(nblk(total, 256)), dim3(256), 0, st, natom,
                        nband, (const float2 *)part, splits, (const double2 *)D, alpha,
-                       (float2 *)Cprime);
+                       (float2 *)Cprime, coef);
   else
     hipLaunchKernelGGL(dapply_kernel<double>, dim3(nblk(total, 256)), dim3(256), 0, st, natom,
                        nband, (const double2 *)part, splits, (const double2 *)D, alpha,
-                       (double2 *)Cprime);
+                       (double2 *)Cprime, coef);
   CHEBFI_HIP(hipGetLastError());
 }
 
@@ -803,16 +809,16 @@ void launch_col_norms(int64_t npw, int64_t nband, const void *X, int64_t ldx, do
 
 void launch_cheb_first(int64_t npw, int64_t nband, const void *X, int64_t ldx, const void *HX,
                        int64_t ldh, double alpha, double c, void *out, int64_t ldo, hipStream_t st,
-                       bool fp32) {
+                       bool fp32, const double *coef) {
   const dim3 g(nblk(npw * nband, 256));
   if (fp32)
     hipLaunchKernelGGL(cheb_first_kernel<float2>, g, dim3(256), 0, st, npw, nband,
                        (const float2 *)X, ldx, (const float2 *)HX, ldh, alpha, c, (float2 *)out,
-                       ldo);
+                       ldo, coef);
   else
     hipLaunchKernelGGL(cheb_first_kernel<double2>, g, dim3(256), 0, st, npw, nband,
                        (const double2 *)X, ldx, (const double2 *)HX, ldh, alpha, c,
-                       (double2 *)out, ldo);
+                       (double2 *)out, ldo, coef);
   CHEBFI_HIP(hipGetLastError());
 }
 
