@@ -374,9 +374,12 @@ abi_status abi_zpotrf_upper(int64_t m, void *A, int64_t lda, void *stream);
 /* Eigen-decomposition of a Hermitian m x m matrix (upper and lower triangles
  * read as the average (A + A^H)/2): w (device, m doubles, ascending) and Z
  * (device, m x m, ldz) with A = Z diag(w) Z^H.  A is overwritten.  The hegvd
- * step of Algorithm "RR" after the Cholesky reduction.  1 <= m <= 2560
- * (ABI_ERR_ARG otherwise); allocates and frees a device workspace of about
- * 55 m^2 bytes per call (0.23 GB at m = 2048) and synchronises the stream. */
+ * step of Algorithm "RR" after the Cholesky reduction.  1 <= m <= 8192
+ * (ABI_ERR_ARG otherwise; 8192 is the paper's largest band count); allocates
+ * and frees a device workspace of about 55 m^2 bytes per call (0.23 GB at
+ * m = 2048), about 110 m^2 above m = 2560 (7.4 GB at m = 8192: the inverse
+ * iteration of eigenvalue clusters then keeps its arrays in global memory
+ * instead of LDS), and synchronises the stream. */
 abi_status abi_zheev(int64_t m, void *A, int64_t lda, double *w, void *Z, int64_t ldz,
                      void *stream);
 

@@ -30,7 +30,8 @@ namespace chebfi {
 namespace {
 
 constexpr int NB = 32;           // Cholesky / trtri block size
-constexpr int kEigMaxM = 2560;   // LDS-resident inverse iteration limit
+constexpr int kEigMaxM = 8192;   // eigensolver size limit
+constexpr int kLdsInvitM = 2560; // clusters' inverse iteration in LDS up to this size
 constexpr int kBtBlock = 64;     // reflectors per block of the back-transformation
 constexpr int kBtMinM = 96;      // smaller problems apply the reflectors one at a time
 constexpr int kBtSplits = 8;     // most K chunks of the V^H Z product
@@ -574,9 +575,12 @@ __global__ __launch_bounds__(64) void invit_lane_kernel(
 // One workgroup per cluster of eigenvalues closer than `gaptol`; the group
 // leader (first index of the cluster) computes all members in order.
 // S (m x m, real, column-major, lds) receives the tridiagonal eigenvectors.
+// gws: NULL, or (m above kLdsInvitM) a global slab of `per` bytes for each
+// cluster leader, which then holds the arrays kept in LDS otherwise.
 __global__ __launch_bounds__(256) void invit_kernel(int64_t m, const double *__restrict__ d, const double *__restrict__ e,
                              const double *__restrict__ w, const double *__restrict__ stats,
-                             double *__restrict__ S, int64_t lds) {
+                             double *__restrict__ S, int64_t lds, unsigned char *gws,
+                             size_t per) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t c0 = blockIdx.x;
   const double scale = stats[2];
@@ -586,7 +590,7 @@ __global__ __launch_bounds__(256) void invit_kernel(int64_t m, const double *__r
   while (c1 < m && w[c1] - w[c1 - 1] <= gaptol) ++c1;
   if (c1 == c0 + 1) return;  // a lone eigenvalue: invit_lane_kernel
 
-  double *sd = reinterpret_cast<double *>(smem_raw);
+  double *sd = reinterpret_cast<double *>(gws ? gws + (size_t)c0 * per : smem_raw);
   double *se = sd + m;
   double *rud = se + m;  // reciprocals of U's diagonal
   double *u1 = rud + m;  // first superdiagonal
@@ -911,6 +915,12 @@ void ztrtri_upper(int64_t m, void *Av, int64_t lda, void *work, hipStream_t st) 
   }
 }
 
+// bytes of one cluster's arrays in the inverse iteration (seven of m doubles,
+// m pivot flags, 256-byte aligned)
+static size_t invit_bytes(int64_t m) {
+  return (sizeof(double) * 7 * (size_t)m + (size_t)m + 64 + 255) / 256 * 256;
+}
+
 size_t zheev_work_bytes(int64_t m) {
   // d, e, e2, w-tmp, stats, tau, u, wrow, two u and two p buffers, a2, S (real
   // m x m), the lane-interleaved inverse iteration's five arrays and pivots
@@ -918,9 +928,11 @@ size_t zheev_work_bytes(int64_t m) {
   // G, T (nb x nb), W1, W2 (nb x m)
   const size_t nb = kBtBlock;
   const size_t lane_slab = (size_t)m * 64 * (size_t)((m + 63) / 64);
+  // (above kLdsInvitM the clusters' arrays take a global slab per possible leader)
+  const size_t invit_slabs = m > kLdsInvitM ? (size_t)m * invit_bytes(m) : 0;
   return sizeof(double) * (size_t)(4 * m + 8) + sizeof(double2) * (size_t)(8 * m) +
          sizeof(double) * (size_t)m * m + (5 * sizeof(double) + 1) * lane_slab +
-         sizeof(double2) * ((3 + kBtSplits) * nb * (size_t)m + 2 * nb * nb) +
+         sizeof(double2) * ((3 + kBtSplits) * nb * (size_t)m + 2 * nb * nb) + invit_slabs +
          24 * 256;  // each of the (at most 24) sub-buffers is rounded up to 256 bytes
 }
 
@@ -967,13 +979,17 @@ void zheev(int64_t m, void *Av, int64_t lda, double *wout, void *Zv, int64_t ldz
   hipLaunchKernelGGL(bisect_kernel, dim3(nblk(m, 4)), dim3(256), 0, st, m, d, e2, stats, wout);
   CHEBFI_HIP(hipGetLastError());
   // eigenvectors of the tridiagonal
-  const size_t lds_bytes = sizeof(double) * 7 * (size_t)m + (size_t)m + 64;
-  CHEBFI_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(invit_kernel),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+  // clusters: arrays in LDS up to kLdsInvitM, else in a global slab per leader
+  const bool in_lds = m <= kLdsInvitM;
+  const size_t lds_bytes = in_lds ? sizeof(double) * 7 * (size_t)m + (size_t)m + 64 : 0;
+  unsigned char *gws = in_lds ? nullptr : (unsigned char *)take((size_t)m * invit_bytes(m));
+  if (in_lds)
+    CHEBFI_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(invit_kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
   hipLaunchKernelGGL(invit_lane_kernel, dim3(nblk(m, 64)), dim3(64), 0, st, m, d, e, wout, stats,
                      S, m, lwork, lswp);
   hipLaunchKernelGGL(invit_kernel, dim3((unsigned)m), dim3(256), lds_bytes, st, m, d, e, wout,
-                     stats, S, m);
+                     stats, S, m, gws, invit_bytes(m));
   CHEBFI_HIP(hipGetLastError());
   hipLaunchKernelGGL(real_to_complex_kernel, dim3(nblk(m * m, 256)), dim3(256), 0, st, m, S, m, Z,
                      ldz);

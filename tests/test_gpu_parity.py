@@ -301,10 +301,11 @@ def test_zheev_degenerate():
     assert np.abs(Z.conj().T @ Z - np.eye(m)).max() <= 1e-11
 
 
-@pytest.mark.parametrize("m", [2048, 2560])
+@pytest.mark.parametrize("m", [2048, 2560, 3000])
 def test_zheev_large(m):
-    """The Rayleigh-Ritz size of the large workload and the largest size the
-    eigensolver accepts (one past it is an argument error)."""
+    """The Rayleigh-Ritz size of the large workload, the largest size whose
+    clusters' inverse iteration runs in LDS, and one above it (global-memory
+    arrays); one past the eigensolver's limit (8192) is an argument error."""
     import torch
     rng = np.random.default_rng(m)
     A = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
@@ -318,24 +319,28 @@ def test_zheev_large(m):
     assert np.abs(w - ref).max() <= 1e-12 * scale * np.sqrt(m)
     assert np.abs(A @ Z - Z * w[None, :]).max() <= 1e-11 * scale
     assert np.abs(Z.conj().T @ Z - np.eye(m)).max() <= 1e-11
-    if m == 2560:
+    if m == 3000:
         with pytest.raises(B.ChebfiError) as e:
-            B.zheev(torch.zeros((m + 1, m + 1), dtype=torch.complex128, device="cuda"))
+            B.zheev(torch.zeros((8193, 8193), dtype=torch.complex128, device="cuda"))
         assert e.value.code == B.ABI_ERR_ARG
 
 
-@pytest.mark.parametrize("kind", ["repeated", "near"])
-def test_zheev_clusters_large(kind):
+@pytest.mark.parametrize("kind,m", [("repeated", 600), ("near", 600), ("repeated", 2700)])
+def test_zheev_clusters_large(kind, m):
     """Wide clusters: 12 eigenvalues of multiplicity 50 (exactly repeated), or
     spread by 1e-10 inside each cluster (closer than the inverse iteration's
-    cluster gap, distinct to the multisection)."""
+    cluster gap, distinct to the multisection); at m = 2700 with 2100 more
+    distinct eigenvalues, so that the clusters' inverse iteration keeps its
+    arrays in global memory (above the LDS size)."""
     import torch
     rng = np.random.default_rng(11)
-    m = 600
     Q, _ = np.linalg.qr(rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)))
     lam = np.repeat(np.arange(12, dtype=np.float64) - 5.5, 50)
     if kind == "near":
         lam = lam + 1e-10 * np.tile(np.arange(50), 12)
+    if m > 600:
+        # distinct values between the clusters (gaps well above the cluster gap)
+        lam = np.concatenate([lam, np.linspace(-6.0, 6.0, m - 600) + 0.0123])
     A = (Q * lam[None, :]) @ Q.conj().T
     A = 0.5 * (A + A.conj().T)
     w, Z = B.zheev(torch.from_numpy(A).cuda())
@@ -344,6 +349,42 @@ def test_zheev_clusters_large(kind):
     assert np.abs(w - np.sort(lam)).max() <= 1e-12 * 6 * np.sqrt(m)
     assert np.abs(A @ Z - Z * w[None, :]).max() <= 1e-11 * 6
     assert np.abs(Z.conj().T @ Z - np.eye(m)).max() <= 1e-11
+
+
+def test_zheev_max_size():
+    """M = 8192 (the paper's largest band count, the eigensolver's limit): A =
+    Q diag(lam) Q^H with Q = I - 2 u u^H (|u| = 1) a Householder reflection, so
+    the eigenvalues are lam exactly; lam holds 8 clusters of 16 equal values
+    among distinct ones.  Residual and orthogonality formed on the GPU (FP64
+    complex products)."""
+    import torch
+    m = 8192
+    rng = np.random.default_rng(8192)
+    lam = np.sort(np.concatenate([np.repeat(np.linspace(-3.0, 3.0, 8), 16),
+                                  rng.uniform(-4.0, 4.0, m - 128)]))
+    u = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    u /= np.linalg.norm(u)
+    dev = "cuda"
+    ut = torch.from_numpy(u).to(dev)
+    lt = torch.from_numpy(lam).to(dev).to(torch.complex128)
+    # A = (I - 2 u u^H) D (I - 2 u u^H) = D - 2 u (D u)^H - 2 (D u) u^H + 4 (u^H D u) u u^H
+    Du = lt * ut
+    A = torch.diag(lt) - 2.0 * torch.outer(ut, Du.conj()) - 2.0 * torch.outer(Du, ut.conj())
+    A = A + 4.0 * (ut.conj() @ Du) * torch.outer(ut, ut.conj())
+    A = 0.5 * (A + A.conj().T)
+    w, Z = B.zheev(A.clone())
+    Z = Z.contiguous()
+    w = w.cpu().numpy()
+    scale = np.abs(lam).max()
+    assert np.all(np.diff(w) >= 0)
+    assert np.abs(w - lam).max() <= 1e-12 * scale * np.sqrt(m)
+    wt = torch.from_numpy(w).to(dev).to(torch.complex128)
+    R = A @ Z - Z * wt[None, :]
+    assert R.abs().max().item() <= 1e-11 * scale
+    O = Z.conj().T @ Z
+    O.diagonal().sub_(1.0)
+    assert O.abs().max().item() <= 1e-10
+    del A, Z, R, O
 
 
 @pytest.mark.parametrize("m", [1, 31, 33, 100, 257])
