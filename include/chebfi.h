@@ -64,7 +64,7 @@ typedef struct {
   double lattice[9];     /* rows a1, a2, a3 in bohr */
   double kpt_red[3];     /* k-point in reduced coordinates of the reciprocal basis */
   double ecut;           /* Ha; basis = {G : 0.5|k+G|^2 < ecut} (strict) */
-  int32_t ngrid[3];      /* FFT box n1, n2, n3; each {2,3,5}-smooth and <= 64 */
+  int32_t ngrid[3];      /* FFT box n1, n2, n3; each {2,3,5}-smooth and <= 96 */
   const double *vloc;    /* n1*n2*n3 reals, V_loc(r_i) with i1 fastest */
   int32_t natom;         /* >= 0; four projectors (s, px, py, pz) per atom */
   const double *tau_cart;/* natom*3 cartesian positions, bohr */
@@ -387,12 +387,13 @@ abi_status abi_zheev(int64_t m, void *A, int64_t lda, double *w, void *Z, int64_
  * The paper applies the operator to a whole block of bands per call instead
  * of band by band (section "Batch processing"); a batch extends this across
  * independent systems (cells, k-points) of uneven plane-wave counts and FFT
- * boxes.  One filter step of every system of the batch is five launches per
- * group of passes (projection + D and the expansion P C' in tiles of 32 bands,
- * the three FFT passes with the recurrence fused into the last), each a
- * grid-stride loop over the work items of all systems; the launches of a
- * filter are captured into a HIP graph on first use and replayed.  Limits: at most 1024 systems, at most 8 atoms
- * (32 projectors) per system, FFT edges up to 64, S = I (no Q). */
+ * boxes.  One filter step of every system of the batch is three launches for
+ * the projector products (projection partial sums in tiles of 32 bands, their
+ * reduction with D, the expansion P C' in tiles) and three FFT-pass launches per
+ * group of boxes (the recurrence fused into the last), each a grid-stride loop
+ * over the work items of all systems; the launches of a filter are captured
+ * into a HIP graph on first use and replayed.  Limits: at most 1024 systems, at
+ * most 8 atoms (32 projectors) per system, FFT edges up to 96, S = I (no Q). */
 typedef struct abi_batch_s *abi_batch;
 
 /* Builds the nsys systems of `descs` (as abi_set_system; all with the same

@@ -158,7 +158,7 @@ void check_desc(const abi_system_desc *d) {
   CHEBFI_REQUIRE(d->ecut > 0.0 && std::isfinite(d->ecut), ABI_ERR_ARG, "ecut must be > 0");
   for (int c = 0; c < 3; ++c) {
     const int n = d->ngrid[c];
-    CHEBFI_REQUIRE(n >= 2 && n <= kMaxN, ABI_ERR_GRID, "FFT box edge must be in [2, 64]");
+    CHEBFI_REQUIRE(n >= 2 && n <= kMaxN, ABI_ERR_GRID, "FFT box edge must be in [2, 96]");
     Plan1D p;
     CHEBFI_REQUIRE(make_plan(n, &p), ABI_ERR_GRID, "FFT box edge must be {2,3,5}-smooth");
   }

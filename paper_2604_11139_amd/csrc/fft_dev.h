@@ -10,7 +10,11 @@
 namespace chebfi {
 namespace {
 
-constexpr int kMaxB = 4;  // butterflies per thread per stage
+// butterflies per thread in one runtime-size stage of radix R: at most 20
+// complex values held per thread (radix 2: 10, 3: 6, 4: 5, 5: 4), which takes
+// every plane up to 96 x 96 in 512 threads
+constexpr int kStageValues = 20;
+__host__ __device__ constexpr int max_butterflies(int r) { return kStageValues / r; }
 
 // Radix-R DFT in registers; sgn = -1 forward (e^{-}), +1 inverse (e^{+}).
 template <typename T, int R> struct Dft;
@@ -144,10 +148,11 @@ __device__ void stage(C2<T> *buf, int n, int estride, int npen, int pstride, int
   const int nbf = n / R;
   const int total = npen * nbf;
   const int m = n / (p * R);
-  C2<T> y[kMaxB][R];
-  int dst[kMaxB];
+  constexpr int MB = max_butterflies(R);
+  C2<T> y[MB][R];
+  int dst[MB];
 #pragma unroll
-  for (int c = 0; c < kMaxB; ++c) {
+  for (int c = 0; c < MB; ++c) {
     const int i = threadIdx.x + c * blockDim.x;
     dst[c] = -1;
     if (i < total) {
@@ -173,7 +178,7 @@ __device__ void stage(C2<T> *buf, int n, int estride, int npen, int pstride, int
   }
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < kMaxB; ++c) {
+  for (int c = 0; c < MB; ++c) {
     if (dst[c] >= 0) {
 #pragma unroll
       for (int t = 0; t < R; ++t) buf[dst[c] + t * p * estride] = y[c][t];
@@ -206,13 +211,14 @@ __device__ void load_twiddles(C2<T> *dst, const double2 *src, int n) {
 }
 
 
-// Smallest multiple of 64 threads with at most kMaxB butterflies per thread in
-// every stage of the plan over npen pencils.
+// Smallest multiple of 64 threads with at most max_butterflies(r) butterflies
+// per thread in every stage of the plan over npen pencils.
 inline int stage_need(const Plan1D &pl, int npen) {
   int need = 64;
   for (int s = 0; s < pl.nstage; ++s) {
     const int total = npen * (pl.n / pl.radix[s]);
-    const int t = (total + kMaxB - 1) / kMaxB;
+    const int mb = max_butterflies(pl.radix[s]);
+    const int t = (total + mb - 1) / mb;
     if (t > need) need = t;
   }
   return (need + 63) / 64 * 64;

@@ -86,7 +86,8 @@ void *scratch_for_device(int dev);
 size_t scratch_bytes();
 
 // ---- FFT plan -------------------------------------------------------------
-constexpr int kMaxN = 64;       // largest box edge handled by the LDS passes
+constexpr int kMaxN = 96;       // largest box edge handled by the LDS passes (an FP64
+                                // 96 x 97 plane with its twiddles: 152 KB of LDS)
 constexpr int kMaxStages = 6;   // radix stages per 1D transform
 
 struct Plan1D {

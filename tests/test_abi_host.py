@@ -63,7 +63,7 @@ def test_grid_errors():
     with pytest.raises(B.ChebfiError) as e:
         B.gsphere_host(s)
     assert e.value.code == B.ABI_ERR_GRID
-    s.ngrid = (32, 32, 72)  # larger than the LDS passes take
+    s.ngrid = (32, 32, 100)  # larger than the LDS passes take (edges up to 96)
     with pytest.raises(B.ChebfiError) as e:
         B.gsphere_host(s)
     assert e.value.code == B.ABI_ERR_GRID
