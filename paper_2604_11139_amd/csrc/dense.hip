@@ -12,7 +12,9 @@
 // * U^-1: blocked, diagonal blocks inverted in LDS, off-diagonal panels by GEMM;
 // * Hermitian eigensolver: Householder reduction to real symmetric tridiagonal
 //   form (reflectors H = I - tau u u^H with a real sub-diagonal, applied from
-//   both sides as a rank-2 update, applied lazily: two launches per column),
+//   both sides as rank-2 updates gathered in panels of 32 columns: per column
+//   a read-only product with the trailing matrix and a row-parallel finish,
+//   per panel one GEMM update),
 //   eigenvalues by Sturm-count multisection (one wave per eigenvalue, 64
 //   points per round), eigenvectors of the tridiagonal by inverse iteration
 //   with partial-pivoting LU (one lane per isolated eigenvalue; one workgroup
@@ -35,6 +37,7 @@ constexpr int kLdsInvitM = 2560; // clusters' inverse iteration in LDS up to thi
 constexpr int kBtBlock = 64;     // reflectors per block of the back-transformation
 constexpr int kBtMinM = 96;      // smaller problems apply the reflectors one at a time
 constexpr int kBtSplits = 8;     // most K chunks of the V^H Z product
+constexpr int kBtGSplits = 64;   // most K chunks of the V^H V product
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -195,145 +198,268 @@ __global__ __launch_bounds__(256) void trtri_diag_kernel(int nb, double2 *__rest
 }
 
 // ------------------------------------------------------ tridiagonalisation --
-// Step j of the reduction uses the reflector H_j = I - tau_j u_j u_j^H of
-// column j (u_j[j+1] = 1, zero above), the product p_j = tau_j A22 u_j with the
-// trailing matrix A22 = A[j+1:, j+1:], a2_j = -tau_j (p_j^H u_j) / 2 and
-// w_j = p_j + a2_j u_j; the two-sided application is the rank-2 update
-// A22 -= u_j w_j^H + w_j u_j^H.  Each step is two launches: the rank-2 update
-// of step j-1 is applied lazily, to column j in tri_col_kernel and to the
-// columns right of it in tri_trail_kernel, which computes p_j from the updated
-// values in the same pass.  u and p alternate between two buffers.
+// Column c of the reduction uses the reflector H_c = I - tau_c u_c u_c^H of
+// the current column c below its subdiagonal (u_c[c+1] = 1, zero above), the
+// product p_c = tau_c A22 u_c with the current trailing matrix A22 =
+// A[c+1:, c+1:], a2_c = -tau_c (p_c^H u_c) / 2 and w_c = p_c + a2_c u_c; the
+// two-sided application is the rank-2 update A22 -= u_c w_c^H + w_c u_c^H.
+//
+// The updates are applied in panels of kTriNB columns (the blocked form of
+// the reduction, Golub & Van Loan section 8.3, as in LAPACK's hetrd/latrd):
+// within a panel the stored matrix keeps its values from the panel's start,
+// the current matrix being A - U W^H - W U^H over the panel's earlier columns
+// (U holds their u, W their w).  So the product A22 u_c reads the stored
+// matrix once, without writing it, and is corrected by the panel's small
+// products, p_c = tau_c (A22 u_c - U (W^H u_c) - W (U^H u_c)); at the panel's
+// end one GEMM applies A22 -= [U W] [W U]^H.  Each column takes two launches:
+// tri_mv_kernel (the reflector of column c; one workgroup per trailing column
+// for (A22 u_c)_i = (column i)^H u_c, A22 being Hermitian; and per block of 64
+// rows the partial products U^H u_c and W^H u_c) and tri_fin_kernel (rows in
+// blocks of 64: w_c, and the current column c+1 with the partial sums of
+// squares of its entries below the subdiagonal).  The first column of a panel
+// is copied by tri_start_kernel after the panel update.
 
-constexpr int kTriColThreads = 512;
+constexpr int kTriNB = 32;     // columns per panel
+constexpr int kTriRows = 64;   // rows per block
+constexpr int kTriFinT = 512;  // threads of tri_fin_kernel: 8 groups share the panel columns
 
 __device__ __forceinline__ double2 conj2(double2 a) { return double2{a.x, -a.y}; }
 
-// Column j, one workgroup.  For j >= 1: a2_{j-1} over rows j .. m-1, then
-// column j (rows j .. m-1) receives step j-1's rank-2 update.  For j <= m-2:
-// the Householder vector of column j below its subdiagonal (LAPACK-style
-// larfg: H^H (alpha, x) = (beta, 0) with beta real, u = (1, x / (alpha - beta)));
-// the scaled x is stored in A (the back-transformation reads it there) and in
-// ucur.  d[j] takes the updated diagonal.
-__global__ __launch_bounds__(kTriColThreads) void tri_col_kernel(
-    int64_t m, double2 *__restrict__ A, int64_t lda, int64_t j, const double2 *__restrict__ uprev,
-    const double2 *__restrict__ pprev, double2 *__restrict__ a2s, double *__restrict__ d,
-    double *__restrict__ e, double2 *__restrict__ tau, double2 *__restrict__ ucur) {
-  constexpr int NT = kTriColThreads, Q = (kEigMaxM + NT - 1) / NT;
-  static_assert(NT >= 64 && NT % 64 == 0, "whole waves");
-  __shared__ double scratch[32];
-  __shared__ double2 sh_alpha;
-  const int tid = threadIdx.x;
-  double2 *col = A + j * lda;
-  double2 c[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int64_t r = j + tid + (int64_t)NT * q;
-    c[q] = r < m ? col[r] : double2{0.0, 0.0};
-  }
-  if (j >= 1) {
-    double sr = 0, si = 0;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int64_t r = j + tid + (int64_t)NT * q;
-      if (r < m) {
-        const double2 pv = pprev[r], uv = uprev[r];
-        sr += pv.x * uv.x + pv.y * uv.y;  // conj(p) u
-        si += pv.x * uv.y - pv.y * uv.x;
-      }
-    }
-    const double2 dot = block_sum2(double2{sr, si}, scratch);
-    const double2 a2 = cscale(cmul(tau[j - 1], dot), -0.5);
-    const double2 uj = uprev[j];
-    const double2 cwj = conj2(cadd(pprev[j], cmul(a2, uj))), cuj = conj2(uj);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int64_t r = j + tid + (int64_t)NT * q;
-      if (r < m) {
-        const double2 ur = uprev[r], wr = cadd(pprev[r], cmul(a2, ur));
-        c[q] = csub(c[q], cadd(cmul(ur, cwj), cmul(wr, cuj)));
-      }
-    }
-    if (tid == 0) a2s[j - 1] = a2;
-  }
-  if (j + 1 >= m) {
-    if (tid == 0) d[j] = c[0].x;
-    return;
-  }
-  if (tid == 1) sh_alpha = c[0];  // row j + 1
-  double s = 0;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int64_t r = j + tid + (int64_t)NT * q;
-    if (r >= j + 2 && r < m) s += c[q].x * c[q].x + c[q].y * c[q].y;
-  }
-  const double xnorm2 = block_sum(s, scratch);  // its barriers also publish sh_alpha
-  const double2 alpha = sh_alpha;
-  double beta, tr, ti;
-  double2 scal{0, 0};
+// Reflector of the current column (alpha = its entry on the subdiagonal,
+// xnorm2 = the sum of squares below it): H^H (alpha, x) = (beta, 0) with beta
+// real (LAPACK's larfg convention); u = (1, x * scal).
+struct Reflector {
+  double beta;
+  double2 tau, scal;
+};
+__device__ Reflector make_reflector(double2 alpha, double xnorm2) {
+  Reflector h;
+  h.scal = double2{0.0, 0.0};
   if (xnorm2 == 0.0 && alpha.y == 0.0) {
-    beta = alpha.x;
-    tr = 0.0;
-    ti = 0.0;
-  } else {
-    const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xnorm2);
-    beta = (alpha.x >= 0.0) ? -nrm : nrm;
-    tr = (beta - alpha.x) / beta;
-    ti = -alpha.y / beta;
-    const double2 den{alpha.x - beta, alpha.y};
-    const double dd = den.x * den.x + den.y * den.y;
-    scal = double2{den.x / dd, -den.y / dd};
+    h.beta = alpha.x;
+    h.tau = double2{0.0, 0.0};
+    return h;
   }
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int64_t r = j + tid + (int64_t)NT * q;
-    if (r >= j + 2 && r < m) {
-      const double2 v = cmul(c[q], scal);
-      col[r] = v;
-      ucur[r] = v;
-    }
-  }
-  if (tid == 0) {
-    ucur[j + 1] = double2{1.0, 0.0};
-    d[j] = c[0].x;
-    e[j] = beta;
-    tau[j] = double2{tr, ti};
-  }
+  const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xnorm2);
+  h.beta = (alpha.x >= 0.0) ? -nrm : nrm;
+  h.tau = double2{(h.beta - alpha.x) / h.beta, -alpha.y / h.beta};
+  const double2 den{alpha.x - h.beta, alpha.y};
+  const double dd = den.x * den.x + den.y * den.y;
+  h.scal = double2{den.x / dd, -den.y / dd};
+  return h;
 }
 
-// Columns j+1 .. m-1, one workgroup per column: for j >= 1, rows j+1 .. m-1
-// of the column receive step j-1's rank-2 update and are stored; p_j[i] =
-// tau_j times the conjugated (updated) column i dotted with u_j, which is row i
-// of A22 u_j because A22 is Hermitian.  Row j of these columns is not
-// updated: no later step reads it.
-__global__ __launch_bounds__(256) void tri_trail_kernel(
-    int64_t m, double2 *__restrict__ A, int64_t lda, int64_t j, const double2 *__restrict__ uprev,
-    const double2 *__restrict__ pprev, const double2 *__restrict__ a2s,
-    const double2 *__restrict__ ucur, const double2 *__restrict__ tau, double2 *__restrict__ pcur) {
+// Column c (rows c .. m-1) of the stored matrix as the current column (the
+// first of a panel): x, d[c], and per block of 64 rows the sum of squares of
+// the rows >= c + 2.  One wave per block.
+__global__ __launch_bounds__(64) void tri_start_kernel(int64_t m, const double2 *__restrict__ A,
+                                                       int64_t lda, int64_t c,
+                                                       double2 *__restrict__ x,
+                                                       double *__restrict__ d,
+                                                       double *__restrict__ normpart) {
+  const int64_t r = c + (int64_t)kTriRows * blockIdx.x + threadIdx.x;
+  double s = 0.0;
+  if (r < m) {
+    const double2 a = A[r + c * lda];
+    x[r] = a;
+    if (r == c) d[c] = a.x;
+    if (r >= c + 2) s = a.x * a.x + a.y * a.y;
+  }
+  s = wave_sum(s);
+  if (threadIdx.x == 0) normpart[blockIdx.x] = s;
+}
+
+// Panel column k = c - j0, L = m - c - 1 trailing columns.  Workgroups
+// 0 .. L-1: column i = c + 1 + blockIdx.x, y[i] = (column i)^H u_c over rows
+// c+1 .. m-1 and yupart[blockIdx.x] = conj(y[i]) u_c[i].  Workgroups L .. L +
+// nrb - 1: rows in blocks of 64, u_c stored into A (rows >= c + 2, read by the
+// back-transformation), into column k of U in P1 = [U | W] (m x 2 kTriNB,
+// ld m) and, conjugated, into Q = [W | U]^H (2 kTriNB x m, ld 2 kTriNB); and
+// stpart[rb * 2 kTriNB + i] = U_i^H u_c (i < kTriNB), then W_i^H u_c, over
+// the block's rows for the panel columns < k.
+__global__ __launch_bounds__(256) void tri_mv_kernel(
+    int64_t m, double2 *__restrict__ A, int64_t lda, int64_t c, int k,
+    const double2 *__restrict__ x, const double *__restrict__ normpart, int nparts,
+    double2 *__restrict__ P1, double2 *__restrict__ Q, double2 *__restrict__ y,
+    double2 *__restrict__ yupart, double2 *__restrict__ stpart, double *__restrict__ e,
+    double2 *__restrict__ tau) {
   __shared__ double scratch[32];
-  const int64_t ci = j + 1 + (int64_t)blockIdx.x;
-  double2 *col = A + ci * lda;
-  const bool upd = j >= 1;
-  double2 a2{0, 0}, cwi{0, 0}, cui{0, 0};
-  if (upd) {
-    a2 = a2s[j - 1];
-    const double2 ui = uprev[ci];
-    cwi = conj2(cadd(pprev[ci], cmul(a2, ui)));
-    cui = conj2(ui);
+  __shared__ double2 urow[kTriRows];
+  __shared__ double2 red[4][2 * kTriNB];
+  const int t = threadIdx.x, lane = t & 63;
+  const int64_t L = m - c - 1;
+  // the reflector of column c (every wave computes it)
+  double s = 0.0;
+  for (int i = lane; i < nparts; i += 64) s += normpart[i];
+  const Reflector h = make_reflector(x[c + 1], wave_sum(s));
+  if (blockIdx.x == 0 && t == 0) {
+    e[c] = h.beta;
+    tau[c] = h.tau;
   }
-  double sr = 0, si = 0;
-  for (int64_t r = j + 1 + threadIdx.x; r < m; r += blockDim.x) {
-    double2 a = col[r];
-    if (upd) {
-      const double2 ur = uprev[r], wr = cadd(pprev[r], cmul(a2, ur));
-      a = csub(a, cadd(cmul(ur, cwi), cmul(wr, cui)));
-      col[r] = a;
+  if (blockIdx.x < L) {
+    const int64_t i = c + 1 + blockIdx.x;
+    const double2 *col = A + i * lda;
+    const double2 a1 = col[c + 1], xi = x[i];
+    double2 acc{0.0, 0.0};  // (rows >= c + 2 of column i)^H x
+    for (int64_t r = c + 2 + t; r < m; r += 256) {
+      const double2 a = col[r], v = x[r];
+      acc.x += a.x * v.x + a.y * v.y;
+      acc.y += a.x * v.y - a.y * v.x;
     }
-    const double2 v = ucur[r];
-    sr += a.x * v.x + a.y * v.y;  // conj(a) v
-    si += a.x * v.y - a.y * v.x;
+    const double2 dot = block_sum2(acc, scratch);
+    if (t == 0) {
+      const double2 yi = cadd(conj2(a1), cmul(h.scal, dot));  // u_c[c+1] = 1
+      const double2 ui = (i == c + 1) ? double2{1.0, 0.0} : cmul(xi, h.scal);
+      y[i] = yi;
+      yupart[blockIdx.x] = cmul(conj2(yi), ui);
+    }
+    return;
   }
-  const double2 dot = block_sum2(double2{sr, si}, scratch);
-  if (threadIdx.x == 0) pcur[ci] = cmul(tau[j], dot);
+  const int64_t r0 = c + 1 + (int64_t)kTriRows * (blockIdx.x - L);
+  if (t < kTriRows) {
+    const int64_t r = r0 + t;
+    double2 u{0.0, 0.0};
+    if (r < m) {
+      u = (r == c + 1) ? double2{1.0, 0.0} : cmul(x[r], h.scal);
+      if (r >= c + 2) A[r + c * lda] = u;
+      P1[r + (int64_t)k * m] = u;
+      Q[(kTriNB + k) + r * 2 * kTriNB] = conj2(u);
+    }
+    urow[t] = u;
+  }
+  if (k == 0) return;
+  __syncthreads();
+  // thread (column i = t & 63, quarter q = t >> 6) sums 16 rows
+  const int i = t & 63, q = t >> 6, ii = i & (kTriNB - 1);
+  double2 dq{0.0, 0.0};
+  if (ii < k) {
+    const double2 *pc = P1 + (int64_t)(i < kTriNB ? ii : kTriNB + ii) * m;
+    for (int l = 16 * q; l < 16 * q + 16; ++l) {
+      const int64_t rl = r0 + l;
+      if (rl < m) dq = cadd(dq, cmul(conj2(pc[rl]), urow[l]));
+    }
+  }
+  red[q][i] = dq;
+  __syncthreads();
+  if (t < 2 * kTriNB)
+    stpart[(int64_t)(blockIdx.x - L) * 2 * kTriNB + t] =
+        cadd(cadd(red[0][t], red[1][t]), cadd(red[2][t], red[3][t]));
+}
+
+// Rows c+1 .. m-1 in blocks of 64 (thread: row lane = t & 63, group g = t >> 6
+// of 8, the groups sharing the panel columns): w_c = tau_c (y - U s - W t) +
+// a2_c u_c with s = W^H u_c, t = U^H u_c and a2_c = -|tau_c|^2 (u_c^H A22 u_c
+// - s^H t - t^H s) / 2, stored as column k of W in P1 and Q.  With next != 0
+// also the current column c+1: A[:, c+1] - [U u_c] [W w_c]^H[:, c+1] -
+// [W w_c] [U u_c]^H[:, c+1] into x (rows c+1 .. m-1), d[c+1], and the
+// per-block sums of squares of its rows >= c + 3.  nrb: the row blocks of
+// tri_mv_kernel's partial products.
+__global__ __launch_bounds__(kTriFinT) void tri_fin_kernel(
+    int64_t m, const double2 *__restrict__ A, int64_t lda, int64_t c, int k, int next, int nrb,
+    double2 *__restrict__ P1, double2 *__restrict__ Q, const double2 *__restrict__ y,
+    const double2 *__restrict__ yupart, const double2 *__restrict__ stpart,
+    const double2 *__restrict__ tau, double2 *__restrict__ x, double *__restrict__ d,
+    double *__restrict__ normpart) {
+  constexpr int NG = kTriFinT / 64, NJ = kTriNB / NG;
+  __shared__ double2 st[2 * kTriNB];
+  __shared__ double2 red[NG][kTriRows];
+  __shared__ double2 red2[NG][kTriRows];
+  __shared__ double sred[NG][6];
+  const int t = threadIdx.x, lane = t & 63, g = t >> 6;
+  const int64_t L = m - c - 1;
+  const int64_t r = c + 1 + (int64_t)kTriRows * blockIdx.x + lane;
+  const bool in = r < m;
+  // loads that depend on nothing else: this row's panel entries (columns
+  // i = g + NG j), row c+1's, this row's y, u and A[r, c+1], the partials
+  double2 ur[NJ], wr[NJ], uc1[NJ], wc1r[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int i = g + NG * j;
+    const bool ok = i < k;
+    ur[j] = ok && in ? P1[r + (int64_t)i * m] : double2{0.0, 0.0};
+    wr[j] = ok && in ? P1[r + (int64_t)(kTriNB + i) * m] : double2{0.0, 0.0};
+    uc1[j] = ok ? P1[c + 1 + (int64_t)i * m] : double2{0.0, 0.0};
+    wc1r[j] = ok ? P1[c + 1 + (int64_t)(kTriNB + i) * m] : double2{0.0, 0.0};
+  }
+  const double2 yr = in ? y[r] : double2{0.0, 0.0};
+  const double2 u = in ? P1[r + (int64_t)k * m] : double2{0.0, 0.0};
+  const double2 anext = (in && next) ? A[r + (c + 1) * lda] : double2{0.0, 0.0};
+  const double2 yc1 = y[c + 1];
+  const double2 tc = tau[c];
+  double2 yu{0.0, 0.0};
+  for (int64_t b = t; b < L; b += kTriFinT) yu = cadd(yu, yupart[b]);
+  double2 stp{0.0, 0.0};
+  if ((lane & (kTriNB - 1)) < k)
+    for (int b = g; b < nrb; b += NG) stp = cadd(stp, stpart[(int64_t)b * 2 * kTriNB + lane]);
+  // s and t
+  red[g][lane] = stp;
+  __syncthreads();
+  if (t < 2 * kTriNB) {
+    double2 v{0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < NG; ++q) v = cadd(v, red[q][t]);
+    st[t] = v;
+  }
+  __syncthreads();
+  // one block reduction: u^H A22 u, s^H t + t^H s and row c+1's correction
+  // (the last two from each group's panel columns, counted on its lane 0)
+  double2 sht{0.0, 0.0}, cc1{0.0, 0.0}, corr{0.0, 0.0}, ncorr{0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int i = g + NG * j;
+    if (i < k) {
+      const double2 ti = st[i], si = st[kTriNB + i];
+      sht = cadd(sht, cadd(cmul(conj2(si), ti), cmul(conj2(ti), si)));
+      cc1 = cadd(cc1, cadd(cmul(uc1[j], si), cmul(wc1r[j], ti)));
+      corr = cadd(corr, cadd(cmul(ur[j], si), cmul(wr[j], ti)));
+      ncorr = cadd(ncorr, cadd(cmul(ur[j], conj2(wc1r[j])), cmul(wr[j], conj2(uc1[j]))));
+    }
+  }
+  if (lane != 0) {
+    sht = double2{0.0, 0.0};
+    cc1 = double2{0.0, 0.0};
+  }
+  double v6[6] = {yu.x, yu.y, sht.x, sht.y, cc1.x, cc1.y};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) v6[q] = wave_sum(v6[q]);
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) sred[g][q] = v6[q];
+  red[g][lane] = corr;
+  red2[g][lane] = ncorr;
+  __syncthreads();
+  if (g != 0) return;
+  double tot[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < NG; ++q)
+#pragma unroll
+    for (int p = 0; p < 6; ++p) tot[p] += sred[q][p];
+  const double tt = tc.x * tc.x + tc.y * tc.y;
+  const double2 a2 = cscale(double2{tot[0] - tot[2], tot[1] - tot[3]}, -0.5 * tt);
+  const double2 wc1 = cadd(cmul(tc, csub(yc1, double2{tot[4], tot[5]})), a2);  // u_c[c+1] = 1
+  double s2 = 0.0;
+  if (in) {
+    double2 cs{0.0, 0.0}, ns{0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      cs = cadd(cs, red[q][lane]);
+      ns = cadd(ns, red2[q][lane]);
+    }
+    const double2 w = (r == c + 1) ? wc1 : cadd(cmul(tc, csub(yr, cs)), cmul(a2, u));
+    P1[r + (int64_t)(kTriNB + k) * m] = w;
+    Q[k + r * 2 * kTriNB] = conj2(w);
+    if (next) {
+      // the panel's column k term: u[r] conj(w[c+1]) + w[r] conj(u[c+1]), u[c+1] = 1
+      const double2 a = csub(csub(anext, ns), cadd(cmul(u, conj2(wc1)), w));
+      x[r] = a;
+      if (r == c + 1) d[c + 1] = a.x;
+      if (r >= c + 3) s2 = a.x * a.x + a.y * a.y;
+    }
+  }
+  if (next) {
+    s2 = wave_sum(s2);
+    if (lane == 0) normpart[blockIdx.x] = s2;
+  }
 }
 
 // ---------------------------------------------------------------- bisection --
@@ -843,31 +969,41 @@ __global__ __launch_bounds__(256) void build_v_kernel(int64_t m, const double2 *
 
 // Upper triangular T with H_{j0} H_{j0+1} ... H_{j0+nb-1} = I - V T V^H (forward
 // accumulation of the block reflector), from G = V^H V: T[k][k] = tau_k and
-// T[i][k] = -tau_k sum_{l=i}^{k-1} T[i][l] G[l][k].  Thread i owns row i.
-__global__ __launch_bounds__(64) void larft_kernel(int nb, const double2 *__restrict__ G,
-                                                   const double2 *__restrict__ tau,
-                                                   double2 *__restrict__ T) {
-  // row i of T depends only on row i and G: thread i runs its row's
-  // recurrence with G and its row held in LDS (column-major, conflict-free)
-  __shared__ double2 Gs[kBtBlock * kBtBlock];
-  __shared__ double2 Ts[kBtBlock * kBtBlock];
-  const int i = threadIdx.x;
-  for (int idx = i; idx < nb * nb; idx += blockDim.x) {
-    Gs[idx] = G[idx];
-    Ts[idx] = double2{0.0, 0.0};
-  }
+// T[i][k] = -tau_k sum_{l=i}^{k-1} T[i][l] G[l][k].  Row i depends only on
+// itself and G; 16 lanes share a row (lane q sums the terms l = i + q (mod 16)
+// and owns the entries T[i][k] with k = i + q (mod 16), the only ones it
+// reads back), the sum completed by shuffles within the 16 lanes.
+constexpr int kLarftLanes = 16;
+__global__ __launch_bounds__(kBtBlock * kLarftLanes) void larft_kernel(
+    int nb, const double2 *__restrict__ G, const double2 *__restrict__ tau,
+    double2 *__restrict__ T) {
+  __shared__ double2 Gs[kBtBlock * kBtBlock];  // column-major, ld nb
+  __shared__ double2 Tr[kBtBlock * kBtBlock];  // row-major, ld kBtBlock
+  __shared__ double2 taus[kBtBlock];
+  const int t = threadIdx.x;
+  for (int idx = t; idx < nb * nb; idx += blockDim.x) Gs[idx] = G[idx];
+  if (t < nb) taus[t] = tau[t];
+  for (int idx = t; idx < kBtBlock * kBtBlock; idx += blockDim.x) Tr[idx] = double2{0.0, 0.0};
   __syncthreads();
-  if (i < nb) {
-    Ts[i + i * nb] = tau[i];
-    for (int k = i + 1; k < nb; ++k) {
-      double2 acc{0.0, 0.0};
-      for (int l = i; l < k; ++l) acc = cadd(acc, cmul(Ts[i + l * nb], Gs[l + k * nb]));
-      const double2 t = cmul(tau[k], acc);
-      Ts[i + k * nb] = double2{-t.x, -t.y};
+  const int i = t / kLarftLanes, q = t % kLarftLanes;
+  double2 *row = Tr + i * kBtBlock;
+  if (i < nb && q == 0) row[i] = taus[i];
+  for (int k = 1; k < nb; ++k) {  // the same trip count on every lane (shuffles below)
+    double2 acc{0.0, 0.0};
+    if (i < k)
+      for (int l = i + q; l < k; l += kLarftLanes) acc = cadd(acc, cmul(row[l], Gs[l + k * nb]));
+    for (int off = kLarftLanes / 2; off > 0; off >>= 1) {
+      acc.x += __shfl_xor(acc.x, off, 64);
+      acc.y += __shfl_xor(acc.y, off, 64);
+    }
+    if (i < k && q == (k - i) % kLarftLanes) {
+      const double2 v = cmul(taus[k], acc);
+      row[k] = double2{-v.x, -v.y};
     }
   }
   __syncthreads();
-  for (int idx = i; idx < nb * nb; idx += blockDim.x) T[idx] = Ts[idx];
+  for (int idx = t; idx < nb * nb; idx += blockDim.x)
+    T[idx] = Tr[(idx % nb) * kBtBlock + idx / nb];
 }
 
 }  // namespace
@@ -922,18 +1058,21 @@ static size_t invit_bytes(int64_t m) {
 }
 
 size_t zheev_work_bytes(int64_t m) {
-  // d, e, e2, w-tmp, stats, tau, u, wrow, two u and two p buffers, a2, S (real
-  // m x m), the lane-interleaved inverse iteration's five arrays and pivots
-  // (m x 64 per wave each), and the blocked back-transformation's V (m x nb),
-  // G, T (nb x nb), W1, W2 (nb x m)
+  // d, e, e2, w-tmp, stats, the norm partials, tau, u, wrow, the current
+  // column, the reduction's panels P1, Q (m x 2 kTriNB each), y, its partial
+  // sums, S (real m x m), the lane-interleaved inverse iteration's five
+  // arrays and pivots (m x 64 per wave each), and the blocked
+  // back-transformation's V (m x nb), G, T (nb x nb), W1, W2 (nb x m)
   const size_t nb = kBtBlock;
+  const size_t tri = 4 * kTriNB * (size_t)m + 3 * (size_t)m + 2 * kTriNB * nblk(m, kTriRows);
   const size_t lane_slab = (size_t)m * 64 * (size_t)((m + 63) / 64);
   // (above kLdsInvitM the clusters' arrays take a global slab per possible leader)
   const size_t invit_slabs = m > kLdsInvitM ? (size_t)m * invit_bytes(m) : 0;
-  return sizeof(double) * (size_t)(4 * m + 8) + sizeof(double2) * (size_t)(8 * m) +
+  return sizeof(double) * (size_t)(4 * m + 8) + sizeof(double2) * (size_t)(4 * m) +
+         sizeof(double2) * tri +
          sizeof(double) * (size_t)m * m + (5 * sizeof(double) + 1) * lane_slab +
          sizeof(double2) * ((3 + kBtSplits) * nb * (size_t)m + 2 * nb * nb) + invit_slabs +
-         24 * 256;  // each of the (at most 24) sub-buffers is rounded up to 256 bytes
+         28 * 256;  // each of the (at most 28) sub-buffers is rounded up to 256 bytes
 }
 
 void zheev(int64_t m, void *Av, int64_t lda, double *wout, void *Zv, int64_t ldz, void *work,
@@ -954,25 +1093,50 @@ void zheev(int64_t m, void *Av, int64_t lda, double *wout, void *Zv, int64_t ldz
   double2 *tau = (double2 *)take(sizeof(double2) * m);
   double2 *u = (double2 *)take(sizeof(double2) * m);
   double2 *wrow = (double2 *)take(sizeof(double2) * m);
-  double2 *ub = (double2 *)take(sizeof(double2) * 2 * m);
-  double2 *pb = (double2 *)take(sizeof(double2) * 2 * m);
-  double2 *a2s = (double2 *)take(sizeof(double2) * m);
+  // blocked reduction: P1 = [U W] (m x 2 kTriNB), Q = [W U]^H (2 kTriNB x m),
+  // the current column, y = A22 u and the partial sums
+  double2 *P1 = (double2 *)take(sizeof(double2) * 2 * kTriNB * (size_t)m);
+  double2 *Q = (double2 *)take(sizeof(double2) * 2 * kTriNB * (size_t)m);
+  double2 *xv = (double2 *)take(sizeof(double2) * m);
+  double2 *yv = (double2 *)take(sizeof(double2) * m);
+  double2 *yupart = (double2 *)take(sizeof(double2) * m);
+  double *normpart = (double *)take(sizeof(double) * nblk(m, kTriRows));
+  double2 *stpart = (double2 *)take(sizeof(double2) * 2 * kTriNB * (size_t)nblk(m, kTriRows));
   double *S = (double *)take(sizeof(double) * (size_t)m * m);
   const size_t lane_slab = (size_t)m * 64 * nblk(m, 64);  // per array, all waves
   double *lwork = (double *)take(sizeof(double) * 5 * lane_slab);
   unsigned char *lswp = (unsigned char *)take(lane_slab);
 
   launch_hermitize(m, A, lda, st);
-  // reduction to tridiagonal form: two launches per column, then the last diagonal
-  for (int64_t j = 0; j < m; ++j) {
-    const int cur = (int)(j & 1), prev = cur ^ 1;
-    hipLaunchKernelGGL(tri_col_kernel, dim3(1), dim3(kTriColThreads), 0, st, m, A, lda, j,
-                       ub + prev * m, pb + prev * m, a2s, d, e, tau, ub + cur * m);
-    const int64_t L = m - j - 1;
-    if (L > 0)
-      hipLaunchKernelGGL(tri_trail_kernel, dim3((unsigned)L), dim3(256), 0, st, m, A, lda, j,
-                         ub + prev * m, pb + prev * m, a2s, ub + cur * m, tau, pb + cur * m);
+  // reduction to tridiagonal form: two launches per column, and per panel of
+  // kTriNB columns one GEMM update of the trailing matrix and one copy of the
+  // next panel's first column
+  hipLaunchKernelGGL(tri_start_kernel, dim3(nblk(m, kTriRows)), dim3(64), 0, st, m, A, lda,
+                     int64_t{0}, xv, d, normpart);
+  int64_t j0 = 0;
+  auto panel_update = [&](int64_t c) {  // A[c:, c:] -= [U W] [W U]^H, then column c
+    const int64_t L = m - c;
+    zgemm(OP_N, OP_N, L, L, 2 * kTriNB, P1 + c, m, Q + c * 2 * kTriNB, 2 * kTriNB,
+          A + c + c * lda, lda, double2{-1, 0}, double2{1, 0}, st);
+    hipLaunchKernelGGL(tri_start_kernel, dim3(nblk(L, kTriRows)), dim3(64), 0, st, m, A, lda, c,
+                       xv, d, normpart);
+  };
+  for (int64_t c = 0; c + 1 < m; ++c) {
+    if (c == j0 + kTriNB) {
+      panel_update(c);
+      j0 = c;
+    }
+    const int k = (int)(c - j0);
+    const int64_t L = m - c - 1;
+    const int nrb = (int)nblk(L, kTriRows);
+    hipLaunchKernelGGL(tri_mv_kernel, dim3((unsigned)(L + nrb)), dim3(256), 0, st, m, A, lda, c, k,
+                       xv, normpart, (int)nblk(m - c, kTriRows), P1, Q, yv, yupart, stpart, e,
+                       tau);
+    const int next = (c + 1 < j0 + kTriNB) ? 1 : 0;
+    hipLaunchKernelGGL(tri_fin_kernel, dim3(nrb), dim3(kTriFinT), 0, st, m, A, lda, c, k, next,
+                       nrb, P1, Q, yv, yupart, stpart, tau, xv, d, normpart);
   }
+  if (m >= 2 && m - 1 == j0 + kTriNB) panel_update(m - 1);  // the last diagonal entry
   CHEBFI_HIP(hipGetLastError());
   // eigenvalues of the tridiagonal
   hipLaunchKernelGGL(tri_prep_kernel, dim3(1), dim3(256), 0, st, m, d, e, e2, stats);
@@ -1011,8 +1175,14 @@ void zheev(int64_t m, void *Av, int64_t lda, double *wout, void *Zv, int64_t ldz
       double2 *Zr = Z + (j0 + 1);
       hipLaunchKernelGGL(build_v_kernel, dim3(nblk(Lr * nb, 256)), dim3(256), 0, st, m, A, lda, j0,
                          nb, V);
-      zgemm(OP_C, OP_N, nb, nb, Lr, V, Lr, V, Lr, G, nb, double2{1, 0}, double2{0, 0}, st);
-      hipLaunchKernelGGL(larft_kernel, dim3(1), dim3(64), 0, st, nb, G, tau + j0, T);
+      // G = V^H V: a 64 x 64 product over Lr rows, split over K to fill the chip
+      const int spg = (int)std::max<int64_t>(
+          1, std::min<int64_t>({Lr / 64, kBtGSplits, (int64_t)kBtSplits * m / nb}));
+      zgemm(OP_C, OP_N, nb, nb, Lr, V, Lr, V, Lr, nullptr, 0, double2{1, 0}, double2{0, 0}, st,
+            Wp, spg);
+      zsum_parts(nb, nb, Wp, spg, G, nb, double2{1, 0}, double2{0, 0}, st);
+      hipLaunchKernelGGL(larft_kernel, dim3(1), dim3(kBtBlock * kLarftLanes), 0, st, nb, G,
+                         tau + j0, T);
       const int sp = std::min(kBtSplits, zgemm_splits(nb, m, Lr));
       zgemm(OP_C, OP_N, nb, m, Lr, V, Lr, Zr, ldz, nullptr, 0, double2{1, 0}, double2{0, 0}, st, Wp,
             sp);

@@ -270,7 +270,7 @@ def test_rayleigh_ritz_rank_deficient():
     assert e.value.code == B.ABI_ERR_NOT_HPD
 
 
-@pytest.mark.parametrize("m", [1, 2, 7, 33, 64, 95, 96, 130, 300, 1000])
+@pytest.mark.parametrize("m", [1, 2, 7, 33, 64, 65, 95, 96, 130, 300, 1000])
 def test_zheev(m):
     import torch
     rng = np.random.default_rng(m)
