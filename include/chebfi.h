@@ -393,12 +393,12 @@ abi_status abi_zheev(int64_t m, void *A, int64_t lda, double *w, void *Z, int64_
  * group of boxes (the recurrence fused into the last), each a grid-stride loop
  * over the work items of all systems; the launches of a filter are captured
  * into a HIP graph on first use and replayed.  Limits: at most 1024 systems, at
- * most 8 atoms (32 projectors) per system, FFT edges up to 96, S = I (no Q). */
+ * most 256 atoms per system, FFT edges up to 96, S = I (no Q). */
 typedef struct abi_batch_s *abi_batch;
 
 /* Builds the nsys systems of `descs` (as abi_set_system; all with the same
  * precision) and the batch around them.  Errors: ABI_ERR_ARG (nsys out of
- * range, more than 8 atoms in a system, mixed precisions), and those of
+ * range, more than 256 atoms in a system, mixed precisions), and those of
  * abi_set_system. */
 abi_status abi_set_system_batch(const abi_system_desc *descs, int32_t nsys, void *stream,
                                 abi_batch *out);

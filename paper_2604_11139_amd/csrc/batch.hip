@@ -3,17 +3,18 @@
 //
 // The paper batches the bands of one system into one FFT call (section "Batch
 // processing"); here the batch spans systems as well.  One filter step of
-// every system is four launches, each a flat, grid-stride ("persistent") loop
-// over the work items of all systems:
-//   K1 proj   (system, band tile, chunk):   partial sums of C = P^H Y_k;
-//   K1r       (system, band tile):          C' = alpha D C per atom;
+// every system is six launches (the passes once per group of boxes), each a
+// flat, grid-stride ("persistent") loop over the work items of all systems:
+//   K1 proj   (system, band tile, projector tile, chunk): partial sums of C = P^H Y_k;
+//   K1r       (system, 8 bands, projector tile): C' = alpha D C per atom;
 //   K1b expand (system, plane-wave tile, band tile): E = P C';
 //   K2 pass A (system, band, i3 group):     sphere planes -> inverse xy FFT -> box;
 //   K3 pass B (system, band, i2 group):     z FFT, * V, z FFT;
 //   K4 pass C (system, band, i3 group):     forward xy FFT -> gather, kinetic term,
 //                                           + E, three-term recurrence.
-// The nonlocal products are small here (4-32 projectors): plain FMA kernels
-// tiled over bands, so that P is read once per tile of 32 bands.  Per-system tables,
+// The nonlocal products are small here (a few to a few hundred projectors):
+// plain FMA kernels tiled over bands and over projectors (32 each), so that P
+// is read once per tile of 32 bands.  Per-system tables,
 // per-step pointers and coefficients are read from device descriptors, so the
 // 4 x degree launches are captured once into a HIP graph and replayed.
 #include <algorithm>
@@ -49,17 +50,17 @@ __device__ __forceinline__ C2<T> wave_sum(C2<T> v) {
 }
 
 // K1: partial sums of C = P^H Y_k over one chunk of kBatchKC plane waves for a
-// tile of kBatchBT bands of one system.  The chunk streams through LDS in
-// pieces of KC, so each element of P is read once per band tile instead of
-// once per band; a thread holds 2 projectors x 2 bands, sums a piece in the
-// block's precision and adds the piece sums in FP64.
+// tile of kBatchBT bands and a tile of kBatchPT projectors of one system.  The
+// chunk streams through LDS in pieces of KC, so each element of P is read once
+// per band tile instead of once per band; a thread holds 2 projectors x 2
+// bands, sums a piece in the block's precision and adds the piece sums in FP64.
 template <typename T>
 __global__ __launch_bounds__(256) void bproj_tile_kernel(const BatchSys *__restrict__ sys,
                                                          const BatchStep *__restrict__ step,
                                                          const int64_t *__restrict__ off,
                                                          int nsys) {
   constexpr int KC = sizeof(T) == 4 ? 64 : 32;
-  constexpr int NJ = kBatchMaxProj, NB = kBatchBT;
+  constexpr int NJ = kBatchPT, NB = kBatchBT;
   __shared__ C2<T> ps[KC][NJ + 1];
   __shared__ C2<T> ys[KC][NB + 1];
   const int t = threadIdx.x;
@@ -71,12 +72,13 @@ __global__ __launch_bounds__(256) void bproj_tile_kernel(const BatchSys *__restr
     const BatchStep &st = step[s];
     const int64_t npw = d.npw;
     const int64_t nch = (npw + kBatchKC - 1) / kBatchKC;
-    const int64_t loc = item - off[s];
-    const int64_t bt = loc / nch, ch = loc - bt * nch;
+    const int64_t loc = item - off[s];  // ((band tile) x npt + projector tile) x nch + chunk
+    const int64_t tp = loc / nch, ch = loc - tp * nch;
+    const int64_t bt = tp / d.npt, pj = tp - bt * d.npt;
     const int64_t b0 = bt * NB;
     const int nb = d.nband - b0 < NB ? (int)(d.nband - b0) : NB;
-    const int np = d.nproj;
-    const C2<T> *P = reinterpret_cast<const C2<T> *>(d.P);
+    const int np = d.nproj - (int)pj * NJ < NJ ? d.nproj - (int)pj * NJ : NJ;
+    const C2<T> *P = reinterpret_cast<const C2<T> *>(d.P) + pj * NJ * npw;
     const C2<T> *y = reinterpret_cast<const C2<T> *>(st.yk) + b0 * st.ldk;
     const int64_t kend = (ch + 1) * kBatchKC < npw ? (ch + 1) * kBatchKC : npw;
     double2 tot[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(256) void bproj_tile_kernel(const BatchSys *__restr
         }
       __syncthreads();
     }
-    double2 *part = d.Cpart + (bt * nch + ch) * (NJ * NB);
+    double2 *part = d.Cpart + (tp * nch + ch) * (NJ * NB);
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -122,14 +124,15 @@ __global__ __launch_bounds__(256) void bproj_tile_kernel(const BatchSys *__restr
   }
 }
 
-// K1r: C' = alpha D C for kBatchBR bands of a tile: the chunk sums added in a
-// fixed order (FP64), then the per-atom 4 x 4 D.
+// K1r: C' = alpha D C for kBatchBR bands and one projector tile: the chunk
+// sums added in a fixed order (FP64), then the per-atom 4 x 4 D (a tile holds
+// whole atoms).
 template <typename T>
 __global__ __launch_bounds__(256) void bproj_reduce_kernel(const BatchSys *__restrict__ sys,
                                                            const BatchStep *__restrict__ step,
                                                            const int64_t *__restrict__ off,
                                                            int nsys) {
-  constexpr int NJ = kBatchMaxProj, NB = kBatchBT, NR = kBatchBR;
+  constexpr int NJ = kBatchPT, NB = kBatchBT, NR = kBatchBR;
   __shared__ double2 cs[NJ][NR];
   const int t = threadIdx.x;
   const int64_t total = off[nsys];
@@ -137,12 +140,15 @@ __global__ __launch_bounds__(256) void bproj_reduce_kernel(const BatchSys *__res
     const int s = find_sys(off, nsys, item);
     const BatchSys &d = sys[s];
     const BatchStep &st = step[s];
-    const int64_t b0 = (item - off[s]) * NR;  // first band of the item
+    const int64_t loc = item - off[s];  // (band group) x npt + projector tile
+    const int64_t bg = loc / d.npt, pj = loc - bg * d.npt;
+    const int64_t b0 = bg * NR;  // first band of the item
     const int64_t bt = b0 / NB, bl = b0 - bt * NB;
     const int nb = d.nband - b0 < NR ? (int)(d.nband - b0) : NR;
-    const int np = d.nproj;
+    const int np = d.nproj - (int)pj * NJ < NJ ? d.nproj - (int)pj * NJ : NJ;
+    const int j0 = (int)pj * NJ;
     const int64_t nch = (d.npw + kBatchKC - 1) / kBatchKC;
-    const double2 *part = d.Cpart + bt * nch * (NJ * NB);
+    const double2 *part = d.Cpart + (bt * d.npt + pj) * nch * (NJ * NB);
     for (int e = t; e < NJ * NR; e += 256) {
       const int j = e / NR, b = e % NR;
       double2 v{0, 0};
@@ -156,25 +162,26 @@ __global__ __launch_bounds__(256) void bproj_reduce_kernel(const BatchSys *__res
     __syncthreads();
     C2<T> *cp = reinterpret_cast<C2<T> *>(d.Cp);
     for (int e = t; e < np * nb; e += 256) {
-      const int j = e % np, b = e / np, R = j >> 2, i = j & 3;
-      const double2 *Dm = d.D + 16 * R + 4 * i;
+      const int j = e % np, b = e / np, R = j >> 2, i = j & 3;  // local atom R of the tile
+      const double2 *Dm = d.D + 16 * (j0 / 4 + R) + 4 * i;
       double2 v{0, 0};
 #pragma unroll
       for (int q = 0; q < 4; ++q) v = cadd(v, cmul(Dm[q], cs[4 * R + q][b]));
-      cp[(b0 + b) * np + j] = C2<T>{(T)(st.alpha * v.x), (T)(st.alpha * v.y)};
+      cp[(b0 + b) * d.nproj + j0 + j] = C2<T>{(T)(st.alpha * v.x), (T)(st.alpha * v.y)};
     }
     __syncthreads();
   }
 }
 
 // K1b: E = P C' for kBatchEP plane waves x kBatchBT bands of one system (E:
-// npw x nband, ld npw; pass C adds it).  A thread holds the P row of its plane
-// wave in registers and applies it to every band of the tile.
+// npw x nband, ld npw; pass C adds it).  Per projector tile a thread holds the
+// P row of its plane wave in registers and applies it to every band of the
+// tile; the first tile stores E, the others add to it.
 template <typename T>
 __global__ __launch_bounds__(kBatchEP) void bexpand_kernel(const BatchSys *__restrict__ sys,
                                                            const int64_t *__restrict__ off,
                                                            int nsys) {
-  constexpr int NJ = kBatchMaxProj, NB = kBatchBT;
+  constexpr int NJ = kBatchPT, NB = kBatchBT;
   __shared__ C2<T> cs[NJ][NB];
   const int t = threadIdx.x;
   const int64_t total = off[nsys];
@@ -186,30 +193,33 @@ __global__ __launch_bounds__(kBatchEP) void bexpand_kernel(const BatchSys *__res
     const int64_t pt = loc / nbt, bt = loc - pt * nbt;  // band tiles fastest
     const int64_t b0 = bt * NB;
     const int nb = d.nband - b0 < NB ? (int)(d.nband - b0) : NB;
-    const int np = d.nproj;
     const int64_t npw = d.npw;
-    const C2<T> *cp = reinterpret_cast<const C2<T> *>(d.Cp);
-    for (int e = t; e < np * nb; e += kBatchEP) {
-      const int j = e % np, b = e / np;
-      cs[j][b] = cp[(b0 + b) * np + j];
-    }
-    __syncthreads();
     const int64_t g = pt * kBatchEP + t;
-    if (g < npw) {
-      const C2<T> *P = reinterpret_cast<const C2<T> *>(d.P);
-      C2<T> pr[NJ];
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) pr[j] = j < np ? P[g + (int64_t)j * npw] : C2<T>{0, 0};
-      C2<T> *E = reinterpret_cast<C2<T> *>(d.E) + b0 * npw + g;
-      for (int b = 0; b < nb; ++b) {
-        C2<T> v{0, 0};
-#pragma unroll
-        for (int j = 0; j < NJ; ++j)
-          if (j < np) v = cadd(v, cmul(pr[j], cs[j][b]));
-        E[(int64_t)b * npw] = v;
+    const C2<T> *cp = reinterpret_cast<const C2<T> *>(d.Cp);
+    C2<T> *E = reinterpret_cast<C2<T> *>(d.E) + b0 * npw + g;
+    for (int pj = 0; pj < d.npt; ++pj) {
+      const int j0 = pj * NJ;
+      const int np = d.nproj - j0 < NJ ? d.nproj - j0 : NJ;
+      for (int e = t; e < np * nb; e += kBatchEP) {
+        const int j = e % np, b = e / np;
+        cs[j][b] = cp[(b0 + b) * d.nproj + j0 + j];
       }
+      __syncthreads();
+      if (g < npw) {
+        const C2<T> *P = reinterpret_cast<const C2<T> *>(d.P) + (int64_t)j0 * npw;
+        C2<T> pr[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) pr[j] = j < np ? P[g + (int64_t)j * npw] : C2<T>{0, 0};
+        for (int b = 0; b < nb; ++b) {
+          C2<T> v = pj == 0 ? C2<T>{0, 0} : E[(int64_t)b * npw];
+#pragma unroll
+          for (int j = 0; j < NJ; ++j)
+            if (j < np) v = cadd(v, cmul(pr[j], cs[j][b]));
+          E[(int64_t)b * npw] = v;
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 

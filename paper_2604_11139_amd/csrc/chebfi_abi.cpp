@@ -359,7 +359,8 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
     o_part[i] = tot;
     if (s->nproj > 0)
       tot += al(sizeof(double2) * (size_t)((nband[i] + kBatchBT - 1) / kBatchBT) *
-                (size_t)((s->npw + kBatchKC - 1) / kBatchKC) * kBatchMaxProj * kBatchBT);
+                (size_t)((s->nproj + kBatchPT - 1) / kBatchPT) *
+                (size_t)((s->npw + kBatchKC - 1) / kBatchKC) * kBatchPT * kBatchBT);
     o_slot[i] = tot;
     if (degree >= 2) tot += 2 * al(esz * (size_t)s->npw * nband[i]);
     min_threads = std::max({min_threads, fft_stage_threads(s->plan.d[0], s->n2),
@@ -383,6 +384,7 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
     d.plan = ordered_plan(s->plan, B->radix_desc != 0);
     d.npw = s->npw;
     d.nproj = s->nproj;
+    d.npt = (s->nproj + kBatchPT - 1) / kBatchPT;
     d.box_index = s->d_box;
     d.plane = s->d_plane;
     d.kin = s->d_kin;
@@ -395,11 +397,12 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
     d.Cp = ws + o_cp[i];
     d.E = ws + o_e[i];
     d.Cpart = (double2 *)(ws + o_part[i]);
-    // projector products in tiles of kBatchBT bands (x kBatchKC-wave chunks for
-    // the projection, x kBatchEP plane waves for the expansion)
+    // projector products in tiles of kBatchBT bands (x kBatchPT projectors x
+    // kBatchKC-wave chunks for the projection, x kBatchEP plane waves for the
+    // expansion)
     const int64_t nbt = s->nproj > 0 ? (nband[i] + kBatchBT - 1) / kBatchBT : 0;
-    offP[i + 1] = offP[i] + nbt * ((s->npw + kBatchKC - 1) / kBatchKC);
-    offR[i + 1] = offR[i] + (s->nproj > 0 ? (nband[i] + kBatchBR - 1) / kBatchBR : 0);
+    offP[i + 1] = offP[i] + nbt * d.npt * ((s->npw + kBatchKC - 1) / kBatchKC);
+    offR[i + 1] = offR[i] + (s->nproj > 0 ? (nband[i] + kBatchBR - 1) / kBatchBR * d.npt : 0);
     offE[i + 1] = offE[i] + nbt * ((s->npw + kBatchEP - 1) / kBatchEP);
     // systems on cubic boxes with specialised passes go to their edge group and
     // contribute no items to the runtime-size passes
@@ -1932,8 +1935,8 @@ abi_status abi_set_system_batch(const abi_system_desc *descs, int32_t nsys, void
     CHEBFI_REQUIRE(descs != nullptr && out != nullptr, ABI_ERR_ARG, "descs or out is NULL");
     CHEBFI_REQUIRE(nsys >= 1 && nsys <= kBatchMaxSys, ABI_ERR_ARG, "nsys out of range");
     for (int i = 0; i < nsys; ++i) {
-      CHEBFI_REQUIRE(descs[i].natom >= 0 && 4 * descs[i].natom <= kBatchMaxProj, ABI_ERR_ARG,
-                     "a batched system has more than 8 atoms");
+      CHEBFI_REQUIRE(descs[i].natom >= 0 && descs[i].natom <= kBatchMaxAtoms, ABI_ERR_ARG,
+                     "a batched system has more than 256 atoms");
       CHEBFI_REQUIRE(descs[i].precision == descs[0].precision, ABI_ERR_ARG,
                      "all systems of a batch need the same precision");
       CHEBFI_REQUIRE(descs[i].abi_version < 2 || descs[i].qij == nullptr, ABI_ERR_ARG,

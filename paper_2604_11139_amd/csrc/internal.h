@@ -154,7 +154,9 @@ void reciprocal(const double lattice[9], double B[9]);
 void build_projectors(const abi_system_desc *d, const Sphere &s, std::vector<double> *P);
 
 // ---- batched filter over many systems ---------------------------------------
-constexpr int kBatchMaxProj = 32;  // projectors per system in the batched path (8 atoms)
+constexpr int kBatchPT = 32;       // projectors per tile of the batched projector products
+                                   // (8 atoms: no atom's 4 projectors straddle two tiles)
+constexpr int kBatchMaxAtoms = 256; // atoms per system in the batched path
 constexpr int kBatchBT = 32;       // bands per tile of the batched projector products
 constexpr int kBatchEP = 256;      // plane waves per tile of the batched expansion
 constexpr int kBatchKC = 256;      // plane waves per partial sum of the batched projection
@@ -166,6 +168,7 @@ struct BatchSys {
   BoxPlan plan;               // radix order chosen for the batch
   int64_t npw = 0;
   int nproj = 0;
+  int npt = 0;                // projector tiles of kBatchPT
   const int32_t *box_index = nullptr;
   const int32_t *plane = nullptr;
   const double *kin = nullptr;
@@ -177,7 +180,7 @@ struct BatchSys {
   void *box = nullptr;        // nband boxes
   void *Cp = nullptr;         // nproj x nband
   void *E = nullptr;          // npw x nband (ld npw): P C' of the current step
-  double2 *Cpart = nullptr;   // per band tile, per plane-wave chunk: P^H Y_k partial sums
+  double2 *Cpart = nullptr;   // per band tile, projector tile, plane-wave chunk: P^H Y_k partials
 };
 
 // Per (filter step, system): Out = alpha (H - cshift) Y_k - beta Y_prev.

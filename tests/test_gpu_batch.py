@@ -14,7 +14,9 @@ for that system:
 * graph replays (with fresh output tensors and eager work between them) equal
   the eager launches bitwise; the autotuned launch shape gives the same
   result bitwise as well as a valid choice;
-* argument errors: too many atoms, Y aliasing X, mixed dtypes.
+* systems of 9 and 20 atoms (more than one tile of 32 projectors) against
+  the oracle and the single-system filter;
+* argument errors: too many atoms (257), Y aliasing X, mixed dtypes.
 """
 import functools
 
@@ -90,6 +92,55 @@ def test_batch_equals_single_system_fp64():
             assert col_rel_err(to_host(Yd[i]), to_host(ref)) <= 1e-12, i
 
 
+@functools.lru_cache(maxsize=None)
+def _many_atom_case():
+    """Systems with more than one tile of 32 projectors: 9 atoms (2 tiles, the
+    second with one atom) on a 20^3 box (runtime-size passes), 20 atoms (3
+    tiles) on a 27^3 box with a k-point offset (specialised passes), beside a
+    3-atom system on a 24^3 box."""
+    systems = [W.make_system(5101, a=10.0, ecut=8.0, n=20, natom=9, nband=40, degree=DEGREE),
+               W.make_system(5102, a=11.0, ecut=8.0, n=27, natom=20, nband=33, degree=DEGREE,
+                             kpt_red=(0.1, 0.2, 0.3)),
+               W.make_system(5103, a=9.0, ecut=8.0, n=24, natom=3, nband=16, degree=DEGREE)]
+    Hs = [O.Hamiltonian.from_system(s) for s in systems]
+    Xs = [W.random_block(H.npw, s.nband, s.tag) for s, H in zip(systems, Hs)]
+    bounds = [O.filter_bounds(H, X, W.random_vector(H.npw, s.tag))
+              for s, H, X in zip(systems, Hs, Xs)]
+    return systems, Hs, Xs, bounds
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_batch_many_atoms_matches_oracle(precision):
+    import torch
+    systems, Hs, Xs, bounds = _many_atom_case()
+    assert [s.natom for s in systems] == [9, 20, 3]
+    mixed = precision == "mixed"
+    prec = B.ABI_PREC_MIXED if mixed else B.ABI_PREC_FP64
+    dt = torch.complex64 if mixed else torch.complex128
+    with B.Batch(systems, precision=prec) as g:
+        Xd = [to_dev(X).to(dt) for X in Xs]
+        got = [Y.cpu().numpy() for Y in g.cheb_filter(Xd, DEGREE, bounds)]
+    tol = 5e-6 * DEGREE if mixed else 1e-9
+    for i, (H, X, bd) in enumerate(zip(Hs, Xs, bounds)):
+        cols = _cols(X.shape[1])
+        Xs_ = X[:, cols]
+        if mixed:
+            Xs_ = Xs_.astype(np.complex64).astype(np.complex128)
+        ref = O.cheb_filter(H, Xs_, DEGREE, *bd)
+        err = col_rel_err(got[i][cols].T.astype(np.complex128), ref)
+        assert err <= tol, (i, err)
+
+
+def test_batch_many_atoms_equals_single_system_fp64():
+    systems, Hs, Xs, bounds = _many_atom_case()
+    with B.Batch(systems, precision=B.ABI_PREC_FP64) as g:
+        Xd = [to_dev(X) for X in Xs]
+        Yd = g.cheb_filter(Xd, DEGREE, bounds)
+        for i, m in enumerate(g.systems):
+            ref = m.cheb_filter(Xd[i], DEGREE, *bounds[i])
+            assert col_rel_err(to_host(Yd[i]), to_host(ref)) <= 1e-12, i
+
+
 def test_graph_replays_equal_eager():
     import torch
     systems, Hs, Xs, bounds = _case()
@@ -139,7 +190,7 @@ def test_autotune_keeps_results():
 def test_batch_argument_errors():
     import torch
     systems, Hs, Xs, bounds = _case()
-    big = W.make_system(4100, a=12.0, ecut=6.0, n=36, natom=9, nband=8)
+    big = W.make_system(4100, a=40.0, ecut=2.0, n=24, natom=257, nband=8)
     with pytest.raises(B.ChebfiError) as ei:
         B.Batch([systems[0], big], precision=B.ABI_PREC_MIXED)
     assert ei.value.code == B.ABI_ERR_ARG
