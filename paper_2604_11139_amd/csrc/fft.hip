@@ -281,61 +281,58 @@ __global__ __launch_bounds__(kCT) void cpass_a_kernel(const C2<T> *__restrict__ 
   }
   __syncthreads();
   cfft<T, N, 0, 1, N, 1, LD, +1>(buf, tw);  // x: N pencils of stride-1 elements
-  cfft<T, N, 0, 1, N, LD, 1, +1>(buf, tw);  // y
+  // y: pencil i1, element i2; the last stage writes the box plane
   C2<T> *dst = box + (int64_t)bl * NXY * N + off;
-  for (int i = threadIdx.x; i < NXY; i += kCT) dst[i] = buf[i + i / N];
+  auto ldm = [&](int pa, int e) { return buf[pa + e * LD]; };
+  auto stm = [&](int pa, int e, C2<T> v) { buf[pa + e * LD] = v; };
+  auto stg = [&](int pa, int e, C2<T> v) { dst[pa + e * N] = v; };
+  cfft_io<T, N, 0, 1, N, +1, true, false>(tw, ldm, stg, ldm, stm);
 }
 
 template <typename T, typename VT, int N>
 __global__ __launch_bounds__(kCT) void cpass_b_kernel(C2<T> *__restrict__ box,
                                                       const VT *__restrict__ V,
                                                       const double2 *__restrict__ twg) {
-  constexpr int NXZ = N * N, LD = N + 1;
+  constexpr int LD = N + 1;
   __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
   const int i2 = blockIdx.x;
   const int bl = blockIdx.y;
   for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(twg[2 * kMaxN + i]);
-  C2<T> *src = box + (int64_t)bl * N * N * N;
-  for (int i = threadIdx.x; i < NXZ; i += kCT) {
-    const int i1 = i % N, i3 = i / N;
-    buf[i3 * LD + i1] = src[i1 + N * (i2 + N * i3)];
-  }
   __syncthreads();
-  cfft<T, N, 0, 1, N, LD, 1, +1>(buf, tw);
-  for (int i = threadIdx.x; i < NXZ; i += kCT) {
-    const int i1 = i % N, i3 = i / N;
-    buf[i3 * LD + i1] = cscale(buf[i3 * LD + i1], (T)V[i1 + N * (i2 + N * i3)]);
-  }
-  __syncthreads();
-  cfft<T, N, 0, 1, N, LD, 1, -1>(buf, tw);
-  for (int i = threadIdx.x; i < NXZ; i += kCT) {
-    const int i1 = i % N, i3 = i / N;
-    src[i1 + N * (i2 + N * i3)] = buf[i3 * LD + i1];
-  }
+  // z transforms of the slab (pencil i1, element i3): the first stage reads the
+  // box, the forward transform's last stage applies V, the inverse's last
+  // stage writes the box
+  C2<T> *src = box + (int64_t)bl * N * N * N + (int64_t)N * i2;
+  const VT *v = V + (int64_t)N * i2;
+  constexpr int64_t ZS = (int64_t)N * N;
+  auto ldm = [&](int pa, int e) { return buf[pa + e * LD]; };
+  auto stm = [&](int pa, int e, C2<T> x) { buf[pa + e * LD] = x; };
+  auto ldg = [&](int pa, int e) { return src[pa + e * ZS]; };
+  auto stg = [&](int pa, int e, C2<T> x) { src[pa + e * ZS] = x; };
+  auto stv = [&](int pa, int e, C2<T> x) { buf[pa + e * LD] = cscale(x, (T)v[pa + e * ZS]); };
+  cfft_io<T, N, 0, 1, N, +1, false, true>(tw, ldg, stv, ldm, stm);
+  cfft_io<T, N, 0, 1, N, -1, true, false>(tw, ldm, stg, ldm, stm);
 }
 
 // z-inverse FFT only (the box then holds the bands in real space).
 template <typename T, int N>
 __global__ __launch_bounds__(kCT) void cpass_b_inv_kernel(C2<T> *__restrict__ box,
                                                           const double2 *__restrict__ twg) {
-  constexpr int NXZ = N * N, LD = N + 1;
+  constexpr int LD = N + 1;
   __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
   const int i2 = blockIdx.x;
   const int bl = blockIdx.y;
   for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(twg[2 * kMaxN + i]);
-  C2<T> *src = box + (int64_t)bl * N * N * N;
-  for (int i = threadIdx.x; i < NXZ; i += kCT) {
-    const int i1 = i % N, i3 = i / N;
-    buf[i3 * LD + i1] = src[i1 + N * (i2 + N * i3)];
-  }
   __syncthreads();
-  cfft<T, N, 0, 1, N, LD, 1, +1>(buf, tw);
-  for (int i = threadIdx.x; i < NXZ; i += kCT) {
-    const int i1 = i % N, i3 = i / N;
-    src[i1 + N * (i2 + N * i3)] = buf[i3 * LD + i1];
-  }
+  C2<T> *src = box + (int64_t)bl * N * N * N + (int64_t)N * i2;
+  constexpr int64_t ZS = (int64_t)N * N;
+  auto ldm = [&](int pa, int e) { return buf[pa + e * LD]; };
+  auto stm = [&](int pa, int e, C2<T> x) { buf[pa + e * LD] = x; };
+  auto ldg = [&](int pa, int e) { return src[pa + e * ZS]; };
+  auto stg = [&](int pa, int e, C2<T> x) { src[pa + e * ZS] = x; };
+  cfft_io<T, N, 0, 1, N, +1, false, false>(tw, ldg, stg, ldm, stm);
 }
 
 // Adjoint pass B: z-inverse of the adjoint band, Re[conj(adjoint) * forward]
@@ -346,33 +343,31 @@ __global__ __launch_bounds__(kCT) void cpass_b_adj_kernel(C2<T> *__restrict__ bo
                                                           C2<T> *__restrict__ fwd,
                                                           const VT *__restrict__ V,
                                                           const double2 *__restrict__ twg) {
-  constexpr int NXZ = N * N, LD = N + 1;
+  constexpr int LD = N + 1;
   __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
   const int i2 = blockIdx.x;
   const int bl = blockIdx.y;
   for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(twg[2 * kMaxN + i]);
-  C2<T> *src = box + (int64_t)bl * N * N * N;
-  C2<T> *fw = fwd + (int64_t)bl * N * N * N;
-  for (int i = threadIdx.x; i < NXZ; i += kCT) {
-    const int i1 = i % N, i3 = i / N;
-    buf[i3 * LD + i1] = src[i1 + N * (i2 + N * i3)];
-  }
   __syncthreads();
-  cfft<T, N, 0, 1, N, LD, 1, +1>(buf, tw);
-  for (int i = threadIdx.x; i < NXZ; i += kCT) {
-    const int i1 = i % N, i3 = i / N;
-    const int64_t r = i1 + N * (i2 + N * i3);
-    const C2<T> a = buf[i3 * LD + i1], y = fw[r];
+  const int64_t o = (int64_t)bl * N * N * N + (int64_t)N * i2;
+  C2<T> *src = box + o;
+  C2<T> *fw = fwd + o;
+  const VT *v = V + (int64_t)N * i2;
+  constexpr int64_t ZS = (int64_t)N * N;
+  auto ldm = [&](int pa, int e) { return buf[pa + e * LD]; };
+  auto stm = [&](int pa, int e, C2<T> x) { buf[pa + e * LD] = x; };
+  auto ldg = [&](int pa, int e) { return src[pa + e * ZS]; };
+  auto stg = [&](int pa, int e, C2<T> x) { src[pa + e * ZS] = x; };
+  // the z-inverse's last stage: Re[conj(a) y] over the forward box, a V into LDS
+  auto stv = [&](int pa, int e, C2<T> a) {
+    const int64_t r = pa + e * ZS;
+    const C2<T> y = fw[r];
     fw[r] = C2<T>{a.x * y.x + a.y * y.y, (T)0};
-    buf[i3 * LD + i1] = cscale(a, (T)V[r]);
-  }
-  __syncthreads();
-  cfft<T, N, 0, 1, N, LD, 1, -1>(buf, tw);
-  for (int i = threadIdx.x; i < NXZ; i += kCT) {
-    const int i1 = i % N, i3 = i / N;
-    src[i1 + N * (i2 + N * i3)] = buf[i3 * LD + i1];
-  }
+    buf[pa + e * LD] = cscale(a, (T)v[r]);
+  };
+  cfft_io<T, N, 0, 1, N, +1, false, true>(tw, ldg, stv, ldm, stm);
+  cfft_io<T, N, 0, 1, N, -1, true, false>(tw, ldm, stg, ldm, stm);
 }
 
 template <typename T, int N>
@@ -394,11 +389,15 @@ __global__ __launch_bounds__(kCT) void cpass_c_kernel(
   const int i3 = blockIdx.x;
   const int bl = blockIdx.y;
   for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(twg[i]);
+  __syncthreads();
   const int off = i3 * NXY;
   const C2<T> *src = box + (int64_t)bl * NXY * N + off;
-  for (int i = threadIdx.x; i < NXY; i += kCT) buf[i + i / N] = src[i];
-  __syncthreads();
-  cfft<T, N, 0, 1, N, LD, 1, -1>(buf, tw);
+  {  // y: pencil i1, element i2; the first stage reads the box plane
+    auto ldm = [&](int pa, int e) { return buf[pa + e * LD]; };
+    auto stm = [&](int pa, int e, C2<T> v) { buf[pa + e * LD] = v; };
+    auto ldg = [&](int pa, int e) { return src[pa + e * N]; };
+    cfft_io<T, N, 0, 1, N, -1, false, true>(tw, ldg, stm, ldm, stm);
+  }
   cfft<T, N, 0, 1, N, 1, LD, -1>(buf, tw);
   const int s0 = plane[i3], s1 = plane[i3 + 1];
   const int64_t b = band0 + bl;

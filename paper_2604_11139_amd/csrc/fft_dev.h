@@ -321,6 +321,80 @@ __device__ __forceinline__ void cfft(C2<T> *buf, const C2<T> *tw) {
   }
 }
 
+// One stage of the same Stockham FFT over NPEN pencils with its inputs taken
+// from ld(pencil, element) and its outputs given to st(pencil, element,
+// value): the first stage of a transform can read straight from global memory
+// and the last one write straight to it (or fuse a pointwise product into its
+// store), saving a pass of the plane through LDS.  SYNC_MID: a barrier
+// between the reads and the writes (needed when both are the same LDS plane).
+template <typename T, int N, int R, int P, int NPEN, int SGN, bool SYNC_MID, class Ld, class St>
+__device__ __forceinline__ void cstage_io(const C2<T> *tw, Ld ld, St st) {
+  constexpr int NBF = N / R;
+  constexpr int TOTAL = NPEN * NBF;
+  constexpr int M = N / (P * R);
+  constexpr int MAXB = (TOTAL + kCT - 1) / kCT;
+  C2<T> y[MAXB][R];
+  int eo[MAXB], pp[MAXB];
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    const int i = threadIdx.x + c * kCT;
+    eo[c] = -1;
+    pp[c] = 0;
+    if (TOTAL % kCT == 0 || i < TOTAL) {
+      const int pa = i % NPEN, bf = i / NPEN;
+      C2<T> x[R];
+#pragma unroll
+      for (int t = 0; t < R; ++t) x[t] = ld(pa, bf + t * NBF);
+      const int k = bf % P;
+      if (P > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) {
+          C2<T> w = tw[t * k * M];
+          if (SGN > 0) w.y = -w.y;
+          x[t] = cmul(x[t], w);
+        }
+      }
+      Dft<T, R>::run(x, SGN);
+#pragma unroll
+      for (int t = 0; t < R; ++t) y[c][t] = x[t];
+      eo[c] = (bf - k) * R + k;
+      pp[c] = pa;
+    }
+  }
+  if (SYNC_MID) __syncthreads();
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    if (TOTAL % kCT == 0 || eo[c] >= 0) {
+#pragma unroll
+      for (int t = 0; t < R; ++t) st(pp[c], eo[c] + t * P, y[c][t]);
+    }
+  }
+}
+
+// A whole transform of NPEN pencils: the first stage reads through ld0 (from
+// LDS if IN_LDS, else from global memory), the last one writes through stl
+// (into LDS if OUT_LDS), the stages between through the LDS accessors ldm /
+// stm.  A barrier follows every stage whose output is in LDS.
+template <typename T, int N, int S, int P, int NPEN, int SGN, bool IN_LDS, bool OUT_LDS, class Ld0,
+          class StL, class LdM, class StM>
+__device__ __forceinline__ void cfft_io(const C2<T> *tw, Ld0 ld0, StL stl, LdM ldm, StM stm) {
+  if constexpr (S < CPlan<N>::ns) {
+    constexpr int R = CPlan<N>::r[S];
+    constexpr bool first = S == 0, last = S + 1 == CPlan<N>::ns;
+    constexpr bool rd = first ? IN_LDS : true, wr = last ? OUT_LDS : true;
+    if constexpr (first && last)
+      cstage_io<T, N, R, P, NPEN, SGN, rd && wr>(tw, ld0, stl);
+    else if constexpr (first)
+      cstage_io<T, N, R, P, NPEN, SGN, rd && wr>(tw, ld0, stm);
+    else if constexpr (last)
+      cstage_io<T, N, R, P, NPEN, SGN, rd && wr>(tw, ldm, stl);
+    else
+      cstage_io<T, N, R, P, NPEN, SGN, true>(tw, ldm, stm);
+    if constexpr (wr) __syncthreads();
+    cfft_io<T, N, S + 1, P * R, NPEN, SGN, IN_LDS, OUT_LDS>(tw, ld0, stl, ldm, stm);
+  }
+}
+
 // Planes (or slabs) of one band that a batched pass keeps in LDS together:
 // about 34 KB of LDS per workgroup, so that four workgroups of kCT threads per
 // CU hold as much box data in flight as the 64^3 passes do.
