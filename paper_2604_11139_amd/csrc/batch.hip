@@ -406,9 +406,14 @@ __global__ __launch_bounds__(kCT) void bcpass_a_kernel(const BatchSys *__restric
     }
     __syncthreads();
     cfft<T, N, 0, 1, NPL * N, 1, LD, +1>(buf, tw);         // x: every row of every plane
-    cfft<T, N, 0, 1, N, LD, 1, +1, NPL, PL>(buf, tw);      // y: the columns of each plane
+    // y: pencil pa = (plane p, column i1), element i2; the last stage writes the box
     C2<T> *dst = reinterpret_cast<C2<T> *>(d.box) + b * (int64_t)NXY * N + off;
-    for (int i = threadIdx.x; i < np3 * NXY; i += kCT) dst[i] = buf[i + i / N];
+    auto ldm = [&](int pa, int e) { return buf[(pa / N) * PL + pa % N + e * LD]; };
+    auto stm = [&](int pa, int e, C2<T> v) { buf[(pa / N) * PL + pa % N + e * LD] = v; };
+    auto stg = [&](int pa, int e, C2<T> v) {
+      if (pa / N < np3) dst[(pa / N) * NXY + pa % N + e * N] = v;
+    };
+    cfft_io<T, N, 0, 1, NPL * N, +1, true, false>(tw, ldm, stg, ldm, stm);
     __syncthreads();
   }
 }
@@ -422,38 +427,35 @@ __global__ __launch_bounds__(kCT) void bcpass_b_kernel(const BatchSys *__restric
   __shared__ C2<T> buf[NPL * PL];
   __shared__ C2<T> tw[N];
   const int64_t total = goff[gns];
+  if ((int64_t)blockIdx.x >= total) return;
+  // the twiddles depend on N only (the same for every system of the group)
+  for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(sys[gsys[0]].tw[2 * kMaxN + i]);
+  __syncthreads();
+  constexpr int64_t ZS = (int64_t)N * N;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     int64_t b;
     int g;
     const int s = group_item(gsys, goff, gns, item, G, &b, &g);
     const int i20 = g * NPL, np2 = N - i20 < NPL ? N - i20 : NPL;
     const BatchSys &d = sys[s];
-    for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(d.tw[2 * kMaxN + i]);
     // slabs i20 .. i20 + np2 - 1: for each i3 their rows are one contiguous run
-    // of np2 N elements in the box (q = p N + i1 along it)
+    // of np2 N elements in the box; pencil pa = p N + i1 is the position along
+    // it, element i3; the forward z transform reads the box and applies V in
+    // its last stage, the inverse's last stage writes the box
     C2<T> *src = reinterpret_cast<C2<T> *>(d.box) + b * (int64_t)N * N * N + (int64_t)i20 * N;
     const T *V = reinterpret_cast<const T *>(d.V) + (int64_t)i20 * N;
     const int run = np2 * N;
-    for (int i = threadIdx.x; i < run * N; i += kCT) {
-      const int q = i % run, i3 = i / run;
-      const int p = q / N, i1 = q - p * N;
-      buf[p * PL + i3 * LD + i1] = src[q + N * N * i3];
-    }
-    __syncthreads();
-    cfft<T, N, 0, 1, N, LD, 1, +1, NPL, PL>(buf, tw);
-    for (int i = threadIdx.x; i < run * N; i += kCT) {
-      const int q = i % run, i3 = i / run;
-      const int p = q / N, i1 = q - p * N;
-      const int o = p * PL + i3 * LD + i1;
-      buf[o] = cscale(buf[o], V[q + N * N * i3]);
-    }
-    __syncthreads();
-    cfft<T, N, 0, 1, N, LD, 1, -1, NPL, PL>(buf, tw);
-    for (int i = threadIdx.x; i < run * N; i += kCT) {
-      const int q = i % run, i3 = i / run;
-      const int p = q / N, i1 = q - p * N;
-      src[q + N * N * i3] = buf[p * PL + i3 * LD + i1];
-    }
+    auto ldm = [&](int pa, int e) { return buf[(pa / N) * PL + pa % N + e * LD]; };
+    auto stm = [&](int pa, int e, C2<T> v) { buf[(pa / N) * PL + pa % N + e * LD] = v; };
+    auto ldg = [&](int pa, int e) { return pa < run ? src[pa + e * ZS] : C2<T>{0, 0}; };
+    auto stv = [&](int pa, int e, C2<T> v) {
+      buf[(pa / N) * PL + pa % N + e * LD] = pa < run ? cscale(v, V[pa + e * ZS]) : v;
+    };
+    auto stg = [&](int pa, int e, C2<T> v) {
+      if (pa < run) src[pa + e * ZS] = v;
+    };
+    cfft_io<T, N, 0, 1, NPL * N, +1, false, true>(tw, ldg, stv, ldm, stm);
+    cfft_io<T, N, 0, 1, NPL * N, -1, true, false>(tw, ldm, stg, ldm, stm);
     __syncthreads();
   }
 }
@@ -468,6 +470,10 @@ __global__ __launch_bounds__(kCT) void bcpass_c_kernel(const BatchSys *__restric
   __shared__ C2<T> buf[NPL * PL];
   __shared__ C2<T> tw[N];
   const int64_t total = goff[gns];
+  if ((int64_t)blockIdx.x >= total) return;
+  // the twiddles depend on N only (the same for every system of the group)
+  for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(sys[gsys[0]].tw[i]);
+  __syncthreads();
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     int64_t b;
     int g;
@@ -476,12 +482,16 @@ __global__ __launch_bounds__(kCT) void bcpass_c_kernel(const BatchSys *__restric
     const BatchSys &d = sys[s];
     const BatchStep &st = step[s];
     const int np = d.nproj;
-    for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(d.tw[i]);
     const int off = i30 * NXY;
     const C2<T> *src = reinterpret_cast<const C2<T> *>(d.box) + b * (int64_t)NXY * N + off;
-    for (int i = threadIdx.x; i < np3 * NXY; i += kCT) buf[i + i / N] = src[i];
-    __syncthreads();
-    cfft<T, N, 0, 1, N, LD, 1, -1, NPL, PL>(buf, tw);      // y: the columns of each plane
+    {  // y: pencil pa = (plane p, column i1), element i2; the first stage reads the box
+      auto ldm = [&](int pa, int e) { return buf[(pa / N) * PL + pa % N + e * LD]; };
+      auto stm = [&](int pa, int e, C2<T> v) { buf[(pa / N) * PL + pa % N + e * LD] = v; };
+      auto ldg = [&](int pa, int e) {
+        return pa / N < np3 ? src[(pa / N) * NXY + pa % N + e * N] : C2<T>{0, 0};
+      };
+      cfft_io<T, N, 0, 1, NPL * N, -1, false, true>(tw, ldg, stm, ldm, stm);
+    }
     cfft<T, N, 0, 1, NPL * N, 1, LD, -1>(buf, tw);         // x: every row of every plane
     const int s0 = d.plane[i30], s1 = d.plane[i30 + np3];
     const C2<T> *yk = reinterpret_cast<const C2<T> *>(st.yk) + b * st.ldk;
