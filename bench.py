@@ -90,12 +90,24 @@ EXPAND_KERNELS = {
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_config3_mixed.md")
 
 
+def kernel_source_sha(src):
+    """SHA-256 over a kernel source file and every header of the library's
+    sources (in name order), so that a change to either marks counters taken
+    before it as stale."""
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2604_11139_amd", "csrc")
+    h = hashlib.sha256()
+    for path in [os.path.join(csrc, src)] + sorted(glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(open(path, "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(cls):
     """HBM bytes per launch of the class's kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
     for a plain device copy of known size), or None if there is none or the
     kernel's source has changed since the counters were taken."""
-    import hashlib
     import re
     if cls not in CLASS_KERNELS or not os.path.exists(COUNTERS_FILE):
         return None
@@ -104,9 +116,7 @@ def measured_traffic(cls):
         return None
     data = json.loads(m.group(1))
     kname, src = CLASS_KERNELS[cls]
-    path = os.path.join(ROOT, "paper_2604_11139_amd", "csrc", src)
-    sha = hashlib.sha256(open(path, "rb").read()).hexdigest()
-    if data.get("source_sha256", {}).get(src) != sha:
+    if data.get("source_sha256", {}).get(src) != kernel_source_sha(src):
         return None
     k = data.get("kernels", {}).get(kname)
     if not k:
