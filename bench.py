@@ -80,6 +80,8 @@ PROJ_KERNELS = {
     14: "zgemm_dl_kernel<128, 128, 2, 4, true, true, true, true, false, 0>",
     11: "zgemm_dl_kernel<128, 128, 2, 4, true, true, true, false, false, 0>",
     4: "zgemm_pl2_kernel<128, 128, 2, 4, true, true, 1, true>",
+    15: "zgemm_dl_kernel<128, 128, 2, 4, true, true, false, true, false, 0>",
+    16: "zgemm_dl_kernel<128, 128, 4, 2, true, true, false, true, false, 0>",
 }
 EXPAND_KERNELS = {
     15: "zgemm_dl_kernel<128, 128, 2, 4, false, false, false, true, true, 0>",

@@ -461,7 +461,11 @@ abi_status abi_apply_H_noalloc(abi_system sys, const void *X, void *HX, int64_t 
  *                      planes made by a split pass; 4 register-staged 128 x 128
  *                      reading the complex64 block; 9..14 direct-to-LDS tiles
  *                      reading the block (14, the default: eight waves with
- *                      scheduled fragment reads)
+ *                      scheduled fragment reads); 15, 16: the direct-to-LDS
+ *                      tile of 14 (2 x 4 / 4 x 2 waves) on bf16 planes, which
+ *                      inside a filter the previous step's last FFT pass writes
+ *                      (a split pass makes them otherwise; a no-allocation call
+ *                      uses 14)
  *   ABI_TUNE_EXPAND    split-BF16 expansion P C': 0..6 register-staged tiles,
  *                      7..14 direct-to-LDS tiles (see gemm.hip), 15 the persistent
  *                      direct-to-LDS 128 x 128 tile (default)

@@ -846,8 +846,16 @@ void cheb_filter_impl(abi_system s, const void *X, const void *HX, void *Y, int6
     auto run = [&](hipStream_t q, const double *dc) {
       struct CoefScope {
         abi_system_s *s;
-        ~CoefScope() { s->coef_dev = nullptr; }
+        ~CoefScope() {
+          s->coef_dev = nullptr;
+          s->pl_chain = false;
+          s->pl_have = nullptr;
+        }
       } scope_c{s};
+      // each step's last FFT pass writes the bf16 planes of its output for the
+      // next step's projection (variants that read planes)
+      s->pl_chain = true;
+      s->pl_have = nullptr;
       // Y_1 = (s1/e)(H - c) X
       s->coef_dev = dc;
       if (HX)
@@ -1650,7 +1658,7 @@ abi_status abi_set_tuning(abi_system s, int32_t param, int32_t value) {
     switch (param) {
       case ABI_TUNE_PROJ:
         CHEBFI_REQUIRE(mixed, ABI_ERR_STATE, "split-BF16 variants need a mixed handle");
-        CHEBFI_REQUIRE(value >= 0 && value <= 14, ABI_ERR_ARG, "projection variant out of range");
+        CHEBFI_REQUIRE(value >= 0 && value <= 16, ABI_ERR_ARG, "projection variant out of range");
         s->pl_proj = value;
         break;
       case ABI_TUNE_EXPAND:
@@ -1795,7 +1803,7 @@ abi_status abi_autotune(abi_system s, const void *X, int64_t nband, int64_t ld, 
       TuneChoice c;
       if (it != all.end() && cache_parse(it->second, &c) && c.fft_batch >= 1 &&
           c.fft_batch <= 4096 && (c.overlap == 0 || c.overlap == 1) &&
-          (!split_bf16 || (c.proj >= 0 && c.proj <= 14 && c.expand >= 0 && c.expand <= 15))) {
+          (!split_bf16 || (c.proj >= 0 && c.proj <= 16 && c.expand >= 0 && c.expand <= 15))) {
         apply(c);
         if (from_cache) *from_cache = 1;
         return;
@@ -1809,8 +1817,18 @@ abi_status abi_autotune(abi_system s, const void *X, int64_t nband, int64_t ld, 
     hipEvent_t e0, e1;
     CHEBFI_HIP(hipEventCreate(&e0));
     CHEBFI_HIP(hipEventCreate(&e1));
+    // a chained-planes projection is timed as inside a filter (planes present)
+    struct ChainScope {
+      abi_system_s *s;
+      ~ChainScope() {
+        s->pl_chain = false;
+        s->pl_assume = false;
+        s->pl_have = nullptr;
+      }
+    } chain_scope{s};
     auto timed = [&](const TuneChoice &c) {
       apply(c);
+      s->pl_chain = s->pl_assume = split_bf16 && c.proj >= 15;
       apply_core(s, X, ld, nullptr, 0, HX, s->npw, nband, 1.0, 0.0, 0.0, st, dtype);
       float best = 1e30f;
       for (int r = 0; r < 3; ++r) {
@@ -1844,7 +1862,7 @@ abi_status abi_autotune(abi_system s, const void *X, int64_t nband, int64_t ld, 
         }
       };
       if (split_bf16) {
-        sweep(&TuneChoice::proj, {14, 11, 4});
+        sweep(&TuneChoice::proj, {14, 15, 11, 4});
         sweep(&TuneChoice::expand, {15, 13, 9, 6});
       }
       const int fb = cur.fft_batch;

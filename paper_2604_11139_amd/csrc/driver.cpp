@@ -18,23 +18,32 @@
 namespace chebfi {
 namespace {
 
-// Projection variants 4 and 9..10 read the complex64 block itself (split into
-// bf16 planes while staged); the others read planes made by a separate pass.
-static bool proj_reads_block(int variant) { return variant == 4 || variant >= 9; }
+// Projection variants 4 and 9..14 read the complex64 block itself (split into
+// bf16 planes while staged); the others read planes made by a separate pass
+// (15 and 16: the pipelined direct-to-LDS tiles of 2 x 4 and 4 x 2 waves).
+static bool proj_reads_block(int variant) { return variant == 4 || (variant >= 9 && variant <= 14); }
+static int proj_planes_variant(int variant) { return variant >= 15 ? variant - 2 : variant; }
 
 }  // namespace
 
 int mixed_proj_splits(abi_system_s *s, int64_t nband) {
-  // 9..12 share the 128 x 128 tile of planes variant 7, 13 the 128 x 256 one of 12
-  const int v = s->pl_proj == 13 ? 12 : s->pl_proj >= 9 ? 7 : s->pl_proj;  // 14: as 9
+  // 9..12 share the 128 x 128 tile of planes variant 7, 13 the 128 x 256 one of
+  // 12, 14..16 the 128 x 128 one
+  const int v = s->pl_proj == 13 ? 12 : s->pl_proj >= 9 ? 7 : s->pl_proj;
   return proj_planes_splits(v, s->nproj, nband, s->npw);
 }
 
+bool proj_chains_planes(const abi_system_s *s) {
+  return s->pl_proj >= 15 && s->mixed_gemm == 0 && s->nproj > 0;
+}
+
 void mixed_project(abi_system_s *s, const void *X, int64_t ldx, int64_t nband, void *part,
-                   int splits, hipStream_t st) {
+                   int splits, hipStream_t st, bool have_planes) {
   const int64_t npw = s->npw;
   const int nproj = s->nproj;
-  const int v = s->pl_proj;
+  // a no-allocation call keeps to the block-reading tile (no planes buffer in
+  // the scratch array); same tile and K split as 15
+  const int v = (g_scratch_arena && s->pl_proj >= 15) ? 14 : s->pl_proj;
   const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
   if (proj_reads_block(v)) {
     const int tok = s->prof.begin(PROF_PROJ, flops, st);
@@ -44,12 +53,14 @@ void mixed_project(abi_system_s *s, const void *X, int64_t ldx, int64_t nband, v
     return;
   }
   void *xpl = s->planes.get(8 * (size_t)s->ldPA * nband);
-  const int tk = s->prof.begin(PROF_SPLIT, 16.0 * (double)npw * (double)nband, st);
-  split_planes(npw, nband, X, ldx, xpl, s->ldPA, st);
-  s->prof.end(tk, st);
+  if (!have_planes) {
+    const int tk = s->prof.begin(PROF_SPLIT, 16.0 * (double)npw * (double)nband, st);
+    split_planes(npw, nband, X, ldx, xpl, s->ldPA, st);
+    s->prof.end(tk, st);
+  }
   const int tok = s->prof.begin(PROF_PROJ, flops, st);
   proj_gemm_planes(nproj, nband, npw, s->d_PA, s->ldPA, (int64_t)nproj * s->ldPA, xpl, s->ldPA,
-                   s->ldPA * nband, part, splits, st, v);
+                   s->ldPA * nband, part, splits, st, proj_planes_variant(v));
   s->prof.end(tok, st);
 }
 
@@ -69,7 +80,7 @@ namespace {
 // mixed_gemm = 1), FP32 partials.
 template <typename T>
 int project_t(abi_system_s *s, const void *X, int64_t ldx, int64_t nband, hipStream_t st,
-              C2<T> **part_out) {
+              C2<T> **part_out, bool have_planes = false) {
   typedef C2<T> V2;
   const bool fp32 = std::is_same<T, float>::value;
   const void *P = fp32 ? (const void *)s->d_Pf : (const void *)s->d_P;
@@ -84,7 +95,7 @@ int project_t(abi_system_s *s, const void *X, int64_t ldx, int64_t nband, hipStr
   const double flops = 8.0 * (double)nproj * (double)npw * (double)nband;
   // the split-BF16 products time themselves (a planes variant's split pass apart)
   if (planes) {
-    mixed_project(s, X, ldx, nband, cpart, splits, st);
+    mixed_project(s, X, ldx, nband, cpart, splits, st, have_planes);
     *part_out = cpart;
     return splits;
   }
@@ -137,7 +148,7 @@ void expand_t(abi_system_s *s, const C2<T> *cprime, void *Out, int64_t ldo, int6
 template <typename T>
 void local_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int64_t ldp,
              void *Out, int64_t ldo, int64_t nband, double alpha, double cshift, double beta,
-             hipStream_t st, const void *E = nullptr, int64_t lde = 0) {
+             hipStream_t st, const void *E = nullptr, int64_t lde = 0, void *ypl = nullptr) {
   typedef C2<T> V2;
   const bool fp32 = std::is_same<T, float>::value;
   const void *V = fp32 ? (const void *)s->d_Vf : (const void *)s->d_V;
@@ -152,7 +163,8 @@ void local_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, int
   for (int64_t b0 = 0; b0 < nband; b0 += fb) {
     const int nb = (int)std::min<int64_t>(fb, nband - b0);
     launch_local_potential<T>(s, X, ldx, Xprev, ldp, Out, ldo, (int)b0, nb, box, V, alpha, cshift,
-                              beta, st, s->prof.on ? &s->prof : nullptr, E, lde);
+                              beta, st, s->prof.on ? &s->prof : nullptr, E, lde, ypl, s->ldPA,
+                              s->ldPA * nband);
   }
 }
 
@@ -175,6 +187,12 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
   // expansion stores E = P C' (no read of the output block) and the last FFT
   // pass adds E while it writes Out
   const bool pre = !side && nproj > 0 && fp32 && s->mixed_gemm == 0;
+  // chained planes: X's planes from the previous step's last pass (or assumed
+  // present while the autotuner times a chained step); this step's last pass
+  // writes Out's (after the projection has read X's from the same buffer)
+  const bool chain = pre && s->pl_chain && proj_chains_planes(s);
+  const bool have_planes = chain && (s->pl_assume || (s->pl_have == X && X != nullptr));
+  s->pl_have = nullptr;
   if (side) {
     CHEBFI_HIP(hipEventRecord(s->ev_fork, st));
     CHEBFI_HIP(hipStreamWaitEvent(s->aux, s->ev_fork, 0));
@@ -186,7 +204,7 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
   if (nproj > 0) {
     // C = P^H X, C' = alpha D C
     V2 *cpart = nullptr;
-    const int splits = project_t<T>(s, X, ldx, nband, st, &cpart);
+    const int splits = project_t<T>(s, X, ldx, nband, st, &cpart, have_planes);
     if (Craw) launch_sum_parts(nproj, nband, cpart, splits, Craw, st, fp32);
     cprime = (V2 *)s->cprime.get(sizeof(V2) * (size_t)nproj * nband);
     const int tok =
@@ -198,7 +216,9 @@ void apply_core_t(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev
   if (pre) {
     void *E = s->expout.get(sizeof(V2) * (size_t)s->npw * nband);
     expand_t<T>(s, cprime, E, s->npw, nband, st, true);  // E = P C'
-    local_t<T>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, st, E, s->npw);
+    void *ypl = chain ? s->planes.get(8 * (size_t)s->ldPA * nband) : nullptr;
+    local_t<T>(s, X, ldx, Xprev, ldp, Out, ldo, nband, alpha, cshift, beta, st, E, s->npw, ypl);
+    if (chain) s->pl_have = Out;
   } else if (nproj > 0) {
     expand_t<T>(s, cprime, Out, ldo, nband, st);  // Out += P C'
   }

@@ -49,9 +49,13 @@ void gen_step(abi_system_s *s, const void *X, int64_t ldx, const void *Xprev, in
 // projection of nband bands; mixed_project: part[z] = P^H X over K chunk z
 // (complex float, splits x nproj x nband); mixed_expand: Out = P C' (or Out +=
 // P C' with accumulate) for complex float C' (nproj x nband, ld nproj).
+// have_planes: X's bf16 planes are already in s->planes (no split pass).
+// proj_chains_planes: the projection variant reads planes that the previous
+// filter step's last FFT pass can write (15, 16).
 int mixed_proj_splits(abi_system_s *s, int64_t nband);
+bool proj_chains_planes(const abi_system_s *s);
 void mixed_project(abi_system_s *s, const void *X, int64_t ldx, int64_t nband, void *part,
-                   int splits, hipStream_t st);
+                   int splits, hipStream_t st, bool have_planes = false);
 void mixed_expand(abi_system_s *s, const void *Cp, void *Out, int64_t ldo, int64_t nband,
                   hipStream_t st, bool accumulate);
 

@@ -29,6 +29,48 @@ namespace chebfi {
 namespace {
 
 // ---- pass A: sphere plane -> inverse xy FFT -> box plane -------------------
+// bf16 planes of the complex64 values a pass writes (the operand layout of the
+// split-BF16 projection: planes re_hi, im_hi, re_lo, im_lo of ps elements each,
+// band b at b * ld): hi = bf16(v) and lo = bf16(v - hi), both rounded to
+// nearest even, the same values as the planes made by a separate split pass.
+struct PlanesOut {
+  unsigned short *p;
+  int64_t ld, ps;
+};
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_float(unsigned short h) {
+  return __uint_as_float(((unsigned)h) << 16);
+}
+// Out[idx] = value(idx) over the sphere rows [s0, s1) with nt threads, and with
+// po.p (T = float) the bf16 planes of each value.  (Pairing neighbouring
+// lanes' planes into 32-bit stores by a shuffle measured slower: the pass is
+// bound by its HBM bytes, which the planes raise by a fifth either way.)
+template <typename T, class F>
+__device__ __forceinline__ void sphere_store(int s0, int s1, int nt, const PlanesOut &po,
+                                             int64_t b, C2<T> *out, F value) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (po.p) {
+      unsigned short *pb = po.p + b * po.ld;
+      for (int idx = s0 + threadIdx.x; idx < s1; idx += nt) {
+        const C2<T> o = value(idx);
+        out[idx] = o;
+        const unsigned short hr = bf16_bits(o.x), hi = bf16_bits(o.y);
+        unsigned short *q = pb + idx;
+        q[0] = hr;
+        q[po.ps] = hi;
+        q[2 * po.ps] = bf16_bits(o.x - bf16_float(hr));
+        q[3 * po.ps] = bf16_bits(o.y - bf16_float(hi));
+      }
+      return;
+    }
+  }
+  for (int idx = s0 + threadIdx.x; idx < s1; idx += nt) out[idx] = value(idx);
+}
+
 template <typename T>
 __global__ __launch_bounds__(512) void pass_a_kernel(const C2<T> *__restrict__ X, int64_t ldx, int band0,
                               const int32_t *__restrict__ box_index,
@@ -108,7 +150,7 @@ __global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ b
                               const C2<T> *__restrict__ Yprev, int64_t ldp,
                               C2<T> *__restrict__ Out, int64_t ldo, T alpha, T cshift, T beta,
                               T scale, const C2<T> *__restrict__ E, int64_t lde,
-                              const double *__restrict__ coef) {
+                              const double *__restrict__ coef, PlanesOut po) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
   if (coef) {  // (alpha, cshift, beta) of this step from device memory (captured filters)
@@ -137,7 +179,7 @@ __global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ b
   const C2<T> *ex = E ? E + b * lde : nullptr;
   if (Yprev != nullptr) {
     const C2<T> *yp = Yprev + b * ldp;
-    for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x) {
+    sphere_store<T>(s0, s1, (int)blockDim.x, po, b, out, [&](int idx) {
       const int e = box_index[idx] - off;
       C2<T> loc = cscale(buf[e + e / n1], scale);
       C2<T> x = yk[idx];
@@ -146,10 +188,10 @@ __global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ b
       C2<T> p = yp[idx];
       C2<T> o{alpha * h.x - beta * p.x, alpha * h.y - beta * p.y};
       if (ex) o = add_rounded(o, ex[idx]);
-      out[idx] = o;
-    }
+      return o;
+    });
   } else {
-    for (int idx = s0 + threadIdx.x; idx < s1; idx += blockDim.x) {
+    sphere_store<T>(s0, s1, (int)blockDim.x, po, b, out, [&](int idx) {
       const int e = box_index[idx] - off;
       C2<T> loc = cscale(buf[e + e / n1], scale);
       C2<T> x = yk[idx];
@@ -157,8 +199,8 @@ __global__ __launch_bounds__(512) void pass_c_kernel(const C2<T> *__restrict__ b
       C2<T> h = cadd(loc, cscale(x, kd));
       C2<T> o = cscale(h, alpha);
       if (ex) o = add_rounded(o, ex[idx]);
-      out[idx] = o;
-    }
+      return o;
+    });
   }
 }
 
@@ -377,7 +419,7 @@ __global__ __launch_bounds__(kCT) void cpass_c_kernel(
     const double *__restrict__ kin, int band0, const C2<T> *__restrict__ Yk, int64_t ldk,
     const C2<T> *__restrict__ Yprev, int64_t ldp, C2<T> *__restrict__ Out, int64_t ldo, T alpha,
     T cshift, T beta, T scale, const C2<T> *__restrict__ E, int64_t lde,
-    const double *__restrict__ coef) {
+    const double *__restrict__ coef, PlanesOut po) {
   constexpr int NXY = N * N, LD = N + 1;
   __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
@@ -406,7 +448,7 @@ __global__ __launch_bounds__(kCT) void cpass_c_kernel(
   const C2<T> *ex = E ? E + b * lde : nullptr;
   if (Yprev != nullptr) {
     const C2<T> *yp = Yprev + b * ldp;
-    for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
+    sphere_store<T>(s0, s1, kCT, po, b, out, [&](int idx) {
       const int e = box_index[idx] - off;
       const C2<T> loc = cscale(buf[e + e / N], scale);
       const C2<T> x = yk[idx];
@@ -415,18 +457,18 @@ __global__ __launch_bounds__(kCT) void cpass_c_kernel(
       const C2<T> p = yp[idx];
       C2<T> o{alpha * h.x - beta * p.x, alpha * h.y - beta * p.y};
       if (ex) o = add_rounded(o, ex[idx]);
-      out[idx] = o;
-    }
+      return o;
+    });
   } else {
-    for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
+    sphere_store<T>(s0, s1, kCT, po, b, out, [&](int idx) {
       const int e = box_index[idx] - off;
       const C2<T> loc = cscale(buf[e + e / N], scale);
       const C2<T> x = yk[idx];
       const T kd = (T)kin[idx] - cshift;
       C2<T> o = cscale(cadd(loc, cscale(x, kd)), alpha);
       if (ex) o = add_rounded(o, ex[idx]);
-      out[idx] = o;
-    }
+      return o;
+    });
   }
 }
 
@@ -434,7 +476,8 @@ template <typename T, int N>
 void launch_cubic(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Yprev,
                   int64_t ldp, void *Out, int64_t ldo, int band0, int nb, void *box, const void *V,
                   double alpha, double cshift, double beta, hipStream_t st, Profiler *prof,
-                  double bytesA, double bytesB, double bytesC, const void *E, int64_t lde) {
+                  double bytesA, double bytesB, double bytesC, const void *E, int64_t lde,
+                  PlanesOut po) {
   typedef C2<T> V2;
   typedef typename std::conditional<std::is_same<T, double>::value, double, float>::type VT;
   const double2 *tw = reinterpret_cast<const double2 *>(s->d_tw);
@@ -455,7 +498,7 @@ void launch_cubic(const abi_system_s *s, const void *Yk, int64_t ldk, const void
                      s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Yk), ldk,
                      reinterpret_cast<const V2 *>(Yprev), ldp, reinterpret_cast<V2 *>(Out), ldo,
                      (T)alpha, (T)cshift, (T)beta, scale, reinterpret_cast<const V2 *>(E), lde,
-                     s->coef_dev);
+                     s->coef_dev, po);
   CHEBFI_HIP(hipGetLastError());
   if (prof) prof->end(tok, st);
 }
@@ -485,7 +528,8 @@ void adjoint_cubic(const abi_system_s *s, const void *Ak1, int64_t lda1, const v
                      s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Ak1), lda1,
                      accumulate ? reinterpret_cast<const V2 *>(Ak) : (const V2 *)nullptr, ldak,
                      reinterpret_cast<V2 *>(Ak), ldak, (T)gamma, (T)cshift, (T)-1, scale,
-                     (const V2 *)nullptr, (int64_t)0, (const double *)nullptr);
+                     (const V2 *)nullptr, (int64_t)0, (const double *)nullptr,
+                     PlanesOut{nullptr, 0, 0});
   CHEBFI_HIP(hipGetLastError());
 }
 
@@ -549,13 +593,13 @@ template <typename T>
 bool try_cubic(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Yprev, int64_t ldp,
                void *Out, int64_t ldo, int band0, int nb, void *box, const void *V, double alpha,
                double cshift, double beta, hipStream_t st, Profiler *prof, double bA, double bB,
-               double bC, const void *E, int64_t lde) {
+               double bC, const void *E, int64_t lde, PlanesOut po) {
   if (s->n1 != s->n2 || s->n1 != s->n3) return false;
   if (s->generic_fft) return false;
 #define CHEBFI_CUBIC(N_)                                                                     \
   case N_:                                                                                   \
     launch_cubic<T, N_>(s, Yk, ldk, Yprev, ldp, Out, ldo, band0, nb, box, V, alpha, cshift,  \
-                        beta, st, prof, bA, bB, bC, E, lde);                                 \
+                        beta, st, prof, bA, bB, bC, E, lde, po);                             \
     return true;
   switch (s->n1) {
     CHEBFI_CUBIC(12)
@@ -590,9 +634,11 @@ template <typename T>
 void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Yprev,
                             int64_t ldp, void *Out, int64_t ldo, int band0, int nb, void *box,
                             const void *V, double alpha, double cshift, double beta,
-                            hipStream_t st, Profiler *prof, const void *E, int64_t lde) {
+                            hipStream_t st, Profiler *prof, const void *E, int64_t lde,
+                            void *ypl, int64_t ldpl, int64_t pspl) {
   using V2 = C2<T>;
   const BoxPlan &plan = s->plan;
+  const PlanesOut po{std::is_same<T, float>::value ? (unsigned short *)ypl : nullptr, ldpl, pspl};
   const int n1 = plan.d[0].n, n2 = plan.d[1].n, n3 = plan.d[2].n;
   const double2 *tw = reinterpret_cast<const double2 *>(s->d_tw);
   const int tA = std::max(stage_threads(plan.d[0], n2), stage_threads(plan.d[1], n1));
@@ -613,7 +659,7 @@ void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, 
   const double bytesB = nb * 2.0 * nbx * es + nbx * (double)sizeof(T);
   const double bytesC = nb * (nbx + np * ((Yprev ? 3.0 : 2.0) + (E ? 1.0 : 0.0))) * es;
   if (try_cubic<T>(s, Yk, ldk, Yprev, ldp, Out, ldo, band0, nb, box, V, alpha, cshift, beta, st,
-                   prof, bytesA, bytesB, bytesC, E, lde))
+                   prof, bytesA, bytesB, bytesC, E, lde, po))
     return;
   int tok = prof ? prof->begin(PROF_FFT_A, bytesA, st) : -1;
   hipLaunchKernelGGL(pass_a_kernel<T>, dim3(n3, nb), dim3(tA), ldsA, st,
@@ -636,7 +682,7 @@ void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, 
                      s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Yk), ldk,
                      reinterpret_cast<const V2 *>(Yprev), ldp, reinterpret_cast<V2 *>(Out), ldo,
                      (T)alpha, (T)cshift, (T)beta, scale, reinterpret_cast<const V2 *>(E), lde,
-                     s->coef_dev);
+                     s->coef_dev, po);
   CHEBFI_HIP(hipGetLastError());
   if (prof) prof->end(tok, st);
 }
@@ -682,7 +728,8 @@ void launch_adjoint_local(const abi_system_s *s, const void *Ak1, int64_t lda1, 
                      s->d_plane, s->d_kin, band0, reinterpret_cast<const V2 *>(Ak1), lda1,
                      accumulate ? reinterpret_cast<const V2 *>(Ak) : (const V2 *)nullptr, ldak,
                      reinterpret_cast<V2 *>(Ak), ldak, (T)gamma, (T)cshift, (T)-1, scale,
-                     (const V2 *)nullptr, (int64_t)0, (const double *)nullptr);
+                     (const V2 *)nullptr, (int64_t)0, (const double *)nullptr,
+                     PlanesOut{nullptr, 0, 0});
   CHEBFI_HIP(hipGetLastError());
 }
 
@@ -729,11 +776,13 @@ template void launch_adjoint_local<float>(const abi_system_s *, const void *, in
 template void launch_local_potential<double>(const abi_system_s *, const void *, int64_t,
                                              const void *, int64_t, void *, int64_t, int, int,
                                              void *, const void *, double, double, double,
-                                             hipStream_t, Profiler *, const void *, int64_t);
+                                             hipStream_t, Profiler *, const void *, int64_t,
+                                             void *, int64_t, int64_t);
 template void launch_local_potential<float>(const abi_system_s *, const void *, int64_t,
                                              const void *, int64_t, void *, int64_t, int, int,
                                              void *, const void *, double, double, double,
-                                             hipStream_t, Profiler *, const void *, int64_t);
+                                             hipStream_t, Profiler *, const void *, int64_t,
+                                             void *, int64_t, int64_t);
 
 int fft_stage_threads(const Plan1D &pl, int npen) { return stage_need(pl, npen); }
 

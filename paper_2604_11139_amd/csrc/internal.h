@@ -260,6 +260,13 @@ struct abi_system_s {
   int mixed_gemm = 0;              // 0: split-BF16 MFMA, 1: FP32 MFMA projector products
   int generic_fft = 0;             // 1: runtime-size FFT passes also for cubic boxes
   int pl_proj = 0, pl_expand = 0;  // tile variants of the split-BF16 products
+  // Chained planes (projection variants 15, 16, inside one filter run): the last
+  // FFT pass of a step also writes the bf16 planes of its output into `planes`,
+  // so that the next step's projection needs no split pass.  pl_have: the block
+  // whose planes `planes` holds (null: none); pl_assume: treat them as present
+  // (the autotuner's timing of a chained step).
+  bool pl_chain = false, pl_assume = false;
+  const void *pl_have = nullptr;
 
   // work buffers
   chebfi::DevBuf box, cpart, cprime, blk1, blk2, blk3, small1, small2, small3, small4, small5, scal;

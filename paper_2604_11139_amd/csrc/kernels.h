@@ -19,12 +19,16 @@ enum Op { OP_N = 0, OP_C = 1 };  // op(X) = X or X^H
 // `box` holds nb boxes; V is double (T = double) or float (T = float).
 // E (optional, ld lde): a block added to Out on the sphere (the projector part
 // of H computed beforehand), with a plain rounded add after the local value.
+// ypl (optional, T = float only): also write Out's bf16 planes there (the
+// layout of split_planes: band b at b * ldpl, plane stride pspl; the padding
+// rows are left as they are).
 template <typename T>
 void launch_local_potential(const abi_system_s *s, const void *Yk, int64_t ldk, const void *Yprev,
                             int64_t ldp, void *Out, int64_t ldo, int band0, int nb, void *box,
                             const void *V, double alpha, double cshift, double beta,
                             hipStream_t st, Profiler *prof = nullptr, const void *E = nullptr,
-                            int64_t lde = 0);
+                            int64_t lde = 0, void *ypl = nullptr, int64_t ldpl = 0,
+                            int64_t pspl = 0);
 
 // Local part of one reverse step of the filter adjoint for bands
 // [band0, band0+nb): dV += gamma/n^3 sum_b Re[conj(Ak1~) Yk~] and

@@ -107,6 +107,31 @@ def test_mixed_filter(name, degree):
     assert col_rel_err(got, ref) <= 5e-6 * degree
 
 
+@pytest.mark.parametrize("name", ["n27", "noncubic"])
+def test_mixed_filter_chained_planes(name):
+    """Projection variants 15 and 16 read the bf16 planes of each step's input,
+    which the previous step's last FFT pass writes (specialised passes on the
+    27^3 box, runtime-size ones on the non-cubic box); the split they write is
+    the one the block-reading variant 14 forms while staging, so the three
+    filters agree to the products' rounding."""
+    import torch
+    H = hamiltonian(name)
+    s = system(name)
+    X = W.random_block(H.npw, 40, 17)
+    a, b, a0 = O.filter_bounds(H, X, W.random_vector(H.npw, s.tag))
+    outs = {}
+    with _mixed(name) as g:
+        for v in (14, 15, 16):
+            g.set_tuning(B.TUNE_PROJ, v)
+            outs[v] = to_host(g.cheb_filter(_c64(X), 6, a, b, a0)).astype(np.complex128)
+            torch.cuda.synchronize()
+    for v in (15, 16):
+        assert np.isfinite(outs[v]).all()
+        err = col_rel_err(outs[v], outs[14])
+        print(f"variant {v} vs 14: {err:.3e}", flush=True)
+        assert err <= 1e-6, (v, err)
+
+
 @pytest.mark.parametrize("name", NAMES)
 def test_mixed_bounds(name):
     H = hamiltonian(name)
