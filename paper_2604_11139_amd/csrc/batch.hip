@@ -361,7 +361,7 @@ __global__ __launch_bounds__(512) void bpass_c_kernel(const BatchSys *__restrict
 // Same three passes as above over the items of the systems listed in gsys,
 // with N, the radix sequence and the plane strides known at compile time (the
 // cubic building blocks).  An item is NPL consecutive planes (pass B: x-z
-// slabs) of one band, stacked in LDS N (N + 1) elements apart, so that a
+// slabs) of one band, stacked in LDS N cld<N>() elements apart, so that a
 // workgroup keeps about as much box data in flight on small boxes as one 64^2
 // plane; G = ceil(N / NPL) items per band (the last may hold fewer planes).
 
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(kCT) void bcpass_a_kernel(const BatchSys *__restric
                                                        const BatchStep *__restrict__ step,
                                                        const int32_t *__restrict__ gsys,
                                                        const int64_t *__restrict__ goff, int gns) {
-  constexpr int NXY = N * N, LD = N + 1, PL = N * LD;
+  constexpr int NXY = N * N, LD = cld<N>(), PL = N * LD;
   constexpr int NPL = cplanes_per_item<T, N>(), G = (N + NPL - 1) / NPL;
   __shared__ C2<T> buf[NPL * PL];
   __shared__ C2<T> tw[N];
@@ -396,13 +396,13 @@ __global__ __launch_bounds__(kCT) void bcpass_a_kernel(const BatchSys *__restric
     for (int i = threadIdx.x; i < NPL * PL; i += kCT) buf[i] = C2<T>{0, 0};
     __syncthreads();
     // the sphere points of planes i30 .. i30 + np3 - 1 are contiguous; element
-    // e of the group (plane p, row r, column c) sits at e + e / N = p PL + r LD + c
+    // e of the group (plane p, row r, column c) sits at (e / N) LD + e % N = p PL + r LD + c
     const int s0 = d.plane[i30], s1 = d.plane[i30 + np3];
     const C2<T> *xb = reinterpret_cast<const C2<T> *>(st.yk) + b * st.ldk;
     const int off = i30 * NXY;
     for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
       const int e = d.box_index[idx] - off;
-      buf[e + e / N] = xb[idx];
+      buf[(e / N) * LD + e % N] = xb[idx];
     }
     __syncthreads();
     cfft<T, N, 0, 1, NPL * N, 1, LD, +1>(buf, tw);         // x: every row of every plane
@@ -422,7 +422,7 @@ template <typename T, int N>
 __global__ __launch_bounds__(kCT) void bcpass_b_kernel(const BatchSys *__restrict__ sys,
                                                        const int32_t *__restrict__ gsys,
                                                        const int64_t *__restrict__ goff, int gns) {
-  constexpr int LD = N + 1, PL = N * LD;
+  constexpr int LD = cld<N>(), PL = N * LD;
   constexpr int NPL = cplanes_per_item<T, N>(), G = (N + NPL - 1) / NPL;
   __shared__ C2<T> buf[NPL * PL];
   __shared__ C2<T> tw[N];
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(kCT) void bcpass_c_kernel(const BatchSys *__restric
                                                        const BatchStep *__restrict__ step,
                                                        const int32_t *__restrict__ gsys,
                                                        const int64_t *__restrict__ goff, int gns) {
-  constexpr int NXY = N * N, LD = N + 1, PL = N * LD;
+  constexpr int NXY = N * N, LD = cld<N>(), PL = N * LD;
   constexpr int NPL = cplanes_per_item<T, N>(), G = (N + NPL - 1) / NPL;
   __shared__ C2<T> buf[NPL * PL];
   __shared__ C2<T> tw[N];
@@ -503,7 +503,7 @@ __global__ __launch_bounds__(kCT) void bcpass_c_kernel(const BatchSys *__restric
     const T scale = (T)(1.0 / ((double)NXY * N));
     for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
       const int e = d.box_index[idx] - off;
-      const C2<T> lc = cscale(buf[e + e / N], scale);
+      const C2<T> lc = cscale(buf[(e / N) * LD + e % N], scale);
       const C2<T> x = yk[idx];
       const T kd = (T)d.kin[idx] - cshift;
       const C2<T> h = cadd(lc, cscale(x, kd));

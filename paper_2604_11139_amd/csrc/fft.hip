@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kCT) void cpass_a_kernel(const C2<T> *__restrict__ 
                                                       const int32_t *__restrict__ plane,
                                                       const double2 *__restrict__ twg,
                                                       C2<T> *__restrict__ box) {
-  constexpr int NXY = N * N, LD = N + 1;
+  constexpr int NXY = N * N, LD = cld<N>();
   __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
   const int i3 = blockIdx.x;
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(kCT) void cpass_a_kernel(const C2<T> *__restrict__ 
   const int off = i3 * NXY;
   for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
     const int e = box_index[idx] - off;
-    buf[e + e / N] = xb[idx];
+    buf[(e / N) * LD + e % N] = xb[idx];
   }
   __syncthreads();
   cfft<T, N, 0, 1, N, 1, LD, +1>(buf, tw);  // x: N pencils of stride-1 elements
@@ -335,7 +335,7 @@ template <typename T, typename VT, int N>
 __global__ __launch_bounds__(kCT) void cpass_b_kernel(C2<T> *__restrict__ box,
                                                       const VT *__restrict__ V,
                                                       const double2 *__restrict__ twg) {
-  constexpr int LD = N + 1;
+  constexpr int LD = cld<N>();
   __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
   const int i2 = blockIdx.x;
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(kCT) void cpass_b_kernel(C2<T> *__restrict__ box,
 template <typename T, int N>
 __global__ __launch_bounds__(kCT) void cpass_b_inv_kernel(C2<T> *__restrict__ box,
                                                           const double2 *__restrict__ twg) {
-  constexpr int LD = N + 1;
+  constexpr int LD = cld<N>();
   __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
   const int i2 = blockIdx.x;
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(kCT) void cpass_b_adj_kernel(C2<T> *__restrict__ bo
                                                           C2<T> *__restrict__ fwd,
                                                           const VT *__restrict__ V,
                                                           const double2 *__restrict__ twg) {
-  constexpr int LD = N + 1;
+  constexpr int LD = cld<N>();
   __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
   const int i2 = blockIdx.x;
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(kCT) void cpass_c_kernel(
     const C2<T> *__restrict__ Yprev, int64_t ldp, C2<T> *__restrict__ Out, int64_t ldo, T alpha,
     T cshift, T beta, T scale, const C2<T> *__restrict__ E, int64_t lde,
     const double *__restrict__ coef, PlanesOut po) {
-  constexpr int NXY = N * N, LD = N + 1;
+  constexpr int NXY = N * N, LD = cld<N>();
   __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
   if (coef) {  // (alpha, cshift, beta) of this step from device memory (captured filters)
@@ -450,7 +450,7 @@ __global__ __launch_bounds__(kCT) void cpass_c_kernel(
     const C2<T> *yp = Yprev + b * ldp;
     sphere_store<T>(s0, s1, kCT, po, b, out, [&](int idx) {
       const int e = box_index[idx] - off;
-      const C2<T> loc = cscale(buf[e + e / N], scale);
+      const C2<T> loc = cscale(buf[(e / N) * LD + e % N], scale);
       const C2<T> x = yk[idx];
       const T kd = (T)kin[idx] - cshift;
       const C2<T> h = cadd(loc, cscale(x, kd));
@@ -462,7 +462,7 @@ __global__ __launch_bounds__(kCT) void cpass_c_kernel(
   } else {
     sphere_store<T>(s0, s1, kCT, po, b, out, [&](int idx) {
       const int e = box_index[idx] - off;
-      const C2<T> loc = cscale(buf[e + e / N], scale);
+      const C2<T> loc = cscale(buf[(e / N) * LD + e % N], scale);
       const C2<T> x = yk[idx];
       const T kd = (T)kin[idx] - cshift;
       C2<T> o = cscale(cadd(loc, cscale(x, kd)), alpha);

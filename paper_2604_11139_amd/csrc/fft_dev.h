@@ -263,6 +263,15 @@ CHEBFI_CPLAN(64, 2, 8, 8, 1)
 
 constexpr int kCT = 512;  // threads of the specialised passes (16 waves per CU per 4 planes)
 
+// LDS row pitch of an N x N plane in the specialised passes: odd, so that the
+// lanes of a wave walking consecutive pencils across rows (8-byte elements,
+// row stride 2 cld dwords) meet every bank pair once: N + 1 for even N, N + 2
+// for odd N (an even pitch such as 46 for N = 45 reaches only 16 banks).
+template <int N>
+constexpr int cld() {
+  return N % 2 ? N + 2 : N + 1;
+}
+
 // NG groups of NPEN pencils (group g's pencils start at g * GS): several
 // planes of one LDS buffer transformed by one pass over all their pencils.
 template <typename T, int N, int R, int P, int NPEN, int ES, int PS, int SGN, int NG = 1,
@@ -400,8 +409,8 @@ __device__ __forceinline__ void cfft_io(const C2<T> *tw, Ld0 ld0, StL stl, LdM l
 // CU hold as much box data in flight as the 64^3 passes do.
 template <typename T, int N>
 constexpr int cplanes_per_item() {
-  return 34000 / (N * (N + 1) * (int)sizeof(C2<T>)) > 1
-             ? 34000 / (N * (N + 1) * (int)sizeof(C2<T>))
+  return 34000 / (N * cld<N>() * (int)sizeof(C2<T>)) > 1
+             ? 34000 / (N * cld<N>() * (int)sizeof(C2<T>))
              : 1;
 }
 
