@@ -392,12 +392,14 @@ __global__ __launch_bounds__(kCT) void bcpass_a_kernel(const BatchSys *__restric
     const int i30 = g * NPL, np3 = N - i30 < NPL ? N - i30 : NPL;
     const BatchSys &d = sys[s];
     const BatchStep &st = step[s];
+    // planes with no sphere points stay unwritten: pass B reads them as zeros
+    const int s0 = d.plane[i30], s1 = d.plane[i30 + np3];
+    if (s0 == s1) continue;
     for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(d.tw[i]);
     for (int i = threadIdx.x; i < NPL * PL; i += kCT) buf[i] = C2<T>{0, 0};
     __syncthreads();
     // the sphere points of planes i30 .. i30 + np3 - 1 are contiguous; element
     // e of the group (plane p, row r, column c) sits at (e / N) LD + e % N = p PL + r LD + c
-    const int s0 = d.plane[i30], s1 = d.plane[i30 + np3];
     const C2<T> *xb = reinterpret_cast<const C2<T> *>(st.yk) + b * st.ldk;
     const int off = i30 * NXY;
     for (int idx = s0 + threadIdx.x; idx < s1; idx += kCT) {
@@ -447,12 +449,18 @@ __global__ __launch_bounds__(kCT) void bcpass_b_kernel(const BatchSys *__restric
     const int run = np2 * N;
     auto ldm = [&](int pa, int e) { return buf[(pa / N) * PL + pa % N + e * LD]; };
     auto stm = [&](int pa, int e, C2<T> v) { buf[(pa / N) * PL + pa % N + e * LD] = v; };
-    auto ldg = [&](int pa, int e) { return pa < run ? src[pa + e * ZS] : C2<T>{0, 0}; };
+    // z-planes without sphere points: zero on input (pass A leaves them
+    // unwritten) and not written on output (pass C does not read them)
+    const uint64_t zocc = d.zocc;
+    auto occ = [&](int e) { return ((zocc >> e) & 1ull) != 0; };
+    auto ldg = [&](int pa, int e) {
+      return (pa < run && occ(e)) ? src[pa + e * ZS] : C2<T>{0, 0};
+    };
     auto stv = [&](int pa, int e, C2<T> v) {
       buf[(pa / N) * PL + pa % N + e * LD] = pa < run ? cscale(v, V[pa + e * ZS]) : v;
     };
     auto stg = [&](int pa, int e, C2<T> v) {
-      if (pa < run) src[pa + e * ZS] = v;
+      if (pa < run && occ(e)) src[pa + e * ZS] = v;
     };
     cfft_io<T, N, 0, 1, NPL * N, +1, false, true>(tw, ldg, stv, ldm, stm);
     cfft_io<T, N, 0, 1, NPL * N, -1, true, false>(tw, ldm, stg, ldm, stm);
@@ -482,6 +490,11 @@ __global__ __launch_bounds__(kCT) void bcpass_c_kernel(const BatchSys *__restric
     const BatchSys &d = sys[s];
     const BatchStep &st = step[s];
     const int np = d.nproj;
+    // no sphere points in these planes: nothing to gather (pass B left them
+    // unwritten; in an item that also holds an occupied plane, such a plane's
+    // values stay within its own 2-D transform and are never gathered)
+    const int s0 = d.plane[i30], s1 = d.plane[i30 + np3];
+    if (s0 == s1) continue;
     const int off = i30 * NXY;
     const C2<T> *src = reinterpret_cast<const C2<T> *>(d.box) + b * (int64_t)NXY * N + off;
     {  // y: pencil pa = (plane p, column i1), element i2; the first stage reads the box
@@ -493,7 +506,6 @@ __global__ __launch_bounds__(kCT) void bcpass_c_kernel(const BatchSys *__restric
       cfft_io<T, N, 0, 1, NPL * N, -1, false, true>(tw, ldg, stm, ldm, stm);
     }
     cfft<T, N, 0, 1, NPL * N, 1, LD, -1>(buf, tw);         // x: every row of every plane
-    const int s0 = d.plane[i30], s1 = d.plane[i30 + np3];
     const C2<T> *yk = reinterpret_cast<const C2<T> *>(st.yk) + b * st.ldk;
     const C2<T> *yp =
         st.yprev ? reinterpret_cast<const C2<T> *>(st.yprev) + b * st.ldp : nullptr;

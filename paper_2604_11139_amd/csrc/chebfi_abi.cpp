@@ -387,6 +387,7 @@ void batch_filter(abi_batch_s *B, const void *const *X, void *const *Y, const in
     d.npt = (s->nproj + kBatchPT - 1) / kBatchPT;
     d.box_index = s->d_box;
     d.plane = s->d_plane;
+    d.zocc = s->zocc;
     d.kin = s->d_kin;
     d.V = fp32 ? (const void *)s->d_Vf : (const void *)s->d_V;
     d.tw = reinterpret_cast<const double2 *>(s->d_tw);
@@ -612,6 +613,12 @@ abi_status abi_set_system(const abi_system_desc *desc, void *stream, abi_system 
         plane[i3] = (int32_t)idx;
       }
       plane[s->n3] = (int32_t)s->npw;
+    }
+    s->zocc = ~0ull;
+    if (s->n3 <= 64) {
+      s->zocc = 0;
+      for (int i3 = 0; i3 < s->n3; ++i3)
+        if (plane[i3] < plane[i3 + 1]) s->zocc |= 1ull << i3;
     }
     std::vector<double> tw(3 * kMaxN * 2, 0.0);
     for (int c = 0; c < 3; ++c) {

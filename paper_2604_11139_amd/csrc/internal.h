@@ -171,6 +171,7 @@ struct BatchSys {
   int npt = 0;                // projector tiles of kBatchPT
   const int32_t *box_index = nullptr;
   const int32_t *plane = nullptr;
+  uint64_t zocc = ~0ull;      // bit i3: z-plane i3 holds sphere points
   const double *kin = nullptr;
   const void *V = nullptr;    // float (complex64 blocks) or double
   const double2 *tw = nullptr;
@@ -239,6 +240,7 @@ struct abi_system_s {
   double *d_kin = nullptr;         // npw
   int32_t *d_box = nullptr;        // npw, box index of each sphere point
   int32_t *d_plane = nullptr;      // n3+1 sphere ranges per i3 plane
+  uint64_t zocc = ~0ull;           // bit i3: z-plane i3 holds sphere points (n3 <= 64)
   double *d_P = nullptr;           // npw x nproj complex (interleaved), ld = npw
   double *d_D = nullptr;           // natom*16 complex, row-major per atom
   double *d_V = nullptr;           // n1*n2*n3
