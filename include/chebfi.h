@@ -506,10 +506,11 @@ abi_status abi_get_tuning(abi_system sys, int32_t param, int32_t *value);
 /* Autotuner (section "Batch processing": FFT plans and tile shapes chosen per
  * problem).  Times H applications of the `nband` bands of X (dtype; X is only
  * read) with the launch choices above, one coordinate at a time from the
- * current ones (projection tile 14 / 11 / 4 and expansion tile 15 / 13 / 9 / 6
- * for complex64 blocks on a mixed handle, then the FFT batch halved / doubled,
- * then the second stream), best of three timed applications each, and keeps
- * the fastest.  With a cache file (cache_path, or if it is NULL the file named
+ * current ones (projection tile 14 / 15 / 11 / 4 and expansion tile 15 / 13 /
+ * 9 / 6 for complex64 blocks on a mixed handle, then the FFT batch halved /
+ * doubled, then the second stream), best of five timed applications each; a
+ * candidate replaces the current choice only when it is more than 1% faster.
+ * With a cache file (cache_path, or if it is NULL the file named
  * by the environment variable ABI_AUTOTUNE_CACHE; no file: no cache) the
  * choice is first looked up under the key (GPU architecture, CU count, plane
  * waves, projectors, bands, FFT box, dtype) and applied without timing

@@ -311,6 +311,8 @@ __global__ __launch_bounds__(kCT) void cpass_a_kernel(const C2<T> *__restrict__ 
   __shared__ C2<T> tw[N];
   const int i3 = blockIdx.x;
   const int bl = blockIdx.y;
+  // a plane with no sphere points is left unwritten: the middle passes read it as zero
+  if (plane[i3] == plane[i3 + 1]) return;
   for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(twg[i]);
   for (int i = threadIdx.x; i < N * LD; i += kCT) buf[i] = C2<T>{0, 0};
   __syncthreads();
@@ -334,7 +336,8 @@ __global__ __launch_bounds__(kCT) void cpass_a_kernel(const C2<T> *__restrict__ 
 template <typename T, typename VT, int N>
 __global__ __launch_bounds__(kCT) void cpass_b_kernel(C2<T> *__restrict__ box,
                                                       const VT *__restrict__ V,
-                                                      const double2 *__restrict__ twg) {
+                                                      const double2 *__restrict__ twg,
+                                                      uint64_t zocc) {
   constexpr int LD = cld<N>();
   __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
@@ -350,8 +353,13 @@ __global__ __launch_bounds__(kCT) void cpass_b_kernel(C2<T> *__restrict__ box,
   constexpr int64_t ZS = (int64_t)N * N;
   auto ldm = [&](int pa, int e) { return buf[pa + e * LD]; };
   auto stm = [&](int pa, int e, C2<T> x) { buf[pa + e * LD] = x; };
-  auto ldg = [&](int pa, int e) { return src[pa + e * ZS]; };
-  auto stg = [&](int pa, int e, C2<T> x) { src[pa + e * ZS] = x; };
+  // reciprocal planes g3 without sphere points: zero in (pass A leaves them
+  // unwritten), not written out (pass C does not read them)
+  auto occ = [&](int e) { return ((zocc >> e) & 1ull) != 0; };
+  auto ldg = [&](int pa, int e) { return occ(e) ? src[pa + e * ZS] : C2<T>{0, 0}; };
+  auto stg = [&](int pa, int e, C2<T> x) {
+    if (occ(e)) src[pa + e * ZS] = x;
+  };
   auto stv = [&](int pa, int e, C2<T> x) { buf[pa + e * LD] = cscale(x, (T)v[pa + e * ZS]); };
   cfft_io<T, N, 0, 1, N, +1, false, true>(tw, ldg, stv, ldm, stm);
   cfft_io<T, N, 0, 1, N, -1, true, false>(tw, ldm, stg, ldm, stm);
@@ -360,7 +368,8 @@ __global__ __launch_bounds__(kCT) void cpass_b_kernel(C2<T> *__restrict__ box,
 // z-inverse FFT only (the box then holds the bands in real space).
 template <typename T, int N>
 __global__ __launch_bounds__(kCT) void cpass_b_inv_kernel(C2<T> *__restrict__ box,
-                                                          const double2 *__restrict__ twg) {
+                                                          const double2 *__restrict__ twg,
+                                                          uint64_t zocc) {
   constexpr int LD = cld<N>();
   __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
@@ -372,7 +381,10 @@ __global__ __launch_bounds__(kCT) void cpass_b_inv_kernel(C2<T> *__restrict__ bo
   constexpr int64_t ZS = (int64_t)N * N;
   auto ldm = [&](int pa, int e) { return buf[pa + e * LD]; };
   auto stm = [&](int pa, int e, C2<T> x) { buf[pa + e * LD] = x; };
-  auto ldg = [&](int pa, int e) { return src[pa + e * ZS]; };
+  // input planes g3 without sphere points are zero; the output is real space (all z)
+  auto ldg = [&](int pa, int e) {
+    return ((zocc >> e) & 1ull) ? src[pa + e * ZS] : C2<T>{0, 0};
+  };
   auto stg = [&](int pa, int e, C2<T> x) { src[pa + e * ZS] = x; };
   cfft_io<T, N, 0, 1, N, +1, false, false>(tw, ldg, stg, ldm, stm);
 }
@@ -384,7 +396,8 @@ template <typename T, typename VT, int N>
 __global__ __launch_bounds__(kCT) void cpass_b_adj_kernel(C2<T> *__restrict__ box,
                                                           C2<T> *__restrict__ fwd,
                                                           const VT *__restrict__ V,
-                                                          const double2 *__restrict__ twg) {
+                                                          const double2 *__restrict__ twg,
+                                                          uint64_t zocc) {
   constexpr int LD = cld<N>();
   __shared__ C2<T> buf[N * LD];
   __shared__ C2<T> tw[N];
@@ -399,8 +412,13 @@ __global__ __launch_bounds__(kCT) void cpass_b_adj_kernel(C2<T> *__restrict__ bo
   constexpr int64_t ZS = (int64_t)N * N;
   auto ldm = [&](int pa, int e) { return buf[pa + e * LD]; };
   auto stm = [&](int pa, int e, C2<T> x) { buf[pa + e * LD] = x; };
-  auto ldg = [&](int pa, int e) { return src[pa + e * ZS]; };
-  auto stg = [&](int pa, int e, C2<T> x) { src[pa + e * ZS] = x; };
+  // the adjoint band's planes g3 without sphere points: zero in, not written
+  // out; the forward band's box is real space (all z)
+  auto occ = [&](int e) { return ((zocc >> e) & 1ull) != 0; };
+  auto ldg = [&](int pa, int e) { return occ(e) ? src[pa + e * ZS] : C2<T>{0, 0}; };
+  auto stg = [&](int pa, int e, C2<T> x) {
+    if (occ(e)) src[pa + e * ZS] = x;
+  };
   // the z-inverse's last stage: Re[conj(a) y] over the forward box, a V into LDS
   auto stv = [&](int pa, int e, C2<T> a) {
     const int64_t r = pa + e * ZS;
@@ -430,6 +448,7 @@ __global__ __launch_bounds__(kCT) void cpass_c_kernel(
   }
   const int i3 = blockIdx.x;
   const int bl = blockIdx.y;
+  if (plane[i3] == plane[i3 + 1]) return;  // no sphere points to gather in this plane
   for (int i = threadIdx.x; i < N; i += kCT) tw[i] = to_c2<T>(twg[i]);
   __syncthreads();
   const int off = i3 * NXY;
@@ -489,7 +508,7 @@ void launch_cubic(const abi_system_s *s, const void *Yk, int64_t ldk, const void
   if (prof) prof->end(tok, st);
   tok = prof ? prof->begin(PROF_FFT_B, bytesB, st) : -1;
   hipLaunchKernelGGL((cpass_b_kernel<T, VT, N>), dim3(N, nb), dim3(kCT), 0, st, bx,
-                     reinterpret_cast<const VT *>(V), tw);
+                     reinterpret_cast<const VT *>(V), tw, s->zocc);
   CHEBFI_HIP(hipGetLastError());
   if (prof) prof->end(tok, st);
   tok = prof ? prof->begin(PROF_FFT_C, bytesC, st) : -1;
@@ -517,9 +536,10 @@ void adjoint_cubic(const abi_system_s *s, const void *Ak1, int64_t lda1, const v
                      reinterpret_cast<const V2 *>(Ak1), lda1, band0, s->d_box, s->d_plane, tw, b1);
   hipLaunchKernelGGL((cpass_a_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st,
                      reinterpret_cast<const V2 *>(Yk), ldy, band0, s->d_box, s->d_plane, tw, b2);
-  hipLaunchKernelGGL((cpass_b_inv_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st, b2, tw);
+  hipLaunchKernelGGL((cpass_b_inv_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st, b2, tw,
+                     s->zocc);
   hipLaunchKernelGGL((cpass_b_adj_kernel<T, VT, N>), dim3(N, nb), dim3(kCT), 0, st, b1, b2,
-                     reinterpret_cast<const VT *>(V), tw);
+                     reinterpret_cast<const VT *>(V), tw, s->zocc);
   const int64_t nbox = (int64_t)N * N * N;
   hipLaunchKernelGGL(dv_reduce_kernel<T>, dim3((unsigned)((nbox + 255) / 256)), dim3(256), 0, st,
                      nbox, nb, (const V2 *)b2, gamma / (double)nbox, dV);
@@ -541,7 +561,8 @@ void density_cubic(const abi_system_s *s, const void *Psi, int64_t ld, int band0
   V2 *bx = reinterpret_cast<V2 *>(box);
   hipLaunchKernelGGL((cpass_a_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st,
                      reinterpret_cast<const V2 *>(Psi), ld, band0, s->d_box, s->d_plane, tw, bx);
-  hipLaunchKernelGGL((cpass_b_inv_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st, bx, tw);
+  hipLaunchKernelGGL((cpass_b_inv_kernel<T, N>), dim3(N, nb), dim3(kCT), 0, st, bx, tw,
+                     s->zocc);
   const int64_t nbox = (int64_t)N * N * N;
   hipLaunchKernelGGL(rho_accum_kernel<T>, dim3((unsigned)((nbox + 255) / 256)), dim3(256), 0, st,
                      nbox, nb, band0, (const V2 *)bx, w, 1.0 / (double)nbox, rho);
