@@ -476,6 +476,23 @@ __device__ int sturm_less(int64_t m, const double *d, const double *e2, double x
   return cnt;
 }
 
+// The same count with d and e2 in LDS (the recurrence's operands are then a
+// short LDS read away instead of a global one).
+__device__ int sturm_less_lds(int64_t m, const double *d, const double *e2, double x,
+                              double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0) ++cnt;
+#pragma unroll 4
+  for (int64_t i = 1; i < m; ++i) {
+    q = (d[i] - x) - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
 __global__ __launch_bounds__(256) void tri_prep_kernel(int64_t m, const double *__restrict__ d,
                                 const double *__restrict__ e, double *__restrict__ e2,
                                 double *__restrict__ stats) {
@@ -518,10 +535,20 @@ __global__ __launch_bounds__(256) void tri_prep_kernel(int64_t m, const double *
 // shrinks to the sub-interval where the count first reaches i + 1 (65 times
 // narrower per round), until it is below the tolerance or no representable
 // point is left inside.
+// lds != 0: d and e2 are first copied into LDS (2 m doubles of dynamic LDS),
+// which the Sturm recurrences of the workgroup's four waves then read
 __global__ __launch_bounds__(256) void bisect_kernel(int64_t m, const double *__restrict__ d,
                                                      const double *__restrict__ e2,
                                                      const double *__restrict__ stats,
-                                                     double *__restrict__ w) {
+                                                     double *__restrict__ w, int lds) {
+  extern __shared__ double sde[];
+  if (lds) {
+    for (int64_t j = threadIdx.x; j < m; j += blockDim.x) {
+      sde[j] = d[j];
+      sde[m + j] = j + 1 < m ? e2[j] : 0.0;
+    }
+    __syncthreads();
+  }
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= m) return;  // uniform per wave
@@ -533,7 +560,10 @@ __global__ __launch_bounds__(256) void bisect_kernel(int64_t m, const double *__
     const double x = lo + (hi - lo) * ((double)(lane + 1) * (1.0 / 65.0));
     const bool inside = x > lo && x < hi;
     if (__ballot(inside) == 0ull) break;
-    const bool above = inside ? sturm_less(m, d, e2, x, pivmin) >= i + 1 : x >= hi;
+    const bool above =
+        inside ? (lds ? sturm_less_lds(m, sde, sde + m, x, pivmin) : sturm_less(m, d, e2, x, pivmin)) >=
+                     i + 1
+               : x >= hi;
     const unsigned long long mask = __ballot(above);
     const int k = mask ? __ffsll((long long)mask) - 1 : 64;
     const double xk = __shfl(x, k < 64 ? k : 63, 64), xk1 = __shfl(x, k > 0 ? k - 1 : 0, 64);
@@ -1140,7 +1170,16 @@ void zheev(int64_t m, void *Av, int64_t lda, double *wout, void *Zv, int64_t ldz
   CHEBFI_HIP(hipGetLastError());
   // eigenvalues of the tridiagonal
   hipLaunchKernelGGL(tri_prep_kernel, dim3(1), dim3(256), 0, st, m, d, e, e2, stats);
-  hipLaunchKernelGGL(bisect_kernel, dim3(nblk(m, 4)), dim3(256), 0, st, m, d, e2, stats, wout);
+  {
+    // d and e2 in LDS up to m = 4096 (64 KB)
+    const int lds = m <= 4096 ? 1 : 0;
+    const size_t lb = lds ? sizeof(double) * 2 * (size_t)m : 0;
+    if (lds)
+      CHEBFI_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(bisect_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
+    hipLaunchKernelGGL(bisect_kernel, dim3(nblk(m, 4)), dim3(256), lb, st, m, d, e2, stats, wout,
+                       lds);
+  }
   CHEBFI_HIP(hipGetLastError());
   // eigenvectors of the tridiagonal
   // clusters: arrays in LDS up to kLdsInvitM, else in a global slab per leader
