@@ -1065,7 +1065,14 @@ __global__ __launch_bounds__(64 * NWM * NWN, 2) void zgemm_pl2_kernel(
 // LDS, one stage: A as [plane][row][32] bf16 with the 16-byte chunk kc of row i
 // at position kc ^ ((i >> 1) & 3) (B planes alike); B32 as [column][32]
 // complex float with the 16-byte chunk c (two complex) of column j at position
-// c ^ (j & 7).  Both layouts make the fragment reads free of bank conflicts.
+// c ^ b32_mask(j).  A column's 256 bytes span all 64 banks, so only the
+// position separates the lanes of a fragment read; the LDS serves a 16-byte
+// read for lanes 0-7 together with lanes 16-23 (and 8-15 with 24-31): eight
+// columns at two adjacent K quarters, i.e. chunks differing in bit 2.  The
+// mask leaves that bit alone and moves bit 2 of the column to bit 3, so those
+// sixteen reads fill all sixteen positions.  Both layouts make the fragment
+// reads free of bank conflicts.
+__device__ __forceinline__ int b32_mask(int j) { return (j & 3) | ((j & 4) << 1); }
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
 typedef float f2v_t __attribute__((ext_vector_type(2)));
@@ -1169,7 +1176,7 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl_kernel(
   // (l & 3) ^ ((row >> 1) & 3) (the same for every q, r0 being a multiple of
   // 16).  B planes alike.  B32: load q covers column c = wave QB + q (clamped
   // to n - 1; uniform), lane l the dword l & 3 of the 16-byte chunk at
-  // position l >> 2, which holds chunk (l >> 2) ^ (c & 7) of the column.
+  // position l >> 2, which holds chunk (l >> 2) ^ b32_mask(c) of the column.
   static_assert(!BF32 || QB % 8 == 0, "B32 lane patterns repeat every 8 columns");
   const int kcl = (lane & 3) ^ ((lane >> 3) & 3);
   // byte offsets of this lane's loads within the tile being loaded (rows and
@@ -1187,7 +1194,7 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl_kernel(
     if constexpr (BF32) {
 #pragma unroll
       for (int c8 = 0; c8 < 8; ++c8) {
-        const int ch = (lane >> 2) ^ c8, w = lane & 3;
+        const int ch = (lane >> 2) ^ b32_mask(c8), w = lane & 3;
         bofs[c8] = (uint32_t)(4 * (2 * (2 * ch + (w >> 1)) + (w & 1)));
       }
     } else {
@@ -1262,7 +1269,7 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl_kernel(
       float4 q4[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int off = A_BYTES + jj * 256 + 16 * ((4 * kq + t) ^ (jj & 7));
+        const int off = A_BYTES + jj * 256 + 16 * ((4 * kq + t) ^ b32_mask(jj));
         q4[t] = *reinterpret_cast<const float4 *>(st + off);
       }
       bf2_t rh[4], rl[4], ih[4], il[4];
@@ -1507,11 +1514,16 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl_kernel(
 // multiplications that consumed them precede the barrier.
 //
 // LDS, one stage: A as [plane][row][16] bf16 with the 16-byte half h of row r
-// at position h ^ ((r >> 2) & 1) (B planes alike); B32 as [column][16] complex
+// at position h ^ dl3_swz(r) (B planes alike); B32 as [column][16] complex
 // float with the 16-byte chunk c (two complex) of column j at position
-// c ^ (j & 7).  Lanes 8q .. 8q + 7 of a fragment read then hit eight
-// different 16-byte bank groups.
+// c ^ dl3_b32_mask(j).  A 16-byte read is served for lanes 0-7 together with
+// lanes 16-23 (and 8-15 with 24-31), rows r and r + 16 of a fragment; eight
+// rows of 32 bytes (or four columns of 128) fill one bank width, so the bit
+// r >> 4 flips the half (the chunk's bit 0) and the sixteen reads fill all
+// sixteen 16-byte positions: free of bank conflicts.
 typedef float v16f __attribute__((ext_vector_type(16)));
+__device__ __forceinline__ int dl3_swz(int r) { return ((r >> 2) & 1) ^ ((r >> 4) & 1); }
+__device__ __forceinline__ int dl3_b32_mask(int j) { return (j & 7) ^ ((j >> 4) & 1); }
 
 __device__ __forceinline__ v16f mfma32_bf16(const v8bf &a, const v8bf &b, v16f c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -1560,7 +1572,7 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl3_kernel(
 #pragma unroll
   for (int q = 0; q < QA; ++q) {
     const int qq = wave * QA + q, p = qq / (BM / 32), r0 = (qq % (BM / 32)) * 32;
-    const int r = r0 + (lane >> 1), h = (lane & 1) ^ ((r >> 2) & 1);
+    const int r = r0 + (lane >> 1), h = (lane & 1) ^ dl3_swz(r);
     const int64_t gr = row0 + r < m ? row0 + r : m - 1;
     asrc[q] = Apl + (int64_t)p * psa + gr * lda + 8 * h;
     aoff[q] = p * BM * 32 + r0 * 32;
@@ -1576,7 +1588,7 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl3_kernel(
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       const int qq = wave * QB + q, p = qq / (BN / 32), r0 = (qq % (BN / 32)) * 32;
-      const int r = r0 + (lane >> 1), h = (lane & 1) ^ ((r >> 2) & 1);
+      const int r = r0 + (lane >> 1), h = (lane & 1) ^ dl3_swz(r);
       const int64_t gr = col0 + r < n ? col0 + r : n - 1;
       bsrc[q] = (const u16 *)Bsrc + (int64_t)p * psb + gr * ldb + 8 * h;
       boff[q] = A_BYTES + p * BN * 32 + r0 * 32;
@@ -1591,7 +1603,7 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl3_kernel(
       if constexpr (BF32) {
         const int c = (wave * QB + q) * 2 + (lane >> 5);
         const int64_t gc = col0 + c < n ? col0 + c : n - 1;
-        const int ch = ((lane >> 2) & 7) ^ (c & 7), w = lane & 3;
+        const int ch = ((lane >> 2) & 7) ^ dl3_b32_mask(c), w = lane & 3;
         int64_t kk = k0 + 2 * ch + (w >> 1);
         if (kk >= kdata) kk = kdata - 1;
         dma4((const float *)Bsrc + 2 * (gc * ldb + kk) + (w & 1),
@@ -1619,7 +1631,7 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl3_kernel(
       float4 q4[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int off = A_BYTES + jj * 128 + 16 * ((4 * hh + t) ^ (jj & 7));
+        const int off = A_BYTES + jj * 128 + 16 * ((4 * hh + t) ^ dl3_b32_mask(jj));
         q4[t] = *reinterpret_cast<const float4 *>(st + off);
       }
       bf2_t rh[4], rl[4], ih[4], il[4];
@@ -1633,7 +1645,7 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl3_kernel(
       b[2] = cat4(rl[0], rl[1], rl[2], rl[3]);
       b[3] = cat4(il[0], il[1], il[2], il[3]);
     } else {
-      const int kb = 16 * (hh ^ ((jj >> 2) & 1));
+      const int kb = 16 * (hh ^ dl3_swz(jj));
 #pragma unroll
       for (int p = 0; p < 4; ++p)
         b[p] = *reinterpret_cast<const v8bf *>(st + (A_BYTES + p * BN * 32 + jj * 32 + kb));
@@ -1641,7 +1653,7 @@ __global__ __launch_bounds__(64 * NWM * NWN) void zgemm_dl3_kernel(
   };
   auto a_frag = [&](const unsigned char *st, int i, v8bf *a) {
     const int ii = wm * WM + i * 32 + (lane & 31);
-    const int kb = 16 * (hh ^ ((ii >> 2) & 1));
+    const int kb = 16 * (hh ^ dl3_swz(ii));
 #pragma unroll
     for (int p = 0; p < 4; ++p)
       a[p] = *reinterpret_cast<const v8bf *>(st + (p * BM * 32 + ii * 32 + kb));

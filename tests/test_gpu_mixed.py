@@ -94,6 +94,28 @@ def test_mixed_apply_H_config2_ragged():
     assert col_rel_err(got.astype(np.complex128), H(X)) <= 2e-6
 
 
+def test_mixed_apply_H_every_gemm_variant():
+    """Every projection (0..16) and expansion (0..15) tile variant the tuning
+    parameters select, on 300 bands of the medium workload (256 projectors: two
+    row tiles; ragged column tiles; split-K over 22119 plane waves), against the
+    oracle's H X.  The autotuner may pick any of them."""
+    s = W.make_system(2)
+    H = O.Hamiltonian.from_system(s)
+    X = W.random_block(H.npw, 300, 5).astype(np.complex64).astype(np.complex128)
+    ref = H(X)
+    with B.System(s, precision=B.ABI_PREC_MIXED) as g:
+        Xd = _c64(X)
+        p0, e0 = g.get_tuning(B.TUNE_PROJ), g.get_tuning(B.TUNE_EXPAND)
+        for param, variants, keep in ((B.TUNE_PROJ, range(17), (B.TUNE_EXPAND, e0)),
+                                      (B.TUNE_EXPAND, range(16), (B.TUNE_PROJ, p0))):
+            g.set_tuning(*keep)
+            for v in variants:
+                g.set_tuning(param, v)
+                err = col_rel_err(to_host(g.apply_H(Xd)).astype(np.complex128), ref)
+                print(f"tuning {param} = {v}: {err:.3e}", flush=True)
+                assert err <= 2e-6, (param, v, err)
+
+
 @pytest.mark.parametrize("name,degree", [("odd15", 3), ("n27", 6), ("c1", 8)])
 def test_mixed_filter(name, degree):
     H = hamiltonian(name)
