@@ -435,6 +435,13 @@ abi_status abi_batch_autotune(abi_batch batch, const void *const *X, void *const
 /* Graph capture on (1, default) or off (0: eager launches). */
 abi_status abi_batch_use_graph(abi_batch batch, int32_t on);
 
+/* Each filter step's projector products (P^H Y, D, P C') on a second stream of
+ * the batch, beside the FFT passes A and B that do not need them, the last
+ * pass waiting for them (1, default), or in line on the caller's stream (0).
+ * The same kernels in either case: the results are bitwise the same.  The
+ * second stream has the default priority. */
+abi_status abi_batch_use_overlap(abi_batch batch, int32_t on);
+
 abi_status abi_destroy_batch(abi_batch batch);
 
 /* ---- no-allocation form ---------------------------------------------------------

@@ -39,6 +39,7 @@ EXPORTS = [
     "abi_zheev", "abi_profile_enable", "abi_profile_read", "abi_update_potential",
     "abi_filter_backward", "abi_density", "abi_last_error", "abi_set_system_batch",
     "abi_batch_system", "abi_cheb_filter_batch", "abi_batch_autotune", "abi_batch_use_graph",
+    "abi_batch_use_overlap",
     "abi_destroy_batch", "abi_chebfi_solve", "abi_apply_S", "abi_apply_Sinv", "abi_overlap_info",
     "abi_lobpcg_solve", "abi_density_add", "abi_occupations", "abi_scf_potential", "abi_scf_solve",
     "abi_get_potential", "abi_set_tuning", "abi_get_tuning", "abi_apply_H_noalloc",
@@ -121,6 +122,7 @@ def lib():
         "abi_cheb_filter_batch": [vp, vp, vp, vp, vp, c_int32, c_int32, vp, vp, vp, vp],
         "abi_batch_autotune": [vp, vp, vp, vp, vp, c_int32, c_int32, vp, vp, vp, vp, vp],
         "abi_batch_use_graph": [vp, c_int32],
+        "abi_batch_use_overlap": [vp, c_int32],
         "abi_destroy_batch": [vp],
         "abi_chebfi_solve": [vp, vp, c_int64, c_int64, c_int32, vp, c_int32, c_int32, c_int32,
                              c_double, c_int32, vp, vp, vp, vp],
@@ -687,6 +689,9 @@ class Batch:
 
     def use_graph(self, on=True):
         _check(lib().abi_batch_use_graph(self._h, 1 if on else 0))
+
+    def use_overlap(self, on=True):
+        _check(lib().abi_batch_use_overlap(self._h, 1 if on else 0))
 
 
 def _make_autograd():

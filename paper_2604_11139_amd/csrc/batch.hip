@@ -39,6 +39,25 @@ __device__ __forceinline__ int find_sys(const int64_t *off, int nsys, int64_t it
   return s;
 }
 
+// The descriptors' pointers are read from memory, so the compiler cannot tell
+// that they address global memory and would use flat accesses, which also
+// count as LDS operations (every LDS wait would then wait for them too);
+// pointers of this type make them global accesses.
+template <typename T>
+using gptr = T __attribute__((address_space(1))) *;
+template <typename T>
+__device__ __forceinline__ C2<T> gload(gptr<const C2<T>> p) {
+  C2<T> v;
+  v.x = p->x;
+  v.y = p->y;
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ void gstore(gptr<C2<T>> p, C2<T> v) {
+  p->x = v.x;
+  p->y = v.y;
+}
+
 template <typename T>
 __device__ __forceinline__ C2<T> wave_sum(C2<T> v) {
 #pragma unroll
@@ -54,6 +73,7 @@ __device__ __forceinline__ C2<T> wave_sum(C2<T> v) {
 // chunk streams through LDS in pieces of KC, so each element of P is read once
 // per band tile instead of once per band; a thread holds 2 projectors x 2
 // bands, sums a piece in the block's precision and adds the piece sums in FP64.
+// The next piece is loaded into registers while the current one is multiplied.
 template <typename T>
 __global__ __launch_bounds__(256) void bproj_tile_kernel(const BatchSys *__restrict__ sys,
                                                          const BatchStep *__restrict__ step,
@@ -61,6 +81,8 @@ __global__ __launch_bounds__(256) void bproj_tile_kernel(const BatchSys *__restr
                                                          int nsys) {
   constexpr int KC = sizeof(T) == 4 ? 64 : 32;
   constexpr int NJ = kBatchPT, NB = kBatchBT;
+  static_assert(NJ == NB && KC * NJ % 256 == 0, "one element of P and of Y per (thread, q)");
+  constexpr int QP = KC * NJ / 256;
   __shared__ C2<T> ps[KC][NJ + 1];
   __shared__ C2<T> ys[KC][NB + 1];
   const int t = threadIdx.x;
@@ -78,34 +100,65 @@ __global__ __launch_bounds__(256) void bproj_tile_kernel(const BatchSys *__restr
     const int64_t b0 = bt * NB;
     const int nb = d.nband - b0 < NB ? (int)(d.nband - b0) : NB;
     const int np = d.nproj - (int)pj * NJ < NJ ? d.nproj - (int)pj * NJ : NJ;
-    const C2<T> *P = reinterpret_cast<const C2<T> *>(d.P) + pj * NJ * npw;
-    const C2<T> *y = reinterpret_cast<const C2<T> *>(st.yk) + b0 * st.ldk;
+    const gptr<const C2<T>> P = (gptr<const C2<T>>)d.P + pj * NJ * npw;
+    const gptr<const C2<T>> y = (gptr<const C2<T>>)st.yk + b0 * st.ldk;
     const int64_t kend = (ch + 1) * kBatchKC < npw ? (ch + 1) * kBatchKC : npw;
-    double2 tot[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
-    for (int64_t k0 = ch * kBatchKC; k0 < kend; k0 += KC) {
-      for (int e = t; e < KC * NJ; e += 256) {
-        const int k = e % KC, j = e / KC;
-        ps[k][j] = (j < np && k0 + k < kend) ? P[k0 + k + (int64_t)j * npw] : C2<T>{0, 0};
+    // this thread's elements of a piece: e = t + 256 q, element k = e % KC of
+    // projector (or band) e / KC; the next piece is fetched into registers
+    // while the current one is multiplied
+    C2<T> pn[QP], yn[QP];
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+      for (int q = 0; q < QP; ++q) {
+        const int e = t + 256 * q, k = e % KC, r = e / KC;
+        C2<T> a{0, 0}, b{0, 0};
+        if (k0 + k < kend) {
+          if (r < np) a = gload<T>(P + k0 + k + (int64_t)r * npw);
+          if (r < nb) b = gload<T>(y + (int64_t)r * st.ldk + k0 + k);
+        }
+        pn[q] = a;
+        yn[q] = b;
       }
-      for (int e = t; e < KC * NB; e += 256) {
-        const int k = e % KC, b = e / KC;
-        ys[k][b] = (b < nb && k0 + k < kend) ? y[(int64_t)b * st.ldk + k0 + k] : C2<T>{0, 0};
+    };
+    // with at most 16 projectors in the tile the second projector of a thread
+    // is zero: only the first one is multiplied
+    const bool two = np > 16;
+    double2 tot[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
+    fetch(ch * kBatchKC);
+    for (int64_t k0 = ch * kBatchKC; k0 < kend; k0 += KC) {
+#pragma unroll
+      for (int q = 0; q < QP; ++q) {
+        const int e = t + 256 * q, k = e % KC, r = e / KC;
+        ps[k][r] = pn[q];
+        ys[k][r] = yn[q];
       }
       __syncthreads();
+      if (k0 + KC < kend) fetch(k0 + KC);
       C2<T> acc[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
+      auto madd = [&](int u, int v, C2<T> p, C2<T> q) {  // acc += conj(p) q
+        acc[u][v].x = fma(p.x, q.x, acc[u][v].x);
+        acc[u][v].x = fma(p.y, q.y, acc[u][v].x);
+        acc[u][v].y = fma(p.x, q.y, acc[u][v].y);
+        acc[u][v].y = fma(-p.y, q.x, acc[u][v].y);
+      };
+      if (two) {
 #pragma unroll 8
-      for (int k = 0; k < KC; ++k) {
-        const C2<T> p0 = ps[k][j0], p1 = ps[k][j0 + 16];
-        const C2<T> y0 = ys[k][bq], y1 = ys[k][bq + 16];
-        // conj(p) y
-        acc[0][0].x += p0.x * y0.x + p0.y * y0.y;
-        acc[0][0].y += p0.x * y0.y - p0.y * y0.x;
-        acc[0][1].x += p0.x * y1.x + p0.y * y1.y;
-        acc[0][1].y += p0.x * y1.y - p0.y * y1.x;
-        acc[1][0].x += p1.x * y0.x + p1.y * y0.y;
-        acc[1][0].y += p1.x * y0.y - p1.y * y0.x;
-        acc[1][1].x += p1.x * y1.x + p1.y * y1.y;
-        acc[1][1].y += p1.x * y1.y - p1.y * y1.x;
+        for (int k = 0; k < KC; ++k) {
+          const C2<T> p0 = ps[k][j0], p1 = ps[k][j0 + 16];
+          const C2<T> y0 = ys[k][bq], y1 = ys[k][bq + 16];
+          madd(0, 0, p0, y0);
+          madd(0, 1, p0, y1);
+          madd(1, 0, p1, y0);
+          madd(1, 1, p1, y1);
+        }
+      } else {
+#pragma unroll 8
+        for (int k = 0; k < KC; ++k) {
+          const C2<T> p0 = ps[k][j0];
+          const C2<T> y0 = ys[k][bq], y1 = ys[k][bq + 16];
+          madd(0, 0, p0, y0);
+          madd(0, 1, p0, y1);
+        }
       }
 #pragma unroll
       for (int u = 0; u < 2; ++u)
@@ -174,9 +227,12 @@ __global__ __launch_bounds__(256) void bproj_reduce_kernel(const BatchSys *__res
 }
 
 // K1b: E = P C' for kBatchEP plane waves x kBatchBT bands of one system (E:
-// npw x nband, ld npw; pass C adds it).  Per projector tile a thread holds the
-// P row of its plane wave in registers and applies it to every band of the
-// tile; the first tile stores E, the others add to it.
+// npw x nband, ld npw; pass C adds it).  A thread owns one plane wave and
+// keeps its kBatchBT outputs in registers over all projector tiles: per
+// projector one P element from global memory and the C' row from LDS (the
+// same address in every lane), four FMAs per band, so E is written once.
+// Projectors come four per atom, so a tile's count is a multiple of four and
+// the loop over them runs in unrolled steps of four. 
 template <typename T>
 __global__ __launch_bounds__(kBatchEP) void bexpand_kernel(const BatchSys *__restrict__ sys,
                                                            const int64_t *__restrict__ off,
@@ -195,30 +251,45 @@ __global__ __launch_bounds__(kBatchEP) void bexpand_kernel(const BatchSys *__res
     const int nb = d.nband - b0 < NB ? (int)(d.nband - b0) : NB;
     const int64_t npw = d.npw;
     const int64_t g = pt * kBatchEP + t;
-    const C2<T> *cp = reinterpret_cast<const C2<T> *>(d.Cp);
-    C2<T> *E = reinterpret_cast<C2<T> *>(d.E) + b0 * npw + g;
+    const gptr<const C2<T>> cp = (gptr<const C2<T>>)d.Cp;
+    C2<T> v[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) v[b] = C2<T>{0, 0};
     for (int pj = 0; pj < d.npt; ++pj) {
       const int j0 = pj * NJ;
       const int np = d.nproj - j0 < NJ ? d.nproj - j0 : NJ;
-      for (int e = t; e < np * nb; e += kBatchEP) {
-        const int j = e % np, b = e / np;
-        cs[j][b] = cp[(b0 + b) * d.nproj + j0 + j];
+      for (int e = t; e < NJ * NB; e += kBatchEP) {
+        const int j = e / NB, b = e % NB;
+        C2<T> c{0, 0};
+        if (j < np && b < nb) c = gload<T>(cp + (b0 + b) * d.nproj + j0 + j);
+        cs[j][b] = c;
       }
       __syncthreads();
       if (g < npw) {
-        const C2<T> *P = reinterpret_cast<const C2<T> *>(d.P) + (int64_t)j0 * npw;
-        C2<T> pr[NJ];
+        const gptr<const C2<T>> P = (gptr<const C2<T>>)d.P + (int64_t)j0 * npw + g;
+        for (int j = 0; j < np; j += 4) {
+          C2<T> pr[4];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) pr[j] = j < np ? P[g + (int64_t)j * npw] : C2<T>{0, 0};
-        for (int b = 0; b < nb; ++b) {
-          C2<T> v = pj == 0 ? C2<T>{0, 0} : E[(int64_t)b * npw];
+          for (int q = 0; q < 4; ++q) pr[q] = gload<T>(P + (int64_t)(j + q) * npw);
 #pragma unroll
-          for (int j = 0; j < NJ; ++j)
-            if (j < np) v = cadd(v, cmul(pr[j], cs[j][b]));
-          E[(int64_t)b * npw] = v;
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              const C2<T> c = cs[j + q][b];
+              v[b].x = fma(pr[q].x, c.x, v[b].x);
+              v[b].x = fma(-pr[q].y, c.y, v[b].x);
+              v[b].y = fma(pr[q].x, c.y, v[b].y);
+              v[b].y = fma(pr[q].y, c.x, v[b].y);
+            }
         }
       }
       __syncthreads();
+    }
+    if (g < npw) {
+      const gptr<C2<T>> E = (gptr<C2<T>>)d.E + b0 * npw + g;
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        if (b < nb) gstore<T>(E + (int64_t)b * npw, v[b]);
     }
   }
 }
@@ -420,8 +491,16 @@ __global__ __launch_bounds__(kCT) void bcpass_a_kernel(const BatchSys *__restric
   }
 }
 
+// Waves per SIMD asked of the batched pass B: six (three workgroups of kCT
+// threads per CU instead of two) for the complex64 edges where that measured
+// faster and compiles without spilling, else the least a workgroup needs.
 template <typename T, int N>
-__global__ __launch_bounds__(kCT) void bcpass_b_kernel(const BatchSys *__restrict__ sys,
+constexpr int bcpass_b_waves() {
+  return sizeof(T) == 4 && (N == 24 || N == 40 || N == 45) ? 6 : kCT / 256;
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(bcpass_b_waves<T, N>()))) void bcpass_b_kernel(const BatchSys *__restrict__ sys,
                                                        const int32_t *__restrict__ gsys,
                                                        const int64_t *__restrict__ goff, int gns) {
   constexpr int LD = cld<N>(), PL = N * LD;
@@ -468,8 +547,17 @@ __global__ __launch_bounds__(kCT) void bcpass_b_kernel(const BatchSys *__restric
   }
 }
 
+// Waves per SIMD asked of the batched pass C: eight (a 64-VGPR budget, four
+// workgroups of kCT threads per CU, as the LDS allows) where the compiler
+// fits it without spilling (complex64, every edge but 36), else the least a
+// workgroup of kCT threads needs.
 template <typename T, int N>
-__global__ __launch_bounds__(kCT) void bcpass_c_kernel(const BatchSys *__restrict__ sys,
+constexpr int bcpass_c_waves() {
+  return sizeof(T) == 4 && N != 36 ? 8 : kCT / 256;
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(bcpass_c_waves<T, N>()))) void bcpass_c_kernel(const BatchSys *__restrict__ sys,
                                                        const BatchStep *__restrict__ step,
                                                        const int32_t *__restrict__ gsys,
                                                        const int64_t *__restrict__ goff, int gns) {
@@ -539,9 +627,14 @@ template <typename F> void set_lds_b(F kernel, size_t bytes) {
 
 }  // namespace
 
-// Host side: launches of one filter step for all systems.
+// Host side: launches of one filter step for all systems.  With a side
+// stream the projector products (which only pass C needs, as E) run there,
+// beside passes A and B: they read the step's input, written by the previous
+// step's pass C before the fork, and write E, C' and their partial sums, which
+// nothing else reads before the join.
 template <typename T>
-void batch_step(const BatchLaunch &L, int j, hipStream_t st) {
+void batch_step(const BatchLaunch &L, int j, hipStream_t st, hipStream_t side, hipEvent_t fork,
+                hipEvent_t join) {
   const BatchStep *stp = L.d_steps + (size_t)j * L.nsys;
   const int64_t *offP = L.d_off;
   const int64_t *offA = L.d_off + (L.nsys + 1);
@@ -551,16 +644,24 @@ void batch_step(const BatchLaunch &L, int j, hipStream_t st) {
   auto grid = [&](int64_t items) {
     return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(items, L.max_wgs)));
   };
+  const bool fork_proj = L.any_proj && side != nullptr;
   if (L.any_proj) {
-    hipLaunchKernelGGL(bproj_tile_kernel<T>, grid(L.items_p), dim3(256), 0, st, L.d_sys, stp,
+    hipStream_t sp = st;
+    if (fork_proj) {
+      CHEBFI_HIP(hipEventRecord(fork, st));
+      CHEBFI_HIP(hipStreamWaitEvent(side, fork, 0));
+      sp = side;
+    }
+    hipLaunchKernelGGL(bproj_tile_kernel<T>, grid(L.items_p), dim3(256), 0, sp, L.d_sys, stp,
                        offP, L.nsys);
     CHEBFI_HIP(hipGetLastError());
-    hipLaunchKernelGGL(bproj_reduce_kernel<T>, grid(L.items_r), dim3(256), 0, st, L.d_sys, stp,
+    hipLaunchKernelGGL(bproj_reduce_kernel<T>, grid(L.items_r), dim3(256), 0, sp, L.d_sys, stp,
                        offR, L.nsys);
     CHEBFI_HIP(hipGetLastError());
-    hipLaunchKernelGGL(bexpand_kernel<T>, grid(L.items_e), dim3(kBatchEP), 0, st, L.d_sys, offE,
+    hipLaunchKernelGGL(bexpand_kernel<T>, grid(L.items_e), dim3(kBatchEP), 0, sp, L.d_sys, offE,
                        L.nsys);
     CHEBFI_HIP(hipGetLastError());
+    if (fork_proj) CHEBFI_HIP(hipEventRecord(join, side));
   }
   const size_t e = sizeof(C2<T>);
   // systems on cubic boxes with specialised passes: one launch per edge and pass
@@ -601,6 +702,7 @@ void batch_step(const BatchLaunch &L, int j, hipStream_t st) {
                        L.d_sys, offB, L.nsys);
     CHEBFI_HIP(hipGetLastError());
   }
+  if (fork_proj) CHEBFI_HIP(hipStreamWaitEvent(st, join, 0));
   cubic(2);
   if (L.items_a > 0) {
     hipLaunchKernelGGL(bpass_c_kernel<T>, grid(L.items_a), dim3(L.fft_threads), e * L.lds_c, st,
@@ -634,8 +736,10 @@ void batch_prepare(const BatchLaunch &L) {
   set_lds_b(bpass_c_kernel<T>, e * L.lds_c);
 }
 
-template void batch_step<float>(const BatchLaunch &, int, hipStream_t);
-template void batch_step<double>(const BatchLaunch &, int, hipStream_t);
+template void batch_step<float>(const BatchLaunch &, int, hipStream_t, hipStream_t, hipEvent_t,
+                                hipEvent_t);
+template void batch_step<double>(const BatchLaunch &, int, hipStream_t, hipStream_t, hipEvent_t,
+                                 hipEvent_t);
 template void batch_prepare<float>(const BatchLaunch &);
 template void batch_prepare<double>(const BatchLaunch &);
 

@@ -254,6 +254,10 @@ struct abi_batch_s {
   std::vector<abi_system_s *> sys;
   int precision = ABI_PREC_FP64;
   hipStream_t cap = nullptr;  // capture stream of the graphs
+  // the projector products' stream beside the FFT passes, and its fork / join
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool overlap = true;
   chebfi::DevBuf d_tab, work;   // device tables [systems | steps | offsets], workspace
   void *h_tab = nullptr;        // pinned staging copy of the tables
   size_t h_tab_bytes = 0;
@@ -267,6 +271,7 @@ struct abi_batch_s {
   hipGraphExec_t gexec = nullptr;
   std::vector<int64_t> g_nband;
   int g_degree = -1, g_dtype = -1, g_fft = 0, g_proj = 0;
+  bool g_overlap = false;
   const void *g_sys = nullptr, *g_steps = nullptr, *g_off = nullptr;
 };
 
@@ -284,13 +289,15 @@ template <typename T>
 void batch_run(abi_batch_s *B, const BatchLaunch &L, int degree, int32_t dtype,
                const std::vector<int64_t> &nb, hipStream_t st) {
   batch_prepare<T>(L);
+  hipStream_t side = B->overlap ? B->side : nullptr;
   if (!B->use_graph) {
-    for (int j = 0; j < degree; ++j) batch_step<T>(L, j, st);
+    for (int j = 0; j < degree; ++j) batch_step<T>(L, j, st, side, B->ev_fork, B->ev_join);
     return;
   }
   const bool same = B->gexec && B->g_nband == nb && B->g_degree == degree && B->g_dtype == dtype &&
                     B->g_fft == L.fft_threads && B->g_proj == L.proj_threads &&
-                    B->g_sys == L.d_sys && B->g_steps == L.d_steps && B->g_off == L.d_off;
+                    B->g_sys == L.d_sys && B->g_steps == L.d_steps && B->g_off == L.d_off &&
+                    B->g_overlap == B->overlap;
   if (!same) {
     if (B->gexec) {
       CHEBFI_HIP(hipGraphExecDestroy(B->gexec));
@@ -299,7 +306,7 @@ void batch_run(abi_batch_s *B, const BatchLaunch &L, int degree, int32_t dtype,
     hipGraph_t g = nullptr;
     CHEBFI_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
     try {
-      for (int j = 0; j < degree; ++j) batch_step<T>(L, j, B->cap);
+      for (int j = 0; j < degree; ++j) batch_step<T>(L, j, B->cap, side, B->ev_fork, B->ev_join);
     } catch (...) {
       (void)hipStreamEndCapture(B->cap, &g);
       if (g) (void)hipGraphDestroy(g);
@@ -317,6 +324,7 @@ void batch_run(abi_batch_s *B, const BatchLaunch &L, int degree, int32_t dtype,
     B->g_sys = L.d_sys;
     B->g_steps = L.d_steps;
     B->g_off = L.d_off;
+    B->g_overlap = B->overlap;
   }
   CHEBFI_HIP(hipGraphLaunch(B->gexec, st));
 }
@@ -1979,11 +1987,17 @@ abi_status abi_set_system_batch(const abi_system_desc *descs, int32_t nsys, void
     }
     B->hsys.resize(nsys);
     CHEBFI_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+    CHEBFI_HIP(hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking));
+    CHEBFI_HIP(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
+    CHEBFI_HIP(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
   });
   if (rc != ABI_OK) {
     if (B) {
       for (abi_system h : B->sys) (void)abi_destroy(h);
       if (B->cap) (void)hipStreamDestroy(B->cap);
+      if (B->side) (void)hipStreamDestroy(B->side);
+      if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
+      if (B->ev_join) (void)hipEventDestroy(B->ev_join);
       delete B;
     }
     return rc;
@@ -2004,6 +2018,13 @@ abi_status abi_batch_use_graph(abi_batch B, int32_t on) {
   return guarded([&] {
     CHEBFI_REQUIRE(B != nullptr, ABI_ERR_ARG, "batch is NULL");
     B->use_graph = (on != 0);
+  });
+}
+
+abi_status abi_batch_use_overlap(abi_batch B, int32_t on) {
+  return guarded([&] {
+    CHEBFI_REQUIRE(B != nullptr, ABI_ERR_ARG, "batch is NULL");
+    B->overlap = (on != 0);
   });
 }
 
@@ -2085,6 +2106,9 @@ abi_status abi_destroy_batch(abi_batch B) {
     (void)hipDeviceSynchronize();
     if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
     if (B->cap) (void)hipStreamDestroy(B->cap);
+    if (B->side) (void)hipStreamDestroy(B->side);
+    if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
+    if (B->ev_join) (void)hipEventDestroy(B->ev_join);
     if (B->tab_copied) (void)hipEventDestroy(B->tab_copied);
     if (B->h_tab) (void)hipHostFree(B->h_tab);
     for (abi_system h : B->sys) (void)abi_destroy(h);

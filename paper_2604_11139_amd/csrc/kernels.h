@@ -259,7 +259,11 @@ void launch_mix(const abi_system_s *s, const double *vin, const double *vout, do
 // ---- batch.hip ------------------------------------------------------------------
 // One filter step (index j of the step table) of every system of a batch:
 // projection + D, FFT passes A, B, C (with expansion and recurrence).
-template <typename T> void batch_step(const BatchLaunch &L, int j, hipStream_t st);
+// side, fork, join (all null, or none): the projector products run on side,
+// beside passes A and B on st, and pass C waits for them.
+template <typename T>
+void batch_step(const BatchLaunch &L, int j, hipStream_t st, hipStream_t side = nullptr,
+                hipEvent_t fork = nullptr, hipEvent_t join = nullptr);
 // True if batched systems on a cubic box of this edge get specialised passes.
 bool batch_edge_specialised(int n);
 // planes (slabs) of one band per work item of the specialised batched passes

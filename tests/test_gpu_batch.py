@@ -168,6 +168,27 @@ def test_graph_replays_equal_eager():
             assert not torch.equal(Yd2[i], eager[i])
 
 
+def test_overlap_keeps_results():
+    """The projector products on the batch's second stream (beside passes A and
+    B) or in line give bitwise the same output, eager and replayed from a
+    graph, over several replays."""
+    import torch
+    systems, Hs, Xs, bounds = _case()
+    with B.Batch(systems, precision=B.ABI_PREC_MIXED) as g:
+        Xd = [to_dev(X).to(torch.complex64) for X in Xs]
+        g.use_graph(False)
+        g.use_overlap(False)
+        ref = [Y.clone() for Y in g.cheb_filter(Xd, DEGREE, bounds)]
+        for graph in (False, True):
+            g.use_graph(graph)
+            g.use_overlap(True)
+            for rep in range(3):
+                Yd = g.cheb_filter(Xd, DEGREE, bounds)
+                torch.cuda.synchronize()
+                for i in range(len(systems)):
+                    assert torch.equal(Yd[i], ref[i]), (graph, rep, i)
+
+
 def test_autotune_keeps_results():
     import torch
     systems, Hs, Xs, bounds = _case()
