@@ -238,6 +238,9 @@ __global__ __launch_bounds__(kBatchEP) void bexpand_kernel(const BatchSys *__res
                                                            const int64_t *__restrict__ off,
                                                            int nsys) {
   constexpr int NJ = kBatchPT, NB = kBatchBT;
+  // a system has four projectors per atom, so with tiles of a multiple of four
+  // every tile's count is one too and the steps of four stay inside the tile
+  static_assert(NJ % 4 == 0, "projector tiles hold whole atoms");
   __shared__ C2<T> cs[NJ][NB];
   const int t = threadIdx.x;
   const int64_t total = off[nsys];
