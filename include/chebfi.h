@@ -511,8 +511,9 @@ abi_status abi_set_tuning(abi_system sys, int32_t param, int32_t value);
 abi_status abi_get_tuning(abi_system sys, int32_t param, int32_t *value);
 
 /* Autotuner (section "Batch processing": FFT plans and tile shapes chosen per
- * problem).  Times H applications of the `nband` bands of X (dtype; X is only
- * read) with the launch choices above, one coordinate at a time from the
+ * problem).  Times filter steps on the `nband` bands of X (dtype; X is only
+ * read; H X - X, so that the last FFT pass also reads a previous block as in
+ * the filter's three-term recurrence) with the launch choices above, one coordinate at a time from the
  * current ones (projection tile 14 / 15 / 11 / 4 and expansion tile 15 / 13 /
  * 9 / 6 for complex64 blocks on a mixed handle, then the FFT batch halved /
  * doubled, then the second stream), best of five timed applications each; a

@@ -1824,10 +1824,13 @@ abi_status abi_autotune(abi_system s, const void *X, int64_t nband, int64_t ld, 
         return;
       }
     }
-    // time one H application per candidate (best of five after a warm-up),
-    // one coordinate at a time from the current choice; a candidate replaces
-    // the current one only if it is more than 1% faster (the timings of one
-    // choice vary by about that much from run to run)
+    // time one filter step per candidate (best of five after a warm-up): H
+    // applied with the recurrence's previous block read as in the filter (X
+    // itself stands in for it; the values do not matter here), so that the last
+    // FFT pass moves the bytes it moves inside a filter.  One coordinate at a
+    // time from the current choice; a candidate replaces the current one only if
+    // it is more than 1% faster (the timings of one choice vary by about that
+    // much from run to run)
     void *HX = s->tune_out.get(elem_bytes(dtype) * (size_t)s->npw * nband);
     const bool prof = s->prof.on;
     s->prof.on = false;
@@ -1846,11 +1849,11 @@ abi_status abi_autotune(abi_system s, const void *X, int64_t nband, int64_t ld, 
     auto timed = [&](const TuneChoice &c) {
       apply(c);
       s->pl_chain = s->pl_assume = split_bf16 && c.proj >= 15;
-      apply_core(s, X, ld, nullptr, 0, HX, s->npw, nband, 1.0, 0.0, 0.0, st, dtype);
+      apply_core(s, X, ld, X, ld, HX, s->npw, nband, 1.0, 0.0, 1.0, st, dtype);
       float best = 1e30f;
       for (int r = 0; r < 5; ++r) {
         CHEBFI_HIP(hipEventRecord(e0, st));
-        apply_core(s, X, ld, nullptr, 0, HX, s->npw, nband, 1.0, 0.0, 0.0, st, dtype);
+        apply_core(s, X, ld, X, ld, HX, s->npw, nband, 1.0, 0.0, 1.0, st, dtype);
         CHEBFI_HIP(hipEventRecord(e1, st));
         CHEBFI_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
