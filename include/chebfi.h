@@ -421,7 +421,8 @@ abi_status abi_cheb_filter_batch(abi_batch batch, const void *const *X, void *co
                                  const double *a0, void *stream);
 
 /* Times the launch variants of the batched filter on the caller's arguments
- * (same as abi_cheb_filter_batch; Y is overwritten) and keeps the fastest:
+ * (same as abi_cheb_filter_batch; Y is overwritten; eager launches, best of
+ * three filters per variant) and keeps the fastest:
  * FFT pass threads per workgroup (256 / 512 where the plans allow) and the
  * radix order of the FFT plans (ascending / descending).  choice (host, 4
  * entries, may be NULL) receives {fft threads, projection threads (256: the
