@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void bproj_reduce_kernel(const BatchSys *__res
 // projector one P element from global memory and the C' row from LDS (the
 // same address in every lane), four FMAs per band, so E is written once.
 // Projectors come four per atom, so a tile's count is a multiple of four and
-// the loop over them runs in unrolled steps of four. 
+// the loop over them runs in unrolled steps of four.
 template <typename T>
 __global__ __launch_bounds__(kBatchEP) void bexpand_kernel(const BatchSys *__restrict__ sys,
                                                            const int64_t *__restrict__ off,
@@ -496,16 +496,17 @@ __global__ __launch_bounds__(kCT) void bcpass_a_kernel(const BatchSys *__restric
 
 // Waves per SIMD asked of the batched pass B: six (three workgroups of kCT
 // threads per CU instead of two) for the complex64 edges where that measured
-// faster and compiles without spilling, else the least a workgroup needs.
+// faster (at 24 and 45 the compiler spills a few registers to fit, and the
+// pass is still faster), else the least a workgroup of kCT threads needs.
 template <typename T, int N>
 constexpr int bcpass_b_waves() {
   return sizeof(T) == 4 && (N == 24 || N == 40 || N == 45) ? 6 : kCT / 256;
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(bcpass_b_waves<T, N>()))) void bcpass_b_kernel(const BatchSys *__restrict__ sys,
-                                                       const int32_t *__restrict__ gsys,
-                                                       const int64_t *__restrict__ goff, int gns) {
+__global__ __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(bcpass_b_waves<T, N>())))
+void bcpass_b_kernel(const BatchSys *__restrict__ sys, const int32_t *__restrict__ gsys,
+                     const int64_t *__restrict__ goff, int gns) {
   constexpr int LD = cld<N>(), PL = N * LD;
   constexpr int NPL = cplanes_per_item<T, N>(), G = (N + NPL - 1) / NPL;
   __shared__ C2<T> buf[NPL * PL];
@@ -560,10 +561,10 @@ constexpr int bcpass_c_waves() {
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(bcpass_c_waves<T, N>()))) void bcpass_c_kernel(const BatchSys *__restrict__ sys,
-                                                       const BatchStep *__restrict__ step,
-                                                       const int32_t *__restrict__ gsys,
-                                                       const int64_t *__restrict__ goff, int gns) {
+__global__ __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(bcpass_c_waves<T, N>())))
+void bcpass_c_kernel(const BatchSys *__restrict__ sys, const BatchStep *__restrict__ step,
+                     const int32_t *__restrict__ gsys, const int64_t *__restrict__ goff,
+                     int gns) {
   constexpr int NXY = N * N, LD = cld<N>(), PL = N * LD;
   constexpr int NPL = cplanes_per_item<T, N>(), G = (N + NPL - 1) / NPL;
   __shared__ C2<T> buf[NPL * PL];
