@@ -2064,9 +2064,10 @@ abi_status abi_batch_autotune(abi_batch B, const void *const *X, void *const *Y,
             B->proj_threads = pt;
             B->radix_desc = rd;
             batch_filter(B, X, Y, nband, ld, dtype, degree, a, b, a0, st);  // warm-up
-            // best of three filters: an eager filter now and then takes much
-            // longer than the others (host-side launch delays), which a sum
-            // would charge to the variant
+            // best of three filters: with the projector products on the second
+            // stream an eager filter now and then takes much longer than the
+            // others (about one in four, seen on the 16-cell batch), which a
+            // sum would charge to the variant
             float ms = 1e30f;
             for (int r = 0; r < 3; ++r) {
               CHEBFI_HIP(hipEventRecord(e0, st));
