@@ -451,17 +451,22 @@ def run_cycles(g, X0, v0, degree, steps, warmup, lowprec=False, fp64_last=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     filt_ms = []
+    # per-kernel event timing on one timed step only (its event pairs around
+    # every launch cost a few percent of the step): the last, or with fp64_last
+    # the one before it, so that the classes are those of the lowprec cycle
+    prof_step = steps - 2 if (fp64_last and lowprec and steps > 1) else steps - 1
+    prof = None
     for i in range(steps):
-        # per-kernel event timing on the last timed step only (its event pairs
-        # around every launch cost a few percent of the step)
-        g.profile(i == steps - 1)
+        g.profile(i == prof_step)
         bounds, ms, ev, res = step(X, Y, lowprec and not (fp64_last and i == steps - 1))
+        if i == prof_step:
+            # read before timing is switched off again (which clears the figures)
+            prof = g.profile_read()
         X, Y = Y, X
         filt_ms.append(ms)
         first_bounds = first_bounds or bounds
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    prof = g.profile_read()
     g.profile(False)
     nband = X.shape[0]
     filt_s = sum(filt_ms) / 1e3
@@ -587,8 +592,10 @@ def main():
     if args.precision in ("both", "fp64"):
         runs["fp64"] = run_cycles(g, X64, v0, degree, args.steps, args.warmup)
     if args.precision in ("both", "mixed"):
+        # the precision form: split-BF16 Rayleigh-Ritz cycles, the last one
+        # with the FP64 Rayleigh-Ritz that wins back the Ritz values
         runs["mixed"] = run_cycles(g, X32, v0, degree, args.steps, args.warmup,
-                                   lowprec=not args.paw)
+                                   lowprec=not args.paw, fp64_last=not args.paw)
     head = runs["mixed"] if "mixed" in runs else runs["fp64"]
     mixed = "mixed" in runs
 
