@@ -1726,6 +1726,8 @@ abi_status abi_get_tuning(abi_system s, int32_t param, int32_t *value) {
 }
 
 // ---- autotuner --------------------------------------------------------------
+}  // extern "C": the cache helpers below return C++ types
+
 namespace {
 
 struct TuneChoice {
@@ -1792,6 +1794,8 @@ void cache_write(const std::string &path, const std::string &key, const TuneChoi
 }
 
 }  // namespace
+
+extern "C" {
 
 abi_status abi_autotune(abi_system s, const void *X, int64_t nband, int64_t ld, int32_t dtype,
                         const char *cache_path, int32_t *from_cache, void *stream) {
